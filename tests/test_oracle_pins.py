@@ -1,0 +1,342 @@
+"""Pins of the CPU oracle against closed forms, brute force, library routines,
+hand-worked fixtures and invariants (no GPU).  Each test names what it pins."""
+import json
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from amp_data import build_index, lossless_index, random_model, rbf_table
+from amp_data.model import gamma_to_gmul
+from amp_data.synth import WORKLOADS, make_base, make_queries
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+# ----------------------------------------------------------------- CL
+def test_coarse_l2_and_ip_match_python_loops():
+    r = np.random.default_rng(1)
+    Q = r.normal(size=(3, 5)).astype(np.float32)
+    C = r.normal(size=(7, 5)).astype(np.float32)
+    for q in Q:
+        D = oracle.coarse_distances(q, C, "l2")
+        Dip = oracle.coarse_distances(q, C, "ip")
+        for c in range(7):
+            s = 0.0
+            t = 0.0
+            for j in range(5):
+                s += (float(q[j]) - float(C[c, j])) ** 2
+                t -= float(q[j]) * float(C[c, j])
+            assert abs(D[c] - s) <= 1e-12 * max(1.0, s)
+            assert abs(Dip[c] - t) <= 1e-12 * max(1.0, abs(t))
+
+
+def test_select_probes_orders_by_distance_then_list_id():
+    D = np.array([5.0, 1.0, 3.0, 1.0, 3.0, 0.5, 9.0])
+    want = [c for _, c in sorted((float(D[c]), c) for c in range(len(D)))]
+    assert oracle.select_probes(D, 7).tolist() == want
+    assert oracle.select_probes(D, 3).tolist() == [5, 1, 3]
+
+
+# ----------------------------------------------------------------- RC
+def test_residual_is_correctly_rounded_fp32_subtraction():
+    r = np.random.default_rng(2)
+    a = (r.normal(size=4000) * 10.0 ** r.integers(-8, 8, size=4000)).astype(np.float32)
+    b = (r.normal(size=4000) * 10.0 ** r.integers(-8, 8, size=4000)).astype(np.float32)
+    a[:4] = [1.0, 3.0e38, 1e-30, 16777216.0]
+    b[:4] = [np.float32(1.0) - np.float32(2.0 ** -24), -3.0e38, 1e-38, 1.0]
+    with np.errstate(over="ignore"):
+        want = a - b  # IEEE float32 subtraction (round to nearest even)
+        got = np.array([oracle.residual_f32(x, y) for x, y in zip(a, b)], dtype=np.float32)
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+
+
+def test_u9_grid_rounds_half_even_and_saturates():
+    x = np.array([0.5, 1.5, 2.5, -0.5, -1.5, 254.5, 255.5, 300.0, -300.0, 7.49999, -7.5])
+    want = [0, 2, 2, 0, -2, 254, 255, 255, -255, 7, -8]
+    assert oracle.grid(x, "u9").tolist() == want
+
+
+def _e4m3_values_from_spec():
+    """Decode all E4M3 (OCP 8-bit float, 'fn' variant) bit patterns: bias 7,
+    subnormals m/8 * 2^-6, S.1111.111 is NaN, no infinities."""
+    vals = []
+    for e in range(16):
+        for m in range(8):
+            if e == 15 and m == 7:
+                continue
+            v = Fraction(m, 8) * Fraction(1, 64) if e == 0 else (1 + Fraction(m, 8)) * Fraction(2) ** (e - 7)
+            vals.append((v, m))
+    return vals
+
+
+def test_e4m3_integer_rounding_matches_spec_table():
+    vals = _e4m3_values_from_spec()
+    for x in range(-700, 701):
+        a = abs(x)
+        if a >= 464:            # at or above the midpoint 448..480: saturate
+            want = 448
+        else:
+            best = min(vals, key=lambda vm: (abs(vm[0] - a), vm[1] % 2))
+            want = best[0]
+        got = int(oracle.e4m3_round_int(np.array([x]))[0])
+        assert Fraction(got) == (want if x >= 0 else -want), x
+
+
+def test_e4m3_rounding_agrees_with_torch_cast():
+    torch = pytest.importorskip("torch")
+    if not hasattr(torch, "float8_e4m3fn"):
+        pytest.skip("torch without float8_e4m3fn")
+    x = np.arange(-460, 461)
+    ref = torch.tensor(x, dtype=torch.float32).to(torch.float8_e4m3fn).to(torch.float32).numpy()
+    got = oracle.e4m3_round_int(x)
+    assert np.array_equal(got, ref.astype(np.int64))
+
+
+# ----------------------------------------------------------------- LC
+def test_lut_int_identity_sum_equals_direct_distance():
+    """I1: sum_m T[m][code_m] = ||ri - cbi(code)||^2 (exact integers)."""
+    r = np.random.default_rng(3)
+    M, dsub = 6, 4
+    cbi = r.integers(-255, 256, size=(M, 256, dsub))
+    ri = r.integers(-255, 256, size=M * dsub)
+    T = oracle.lut_int(ri, cbi, "l2")
+    Tip = oracle.lut_int(ri, cbi, "ip")
+    for _ in range(50):
+        code = r.integers(0, 256, size=M)
+        rec = [int(v) for m in range(M) for v in cbi[m, code[m]]]
+        direct = sum((int(a) - b) ** 2 for a, b in zip(ri, rec))
+        assert int(sum(T[m, code[m]] for m in range(M))) == direct
+        assert int(sum(Tip[m, code[m]] for m in range(M))) == -sum(int(a) * b for a, b in zip(ri, rec))
+
+
+def test_full_precision_adc_equals_reconstruction_distance():
+    """Full-precision ADC sum = ||q - x_hat||^2, x_hat = c + concat cb(code)."""
+    r = np.random.default_rng(4)
+    M, dsub, d = 8, 4, 32
+    CB = r.normal(size=(M, 256, dsub)).astype(np.float32)
+    c = r.normal(size=d).astype(np.float32) * 5
+    for _ in range(20):
+        q = r.normal(size=d).astype(np.float32) * 5
+        code = r.integers(0, 256, size=M)
+        res = oracle.residual_f32(q, c)
+        T = oracle.lut_f64(res, CB)
+        adc = float(sum(T[m, code[m]] for m in range(M)))
+        xhat = c.astype(np.float64) + np.concatenate([CB[m, code[m]] for m in range(M)]).astype(np.float64)
+        direct = float(((res.astype(np.float64) + c - xhat) ** 2).sum())
+        assert abs(adc - direct) <= 1e-12 * direct
+
+
+# ----------------------------------------------------------------- quantiser
+def test_quantizer_hand_worked_fixture():
+    g = _gold("quantize_worked.json")
+    T = np.array(g["T"])
+    for case in g["cases"]:
+        Q, s, base = oracle.quantize_lut(T, case["b"])
+        assert s == case["s"] and base == case["base"]
+        assert Q.tolist() == case["Q"]
+        for codes, est, ex in zip(case["codes"], case["estimate"], case["exact"]):
+            S = sum(int(Q[m, c]) for m, c in enumerate(codes))
+            assert base + (S << s) == est
+            assert sum(int(T[m, c]) for m, c in enumerate(codes)) == ex
+
+
+@pytest.mark.parametrize("b", [4, 8, 12, 16])
+def test_quantizer_bounds_and_rounding(b):
+    """I2 range, I3 error bound, I4 exact case, minimal shift, and the rounding
+    checked with exact rationals."""
+    r = np.random.default_rng(10 + b)
+    for trial in range(30):
+        M = int(r.integers(1, 9))
+        scale = int(10 ** r.integers(1, 7))
+        T = r.integers(0, scale, size=(M, 256)) + r.integers(-1000, 1000, size=(M, 1))
+        Q, s, base = oracle.quantize_lut(T, b)
+        top = (1 << b) - 1
+        assert Q.min() >= 0 and Q.max() <= top                         # I2
+        lo = T.min(1)
+        R = int((T - lo[:, None]).max())
+        hf = lambda t: (1 << (t - 1)) if t else 0  # noqa: E731
+        assert ((R + hf(s)) >> s) <= top
+        if s > 0:
+            assert ((R + hf(s - 1)) >> (s - 1)) > top                    # minimal s
+        else:
+            assert R <= top                                              # I4
+        for m in range(M):
+            for j in r.integers(0, 256, size=8):
+                exact = Fraction(int(T[m, j] - lo[m]), 1 << s)
+                assert int(Q[m, j]) == math.floor(exact + Fraction(1, 2))
+        codes = r.integers(0, 256, size=(40, M))
+        for cd in codes:
+            Dint = sum(int(T[m, cd[m]]) for m in range(M))
+            Dq = base + (sum(int(Q[m, cd[m]]) for m in range(M)) << s)
+            assert abs(Dq - Dint) <= M * (hf(s))                       # I3
+            if s == 0:
+                assert Dq == Dint
+
+
+# ----------------------------------------------------------------- PPM
+def test_mitchell_log2_hand_worked_and_bounds():
+    g = _gold("mitchell_log2.json")
+    assert oracle.mitchell_log2_q8(np.array(g["x"])).tolist() == g["L"]
+    x = np.concatenate([np.arange(0, 5000), (2 ** np.arange(0, 40)) - 1,
+                        np.random.default_rng(5).integers(0, 2 ** 40, size=2000)])
+    L = oracle.mitchell_log2_q8(x)
+    # exact at powers of two, within Mitchell's maximum error (0.0861) elsewhere
+    pw = (2 ** np.arange(0, 40)) - 1
+    assert oracle.mitchell_log2_q8(pw).tolist() == (256 * np.arange(0, 40)).tolist()
+    err = np.abs(L / 256.0 - np.log2(x.astype(np.float64) + 1))
+    assert err.max() <= 0.0861 + 1 / 256
+    xs = np.sort(x)
+    assert np.all(np.diff(oracle.mitchell_log2_q8(xs)) >= 0)
+
+
+def _lin_model(n_sv=64, gamma=1.0, seed=0):
+    return random_model(seed, n_sv, feat_lo=[0] * 5, feat_mul=[1 << 12] * 5, gamma=gamma)
+
+
+def test_rbf_kernel_table_matches_gaussian_within_table_step():
+    """The table-read kernel equals exp(-gamma ||du/1023||^2) within the
+    table's resolution (1/64 in the exponent, Q20 values)."""
+    for gamma in (0.1, 1.0, 3.0):
+        m = _lin_model(gamma=gamma)
+        table = np.asarray(m["table"], dtype=np.float64) / 2 ** 20
+        r = np.random.default_rng(6)
+        for _ in range(200):
+            du = r.integers(-1023, 1024, size=5)
+            dist2 = int((du * du).sum())
+            idx = min((dist2 * m["g_mul"]) >> 32, 1023)
+            arg = gamma * dist2 / 1023 ** 2
+            if arg * 64 >= 1023:
+                continue
+            # table midpoint rule: |exp(-a) - exp(-(i+1/2)/64)| <= exp(-a)(e^(1/128)-1) + rounding
+            tol = math.exp(-arg) * (math.exp(1 / 128 + 1e-6) - 1) + 2 ** -20 + 1e-9
+            assert abs(table[idx] - math.exp(-arg)) <= tol * 1.01 + abs(
+                gamma_to_gmul(gamma) / 2 ** 32 - gamma * 64 / 1023 ** 2) * dist2 * math.exp(-arg)
+
+
+def test_svr_score_matches_real_rbf_regression():
+    """y / 2^40 = beta0 + sum beta_i exp(-gamma ||u - s_i||^2) within the
+    table error; the regressor sums over every support vector."""
+    m = _lin_model(n_sv=100, gamma=1.0, seed=3)
+    r = np.random.default_rng(7)
+    for _ in range(30):
+        u = r.integers(0, 1024, size=5)
+        y = oracle.svr_eval(u, m) / 2.0 ** 40
+        du = (np.asarray(m["sv"], dtype=np.float64) - u) / 1023.0
+        K = np.exp(-1.0 * (du * du).sum(1))
+        beta = np.asarray(m["beta"], dtype=np.float64) / 2 ** 20
+        ref = m["beta0"] / 2.0 ** 40 + float((beta * K).sum())
+        bound = float(np.abs(beta).sum()) * (math.exp(1 / 128) - 1 + 2 ** -19)
+        assert abs(y - ref) <= bound
+
+
+def test_degenerate_predictor_gives_constant_bits_and_thresholds_are_inclusive():
+    m = _lin_model()
+    m["beta"] = np.zeros_like(m["beta"])
+    for b0, want in [(-0.5, 4), (-0.2, 4), (-0.1, 8), (0.0, 8), (0.1, 12), (0.3, 16)]:
+        m["beta0"] = int(round(b0 * 2 ** 40))
+        u = np.random.default_rng(8).integers(0, 1024, size=5)
+        y = oracle.svr_eval(u, m)
+        assert y == m["beta0"]
+        assert oracle.bits_from_score(y, m) == want
+    # allowed subsets: never returns a disallowed width
+    m["beta0"] = int(0.1 * 2 ** 40)
+    assert oracle.bits_from_score(m["beta0"], m, allowed=(4, 8, 16)) == 16
+    assert oracle.bits_from_score(m["beta0"], m, allowed=(4, 8)) == 8
+    m["beta0"] = int(-0.5 * 2 ** 40)
+    assert oracle.bits_from_score(m["beta0"], m, allowed=(8, 16)) == 8
+
+
+def test_single_support_vector_score_decreases_with_distance():
+    m = _lin_model(n_sv=1)
+    m["sv"] = np.array([[500] * 5], dtype=np.int32)
+    m["beta"] = np.array([1 << 20], dtype=np.int32)
+    m["beta0"] = 0
+    ys = [oracle.svr_eval(np.array([500 + t] * 5), m) for t in range(0, 500, 25)]
+    assert all(a >= b for a, b in zip(ys, ys[1:])) and ys[0] > ys[-1]
+
+
+# ----------------------------------------------------------------- DC + TS
+def _tiny_index(seed=11, n=3000, d=16, nlist=12, M=4):
+    r = np.random.default_rng(seed)
+    means = r.uniform(-5, 5, size=(nlist, d))
+    base = (means[r.integers(0, nlist, size=n)] + r.normal(size=(n, d))).astype(np.float32)
+    idx = build_index(base, nlist, M, iters=8, seed=seed)
+    return idx, base
+
+
+def test_search_equals_bruteforce_over_all_candidates():
+    idx, base = _tiny_index()
+    Q = np.random.default_rng(12).normal(size=(6, 16)).astype(np.float32) * 3
+    for policy, b in [("fixed", 4), ("fixed", 8), ("fixed", 16)]:
+        res = oracle.search(idx, Q, k=7, nprobe=5, policy=policy, bits=b)
+        cbi, _ = oracle.index_grid(idx)
+        for i, q in enumerate(Q):
+            D = oracle.coarse_distances(q, idx["centroids"])
+            P = sorted(range(idx["nlist"]), key=lambda c: (D[c], c))[:5]
+            assert res["probes"][i].tolist() == P
+            cands = []
+            for p in P:
+                rr = oracle.grid(oracle.residual_f32(q, idx["centroids"][p]).astype(np.float64)
+                                 * 2.0 ** -idx["grid_e"])
+                Qt, s, base0 = oracle.quantize_lut(oracle.lut_int(rr, cbi), b)
+                for pos in range(idx["list_offsets"][p], idx["list_offsets"][p + 1]):
+                    S = sum(int(Qt[m, idx["codes"][pos, m]]) for m in range(idx["M"]))
+                    cands.append((base0 + (S << s), int(idx["ids"][pos])))
+            cands.sort()
+            assert res["ids"][i].tolist() == [c[1] for c in cands[:7]]
+            assert res["qdist"][i].tolist() == [c[0] for c in cands[:7]]
+            assert len({c[1] for c in cands}) == len(cands)
+
+
+def test_padding_when_fewer_candidates_than_k():
+    idx, _ = _tiny_index(n=60, nlist=12)
+    q = np.zeros((1, 16), dtype=np.float32)
+    res = oracle.search(idx, q, k=50, nprobe=1, policy="fixed", bits=16)
+    p = res["probes"][0, 0]
+    n = int(idx["list_sizes"][p])
+    assert n < 50
+    assert (res["ids"][0, n:] == -1).all()
+    assert (res["qdist"][0, n:] == np.iinfo(np.int64).max).all()
+    assert np.isinf(res["dist"][0, n:]).all()
+
+
+def test_lossless_index_recovers_exact_knn():
+    """Base vectors are exactly centroid + codewords: with every list probed,
+    the full-precision search and the exact integer search (s = 0) return the
+    exact k nearest neighbours with their exact distances."""
+    idx, base = lossless_index(seed=5, nlist=6, M=4, dsub=4, per_list=[40, 3, 77, 0, 12, 60])
+    Q = np.random.default_rng(13).integers(-40, 41, size=(8, 16)).astype(np.float32)
+    truth = oracle.exact_knn(base, Q, 10)
+    r32 = oracle.search(idx, Q, 10, 6, policy="fp32")
+    assert np.array_equal(r32["ids"], truth)
+    r16 = oracle.search(idx, Q, 10, 6, policy="fixed", bits=16)
+    assert (r16["shift"] == 0).all()
+    assert np.array_equal(r16["ids"], truth)
+    d64 = ((base[truth].astype(np.float64) - Q[:, None, :]) ** 2).sum(-1)
+    assert np.array_equal(r16["qdist"], d64.astype(np.int64))
+    assert oracle.recall_at(r16["ids"], truth) == 1.0
+
+
+@pytest.mark.slow
+def test_tiny_workload_recall_against_exact_knn():
+    w = WORKLOADS["tiny"].scaled(n=20_000, nq=40)
+    base = make_base(w)
+    idx = build_index(base, w.nlist, w.M, iters=10, seed=w.seed)
+    Q = make_queries(w, 40)
+    truth = oracle.exact_knn(base, Q, 10)
+    rec = {}
+    for npb in (1, 8, 64):
+        res = oracle.search(idx, Q, 10, npb, policy="fixed", bits=16)
+        rec[npb] = oracle.recall_at(res["ids"], truth)
+    r32 = oracle.recall_at(oracle.search(idx, Q, 10, 8, policy="fp32")["ids"], truth)
+    assert rec[1] <= rec[8] <= rec[64] + 1e-9
+    assert rec[8] >= 0.3 and abs(rec[8] - r32) <= 0.05
