@@ -80,8 +80,6 @@ def _mixture_params(w: Workload):
         weights = np.full(w.n_comp, 1.0 / w.n_comp)
     if w.kind == "aniso":
         sigma = _rng(w.seed, _SIGMA).uniform(0.1, 2.0, size=w.d)
-    elif w.kind == "uint8":
-        sigma = np.full(w.d, 32.0)
     elif w.kind == "vmf":
         sigma = np.full(w.d, 0.75 / np.sqrt(w.d))
     else:
@@ -89,18 +87,40 @@ def _mixture_params(w: Workload):
     return means, weights, sigma
 
 
+# The uint8 workload's components have a low-rank covariance: a 16-dimensional
+# latent Gaussian mapped by a per-component random matrix (per-dimension
+# spread LATENT_SIGMA) plus small isotropic noise.  Descriptor data such as
+# SIFT has an intrinsic dimension of this order; isotropic 128-d clusters
+# would make every member of a cluster nearly equidistant from a query.
+LATENT_DIM, LATENT_SIGMA, NOISE_SIGMA = 16, 20.0, 2.0
+
+
+def _latent_maps(w: Workload):
+    r = _rng(w.seed, _SIGMA + 10)
+    return r.standard_normal(size=(w.n_comp, w.d, LATENT_DIM)) * (LATENT_SIGMA / np.sqrt(LATENT_DIM))
+
+
 def _draw(w: Workload, n: int, purpose: int, chunk: int = 1 << 18):
     means, weights, sigma = _mixture_params(w)
     r = _rng(w.seed, purpose)
     comp = r.choice(w.n_comp, size=n, p=weights)
     out = np.empty((n, w.d), dtype=np.float32)
+    maps = _latent_maps(w) if w.kind == "uint8" else None
     for s in range(0, n, chunk):
         e = min(n, s + chunk)
-        x = means[comp[s:e]] + r.standard_normal(size=(e - s, w.d)) * sigma
-        if w.kind == "uint8":
+        if maps is not None:
+            z = r.standard_normal(size=(e - s, LATENT_DIM))
+            x = means[comp[s:e]] + r.standard_normal(size=(e - s, w.d)) * NOISE_SIGMA
+            cc = comp[s:e]
+            order = np.argsort(cc, kind="stable")
+            bounds = np.flatnonzero(np.diff(cc[order])) + 1
+            for grp in np.split(order, bounds):
+                x[grp] += z[grp] @ maps[cc[grp[0]]].T
             x = np.rint(np.clip(x, 0.0, 255.0))
-        elif w.kind == "vmf":
-            x /= np.linalg.norm(x, axis=1, keepdims=True)
+        else:
+            x = means[comp[s:e]] + r.standard_normal(size=(e - s, w.d)) * sigma
+            if w.kind == "vmf":
+                x /= np.linalg.norm(x, axis=1, keepdims=True)
         out[s:e] = x
     if w.kind == "vmf":
         # the serving corpus is stored in bf16: round to bf16 (nearest-even)

@@ -1,0 +1,233 @@
+"""Throughput benchmark of the adaptive-precision IVF-PQ search on one MI355X.
+
+A step is one search of the whole query batch of the mid-size workload
+(1M x 128 integer-valued vectors from a 1024-component Gaussian mixture,
+IVF1024 / PQ16x256, 10 000 queries, nprobe 32, k 10): coarse distances,
+probe selection, precision prediction, work queue, LUT build + quantisation
++ scan, top-k merge.  Queries and the index are resident in HBM before the
+timed region.  Prints one JSON line (see the fields below); a per-policy
+table goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _cpu_worker(args):
+    import oracle
+    idx, Q, k, nprobe, kw = args
+    t = time.perf_counter()
+    oracle.search(idx, Q, k, nprobe, **kw)
+    return time.perf_counter() - t
+
+
+def cpu_baseline(idx, Q, k, nprobe, kw, budget_s=20.0):
+    """Time the oracle on a bounded sample of the same queries, one worker
+    process per host core."""
+    cores = os.cpu_count() or 1
+    cores = min(cores, 16)
+    t0 = time.perf_counter()
+    _cpu_worker((idx, Q[:2], k, nprobe, kw))
+    per_q = max((time.perf_counter() - t0) / 2, 1e-4)
+    n = int(min(len(Q), max(cores, budget_s * cores / per_q)))
+    n = max(cores, (n // cores) * cores)
+    chunks = [(idx, Q[i::cores][: n // cores], k, nprobe, kw) for i in range(cores)]
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        pool.map(_cpu_worker, chunks)
+    wall = time.perf_counter() - t0
+    return dict(value=n / wall, unit="queries/s", cores=cores, kind="oracle",
+                sample=f"first {n} of {len(Q)} queries (interleaved over {cores} processes), "
+                       f"{wall:.1f} s wall")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="mid")
+    ap.add_argument("--nq", type=int, default=0)
+    ap.add_argument("--policies", default="adaptive,fp32,fixed16,fixed8,fixed4")
+    ap.add_argument("--train-queries", type=int, default=256)
+    ap.add_argument("--gamma", type=float, default=10.0)
+    ap.add_argument("--epsilon", type=float, default=0.1)
+    ap.add_argument("--svr-c", type=float, default=1.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--recall-queries", type=int, default=200)
+    ap.add_argument("--cache-dir", default="/tmp/amp_bench_cache")
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.calibrate_copy_mb:
+        import torch
+        n = args.calibrate_copy_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(max(1, args.steps)):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copied {args.calibrate_copy_mb} MiB x {max(1, args.steps)}")
+        return
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU path is a design "
+              "note, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2606_07156_amd as amp
+    from amp_data import build_index
+    from amp_data.synth import WORKLOADS, make_base, make_queries
+
+    w = WORKLOADS[args.workload]
+    if args.nq:
+        w = w.scaled(nq=args.nq)
+    cache = os.path.join(args.cache_dir, f"amp_{w.name}_{w.n}_{w.nlist}_{w.M}_{w.seed}.npz")
+    t = time.perf_counter()
+    if os.path.exists(cache):
+        z = np.load(cache, allow_pickle=False)
+        base = z["base"]
+        idx = {k2: (z[k2] if z[k2].ndim else z[k2].item()) for k2 in z.files if k2 != "base"}
+        log(f"[bench] loaded cached base and index from {cache} in {time.perf_counter() - t:.1f}s")
+    else:
+        base = make_base(w)
+        log(f"[bench] generated base {base.shape} in {time.perf_counter() - t:.1f}s")
+        t = time.perf_counter()
+        idx = build_index(base, w.nlist, w.M, iters=20, seed=w.seed, integer_data=w.integer_data,
+                          grid_kind=w.grid_kind, metric=w.metric)
+        log(f"[bench] built IVF{w.nlist}/PQ{w.M} index in {time.perf_counter() - t:.1f}s")
+        if args.cache_dir:
+            os.makedirs(args.cache_dir, exist_ok=True)
+            np.savez(cache, base=base, **idx)
+    log(f"[bench] list sizes min/mean/max {idx['list_sizes'].min()}/{idx['list_sizes'].mean():.0f}/"
+        f"{idx['list_sizes'].max()}")
+    Q = make_queries(w)
+    h = amp.amp_index_from_arrays(idx)
+    amp.amp_index_to_device(h, 0)
+    dev = torch.device("cuda:0")
+    qd = torch.from_numpy(Q).to(dev)
+    nq, k, nprobe = len(Q), w.k, w.nprobe
+    out = dict(ids=torch.empty((nq, k), dtype=torch.int64, device=dev),
+               dist=torch.empty((nq, k), dtype=torch.float32, device=dev),
+               qdist=torch.empty((nq, k), dtype=torch.int64, device=dev))
+    stream = torch.cuda.current_stream()
+
+    # exact ground truth for recall@10 on a sample of queries (FP64 brute force)
+    import oracle
+    nr = min(args.recall_queries, nq)
+    t = time.perf_counter()
+    truth = oracle.exact_knn(base, Q[:nr], k)
+    log(f"[bench] exact kNN of {nr} queries in {time.perf_counter() - t:.1f}s")
+
+    # precision predictor fitted on a disjoint training query stream
+    t = time.perf_counter()
+    TQ = make_queries(w, args.train_queries, train=True)
+    rep = amp.amp_index_train_predictor(h, TQ, k, nprobe, gamma=args.gamma, epsilon=args.epsilon,
+                                        C_=args.svr_c, n_samples=1280)
+    model = amp.amp_index_get_predictor(h)
+    log(f"[bench] trained predictor in {time.perf_counter() - t:.1f}s: {rep}")
+
+    pols = []
+    for p in args.policies.split(","):
+        if p == "fp32":
+            pols.append(("fp32", dict(policy="fp32")))
+        elif p == "adaptive":
+            pols.append(("adaptive", dict(policy="adaptive")))
+        elif p.startswith("fixed"):
+            pols.append((p, dict(policy="fixed", bits=int(p[5:]))))
+    results = {}
+    # algorithmic bytes of the scan: one read of each probed list's codes per pair
+    sizes = idx["list_sizes"].astype(np.int64)
+    for name, kw in pols:
+        for _ in range(args.warmup):
+            amp.amp_search(h, qd, k, nprobe, out=out, stream=stream, **kw)
+        torch.cuda.synchronize()
+        stages, lat = [], []
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            o = amp.amp_search(h, qd, k, nprobe, out=out, stream=stream, stage_ms=True, **kw)
+            stages.append(o["stage_ms"])
+            lat.append(o["stage_ms"]["total"])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        g = amp.amp_search(h, Q[:nr], k, nprobe, want_probes=True, want_bits=True, **kw)
+        rec1 = oracle.recall_1_at(g["ids"], truth)
+        rec10 = oracle.recall_at(g["ids"], truth)
+        pr = g["probes"]
+        bits = g["bits"][pr >= 0]
+        hist = {int(b): round(float((bits == b).mean()), 4) for b in np.unique(bits)}
+        code_bytes = float(sizes[pr[pr >= 0]].sum()) * w.M * (nq / nr)
+        st = {s: float(np.mean([x[s] for x in stages])) for s in stages[0]}
+        results[name] = dict(qps=nq / (ms / 1e3), ms=ms, recall1=rec1, recall10=rec10, stages=st,
+                             code_bytes=code_bytes, bits=hist, p50=float(np.percentile(lat, 50)),
+                             p99=float(np.percentile(lat, 99)))
+        log(f"[bench] {name:8s} {ms:8.3f} ms/step  {nq / ms * 1e3:12.0f} QPS  1-recall@10 {rec1:.4f}  "
+            f"10-recall@10 {rec10:.4f}  bits {hist}  " + " ".join(f"{s}={v:.3f}" for s, v in st.items()))
+
+    head = "adaptive" if "adaptive" in results else next(iter(results))
+    r = results[head]
+    scan_ms = r["stages"]["scan2"]
+    achieved = r["code_bytes"] / (scan_ms / 1e3) / 1e9
+    fp = results.get("fp32")
+    line = {
+        "metric": "QPS at recall@10 (adaptive vs full-precision, same GPU); p99 latency",
+        "value": round(r["qps"], 1),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ms"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32" if head != "fp32" else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {w.n}x{w.d} integer-valued Gaussian mixture ({w.n_comp} components), "
+                               f"IVF{w.nlist}/PQ{w.M}x256, {nq} queries per step, nprobe {nprobe}, k {k}",
+                   "policy": head,
+                   "recall_at_10": round(r["recall1"], 4),
+                   "recall_definition": "1-recall@10 (exact nearest neighbour within the 10 returned); "
+                                        f"10-recall@10 {r['recall10']:.4f}; {nr} queries vs FP64 brute force",
+                   "speedup_vs_fp32": round(r["qps"] / fp["qps"], 3) if fp else None,
+                   "recall_vs_fp32": round(r["recall1"] - fp["recall1"], 4) if fp else None,
+                   "bits_share": r["bits"],
+                   "batch_latency_ms_p50_p99": [round(r["p50"], 4), round(r["p99"], 4)],
+                   "predictor": {kk: rep[kk] for kk in ("n_sv", "label_hist", "n_pairs")},
+                   "policies": {n: {"qps": round(x["qps"], 1), "recall_at_10": round(x["recall1"], 4),
+                                    "10_recall_at_10": round(x["recall10"], 4), "ms": round(x["ms"], 4),
+                                    "scan_ms": round(x["stages"]["scan2"], 4)}
+                                for n, x in results.items()}},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_scan phase 2 (LUT build + scan)", "kernel_ms": round(scan_ms, 4)},
+    }
+    if not args.no_cpu:
+        kw = dict(pols)[head]
+        if head == "adaptive":
+            kw = dict(kw, model=model)
+        line["cpu_baseline"] = cpu_baseline(idx, Q, k, nprobe, kw)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

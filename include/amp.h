@@ -1,0 +1,240 @@
+/*
+ * amp.h - C ABI of the MI355X cluster-adaptive IVF-PQ search library.
+ *
+ * The library answers top-k nearest-neighbour queries over a cluster-based
+ * product-quantised (IVF-PQ) index (paper Sec. 2.1): cluster locating (CL),
+ * residual calculation (RC), look-up-table construction (LC), distance
+ * calculation (DC) and top-k selection (TS), with the precision of each probed
+ * cluster's LUT chosen per (query, cluster) by a support-vector regressor over
+ * size, radius and query-distance features (Sec. 3.3-3.4, Sec. 4.1 PPM).
+ * Every stage of a search runs in HIP kernels on one gfx950 GPU.
+ *
+ * Conventions
+ *  - Status: every call returns AMP_OK (0) or a negative amp_status.  On error
+ *    the outputs are unspecified and the index is unchanged; nothing aborts.
+ *    amp_last_error() returns a thread-local message for the last failure.
+ *  - Ownership: handles (amp_index) are owned by the library and released
+ *    with amp_index_free().  Every buffer passed in is owned by the caller and
+ *    only read (inputs) or written (outputs) during the call (host mode) or
+ *    until the stream reaches the end of the call (device mode).
+ *  - Memory: amp_search_opts.mem says whether queries and outputs are host or
+ *    device pointers.  Host mode is synchronous.  Device mode enqueues all
+ *    work on amp_search_opts.stream (a hipStream_t, NULL = default stream)
+ *    and returns without waiting.
+ *  - Results are ordered ascending by (distance, id).  Fewer than k
+ *    candidates: the tail is padded with id -1, distance +inf, integer
+ *    distance INT64_MAX.
+ *  - An index is immutable once built; searches may run concurrently on
+ *    different streams (they serialise on the index's scratch space).
+ */
+#ifndef AMP_H
+#define AMP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t amp_status;
+enum {
+  AMP_OK = 0,
+  AMP_EINVAL = -1,       /* bad argument (null pointer, size out of range)    */
+  AMP_ENOMEM = -2,       /* host or device allocation failed                  */
+  AMP_EDEVICE = -3,      /* HIP runtime error or no usable gfx950 device      */
+  AMP_EIO = -4,          /* file could not be opened / read / written         */
+  AMP_EFORMAT = -5,      /* index file corrupt, truncated or wrong version     */
+  AMP_EBUSY = -6,
+  AMP_ECANCELED = -7,
+  AMP_EUNSUPPORTED = -8, /* valid request this build does not implement       */
+  AMP_EOVERFLOW = -9     /* a query's candidate buffer overflowed             */
+};
+
+enum { AMP_L2 = 0, AMP_IP = 1 };                 /* metric                      */
+enum { AMP_GRID_U9 = 0, AMP_GRID_E4M3 = 1 };     /* LC operand grid             */
+enum { AMP_MEM_HOST = 0, AMP_MEM_DEVICE = 1 };
+enum {                                           /* precision policy kind       */
+  AMP_POLICY_FP32 = 0,      /* full-precision FP32 LUT and FP32 sums           */
+  AMP_POLICY_FIXED = 1,     /* every probed cluster at fixed_bits              */
+  AMP_POLICY_ADAPTIVE = 2,  /* regressor picks the width per probed cluster    */
+  AMP_POLICY_EXPLICIT = 3   /* caller gives the width per (query, probe rank)  */
+};
+enum { AMP_LUT_BF16 = 1, AMP_LUT_F16 = 2, AMP_LUT_F8E4M3 = 3 }; /* LC matrix dtype */
+
+#define AMP_KSUB 256        /* codewords per subspace                          */
+#define AMP_MAX_K 1024
+#define AMP_MAX_NPROBE 256
+#define AMP_MAX_NLIST 8192
+#define AMP_N_FEAT 5
+
+typedef struct amp_index amp_index;
+
+/*
+ * Arrays of an IVF-PQ index (Sec. 2.1).  All host pointers, read during
+ * amp_index_from_arrays and copied.  N = list_offsets[nlist].
+ *   centroids    [nlist][d] float   coarse centroids
+ *   codebook     [M][256][d/M] float  residual PQ codebook shared by all lists
+ *   list_offsets [nlist+1] int64    list p holds positions [off[p], off[p+1])
+ *   ids          [N] int64          id of each position; strictly increasing
+ *                                   inside each list (ties in the search are
+ *                                   broken by id)
+ *   codes        [N][M] uint8       PQ codes by position
+ *   radq         [nlist] int32      list radius max ||x - c|| in grid units
+ * grid_e: the LC operand grid step is h = 2^grid_e; grid_kind selects the
+ * 9-bit integer grid (|v| <= 255) or the e4m3-representable integers.
+ * Constraints: d % M == 0, d/M <= 8, M even, M % 4 == 0, nlist <= 8192.
+ */
+typedef struct amp_index_arrays {
+  int32_t d, M, nlist, metric, grid_kind, grid_e;
+  const float* centroids;
+  const float* codebook;
+  const int64_t* list_offsets;
+  const int64_t* ids;
+  const uint8_t* codes;
+  const int32_t* radq;
+} amp_index_arrays;
+
+/*
+ * Fixed-point RBF support-vector regressor of the precision predictor
+ * (Sec. 3.4: Gaussian kernel read from a table at run time).  For pair
+ * (q, p) with features x = {d', r1, r2, n1, n2} (Sec. 3.3):
+ *   L_f = 256*k + ((y << 8) >> k) - 256,  y = x_f + 1, k = leading-bit index
+ *   u_f = clamp(((L_f - feat_lo[f]) * feat_mul[f]) >> 16, 0, 1023)
+ *   y   = beta0 + sum_i beta[i] * table[min(1023, (g_mul * |u - sv_i|^2) >> 32)]
+ *   bits = smallest allowed b in {4,8,12} with y + margin <= theta[b/4-1],
+ *          else the largest allowed width.
+ * sv [n_sv][5] int32, beta [n_sv] int32 (Q20), table [1024] int32 (Q20),
+ * beta0 and theta in Q40.  n_sv <= 4096.  Host pointers, copied.
+ */
+typedef struct amp_predictor_model {
+  int32_t n_sv;
+  const int32_t* sv;
+  const int32_t* beta;
+  const int32_t* table;
+  int64_t beta0;
+  int64_t feat_lo[AMP_N_FEAT];
+  int64_t feat_mul[AMP_N_FEAT];
+  uint64_t g_mul;
+  int64_t theta[3];
+} amp_predictor_model;
+
+/*
+ * Precision policy of a search.
+ *   kind              AMP_POLICY_*
+ *   fixed_bits        width for AMP_POLICY_FIXED: 4, 8, 12 or 16
+ *   allowed_bits_mask bit b set => width b allowed (ADAPTIVE); 0 = all four
+ *   lut_dtype         AMP_LUT_* matrix dtype of the integer LUT build
+ *                     (0 = BF16); the result does not depend on it
+ *   margin_q40        added to the regressor score before thresholding
+ *   explicit_bits     host [nq][npmax] uint8 widths by probe rank (EXPLICIT)
+ */
+typedef struct amp_precision_policy {
+  int32_t kind;
+  int32_t fixed_bits;
+  uint32_t allowed_bits_mask;
+  int32_t lut_dtype;
+  int64_t margin_q40;
+  const uint8_t* explicit_bits;
+} amp_precision_policy;
+
+/*
+ * Options of a search.  Optional outputs (NULL = not wanted) live in the
+ * same memory space as the main outputs (opts.mem):
+ *   out_qdist  [nq][kmax] int64  integer distance estimates (-1 under FP32)
+ *   out_probes [nq][npmax] int32 probed lists by rank (-1 padded)
+ *   out_bits   [nq][npmax] uint8 LUT width of each probed list (32 = FP32)
+ *   out_coarse [nq][nlist] float coarse (CL) distances
+ * stage_ms (host, [AMP_N_STAGES] float, optional): per-stage GPU time of this
+ * call from events on the stream; forces a synchronisation at the end.
+ */
+#define AMP_N_STAGES 8
+typedef struct amp_search_opts {
+  int32_t mem;
+  void* stream;
+  int64_t* out_qdist;
+  int32_t* out_probes;
+  uint8_t* out_bits;
+  float* out_coarse;
+  float* stage_ms;
+} amp_search_opts;
+
+/* Build an index handle from arrays (copied).  Validates every constraint
+ * listed with amp_index_arrays, including id order inside lists. */
+amp_status amp_index_from_arrays(const amp_index_arrays* arrays, amp_index** out);
+
+/* Attach (or replace) the precision predictor of an index (copied). */
+amp_status amp_index_set_predictor(amp_index* index, const amp_predictor_model* model);
+
+/*
+ * Offline fit of the precision predictor (Sec. 3.3-3.4) on training queries
+ * (host [nq][d] float).  For every (query, probed list) pair of a search at
+ * (k, nprobe) the trainer computes the features {d', r1, r2, n1, n2} and a
+ * label: the smallest allowed width whose worst-case LUT quantisation error
+ * M * 2^(s-1) stays below the list's margin between the query's k neighbours
+ * and its non-neighbours (exact integer ADC distances on the operand grid,
+ * Sec. 3.3 label definition).  It keeps n_samples pairs stratified by label,
+ * fits an epsilon-SVR with the Gaussian kernel exp(-gamma |du|^2) on the
+ * 10-bit feature grid by SMO (at most max_iter pair updates, tolerance tol),
+ * exports it to fixed point and attaches it to the index.  Host computation
+ * only; the search kernels evaluate the model.
+ */
+typedef struct amp_train_params {
+  int32_t n_samples;          /* paper: 1280 */
+  int32_t max_iter;           /* 0 = 100000 */
+  double gamma, C, epsilon, tol;
+  uint32_t allowed_bits_mask; /* 0 = {4, 8, 12, 16} */
+  uint64_t seed;
+} amp_train_params;
+
+typedef struct amp_train_report {
+  int64_t n_pairs;            /* labelled pairs */
+  int64_t label_hist[4];      /* pairs labelled 4, 8, 12, 16 bits */
+  int32_t n_samples, n_sv, smo_iterations;
+  double train_rmse;          /* of the real-valued regressor on the sample */
+} amp_train_report;
+
+amp_status amp_index_train_predictor(amp_index* index, const float* train_queries, int64_t nq,
+                                     int32_t k, int32_t nprobe, const amp_train_params* params,
+                                     amp_train_report* report /* optional */);
+
+/* Copy the index's predictor into caller buffers: sv [capacity][5], beta
+ * [capacity], table [1024] (host).  out->n_sv is always set; if capacity is
+ * below it nothing else is written and AMP_EINVAL is returned, so a first
+ * call with capacity 0 sizes the buffers.  AMP_EINVAL if no predictor. */
+amp_status amp_index_get_predictor(const amp_index* index, amp_predictor_model* out, int32_t* sv,
+                                   int32_t* beta, int32_t* table, int32_t capacity);
+
+/* Copy the index to device `device` (hipGetDevice numbering) and derive the
+ * device-side tables (centroid norms, grid codebook).  Called implicitly by
+ * the first search on the current device. */
+amp_status amp_index_to_device(amp_index* index, int32_t device);
+
+/* Versioned binary file with a checksum per section. */
+amp_status amp_index_save(const amp_index* index, const char* path);
+amp_status amp_index_load(const char* path, amp_index** out);
+
+/* Basic properties: d, M, nlist, N (any pointer may be NULL). */
+amp_status amp_index_info(const amp_index* index, int32_t* d, int32_t* M,
+                          int32_t* nlist, int64_t* n);
+
+/*
+ * Search nq queries ([nq][d] float, row-major).  k and nprobe are host
+ * arrays of nq entries when per_query != 0, else single values; kmax and
+ * npmax are their maxima.  Outputs: out_ids [nq][kmax] int64 and out_dist
+ * [nq][kmax] float (h^2 * integer estimate for integer policies, FP32 sum for
+ * the FP32 policy).  Requires 1 <= k <= AMP_MAX_K, 1 <= nprobe <=
+ * min(nlist, AMP_MAX_NPROBE); AMP_POLICY_ADAPTIVE requires a predictor.
+ */
+amp_status amp_search(amp_index* index, const float* queries, int64_t nq,
+                      const int32_t* k, const int32_t* nprobe, int32_t per_query,
+                      const amp_precision_policy* policy, const amp_search_opts* opts,
+                      int64_t* out_ids, float* out_dist);
+
+void amp_index_free(amp_index* index);
+const char* amp_status_str(amp_status status);
+const char* amp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AMP_H */

@@ -15,4 +15,4 @@ from .search import (  # noqa: F401
     index_grid, lut_int, lut_f64, quantize_lut, mitchell_log2_q8,
     feature_u, svr_eval, bits_from_score, predict_pair_bits, search,
 )
-from .exact import exact_knn, recall_at  # noqa: F401
+from .exact import exact_knn, recall_1_at, recall_at  # noqa: F401

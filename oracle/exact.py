@@ -35,3 +35,12 @@ def recall_at(found, truth, r=None):
     r = r or found.shape[1]
     hits = [len(set(f[:r].tolist()) & set(t.tolist())) for f, t in zip(found, truth)]
     return float(np.mean(hits)) / truth.shape[1]
+
+
+def recall_1_at(found, truth, r=None):
+    """1-recall@r: fraction of queries whose exact nearest neighbour is among
+    the first r returned ids."""
+    found = np.asarray(found)
+    truth = np.asarray(truth)
+    r = r or found.shape[1]
+    return float(np.mean([t[0] in set(f[:r].tolist()) for f, t in zip(found, truth)]))

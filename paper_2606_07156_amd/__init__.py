@@ -1,0 +1,298 @@
+"""Python binding of the MI355X adaptive-precision IVF-PQ search library.
+
+Thin ctypes marshalling over the C ABI declared in include/amp.h; every
+function keeps the C name.  Numpy arrays are passed for host memory, torch
+CUDA tensors (via data_ptr) for device memory.  No search arithmetic happens
+here: if the HIP library is missing, loading fails with an error.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libamp.so")
+
+AMP_OK, AMP_EINVAL, AMP_ENOMEM, AMP_EDEVICE, AMP_EIO, AMP_EFORMAT = 0, -1, -2, -3, -4, -5
+AMP_EBUSY, AMP_ECANCELED, AMP_EUNSUPPORTED, AMP_EOVERFLOW = -6, -7, -8, -9
+AMP_L2, AMP_IP = 0, 1
+AMP_GRID_U9, AMP_GRID_E4M3 = 0, 1
+AMP_MEM_HOST, AMP_MEM_DEVICE = 0, 1
+AMP_POLICY_FP32, AMP_POLICY_FIXED, AMP_POLICY_ADAPTIVE, AMP_POLICY_EXPLICIT = 0, 1, 2, 3
+AMP_LUT_BF16, AMP_LUT_F16, AMP_LUT_F8E4M3 = 1, 2, 3
+AMP_N_STAGES = 8
+STAGES = ("cl", "topn", "predict", "queue", "scan1", "scan2", "merge", "total")
+POLICIES = {"fp32": AMP_POLICY_FP32, "fixed": AMP_POLICY_FIXED,
+            "adaptive": AMP_POLICY_ADAPTIVE, "explicit": AMP_POLICY_EXPLICIT}
+
+
+class AmpError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class _Arrays(C.Structure):
+    _fields_ = [("d", C.c_int32), ("M", C.c_int32), ("nlist", C.c_int32), ("metric", C.c_int32),
+                ("grid_kind", C.c_int32), ("grid_e", C.c_int32),
+                ("centroids", C.c_void_p), ("codebook", C.c_void_p), ("list_offsets", C.c_void_p),
+                ("ids", C.c_void_p), ("codes", C.c_void_p), ("radq", C.c_void_p)]
+
+
+class _Model(C.Structure):
+    _fields_ = [("n_sv", C.c_int32), ("sv", C.c_void_p), ("beta", C.c_void_p), ("table", C.c_void_p),
+                ("beta0", C.c_int64), ("feat_lo", C.c_int64 * 5), ("feat_mul", C.c_int64 * 5),
+                ("g_mul", C.c_uint64), ("theta", C.c_int64 * 3)]
+
+
+class _Policy(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("fixed_bits", C.c_int32), ("allowed_bits_mask", C.c_uint32),
+                ("lut_dtype", C.c_int32), ("margin_q40", C.c_int64), ("explicit_bits", C.c_void_p)]
+
+
+class _Opts(C.Structure):
+    _fields_ = [("mem", C.c_int32), ("stream", C.c_void_p), ("out_qdist", C.c_void_p),
+                ("out_probes", C.c_void_p), ("out_bits", C.c_void_p), ("out_coarse", C.c_void_p),
+                ("stage_ms", C.c_void_p)]
+
+
+class _TrainParams(C.Structure):
+    _fields_ = [("n_samples", C.c_int32), ("max_iter", C.c_int32), ("gamma", C.c_double),
+                ("C", C.c_double), ("epsilon", C.c_double), ("tol", C.c_double),
+                ("allowed_bits_mask", C.c_uint32), ("seed", C.c_uint64)]
+
+
+class _TrainReport(C.Structure):
+    _fields_ = [("n_pairs", C.c_int64), ("label_hist", C.c_int64 * 4), ("n_samples", C.c_int32),
+                ("n_sv", C.c_int32), ("smo_iterations", C.c_int32), ("train_rmse", C.c_double)]
+
+
+_lib = None
+EXPORTS = ("amp_index_from_arrays", "amp_index_set_predictor", "amp_index_get_predictor",
+           "amp_index_train_predictor",
+           "amp_index_to_device",
+           "amp_index_save", "amp_index_load", "amp_index_info", "amp_search",
+           "amp_index_free", "amp_status_str", "amp_last_error")
+
+
+def lib():
+    """Load libamp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2606_07156_amd/build.py")
+        try:
+            # load torch's HIP runtime first: the library then binds to the
+            # same runtime (matched by soname), so device pointers and streams
+            # are shared with torch in this process
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        L = C.CDLL(LIB_PATH)
+        L.amp_index_from_arrays.argtypes = [C.POINTER(_Arrays), C.POINTER(C.c_void_p)]
+        L.amp_index_set_predictor.argtypes = [C.c_void_p, C.POINTER(_Model)]
+        L.amp_index_get_predictor.argtypes = [C.c_void_p, C.POINTER(_Model), C.c_void_p, C.c_void_p,
+                                              C.c_void_p, C.c_int32]
+        L.amp_index_train_predictor.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32,
+                                                C.POINTER(_TrainParams), C.POINTER(_TrainReport)]
+        L.amp_index_to_device.argtypes = [C.c_void_p, C.c_int32]
+        L.amp_index_save.argtypes = [C.c_void_p, C.c_char_p]
+        L.amp_index_load.argtypes = [C.c_char_p, C.POINTER(C.c_void_p)]
+        L.amp_index_info.argtypes = [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                     C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
+        L.amp_search.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_int32,
+                                 C.POINTER(_Policy), C.POINTER(_Opts), C.c_void_p, C.c_void_p]
+        L.amp_index_free.argtypes = [C.c_void_p]
+        L.amp_index_free.restype = None
+        L.amp_status_str.argtypes = [C.c_int32]
+        L.amp_status_str.restype = C.c_char_p
+        L.amp_last_error.restype = C.c_char_p
+        for name in EXPORTS:
+            if name not in ("amp_index_free", "amp_status_str", "amp_last_error"):
+                getattr(L, name).restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def amp_status_str(status):
+    return lib().amp_status_str(status).decode()
+
+
+def amp_last_error():
+    return lib().amp_last_error().decode()
+
+
+def _check(status):
+    if status != AMP_OK:
+        raise AmpError(status, f"{amp_status_str(status)}: {amp_last_error()}")
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return C.c_void_p(a.data_ptr())
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class Index:
+    """Owning wrapper of an amp_index handle."""
+
+    def __init__(self, handle):
+        self.handle = C.c_void_p(handle)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and self.handle.value and _lib is not None:
+            _lib.amp_index_free(self.handle)
+            self.handle = C.c_void_p(None)
+
+    def free(self):
+        self.__del__()
+
+
+def amp_index_from_arrays(ix):
+    """``ix``: dict as produced by amp_data.build_index."""
+    keep = dict(
+        centroids=np.ascontiguousarray(ix["centroids"], dtype=np.float32),
+        codebook=np.ascontiguousarray(ix["codebook"], dtype=np.float32),
+        offsets=np.ascontiguousarray(ix["list_offsets"], dtype=np.int64),
+        ids=np.ascontiguousarray(ix["ids"], dtype=np.int64),
+        codes=np.ascontiguousarray(ix["codes"], dtype=np.uint8),
+        radq=np.ascontiguousarray(ix["radq"], dtype=np.int32),
+    )
+    a = _Arrays(int(ix["d"]), int(ix["M"]), int(ix["nlist"]),
+                AMP_L2 if ix.get("metric", "l2") == "l2" else AMP_IP,
+                AMP_GRID_U9 if ix.get("grid_kind", "u9") == "u9" else AMP_GRID_E4M3,
+                int(ix["grid_e"]), _ptr(keep["centroids"]), _ptr(keep["codebook"]),
+                _ptr(keep["offsets"]), _ptr(keep["ids"]), _ptr(keep["codes"]), _ptr(keep["radq"]))
+    h = C.c_void_p()
+    _check(lib().amp_index_from_arrays(C.byref(a), C.byref(h)))
+    return Index(h.value)
+
+
+def amp_index_set_predictor(index, model):
+    sv = np.ascontiguousarray(model["sv"], dtype=np.int32)
+    beta = np.ascontiguousarray(model["beta"], dtype=np.int32)
+    table = np.ascontiguousarray(model["table"], dtype=np.int32)
+    m = _Model(int(model["n_sv"]), _ptr(sv), _ptr(beta), _ptr(table), int(model["beta0"]),
+               (C.c_int64 * 5)(*[int(v) for v in model["feat_lo"]]),
+               (C.c_int64 * 5)(*[int(v) for v in model["feat_mul"]]),
+               int(model["g_mul"]), (C.c_int64 * 3)(*[int(v) for v in model["theta"]]))
+    _check(lib().amp_index_set_predictor(index.handle, C.byref(m)))
+
+
+def amp_index_get_predictor(index):
+    """The index's predictor as a model dict (the format amp_index_set_predictor takes)."""
+    m = _Model()
+    st = lib().amp_index_get_predictor(index.handle, C.byref(m), None, None, None, 0)
+    n = m.n_sv
+    if st != AMP_OK and n == 0 and "no predictor" in amp_last_error():
+        _check(st)
+    sv = np.zeros((max(n, 1), 5), np.int32)
+    beta = np.zeros(max(n, 1), np.int32)
+    table = np.zeros(1024, np.int32)
+    _check(lib().amp_index_get_predictor(index.handle, C.byref(m), _ptr(sv), _ptr(beta), _ptr(table), n))
+    return dict(n_sv=n, sv=sv[:n], beta=beta[:n], table=table, beta0=m.beta0,
+                feat_lo=np.array(m.feat_lo[:], np.int64), feat_mul=np.array(m.feat_mul[:], np.int64),
+                g_mul=int(m.g_mul), theta=np.array(m.theta[:], np.int64))
+
+
+def amp_index_train_predictor(index, train_queries, k, nprobe, n_samples=1280, gamma=1.0, C_=1.0,
+                              epsilon=0.05, tol=1e-3, max_iter=0, allowed=(4, 8, 12, 16), seed=0):
+    """Fit and attach the precision predictor; returns the training report."""
+    q = np.ascontiguousarray(train_queries, dtype=np.float32)
+    mask = 0
+    for b in allowed:
+        mask |= 1 << int(b)
+    p = _TrainParams(int(n_samples), int(max_iter), float(gamma), float(C_), float(epsilon), float(tol),
+                     mask, int(seed))
+    r = _TrainReport()
+    _check(lib().amp_index_train_predictor(index.handle, _ptr(q), int(q.shape[0]), int(k), int(nprobe),
+                                           C.byref(p), C.byref(r)))
+    return dict(n_pairs=r.n_pairs, label_hist=list(r.label_hist), n_samples=r.n_samples, n_sv=r.n_sv,
+                smo_iterations=r.smo_iterations, train_rmse=r.train_rmse)
+
+
+def amp_index_to_device(index, device=0):
+    _check(lib().amp_index_to_device(index.handle, int(device)))
+
+
+def amp_index_save(index, path):
+    _check(lib().amp_index_save(index.handle, str(path).encode()))
+
+
+def amp_index_load(path):
+    h = C.c_void_p()
+    _check(lib().amp_index_load(str(path).encode(), C.byref(h)))
+    return Index(h.value)
+
+
+def amp_index_info(index):
+    d, M, nl, n = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int64()
+    _check(lib().amp_index_info(index.handle, C.byref(d), C.byref(M), C.byref(nl), C.byref(n)))
+    return dict(d=d.value, M=M.value, nlist=nl.value, n=n.value)
+
+
+def make_policy(policy="fixed", bits=16, allowed=(4, 8, 12, 16), margin_q40=0,
+                explicit_bits=None, lut_dtype=0):
+    mask = 0
+    for b in allowed:
+        mask |= 1 << int(b)
+    xb = None if explicit_bits is None else np.ascontiguousarray(explicit_bits, dtype=np.uint8)
+    pol = _Policy(POLICIES[policy], int(bits), mask, int(lut_dtype), int(margin_q40), _ptr(xb))
+    return pol, xb
+
+
+def amp_search(index, queries, k, nprobe, policy="fixed", bits=16, allowed=(4, 8, 12, 16),
+               margin_q40=0, explicit_bits=None, lut_dtype=0, want_qdist=True,
+               want_probes=False, want_bits=False, want_coarse=False, stage_ms=False,
+               out=None, stream=None):
+    """Search a batch.
+
+    Host mode (``queries`` a numpy array): returns a dict of numpy arrays.
+    Device mode (``queries`` a torch CUDA tensor): ``out`` must be a dict of
+    preallocated torch CUDA tensors ids [nq,kmax] int64, dist [nq,kmax] float32
+    and optionally qdist / probes / bits / coarse; work is enqueued on
+    ``stream`` (a torch stream or raw handle) and the call returns at once.
+    """
+    device = hasattr(queries, "data_ptr")
+    nq = int(queries.shape[0])
+    kk = np.atleast_1d(np.asarray(k, dtype=np.int32))
+    npb = np.atleast_1d(np.asarray(nprobe, dtype=np.int32))
+    per_query = int(kk.size > 1 or npb.size > 1)
+    if per_query:
+        kk = np.ascontiguousarray(np.broadcast_to(kk, (nq,)), dtype=np.int32)
+        npb = np.ascontiguousarray(np.broadcast_to(npb, (nq,)), dtype=np.int32)
+    kmax, npmax = int(kk.max()), int(npb.max())
+    pol, xb = make_policy(policy, bits, allowed, margin_q40, explicit_bits, lut_dtype)
+    ms = np.zeros(AMP_N_STAGES, dtype=np.float32) if stage_ms else None
+    if device:
+        o = out
+        sh = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+        opts = _Opts(AMP_MEM_DEVICE, C.c_void_p(sh) if sh else None, _ptr(o.get("qdist")),
+                     _ptr(o.get("probes")), _ptr(o.get("bits")), _ptr(o.get("coarse")), _ptr(ms))
+        _check(lib().amp_search(index.handle, _ptr(queries), nq, _ptr(kk), _ptr(npb), per_query,
+                                C.byref(pol), C.byref(opts), _ptr(o["ids"]), _ptr(o["dist"])))
+        if stage_ms:
+            o["stage_ms"] = dict(zip(STAGES, ms.tolist()))
+        return o
+    q = np.ascontiguousarray(queries, dtype=np.float32)
+    res = dict(ids=np.empty((nq, kmax), np.int64), dist=np.empty((nq, kmax), np.float32))
+    if want_qdist:
+        res["qdist"] = np.empty((nq, kmax), np.int64)
+    if want_probes:
+        res["probes"] = np.empty((nq, npmax), np.int32)
+    if want_bits:
+        res["bits"] = np.empty((nq, npmax), np.uint8)
+    if want_coarse:
+        info = amp_index_info(index)
+        res["coarse"] = np.empty((nq, info["nlist"]), np.float32)
+    opts = _Opts(AMP_MEM_HOST, None, _ptr(res.get("qdist")), _ptr(res.get("probes")),
+                 _ptr(res.get("bits")), _ptr(res.get("coarse")), _ptr(ms))
+    _check(lib().amp_search(index.handle, _ptr(q), nq, _ptr(kk), _ptr(npb), per_query,
+                            C.byref(pol), C.byref(opts), _ptr(res["ids"]), _ptr(res["dist"])))
+    if stage_ms:
+        res["stage_ms"] = dict(zip(STAGES, ms.tolist()))
+    return res

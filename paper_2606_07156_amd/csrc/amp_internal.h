@@ -1,0 +1,157 @@
+// Internal declarations shared by the host side (capi.cpp) and the kernels
+// (kernels.hip) of the adaptive-precision IVF-PQ search library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/amp.h"
+
+namespace amp {
+
+// -------------------------------------------------------------- constants
+constexpr int kKsub = AMP_KSUB;
+constexpr int kThreads = 256;          // threads per workgroup of the scan
+constexpr int kMaxDsub = 8;            // one MFMA lane group holds a subspace
+constexpr int kTableN = 1024;          // predictor kernel table entries
+constexpr int kNCls = 3;               // LUT lane-width classes: 8, 16, 32 bit
+
+// lane-width class of a b-bit LUT for M subspaces: the sum of M entries of at
+// most 2^b - 1 must fit in the lane
+inline int lane_class(int M, int b) {
+  uint64_t top = (uint64_t)M * ((1ull << b) - 1);
+  if (top <= 0xFFull) return 0;
+  if (top <= 0xFFFFull) return 1;
+  return 2;
+}
+inline int lane_bits(int cls) { return 8 << cls; }
+
+// -------------------------------------------------------------- device data
+struct DeviceModel {
+  int32_t n_sv = 0;
+  int32_t* sv = nullptr;       // [n_sv][5]
+  int32_t* beta = nullptr;     // [n_sv]
+  int32_t* table = nullptr;    // [1024]
+};
+
+struct DeviceIndex {
+  int device = -1;
+  float* centroids = nullptr;  // [nlist][d]
+  float* cnorm = nullptr;      // [nlist] squared norms (FP32, sequential order)
+  float* codebook = nullptr;   // [M][256][dsub]
+  uint4* bsw = nullptr;        // [M/2][16][64] MFMA B fragments (8 bf16 each)
+  uint8_t* codes = nullptr;    // [N][M]
+  int64_t* ids = nullptr;      // [N]
+  int64_t* offsets = nullptr;  // [nlist+1]
+  int32_t* radq = nullptr;     // [nlist]
+  DeviceModel model;
+};
+
+// Scratch of one search, grown on demand and kept with the index.
+struct Workspace {
+  std::vector<void*> blocks;
+  size_t cap_nq = 0, cap_np = 0, cap_k = 0;
+  // per query
+  float* queries = nullptr;    // [nq][d] (host-mode staging)
+  int32_t* kq = nullptr;       // [nq]
+  int32_t* npq = nullptr;      // [nq]
+  float* qnorm = nullptr;      // [nq]
+  float* coarse = nullptr;     // [nq][nlist]
+  int32_t* probes = nullptr;   // [nq][npmax]
+  float* pdist = nullptr;      // [nq][npmax]
+  uint8_t* pbits = nullptr;    // [nq][npmax]
+  uint8_t* xbits = nullptr;    // [nq][npmax] explicit widths (uploaded)
+  uint64_t* tau = nullptr;     // [nq] pruning threshold key
+  uint32_t* ccount = nullptr;  // [nq] candidate count
+  uint64_t* ckey = nullptr;    // [nq][capq]
+  int64_t* cid = nullptr;      // [nq][capq]
+  // queue (buckets are class-major: b = cls * nlist + list)
+  int32_t* cnt = nullptr;      // [2][NB]   pairs per bucket (phase 1, phase 2)
+  int32_t* rank = nullptr;     // [2][nq*npmax] rank of a pair inside its bucket
+  int4* units = nullptr;       // [2][max_units] work units
+  int64_t cap_units = 0;
+  int64_t* pairoff = nullptr;  // [2][NB+1]
+  int64_t* unitoff = nullptr;  // [2][NB+1]
+  int32_t* sorted = nullptr;   // [2][nq*npmax]
+  uint32_t* counters = nullptr;// [2][kNCls+1] unit counters
+  int32_t* flags = nullptr;    // [4]: overflow, ...
+  // outputs staged for host mode
+  int64_t* o_ids = nullptr;
+  float* o_dist = nullptr;
+  int64_t* o_qdist = nullptr;
+  size_t capq = 0;
+};
+
+}  // namespace amp
+
+struct amp_index {
+  // host copies
+  int32_t d = 0, M = 0, dsub = 0, nlist = 0, metric = 0, grid_kind = 0, grid_e = 0;
+  int64_t n = 0, max_list = 0;
+  std::vector<float> centroids, codebook;
+  std::vector<int64_t> offsets, ids;
+  std::vector<uint8_t> codes;
+  std::vector<int32_t> radq, sizes;
+  // predictor (host copy)
+  bool has_model = false;
+  int32_t n_sv = 0;
+  std::vector<int32_t> sv, beta, table;
+  int64_t beta0 = 0, feat_lo[5] = {}, feat_mul[5] = {}, theta[3] = {};
+  uint64_t g_mul = 0;
+  // device side
+  amp::DeviceIndex dev;
+  bool dev_model_stale = true;
+  amp::Workspace ws;
+  std::mutex mu;
+};
+
+namespace amp {
+
+// -------------------------------------------------------------- errors
+amp_status set_error(amp_status s, const char* fmt, ...);
+#define AMP_HIP(call)                                                        \
+  do {                                                                       \
+    hipError_t e_ = (call);                                                  \
+    if (e_ != hipSuccess)                                                    \
+      return ::amp::set_error(AMP_EDEVICE, "%s failed: %s", #call,          \
+                              hipGetErrorString(e_));                        \
+  } while (0)
+
+// -------------------------------------------------------------- launches
+struct SearchDims {
+  int nq, d, M, dsub, nlist, npmax, kmax, metric, grid_kind, grid_e;
+  int kconst, npconst;   // used when the per-query arrays are null
+  int wpr;               // LUT words per row
+  int64_t chunk;         // list chunk length of one work unit
+  int64_t max_units;     // capacity of each phase's unit table
+  size_t capq;
+  int policy;            // AMP_POLICY_*
+  int fixed_bits;
+  uint32_t allowed_mask;
+  int64_t margin;
+};
+
+struct ModelArgs {
+  int32_t n_sv;
+  const int32_t* sv;
+  const int32_t* beta;
+  const int32_t* table;
+  int64_t beta0;
+  int64_t feat_lo[5];
+  int64_t feat_mul[5];
+  uint64_t g_mul;
+  int64_t theta[3];
+};
+
+hipError_t launch_prep_index(const amp_index* ix, hipStream_t st);
+hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* queries,
+                         const SearchDims& sd, const ModelArgs& ma, int64_t* out_ids,
+                         float* out_dist, int64_t* out_qdist, float* out_coarse,
+                         hipStream_t st, hipEvent_t* ev /* [AMP_N_STAGES+1] or null */);
+size_t scan_lds_bytes(int lw_bits, int phase, int M, int d);
+int scan_wpr(int M);
+
+}  // namespace amp

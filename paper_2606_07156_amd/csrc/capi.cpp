@@ -1,0 +1,607 @@
+// C ABI of the adaptive-precision IVF-PQ search: argument validation, index
+// residency on the device, the index file format and the search driver.  All
+// arithmetic of a search runs in the kernels of kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "amp_internal.h"
+
+namespace amp {
+
+static thread_local char g_err[512] = "";
+
+amp_status set_error(amp_status s, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return s;
+}
+
+static size_t env_size(const char* name, size_t dflt) {
+  const char* v = getenv(name);
+  if (!v || !*v) return dflt;
+  long long x = atoll(v);
+  return x > 0 ? (size_t)x : dflt;
+}
+
+template <typename T>
+static amp_status dalloc(T** p, size_t n, std::vector<void*>* track = nullptr) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), n * sizeof(T));
+  if (e != hipSuccess) {
+    hipGetLastError();
+    return set_error(AMP_ENOMEM, "hipMalloc of %zu bytes failed: %s", n * sizeof(T), hipGetErrorString(e));
+  }
+  if (track) track->push_back(*p);
+  return AMP_OK;
+}
+
+static void free_device_index(DeviceIndex& d) {
+  void* ptrs[] = {d.centroids, d.cnorm, d.codebook, d.bsw, d.codes, d.ids, d.offsets, d.radq,
+                  d.model.sv, d.model.beta, d.model.table};
+  for (void* p : ptrs)
+    if (p) hipFree(p);
+  d = DeviceIndex();
+}
+
+static void free_workspace(Workspace& w) {
+  for (void* p : w.blocks) hipFree(p);
+  w = Workspace();
+}
+
+}  // namespace amp
+
+using namespace amp;
+
+extern "C" {
+
+const char* amp_status_str(amp_status s) {
+  switch (s) {
+    case AMP_OK: return "ok";
+    case AMP_EINVAL: return "invalid argument";
+    case AMP_ENOMEM: return "out of memory";
+    case AMP_EDEVICE: return "device error";
+    case AMP_EIO: return "i/o error";
+    case AMP_EFORMAT: return "bad index file";
+    case AMP_EBUSY: return "busy";
+    case AMP_ECANCELED: return "canceled";
+    case AMP_EUNSUPPORTED: return "unsupported";
+    case AMP_EOVERFLOW: return "candidate buffer overflow";
+    default: return "unknown status";
+  }
+}
+
+const char* amp_last_error(void) { return g_err; }
+
+amp_status amp_index_from_arrays(const amp_index_arrays* a, amp_index** out) {
+  if (!a || !out) return set_error(AMP_EINVAL, "null argument");
+  *out = nullptr;
+  if (!a->centroids || !a->codebook || !a->list_offsets || !a->ids || !a->codes || !a->radq)
+    return set_error(AMP_EINVAL, "null array in amp_index_arrays");
+  if (a->d <= 0 || a->M <= 0 || a->nlist <= 0) return set_error(AMP_EINVAL, "d, M, nlist must be positive");
+  if (a->d % a->M) return set_error(AMP_EINVAL, "d (%d) must be a multiple of M (%d)", a->d, a->M);
+  if (a->d / a->M > kMaxDsub) return set_error(AMP_EUNSUPPORTED, "d/M = %d > %d", a->d / a->M, kMaxDsub);
+  if (a->M % 4) return set_error(AMP_EUNSUPPORTED, "M (%d) must be a multiple of 4", a->M);
+  if (a->nlist > AMP_MAX_NLIST) return set_error(AMP_EINVAL, "nlist %d > %d", a->nlist, AMP_MAX_NLIST);
+  if (a->metric != AMP_L2 && a->metric != AMP_IP) return set_error(AMP_EINVAL, "bad metric %d", a->metric);
+  if (a->grid_kind != AMP_GRID_U9 && a->grid_kind != AMP_GRID_E4M3)
+    return set_error(AMP_EINVAL, "bad grid kind %d", a->grid_kind);
+  if (a->grid_e < -60 || a->grid_e > 60) return set_error(AMP_EINVAL, "grid exponent out of range");
+  if (a->list_offsets[0] != 0) return set_error(AMP_EINVAL, "list_offsets[0] must be 0");
+  for (int p = 0; p < a->nlist; ++p)
+    if (a->list_offsets[p + 1] < a->list_offsets[p]) return set_error(AMP_EINVAL, "list_offsets not monotone");
+  const int64_t n = a->list_offsets[a->nlist];
+  if (n >= (1ll << 31)) return set_error(AMP_EUNSUPPORTED, "more than 2^31 vectors");
+  for (int p = 0; p < a->nlist; ++p)
+    for (int64_t i = a->list_offsets[p] + 1; i < a->list_offsets[p + 1]; ++i)
+      if (a->ids[i] <= a->ids[i - 1])
+        return set_error(AMP_EINVAL, "ids not strictly increasing inside list %d", p);
+  amp_index* ix = new (std::nothrow) amp_index();
+  if (!ix) return set_error(AMP_ENOMEM, "host allocation failed");
+  try {
+    ix->d = a->d;
+    ix->M = a->M;
+    ix->dsub = a->d / a->M;
+    ix->nlist = a->nlist;
+    ix->metric = a->metric;
+    ix->grid_kind = a->grid_kind;
+    ix->grid_e = a->grid_e;
+    ix->n = n;
+    for (int p = 0; p < a->nlist; ++p)
+      ix->max_list = std::max<int64_t>(ix->max_list, a->list_offsets[p + 1] - a->list_offsets[p]);
+    ix->centroids.assign(a->centroids, a->centroids + (size_t)a->nlist * a->d);
+    ix->codebook.assign(a->codebook, a->codebook + (size_t)a->M * kKsub * ix->dsub);
+    ix->offsets.assign(a->list_offsets, a->list_offsets + a->nlist + 1);
+    ix->ids.assign(a->ids, a->ids + n);
+    ix->codes.assign(a->codes, a->codes + (size_t)n * a->M);
+    ix->radq.assign(a->radq, a->radq + a->nlist);
+  } catch (...) {
+    delete ix;
+    return set_error(AMP_ENOMEM, "host allocation failed");
+  }
+  *out = ix;
+  return AMP_OK;
+}
+
+amp_status amp_index_set_predictor(amp_index* ix, const amp_predictor_model* m) {
+  if (!ix || !m) return set_error(AMP_EINVAL, "null argument");
+  if (m->n_sv < 0 || m->n_sv > 4096) return set_error(AMP_EINVAL, "n_sv %d outside [0, 4096]", m->n_sv);
+  if ((m->n_sv && (!m->sv || !m->beta)) || !m->table) return set_error(AMP_EINVAL, "null model array");
+  if (m->g_mul >= (1ull << 32)) return set_error(AMP_EINVAL, "g_mul must be below 2^32");
+  std::lock_guard<std::mutex> lk(ix->mu);
+  ix->n_sv = m->n_sv;
+  ix->sv.assign(m->sv, m->sv + 5 * (size_t)m->n_sv);
+  ix->beta.assign(m->beta, m->beta + m->n_sv);
+  ix->table.assign(m->table, m->table + kTableN);
+  ix->beta0 = m->beta0;
+  for (int f = 0; f < 5; ++f) {
+    ix->feat_lo[f] = m->feat_lo[f];
+    ix->feat_mul[f] = m->feat_mul[f];
+  }
+  for (int i = 0; i < 3; ++i) ix->theta[i] = m->theta[i];
+  ix->g_mul = m->g_mul;
+  ix->has_model = true;
+  ix->dev_model_stale = true;
+  return AMP_OK;
+}
+
+amp_status amp_index_get_predictor(const amp_index* ix, amp_predictor_model* m, int32_t* sv, int32_t* beta,
+                                   int32_t* table, int32_t capacity) {
+  if (!ix || !m) return set_error(AMP_EINVAL, "null argument");
+  if (!ix->has_model) return set_error(AMP_EINVAL, "index has no predictor");
+  m->n_sv = ix->n_sv;
+  if (capacity < ix->n_sv) return set_error(AMP_EINVAL, "capacity %d below n_sv %d", capacity, ix->n_sv);
+  if ((ix->n_sv && (!sv || !beta)) || !table) return set_error(AMP_EINVAL, "null output buffer");
+  std::copy(ix->sv.begin(), ix->sv.end(), sv);
+  std::copy(ix->beta.begin(), ix->beta.end(), beta);
+  std::copy(ix->table.begin(), ix->table.end(), table);
+  m->sv = sv;
+  m->beta = beta;
+  m->table = table;
+  m->beta0 = ix->beta0;
+  for (int f = 0; f < 5; ++f) m->feat_lo[f] = ix->feat_lo[f], m->feat_mul[f] = ix->feat_mul[f];
+  for (int i = 0; i < 3; ++i) m->theta[i] = ix->theta[i];
+  m->g_mul = ix->g_mul;
+  return AMP_OK;
+}
+
+static amp_status upload_model(amp_index* ix) {
+  DeviceModel& dm = ix->dev.model;
+  if (dm.sv) hipFree(dm.sv);
+  if (dm.beta) hipFree(dm.beta);
+  if (dm.table) hipFree(dm.table);
+  dm = DeviceModel();
+  amp_status s;
+  if ((s = dalloc(&dm.sv, 5 * (size_t)std::max(1, ix->n_sv))) != AMP_OK) return s;
+  if ((s = dalloc(&dm.beta, (size_t)std::max(1, ix->n_sv))) != AMP_OK) return s;
+  if ((s = dalloc(&dm.table, (size_t)kTableN)) != AMP_OK) return s;
+  if (ix->n_sv) {
+    AMP_HIP(hipMemcpy(dm.sv, ix->sv.data(), ix->sv.size() * 4, hipMemcpyHostToDevice));
+    AMP_HIP(hipMemcpy(dm.beta, ix->beta.data(), ix->beta.size() * 4, hipMemcpyHostToDevice));
+  }
+  AMP_HIP(hipMemcpy(dm.table, ix->table.data(), kTableN * 4, hipMemcpyHostToDevice));
+  dm.n_sv = ix->n_sv;
+  ix->dev_model_stale = false;
+  return AMP_OK;
+}
+
+static amp_status to_device_locked(amp_index* ix, int device) {
+  if (ix->dev.device == device && ix->dev.centroids) return AMP_OK;
+  free_device_index(ix->dev);
+  free_workspace(ix->ws);
+  AMP_HIP(hipSetDevice(device));
+  DeviceIndex& d = ix->dev;
+  amp_status s;
+  const size_t nl = ix->nlist, dd = ix->d, M = ix->M, n = ix->n;
+  if ((s = dalloc(&d.centroids, nl * dd)) || (s = dalloc(&d.cnorm, nl)) ||
+      (s = dalloc(&d.codebook, M * kKsub * ix->dsub)) || (s = dalloc(&d.bsw, (M / 2) * 16 * 64)) ||
+      (s = dalloc(&d.codes, std::max<size_t>(1, n * M))) || (s = dalloc(&d.ids, std::max<size_t>(1, n))) ||
+      (s = dalloc(&d.offsets, nl + 1)) || (s = dalloc(&d.radq, nl))) {
+    free_device_index(d);
+    return s;
+  }
+  AMP_HIP(hipMemcpy(d.centroids, ix->centroids.data(), nl * dd * 4, hipMemcpyHostToDevice));
+  AMP_HIP(hipMemcpy(d.codebook, ix->codebook.data(), ix->codebook.size() * 4, hipMemcpyHostToDevice));
+  if (n) {
+    AMP_HIP(hipMemcpy(d.codes, ix->codes.data(), n * M, hipMemcpyHostToDevice));
+    AMP_HIP(hipMemcpy(d.ids, ix->ids.data(), n * 8, hipMemcpyHostToDevice));
+  }
+  AMP_HIP(hipMemcpy(d.offsets, ix->offsets.data(), (nl + 1) * 8, hipMemcpyHostToDevice));
+  AMP_HIP(hipMemcpy(d.radq, ix->radq.data(), nl * 4, hipMemcpyHostToDevice));
+  AMP_HIP(launch_prep_index(ix, nullptr));
+  AMP_HIP(hipDeviceSynchronize());
+  d.device = device;
+  ix->dev_model_stale = true;
+  return AMP_OK;
+}
+
+amp_status amp_index_to_device(amp_index* ix, int32_t device) {
+  if (!ix) return set_error(AMP_EINVAL, "null index");
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count == 0) {
+    hipGetLastError();
+    return set_error(AMP_EDEVICE, "no HIP device");
+  }
+  if (device < 0 || device >= count) return set_error(AMP_EINVAL, "device %d out of range", device);
+  std::lock_guard<std::mutex> lk(ix->mu);
+  return to_device_locked(ix, device);
+}
+
+amp_status amp_index_info(const amp_index* ix, int32_t* d, int32_t* M, int32_t* nlist, int64_t* n) {
+  if (!ix) return set_error(AMP_EINVAL, "null index");
+  if (d) *d = ix->d;
+  if (M) *M = ix->M;
+  if (nlist) *nlist = ix->nlist;
+  if (n) *n = ix->n;
+  return AMP_OK;
+}
+
+void amp_index_free(amp_index* ix) {
+  if (!ix) return;
+  if (ix->dev.device >= 0) hipSetDevice(ix->dev.device);
+  free_workspace(ix->ws);
+  free_device_index(ix->dev);
+  delete ix;
+}
+
+// ------------------------------------------------------------------ file format
+// "AMPIDX\0\1" | u32 version | i32 d, M, nlist, metric, grid_kind, grid_e | i64 n
+// | u32 has_model | sections: u32 tag, u64 bytes, u64 fnv1a-64, payload.
+static const char kMagic[8] = {'A', 'M', 'P', 'I', 'D', 'X', 0, 1};
+static const uint32_t kVersion = 1;
+
+static uint64_t fnv1a(const void* p, size_t n) {
+  const uint8_t* b = static_cast<const uint8_t*>(p);
+  uint64_t h = 1469598103934665603ull;
+  for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+  return h;
+}
+
+static bool wr(FILE* f, const void* p, size_t n) { return fwrite(p, 1, n, f) == n; }
+static bool wsec(FILE* f, uint32_t tag, const void* p, size_t n) {
+  uint64_t bytes = n, h = fnv1a(p, n);
+  return wr(f, &tag, 4) && wr(f, &bytes, 8) && wr(f, &h, 8) && (n == 0 || wr(f, p, n));
+}
+
+amp_status amp_index_save(const amp_index* ix, const char* path) {
+  if (!ix || !path) return set_error(AMP_EINVAL, "null argument");
+  FILE* f = fopen(path, "wb");
+  if (!f) return set_error(AMP_EIO, "cannot open %s for writing", path);
+  int32_t hdr[6] = {ix->d, ix->M, ix->nlist, ix->metric, ix->grid_kind, ix->grid_e};
+  uint32_t hm = ix->has_model ? 1 : 0;
+  bool ok = wr(f, kMagic, 8) && wr(f, &kVersion, 4) && wr(f, hdr, sizeof hdr) && wr(f, &ix->n, 8) && wr(f, &hm, 4);
+  ok = ok && wsec(f, 1, ix->centroids.data(), ix->centroids.size() * 4);
+  ok = ok && wsec(f, 2, ix->codebook.data(), ix->codebook.size() * 4);
+  ok = ok && wsec(f, 3, ix->offsets.data(), ix->offsets.size() * 8);
+  ok = ok && wsec(f, 4, ix->ids.data(), ix->ids.size() * 8);
+  ok = ok && wsec(f, 5, ix->codes.data(), ix->codes.size());
+  ok = ok && wsec(f, 6, ix->radq.data(), ix->radq.size() * 4);
+  if (hm) {
+    int64_t scal[15];
+    scal[0] = ix->n_sv;
+    scal[1] = ix->beta0;
+    for (int i = 0; i < 5; ++i) scal[2 + i] = ix->feat_lo[i], scal[7 + i] = ix->feat_mul[i];
+    scal[12] = ix->theta[0];
+    scal[13] = ix->theta[1];
+    scal[14] = ix->theta[2];
+    ok = ok && wsec(f, 7, scal, sizeof scal) && wsec(f, 8, &ix->g_mul, 8);
+    ok = ok && wsec(f, 9, ix->sv.data(), ix->sv.size() * 4) && wsec(f, 10, ix->beta.data(), ix->beta.size() * 4);
+    ok = ok && wsec(f, 11, ix->table.data(), ix->table.size() * 4);
+  }
+  ok = (fclose(f) == 0) && ok;
+  return ok ? AMP_OK : set_error(AMP_EIO, "write to %s failed", path);
+}
+
+static amp_status rsec(FILE* f, uint32_t tag, void* p, size_t n) {
+  uint32_t t;
+  uint64_t bytes, h;
+  if (fread(&t, 4, 1, f) != 1 || fread(&bytes, 8, 1, f) != 1 || fread(&h, 8, 1, f) != 1)
+    return set_error(AMP_EFORMAT, "truncated index file (section %u header)", tag);
+  if (t != tag || bytes != n) return set_error(AMP_EFORMAT, "section %u: unexpected tag/size", tag);
+  if (n && fread(p, 1, n, f) != n) return set_error(AMP_EFORMAT, "truncated index file (section %u)", tag);
+  if (fnv1a(p, n) != h) return set_error(AMP_EFORMAT, "checksum mismatch in section %u", tag);
+  return AMP_OK;
+}
+
+amp_status amp_index_load(const char* path, amp_index** out) {
+  if (!path || !out) return set_error(AMP_EINVAL, "null argument");
+  *out = nullptr;
+  FILE* f = fopen(path, "rb");
+  if (!f) return set_error(AMP_EIO, "cannot open %s", path);
+  char mg[8];
+  uint32_t ver = 0, hm = 0;
+  int32_t hdr[6];
+  int64_t n = 0;
+  if (fread(mg, 1, 8, f) != 8 || memcmp(mg, kMagic, 8) != 0) {
+    fclose(f);
+    return set_error(AMP_EFORMAT, "%s is not an index file", path);
+  }
+  if (fread(&ver, 4, 1, f) != 1 || ver != kVersion) {
+    fclose(f);
+    return set_error(AMP_EFORMAT, "index file version %u, expected %u", ver, kVersion);
+  }
+  if (fread(hdr, sizeof hdr, 1, f) != 1 || fread(&n, 8, 1, f) != 1 || fread(&hm, 4, 1, f) != 1) {
+    fclose(f);
+    return set_error(AMP_EFORMAT, "truncated header");
+  }
+  const int d = hdr[0], M = hdr[1], nlist = hdr[2];
+  if (d <= 0 || M <= 0 || nlist <= 0 || d % M || nlist > AMP_MAX_NLIST || n < 0 || n >= (1ll << 31)) {
+    fclose(f);
+    return set_error(AMP_EFORMAT, "implausible header");
+  }
+  std::vector<float> C((size_t)nlist * d), CB((size_t)M * kKsub * (d / M));
+  std::vector<int64_t> off(nlist + 1), ids(n);
+  std::vector<uint8_t> codes((size_t)n * M);
+  std::vector<int32_t> radq(nlist);
+  amp_status s;
+  if ((s = rsec(f, 1, C.data(), C.size() * 4)) || (s = rsec(f, 2, CB.data(), CB.size() * 4)) ||
+      (s = rsec(f, 3, off.data(), off.size() * 8)) || (s = rsec(f, 4, ids.data(), ids.size() * 8)) ||
+      (s = rsec(f, 5, codes.data(), codes.size())) || (s = rsec(f, 6, radq.data(), radq.size() * 4))) {
+    fclose(f);
+    return s;
+  }
+  if (off[nlist] != n) {
+    fclose(f);
+    return set_error(AMP_EFORMAT, "list offsets do not match n");
+  }
+  amp_index_arrays a{d, M, nlist, hdr[3], hdr[4], hdr[5], C.data(), CB.data(), off.data(), ids.data(), codes.data(),
+                     radq.data()};
+  amp_index* ix = nullptr;
+  if ((s = amp_index_from_arrays(&a, &ix)) != AMP_OK) {
+    fclose(f);
+    return s == AMP_EINVAL ? set_error(AMP_EFORMAT, "index content invalid: %s", g_err) : s;
+  }
+  if (hm) {
+    int64_t scal[15];
+    uint64_t gm = 0;
+    if ((s = rsec(f, 7, scal, sizeof scal)) || (s = rsec(f, 8, &gm, 8))) {
+      fclose(f);
+      amp_index_free(ix);
+      return s;
+    }
+    const int nsv = (int)scal[0];
+    if (nsv < 0 || nsv > 4096) {
+      fclose(f);
+      amp_index_free(ix);
+      return set_error(AMP_EFORMAT, "bad model size");
+    }
+    std::vector<int32_t> sv(5 * (size_t)nsv), beta(nsv), table(kTableN);
+    if ((s = rsec(f, 9, sv.data(), sv.size() * 4)) || (s = rsec(f, 10, beta.data(), beta.size() * 4)) ||
+        (s = rsec(f, 11, table.data(), table.size() * 4))) {
+      fclose(f);
+      amp_index_free(ix);
+      return s;
+    }
+    amp_predictor_model m{};
+    m.n_sv = nsv;
+    m.sv = sv.data();
+    m.beta = beta.data();
+    m.table = table.data();
+    m.beta0 = scal[1];
+    for (int i = 0; i < 5; ++i) m.feat_lo[i] = scal[2 + i], m.feat_mul[i] = scal[7 + i];
+    m.theta[0] = scal[12];
+    m.theta[1] = scal[13];
+    m.theta[2] = scal[14];
+    m.g_mul = gm;
+    if ((s = amp_index_set_predictor(ix, &m)) != AMP_OK) {
+      fclose(f);
+      amp_index_free(ix);
+      return s;
+    }
+  }
+  fclose(f);
+  *out = ix;
+  return AMP_OK;
+}
+
+// ------------------------------------------------------------------ search
+static amp_status ensure_workspace(amp_index* ix, size_t nq, size_t np, size_t kmax, size_t capq,
+                                   int64_t units) {
+  Workspace& w = ix->ws;
+  if (nq <= w.cap_nq && np <= w.cap_np && kmax <= w.cap_k && capq == w.capq && units <= w.cap_units)
+    return AMP_OK;
+  nq = std::max(nq, w.cap_nq);
+  np = std::max(np, w.cap_np);
+  kmax = std::max(kmax, w.cap_k);
+  units = std::max(units, w.cap_units);
+  free_workspace(w);
+  const size_t NB = (size_t)kNCls * ix->nlist, npairs = nq * np;
+  std::vector<void*>* t = &w.blocks;
+  amp_status s;
+  if ((s = dalloc(&w.queries, nq * ix->d, t)) || (s = dalloc(&w.kq, nq, t)) || (s = dalloc(&w.npq, nq, t)) ||
+      (s = dalloc(&w.qnorm, nq, t)) || (s = dalloc(&w.coarse, nq * ix->nlist, t)) ||
+      (s = dalloc(&w.probes, npairs, t)) || (s = dalloc(&w.pdist, npairs, t)) ||
+      (s = dalloc(&w.pbits, npairs, t)) || (s = dalloc(&w.xbits, npairs, t)) || (s = dalloc(&w.tau, nq, t)) ||
+      (s = dalloc(&w.ccount, nq, t)) || (s = dalloc(&w.ckey, nq * capq, t)) || (s = dalloc(&w.cid, nq * capq, t)) ||
+      (s = dalloc(&w.cnt, 2 * NB, t)) || (s = dalloc(&w.rank, 2 * npairs, t)) ||
+      (s = dalloc(&w.units, 2 * (size_t)units, t)) || (s = dalloc(&w.pairoff, 2 * (NB + 1), t)) ||
+      (s = dalloc(&w.unitoff, 2 * (NB + 1), t)) || (s = dalloc(&w.sorted, 2 * npairs, t)) ||
+      (s = dalloc(&w.counters, 2 * (size_t)(kNCls + 1), t)) || (s = dalloc(&w.flags, 4, t)) ||
+      (s = dalloc(&w.o_ids, nq * kmax, t)) || (s = dalloc(&w.o_dist, nq * kmax, t)) ||
+      (s = dalloc(&w.o_qdist, nq * kmax, t))) {
+    free_workspace(w);
+    return s;
+  }
+  w.cap_nq = nq;
+  w.cap_np = np;
+  w.cap_k = kmax;
+  w.capq = capq;
+  w.cap_units = units;
+  return AMP_OK;
+}
+
+amp_status amp_search(amp_index* ix, const float* queries, int64_t nq, const int32_t* k, const int32_t* nprobe,
+                      int32_t per_query, const amp_precision_policy* pol, const amp_search_opts* opts,
+                      int64_t* out_ids, float* out_dist) {
+  if (!ix || !queries || !k || !nprobe || !pol || !opts || !out_ids || !out_dist)
+    return set_error(AMP_EINVAL, "null argument");
+  if (nq <= 0 || nq > (1 << 24)) return set_error(AMP_EINVAL, "nq %lld out of range", (long long)nq);
+  if (opts->mem != AMP_MEM_HOST && opts->mem != AMP_MEM_DEVICE) return set_error(AMP_EINVAL, "bad mem kind");
+  if (ix->metric != AMP_L2) return set_error(AMP_EUNSUPPORTED, "inner-product search is not implemented yet");
+  const int npmax_lim = std::min(ix->nlist, AMP_MAX_NPROBE);
+  int kmax = 0, npmax = 0;
+  const int64_t nk = per_query ? nq : 1;
+  for (int64_t i = 0; i < nk; ++i) {
+    if (k[i] < 1 || k[i] > AMP_MAX_K) return set_error(AMP_EINVAL, "k = %d outside [1, %d]", k[i], AMP_MAX_K);
+    if (nprobe[i] < 1 || nprobe[i] > npmax_lim)
+      return set_error(AMP_EINVAL, "nprobe = %d outside [1, %d]", nprobe[i], npmax_lim);
+    kmax = std::max(kmax, k[i]);
+    npmax = std::max(npmax, nprobe[i]);
+  }
+  switch (pol->kind) {
+    case AMP_POLICY_FP32: break;
+    case AMP_POLICY_FIXED:
+      if (pol->fixed_bits != 4 && pol->fixed_bits != 8 && pol->fixed_bits != 12 && pol->fixed_bits != 16)
+        return set_error(AMP_EINVAL, "fixed_bits must be 4, 8, 12 or 16");
+      break;
+    case AMP_POLICY_ADAPTIVE:
+      if (!ix->has_model) return set_error(AMP_EINVAL, "adaptive policy needs a predictor");
+      if (pol->allowed_bits_mask & ~((1u << 4) | (1u << 8) | (1u << 12) | (1u << 16)))
+        return set_error(AMP_EINVAL, "allowed_bits_mask has widths outside {4,8,12,16}");
+      break;
+    case AMP_POLICY_EXPLICIT:
+      if (!pol->explicit_bits) return set_error(AMP_EINVAL, "explicit policy needs explicit_bits");
+      for (int64_t i = 0; i < nq * npmax; ++i) {
+        int b = pol->explicit_bits[i];
+        if (b != 4 && b != 8 && b != 12 && b != 16) return set_error(AMP_EINVAL, "explicit width %d", b);
+      }
+      break;
+    default: return set_error(AMP_EINVAL, "bad policy kind %d", pol->kind);
+  }
+  if (pol->lut_dtype != 0 && pol->lut_dtype != AMP_LUT_BF16)
+    return set_error(AMP_EUNSUPPORTED, "LUT build dtype %d is not implemented yet", pol->lut_dtype);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    hipGetLastError();
+    return set_error(AMP_EDEVICE, "no HIP device");
+  }
+  std::lock_guard<std::mutex> lk(ix->mu);
+  amp_status s = to_device_locked(ix, dev);
+  if (s != AMP_OK) return s;
+  if (pol->kind == AMP_POLICY_ADAPTIVE && ix->dev_model_stale && (s = upload_model(ix)) != AMP_OK) return s;
+  size_t capq = 16;  // a power of two: the merge sorts up to capq keys in place
+  while (capq < env_size("AMP_CAPQ", 4096) && capq < (1u << 16)) capq <<= 1;
+  const int64_t chunk = (int64_t)env_size("AMP_CHUNK", 1 << 16);
+  const int64_t max_nch = std::max<int64_t>(1, (ix->max_list + chunk - 1) / chunk);
+  const int64_t max_units = (int64_t)nq * npmax * max_nch;
+  if ((s = ensure_workspace(ix, nq, npmax, kmax, capq, max_units)) != AMP_OK) return s;
+  Workspace& w = ix->ws;
+  hipStream_t st = reinterpret_cast<hipStream_t>(opts->stream);
+  const bool host = opts->mem == AMP_MEM_HOST;
+  const float* qdev = queries;
+  if (host) {
+    AMP_HIP(hipMemcpyAsync(w.queries, queries, (size_t)nq * ix->d * 4, hipMemcpyHostToDevice, st));
+    qdev = w.queries;
+  }
+  if (per_query) {
+    AMP_HIP(hipMemcpyAsync(w.kq, k, nq * 4, hipMemcpyHostToDevice, st));
+    AMP_HIP(hipMemcpyAsync(w.npq, nprobe, nq * 4, hipMemcpyHostToDevice, st));
+  }
+  if (pol->kind == AMP_POLICY_EXPLICIT)
+    AMP_HIP(hipMemcpyAsync(w.xbits, pol->explicit_bits, (size_t)nq * npmax, hipMemcpyHostToDevice, st));
+  if (per_query && !host) AMP_HIP(hipStreamSynchronize(st));  // host arrays may go away after return
+  SearchDims sd;
+  sd.nq = (int)nq;
+  sd.d = ix->d;
+  sd.M = ix->M;
+  sd.dsub = ix->dsub;
+  sd.nlist = ix->nlist;
+  sd.npmax = npmax;
+  sd.kmax = kmax;
+  sd.metric = ix->metric;
+  sd.grid_kind = ix->grid_kind;
+  sd.grid_e = ix->grid_e;
+  sd.kconst = per_query ? 0 : k[0];
+  sd.npconst = per_query ? 0 : nprobe[0];
+  sd.wpr = scan_wpr(ix->M);
+  sd.chunk = chunk;
+  sd.max_units = w.cap_units;
+  sd.capq = capq;
+  sd.policy = pol->kind;
+  sd.fixed_bits = pol->fixed_bits;
+  sd.allowed_mask = pol->allowed_bits_mask ? pol->allowed_bits_mask
+                                           : ((1u << 4) | (1u << 8) | (1u << 12) | (1u << 16));
+  sd.margin = pol->margin_q40;
+  ModelArgs ma{};
+  if (ix->has_model) {
+    ma.n_sv = ix->n_sv;
+    ma.sv = ix->dev.model.sv;
+    ma.beta = ix->dev.model.beta;
+    ma.table = ix->dev.model.table;
+    ma.beta0 = ix->beta0;
+    for (int f = 0; f < 5; ++f) ma.feat_lo[f] = ix->feat_lo[f], ma.feat_mul[f] = ix->feat_mul[f];
+    ma.g_mul = ix->g_mul;
+    for (int i = 0; i < 3; ++i) ma.theta[i] = ix->theta[i];
+  }
+  hipEvent_t ev[AMP_N_STAGES + 1];
+  const bool timed = opts->stage_ms != nullptr;
+  if (timed)
+    for (auto& e : ev) AMP_HIP(hipEventCreate(&e));
+  Workspace wv = w;  // view with per-query pointers nulled when constant
+  if (!per_query) {
+    wv.kq = nullptr;
+    wv.npq = nullptr;
+  }
+  int64_t* oi = host ? w.o_ids : out_ids;
+  float* od = host ? w.o_dist : out_dist;
+  int64_t* oq = host ? (opts->out_qdist ? w.o_qdist : nullptr) : opts->out_qdist;
+  float* oc = (!host && opts->out_coarse) ? opts->out_coarse : nullptr;
+  hipError_t he = launch_search(ix, wv, qdev, sd, ma, oi, od, oq, oc, st, timed ? ev : nullptr);
+  if (he != hipSuccess) {
+    if (timed)
+      for (auto& e : ev) hipEventDestroy(e);
+    return set_error(AMP_EDEVICE, "kernel launch failed: %s", hipGetErrorString(he));
+  }
+  const hipMemcpyKind out_kind = host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+  if (opts->out_probes)
+    AMP_HIP(hipMemcpyAsync(opts->out_probes, w.probes, (size_t)nq * npmax * 4, out_kind, st));
+  if (opts->out_bits) AMP_HIP(hipMemcpyAsync(opts->out_bits, w.pbits, (size_t)nq * npmax, out_kind, st));
+  if (host && opts->out_coarse)
+    AMP_HIP(hipMemcpyAsync(opts->out_coarse, w.coarse, (size_t)nq * ix->nlist * 4, hipMemcpyDeviceToHost, st));
+  int32_t flags[4] = {0, 0, 0, 0};
+  if (host) {
+    AMP_HIP(hipMemcpyAsync(out_ids, w.o_ids, (size_t)nq * kmax * 8, hipMemcpyDeviceToHost, st));
+    AMP_HIP(hipMemcpyAsync(out_dist, w.o_dist, (size_t)nq * kmax * 4, hipMemcpyDeviceToHost, st));
+    if (opts->out_qdist)
+      AMP_HIP(hipMemcpyAsync(opts->out_qdist, w.o_qdist, (size_t)nq * kmax * 8, hipMemcpyDeviceToHost, st));
+    AMP_HIP(hipMemcpyAsync(flags, w.flags, sizeof flags, hipMemcpyDeviceToHost, st));
+    AMP_HIP(hipStreamSynchronize(st));
+  }
+  if (timed) {
+    // stages: 0 CL, 1 top-nprobe, 2 predictor, 3 queue, 4 scan phase 1,
+    // 5 scan phase 2, 6 merge; slot 7 holds the sum
+    AMP_HIP(hipEventSynchronize(ev[7]));
+    float total = 0.f;
+    for (int i = 0; i < 7; ++i) {
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+      opts->stage_ms[i] = ms;
+      total += ms;
+    }
+    opts->stage_ms[7] = total;
+    for (auto& e : ev) hipEventDestroy(e);
+  }
+  if (getenv("AMP_STATS")) {
+    // debug: candidates forwarded to the merge per query
+    std::vector<uint32_t> cc(nq);
+    AMP_HIP(hipStreamSynchronize(st));
+    AMP_HIP(hipMemcpy(cc.data(), w.ccount, nq * 4, hipMemcpyDeviceToHost));
+    double sum = 0;
+    uint32_t mx = 0;
+    for (uint32_t c : cc) sum += c, mx = std::max(mx, c);
+    fprintf(stderr, "[amp] candidates per query: mean %.1f max %u (capacity %zu)\n", sum / nq, mx, capq);
+  }
+  if (flags[0] & 4) return set_error(AMP_EOVERFLOW, "work-unit table overflowed");
+  if (flags[0]) return set_error(AMP_EOVERFLOW, "candidate buffer of %zu entries overflowed", capq);
+  return AMP_OK;
+}
+
+}  // extern "C"

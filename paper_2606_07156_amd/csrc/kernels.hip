@@ -1,0 +1,1225 @@
+// HIP kernels (gfx950) of the cluster-adaptive IVF-PQ search.
+//
+// Stage map (paper Sec. 2.1 and Sec. 4.1):
+//   k_sqnorm / k_coarse  CL distances on FP32 MFMA (16x16x4) with norm epilogue
+//   k_topn               CL selection: nprobe smallest by (distance, list id)
+//   k_pairs              RC on the operand grid, PPM features and the fixed-point
+//                        RBF regressor -> LUT width per (query, probed list)
+//   k_qhist/qscan/qscatter  work queue: pairs grouped by (lane class, list)
+//   k_scan<...>          persistent: LC on BF16 MFMA (exact on the grid),
+//                        per-pair quantisation, packed-lane DC scan, pruning
+//                        against the query's running threshold (TSM forwarding)
+//   k_merge              TS: per-query top-k by (distance, id)
+#include "amp_internal.h"
+
+#include <cstdio>
+#include <cstring>
+
+namespace amp {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// ------------------------------------------------------------------ helpers
+// order-preserving keys: integers (sign flip) and floats (IEEE total order)
+__device__ __forceinline__ uint64_t ikey(int64_t v) { return (uint64_t)v ^ 0x8000000000000000ull; }
+__device__ __forceinline__ int64_t ikey_val(uint64_t k) { return (int64_t)(k ^ 0x8000000000000000ull); }
+__device__ __forceinline__ uint32_t fkey(float f) {
+  uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float fkey_val(uint32_t k) {
+  uint32_t u = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
+  return __uint_as_float(u);
+}
+
+// nearest E4M3 value of an integer: 3 mantissa bits, ties to even, saturating
+// at 448 (OCP 8-bit floating point specification, E4M3 "fn" encoding)
+__device__ __forceinline__ int e4m3_int(int v) {
+  int a = v < 0 ? -v : v;
+  if (a >= 16) {
+    int E = 31 - __clz(a);
+    int sh = E - 3;
+    int q = a >> sh;
+    int rem = a & ((1 << sh) - 1);
+    int half = 1 << (sh - 1);
+    if (rem > half || (rem == half && (q & 1))) q++;
+    a = q << sh;
+  }
+  a = a > 448 ? 448 : a;
+  return v < 0 ? -a : a;
+}
+
+// operand grid: round half to even of r * 2^-e, then saturate (9-bit grid) or
+// round to the e4m3-representable integers
+__device__ __forceinline__ int grid_val(float r, int e, int kind) {
+  float x = rintf(ldexpf(r, -e));
+  if (kind == AMP_GRID_U9) {
+    x = fminf(fmaxf(x, -255.f), 255.f);
+    return (int)x;
+  }
+  x = fminf(fmaxf(x, -65536.f), 65536.f);
+  return e4m3_int((int)x);
+}
+
+__device__ __forceinline__ uint32_t bf16_bits(float v) {  // exact inputs only
+  return __float_as_uint(v) >> 16;
+}
+
+// ------------------------------------------------------------------ fills
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_fill_u64(uint64_t* p, uint64_t v, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// ------------------------------------------------------------------ CL
+// squared norm of each row, FP32: one wave per row, lane-strided partial sums
+// combined by a butterfly (a fixed order for a given d)
+__global__ void k_sqnorm(const float* __restrict__ X, int rows, int d, float* __restrict__ out) {
+  const int r = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (r >= rows) return;
+  const float* x = X + (size_t)r * d;
+  float s = 0.f;
+  for (int t = lane; t < d; t += 64) s = fmaf(x[t], x[t], s);
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (lane == 0) out[r] = s;
+}
+
+// D[q][c] = (|q|^2 + |c|^2) - 2 q.c (L2) or -q.c (IP).  64x64 tile per
+// workgroup, each wave a 32x32 quarter of 2x2 MFMA 16x16x4 FP32 tiles.
+constexpr int CL_T = 64, CL_K = 32;
+__global__ __launch_bounds__(256) void k_coarse(const float* __restrict__ Q, const float* __restrict__ C,
+                                                const float* __restrict__ qn, const float* __restrict__ cn,
+                                                float* __restrict__ D, int nq, int nlist, int d, int metric) {
+  __shared__ float Qs[CL_T][CL_K + 1];
+  __shared__ float Cs[CL_T][CL_K + 1];
+  const int q0 = blockIdx.y * CL_T, c0 = blockIdx.x * CL_T;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  f4 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < d; k0 += CL_K) {
+    for (int i = tid; i < CL_T * CL_K; i += 256) {
+      int r = i / CL_K, kk = i % CL_K, gk = k0 + kk;
+      Qs[r][kk] = (q0 + r < nq && gk < d) ? Q[(size_t)(q0 + r) * d + gk] : 0.f;
+      Cs[r][kk] = (c0 + r < nlist && gk < d) ? C[(size_t)(c0 + r) * d + gk] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < CL_K; kk += 4) {
+      float a0 = Qs[wr + (lane & 15)][kk + (lane >> 4)];
+      float a1 = Qs[wr + 16 + (lane & 15)][kk + (lane >> 4)];
+      float b0 = Cs[wc + (lane & 15)][kk + (lane >> 4)];
+      float b1 = Cs[wc + 16 + (lane & 15)][kk + (lane >> 4)];
+      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int r = 0; r < 4; ++r) {
+        int qi = q0 + wr + 16 * i + 4 * (lane >> 4) + r;
+        int ci = c0 + wc + 16 * j + (lane & 15);
+        if (qi < nq && ci < nlist) {
+          float dot = acc[i][j][r];
+          D[(size_t)qi * nlist + ci] = metric == AMP_L2 ? (qn[qi] + cn[ci]) - 2.f * dot : -dot;
+        }
+      }
+}
+
+// ------------------------------------------------------------------ sorting
+// ascending bitonic sort of n (power of two) 64-bit keys in LDS by the block
+__device__ void block_bitonic_u64(uint64_t* keys, int n) {
+  for (int size = 2; size <= n; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < (n >> 1); i += blockDim.x) {
+        int pos = 2 * i - (i & (stride - 1));
+        int oth = pos + stride;
+        bool asc = (pos & size) == 0;
+        uint64_t a = keys[pos], b = keys[oth];
+        if ((a > b) == asc) {
+          keys[pos] = b;
+          keys[oth] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// same with a secondary signed 64-bit tie-breaker
+__device__ void block_bitonic_u64_i64(uint64_t* keys, int64_t* vals, int n) {
+  for (int size = 2; size <= n; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < (n >> 1); i += blockDim.x) {
+        int pos = 2 * i - (i & (stride - 1));
+        int oth = pos + stride;
+        bool asc = (pos & size) == 0;
+        uint64_t a = keys[pos], b = keys[oth];
+        int64_t va = vals[pos], vb = vals[oth];
+        bool gt = (a > b) || (a == b && va > vb);
+        if (gt == asc) {
+          keys[pos] = b;
+          keys[oth] = a;
+          vals[pos] = vb;
+          vals[oth] = va;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// CL selection: the nprobe smallest (distance, list) of each query
+__global__ __launch_bounds__(256) void k_topn(const float* __restrict__ D, int nlist, int np2,
+                                              const int32_t* __restrict__ npq, int npconst, int npmax,
+                                              int32_t* __restrict__ probes, float* __restrict__ pdist) {
+  extern __shared__ uint64_t keys[];
+  const int q = blockIdx.x;
+  const float* row = D + (size_t)q * nlist;
+  for (int i = threadIdx.x; i < np2; i += blockDim.x)
+    keys[i] = i < nlist ? (((uint64_t)fkey(row[i]) << 32) | (uint32_t)i) : ~0ull;
+  __syncthreads();
+  block_bitonic_u64(keys, np2);
+  const int np = npq ? npq[q] : npconst;
+  for (int r = threadIdx.x; r < npmax; r += blockDim.x) {
+    bool on = r < np;
+    probes[(size_t)q * npmax + r] = on ? (int32_t)(keys[r] & 0xFFFFFFFFu) : -1;
+    pdist[(size_t)q * npmax + r] = on ? fkey_val((uint32_t)(keys[r] >> 32)) : __builtin_inff();
+  }
+}
+
+// ------------------------------------------------------------------ PPM
+struct PairArgs {
+  const float* Q;
+  const float* C;
+  const int32_t* probes;
+  const int32_t* radq;
+  const int64_t* offsets;
+  const uint8_t* xbits;
+  uint8_t* pbits;
+  int nq, d, npmax, grid_e, grid_kind, metric, policy, fixed_bits, lane_sel_M;
+  uint32_t allowed;
+  int64_t margin;
+};
+
+__device__ __forceinline__ int64_t mitchell_q8(int64_t x) {
+  uint64_t y = (uint64_t)x + 1;
+  int k = 63 - __clzll((long long)y);
+  return 256 * (int64_t)k + (int64_t)((y << 8) >> k) - 256;
+}
+
+__device__ __forceinline__ int pick_bits(int64_t y, const int64_t* theta, uint32_t allowed, int64_t margin) {
+  int last = 16;
+  for (int b = 4; b <= 16; b += 4) {
+    if (!(allowed & (1u << b))) continue;
+    last = b;
+    if (b == 16 || y + margin <= theta[b / 4 - 1]) return b;
+  }
+  return last;
+}
+
+// one workgroup per query, one thread per probe rank
+__global__ void k_pairs(PairArgs a, ModelArgs ma) {
+  __shared__ unsigned long long s_best;
+  __shared__ int32_t s_table[kTableN];
+  const int q = blockIdx.x, r = threadIdx.x;
+  const bool adaptive = a.policy == AMP_POLICY_ADAPTIVE;
+  if (adaptive)
+    for (int i = threadIdx.x; i < kTableN; i += blockDim.x) s_table[i] = ma.table[i];
+  if (threadIdx.x == 0) s_best = ~0ull;
+  __syncthreads();
+  const int p = r < a.npmax ? a.probes[(size_t)q * a.npmax + r] : -1;
+  int64_t dq2 = 0;
+  if (adaptive && p >= 0) {
+    const float* qv = a.Q + (size_t)q * a.d;
+    const float* cv = a.C + (size_t)p * a.d;
+    if (a.metric == AMP_L2) {
+      for (int t = 0; t < a.d; ++t) {
+        int v = grid_val(qv[t] - cv[t], a.grid_e, a.grid_kind);
+        dq2 += (int64_t)v * v;
+      }
+    } else {
+      for (int t = 0; t < a.d; ++t) {
+        int v = grid_val(qv[t], a.grid_e, a.grid_kind) - grid_val(cv[t], a.grid_e, a.grid_kind);
+        dq2 += (int64_t)v * v;
+      }
+    }
+    atomicMin(&s_best, (unsigned long long)((uint64_t)dq2 << 13 | (uint64_t)p));
+  }
+  __syncthreads();
+  if (r >= a.npmax) return;
+  uint8_t bits = 0;
+  if (p >= 0) {
+    if (a.policy == AMP_POLICY_FP32) {
+      bits = 32;
+    } else if (a.policy == AMP_POLICY_FIXED) {
+      bits = (uint8_t)a.fixed_bits;
+    } else if (a.policy == AMP_POLICY_EXPLICIT) {
+      bits = a.xbits[(size_t)q * a.npmax + r];
+    } else {
+      const int c1 = (int)(s_best & 8191ull);
+      int64_t x[5];
+      x[0] = dq2;
+      x[1] = a.radq[c1];
+      x[2] = a.radq[p];
+      x[3] = a.offsets[c1 + 1] - a.offsets[c1];
+      x[4] = a.offsets[p + 1] - a.offsets[p];
+      int32_t u[5];
+      for (int f = 0; f < 5; ++f) {
+        int64_t v = ((mitchell_q8(x[f]) - ma.feat_lo[f]) * ma.feat_mul[f]) >> 16;
+        u[f] = (int32_t)(v < 0 ? 0 : (v > 1023 ? 1023 : v));
+      }
+      int64_t y = ma.beta0;
+      for (int i = 0; i < ma.n_sv; ++i) {
+        const int32_t* s = ma.sv + 5 * i;
+        int32_t d0 = u[0] - s[0], d1 = u[1] - s[1], d2 = u[2] - s[2], d3 = u[3] - s[3], d4 = u[4] - s[4];
+        uint32_t dist2 = (uint32_t)(d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3 + d4 * d4);
+        uint64_t idx = ((uint64_t)dist2 * ma.g_mul) >> 32;
+        int32_t K = s_table[idx > (kTableN - 1) ? (kTableN - 1) : idx];
+        y += (int64_t)ma.beta[i] * K;
+      }
+      bits = (uint8_t)pick_bits(y, ma.theta, a.allowed, a.margin);
+    }
+  }
+  a.pbits[(size_t)q * a.npmax + r] = bits;
+}
+
+// ------------------------------------------------------------------ queue
+// Buckets are class-major: b = cls * nlist + list.  Phase 1 holds the
+// rank-0 pair of every query, phase 2 every active pair.  One atomic per
+// pair gives its rank inside the bucket; the scatter and the work-unit
+// table are then written without atomics.
+struct QueueArgs {
+  const int32_t* probes;
+  const uint8_t* pbits;
+  const int64_t* offsets;
+  int32_t* cnt;       // [2][NB]
+  int32_t* rank;      // [2][nq*npmax]
+  int64_t* pairoff;   // [2][NB+1]
+  int64_t* unitoff;   // [2][NB+1]
+  int32_t* sorted;    // [2][nq*npmax]
+  int4* units;        // [2][max_units]: {list, first pair, pair count, chunk}
+  int32_t* flags;
+  int nq, npmax, nlist, M, ncls, wpr;
+  int64_t chunk, max_units;
+};
+
+__device__ __forceinline__ int pair_class(int bits, int M) {
+  if (bits == 32) return 0;
+  uint64_t top = (uint64_t)M * ((1ull << bits) - 1);
+  return top <= 0xFFull ? 0 : (top <= 0xFFFFull ? 1 : 2);
+}
+__device__ __forceinline__ int class_pairs(int cls, int wpr, bool fp32) {
+  return fp32 ? wpr : wpr * (4 >> cls);
+}
+
+__global__ void k_qhist(QueueArgs a) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t n = (size_t)a.nq * a.npmax;
+  if (i >= n) return;
+  const int p = a.probes[i];
+  if (p < 0) return;
+  const int cls = pair_class(a.pbits[i], a.M);
+  const int b = cls * a.nlist + p;
+  const int NB = a.ncls * a.nlist;
+  a.rank[n + i] = atomicAdd(&a.cnt[NB + b], 1);
+  if (i % a.npmax == 0) a.rank[i] = atomicAdd(&a.cnt[b], 1);
+}
+
+// exclusive scans of pair and unit counts, one workgroup of 1024 threads
+__global__ __launch_bounds__(1024) void k_qscan(QueueArgs a, int fp32) {
+  __shared__ int64_t s_part[2][1024];
+  const int NB = a.ncls * a.nlist;
+  const int per = (NB + 1023) / 1024;
+  for (int ph = 0; ph < 2; ++ph) {
+    const int32_t* cnt = a.cnt + (size_t)ph * NB;
+    int64_t* po = a.pairoff + (size_t)ph * (NB + 1);
+    int64_t* uo = a.unitoff + (size_t)ph * (NB + 1);
+    const int b0 = threadIdx.x * per;
+    int64_t sp = 0, su = 0;
+    for (int b = b0; b < b0 + per && b < NB; ++b) {
+      const int cls = b / a.nlist, p = b % a.nlist;
+      const int64_t n = a.offsets[p + 1] - a.offsets[p];
+      const int64_t nch = (n + a.chunk - 1) / a.chunk;
+      const int G = class_pairs(cls, a.wpr, fp32);
+      sp += cnt[b];
+      su += ((cnt[b] + G - 1) / G) * nch;
+    }
+    s_part[0][threadIdx.x] = sp;
+    s_part[1][threadIdx.x] = su;
+    __syncthreads();
+    // Hillis-Steele inclusive scan over the 1024 partial sums
+    for (int off = 1; off < 1024; off <<= 1) {
+      const int64_t xp = threadIdx.x >= off ? s_part[0][threadIdx.x - off] : 0;
+      const int64_t xu = threadIdx.x >= off ? s_part[1][threadIdx.x - off] : 0;
+      __syncthreads();
+      s_part[0][threadIdx.x] += xp;
+      s_part[1][threadIdx.x] += xu;
+      __syncthreads();
+    }
+    sp = s_part[0][threadIdx.x] - sp;  // exclusive
+    su = s_part[1][threadIdx.x] - su;
+    if (threadIdx.x == 1023) {
+      po[NB] = s_part[0][1023];
+      uo[NB] = s_part[1][1023];
+    }
+    for (int b = b0; b < b0 + per && b < NB; ++b) {
+      const int cls = b / a.nlist, p = b % a.nlist;
+      const int64_t n = a.offsets[p + 1] - a.offsets[p];
+      const int64_t nch = (n + a.chunk - 1) / a.chunk;
+      const int G = class_pairs(cls, a.wpr, fp32);
+      po[b] = sp;
+      uo[b] = su;
+      sp += cnt[b];
+      su += ((cnt[b] + G - 1) / G) * nch;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_qscatter(QueueArgs a) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t n = (size_t)a.nq * a.npmax;
+  if (i >= n) return;
+  const int p = a.probes[i];
+  if (p < 0) return;
+  const int cls = pair_class(a.pbits[i], a.M);
+  const int b = cls * a.nlist + p;
+  const int NB = a.ncls * a.nlist;
+  a.sorted[n + a.pairoff[(NB + 1) + b] + a.rank[n + i]] = (int32_t)i;
+  if (i % a.npmax == 0) a.sorted[a.pairoff[b] + a.rank[i]] = (int32_t)i;
+}
+
+// grid-stride over (phase, unit): find the unit's bucket by binary search of
+// the unit offsets and write its descriptor
+__global__ void k_qunits(QueueArgs a, int fp32) {
+  const int NB = a.ncls * a.nlist;
+  for (int ph = 0; ph < 2; ++ph) {
+    const int64_t* po = a.pairoff + (size_t)ph * (NB + 1);
+    const int64_t* uo = a.unitoff + (size_t)ph * (NB + 1);
+    const int64_t total = uo[NB];
+    if (total > a.max_units) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&a.flags[0], 4);
+      continue;
+    }
+    int4* units = a.units + (size_t)ph * a.max_units;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < total;
+         u += (int64_t)gridDim.x * blockDim.x) {
+      int lo = 0, hi = NB;  // uo[lo] <= u < uo[hi]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (uo[mid] <= u) lo = mid; else hi = mid;
+      }
+      const int b = lo, cls = b / a.nlist, p = b % a.nlist;
+      const int64_t n = a.offsets[p + 1] - a.offsets[p];
+      const int64_t nch = (n + a.chunk - 1) / a.chunk;
+      const int G = class_pairs(cls, a.wpr, fp32);
+      const int64_t local = u - uo[b], grp = local / nch, ch = local % nch;
+      const int64_t left = (po[b + 1] - po[b]) - grp * G;
+      units[u] = make_int4(p, (int)(po[b] + grp * G), (int)(left < G ? left : G), (int)ch);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ scan
+struct ScanArgs {
+  const float* Q;
+  const float* C;
+  const float* codebook;   // FP32 policy
+  const u32x4* bsw;        // integer policy MFMA B fragments
+  const uint8_t* codes;
+  const int64_t* ids;
+  const int64_t* offsets;
+  const int32_t* kq;
+  const uint8_t* pbits;
+  const int32_t* sorted;   // this phase's sorted pairs
+  const int64_t* unitoff;  // this phase's unit offsets (NB+1)
+  const int4* units;       // this phase's unit table
+  uint32_t* counter;       // this phase/class unit counter
+  uint64_t* tau;
+  uint32_t* ccount;
+  uint64_t* ckey;
+  int64_t* cid;
+  int32_t* flags;
+  int nq, d, M, dsub, nlist, npmax, grid_e, grid_kind, metric, kconst, cls;
+  int64_t chunk;
+  size_t capq;
+};
+
+// words per LUT row for a subspace count: the LUT of one work unit takes
+// M * 256 * WPR * 4 bytes of LDS
+__host__ __device__ constexpr int wpr_for(int M) { return M <= 16 ? 4 : (M <= 32 ? 2 : 1); }
+
+// LDS carve-up of one scan workgroup (all offsets in bytes, 16-aligned)
+struct ScanLds {
+  int lut, ri, rr, lo, hi, pq, pb, ps, pbase, psig, lmin, total;
+};
+__host__ __device__ inline ScanLds scan_lds_layout(int G, int wpr, int M, int d, bool fp32, int phase) {
+  ScanLds L;
+  int o = 0;
+  auto take = [&](int bytes) { int r = o; o += (bytes + 15) & ~15; return r; };
+  L.lut = take(M * kKsub * wpr * 4);
+  L.ri = take(G * d * (fp32 ? 4 : 2));
+  L.rr = take(G * M * 4);
+  L.lo = take(G * M * 4);
+  L.hi = take(G * M * 4);
+  L.pq = take(G * 4);
+  L.pb = take(G * 4);
+  L.ps = take(G * 4);
+  L.pbase = take(G * 8);
+  L.psig = take(G * 4);
+  // phase 1 keeps per-thread minima after the scan: reuse the LUT space
+  L.lmin = L.lut;
+  if (phase == 1 && G * kThreads * 4 > M * kKsub * wpr * 4) L.lmin = take(G * kThreads * 4);
+  L.total = o;
+  return L;
+}
+
+template <int LWB>  // lane bits 8/16/32, 0 = FP32 LUT
+struct Lane {
+  static constexpr int W = LWB ? 32 / LWB : 1;
+  static constexpr uint32_t MASK = LWB == 32 || LWB == 0 ? 0xFFFFFFFFu : ((1u << LWB) - 1);
+};
+
+template <int WPR>
+__device__ __forceinline__ void lut_row_load(const uint32_t* lut, int row, uint32_t* w) {
+  if constexpr (WPR == 4) {
+    u32x4 x = *reinterpret_cast<const u32x4*>(lut + row);
+    w[0] = x[0]; w[1] = x[1]; w[2] = x[2]; w[3] = x[3];
+  } else if constexpr (WPR == 2) {
+    u32x2 x = *reinterpret_cast<const u32x2*>(lut + row);
+    w[0] = x[0]; w[1] = x[1];
+  } else {
+    w[0] = lut[row];
+  }
+}
+
+// One m-pair of the integer LUT of a work unit on BF16 MFMA 16x16x32.  Rows
+// of the A operand are (subspace slot ms, pair g) = ms*8 + g; K holds
+// [dims m0 | aug m0 | dims m1 | aug m1], 8 slots each.  The aug slots carry
+// |cbi|^2 (digits in B, powers of two in A) and |ri|^2 + off (digits in A,
+// powers of two in B), all scaled by 2^-s in A, so the product is exactly
+// 2^-s (T + off): every partial sum is an integer multiple of 2^-s below
+// 2^(24-s).  pass 1: off = 0, s = 0, record min/max over the codewords;
+// pass 2: quantise (truncation of the exact non-negative value) and pack.
+template <int LWB, int WPR>
+__device__ __forceinline__ void lut_mpair(const ScanArgs& a, char* lds, const ScanLds& L, int M, int np_u,
+                                          int pass, int mp, const u32x4 (&B)[16]) {
+  constexpr int W = Lane<LWB>::W;
+  constexpr int G = WPR * W;
+  constexpr int NGT = (G + 7) / 8;
+  const int lane = threadIdx.x & 63;
+  const int16_t* ri = reinterpret_cast<const int16_t*>(lds + L.ri);
+  const int32_t* rr = reinterpret_cast<const int32_t*>(lds + L.rr);
+  int32_t* lo = reinterpret_cast<int32_t*>(lds + L.lo);
+  int32_t* hi = reinterpret_cast<int32_t*>(lds + L.hi);
+  const int32_t* ps = reinterpret_cast<const int32_t*>(lds + L.ps);
+  uint32_t* lut = reinterpret_cast<uint32_t*>(lds + L.lut);
+  const int row = lane & 15, kg = lane >> 4;
+  const int ms_row = row >> 3;
+  const int dsub = a.dsub;
+  bf16x8 A[NGT];
+#pragma unroll
+  for (int gt = 0; gt < NGT; ++gt) {
+    const int g = gt * 8 + (row & 7);
+    const int m = 2 * mp + ms_row;
+    uint32_t pk[4] = {0, 0, 0, 0};
+    if (g < np_u && (kg >> 1) == ms_row) {
+      const int s = pass == 1 ? 0 : ps[g];
+      const float sc = ldexpf(1.f, -s);
+      float v[8];
+      if ((kg & 1) == 0) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+          v[t] = t < dsub ? (float)(-2 * (int)ri[g * a.d + m * dsub + t]) * sc : 0.f;
+      } else {
+        int32_t X = rr[g * M + m];
+        if (pass == 2) X += lo[g * M + m];  // lo holds off = hf(s) - min after pass 1
+        const float sg = X < 0 ? -1.f : 1.f;
+        const uint32_t ax = (uint32_t)(X < 0 ? -X : X);
+        v[0] = 65536.f * sc;
+        v[1] = 256.f * sc;
+        v[2] = sc;
+        v[3] = sg * (float)(ax >> 16) * sc;
+        v[4] = sg * (float)((ax >> 8) & 255u) * sc;
+        v[5] = sg * (float)(ax & 255u) * sc;
+        v[6] = 0.f;
+        v[7] = 0.f;
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) pk[t] = bf16_bits(v[2 * t]) | (bf16_bits(v[2 * t + 1]) << 16);
+    }
+    u32x4 u = {pk[0], pk[1], pk[2], pk[3]};
+    A[gt] = __builtin_bit_cast(bf16x8, u);
+  }
+  // D rows of this lane: (ms = kg>>1, g = gt*8 + 4*(kg&1) + i), column j
+  const int m_out = 2 * mp + (kg >> 1);
+  float mn[NGT][4], mx[NGT][4];
+#pragma unroll
+  for (int gt = 0; gt < NGT; ++gt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { mn[gt][i] = 3.0e38f; mx[gt][i] = -3.0e38f; }
+#pragma unroll
+  for (int jt = 0; jt < 16; ++jt) {
+    const bf16x8 Bf = __builtin_bit_cast(bf16x8, B[jt]);
+    const int j = jt * 16 + (lane & 15);
+#pragma unroll
+    for (int gt = 0; gt < NGT; ++gt) {
+      f4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[gt], Bf, (f4){0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+      const int g0 = gt * 8 + 4 * (kg & 1);
+      if (pass == 1) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          mn[gt][i] = fminf(mn[gt][i], acc[i]);
+          mx[gt][i] = fmaxf(mx[gt][i], acc[i]);
+        }
+      } else if (g0 < G) {
+        uint32_t qv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) qv[i] = (uint32_t)acc[i];  // exact and >= 0: truncation = floor
+        uint32_t* dst = lut + (size_t)(m_out * kKsub + j) * WPR;
+        if constexpr (LWB == 8) {
+          dst[g0 >> 2] = qv[0] | (qv[1] << 8) | (qv[2] << 16) | (qv[3] << 24);
+        } else if constexpr (LWB == 16) {
+          const int w0 = g0 >> 1;
+          if (w0 < WPR) dst[w0] = qv[0] | (qv[1] << 16);
+          if (w0 + 1 < WPR) dst[w0 + 1] = qv[2] | (qv[3] << 16);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (g0 + i < WPR) dst[g0 + i] = qv[i];
+        }
+      }
+    }
+  }
+  if (pass == 1) {
+#pragma unroll
+    for (int gt = 0; gt < NGT; ++gt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float a0 = mn[gt][i], b0 = mx[gt][i];
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+          a0 = fminf(a0, __shfl_xor(a0, off, 16));
+          b0 = fmaxf(b0, __shfl_xor(b0, off, 16));
+        }
+        const int g = gt * 8 + 4 * (kg & 1) + i;
+        if ((lane & 15) == 0 && g < np_u) {
+          lo[g * M + m_out] = (int32_t)a0;
+          hi[g * M + m_out] = (int32_t)b0;
+        }
+      }
+  }
+}
+
+template <int WPR, int MT>
+struct Owned {
+  // codewords of the FP32 LUT entries a thread owns: (m, j = tid) for every m
+  static constexpr int NM = MT ? MT : 1;
+  float c[NM][kMaxDsub];
+};
+
+template <int LWB, int MT, int PHASE>
+__global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  constexpr int WPR = wpr_for(MT ? MT : 64);
+  constexpr bool FP = LWB == 0;
+  constexpr int W = Lane<LWB>::W;
+  constexpr int G = WPR * W;
+  constexpr uint32_t MASK = Lane<LWB>::MASK;
+  constexpr bool CRES = FP && MT != 0;               // FP32 codewords stay in registers
+  const int M = MT ? MT : a.M;
+  const ScanLds L = scan_lds_layout(G, WPR, M, a.d, FP, PHASE);
+  __shared__ int s_u;
+  __shared__ int4 s_unit;
+  int32_t* pq = reinterpret_cast<int32_t*>(lds + L.pq);
+  int32_t* pb = reinterpret_cast<int32_t*>(lds + L.pb);
+  int32_t* ps = reinterpret_cast<int32_t*>(lds + L.ps);
+  int64_t* pbase = reinterpret_cast<int64_t*>(lds + L.pbase);
+  uint32_t* psig = reinterpret_cast<uint32_t*>(lds + L.psig);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t ub = a.unitoff[(size_t)a.cls * a.nlist];
+  const int64_t ue = a.unitoff[(size_t)(a.cls + 1) * a.nlist];
+  Owned<WPR, CRES ? MT : 0> own;
+  if constexpr (CRES) {
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int t = 0; t < kMaxDsub; ++t)
+        own.c[m][t] = t < a.dsub ? a.codebook[((size_t)m * kKsub + tid) * a.dsub + t] : 0.f;
+  }
+  for (;;) {
+    if (tid == 0) {
+      const int uu = (int)atomicAdd(a.counter, 1u);
+      s_u = uu;
+      if (ub + uu < ue) s_unit = a.units[ub + uu];
+    }
+    __syncthreads();
+    if (ub + s_u >= ue) break;
+    const int p = s_unit.x, np_u = s_unit.z;
+    const int64_t L0 = a.offsets[p];
+    const int64_t n_list = a.offsets[p + 1] - L0;
+    const int64_t v0 = (int64_t)s_unit.w * a.chunk;
+    const int64_t v1 = v0 + a.chunk < n_list ? v0 + a.chunk : n_list;
+    if (tid < G) {
+      if (tid < np_u) {
+        const int pid = a.sorted[s_unit.y + tid];
+        pq[tid] = pid / a.npmax;
+        pb[tid] = a.pbits[pid];
+      } else {
+        pq[tid] = -1;
+        pb[tid] = 16;
+      }
+    }
+    __syncthreads();
+    // ---- RC: residuals (FP32, then onto the grid for integer policies)
+    for (int e = tid; e < np_u * a.d; e += kThreads) {
+      const int g = e / a.d, t = e % a.d;
+      const float r = a.Q[(size_t)pq[g] * a.d + t] - a.C[(size_t)p * a.d + t];
+      if constexpr (FP)
+        reinterpret_cast<float*>(lds + L.ri)[e] = r;
+      else
+        reinterpret_cast<int16_t*>(lds + L.ri)[e] = (int16_t)grid_val(r, a.grid_e, a.grid_kind);
+    }
+    __syncthreads();
+    // ---- LC
+    if constexpr (FP) {
+      const float* r32 = reinterpret_cast<const float*>(lds + L.ri);
+      float* lut = reinterpret_cast<float*>(lds + L.lut);
+      for (int m = 0; m < M; ++m) {
+        const int e = m * kKsub + tid;
+        float c[kMaxDsub];
+        if constexpr (CRES) {
+#pragma unroll
+          for (int t = 0; t < kMaxDsub; ++t) c[t] = own.c[MT ? m : 0][t];
+        } else {
+#pragma unroll
+          for (int t = 0; t < kMaxDsub; ++t) c[t] = t < a.dsub ? a.codebook[(size_t)e * a.dsub + t] : 0.f;
+        }
+        float out[WPR];
+#pragma unroll
+        for (int g = 0; g < WPR; ++g) {
+          float s = 0.f;
+          if (g < np_u) {
+            const float* r = r32 + g * a.d + m * a.dsub;
+#pragma unroll
+            for (int t = 0; t < kMaxDsub; ++t) {
+              if (t < a.dsub) {
+                const float df = r[t] - c[t];
+                s = fmaf(df, df, s);
+              }
+            }
+          }
+          out[g] = s;
+        }
+        float* dst = lut + (size_t)e * WPR;
+#pragma unroll
+        for (int g = 0; g < WPR; ++g) dst[g] = out[g];
+      }
+      if (tid < G) {
+        ps[tid] = 0;
+        pbase[tid] = 0;
+      }
+    } else {
+      int32_t* rr = reinterpret_cast<int32_t*>(lds + L.rr);
+      const int16_t* ri = reinterpret_cast<const int16_t*>(lds + L.ri);
+      for (int e = tid; e < np_u * M; e += kThreads) {
+        const int g = e / M, m = e % M;
+        int32_t s = 0;
+        for (int t = 0; t < a.dsub; ++t) {
+          const int v = ri[g * a.d + m * a.dsub + t];
+          s += v * v;
+        }
+        rr[e] = s;
+      }
+      __syncthreads();
+      for (int pass = 1; pass <= 2; ++pass) {
+        // the 16 B fragments of an m-pair are issued together, then consumed
+        for (int mp = wave; mp < M / 2; mp += kThreads / 64) {
+          u32x4 Bt[16];
+#pragma unroll
+          for (int jt = 0; jt < 16; ++jt) Bt[jt] = a.bsw[((size_t)mp * 16 + jt) * 64 + lane];
+          lut_mpair<LWB, WPR>(a, lds, L, M, np_u, pass, mp, Bt);
+        }
+        __syncthreads();
+        if (pass == 1) {
+          int32_t* lo = reinterpret_cast<int32_t*>(lds + L.lo);
+          const int32_t* hi = reinterpret_cast<const int32_t*>(lds + L.hi);
+          if (tid < np_u) {
+            const int g = tid;
+            int64_t R = 0, base = 0;
+            for (int m = 0; m < M; ++m) {
+              const int64_t span = (int64_t)hi[g * M + m] - lo[g * M + m];
+              R = span > R ? span : R;
+              base += lo[g * M + m];
+            }
+            const int64_t top = (1ll << pb[g]) - 1;
+            int s = 0;
+            while (((R + (s ? (1ll << (s - 1)) : 0)) >> s) > top) ++s;
+            const int32_t hf = s ? (1 << (s - 1)) : 0;
+            for (int m = 0; m < M; ++m) lo[g * M + m] = hf - lo[g * M + m];  // -> off
+            ps[g] = s;
+            pbase[g] = base;
+          }
+          __syncthreads();
+        }
+      }
+    }
+    // ---- per-pair pruning threshold in the lane domain (phase 2)
+    if (PHASE == 2 && tid < G) {
+      uint32_t sig = 0;
+      bool live = false;
+      if (tid < np_u) {
+        const uint64_t tk = a.tau[pq[tid]];
+        live = true;
+        if (tk == ~0ull) {
+          sig = 0xFFFFFFFFu;
+        } else if constexpr (FP) {
+          sig = (uint32_t)tk;
+        } else {
+          const int64_t t = ikey_val(tk);
+          if (t < pbase[tid]) {
+            live = false;
+          } else {
+            const int64_t dd = (t - pbase[tid]) >> ps[tid];
+            sig = dd > (int64_t)MASK ? MASK : (uint32_t)dd;
+          }
+        }
+      }
+      psig[tid] = live ? sig : 0;
+      pb[tid] = live ? pb[tid] : -1;  // -1: no candidate can pass
+    }
+    __syncthreads();
+    // ---- DC scan: one vector per thread, codes of the next vector prefetched
+    uint32_t sig[G];
+    bool live[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      sig[g] = psig[g];
+      live[g] = PHASE == 2 ? pb[g] >= 0 : g < np_u;
+    }
+    uint32_t lmin[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) lmin[g] = 0xFFFFFFFFu;
+    const uint32_t* lut = reinterpret_cast<const uint32_t*>(lds + L.lut);
+    constexpr int MQ = MT ? MT / 4 : 1;  // code dwords per vector held in registers
+    uint32_t cw_next[MQ];
+    {
+      const int64_t v = v0 + tid;
+      if constexpr (MT != 0) {
+        if (v < v1) {
+          const uint32_t* cp = reinterpret_cast<const uint32_t*>(a.codes + (size_t)(L0 + v) * MT);
+#pragma unroll
+          for (int i = 0; i < MQ; ++i) cw_next[i] = cp[i];
+        }
+      }
+    }
+    for (int64_t vb = v0; vb < v1; vb += kThreads) {
+      const int64_t v = vb + tid;
+      uint32_t cw[MQ];
+#pragma unroll
+      for (int i = 0; i < MQ; ++i) cw[i] = cw_next[i];
+      if constexpr (MT != 0) {
+        const int64_t vn = v + kThreads;
+        if (vn < v1) {
+          const uint32_t* cp = reinterpret_cast<const uint32_t*>(a.codes + (size_t)(L0 + vn) * MT);
+#pragma unroll
+          for (int i = 0; i < MQ; ++i) cw_next[i] = cp[i];
+        }
+      }
+      if (v < v1) {
+        uint32_t acc[WPR];
+        float accf[WPR];
+#pragma unroll
+        for (int w = 0; w < WPR; ++w) { acc[w] = 0; accf[w] = 0.f; }
+        const uint32_t* cpg = reinterpret_cast<const uint32_t*>(a.codes + (size_t)(L0 + v) * M);
+        for (int m4 = 0; m4 < M; m4 += 4) {
+          uint32_t c4;
+          if constexpr (MT != 0) c4 = cw[m4 >> 2];
+          else c4 = cpg[m4 >> 2];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int rowi = ((m4 + i) * kKsub + ((c4 >> (8 * i)) & 255u)) * WPR;
+            uint32_t x[WPR];
+            lut_row_load<WPR>(lut, rowi, x);
+#pragma unroll
+            for (int w = 0; w < WPR; ++w) {
+              if constexpr (FP) accf[w] += __uint_as_float(x[w]);
+              else acc[w] += x[w];
+            }
+          }
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          const int w = g / W, f = g % W;
+          uint32_t S;
+          if constexpr (FP) S = fkey(accf[w]);
+          else S = LWB == 32 ? acc[w] : ((acc[w] >> (f * LWB)) & MASK);
+          if (PHASE == 1) {
+            lmin[g] = S < lmin[g] ? S : lmin[g];
+          } else if (live[g] && S <= sig[g]) {
+            const int q = pq[g];
+            const uint32_t pos = atomicAdd(&a.ccount[q], 1u);
+            if (pos < a.capq) {
+              uint64_t key;
+              if constexpr (FP) key = (uint64_t)S;
+              else key = ikey(pbase[g] + ((int64_t)S << ps[g]));
+              a.ckey[(size_t)q * a.capq + pos] = key;
+              a.cid[(size_t)q * a.capq + pos] = a.ids[L0 + v];
+            } else {
+              atomicOr(&a.flags[0], 1);
+            }
+          }
+        }
+      }
+    }
+    if (PHASE == 1) {
+      // the k-th smallest of the per-thread minima bounds the pair's k-th
+      // smallest (each minimum is a distinct vector)
+      __syncthreads();  // the LUT space is reused below
+      uint32_t* lm = reinterpret_cast<uint32_t*>(lds + L.lmin);
+#pragma unroll
+      for (int g = 0; g < G; ++g) lm[g * kThreads + tid] = lmin[g];
+      __syncthreads();
+      for (int size = 2; size <= kThreads; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+          for (int i = tid; i < G * (kThreads / 2); i += kThreads) {
+            const int g = i / (kThreads / 2), ii = i % (kThreads / 2);
+            const int pos = 2 * ii - (ii & (stride - 1));
+            const bool asc = (pos & size) == 0;
+            uint32_t* arr = lm + g * kThreads;
+            const uint32_t x0 = arr[pos], x1 = arr[pos + stride];
+            if ((x0 > x1) == asc) { arr[pos] = x1; arr[pos + stride] = x0; }
+          }
+          __syncthreads();
+        }
+      if (tid < np_u) {
+        const int q = pq[tid];
+        const int kk = a.kq ? a.kq[q] : a.kconst;
+        if (kk <= kThreads) {
+          const uint32_t val = lm[tid * kThreads + kk - 1];
+          if (val != 0xFFFFFFFFu) {
+            uint64_t key;
+            if constexpr (FP) key = (uint64_t)val;
+            else key = ikey(pbase[tid] + ((int64_t)val << ps[tid]));
+            atomicMin((unsigned long long*)&a.tau[q], (unsigned long long)key);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ TS
+struct MergeArgs {
+  const uint32_t* ccount;
+  const uint64_t* ckey;
+  const int64_t* cid;
+  const int32_t* kq;
+  int32_t* flags;
+  int64_t* out_ids;
+  float* out_dist;
+  int64_t* out_qdist;
+  int kconst, kmax, fp32;
+  float h2;
+  size_t capq;
+};
+
+__global__ __launch_bounds__(256) void k_merge(MergeArgs a) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  const int q = blockIdx.x;
+  const uint32_t cnt = a.ccount[q];
+  if (cnt > a.capq && threadIdx.x == 0) atomicOr(&a.flags[0], 2);
+  const int n = (int)(cnt < a.capq ? cnt : a.capq);
+  int np2 = 1;
+  while (np2 < n) np2 <<= 1;
+  uint64_t* keys = reinterpret_cast<uint64_t*>(lds);
+  int64_t* vals = reinterpret_cast<int64_t*>(lds + a.capq * 8);
+  for (int i = threadIdx.x; i < np2; i += blockDim.x) {
+    keys[i] = i < n ? a.ckey[(size_t)q * a.capq + i] : ~0ull;
+    vals[i] = i < n ? a.cid[(size_t)q * a.capq + i] : INT64_MAX;
+  }
+  __syncthreads();
+  block_bitonic_u64_i64(keys, vals, np2);
+  const int kk = a.kq ? a.kq[q] : a.kconst;
+  for (int r = threadIdx.x; r < a.kmax; r += blockDim.x) {
+    const size_t o = (size_t)q * a.kmax + r;
+    if (r < kk && r < n) {
+      a.out_ids[o] = vals[r];
+      if (a.fp32) {
+        a.out_dist[o] = fkey_val((uint32_t)keys[r]);
+        if (a.out_qdist) a.out_qdist[o] = -1;
+      } else {
+        const int64_t D = ikey_val(keys[r]);
+        a.out_dist[o] = __ll2float_rn(D) * a.h2;
+        if (a.out_qdist) a.out_qdist[o] = D;
+      }
+    } else {
+      a.out_ids[o] = -1;
+      a.out_dist[o] = __builtin_inff();
+      if (a.out_qdist) a.out_qdist[o] = INT64_MAX;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ index prep
+// MFMA B fragments of the grid codebook: for m-pair mp, codeword tile jt and
+// lane l (group kg = l/16, codeword j = 16 jt + l%16):
+//   kg even: cbi[m][j][0..dsub) zero-padded to 8;  kg odd: digits of
+//   cc = |cbi[m][j]|^2 (base 256, most significant first) then 65536, 256, 1
+__global__ void k_prep_bsw(const float* __restrict__ cb, int M, int dsub, int grid_e, int grid_kind,
+                           u32x4* __restrict__ bsw) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int total = (M / 2) * 16 * 64;
+  if (idx >= total) return;
+  const int lane = idx & 63, jt = (idx >> 6) & 15, mp = idx >> 10;
+  const int kg = lane >> 4, j = jt * 16 + (lane & 15);
+  const int m = 2 * mp + (kg >> 1);
+  const float* c = cb + ((size_t)m * kKsub + j) * dsub;
+  float v[8];
+  int ci[kMaxDsub];
+  int cc = 0;
+  for (int t = 0; t < kMaxDsub; ++t) {
+    ci[t] = t < dsub ? grid_val(c[t], grid_e, grid_kind) : 0;
+    cc += ci[t] * ci[t];
+  }
+  if ((kg & 1) == 0) {
+    for (int t = 0; t < 8; ++t) v[t] = (float)ci[t];
+  } else {
+    v[0] = (float)(cc >> 16);
+    v[1] = (float)((cc >> 8) & 255);
+    v[2] = (float)(cc & 255);
+    v[3] = 65536.f;
+    v[4] = 256.f;
+    v[5] = 1.f;
+    v[6] = 0.f;
+    v[7] = 0.f;
+  }
+  u32x4 o;
+  for (int t = 0; t < 4; ++t) o[t] = bf16_bits(v[2 * t]) | (bf16_bits(v[2 * t + 1]) << 16);
+  bsw[idx] = o;
+}
+
+// ------------------------------------------------------------------ host launchers
+template <typename K>
+static void* kaddr(K k) { return reinterpret_cast<void*>(k); }
+
+hipError_t launch_prep_index(const amp_index* ix, hipStream_t st) {
+  const DeviceIndex& dv = ix->dev;
+  hipLaunchKernelGGL(k_sqnorm, dim3((ix->nlist + 3) / 4), dim3(256), 0, st, dv.centroids, ix->nlist,
+                     ix->d, dv.cnorm);
+  const int total = (ix->M / 2) * 16 * 64;
+  hipLaunchKernelGGL(k_prep_bsw, dim3((total + 255) / 256), dim3(256), 0, st, dv.codebook, ix->M, ix->dsub,
+                     ix->grid_e, ix->grid_kind, reinterpret_cast<u32x4*>(dv.bsw));
+  return hipGetLastError();
+}
+
+size_t scan_lds_bytes(int lw_bits, int phase, int M, int d) {
+  const bool fp = lw_bits == 0;
+  const int wpr = wpr_for(M);
+  const int G = fp ? wpr : wpr * (32 / lw_bits);
+  return (size_t)scan_lds_layout(G, wpr, M, d, fp, phase).total;
+}
+int scan_wpr(int M) { return wpr_for(M); }
+
+typedef void (*ScanFn)(ScanArgs);
+template <int LWB, int MT, int PH>
+static ScanFn scan_fn() { return k_scan<LWB, MT, PH>; }
+
+// kernels specialised for the subspace counts 8, 16 and 24 (codes and, for
+// M <= 16, the MFMA B fragments kept in registers); any other M runs the
+// generic variant
+static ScanFn pick_scan(int lwb, int M, int ph) {
+#define AMP_PICK_M(L, MT) \
+  if (M == MT || MT == 0) return ph == 1 ? scan_fn<L, MT, 1>() : scan_fn<L, MT, 2>();
+#define AMP_PICK(L)     \
+  if (lwb == L) {       \
+    AMP_PICK_M(L, 8)    \
+    AMP_PICK_M(L, 16)   \
+    AMP_PICK_M(L, 24)   \
+    AMP_PICK_M(L, 0)    \
+  }
+  AMP_PICK(0)
+  AMP_PICK(8)
+  AMP_PICK(16)
+  AMP_PICK(32)
+#undef AMP_PICK
+#undef AMP_PICK_M
+  return nullptr;
+}
+
+static int g_num_cu = 0;
+
+static hipError_t launch_scan(int lwb, int ph, const ScanArgs& sa, hipStream_t st) {
+  ScanFn fn = pick_scan(lwb, sa.M, ph);
+  const size_t lds = scan_lds_bytes(lwb, ph, sa.M, sa.d);
+  hipError_t e = hipFuncSetAttribute(kaddr(fn), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  int per_cu = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kaddr(fn), kThreads, lds);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) return hipErrorInvalidConfiguration;
+  if (!g_num_cu) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&g_num_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  }
+  hipLaunchKernelGGL(fn, dim3(g_num_cu * per_cu), dim3(kThreads), lds, st, sa);
+  return hipGetLastError();
+}
+
+hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* queries, const SearchDims& sd,
+                         const ModelArgs& ma, int64_t* out_ids, float* out_dist, int64_t* out_qdist,
+                         float* out_coarse, hipStream_t st, hipEvent_t* ev) {
+  const DeviceIndex& dv = ix->dev;
+  const bool fp32 = sd.policy == AMP_POLICY_FP32;
+  const int ncls = fp32 ? 1 : kNCls;
+  const int NB = ncls * sd.nlist;
+  const size_t npairs = (size_t)sd.nq * sd.npmax;
+  auto mark = [&](int i) { if (ev) (void)hipEventRecord(ev[i], st); };
+  mark(0);
+  // CL
+  hipLaunchKernelGGL(k_sqnorm, dim3((sd.nq + 3) / 4), dim3(256), 0, st, queries, sd.nq, sd.d, ws.qnorm);
+  float* coarse = out_coarse ? out_coarse : ws.coarse;
+  hipLaunchKernelGGL(k_coarse, dim3((sd.nlist + CL_T - 1) / CL_T, (sd.nq + CL_T - 1) / CL_T), dim3(256), 0, st,
+                     queries, dv.centroids, ws.qnorm, dv.cnorm, coarse, sd.nq, sd.nlist, sd.d, sd.metric);
+  mark(1);
+  int np2 = 1;
+  while (np2 < sd.nlist) np2 <<= 1;
+  hipLaunchKernelGGL(k_topn, dim3(sd.nq), dim3(256), np2 * sizeof(uint64_t), st, coarse, sd.nlist, np2,
+                     ws.npq ? ws.npq : nullptr, sd.npconst, sd.npmax, ws.probes, ws.pdist);
+  mark(2);
+  // resets
+  hipLaunchKernelGGL(k_fill_u32, dim3(64), dim3(256), 0, st, reinterpret_cast<uint32_t*>(ws.cnt), 0u,
+                     (size_t)2 * NB);
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, ws.counters, 0u, (size_t)2 * (kNCls + 1));
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(ws.flags), 0u, (size_t)4);
+  hipLaunchKernelGGL(k_fill_u64, dim3(64), dim3(256), 0, st, ws.tau, ~0ull, (size_t)sd.nq);
+  hipLaunchKernelGGL(k_fill_u32, dim3(64), dim3(256), 0, st, ws.ccount, 0u, (size_t)sd.nq);
+  // PPM
+  PairArgs pa;
+  pa.Q = queries;
+  pa.C = dv.centroids;
+  pa.probes = ws.probes;
+  pa.radq = dv.radq;
+  pa.offsets = dv.offsets;
+  pa.xbits = ws.xbits;
+  pa.pbits = ws.pbits;
+  pa.nq = sd.nq;
+  pa.d = sd.d;
+  pa.npmax = sd.npmax;
+  pa.grid_e = sd.grid_e;
+  pa.grid_kind = sd.grid_kind;
+  pa.metric = sd.metric;
+  pa.policy = sd.policy;
+  pa.fixed_bits = sd.fixed_bits;
+  pa.lane_sel_M = sd.M;
+  pa.allowed = sd.allowed_mask;
+  pa.margin = sd.margin;
+  const int pthreads = ((sd.npmax + 63) / 64) * 64;
+  hipLaunchKernelGGL(k_pairs, dim3(sd.nq), dim3(pthreads), 0, st, pa, ma);
+  mark(3);
+  // queue
+  QueueArgs qa;
+  qa.probes = ws.probes;
+  qa.pbits = ws.pbits;
+  qa.offsets = dv.offsets;
+  qa.cnt = ws.cnt;
+  qa.rank = ws.rank;
+  qa.pairoff = ws.pairoff;
+  qa.unitoff = ws.unitoff;
+  qa.sorted = ws.sorted;
+  qa.units = ws.units;
+  qa.flags = ws.flags;
+  qa.nq = sd.nq;
+  qa.npmax = sd.npmax;
+  qa.nlist = sd.nlist;
+  qa.M = sd.M;
+  qa.ncls = ncls;
+  qa.wpr = sd.wpr;
+  qa.chunk = sd.chunk;
+  qa.max_units = sd.max_units;
+  const int qb = (int)((npairs + 255) / 256);
+  hipLaunchKernelGGL(k_qhist, dim3(qb), dim3(256), 0, st, qa);
+  hipLaunchKernelGGL(k_qscan, dim3(1), dim3(1024), 0, st, qa, fp32 ? 1 : 0);
+  hipLaunchKernelGGL(k_qscatter, dim3(qb), dim3(256), 0, st, qa);
+  hipLaunchKernelGGL(k_qunits, dim3(512), dim3(256), 0, st, qa, fp32 ? 1 : 0);
+  mark(4);
+  // LC + DC, phase 1 then phase 2
+  ScanArgs sa;
+  sa.Q = queries;
+  sa.C = dv.centroids;
+  sa.codebook = dv.codebook;
+  sa.bsw = reinterpret_cast<const u32x4*>(dv.bsw);
+  sa.codes = dv.codes;
+  sa.ids = dv.ids;
+  sa.offsets = dv.offsets;
+  sa.kq = ws.kq;
+  sa.pbits = ws.pbits;
+  sa.tau = ws.tau;
+  sa.ccount = ws.ccount;
+  sa.ckey = ws.ckey;
+  sa.cid = ws.cid;
+  sa.flags = ws.flags;
+  sa.nq = sd.nq;
+  sa.d = sd.d;
+  sa.M = sd.M;
+  sa.dsub = sd.dsub;
+  sa.nlist = sd.nlist;
+  sa.npmax = sd.npmax;
+  sa.grid_e = sd.grid_e;
+  sa.grid_kind = sd.grid_kind;
+  sa.metric = sd.metric;
+  sa.kconst = sd.kconst;
+  sa.chunk = sd.chunk;
+  sa.capq = sd.capq;
+  hipError_t err = hipSuccess;
+  for (int ph = 1; ph <= 2; ++ph) {
+    sa.sorted = ws.sorted + (ph == 2 ? npairs : 0);
+    sa.unitoff = ws.unitoff + (ph == 2 ? (NB + 1) : 0);
+    sa.units = ws.units + (ph == 2 ? sd.max_units : 0);
+    for (int c = 0; c < ncls; ++c) {
+      sa.cls = c;
+      sa.counter = ws.counters + (ph - 1) * (kNCls + 1) + c;
+      err = launch_scan(fp32 ? 0 : lane_bits(c), ph, sa, st);
+      if (err != hipSuccess) return err;
+    }
+    mark(4 + ph);
+  }
+  // TS
+  MergeArgs ma2;
+  ma2.ccount = ws.ccount;
+  ma2.ckey = ws.ckey;
+  ma2.cid = ws.cid;
+  ma2.kq = ws.kq;
+  ma2.flags = ws.flags;
+  ma2.out_ids = out_ids;
+  ma2.out_dist = out_dist;
+  ma2.out_qdist = out_qdist;
+  ma2.kconst = sd.kconst;
+  ma2.kmax = sd.kmax;
+  ma2.fp32 = fp32 ? 1 : 0;
+  ma2.h2 = ldexpf(1.f, 2 * sd.grid_e);
+  ma2.capq = sd.capq;
+  const size_t mlds = sd.capq * 16;
+  err = hipFuncSetAttribute(kaddr(k_merge), hipFuncAttributeMaxDynamicSharedMemorySize, (int)mlds);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_merge, dim3(sd.nq), dim3(256), mlds, st, ma2);
+  mark(7);
+  return hipGetLastError();
+}
+
+}  // namespace amp

@@ -1,0 +1,114 @@
+"""The C-ABI library loads, exports every declared symbol and validates its
+arguments on the host (no GPU needed; no compute call is made)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2606_07156_amd as amp
+from amp_data import lossless_index
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    with open(os.path.join(ROOT, "include", "amp.h")) as f:
+        decl = set(re.findall(r"^\s*(?:amp_status|void|const char\*)\s+(amp_\w+)\s*\(", f.read(), re.M))
+    assert decl, "no declarations parsed"
+    L = ctypes.CDLL(amp.LIB_PATH)
+    for name in sorted(decl):
+        assert hasattr(L, name), name
+    assert decl == set(amp.EXPORTS)
+
+
+def _idx():
+    idx, base = lossless_index(seed=5, nlist=6, M=4, dsub=4, per_list=[40, 3, 77, 0, 12, 60])
+    return idx
+
+
+def test_from_arrays_info_and_file_roundtrip(tmp_path):
+    idx = _idx()
+    h = amp.amp_index_from_arrays(idx)
+    info = amp.amp_index_info(h)
+    assert info == dict(d=16, M=4, nlist=6, n=192)
+    p = tmp_path / "a.idx"
+    amp.amp_index_save(h, p)
+    h2 = amp.amp_index_load(p)
+    assert amp.amp_index_info(h2) == info
+    p2 = tmp_path / "b.idx"
+    amp.amp_index_save(h2, p2)
+    assert p.read_bytes() == p2.read_bytes()
+
+
+def test_corrupt_truncated_and_foreign_files_are_rejected(tmp_path):
+    h = amp.amp_index_from_arrays(_idx())
+    p = tmp_path / "a.idx"
+    amp.amp_index_save(h, p)
+    raw = bytearray(p.read_bytes())
+    bad = tmp_path / "bad.idx"
+    flip = bytearray(raw)
+    flip[len(flip) // 2] ^= 0xFF
+    bad.write_bytes(bytes(flip))
+    with pytest.raises(amp.AmpError) as e:
+        amp.amp_index_load(bad)
+    assert e.value.status == amp.AMP_EFORMAT
+    bad.write_bytes(bytes(raw[: len(raw) - 7]))
+    with pytest.raises(amp.AmpError) as e:
+        amp.amp_index_load(bad)
+    assert e.value.status == amp.AMP_EFORMAT
+    bad.write_bytes(b"not an index at all")
+    with pytest.raises(amp.AmpError) as e:
+        amp.amp_index_load(bad)
+    assert e.value.status == amp.AMP_EFORMAT
+    v2 = bytearray(raw)
+    v2[8] = 99
+    bad.write_bytes(bytes(v2))
+    with pytest.raises(amp.AmpError) as e:
+        amp.amp_index_load(bad)
+    assert e.value.status == amp.AMP_EFORMAT
+    with pytest.raises(amp.AmpError) as e:
+        amp.amp_index_load(tmp_path / "missing.idx")
+    assert e.value.status == amp.AMP_EIO
+
+
+def test_invalid_index_arrays_are_rejected():
+    idx = _idx()
+    bad = dict(idx)
+    bad["ids"] = idx["ids"].copy()
+    off = idx["list_offsets"]
+    bad["ids"][off[0]], bad["ids"][off[0] + 1] = idx["ids"][off[0] + 1], idx["ids"][off[0]]
+    with pytest.raises(amp.AmpError) as e:
+        amp.amp_index_from_arrays(bad)
+    assert e.value.status == amp.AMP_EINVAL and "increasing" in str(e.value)
+    bad = dict(idx, M=3)
+    with pytest.raises(amp.AmpError):
+        amp.amp_index_from_arrays(bad)
+    bad = dict(idx, d=80, M=4, centroids=np.zeros((6, 80), np.float32),
+               codebook=np.zeros((4, 256, 20), np.float32))
+    with pytest.raises(amp.AmpError) as e:
+        amp.amp_index_from_arrays(bad)
+    assert e.value.status == amp.AMP_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("kw,frag", [
+    (dict(k=0, nprobe=2), "k = 0"),
+    (dict(k=2000, nprobe=2), "k = 2000"),
+    (dict(k=3, nprobe=0), "nprobe = 0"),
+    (dict(k=3, nprobe=7), "nprobe = 7"),
+    (dict(k=3, nprobe=2, policy="fixed", bits=5), "fixed_bits"),
+    (dict(k=3, nprobe=2, policy="adaptive"), "predictor"),
+    (dict(k=3, nprobe=2, policy="explicit"), "explicit_bits"),
+    (dict(k=3, nprobe=2, policy="explicit", explicit_bits=np.full((2, 2), 6, np.uint8)), "explicit width"),
+])
+def test_search_argument_validation_happens_before_device_work(kw, frag):
+    h = amp.amp_index_from_arrays(_idx())
+    with pytest.raises(amp.AmpError) as e:
+        amp.amp_search(h, np.zeros((2, 16), np.float32), **kw)
+    assert e.value.status == amp.AMP_EINVAL and frag in str(e.value)
+
+
+def test_status_strings():
+    assert amp.amp_status_str(0) == "ok"
+    assert amp.amp_status_str(amp.AMP_EOVERFLOW) == "candidate buffer overflow"

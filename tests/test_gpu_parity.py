@@ -1,0 +1,246 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle on the
+same seeded inputs.  Integer policies: ids, integer distances and float
+distances bit-exact (given the probe set, whose differences must be certified
+FP32 near-ties).  FP32 policy and coarse distances: within the FP32 bounds
+stated in tests/_parity.py (at most 1e-3 relative)."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2606_07156_amd as amp
+from amp_data import build_index, lossless_index, random_model
+from amp_data.synth import WORKLOADS, make_base, make_queries
+from _parity import certify_probes, check_coarse, compare_fp32, compare_integer
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(idx, Q, base=None):
+    h = amp.amp_index_from_arrays(idx)
+    amp.amp_index_to_device(h, 0)
+    return dict(idx=idx, Q=Q, base=base, h=h)
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    w = WORKLOADS["tiny"]
+    base = make_base(w)
+    idx = build_index(base, w.nlist, w.M, iters=10, seed=w.seed)
+    return _ctx(idx, make_queries(w, 100), base)
+
+
+@pytest.fixture(scope="module")
+def midint():
+    # the mid-size workload's shape (d=128, M=16, integer data) at a size the
+    # oracle finishes in seconds
+    w = WORKLOADS["mid"].scaled(n=60_000, nq=48, nlist=128)
+    base = make_base(w)
+    idx = build_index(base, w.nlist, w.M, iters=8, seed=w.seed, integer_data=True)
+    return _ctx(idx, make_queries(w, 48), base)
+
+
+def _gpu(ctx, k, nprobe, **pol):
+    return amp.amp_search(ctx["h"], ctx["Q"], k, nprobe, want_probes=True, want_bits=True,
+                          want_coarse=True, **pol)
+
+
+def _oracle(ctx, k, nprobe, g, **pol):
+    return oracle.search(ctx["idx"], ctx["Q"], k, nprobe, probes=g["probes"], **pol)
+
+
+def test_coarse_distances_and_probe_sets(tiny):
+    g = _gpu(tiny, 10, 8)
+    check_coarse(g["coarse"], tiny["idx"], tiny["Q"])
+    ties = certify_probes(g["probes"], tiny["idx"], tiny["Q"], 8)
+    assert ties <= 2
+
+
+@pytest.mark.parametrize("bits", [4, 8, 12, 16])
+def test_fixed_width_is_bit_exact(tiny, bits):
+    g = _gpu(tiny, 10, 8, policy="fixed", bits=bits)
+    certify_probes(g["probes"], tiny["idx"], tiny["Q"], 8)
+    ref = _oracle(tiny, 10, 8, g, policy="fixed", bits=bits)
+    assert (g["bits"] == bits).all()
+    compare_integer(g, ref)
+
+
+def test_fp32_policy_within_fp32_bound(tiny):
+    g = _gpu(tiny, 10, 8, policy="fp32")
+    ref = _oracle(tiny, 10, 8, g, policy="fp32")
+    assert (g["qdist"] == -1).all()
+    swaps = compare_fp32(g, ref, tiny["idx"]["M"])
+    assert swaps <= 3
+
+
+def test_explicit_widths_are_bit_exact(tiny):
+    r = np.random.default_rng(3)
+    xb = r.choice(np.array([4, 8, 12, 16], np.uint8), size=(len(tiny["Q"]), 8))
+    g = _gpu(tiny, 10, 8, policy="explicit", explicit_bits=xb)
+    assert np.array_equal(g["bits"], xb)
+    ref = _oracle(tiny, 10, 8, g, policy="explicit", explicit_bits=xb)
+    compare_integer(g, ref)
+
+
+def _spread_model(ctx, nprobe, seed=0, n_sv=200):
+    """A seeded random regressor whose feature map covers the index's feature
+    ranges and whose thresholds split the scores of these queries into four
+    width classes (scores from the oracle)."""
+    idx, Q = ctx["idx"], ctx["Q"]
+    inv = 2.0 ** -idx["grid_e"]
+    dq = []
+    for q in Q[:16]:
+        P = oracle.select_probes(oracle.coarse_distances(q, idx["centroids"]), nprobe)
+        for p in P:
+            r = oracle.grid(oracle.residual_f32(q, idx["centroids"][p]).astype(np.float64) * inv,
+                            idx["grid_kind"])
+            dq.append(int((r * r).sum()))
+    feats = [np.asarray(dq), idx["radq"], idx["radq"], idx["list_sizes"], idx["list_sizes"]]
+    lo, mul = [], []
+    for f in feats:
+        L = oracle.mitchell_log2_q8(np.asarray(f, dtype=np.int64))
+        a, b = int(L.min()), int(L.max())
+        lo.append(a)
+        mul.append(int(1023 * 65536 // max(1, b - a)))
+    m = random_model(seed, n_sv, lo, mul, gamma=1.0)
+    ys = []
+    for q in Q[:16]:
+        P = oracle.select_probes(oracle.coarse_distances(q, idx["centroids"]), nprobe)
+        d2 = []
+        for p in P:
+            r = oracle.grid(oracle.residual_f32(q, idx["centroids"][p]).astype(np.float64) * inv,
+                            idx["grid_kind"])
+            d2.append(int((r * r).sum()))
+        _, y = oracle.predict_pair_bits(np.asarray(d2), P, idx["radq"], idx["list_sizes"], m)
+        ys.extend(int(v) for v in y)
+    m["theta"] = np.quantile(np.asarray(ys, dtype=np.float64), [0.25, 0.5, 0.75]).astype(np.int64)
+    return m
+
+
+def test_adaptive_predictor_and_search_are_bit_exact(tiny):
+    m = _spread_model(tiny, 8)
+    amp.amp_index_set_predictor(tiny["h"], m)
+    g = _gpu(tiny, 10, 8, policy="adaptive")
+    ref = _oracle(tiny, 10, 8, g, policy="adaptive", model=m)
+    assert np.array_equal(g["bits"], ref["bits"].astype(np.uint8))
+    assert len(np.unique(g["bits"])) >= 3
+    compare_integer(g, ref)
+    # restricted width sets and a score margin
+    g2 = _gpu(tiny, 10, 8, policy="adaptive", allowed=(4, 8, 16), margin_q40=int(m["theta"][1] - m["theta"][0]))
+    ref2 = _oracle(tiny, 10, 8, g2, policy="adaptive", model=m, allowed=(4, 8, 16),
+                   margin_q40=int(m["theta"][1] - m["theta"][0]))
+    assert np.array_equal(g2["bits"], ref2["bits"].astype(np.uint8))
+    assert not (g2["bits"] == 12).any()
+    compare_integer(g2, ref2)
+
+
+@pytest.mark.parametrize("policy,bits", [("fixed", 4), ("fixed", 8), ("fixed", 12), ("fixed", 16), ("fp32", 0)])
+def test_integer_data_exact_end_to_end(midint, policy, bits):
+    """Integer data: coarse distances are exact in FP32, so probe sets must be
+    identical with no near-tie allowance."""
+    g = _gpu(midint, 10, 16, policy=policy, bits=bits)
+    for i, q in enumerate(midint["Q"]):
+        D64 = oracle.coarse_distances(q, midint["idx"]["centroids"])
+        assert np.array_equal(g["coarse"][i].astype(np.float64), D64)
+        assert np.array_equal(g["probes"][i], oracle.select_probes(D64, 16))
+    ref = oracle.search(midint["idx"], midint["Q"], 10, 16, policy=policy, bits=bits)
+    if policy == "fp32":
+        compare_fp32(g, ref, 16)
+    else:
+        compare_integer(g, ref)
+
+
+def test_lut_build_is_exact_at_the_grid_extremes():
+    """Codewords and residuals at the +-255 ends of the 9-bit grid: the
+    largest LUT entries (8 * 510^2) and |ri|^2 + off terms the MFMA path must
+    still reproduce exactly."""
+    r = np.random.default_rng(21)
+    nlist, M, dsub = 4, 16, 8
+    d = M * dsub
+    C = np.zeros((nlist, d), np.float32)
+    C[1:] = r.choice([-255.0, 255.0], size=(nlist - 1, d))
+    CB = r.choice([-255.0, 255.0, 0.0, 254.0, -1.0], size=(M, 256, dsub)).astype(np.float32)
+    CB[:, :8] = 255.0
+    CB[:, 8:16] = -255.0
+    n_per = 300
+    codes = r.integers(0, 256, size=(nlist * n_per, M)).astype(np.uint8)
+    idx = dict(d=d, M=M, dsub=dsub, nlist=nlist, ksub=256, metric="l2", grid_kind="u9", grid_e=0,
+               centroids=C, codebook=CB, list_offsets=np.arange(0, nlist * n_per + 1, n_per),
+               ids=np.arange(nlist * n_per, dtype=np.int64), codes=codes,
+               list_sizes=np.full(nlist, n_per, np.int32), radq=np.full(nlist, 100, np.int32))
+    Q = r.choice([-255.0, 255.0, 0.0], size=(12, d)).astype(np.float32)
+    Q[:4] = 255.0
+    Q[4:8] = -255.0
+    ctx = _ctx(idx, Q)
+    for bits in (16, 12, 4):
+        g = _gpu(ctx, 20, 4, policy="fixed", bits=bits)
+        ref = _oracle(ctx, 20, 4, g, policy="fixed", bits=bits)
+        compare_integer(g, ref)
+
+
+def test_edge_cases_padding_chunking_empty_lists_and_per_query_sizes(monkeypatch):
+    idx, base = lossless_index(seed=9, nlist=10, M=8, dsub=4,
+                               per_list=[0, 1, 257, 600, 3, 0, 1025, 64, 255, 9])
+    r = np.random.default_rng(4)
+    Q = r.integers(-40, 41, size=(37, 32)).astype(np.float32)
+    ctx = _ctx(idx, Q, base)
+    # k larger than every candidate set, nprobe = nlist, nq not a multiple of anything
+    g = _gpu(ctx, 1024, 10, policy="fixed", bits=16)
+    ref = _oracle(ctx, 1024, 10, g, policy="fixed", bits=16)
+    compare_integer(g, ref)
+    g = _gpu(ctx, 1024, 2, policy="fixed", bits=16)
+    ref = _oracle(ctx, 1024, 2, g, policy="fixed", bits=16)
+    compare_integer(g, ref)
+    assert (g["ids"] == -1).any() and (g["qdist"][g["ids"] == -1] == np.iinfo(np.int64).max).all()
+    # the lossless index at 16 bits with s = 0 reproduces exact kNN
+    truth = oracle.exact_knn(base, Q, 10)
+    g10 = _gpu(ctx, 10, 10, policy="fixed", bits=16)
+    assert np.array_equal(g10["ids"], truth)
+    # lists split into many work-unit chunks (ragged tails)
+    monkeypatch.setenv("AMP_CHUNK", "100")
+    for bits in (4, 16):
+        g = _gpu(ctx, 7, 6, policy="fixed", bits=bits)
+        compare_integer(g, _oracle(ctx, 7, 6, g, policy="fixed", bits=bits))
+    gf = _gpu(ctx, 7, 6, policy="fp32")
+    compare_fp32(gf, _oracle(ctx, 7, 6, gf, policy="fp32"), 8)
+    monkeypatch.delenv("AMP_CHUNK")
+    # per-query k and nprobe
+    kq = r.integers(1, 40, size=len(Q)).astype(np.int32)
+    npq = r.integers(1, 11, size=len(Q)).astype(np.int32)
+    g = _gpu(ctx, kq, npq, policy="fixed", bits=8)
+    ref = _oracle(ctx, kq, npq, g, policy="fixed", bits=8)
+    compare_integer(g, ref)
+    # a single query
+    g1 = amp.amp_search(ctx["h"], Q[:1], 5, 3)
+    r1 = oracle.search(idx, Q[:1], 5, 3)
+    compare_integer(g1, r1)
+
+
+def test_results_do_not_depend_on_batch_composition(tiny):
+    Q = tiny["Q"]
+    full = amp.amp_search(tiny["h"], Q, 10, 8, policy="fixed", bits=4)
+    for i in (0, 17, 99):
+        one = amp.amp_search(tiny["h"], Q[i:i + 1], 10, 8, policy="fixed", bits=4)
+        assert np.array_equal(one["ids"][0], full["ids"][i])
+        assert np.array_equal(one["qdist"][0], full["qdist"][i])
+    perm = np.random.default_rng(5).permutation(len(Q))
+    shuf = amp.amp_search(tiny["h"], Q[perm], 10, 8, policy="fixed", bits=4)
+    assert np.array_equal(shuf["ids"], full["ids"][perm])
+    again = amp.amp_search(tiny["h"], Q, 10, 8, policy="fixed", bits=4)
+    assert np.array_equal(again["ids"], full["ids"]) and np.array_equal(again["qdist"], full["qdist"])
+
+
+def test_device_mode_matches_host_mode(tiny):
+    torch = pytest.importorskip("torch")
+    Q = tiny["Q"]
+    host = amp.amp_search(tiny["h"], Q, 10, 8, policy="fixed", bits=8)
+    qd = torch.from_numpy(Q).cuda()
+    out = dict(ids=torch.empty((len(Q), 10), dtype=torch.int64, device="cuda"),
+               dist=torch.empty((len(Q), 10), dtype=torch.float32, device="cuda"),
+               qdist=torch.empty((len(Q), 10), dtype=torch.int64, device="cuda"))
+    s = torch.cuda.current_stream()
+    amp.amp_search(tiny["h"], qd, 10, 8, policy="fixed", bits=8, out=out, stream=s)
+    torch.cuda.synchronize()
+    assert np.array_equal(out["ids"].cpu().numpy(), host["ids"])
+    assert np.array_equal(out["qdist"].cpu().numpy(), host["qdist"])
