@@ -453,7 +453,7 @@ struct ScanArgs {
   uint64_t* ckey;
   int64_t* cid;
   int32_t* flags;
-  int nq, d, M, dsub, nlist, npmax, grid_e, grid_kind, metric, kconst, cls;
+  int nq, d, M, dsub, nlist, npmax, grid_e, grid_kind, metric, kconst, kmax, cls;
   int64_t chunk;
   size_t capq;
 };
@@ -660,14 +660,19 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
       for (int t = 0; t < kMaxDsub; ++t)
         own.c[m][t] = t < a.dsub ? a.codebook[((size_t)m * kKsub + tid) * a.dsub + t] : 0.f;
   }
+  // the next unit is claimed while the current one is processed: its index
+  // at the start, its descriptor before the scan, published at the end
+  if (tid == 0) {
+    const int uu = (int)atomicAdd(a.counter, 1u);
+    s_u = uu;
+    if (ub + uu < ue) s_unit = a.units[ub + uu];
+  }
+  __syncthreads();
   for (;;) {
-    if (tid == 0) {
-      const int uu = (int)atomicAdd(a.counter, 1u);
-      s_u = uu;
-      if (ub + uu < ue) s_unit = a.units[ub + uu];
-    }
-    __syncthreads();
     if (ub + s_u >= ue) break;
+    int next_u = 0;
+    int4 next_unit = make_int4(0, 0, 0, 0);
+    if (tid == 0) next_u = (int)atomicAdd(a.counter, 1u);
     const int p = s_unit.x, np_u = s_unit.z;
     const int64_t L0 = a.offsets[p];
     const int64_t n_list = a.offsets[p + 1] - L0;
@@ -696,37 +701,54 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
     __syncthreads();
     // ---- LC
     if constexpr (FP) {
+      // T[m][j] = (|r_m|^2 + |c_mj|^2) - 2 r_m.c_mj in FP32 (one FMA chain per entry)
       const float* r32 = reinterpret_cast<const float*>(lds + L.ri);
+      float* rr32 = reinterpret_cast<float*>(lds + L.rr);
+      for (int e = tid; e < np_u * M; e += kThreads) {
+        const int g = e / M, m = e % M;
+        const float* r = r32 + g * a.d + m * a.dsub;
+        float sq = 0.f;
+#pragma unroll
+        for (int t = 0; t < kMaxDsub; ++t)
+          if (t < a.dsub) sq = fmaf(r[t], r[t], sq);
+        rr32[e] = sq;
+      }
+      __syncthreads();
       float* lut = reinterpret_cast<float*>(lds + L.lut);
-      for (int m = 0; m < M; ++m) {
+      auto entry = [&](int m, const float (&c)[kMaxDsub]) {
         const int e = m * kKsub + tid;
-        float c[kMaxDsub];
-        if constexpr (CRES) {
+        float cc = 0.f;
 #pragma unroll
-          for (int t = 0; t < kMaxDsub; ++t) c[t] = own.c[MT ? m : 0][t];
-        } else {
-#pragma unroll
-          for (int t = 0; t < kMaxDsub; ++t) c[t] = t < a.dsub ? a.codebook[(size_t)e * a.dsub + t] : 0.f;
-        }
+        for (int t = 0; t < kMaxDsub; ++t) cc = fmaf(c[t], c[t], cc);
         float out[WPR];
 #pragma unroll
         for (int g = 0; g < WPR; ++g) {
-          float s = 0.f;
+          float sv = 0.f;
           if (g < np_u) {
             const float* r = r32 + g * a.d + m * a.dsub;
+            float dot = 0.f;
 #pragma unroll
-            for (int t = 0; t < kMaxDsub; ++t) {
-              if (t < a.dsub) {
-                const float df = r[t] - c[t];
-                s = fmaf(df, df, s);
-              }
-            }
+            for (int t = 0; t < kMaxDsub; ++t)
+              if (t < a.dsub) dot = fmaf(r[t], c[t], dot);
+            sv = fmaf(-2.f, dot, rr32[g * M + m] + cc);
           }
-          out[g] = s;
+          out[g] = sv;
         }
         float* dst = lut + (size_t)e * WPR;
 #pragma unroll
         for (int g = 0; g < WPR; ++g) dst[g] = out[g];
+      };
+      if constexpr (CRES) {
+#pragma unroll
+        for (int m = 0; m < MT; ++m) entry(m, own.c[m]);
+      } else {
+        for (int m = 0; m < M; ++m) {
+          float c[kMaxDsub];
+#pragma unroll
+          for (int t = 0; t < kMaxDsub; ++t)
+            c[t] = t < a.dsub ? a.codebook[((size_t)m * kKsub + tid) * a.dsub + t] : 0.f;
+          entry(m, c);
+        }
       }
       if (tid < G) {
         ps[tid] = 0;
@@ -813,6 +835,24 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
     uint32_t lmin[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) lmin[g] = 0xFFFFFFFFu;
+    // packed thresholds of the 8-bit lane class: fields 0,2 and 1,3 of each
+    // word in 16-bit halves with guard bit 8; dead pairs never hit
+    uint32_t sig_e[WPR], sig_o[WPR], msk_e[WPR], msk_o[WPR];
+    if constexpr (PHASE == 2 && LWB == 8) {
+#pragma unroll
+      for (int w = 0; w < WPR; ++w) {
+        uint32_t se = 0, so = 0, me = 0, mo = 0;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+          const int g = 4 * w + f;
+          const uint32_t sg = live[g] ? (sig[g] > 255u ? 255u : sig[g]) : 255u;
+          const uint32_t gb = live[g] ? 0x100u : 0u;
+          if (f & 1) { so |= (sg | 0x100u) << (16 * (f >> 1)); mo |= gb << (16 * (f >> 1)); }
+          else { se |= (sg | 0x100u) << (16 * (f >> 1)); me |= gb << (16 * (f >> 1)); }
+        }
+        sig_e[w] = se; sig_o[w] = so; msk_e[w] = me; msk_o[w] = mo;
+      }
+    }
     const uint32_t* lut = reinterpret_cast<const uint32_t*>(lds + L.lut);
     constexpr int MQ = MT ? MT / 4 : 1;  // code dwords per vector held in registers
     uint32_t cw_next[MQ];
@@ -826,6 +866,7 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
         }
       }
     }
+    if (tid == 0 && ub + next_u < ue) next_unit = a.units[ub + next_u];
     for (int64_t vb = v0; vb < v1; vb += kThreads) {
       const int64_t v = vb + tid;
       uint32_t cw[MQ];
@@ -861,33 +902,76 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
             }
           }
         }
+        auto emit = [&](int g, uint32_t S) {
+          const int q = pq[g];
+          const uint32_t pos = atomicAdd(&a.ccount[q], 1u);
+          if (pos < a.capq) {
+            uint64_t key;
+            if constexpr (FP) key = (uint64_t)S;
+            else key = ikey(pbase[g] + ((int64_t)S << ps[g]));
+            a.ckey[(size_t)q * a.capq + pos] = key;
+            a.cid[(size_t)q * a.capq + pos] = a.ids[L0 + v];
+          } else {
+            atomicOr(&a.flags[0], 1);
+          }
+        };
+        if constexpr (PHASE == 2 && LWB == 8) {
+          // four 8-bit sums per word: test all four against their thresholds
+          // at once in two 16-bit-lane halves (guard bit 8 survives iff S <= sigma)
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-          const int w = g / W, f = g % W;
-          uint32_t S;
-          if constexpr (FP) S = fkey(accf[w]);
-          else S = LWB == 32 ? acc[w] : ((acc[w] >> (f * LWB)) & MASK);
-          if (PHASE == 1) {
-            lmin[g] = S < lmin[g] ? S : lmin[g];
-          } else if (live[g] && S <= sig[g]) {
-            const int q = pq[g];
-            const uint32_t pos = atomicAdd(&a.ccount[q], 1u);
-            if (pos < a.capq) {
-              uint64_t key;
-              if constexpr (FP) key = (uint64_t)S;
-              else key = ikey(pbase[g] + ((int64_t)S << ps[g]));
-              a.ckey[(size_t)q * a.capq + pos] = key;
-              a.cid[(size_t)q * a.capq + pos] = a.ids[L0 + v];
-            } else {
-              atomicOr(&a.flags[0], 1);
+          for (int w = 0; w < WPR; ++w) {
+            const uint32_t e = acc[w] & 0x00FF00FFu, o = (acc[w] >> 8) & 0x00FF00FFu;
+            const uint32_t hit = ((sig_e[w] - e) & msk_e[w]) | ((sig_o[w] - o) & msk_o[w]);
+            if (hit) {
+#pragma unroll
+              for (int f = 0; f < 4; ++f) {
+                const uint32_t S = (acc[w] >> (8 * f)) & 0xFFu;
+                if (live[4 * w + f] && S <= sig[4 * w + f]) emit(4 * w + f, S);
+              }
+            }
+          }
+        } else {
+#pragma unroll
+          for (int g = 0; g < G; ++g) {
+            const int w = g / W, f = g % W;
+            uint32_t S;
+            if constexpr (FP) S = fkey(accf[w]);
+            else S = LWB == 32 ? acc[w] : ((acc[w] >> (f * LWB)) & MASK);
+            if (PHASE == 1) {
+              lmin[g] = S < lmin[g] ? S : lmin[g];
+            } else if (live[g] && S <= sig[g]) {
+              emit(g, S);
             }
           }
         }
       }
     }
-    if (PHASE == 1) {
-      // the k-th smallest of the per-thread minima bounds the pair's k-th
-      // smallest (each minimum is a distinct vector)
+    if (PHASE == 1 && a.kmax <= 64) {
+      // the k-th smallest of a wave's per-lane minima bounds the pair's k-th
+      // smallest (each minimum is a distinct vector); bitonic sort of the
+      // 64 minima across the lanes, then the tightest bound over the waves
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        if (g >= np_u) break;
+        uint32_t v = lmin[g];
+        for (int kb = 2; kb <= 64; kb <<= 1)
+          for (int jb = kb >> 1; jb > 0; jb >>= 1) {
+            const uint32_t o = (uint32_t)__shfl_xor((int)v, jb);
+            const bool asc = (lane & kb) == 0, lower = (lane & jb) == 0;
+            v = (lower == asc) ? (o < v ? o : v) : (o > v ? o : v);
+          }
+        const int q = pq[g];
+        const int kk = a.kq ? a.kq[q] : a.kconst;
+        const uint32_t val = (uint32_t)__shfl((int)v, kk - 1);
+        if (lane == 0 && val != 0xFFFFFFFFu) {
+          uint64_t key;
+          if constexpr (FP) key = (uint64_t)val;
+          else key = ikey(pbase[g] + ((int64_t)val << ps[g]));
+          atomicMin((unsigned long long*)&a.tau[q], (unsigned long long)key);
+        }
+      }
+    } else if (PHASE == 1) {
+      // k > 64: the k-th smallest of the workgroup's per-thread minima
       __syncthreads();  // the LUT space is reused below
       uint32_t* lm = reinterpret_cast<uint32_t*>(lds + L.lmin);
 #pragma unroll
@@ -918,6 +1002,11 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
           }
         }
       }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      s_u = next_u;
+      s_unit = next_unit;
     }
     __syncthreads();
   }
@@ -1184,6 +1273,7 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   sa.grid_kind = sd.grid_kind;
   sa.metric = sd.metric;
   sa.kconst = sd.kconst;
+  sa.kmax = sd.kmax;
   sa.chunk = sd.chunk;
   sa.capq = sd.capq;
   hipError_t err = hipSuccess;

@@ -76,7 +76,10 @@ def compare_fp32(gpu, ref, M):
     fin = np.isfinite(r_d)
     assert np.array_equal(np.isfinite(g_d), fin)
     scale = np.where(fin, np.abs(r_d), 0).max(1, keepdims=True) + 1e-30
-    tol = (M + 8) * 2.0 ** -22 * scale + 1e-3 * 0
+    # FP32 sums of M entries, each formed as |r|^2 + |c|^2 - 2 r.c: a few
+    # ulps of the row's distance scale; 1e-4 relative stays well inside the
+    # 1e-3 bar
+    tol = 1e-4 * scale
     assert np.all(np.abs(np.where(fin, g_d - r_d, 0)) <= tol)
     mism = gpu["ids"] != ref["ids"]
     for i, j in np.argwhere(mism):
