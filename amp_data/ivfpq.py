@@ -18,8 +18,9 @@ Conventions fixed here (the paper leaves them open):
   * members of a list are stored in increasing id order;
   * ``grid_e``: the operand grid step of the LUT build is h = 2**grid_e, the
     smallest power of two with max(|codeword entry|, |residual entry|) / h
-    within the grid's largest magnitude (255 for the 9-bit integer grid, 448
-    for the e4m3 grid); integer data uses h = 1;
+    (inner product: also |centroid entry| and |vector entry|) within the
+    grid's largest magnitude (255 for the 9-bit integer grid, 448 for the e4m3
+    grid); integer data uses h = 1;
   * ``radq``: the radius max ||x - c||_2 in grid units, rounded to nearest.
 """
 from __future__ import annotations
@@ -139,6 +140,9 @@ def build_index(base, nlist, M, iters=20, seed=0, integer_data=False,
         e = 0
     else:
         A = max(float(np.abs(CB).max()), float(np.abs(resid).max()))
+        if metric == "ip":
+            # inner product puts queries and centroids on the grid
+            A = max(A, float(np.abs(C).max()), float(np.abs(base).max()))
         e = int(np.ceil(np.log2(A / GRID_MAX[grid_kind])))
     h = 2.0 ** e
     return dict(

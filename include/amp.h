@@ -124,7 +124,12 @@ typedef struct amp_predictor_model {
  *   fixed_bits        width for AMP_POLICY_FIXED: 4, 8, 12 or 16
  *   allowed_bits_mask bit b set => width b allowed (ADAPTIVE); 0 = all four
  *   lut_dtype         AMP_LUT_* matrix dtype of the integer LUT build
- *                     (0 = BF16); the result does not depend on it
+ *                     (0 = BF16); the result does not depend on it.
+ *                     AMP_LUT_F8E4M3 is reserved and rejected with
+ *                     AMP_EUNSUPPORTED: the FP8 MFMA of gfx950 does not
+ *                     return exact sums of e4m3-grid products, so the
+ *                     entries would not be the exact integers the
+ *                     quantiser is defined on
  *   margin_q40        added to the regressor score before thresholding
  *   explicit_bits     host [nq][npmax] uint8 widths by probe rank (EXPLICIT)
  */
@@ -148,6 +153,12 @@ typedef struct amp_precision_policy {
  * call from events on the stream; forces a synchronisation at the end.
  */
 #define AMP_N_STAGES 8
+#define AMP_SEARCH_GRAPH 1u  /* flags: capture the search as a HIP graph once
+                                and replay it while queries/outputs pointers,
+                                sizes, policy and stream are unchanged (device
+                                mode, a created stream, constant k and
+                                nprobe, no stage_ms, not EXPLICIT).  Replays
+                                read the query buffer's current contents. */
 typedef struct amp_search_opts {
   int32_t mem;
   void* stream;
@@ -156,6 +167,7 @@ typedef struct amp_search_opts {
   uint8_t* out_bits;
   float* out_coarse;
   float* stage_ms;
+  uint32_t flags;
 } amp_search_opts;
 
 /* Build an index handle from arrays (copied).  Validates every constraint
@@ -196,6 +208,14 @@ typedef struct amp_train_report {
 amp_status amp_index_train_predictor(amp_index* index, const float* train_queries, int64_t nq,
                                      int32_t k, int32_t nprobe, const amp_train_params* params,
                                      amp_train_report* report /* optional */);
+
+/* The solver amp_index_train_predictor uses, exposed for testing: fit
+ * f(x) = sum_i coef[i] K(x_i, x) + bias to targets y [l] for a host kernel
+ * matrix K [l][l] (row-major, symmetric positive semi-definite) by the
+ * epsilon-insensitive SVR dual with box C, tolerance tol, at most max_iter
+ * pair updates.  coef [l] and bias are written; iterations may be NULL. */
+amp_status amp_svr_fit(const double* K, const double* y, int32_t l, double C, double eps, double tol,
+                       int32_t max_iter, double* coef, double* bias, int32_t* iterations);
 
 /* Copy the index's predictor into caller buffers: sv [capacity][5], beta
  * [capacity], table [1024] (host).  out->n_sv is always set; if capacity is

@@ -52,10 +52,13 @@ class _Policy(C.Structure):
                 ("lut_dtype", C.c_int32), ("margin_q40", C.c_int64), ("explicit_bits", C.c_void_p)]
 
 
+AMP_SEARCH_GRAPH = 1
+
+
 class _Opts(C.Structure):
     _fields_ = [("mem", C.c_int32), ("stream", C.c_void_p), ("out_qdist", C.c_void_p),
                 ("out_probes", C.c_void_p), ("out_bits", C.c_void_p), ("out_coarse", C.c_void_p),
-                ("stage_ms", C.c_void_p)]
+                ("stage_ms", C.c_void_p), ("flags", C.c_uint32)]
 
 
 class _TrainParams(C.Structure):
@@ -71,7 +74,7 @@ class _TrainReport(C.Structure):
 
 _lib = None
 EXPORTS = ("amp_index_from_arrays", "amp_index_set_predictor", "amp_index_get_predictor",
-           "amp_index_train_predictor",
+           "amp_index_train_predictor", "amp_svr_fit",
            "amp_index_to_device",
            "amp_index_save", "amp_index_load", "amp_index_info", "amp_search",
            "amp_index_free", "amp_status_str", "amp_last_error")
@@ -97,6 +100,8 @@ def lib():
                                               C.c_void_p, C.c_int32]
         L.amp_index_train_predictor.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32,
                                                 C.POINTER(_TrainParams), C.POINTER(_TrainReport)]
+        L.amp_svr_fit.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double,
+                                  C.c_int32, C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)]
         L.amp_index_to_device.argtypes = [C.c_void_p, C.c_int32]
         L.amp_index_save.argtypes = [C.c_void_p, C.c_char_p]
         L.amp_index_load.argtypes = [C.c_char_p, C.POINTER(C.c_void_p)]
@@ -215,6 +220,17 @@ def amp_index_train_predictor(index, train_queries, k, nprobe, n_samples=1280, g
                 smo_iterations=r.smo_iterations, train_rmse=r.train_rmse)
 
 
+def amp_svr_fit(K, y, C_=1.0, epsilon=0.1, tol=1e-3, max_iter=100000):
+    """Test hook: the SVR solver of the trainer on a precomputed kernel."""
+    K = np.ascontiguousarray(K, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    coef = np.zeros(len(y), np.float64)
+    b, it = C.c_double(), C.c_int32()
+    _check(lib().amp_svr_fit(_ptr(K), _ptr(y), len(y), float(C_), float(epsilon), float(tol), int(max_iter),
+                             _ptr(coef), C.byref(b), C.byref(it)))
+    return coef, b.value, it.value
+
+
 def amp_index_to_device(index, device=0):
     _check(lib().amp_index_to_device(index.handle, int(device)))
 
@@ -248,7 +264,7 @@ def make_policy(policy="fixed", bits=16, allowed=(4, 8, 12, 16), margin_q40=0,
 def amp_search(index, queries, k, nprobe, policy="fixed", bits=16, allowed=(4, 8, 12, 16),
                margin_q40=0, explicit_bits=None, lut_dtype=0, want_qdist=True,
                want_probes=False, want_bits=False, want_coarse=False, stage_ms=False,
-               out=None, stream=None):
+               out=None, stream=None, graph=False):
     """Search a batch.
 
     Host mode (``queries`` a numpy array): returns a dict of numpy arrays.
@@ -272,7 +288,8 @@ def amp_search(index, queries, k, nprobe, policy="fixed", bits=16, allowed=(4, 8
         o = out
         sh = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
         opts = _Opts(AMP_MEM_DEVICE, C.c_void_p(sh) if sh else None, _ptr(o.get("qdist")),
-                     _ptr(o.get("probes")), _ptr(o.get("bits")), _ptr(o.get("coarse")), _ptr(ms))
+                     _ptr(o.get("probes")), _ptr(o.get("bits")), _ptr(o.get("coarse")), _ptr(ms),
+                     AMP_SEARCH_GRAPH if graph else 0)
         _check(lib().amp_search(index.handle, _ptr(queries), nq, _ptr(kk), _ptr(npb), per_query,
                                 C.byref(pol), C.byref(opts), _ptr(o["ids"]), _ptr(o["dist"])))
         if stage_ms:
@@ -290,7 +307,8 @@ def amp_search(index, queries, k, nprobe, policy="fixed", bits=16, allowed=(4, 8
         info = amp_index_info(index)
         res["coarse"] = np.empty((nq, info["nlist"]), np.float32)
     opts = _Opts(AMP_MEM_HOST, None, _ptr(res.get("qdist")), _ptr(res.get("probes")),
-                 _ptr(res.get("bits")), _ptr(res.get("coarse")), _ptr(ms))
+                 _ptr(res.get("bits")), _ptr(res.get("coarse")), _ptr(ms),
+                 AMP_SEARCH_GRAPH if graph else 0)
     _check(lib().amp_search(index.handle, _ptr(q), nq, _ptr(kk), _ptr(npb), per_query,
                             C.byref(pol), C.byref(opts), _ptr(res["ids"]), _ptr(res["dist"])))
     if stage_ms:

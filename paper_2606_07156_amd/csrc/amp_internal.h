@@ -43,11 +43,15 @@ struct DeviceIndex {
   float* cnorm = nullptr;      // [nlist] squared norms (FP32, sequential order)
   float* codebook = nullptr;   // [M][256][dsub]
   uint4* bsw = nullptr;        // [M/2][16][64] MFMA B fragments (8 bf16 each)
+  uint4* bsw16 = nullptr;      // [M/2][16][64] FP16 dims fragments
+  int32_t* lorder = nullptr;   // [nlist] lists by decreasing size (ties: id)
+  int32_t* lpos = nullptr;     // [nlist] position of each list in lorder
   uint8_t* codes = nullptr;    // [N][M]
   int64_t* ids = nullptr;      // [N]
   int64_t* offsets = nullptr;  // [nlist+1]
   int32_t* radq = nullptr;     // [nlist]
   DeviceModel model;
+  hipEvent_t ev_done = nullptr;  // end of the last search on this index
 };
 
 // Scratch of one search, grown on demand and kept with the index.
@@ -87,6 +91,27 @@ struct Workspace {
 
 }  // namespace amp
 
+namespace amp {
+// what a captured search graph depends on
+struct GraphKey {
+  const void* q;
+  const void *ids, *dist, *qdist, *probes, *bits, *coarse;
+  void* stream;
+  int64_t nq;
+  int32_t k, nprobe, kind, fixed_bits;
+  uint32_t allowed;
+  int64_t margin;
+  int32_t lut_dtype;
+  uint64_t ws_gen, model_gen;
+  bool operator==(const GraphKey& o) const {
+    return q == o.q && ids == o.ids && dist == o.dist && qdist == o.qdist && probes == o.probes &&
+           bits == o.bits && coarse == o.coarse && stream == o.stream && nq == o.nq && k == o.k &&
+           nprobe == o.nprobe && kind == o.kind && fixed_bits == o.fixed_bits && allowed == o.allowed &&
+           margin == o.margin && lut_dtype == o.lut_dtype && ws_gen == o.ws_gen && model_gen == o.model_gen;
+  }
+};
+}  // namespace amp
+
 struct amp_index {
   // host copies
   int32_t d = 0, M = 0, dsub = 0, nlist = 0, metric = 0, grid_kind = 0, grid_e = 0;
@@ -105,6 +130,9 @@ struct amp_index {
   amp::DeviceIndex dev;
   bool dev_model_stale = true;
   amp::Workspace ws;
+  uint64_t ws_generation = 0, model_generation = 0;
+  hipGraphExec_t graph_exec = nullptr;
+  amp::GraphKey graph_key{};
   std::mutex mu;
 };
 
@@ -129,6 +157,7 @@ struct SearchDims {
   int64_t max_units;     // capacity of each phase's unit table
   size_t capq;
   int policy;            // AMP_POLICY_*
+  int lut_dtype;         // AMP_LUT_* (0 = BF16)
   int fixed_bits;
   uint32_t allowed_mask;
   int64_t margin;
@@ -151,7 +180,8 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
                          const SearchDims& sd, const ModelArgs& ma, int64_t* out_ids,
                          float* out_dist, int64_t* out_qdist, float* out_coarse,
                          hipStream_t st, hipEvent_t* ev /* [AMP_N_STAGES+1] or null */);
-size_t scan_lds_bytes(int lw_bits, int phase, int M, int d);
-int scan_wpr(int M);
+// LUT words per row of the scan variants a search runs (the queue packs its
+// work units to match)
+int scan_wpr(int M, bool fp32, int lut_dtype);
 
 }  // namespace amp

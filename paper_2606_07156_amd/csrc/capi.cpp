@@ -45,8 +45,9 @@ static amp_status dalloc(T** p, size_t n, std::vector<void*>* track = nullptr) {
 }
 
 static void free_device_index(DeviceIndex& d) {
-  void* ptrs[] = {d.centroids, d.cnorm, d.codebook, d.bsw, d.codes, d.ids, d.offsets, d.radq,
-                  d.model.sv, d.model.beta, d.model.table};
+  if (d.ev_done) hipEventDestroy(d.ev_done);
+  void* ptrs[] = {d.centroids, d.cnorm, d.codebook, d.bsw, d.bsw16, d.lorder, d.lpos, d.codes, d.ids,
+                  d.offsets, d.radq, d.model.sv, d.model.beta, d.model.table};
   for (void* p : ptrs)
     if (p) hipFree(p);
   d = DeviceIndex();
@@ -150,6 +151,7 @@ amp_status amp_index_set_predictor(amp_index* ix, const amp_predictor_model* m) 
   ix->g_mul = m->g_mul;
   ix->has_model = true;
   ix->dev_model_stale = true;
+  ix->model_generation++;
   return AMP_OK;
 }
 
@@ -203,6 +205,8 @@ static amp_status to_device_locked(amp_index* ix, int device) {
   const size_t nl = ix->nlist, dd = ix->d, M = ix->M, n = ix->n;
   if ((s = dalloc(&d.centroids, nl * dd)) || (s = dalloc(&d.cnorm, nl)) ||
       (s = dalloc(&d.codebook, M * kKsub * ix->dsub)) || (s = dalloc(&d.bsw, (M / 2) * 16 * 64)) ||
+      (s = dalloc(&d.bsw16, (M / 2) * 16 * 64)) ||
+      (s = dalloc(&d.lorder, nl)) || (s = dalloc(&d.lpos, nl)) ||
       (s = dalloc(&d.codes, std::max<size_t>(1, n * M))) || (s = dalloc(&d.ids, std::max<size_t>(1, n))) ||
       (s = dalloc(&d.offsets, nl + 1)) || (s = dalloc(&d.radq, nl))) {
     free_device_index(d);
@@ -216,6 +220,22 @@ static amp_status to_device_locked(amp_index* ix, int device) {
   }
   AMP_HIP(hipMemcpy(d.offsets, ix->offsets.data(), (nl + 1) * 8, hipMemcpyHostToDevice));
   AMP_HIP(hipMemcpy(d.radq, ix->radq.data(), nl * 4, hipMemcpyHostToDevice));
+  {
+    // work units are enumerated largest list first (longest-processing-time
+    // order for the persistent scan); index metadata, computed once
+    // (AMP_LIST_ORDER=natural keeps list-id order, for comparison)
+    std::vector<int32_t> order(nl), pos(nl);
+    for (size_t p = 0; p < nl; ++p) order[p] = (int32_t)p;
+    const char* lo_env = getenv("AMP_LIST_ORDER");
+    if (!lo_env || strcmp(lo_env, "natural") != 0)
+      std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+        return ix->offsets[x + 1] - ix->offsets[x] > ix->offsets[y + 1] - ix->offsets[y];
+      });
+    for (size_t i = 0; i < nl; ++i) pos[order[i]] = (int32_t)i;
+    AMP_HIP(hipMemcpy(d.lorder, order.data(), nl * 4, hipMemcpyHostToDevice));
+    AMP_HIP(hipMemcpy(d.lpos, pos.data(), nl * 4, hipMemcpyHostToDevice));
+  }
+  AMP_HIP(hipEventCreateWithFlags(&d.ev_done, hipEventDisableTiming));
   AMP_HIP(launch_prep_index(ix, nullptr));
   AMP_HIP(hipDeviceSynchronize());
   d.device = device;
@@ -247,6 +267,7 @@ amp_status amp_index_info(const amp_index* ix, int32_t* d, int32_t* M, int32_t* 
 void amp_index_free(amp_index* ix) {
   if (!ix) return;
   if (ix->dev.device >= 0) hipSetDevice(ix->dev.device);
+  if (ix->graph_exec) hipGraphExecDestroy(ix->graph_exec);
   free_workspace(ix->ws);
   free_device_index(ix->dev);
   delete ix;
@@ -430,6 +451,7 @@ static amp_status ensure_workspace(amp_index* ix, size_t nq, size_t np, size_t k
     free_workspace(w);
     return s;
   }
+  ix->ws_generation++;
   w.cap_nq = nq;
   w.cap_np = np;
   w.cap_k = kmax;
@@ -445,7 +467,6 @@ amp_status amp_search(amp_index* ix, const float* queries, int64_t nq, const int
     return set_error(AMP_EINVAL, "null argument");
   if (nq <= 0 || nq > (1 << 24)) return set_error(AMP_EINVAL, "nq %lld out of range", (long long)nq);
   if (opts->mem != AMP_MEM_HOST && opts->mem != AMP_MEM_DEVICE) return set_error(AMP_EINVAL, "bad mem kind");
-  if (ix->metric != AMP_L2) return set_error(AMP_EUNSUPPORTED, "inner-product search is not implemented yet");
   const int npmax_lim = std::min(ix->nlist, AMP_MAX_NPROBE);
   int kmax = 0, npmax = 0;
   const int64_t nk = per_query ? nq : 1;
@@ -476,8 +497,11 @@ amp_status amp_search(amp_index* ix, const float* queries, int64_t nq, const int
       break;
     default: return set_error(AMP_EINVAL, "bad policy kind %d", pol->kind);
   }
-  if (pol->lut_dtype != 0 && pol->lut_dtype != AMP_LUT_BF16)
-    return set_error(AMP_EUNSUPPORTED, "LUT build dtype %d is not implemented yet", pol->lut_dtype);
+  if (pol->lut_dtype == AMP_LUT_F8E4M3)
+    return set_error(AMP_EUNSUPPORTED, "FP8 LUT build: the gfx950 FP8 MFMA does not accumulate e4m3-grid "
+                                       "products exactly; use AMP_LUT_BF16 or AMP_LUT_F16");
+  if (pol->lut_dtype != 0 && pol->lut_dtype != AMP_LUT_BF16 && pol->lut_dtype != AMP_LUT_F16)
+    return set_error(AMP_EINVAL, "bad LUT build dtype %d", pol->lut_dtype);
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) {
     hipGetLastError();
@@ -496,6 +520,8 @@ amp_status amp_search(amp_index* ix, const float* queries, int64_t nq, const int
   Workspace& w = ix->ws;
   hipStream_t st = reinterpret_cast<hipStream_t>(opts->stream);
   const bool host = opts->mem == AMP_MEM_HOST;
+  // the scratch space is reused: start after the previous search on this index
+  AMP_HIP(hipStreamWaitEvent(st, ix->dev.ev_done, 0));
   const float* qdev = queries;
   if (host) {
     AMP_HIP(hipMemcpyAsync(w.queries, queries, (size_t)nq * ix->d * 4, hipMemcpyHostToDevice, st));
@@ -521,11 +547,12 @@ amp_status amp_search(amp_index* ix, const float* queries, int64_t nq, const int
   sd.grid_e = ix->grid_e;
   sd.kconst = per_query ? 0 : k[0];
   sd.npconst = per_query ? 0 : nprobe[0];
-  sd.wpr = scan_wpr(ix->M);
+  sd.wpr = scan_wpr(ix->M, pol->kind == AMP_POLICY_FP32, pol->lut_dtype);
   sd.chunk = chunk;
   sd.max_units = w.cap_units;
   sd.capq = capq;
   sd.policy = pol->kind;
+  sd.lut_dtype = pol->lut_dtype;
   sd.fixed_bits = pol->fixed_bits;
   sd.allowed_mask = pol->allowed_bits_mask ? pol->allowed_bits_mask
                                            : ((1u << 4) | (1u << 8) | (1u << 12) | (1u << 16));
@@ -541,6 +568,12 @@ amp_status amp_search(amp_index* ix, const float* queries, int64_t nq, const int
     ma.g_mul = ix->g_mul;
     for (int i = 0; i < 3; ++i) ma.theta[i] = ix->theta[i];
   }
+  const bool use_graph = (opts->flags & AMP_SEARCH_GRAPH) != 0;
+  if (use_graph && (host || per_query || opts->stage_ms || pol->kind == AMP_POLICY_EXPLICIT))
+    return set_error(AMP_EINVAL, "graph replay needs device memory, constant k and nprobe, no stage timing "
+                                 "and a non-explicit policy");
+  if (use_graph && st == nullptr)
+    return set_error(AMP_EINVAL, "graph replay needs a created stream (the null stream cannot be captured)");
   hipEvent_t ev[AMP_N_STAGES + 1];
   const bool timed = opts->stage_ms != nullptr;
   if (timed)
@@ -554,16 +587,45 @@ amp_status amp_search(amp_index* ix, const float* queries, int64_t nq, const int
   float* od = host ? w.o_dist : out_dist;
   int64_t* oq = host ? (opts->out_qdist ? w.o_qdist : nullptr) : opts->out_qdist;
   float* oc = (!host && opts->out_coarse) ? opts->out_coarse : nullptr;
-  hipError_t he = launch_search(ix, wv, qdev, sd, ma, oi, od, oq, oc, st, timed ? ev : nullptr);
+  const hipMemcpyKind out_kind = host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+  auto enqueue = [&](hipEvent_t* evs) -> hipError_t {
+    hipError_t e = launch_search(ix, wv, qdev, sd, ma, oi, od, oq, oc, st, evs);
+    if (e != hipSuccess) return e;
+    if (opts->out_probes &&
+        (e = hipMemcpyAsync(opts->out_probes, w.probes, (size_t)nq * npmax * 4, out_kind, st)) != hipSuccess)
+      return e;
+    if (opts->out_bits && (e = hipMemcpyAsync(opts->out_bits, w.pbits, (size_t)nq * npmax, out_kind, st)) != hipSuccess)
+      return e;
+    return hipSuccess;
+  };
+  hipError_t he = hipSuccess;
+  if (use_graph) {
+    // one captured graph per index, replayed while the launch key is unchanged
+    GraphKey key{qdev, out_ids, out_dist, opts->out_qdist, opts->out_probes, opts->out_bits, opts->out_coarse,
+                 st, nq, k[0], nprobe[0], pol->kind, pol->fixed_bits, sd.allowed_mask, pol->margin_q40,
+                 pol->lut_dtype, ix->ws_generation, ix->model_generation};
+    if (!ix->graph_exec || !(ix->graph_key == key)) {
+      if (ix->graph_exec) hipGraphExecDestroy(ix->graph_exec);
+      ix->graph_exec = nullptr;
+      hipGraph_t g = nullptr;
+      AMP_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+      he = enqueue(nullptr);
+      hipError_t ec = hipStreamEndCapture(st, &g);
+      if (he == hipSuccess) he = ec;
+      if (he == hipSuccess) he = hipGraphInstantiate(&ix->graph_exec, g, nullptr, nullptr, 0);
+      if (g) hipGraphDestroy(g);
+      if (he == hipSuccess) ix->graph_key = key;
+      else ix->graph_exec = nullptr;
+    }
+    if (he == hipSuccess) he = hipGraphLaunch(ix->graph_exec, st);
+  } else {
+    he = enqueue(timed ? ev : nullptr);
+  }
   if (he != hipSuccess) {
     if (timed)
       for (auto& e : ev) hipEventDestroy(e);
     return set_error(AMP_EDEVICE, "kernel launch failed: %s", hipGetErrorString(he));
   }
-  const hipMemcpyKind out_kind = host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
-  if (opts->out_probes)
-    AMP_HIP(hipMemcpyAsync(opts->out_probes, w.probes, (size_t)nq * npmax * 4, out_kind, st));
-  if (opts->out_bits) AMP_HIP(hipMemcpyAsync(opts->out_bits, w.pbits, (size_t)nq * npmax, out_kind, st));
   if (host && opts->out_coarse)
     AMP_HIP(hipMemcpyAsync(opts->out_coarse, w.coarse, (size_t)nq * ix->nlist * 4, hipMemcpyDeviceToHost, st));
   int32_t flags[4] = {0, 0, 0, 0};
@@ -573,8 +635,9 @@ amp_status amp_search(amp_index* ix, const float* queries, int64_t nq, const int
     if (opts->out_qdist)
       AMP_HIP(hipMemcpyAsync(opts->out_qdist, w.o_qdist, (size_t)nq * kmax * 8, hipMemcpyDeviceToHost, st));
     AMP_HIP(hipMemcpyAsync(flags, w.flags, sizeof flags, hipMemcpyDeviceToHost, st));
-    AMP_HIP(hipStreamSynchronize(st));
   }
+  AMP_HIP(hipEventRecord(ix->dev.ev_done, st));
+  if (host) AMP_HIP(hipStreamSynchronize(st));
   if (timed) {
     // stages: 0 CL, 1 top-nprobe, 2 predictor, 3 queue, 4 scan phase 1,
     // 5 scan phase 2, 6 merge; slot 7 holds the sum
@@ -599,6 +662,7 @@ amp_status amp_search(amp_index* ix, const float* queries, int64_t nq, const int
     for (uint32_t c : cc) sum += c, mx = std::max(mx, c);
     fprintf(stderr, "[amp] candidates per query: mean %.1f max %u (capacity %zu)\n", sum / nq, mx, capq);
   }
+  if (flags[0] & 8) return set_error(AMP_EDEVICE, "internal error: a work unit exceeded the scan tile");
   if (flags[0] & 4) return set_error(AMP_EOVERFLOW, "work-unit table overflowed");
   if (flags[0]) return set_error(AMP_EOVERFLOW, "candidate buffer of %zu entries overflowed", capq);
   return AMP_OK;

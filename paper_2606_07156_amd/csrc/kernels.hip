@@ -13,6 +13,7 @@
 #include "amp_internal.h"
 
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 namespace amp {
@@ -21,6 +22,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 // ------------------------------------------------------------------ helpers
 // order-preserving keys: integers (sign flip) and floats (IEEE total order)
@@ -297,18 +299,22 @@ __global__ void k_pairs(PairArgs a, ModelArgs ma) {
 }
 
 // ------------------------------------------------------------------ queue
-// Buckets are class-major: b = cls * nlist + list.  Phase 1 holds the
-// rank-0 pair of every query, phase 2 every active pair.  One atomic per
-// pair gives its rank inside the bucket; the scatter and the work-unit
-// table are then written without atomics.
+// Buckets are class-major.  Phase 1 holds the rank-0 pair of every query,
+// phase 2 every active pair.  One atomic per pair on its (class, list)
+// counter gives its rank inside the bucket; the scatter and the work-unit
+// table are then written without atomics.  Counters are indexed by list id
+// (the most-probed lists stay spread over memory channels), offsets and
+// units by the list's position in the launch order lorder (largest first).
 struct QueueArgs {
   const int32_t* probes;
   const uint8_t* pbits;
   const int64_t* offsets;
-  int32_t* cnt;       // [2][NB]
+  const int32_t* lorder;  // bucket position -> list (largest list first)
+  const int32_t* lpos;    // list -> bucket position
+  int32_t* cnt;       // [2][NB] by (class, list id)
   int32_t* rank;      // [2][nq*npmax]
-  int64_t* pairoff;   // [2][NB+1]
-  int64_t* unitoff;   // [2][NB+1]
+  int64_t* pairoff;   // [2][NB+1] by (class, launch position)
+  int64_t* unitoff;   // [2][NB+1] by (class, launch position)
   int32_t* sorted;    // [2][nq*npmax]
   int4* units;        // [2][max_units]: {list, first pair, pair count, chunk}
   int32_t* flags;
@@ -350,12 +356,13 @@ __global__ __launch_bounds__(1024) void k_qscan(QueueArgs a, int fp32) {
     const int b0 = threadIdx.x * per;
     int64_t sp = 0, su = 0;
     for (int b = b0; b < b0 + per && b < NB; ++b) {
-      const int cls = b / a.nlist, p = b % a.nlist;
+      const int cls = b / a.nlist, p = a.lorder[b % a.nlist];
       const int64_t n = a.offsets[p + 1] - a.offsets[p];
       const int64_t nch = (n + a.chunk - 1) / a.chunk;
       const int G = class_pairs(cls, a.wpr, fp32);
-      sp += cnt[b];
-      su += ((cnt[b] + G - 1) / G) * nch;
+      const int c = cnt[cls * a.nlist + p];
+      sp += c;
+      su += ((c + G - 1) / G) * nch;
     }
     s_part[0][threadIdx.x] = sp;
     s_part[1][threadIdx.x] = su;
@@ -376,14 +383,15 @@ __global__ __launch_bounds__(1024) void k_qscan(QueueArgs a, int fp32) {
       uo[NB] = s_part[1][1023];
     }
     for (int b = b0; b < b0 + per && b < NB; ++b) {
-      const int cls = b / a.nlist, p = b % a.nlist;
+      const int cls = b / a.nlist, p = a.lorder[b % a.nlist];
       const int64_t n = a.offsets[p + 1] - a.offsets[p];
       const int64_t nch = (n + a.chunk - 1) / a.chunk;
       const int G = class_pairs(cls, a.wpr, fp32);
+      const int c = cnt[cls * a.nlist + p];
       po[b] = sp;
       uo[b] = su;
-      sp += cnt[b];
-      su += ((cnt[b] + G - 1) / G) * nch;
+      sp += c;
+      su += ((c + G - 1) / G) * nch;
     }
     __syncthreads();
   }
@@ -396,7 +404,7 @@ __global__ void k_qscatter(QueueArgs a) {
   const int p = a.probes[i];
   if (p < 0) return;
   const int cls = pair_class(a.pbits[i], a.M);
-  const int b = cls * a.nlist + p;
+  const int b = cls * a.nlist + a.lpos[p];
   const int NB = a.ncls * a.nlist;
   a.sorted[n + a.pairoff[(NB + 1) + b] + a.rank[n + i]] = (int32_t)i;
   if (i % a.npmax == 0) a.sorted[a.pairoff[b] + a.rank[i]] = (int32_t)i;
@@ -422,7 +430,7 @@ __global__ void k_qunits(QueueArgs a, int fp32) {
         const int mid = (lo + hi) >> 1;
         if (uo[mid] <= u) lo = mid; else hi = mid;
       }
-      const int b = lo, cls = b / a.nlist, p = b % a.nlist;
+      const int b = lo, cls = b / a.nlist, p = a.lorder[b % a.nlist];
       const int64_t n = a.offsets[p + 1] - a.offsets[p];
       const int64_t nch = (n + a.chunk - 1) / a.chunk;
       const int G = class_pairs(cls, a.wpr, fp32);
@@ -438,7 +446,8 @@ struct ScanArgs {
   const float* Q;
   const float* C;
   const float* codebook;   // FP32 policy
-  const u32x4* bsw;        // integer policy MFMA B fragments
+  const u32x4* bsw;        // integer policy MFMA B fragments (BF16, with aug slots)
+  const u32x4* bsw16;      // FP16 dims fragments
   const uint8_t* codes;
   const int64_t* ids;
   const int64_t* offsets;
@@ -461,6 +470,11 @@ struct ScanArgs {
 // words per LUT row for a subspace count: the LUT of one work unit takes
 // M * 256 * WPR * 4 bytes of LDS
 __host__ __device__ constexpr int wpr_for(int M) { return M <= 16 ? 4 : (M <= 32 ? 2 : 1); }
+// words per LUT row of a scan kernel variant: the variants specialised for a
+// subspace count MT pack wpr_for(MT) words, the generic one (MT = 0) one word.
+// The work-unit queue packs pairs into units with the same figure, so both
+// sides take it from here.
+__host__ __device__ constexpr int kernel_wpr(int MT) { return MT ? wpr_for(MT) : 1; }
 
 // LDS carve-up of one scan workgroup (all offsets in bytes, 16-aligned)
 struct ScanLds {
@@ -506,17 +520,30 @@ __device__ __forceinline__ void lut_row_load(const uint32_t* lut, int row, uint3
   }
 }
 
-// One m-pair of the integer LUT of a work unit on BF16 MFMA 16x16x32.  Rows
-// of the A operand are (subspace slot ms, pair g) = ms*8 + g; K holds
-// [dims m0 | aug m0 | dims m1 | aug m1], 8 slots each.  The aug slots carry
-// |cbi|^2 (digits in B, powers of two in A) and |ri|^2 + off (digits in A,
-// powers of two in B), all scaled by 2^-s in A, so the product is exactly
-// 2^-s (T + off): every partial sum is an integer multiple of 2^-s below
-// 2^(24-s).  pass 1: off = 0, s = 0, record min/max over the codewords;
+// LC matrix dtypes of the integer LUT build.  (An FP8 e4m3 variant is not
+// offered: the 16x16x32 FP8 MFMA of gfx950 does not return the exact sum of
+// e4m3-grid products of the magnitudes the grid allows.)
+enum { DT_BF16 = 1, DT_F16 = 2 };
+
+__device__ __forceinline__ uint32_t f16_bits(float v) {  // exact inputs only
+  return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)v);
+}
+// One m-pair of the integer LUT of a work unit.  Rows of the A operand are
+// (subspace slot ms, pair g) = ms*8 + g; K holds [dims m0 | aug m0 | dims m1 |
+// aug m1], 8 slots each.  The aug slots carry |cbi|^2 (digits in B, powers
+// of two in A) and |ri|^2 + off (digits in A, powers of two in B).
+//  * DT_BF16: one BF16 MFMA 16x16x32 with everything scaled by 2^-s in A
+//    gives exactly 2^-s (T + off) (every partial sum is an integer multiple of
+//    2^-s below 2^(24-s));
+//  * DT_F16: the aug terms on BF16 MFMA, then the dot products (-2 ri, or
+//    -ri for inner product) on an FP16 MFMA accumulating into the same FP32
+//    registers: T + off exactly, scaled by 2^-s afterwards.
+// Inner product: dims coefficient -1 and no |ri|^2, |cbi|^2 terms.
+// pass 1: off = 0, s = 0, record min/max over the codewords;
 // pass 2: quantise (truncation of the exact non-negative value) and pack.
-template <int LWB, int WPR>
+template <int LWB, int WPR, int DT>
 __device__ __forceinline__ void lut_mpair(const ScanArgs& a, char* lds, const ScanLds& L, int M, int np_u,
-                                          int pass, int mp, const u32x4 (&B)[16]) {
+                                          int pass, int mp, const u32x4 (&B)[16], const u32x4 (&Bd)[16]) {
   constexpr int W = Lane<LWB>::W;
   constexpr int G = WPR * W;
   constexpr int NGT = (G + 7) / 8;
@@ -530,42 +557,65 @@ __device__ __forceinline__ void lut_mpair(const ScanArgs& a, char* lds, const Sc
   const int row = lane & 15, kg = lane >> 4;
   const int ms_row = row >> 3;
   const int dsub = a.dsub;
+  const bool ip = a.metric == AMP_IP;
   bf16x8 A[NGT];
+  u32x4 Ad[NGT];
 #pragma unroll
   for (int gt = 0; gt < NGT; ++gt) {
     const int g = gt * 8 + (row & 7);
     const int m = 2 * mp + ms_row;
-    uint32_t pk[4] = {0, 0, 0, 0};
+    uint32_t pk[4] = {0, 0, 0, 0}, pd[4] = {0, 0, 0, 0};
     if (g < np_u && (kg >> 1) == ms_row) {
       const int s = pass == 1 ? 0 : ps[g];
-      const float sc = ldexpf(1.f, -s);
-      float v[8];
+      const float sc = DT == DT_BF16 ? ldexpf(1.f, -s) : 1.f;
       if ((kg & 1) == 0) {
+        const int coef = ip ? -1 : -2;
+        if constexpr (DT == DT_BF16) {
+          float v[8];
 #pragma unroll
-        for (int t = 0; t < 8; ++t)
-          v[t] = t < dsub ? (float)(-2 * (int)ri[g * a.d + m * dsub + t]) * sc : 0.f;
+          for (int t = 0; t < 8; ++t) v[t] = t < dsub ? (float)(coef * (int)ri[g * a.d + m * dsub + t]) * sc : 0.f;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) pk[t] = bf16_bits(v[2 * t]) | (bf16_bits(v[2 * t + 1]) << 16);
+        } else {
+          float v[8];
+#pragma unroll
+          for (int t = 0; t < 8; ++t) v[t] = t < dsub ? (float)(coef * (int)ri[g * a.d + m * dsub + t]) : 0.f;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) pd[t] = f16_bits(v[2 * t]) | (f16_bits(v[2 * t + 1]) << 16);
+        }
       } else {
-        int32_t X = rr[g * M + m];
+        int32_t X = ip ? 0 : rr[g * M + m];
         if (pass == 2) X += lo[g * M + m];  // lo holds off = hf(s) - min after pass 1
         const float sg = X < 0 ? -1.f : 1.f;
         const uint32_t ax = (uint32_t)(X < 0 ? -X : X);
-        v[0] = 65536.f * sc;
-        v[1] = 256.f * sc;
-        v[2] = sc;
+        const float cm = ip ? 0.f : sc;
+        float v[8];
+        v[0] = 65536.f * cm;
+        v[1] = 256.f * cm;
+        v[2] = cm;
         v[3] = sg * (float)(ax >> 16) * sc;
         v[4] = sg * (float)((ax >> 8) & 255u) * sc;
         v[5] = sg * (float)(ax & 255u) * sc;
         v[6] = 0.f;
         v[7] = 0.f;
-      }
 #pragma unroll
-      for (int t = 0; t < 4; ++t) pk[t] = bf16_bits(v[2 * t]) | (bf16_bits(v[2 * t + 1]) << 16);
+        for (int t = 0; t < 4; ++t) pk[t] = bf16_bits(v[2 * t]) | (bf16_bits(v[2 * t + 1]) << 16);
+      }
     }
     u32x4 u = {pk[0], pk[1], pk[2], pk[3]};
     A[gt] = __builtin_bit_cast(bf16x8, u);
+    Ad[gt] = (u32x4){pd[0], pd[1], pd[2], pd[3]};
   }
   // D rows of this lane: (ms = kg>>1, g = gt*8 + 4*(kg&1) + i), column j
   const int m_out = 2 * mp + (kg >> 1);
+  float rsc[NGT][4];  // 2^-s of each row (used after a non-BF16 build)
+#pragma unroll
+  for (int gt = 0; gt < NGT; ++gt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int g = gt * 8 + 4 * (kg & 1) + i;
+      rsc[gt][i] = (DT == DT_BF16 || pass == 1 || g >= np_u) ? 1.f : ldexpf(1.f, -ps[g]);
+    }
   float mn[NGT][4], mx[NGT][4];
 #pragma unroll
   for (int gt = 0; gt < NGT; ++gt)
@@ -578,6 +628,10 @@ __device__ __forceinline__ void lut_mpair(const ScanArgs& a, char* lds, const Sc
 #pragma unroll
     for (int gt = 0; gt < NGT; ++gt) {
       f4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[gt], Bf, (f4){0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+      if constexpr (DT == DT_F16) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, Ad[gt]),
+                                                     __builtin_bit_cast(f16x8, Bd[jt]), acc, 0, 0, 0);
+      }
       const int g0 = gt * 8 + 4 * (kg & 1);
       if (pass == 1) {
 #pragma unroll
@@ -588,7 +642,10 @@ __device__ __forceinline__ void lut_mpair(const ScanArgs& a, char* lds, const Sc
       } else if (g0 < G) {
         uint32_t qv[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) qv[i] = (uint32_t)acc[i];  // exact and >= 0: truncation = floor
+        for (int i = 0; i < 4; ++i) {
+          const float vv = DT == DT_BF16 ? acc[i] : acc[i] * rsc[gt][i];  // power-of-two scale: exact
+          qv[i] = (uint32_t)vv;  // exact and >= 0: truncation = floor
+        }
         uint32_t* dst = lut + (size_t)(m_out * kKsub + j) * WPR;
         if constexpr (LWB == 8) {
           dst[g0 >> 2] = qv[0] | (qv[1] << 8) | (qv[2] << 16) | (qv[3] << 24);
@@ -631,10 +688,10 @@ struct Owned {
   float c[NM][kMaxDsub];
 };
 
-template <int LWB, int MT, int PHASE>
+template <int LWB, int MT, int PHASE, int DT>
 __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
-  constexpr int WPR = wpr_for(MT ? MT : 64);
+  constexpr int WPR = kernel_wpr(MT);
   constexpr bool FP = LWB == 0;
   constexpr int W = Lane<LWB>::W;
   constexpr int G = WPR * W;
@@ -673,7 +730,12 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
     int next_u = 0;
     int4 next_unit = make_int4(0, 0, 0, 0);
     if (tid == 0) next_u = (int)atomicAdd(a.counter, 1u);
-    const int p = s_unit.x, np_u = s_unit.z;
+    const int p = s_unit.x;
+    int np_u = s_unit.z;
+    if (np_u > G) {  // a unit never holds more pairs than the tile (guarded, flagged)
+      if (tid == 0) atomicOr(&a.flags[0], 8);
+      np_u = G;
+    }
     const int64_t L0 = a.offsets[p];
     const int64_t n_list = a.offsets[p + 1] - L0;
     const int64_t v0 = (int64_t)s_unit.w * a.chunk;
@@ -690,9 +752,12 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
     }
     __syncthreads();
     // ---- RC: residuals (FP32, then onto the grid for integer policies)
+    // (inner product: the query itself, on the grid for integer policies)
+    const bool ip = a.metric == AMP_IP;
     for (int e = tid; e < np_u * a.d; e += kThreads) {
       const int g = e / a.d, t = e % a.d;
-      const float r = a.Q[(size_t)pq[g] * a.d + t] - a.C[(size_t)p * a.d + t];
+      const float qv = a.Q[(size_t)pq[g] * a.d + t];
+      const float r = ip ? qv : qv - a.C[(size_t)p * a.d + t];
       if constexpr (FP)
         reinterpret_cast<float*>(lds + L.ri)[e] = r;
       else
@@ -708,12 +773,23 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
         const int g = e / M, m = e % M;
         const float* r = r32 + g * a.d + m * a.dsub;
         float sq = 0.f;
+        if (ip) {  // partial -q.c of this subspace
+          const float* c = a.C + (size_t)p * a.d + m * a.dsub;
 #pragma unroll
-        for (int t = 0; t < kMaxDsub; ++t)
-          if (t < a.dsub) sq = fmaf(r[t], r[t], sq);
+          for (int t = 0; t < kMaxDsub; ++t)
+            if (t < a.dsub) sq = fmaf(-r[t], c[t], sq);
+        } else {
+#pragma unroll
+          for (int t = 0; t < kMaxDsub; ++t)
+            if (t < a.dsub) sq = fmaf(r[t], r[t], sq);
+        }
         rr32[e] = sq;
       }
       __syncthreads();
+      if (tid < G) {
+        ps[tid] = 0;
+        pbase[tid] = 0;
+      }
       float* lut = reinterpret_cast<float*>(lds + L.lut);
       auto entry = [&](int m, const float (&c)[kMaxDsub]) {
         const int e = m * kKsub + tid;
@@ -730,7 +806,16 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
 #pragma unroll
             for (int t = 0; t < kMaxDsub; ++t)
               if (t < a.dsub) dot = fmaf(r[t], c[t], dot);
-            sv = fmaf(-2.f, dot, rr32[g * M + m] + cc);
+            if (ip) {
+              // inner product: the pair's base -q.c (sum of the subspace
+              // partials) is folded into subspace 0's entries
+              float bf = 0.f;
+              if (m == 0)
+                for (int mm = 0; mm < M; ++mm) bf += rr32[g * M + mm];
+              sv = bf - dot;
+            } else {
+              sv = fmaf(-2.f, dot, rr32[g * M + m] + cc);
+            }
           }
           out[g] = sv;
         }
@@ -750,30 +835,32 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
           entry(m, c);
         }
       }
-      if (tid < G) {
-        ps[tid] = 0;
-        pbase[tid] = 0;
-      }
     } else {
       int32_t* rr = reinterpret_cast<int32_t*>(lds + L.rr);
       const int16_t* ri = reinterpret_cast<const int16_t*>(lds + L.ri);
       for (int e = tid; e < np_u * M; e += kThreads) {
         const int g = e / M, m = e % M;
-        int32_t s = 0;
+        int32_t sacc = 0;
         for (int t = 0; t < a.dsub; ++t) {
           const int v = ri[g * a.d + m * a.dsub + t];
-          s += v * v;
+          // L2: |ri|^2 of the subspace; IP: qi.ci of the subspace (base term)
+          sacc += ip ? v * grid_val(a.C[(size_t)p * a.d + m * a.dsub + t], a.grid_e, a.grid_kind) : v * v;
         }
-        rr[e] = s;
+        rr[e] = sacc;
       }
       __syncthreads();
       for (int pass = 1; pass <= 2; ++pass) {
         // the 16 B fragments of an m-pair are issued together, then consumed
         for (int mp = wave; mp < M / 2; mp += kThreads / 64) {
-          u32x4 Bt[16];
+          u32x4 Bt[16], Bd[16];
 #pragma unroll
-          for (int jt = 0; jt < 16; ++jt) Bt[jt] = a.bsw[((size_t)mp * 16 + jt) * 64 + lane];
-          lut_mpair<LWB, WPR>(a, lds, L, M, np_u, pass, mp, Bt);
+          for (int jt = 0; jt < 16; ++jt) {
+            const size_t fi = ((size_t)mp * 16 + jt) * 64 + lane;
+            Bt[jt] = a.bsw[fi];
+            if constexpr (DT == DT_F16) Bd[jt] = a.bsw16[fi];
+            else Bd[jt] = (u32x4){0u, 0u, 0u, 0u};
+          }
+          lut_mpair<LWB, WPR, DT>(a, lds, L, M, np_u, pass, mp, Bt, Bd);
         }
         __syncthreads();
         if (pass == 1) {
@@ -786,6 +873,10 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
               const int64_t span = (int64_t)hi[g * M + m] - lo[g * M + m];
               R = span > R ? span : R;
               base += lo[g * M + m];
+            }
+            if (ip) {
+              const int32_t* rrp = reinterpret_cast<const int32_t*>(lds + L.rr);
+              for (int m = 0; m < M; ++m) base -= rrp[g * M + m];  // -qi.ci
             }
             const int64_t top = (1ll << pb[g]) - 1;
             int s = 0;
@@ -1069,8 +1160,9 @@ __global__ __launch_bounds__(256) void k_merge(MergeArgs a) {
 // lane l (group kg = l/16, codeword j = 16 jt + l%16):
 //   kg even: cbi[m][j][0..dsub) zero-padded to 8;  kg odd: digits of
 //   cc = |cbi[m][j]|^2 (base 256, most significant first) then 65536, 256, 1
+// bsw: BF16 (all groups); bsw16: FP16 dims (odd groups zero).
 __global__ void k_prep_bsw(const float* __restrict__ cb, int M, int dsub, int grid_e, int grid_kind,
-                           u32x4* __restrict__ bsw) {
+                           u32x4* __restrict__ bsw, u32x4* __restrict__ bsw16) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   const int total = (M / 2) * 16 * 64;
   if (idx >= total) return;
@@ -1085,8 +1177,10 @@ __global__ void k_prep_bsw(const float* __restrict__ cb, int M, int dsub, int gr
     ci[t] = t < dsub ? grid_val(c[t], grid_e, grid_kind) : 0;
     cc += ci[t] * ci[t];
   }
+  uint32_t h[4] = {0, 0, 0, 0};
   if ((kg & 1) == 0) {
     for (int t = 0; t < 8; ++t) v[t] = (float)ci[t];
+    for (int t = 0; t < 4; ++t) h[t] = f16_bits(v[2 * t]) | (f16_bits(v[2 * t + 1]) << 16);
   } else {
     v[0] = (float)(cc >> 16);
     v[1] = (float)((cc >> 8) & 255);
@@ -1100,6 +1194,7 @@ __global__ void k_prep_bsw(const float* __restrict__ cb, int M, int dsub, int gr
   u32x4 o;
   for (int t = 0; t < 4; ++t) o[t] = bf16_bits(v[2 * t]) | (bf16_bits(v[2 * t + 1]) << 16);
   bsw[idx] = o;
+  bsw16[idx] = (u32x4){h[0], h[1], h[2], h[3]};
 }
 
 // ------------------------------------------------------------------ host launchers
@@ -1112,34 +1207,51 @@ hipError_t launch_prep_index(const amp_index* ix, hipStream_t st) {
                      ix->d, dv.cnorm);
   const int total = (ix->M / 2) * 16 * 64;
   hipLaunchKernelGGL(k_prep_bsw, dim3((total + 255) / 256), dim3(256), 0, st, dv.codebook, ix->M, ix->dsub,
-                     ix->grid_e, ix->grid_kind, reinterpret_cast<u32x4*>(dv.bsw));
+                     ix->grid_e, ix->grid_kind, reinterpret_cast<u32x4*>(dv.bsw),
+                     reinterpret_cast<u32x4*>(dv.bsw16));
   return hipGetLastError();
 }
 
-size_t scan_lds_bytes(int lw_bits, int phase, int M, int d) {
+// LC matrix dtype of an AMP_LUT_* value (0 selects BF16; the FP8 value is
+// rejected before a search launches)
+static int dt_of(int lut_dtype) {
+  return lut_dtype == AMP_LUT_F16 ? DT_F16 : DT_BF16;
+}
+
+// subspace count of the scan variant that runs a lane class (0: generic):
+// registers-resident variants exist for M = 8, 16, 24 with the BF16 LUT build
+// (the FP32 LUT has no LC dtype)
+static int scan_mt(int lwb, int M, int dt) {
+  if (lwb != 0 && dt != DT_BF16) return 0;
+  return (M == 8 || M == 16 || M == 24) ? M : 0;
+}
+
+static size_t scan_lds_bytes(int lw_bits, int phase, int M, int d, int wpr) {
   const bool fp = lw_bits == 0;
-  const int wpr = wpr_for(M);
   const int G = fp ? wpr : wpr * (32 / lw_bits);
   return (size_t)scan_lds_layout(G, wpr, M, d, fp, phase).total;
 }
-int scan_wpr(int M) { return wpr_for(M); }
+
+int scan_wpr(int M, bool fp32, int lut_dtype) { return kernel_wpr(scan_mt(fp32 ? 0 : 8, M, dt_of(lut_dtype))); }
 
 typedef void (*ScanFn)(ScanArgs);
-template <int LWB, int MT, int PH>
-static ScanFn scan_fn() { return k_scan<LWB, MT, PH>; }
+template <int LWB, int MT, int PH, int DT>
+static ScanFn scan_fn() { return k_scan<LWB, MT, PH, DT>; }
 
 // kernels specialised for the subspace counts 8, 16 and 24 (codes and, for
-// M <= 16, the MFMA B fragments kept in registers); any other M runs the
-// generic variant
-static ScanFn pick_scan(int lwb, int M, int ph) {
+// the FP32 LUT, codewords kept in registers) with the BF16 LUT build; any
+// other M, and the FP16 / FP8 LUT builds, run the generic variant
+static ScanFn pick_scan(int lwb, int M, int ph, int dt) {
+  const int mt = scan_mt(lwb, M, dt);
 #define AMP_PICK_M(L, MT) \
-  if (M == MT || MT == 0) return ph == 1 ? scan_fn<L, MT, 1>() : scan_fn<L, MT, 2>();
-#define AMP_PICK(L)     \
-  if (lwb == L) {       \
-    AMP_PICK_M(L, 8)    \
-    AMP_PICK_M(L, 16)   \
-    AMP_PICK_M(L, 24)   \
-    AMP_PICK_M(L, 0)    \
+  if (mt == MT) return ph == 1 ? scan_fn<L, MT, 1, DT_BF16>() : scan_fn<L, MT, 2, DT_BF16>();
+#define AMP_PICK(L)                                                                        \
+  if (lwb == L) {                                                                          \
+    if (L != 0 && dt == DT_F16) return ph == 1 ? scan_fn<L, 0, 1, DT_F16>() : scan_fn<L, 0, 2, DT_F16>(); \
+    AMP_PICK_M(L, 8)                                                                       \
+    AMP_PICK_M(L, 16)                                                                      \
+    AMP_PICK_M(L, 24)                                                                      \
+    AMP_PICK_M(L, 0)                                                                       \
   }
   AMP_PICK(0)
   AMP_PICK(8)
@@ -1152,9 +1264,11 @@ static ScanFn pick_scan(int lwb, int M, int ph) {
 
 static int g_num_cu = 0;
 
-static hipError_t launch_scan(int lwb, int ph, const ScanArgs& sa, hipStream_t st) {
-  ScanFn fn = pick_scan(lwb, sa.M, ph);
-  const size_t lds = scan_lds_bytes(lwb, ph, sa.M, sa.d);
+static hipError_t launch_scan(int lwb, int ph, int dt, int wpr, const ScanArgs& sa, hipStream_t st) {
+  ScanFn fn = pick_scan(lwb, sa.M, ph, dt);
+  // the queue packed units for `wpr` words per row: the variant must agree
+  if (!fn || kernel_wpr(scan_mt(lwb, sa.M, dt)) != wpr) return hipErrorInvalidValue;
+  const size_t lds = scan_lds_bytes(lwb, ph, sa.M, sa.d, wpr);
   hipError_t e = hipFuncSetAttribute(kaddr(fn), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   int per_cu = 0;
@@ -1226,6 +1340,8 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   qa.probes = ws.probes;
   qa.pbits = ws.pbits;
   qa.offsets = dv.offsets;
+  qa.lorder = dv.lorder;
+  qa.lpos = dv.lpos;
   qa.cnt = ws.cnt;
   qa.rank = ws.rank;
   qa.pairoff = ws.pairoff;
@@ -1253,6 +1369,7 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   sa.C = dv.centroids;
   sa.codebook = dv.codebook;
   sa.bsw = reinterpret_cast<const u32x4*>(dv.bsw);
+  sa.bsw16 = reinterpret_cast<const u32x4*>(dv.bsw16);
   sa.codes = dv.codes;
   sa.ids = dv.ids;
   sa.offsets = dv.offsets;
@@ -1277,6 +1394,11 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   sa.chunk = sd.chunk;
   sa.capq = sd.capq;
   hipError_t err = hipSuccess;
+  // the lane classes run one after another on the caller's stream, each a
+  // persistent kernel over its own unit range.  (Running them concurrently
+  // on separate streams was measured slower on the mid-size workload: scan
+  // phase 2 took 1.86 ms against 1.50 ms serially.)
+  const int dt = dt_of(sd.lut_dtype);
   for (int ph = 1; ph <= 2; ++ph) {
     sa.sorted = ws.sorted + (ph == 2 ? npairs : 0);
     sa.unitoff = ws.unitoff + (ph == 2 ? (NB + 1) : 0);
@@ -1284,8 +1406,7 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
     for (int c = 0; c < ncls; ++c) {
       sa.cls = c;
       sa.counter = ws.counters + (ph - 1) * (kNCls + 1) + c;
-      err = launch_scan(fp32 ? 0 : lane_bits(c), ph, sa, st);
-      if (err != hipSuccess) return err;
+      if ((err = launch_scan(fp32 ? 0 : lane_bits(c), ph, dt, sd.wpr, sa, st)) != hipSuccess) return err;
     }
     mark(4 + ph);
   }

@@ -119,6 +119,18 @@ void svr_smo(const std::vector<double>& K, const std::vector<double>& y, double 
 
 using namespace amp;
 
+extern "C" amp_status amp_svr_fit(const double* K, const double* y, int32_t l, double C, double eps, double tol,
+                                  int32_t max_iter, double* coef, double* bias, int32_t* iterations) {
+  if (!K || !y || !coef || !bias || l < 1 || !(C > 0) || !(eps >= 0) || !(tol > 0) || max_iter < 1)
+    return set_error(AMP_EINVAL, "bad SVR fit arguments");
+  std::vector<double> Kv(K, K + (size_t)l * l), yv(y, y + l), cv;
+  int it = 0;
+  svr_smo(Kv, yv, C, eps, tol, max_iter, cv, *bias, it);
+  std::copy(cv.begin(), cv.end(), coef);
+  if (iterations) *iterations = it;
+  return AMP_OK;
+}
+
 extern "C" amp_status amp_index_train_predictor(amp_index* ix, const float* tq, int64_t nq, int32_t k, int32_t nprobe,
                                                 const amp_train_params* prm, amp_train_report* rep) {
   if (!ix || !tq || !prm) return set_error(AMP_EINVAL, "null argument");

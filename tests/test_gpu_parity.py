@@ -244,3 +244,141 @@ def test_device_mode_matches_host_mode(tiny):
     torch.cuda.synchronize()
     assert np.array_equal(out["ids"].cpu().numpy(), host["ids"])
     assert np.array_equal(out["qdist"].cpu().numpy(), host["qdist"])
+
+
+def _small(kind, metric="l2", grid_kind="u9", n=12_000, d=64, n_comp=48, nlist=32, M=16, seed=77, nq=40):
+    from amp_data.synth import Workload
+    w = Workload("t", n, d, n_comp, nq, nlist, M, 8, 10, kind, seed, metric=metric, grid_kind=grid_kind)
+    base = make_base(w)
+    idx = build_index(base, nlist, M, iters=8, seed=seed, grid_kind=grid_kind, metric=metric)
+    return _ctx(idx, make_queries(w, nq), base)
+
+
+@pytest.fixture(scope="module")
+def ipctx():
+    # unit-normalised clusters, inner product (the serving workload's metric)
+    return _small("vmf", metric="ip", d=64, M=16)
+
+
+@pytest.mark.parametrize("policy,bits", [("fixed", 4), ("fixed", 8), ("fixed", 16), ("fp32", 0)])
+def test_inner_product_search(ipctx, policy, bits):
+    g = _gpu(ipctx, 10, 6, policy=policy, bits=bits)
+    check_coarse(g["coarse"], ipctx["idx"], ipctx["Q"])
+    certify_probes(g["probes"], ipctx["idx"], ipctx["Q"], 6)
+    ref = _oracle(ipctx, 10, 6, g, policy=policy, bits=bits)
+    if policy == "fp32":
+        compare_fp32(g, ref, 16)
+    else:
+        compare_integer(g, ref)
+
+
+@pytest.fixture(scope="module")
+def e4ctx():
+    # anisotropic clusters on the e4m3 operand grid, d/M = 8 (the high-dim shape)
+    return _small("aniso", grid_kind="e4m3", d=96, M=12, nlist=24)
+
+
+@pytest.mark.parametrize("dtype", [amp.AMP_LUT_BF16, amp.AMP_LUT_F16])
+@pytest.mark.parametrize("bits", [4, 8, 16])
+def test_lut_build_dtypes_are_bit_exact_on_the_e4m3_grid(e4ctx, dtype, bits):
+    g = _gpu(e4ctx, 20, 5, policy="fixed", bits=bits, lut_dtype=dtype)
+    certify_probes(g["probes"], e4ctx["idx"], e4ctx["Q"], 5)
+    ref = _oracle(e4ctx, 20, 5, g, policy="fixed", bits=bits)
+    compare_integer(g, ref)
+
+
+@pytest.mark.parametrize("M,d", [(4, 16), (32, 128), (40, 80)])
+def test_generic_subspace_counts(M, d):
+    """Subspace counts without a specialised scan variant (the generic kernel,
+    one LUT word per row), including d/M = 2 and 4."""
+    ctx = _small("aniso", d=d, M=M, nlist=16, n=6000, n_comp=24, nq=24, seed=31 + M)
+    for policy, bits in (("fixed", 4), ("fixed", 16), ("fp32", 0)):
+        g = _gpu(ctx, 10, 4, policy=policy, bits=bits)
+        certify_probes(g["probes"], ctx["idx"], ctx["Q"], 4)
+        ref = _oracle(ctx, 10, 4, g, policy=policy, bits=bits)
+        if policy == "fp32":
+            compare_fp32(g, ref, M)
+        else:
+            compare_integer(g, ref)
+
+
+@pytest.mark.parametrize("bits", [4, 12])
+def test_fp16_lut_build_on_the_9bit_grid(tiny, bits):
+    g = _gpu(tiny, 10, 8, policy="fixed", bits=bits, lut_dtype=amp.AMP_LUT_F16)
+    ref = _oracle(tiny, 10, 8, g, policy="fixed", bits=bits)
+    compare_integer(g, ref)
+
+
+def test_fp8_build_is_rejected(tiny, e4ctx):
+    for ctx in (tiny, e4ctx):
+        with pytest.raises(amp.AmpError) as e:
+            amp.amp_search(ctx["h"], ctx["Q"][:2], 5, 2, policy="fixed", bits=8, lut_dtype=amp.AMP_LUT_F8E4M3)
+        assert e.value.status == amp.AMP_EUNSUPPORTED
+    with pytest.raises(amp.AmpError) as e:
+        amp.amp_search(tiny["h"], tiny["Q"][:2], 5, 2, policy="fixed", bits=8, lut_dtype=7)
+    assert e.value.status == amp.AMP_EINVAL
+
+
+def test_graph_replay_matches_eager(tiny):
+    """A captured search replayed several times, with other eager work and
+    synchronisations between replays and new query contents before some of
+    them, gives the eager result every time."""
+    torch = pytest.importorskip("torch")
+    Q = tiny["Q"]
+    nq = len(Q)
+    s = torch.cuda.Stream()
+    qd = torch.from_numpy(Q).cuda()
+
+    def outs():
+        return dict(ids=torch.empty((nq, 10), dtype=torch.int64, device="cuda"),
+                    dist=torch.empty((nq, 10), dtype=torch.float32, device="cuda"),
+                    qdist=torch.empty((nq, 10), dtype=torch.int64, device="cuda"),
+                    bits=torch.empty((nq, 8), dtype=torch.uint8, device="cuda"))
+
+    Q2 = np.ascontiguousarray(Q[::-1])
+    want = {0: amp.amp_search(tiny["h"], Q, 10, 8, policy="fixed", bits=8),
+            1: amp.amp_search(tiny["h"], Q2, 10, 8, policy="fixed", bits=8)}
+    og = outs()
+    for rep in range(5):
+        src = rep % 2
+        with torch.cuda.stream(s):
+            qd.copy_(torch.from_numpy(Q if src == 0 else Q2).cuda())
+            for v in og.values():
+                v.fill_(-1)
+        amp.amp_search(tiny["h"], qd, 10, 8, policy="fixed", bits=8, out=og, stream=s, graph=True)
+        s.synchronize()
+        # unrelated eager work between replays
+        x = torch.randn(512, 512, device="cuda")
+        (x @ x).sum().item()
+        torch.cuda.synchronize()
+        assert np.array_equal(og["ids"].cpu().numpy(), want[src]["ids"]), rep
+        assert np.array_equal(og["qdist"].cpu().numpy(), want[src]["qdist"]), rep
+        assert np.array_equal(og["dist"].cpu().numpy().view(np.uint32), want[src]["dist"].view(np.uint32)), rep
+        assert np.all(og["bits"].cpu().numpy() == 8)
+    # an eager device-mode search on the same index afterwards is unaffected
+    oe = outs()
+    amp.amp_search(tiny["h"], qd, 10, 8, policy="fixed", bits=8, out=oe, stream=s)
+    s.synchronize()
+    assert np.array_equal(oe["ids"].cpu().numpy(), og["ids"].cpu().numpy())
+
+
+def test_graph_mode_rejections(tiny):
+    torch = pytest.importorskip("torch")
+    Q = tiny["Q"][:4]
+    qd = torch.from_numpy(Q).cuda()
+    o = dict(ids=torch.empty((4, 10), dtype=torch.int64, device="cuda"),
+             dist=torch.empty((4, 10), dtype=torch.float32, device="cuda"))
+    s = torch.cuda.Stream()
+    bad = [dict(stream=None),                                    # null stream
+           dict(stream=s, stage_ms=True),
+           dict(stream=s, policy="explicit", explicit_bits=np.full((4, 8), 8, np.uint8))]
+    for kw in bad:
+        args = dict(policy="fixed", bits=8)
+        args.update(kw)
+        with pytest.raises(amp.AmpError) as e:
+            amp.amp_search(tiny["h"], qd, 10, 8, out=o, graph=True, **args)
+        assert e.value.status == amp.AMP_EINVAL
+    with pytest.raises(amp.AmpError):
+        amp.amp_search(tiny["h"], qd, [10, 5, 10, 5], 8, out=o, stream=s, graph=True)
+    with pytest.raises(amp.AmpError):
+        amp.amp_search(tiny["h"], Q, 10, 8, graph=True)
