@@ -97,6 +97,8 @@ def main():
     ap.add_argument("--recall-queries", type=int, default=200,
                     help="queries checked against exact kNN (0: skip; profiling runs)")
     ap.add_argument("--cache-dir", default="/tmp/amp_bench_cache")
+    ap.add_argument("--graph", type=int, default=1,
+                    help="1: timed searches replay a captured HIP graph (0: plain launches)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -118,29 +120,12 @@ def main():
     import torch
 
     import paper_2606_07156_amd as amp
-    from amp_data import build_index
-    from amp_data.synth import WORKLOADS, make_base, make_queries
+    from amp_data.synth import make_queries
+    from amp_data.workloads import load_or_build
 
-    w = WORKLOADS[args.workload]
+    w, base, idx = load_or_build(args.workload, args.cache_dir, log=lambda m: log("[bench] " + m))
     if args.nq:
         w = w.scaled(nq=args.nq)
-    cache = os.path.join(args.cache_dir, f"amp_{w.name}_{w.n}_{w.nlist}_{w.M}_{w.seed}.npz")
-    t = time.perf_counter()
-    if os.path.exists(cache):
-        z = np.load(cache, allow_pickle=False)
-        base = z["base"]
-        idx = {k2: (z[k2] if z[k2].ndim else z[k2].item()) for k2 in z.files if k2 != "base"}
-        log(f"[bench] loaded cached base and index from {cache} in {time.perf_counter() - t:.1f}s")
-    else:
-        base = make_base(w)
-        log(f"[bench] generated base {base.shape} in {time.perf_counter() - t:.1f}s")
-        t = time.perf_counter()
-        idx = build_index(base, w.nlist, w.M, iters=20, seed=w.seed, integer_data=w.integer_data,
-                          grid_kind=w.grid_kind, metric=w.metric)
-        log(f"[bench] built IVF{w.nlist}/PQ{w.M} index in {time.perf_counter() - t:.1f}s")
-        if args.cache_dir:
-            os.makedirs(args.cache_dir, exist_ok=True)
-            np.savez(cache, base=base, **idx)
     log(f"[bench] list sizes min/mean/max {idx['list_sizes'].min()}/{idx['list_sizes'].mean():.0f}/"
         f"{idx['list_sizes'].max()}")
     Q = make_queries(w)
@@ -154,7 +139,9 @@ def main():
                qdist=torch.empty((nq, k), dtype=torch.int64, device=dev))
     out_probes = torch.empty((nq, nprobe), dtype=torch.int32, device=dev)
     out_bits = torch.empty((nq, nprobe), dtype=torch.uint8, device=dev)
-    stream = torch.cuda.current_stream()
+    # a created stream (default priority): graph capture needs one
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
 
     # exact ground truth for recall@10 on a sample of queries (FP64 brute force)
     import oracle
@@ -183,20 +170,24 @@ def main():
     # algorithmic bytes of the scan: one read of each probed list's codes per pair
     sizes = idx["list_sizes"].astype(np.int64)
     for name, kw in pols:
+        out["probes"], out["bits"] = (None, None) if nr else (out_probes, out_bits)
         for _ in range(args.warmup):
-            amp.amp_search(h, qd, k, nprobe, out=out, stream=stream, **kw)
+            amp.amp_search(h, qd, k, nprobe, out=out, stream=stream, graph=args.graph, **kw)
         torch.cuda.synchronize()
-        stages, lat = [], []
+        # timed region: K searches enqueued back to back on one stream
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        out["probes"], out["bits"] = (None, None) if nr else (out_probes, out_bits)
+        for _ in range(args.steps):
+            amp.amp_search(h, qd, k, nprobe, out=out, stream=stream, graph=args.graph, **kw)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        # stage breakdown and per-batch latency: separate, synchronised searches
+        stages, lat = [], []
         for _ in range(args.steps):
             o = amp.amp_search(h, qd, k, nprobe, out=out, stream=stream, stage_ms=True, **kw)
             stages.append(o["stage_ms"])
             lat.append(o["stage_ms"]["total"])
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / args.steps
         if nr:
             g = amp.amp_search(h, Q[:nr], k, nprobe, want_probes=True, want_bits=True, **kw)
             rec1 = oracle.recall_1_at(g["ids"], truth)
@@ -242,6 +233,7 @@ def main():
         "config": {"workload": f"{w.name}: {w.n}x{w.d} integer-valued Gaussian mixture ({w.n_comp} components), "
                                f"IVF{w.nlist}/PQ{w.M}x256, {nq} queries per step, nprobe {nprobe}, k {k}",
                    "policy": head,
+                   "launch": "HIP graph replay" if args.graph else "kernel launches",
                    "recall_at_10": round(r["recall1"], 4),
                    "recall_definition": "1-recall@10 (exact nearest neighbour within the 10 returned); "
                                         f"10-recall@10 {r['recall10']:.4f}; {nr} queries vs FP64 brute force",

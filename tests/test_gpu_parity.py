@@ -382,3 +382,87 @@ def test_graph_mode_rejections(tiny):
         amp.amp_search(tiny["h"], qd, [10, 5, 10, 5], 8, out=o, stream=s, graph=True)
     with pytest.raises(amp.AmpError):
         amp.amp_search(tiny["h"], Q, 10, 8, graph=True)
+
+
+# ---- the other workload shapes at sizes the oracle finishes in seconds
+def _shape(name, n, nq, nlist, nprobe, seed_off=0):
+    import dataclasses
+    w = dataclasses.replace(WORKLOADS[name], n=n, nq=nq, nlist=nlist, nprobe=nprobe)
+    base = make_base(w)
+    idx = build_index(base, w.nlist, w.M, iters=8, seed=w.seed + seed_off, integer_data=w.integer_data,
+                      grid_kind=w.grid_kind, metric=w.metric)
+    return _ctx(idx, make_queries(w, nq), base), w
+
+
+@pytest.fixture(scope="module")
+def skewed_shape():
+    # d 96, PQ24 (the M = 24 register variant), Zipf-skewed lists, uneven nprobe
+    return _shape("skewed", 60_000, 48, 256, 64)
+
+
+def test_skewed_shape_uneven_nprobe(skewed_shape):
+    ctx, w = skewed_shape
+    sizes = ctx["idx"]["list_sizes"]
+    assert sizes.max() >= 4 * np.median(sizes)  # Zipf-skewed list sizes
+    npq = np.random.default_rng(3).integers(8, 65, size=len(ctx["Q"])).astype(np.int32)
+    m = _spread_model(ctx, 64)
+    amp.amp_index_set_predictor(ctx["h"], m)
+    for policy, bits in (("fixed", 4), ("fixed", 16), ("adaptive", 0), ("fp32", 0)):
+        g = _gpu(ctx, 10, npq, policy=policy, bits=bits)
+        certify_probes(g["probes"], ctx["idx"], ctx["Q"], npq)
+        kw = dict(model=m) if policy == "adaptive" else {}
+        ref = _oracle(ctx, 10, npq, g, policy=policy, bits=bits, **kw)
+        if policy == "fp32":
+            compare_fp32(g, ref, w.M)
+        else:
+            compare_integer(g, ref)
+            if policy == "adaptive":
+                assert np.array_equal(g["bits"], ref["bits"])
+
+
+@pytest.fixture(scope="module")
+def highdim_shape():
+    # d 960, PQ120 (d/M = 8) on the e4m3 grid, k 100 (the workgroup-level bound)
+    return _shape("highdim", 16_000, 12, 32, 12)
+
+
+@pytest.mark.parametrize("dtype", [amp.AMP_LUT_BF16, amp.AMP_LUT_F16])
+def test_highdim_shape_k100(highdim_shape, dtype):
+    ctx, w = highdim_shape
+    m = _spread_model(ctx, 12)
+    amp.amp_index_set_predictor(ctx["h"], m)
+    for policy, bits in (("fixed", 4), ("fixed", 16), ("adaptive", 0), ("fp32", 0)):
+        if policy == "fp32" and dtype != amp.AMP_LUT_BF16:
+            continue
+        kw = dict(allowed=(4, 8, 16)) if policy == "adaptive" else {}
+        g = _gpu(ctx, 100, 12, policy=policy, bits=bits, lut_dtype=dtype, **kw)
+        certify_probes(g["probes"], ctx["idx"], ctx["Q"], 12)
+        if policy == "adaptive":
+            kw["model"] = m
+        ref = _oracle(ctx, 100, 12, g, policy=policy, bits=bits, **kw)
+        if policy == "fp32":
+            compare_fp32(g, ref, w.M)
+        else:
+            compare_integer(g, ref)
+            assert np.array_equal(g["bits"], ref["bits"])
+
+
+@pytest.fixture(scope="module")
+def serving_shape():
+    # d 768 unit-normalised, inner product, PQ96 (generic variant)
+    return _shape("serving", 20_000, 24, 32, 16)
+
+
+def test_serving_shape_inner_product_mixed_k(serving_shape):
+    ctx, w = serving_shape
+    r = np.random.default_rng(11)
+    kq = r.choice([10, 50, 100], size=len(ctx["Q"])).astype(np.int32)
+    npq = r.choice([4, 8, 16], size=len(ctx["Q"])).astype(np.int32)
+    for policy, bits in (("fixed", 4), ("fixed", 8), ("fixed", 16), ("fp32", 0)):
+        g = _gpu(ctx, kq, npq, policy=policy, bits=bits)
+        certify_probes(g["probes"], ctx["idx"], ctx["Q"], npq)
+        ref = _oracle(ctx, kq, npq, g, policy=policy, bits=bits)
+        if policy == "fp32":
+            compare_fp32(g, ref, w.M)
+        else:
+            compare_integer(g, ref)
