@@ -244,6 +244,8 @@ amp_status amp_index_info(const amp_index* index, int32_t* d, int32_t* M,
  * [nq][kmax] float (h^2 * integer estimate for integer policies, FP32 sum for
  * the FP32 policy).  Requires 1 <= k <= AMP_MAX_K, 1 <= nprobe <=
  * min(nlist, AMP_MAX_NPROBE); AMP_POLICY_ADAPTIVE requires a predictor.
+ * In device mode the query buffer must be 16-byte aligned (rows are read as
+ * float4; d is a multiple of 4), else AMP_EINVAL.
  */
 amp_status amp_search(amp_index* index, const float* queries, int64_t nq,
                       const int32_t* k, const int32_t* nprobe, int32_t per_query,

@@ -516,6 +516,8 @@ amp_status amp_search(amp_index* ix, const float* queries, int64_t nq, const int
   const int64_t chunk = (int64_t)env_size("AMP_CHUNK", 1 << 16);
   const int64_t max_nch = std::max<int64_t>(1, (ix->max_list + chunk - 1) / chunk);
   const int64_t max_units = (int64_t)nq * npmax * max_nch;
+  if (opts->mem != AMP_MEM_HOST && (reinterpret_cast<uintptr_t>(queries) & 15))
+    return set_error(AMP_EINVAL, "device query buffer must be 16-byte aligned");
   if ((s = ensure_workspace(ix, nq, npmax, kmax, capq, max_units)) != AMP_OK) return s;
   Workspace& w = ix->ws;
   hipStream_t st = reinterpret_cast<hipStream_t>(opts->stream);

@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <type_traits>
 
 namespace amp {
 
@@ -520,6 +521,18 @@ __device__ __forceinline__ void lut_row_load(const uint32_t* lut, int row, uint3
   }
 }
 
+// min / max over each 16-lane row of a wave: after row shifts by 1, 2, 4, 8
+// (lanes without a source keep their value) lane 15 of the row holds it
+template <bool MAX, int K>
+__device__ __forceinline__ int row16_step(int v) {
+  const int o = __builtin_amdgcn_update_dpp(v, v, 0x110 + K, 0xF, 0xF, false);  // row_shr:K
+  return MAX ? (o > v ? o : v) : (o < v ? o : v);
+}
+template <bool MAX>
+__device__ __forceinline__ int row16_reduce(int v) {
+  return row16_step<MAX, 8>(row16_step<MAX, 4>(row16_step<MAX, 2>(row16_step<MAX, 1>(v))));
+}
+
 // LC matrix dtypes of the integer LUT build.  (An FP8 e4m3 variant is not
 // offered: the 16x16x32 FP8 MFMA of gfx950 does not return the exact sum of
 // e4m3-grid products of the magnitudes the grid allows.)
@@ -539,11 +552,15 @@ __device__ __forceinline__ uint32_t f16_bits(float v) {  // exact inputs only
 //    -ri for inner product) on an FP16 MFMA accumulating into the same FP32
 //    registers: T + off exactly, scaled by 2^-s afterwards.
 // Inner product: dims coefficient -1 and no |ri|^2, |cbi|^2 terms.
-// pass 1: off = 0, s = 0, record min/max over the codewords;
-// pass 2: quantise (truncation of the exact non-negative value) and pack.
-template <int LWB, int WPR, int DT>
+// PASS 1: off = 0, s = 0, record min/max over the codewords (integer
+// compares of the exact values);
+// PASS 2: quantise (truncation of the exact non-negative value) and pack.
+// The pass is a template argument so that the 16 x NGT products of an m-pair
+// are independent straight-line code the compiler can overlap.
+template <int LWB, int WPR, int DT, int PASS>
 __device__ __forceinline__ void lut_mpair(const ScanArgs& a, char* lds, const ScanLds& L, int M, int np_u,
-                                          int pass, int mp, const u32x4 (&B)[16], const u32x4 (&Bd)[16]) {
+                                          int mp, const u32x4 (&B)[16], const u32x4 (&Bd)[16]) {
+  constexpr int pass = PASS;
   constexpr int W = Lane<LWB>::W;
   constexpr int G = WPR * W;
   constexpr int NGT = (G + 7) / 8;
@@ -616,11 +633,11 @@ __device__ __forceinline__ void lut_mpair(const ScanArgs& a, char* lds, const Sc
       const int g = gt * 8 + 4 * (kg & 1) + i;
       rsc[gt][i] = (DT == DT_BF16 || pass == 1 || g >= np_u) ? 1.f : ldexpf(1.f, -ps[g]);
     }
-  float mn[NGT][4], mx[NGT][4];
+  int mn[NGT][4], mx[NGT][4];
 #pragma unroll
   for (int gt = 0; gt < NGT; ++gt)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) { mn[gt][i] = 3.0e38f; mx[gt][i] = -3.0e38f; }
+    for (int i = 0; i < 4; ++i) { mn[gt][i] = 0x7FFFFFFF; mx[gt][i] = -0x7FFFFFFF - 1; }
 #pragma unroll
   for (int jt = 0; jt < 16; ++jt) {
     const bf16x8 Bf = __builtin_bit_cast(bf16x8, B[jt]);
@@ -633,11 +650,14 @@ __device__ __forceinline__ void lut_mpair(const ScanArgs& a, char* lds, const Sc
                                                      __builtin_bit_cast(f16x8, Bd[jt]), acc, 0, 0, 0);
       }
       const int g0 = gt * 8 + 4 * (kg & 1);
-      if (pass == 1) {
+      if constexpr (PASS == 1) {
+        // exact integers: for L2 (T >= 0) the float bit patterns order as
+        // integers; inner product values may be negative and are converted
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          mn[gt][i] = fminf(mn[gt][i], acc[i]);
-          mx[gt][i] = fmaxf(mx[gt][i], acc[i]);
+          const int t = ip ? (int)acc[i] : __float_as_int(acc[i]);
+          mn[gt][i] = t < mn[gt][i] ? t : mn[gt][i];
+          mx[gt][i] = t > mx[gt][i] ? t : mx[gt][i];
         }
       } else if (g0 < G) {
         uint32_t qv[4];
@@ -661,21 +681,20 @@ __device__ __forceinline__ void lut_mpair(const ScanArgs& a, char* lds, const Sc
       }
     }
   }
-  if (pass == 1) {
+  if constexpr (PASS == 1) {
 #pragma unroll
     for (int gt = 0; gt < NGT; ++gt)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        float a0 = mn[gt][i], b0 = mx[gt][i];
-#pragma unroll
-        for (int off = 1; off < 16; off <<= 1) {
-          a0 = fminf(a0, __shfl_xor(a0, off, 16));
-          b0 = fmaxf(b0, __shfl_xor(b0, off, 16));
+        int a0 = row16_reduce<false>(mn[gt][i]), b0 = row16_reduce<true>(mx[gt][i]);
+        if (!ip) {
+          a0 = (int)__int_as_float(a0);
+          b0 = (int)__int_as_float(b0);
         }
         const int g = gt * 8 + 4 * (kg & 1) + i;
-        if ((lane & 15) == 0 && g < np_u) {
-          lo[g * M + m_out] = (int32_t)a0;
-          hi[g * M + m_out] = (int32_t)b0;
+        if ((lane & 15) == 15 && g < np_u) {
+          lo[g * M + m_out] = a0;
+          hi[g * M + m_out] = b0;
         }
       }
   }
@@ -689,7 +708,7 @@ struct Owned {
 };
 
 template <int LWB, int MT, int PHASE, int DT>
-__global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
+__global__ __launch_bounds__(kThreads, LWB == 0 ? 1 : 2) void k_scan(ScanArgs a) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   constexpr int WPR = kernel_wpr(MT);
   constexpr bool FP = LWB == 0;
@@ -753,15 +772,40 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
     __syncthreads();
     // ---- RC: residuals (FP32, then onto the grid for integer policies)
     // (inner product: the query itself, on the grid for integer policies)
+    // four coordinates per thread and step (d is a multiple of 4, query rows
+    // and centroids 16-byte aligned); (pair, quad) advanced without division
     const bool ip = a.metric == AMP_IP;
-    for (int e = tid; e < np_u * a.d; e += kThreads) {
-      const int g = e / a.d, t = e % a.d;
-      const float qv = a.Q[(size_t)pq[g] * a.d + t];
-      const float r = ip ? qv : qv - a.C[(size_t)p * a.d + t];
-      if constexpr (FP)
-        reinterpret_cast<float*>(lds + L.ri)[e] = r;
-      else
-        reinterpret_cast<int16_t*>(lds + L.ri)[e] = (int16_t)grid_val(r, a.grid_e, a.grid_kind);
+    {
+      const int d4 = a.d >> 2;
+      const int gstep = kThreads / d4, tstep = kThreads - gstep * d4;
+      int g = tid / d4, t4 = tid - g * d4;
+      const float4* C4 = reinterpret_cast<const float4*>(a.C + (size_t)p * a.d);
+      while (g < np_u) {
+        const float4 qv = reinterpret_cast<const float4*>(a.Q + (size_t)pq[g] * a.d)[t4];
+        float4 r = qv;
+        if (!ip) {
+          const float4 cv = C4[t4];
+          r.x = qv.x - cv.x;
+          r.y = qv.y - cv.y;
+          r.z = qv.z - cv.z;
+          r.w = qv.w - cv.w;
+        }
+        if constexpr (FP) {
+          reinterpret_cast<float4*>(lds + L.ri)[g * d4 + t4] = r;
+        } else {
+          const uint32_t v0 = (uint32_t)grid_val(r.x, a.grid_e, a.grid_kind) & 0xFFFFu;
+          const uint32_t v1 = (uint32_t)grid_val(r.y, a.grid_e, a.grid_kind) & 0xFFFFu;
+          const uint32_t v2 = (uint32_t)grid_val(r.z, a.grid_e, a.grid_kind) & 0xFFFFu;
+          const uint32_t v3 = (uint32_t)grid_val(r.w, a.grid_e, a.grid_kind) & 0xFFFFu;
+          reinterpret_cast<u32x2*>(lds + L.ri)[g * d4 + t4] = (u32x2){v0 | (v1 << 16), v2 | (v3 << 16)};
+        }
+        g += gstep;
+        t4 += tstep;
+        if (t4 >= d4) {
+          t4 -= d4;
+          ++g;
+        }
+      }
     }
     __syncthreads();
     // ---- LC
@@ -849,8 +893,9 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
         rr[e] = sacc;
       }
       __syncthreads();
-      for (int pass = 1; pass <= 2; ++pass) {
-        // the 16 B fragments of an m-pair are issued together, then consumed
+      // the 16 B fragments of an m-pair are issued together, then consumed
+      auto build = [&](auto pass_tag) {
+        constexpr int PASS = decltype(pass_tag)::value;
         for (int mp = wave; mp < M / 2; mp += kThreads / 64) {
           u32x4 Bt[16], Bd[16];
 #pragma unroll
@@ -860,35 +905,38 @@ __global__ __launch_bounds__(kThreads) void k_scan(ScanArgs a) {
             if constexpr (DT == DT_F16) Bd[jt] = a.bsw16[fi];
             else Bd[jt] = (u32x4){0u, 0u, 0u, 0u};
           }
-          lut_mpair<LWB, WPR, DT>(a, lds, L, M, np_u, pass, mp, Bt, Bd);
+          lut_mpair<LWB, WPR, DT, PASS>(a, lds, L, M, np_u, mp, Bt, Bd);
         }
-        __syncthreads();
-        if (pass == 1) {
-          int32_t* lo = reinterpret_cast<int32_t*>(lds + L.lo);
-          const int32_t* hi = reinterpret_cast<const int32_t*>(lds + L.hi);
-          if (tid < np_u) {
-            const int g = tid;
-            int64_t R = 0, base = 0;
-            for (int m = 0; m < M; ++m) {
-              const int64_t span = (int64_t)hi[g * M + m] - lo[g * M + m];
-              R = span > R ? span : R;
-              base += lo[g * M + m];
-            }
-            if (ip) {
-              const int32_t* rrp = reinterpret_cast<const int32_t*>(lds + L.rr);
-              for (int m = 0; m < M; ++m) base -= rrp[g * M + m];  // -qi.ci
-            }
-            const int64_t top = (1ll << pb[g]) - 1;
-            int s = 0;
-            while (((R + (s ? (1ll << (s - 1)) : 0)) >> s) > top) ++s;
-            const int32_t hf = s ? (1 << (s - 1)) : 0;
-            for (int m = 0; m < M; ++m) lo[g * M + m] = hf - lo[g * M + m];  // -> off
-            ps[g] = s;
-            pbase[g] = base;
+      };
+      build(std::integral_constant<int, 1>{});
+      __syncthreads();
+      {
+        int32_t* lo = reinterpret_cast<int32_t*>(lds + L.lo);
+        const int32_t* hi = reinterpret_cast<const int32_t*>(lds + L.hi);
+        if (tid < np_u) {
+          const int g = tid;
+          int64_t R = 0, base = 0;
+          for (int m = 0; m < M; ++m) {
+            const int64_t span = (int64_t)hi[g * M + m] - lo[g * M + m];
+            R = span > R ? span : R;
+            base += lo[g * M + m];
           }
-          __syncthreads();
+          if (ip) {
+            const int32_t* rrp = reinterpret_cast<const int32_t*>(lds + L.rr);
+            for (int m = 0; m < M; ++m) base -= rrp[g * M + m];  // -qi.ci
+          }
+          const int64_t top = (1ll << pb[g]) - 1;
+          int s = 0;
+          while (((R + (s ? (1ll << (s - 1)) : 0)) >> s) > top) ++s;
+          const int32_t hf = s ? (1 << (s - 1)) : 0;
+          for (int m = 0; m < M; ++m) lo[g * M + m] = hf - lo[g * M + m];  // -> off
+          ps[g] = s;
+          pbase[g] = base;
         }
       }
+      __syncthreads();
+      build(std::integral_constant<int, 2>{});
+      __syncthreads();
     }
     // ---- per-pair pruning threshold in the lane domain (phase 2)
     if (PHASE == 2 && tid < G) {

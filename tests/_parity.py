@@ -80,7 +80,9 @@ def compare_fp32(gpu, ref, M):
     # ulps of the row's distance scale; 1e-4 relative stays well inside the
     # 1e-3 bar
     tol = 1e-4 * scale
-    assert np.all(np.abs(np.where(fin, g_d - r_d, 0)) <= tol)
+    diff = np.zeros_like(g_d)
+    diff[fin] = g_d[fin] - r_d[fin]
+    assert np.all(np.abs(diff) <= tol)
     mism = gpu["ids"] != ref["ids"]
     for i, j in np.argwhere(mism):
         # a swapped id must sit among distances within the bound

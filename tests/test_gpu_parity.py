@@ -466,3 +466,20 @@ def test_serving_shape_inner_product_mixed_k(serving_shape):
             compare_fp32(g, ref, w.M)
         else:
             compare_integer(g, ref)
+
+
+def test_device_queries_must_be_16_byte_aligned(tiny):
+    torch = pytest.importorskip("torch")
+    Q = tiny["Q"][:5]
+    flat = torch.from_numpy(np.ascontiguousarray(Q).ravel()).cuda()
+    o = dict(ids=torch.empty((4, 5), dtype=torch.int64, device="cuda"),
+             dist=torch.empty((4, 5), dtype=torch.float32, device="cuda"))
+    bad = flat[1:1 + 4 * Q.shape[1]].view(4, Q.shape[1])  # 4-byte offset
+    with pytest.raises(amp.AmpError) as e:
+        amp.amp_search(tiny["h"], bad, 5, 4, out=o, stream=torch.cuda.current_stream())
+    assert e.value.status == amp.AMP_EINVAL
+    good = flat[Q.shape[1]:].view(4, Q.shape[1])  # one row in: aligned (d % 4 == 0)
+    amp.amp_search(tiny["h"], good, 5, 4, out=o, stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    ref = amp.amp_search(tiny["h"], Q[1:], 5, 4)
+    assert np.array_equal(o["ids"].cpu().numpy(), ref["ids"])
