@@ -18,6 +18,7 @@ constexpr int kThreads = 256;          // threads per workgroup of the scan
 constexpr int kMaxDsub = 8;            // one MFMA lane group holds a subspace
 constexpr int kTableN = 1024;          // predictor kernel table entries
 constexpr int kNCls = 3;               // LUT lane-width classes: 8, 16, 32 bit
+constexpr int kQSub = 16;              // queue sub-counters per (class, list) bucket
 
 // lane-width class of a b-bit LUT for M subspaces: the sum of M entries of at
 // most 2^b - 1 must fit in the lane
@@ -73,7 +74,7 @@ struct Workspace {
   uint64_t* ckey = nullptr;    // [nq][capq]
   int64_t* cid = nullptr;      // [nq][capq]
   // queue (buckets are class-major: b = cls * nlist + list)
-  int32_t* cnt = nullptr;      // [2][NB]   pairs per bucket (phase 1, phase 2)
+  int32_t* cnt = nullptr;      // [2][kQSub][NB] pairs per bucket and sub-counter
   int32_t* rank = nullptr;     // [2][nq*npmax] rank of a pair inside its bucket
   int4* units = nullptr;       // [2][max_units] work units
   int64_t cap_units = 0;

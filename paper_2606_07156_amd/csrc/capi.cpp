@@ -442,7 +442,7 @@ static amp_status ensure_workspace(amp_index* ix, size_t nq, size_t np, size_t k
       (s = dalloc(&w.probes, npairs, t)) || (s = dalloc(&w.pdist, npairs, t)) ||
       (s = dalloc(&w.pbits, npairs, t)) || (s = dalloc(&w.xbits, npairs, t)) || (s = dalloc(&w.tau, nq, t)) ||
       (s = dalloc(&w.ccount, nq, t)) || (s = dalloc(&w.ckey, nq * capq, t)) || (s = dalloc(&w.cid, nq * capq, t)) ||
-      (s = dalloc(&w.cnt, 2 * NB, t)) || (s = dalloc(&w.rank, 2 * npairs, t)) ||
+      (s = dalloc(&w.cnt, 2 * kQSub * NB, t)) || (s = dalloc(&w.rank, 2 * npairs, t)) ||
       (s = dalloc(&w.units, 2 * (size_t)units, t)) || (s = dalloc(&w.pairoff, 2 * (NB + 1), t)) ||
       (s = dalloc(&w.unitoff, 2 * (NB + 1), t)) || (s = dalloc(&w.sorted, 2 * npairs, t)) ||
       (s = dalloc(&w.counters, 2 * (size_t)(kNCls + 1), t)) || (s = dalloc(&w.flags, 4, t)) ||
@@ -511,8 +511,10 @@ amp_status amp_search(amp_index* ix, const float* queries, int64_t nq, const int
   amp_status s = to_device_locked(ix, dev);
   if (s != AMP_OK) return s;
   if (pol->kind == AMP_POLICY_ADAPTIVE && ix->dev_model_stale && (s = upload_model(ix)) != AMP_OK) return s;
-  size_t capq = 16;  // a power of two: the merge sorts up to capq keys in place
-  while (capq < env_size("AMP_CAPQ", 4096) && capq < (1u << 16)) capq <<= 1;
+  // candidate capacity per query: a power of two (the merge sorts up to capq
+  // keys in place, 16 bytes each in LDS: at most 8192), at least kmax
+  size_t capq = 16;
+  while ((capq < env_size("AMP_CAPQ", 4096) || capq < (size_t)kmax) && capq < (1u << 13)) capq <<= 1;
   const int64_t chunk = (int64_t)env_size("AMP_CHUNK", 1 << 16);
   const int64_t max_nch = std::max<int64_t>(1, (ix->max_list + chunk - 1) / chunk);
   const int64_t max_units = (int64_t)nq * npmax * max_nch;

@@ -58,13 +58,9 @@ __device__ __forceinline__ int e4m3_int(int v) {
 // operand grid: round half to even of r * 2^-e, then saturate (9-bit grid) or
 // round to the e4m3-representable integers
 __device__ __forceinline__ int grid_val(float r, int e, int kind) {
-  float x = rintf(ldexpf(r, -e));
-  if (kind == AMP_GRID_U9) {
-    x = fminf(fmaxf(x, -255.f), 255.f);
-    return (int)x;
-  }
-  x = fminf(fmaxf(x, -65536.f), 65536.f);
-  return e4m3_int((int)x);
+  const float x = rintf(ldexpf(r, -e));
+  if (kind == AMP_GRID_U9) return (int)__builtin_amdgcn_fmed3f(x, -255.f, 255.f);
+  return e4m3_int((int)__builtin_amdgcn_fmed3f(x, -65536.f, 65536.f));
 }
 
 __device__ __forceinline__ uint32_t bf16_bits(float v) {  // exact inputs only
@@ -213,6 +209,7 @@ struct PairArgs {
   const uint8_t* xbits;
   uint8_t* pbits;
   int nq, d, npmax, grid_e, grid_kind, metric, policy, fixed_bits, lane_sel_M;
+  int lg_npp;  // log2 of the threads per query (power of two >= npmax, <= 256)
   uint32_t allowed;
   int64_t margin;
 };
@@ -233,36 +230,47 @@ __device__ __forceinline__ int pick_bits(int64_t y, const int64_t* theta, uint32
   return last;
 }
 
-// one workgroup per query, one thread per probe rank
-__global__ void k_pairs(PairArgs a, ModelArgs ma) {
-  __shared__ unsigned long long s_best;
+// 256 threads per workgroup: 256 / npp queries, npp (power of two >= npmax)
+// threads per query, one per probe rank
+__global__ __launch_bounds__(256) void k_pairs(PairArgs a, ModelArgs ma) {
+  __shared__ unsigned long long s_best[256];
   __shared__ int32_t s_table[kTableN];
-  const int q = blockIdx.x, r = threadIdx.x;
+  const int lg = a.lg_npp;
+  const int slot = threadIdx.x >> lg, r = threadIdx.x & ((1 << lg) - 1);
+  const int q = blockIdx.x * (256 >> lg) + slot;
   const bool adaptive = a.policy == AMP_POLICY_ADAPTIVE;
   if (adaptive)
     for (int i = threadIdx.x; i < kTableN; i += blockDim.x) s_table[i] = ma.table[i];
-  if (threadIdx.x == 0) s_best = ~0ull;
+  if (r == 0) s_best[slot] = ~0ull;
   __syncthreads();
-  const int p = r < a.npmax ? a.probes[(size_t)q * a.npmax + r] : -1;
+  const bool valid = q < a.nq && r < a.npmax;
+  const int p = valid ? a.probes[(size_t)q * a.npmax + r] : -1;
   int64_t dq2 = 0;
   if (adaptive && p >= 0) {
-    const float* qv = a.Q + (size_t)q * a.d;
-    const float* cv = a.C + (size_t)p * a.d;
-    if (a.metric == AMP_L2) {
-      for (int t = 0; t < a.d; ++t) {
-        int v = grid_val(qv[t] - cv[t], a.grid_e, a.grid_kind);
-        dq2 += (int64_t)v * v;
+    // d' = |grid residual|^2, four coordinates per step (d % 4 == 0)
+    const float4* qv = reinterpret_cast<const float4*>(a.Q + (size_t)q * a.d);
+    const float4* cv = reinterpret_cast<const float4*>(a.C + (size_t)p * a.d);
+    const bool l2 = a.metric == AMP_L2;
+    for (int t = 0; t < (a.d >> 2); ++t) {
+      const float4 x = qv[t], c = cv[t];
+      int v0, v1, v2, v3;
+      if (l2) {
+        v0 = grid_val(x.x - c.x, a.grid_e, a.grid_kind);
+        v1 = grid_val(x.y - c.y, a.grid_e, a.grid_kind);
+        v2 = grid_val(x.z - c.z, a.grid_e, a.grid_kind);
+        v3 = grid_val(x.w - c.w, a.grid_e, a.grid_kind);
+      } else {
+        v0 = grid_val(x.x, a.grid_e, a.grid_kind) - grid_val(c.x, a.grid_e, a.grid_kind);
+        v1 = grid_val(x.y, a.grid_e, a.grid_kind) - grid_val(c.y, a.grid_e, a.grid_kind);
+        v2 = grid_val(x.z, a.grid_e, a.grid_kind) - grid_val(c.z, a.grid_e, a.grid_kind);
+        v3 = grid_val(x.w, a.grid_e, a.grid_kind) - grid_val(c.w, a.grid_e, a.grid_kind);
       }
-    } else {
-      for (int t = 0; t < a.d; ++t) {
-        int v = grid_val(qv[t], a.grid_e, a.grid_kind) - grid_val(cv[t], a.grid_e, a.grid_kind);
-        dq2 += (int64_t)v * v;
-      }
+      dq2 += (int64_t)(v0 * v0 + v1 * v1) + (int64_t)(v2 * v2 + v3 * v3);
     }
-    atomicMin(&s_best, (unsigned long long)((uint64_t)dq2 << 13 | (uint64_t)p));
+    atomicMin(&s_best[slot], (unsigned long long)((uint64_t)dq2 << 13 | (uint64_t)p));
   }
   __syncthreads();
-  if (r >= a.npmax) return;
+  if (!valid) return;
   uint8_t bits = 0;
   if (p >= 0) {
     if (a.policy == AMP_POLICY_FP32) {
@@ -272,7 +280,7 @@ __global__ void k_pairs(PairArgs a, ModelArgs ma) {
     } else if (a.policy == AMP_POLICY_EXPLICIT) {
       bits = a.xbits[(size_t)q * a.npmax + r];
     } else {
-      const int c1 = (int)(s_best & 8191ull);
+      const int c1 = (int)(s_best[slot] & 8191ull);
       int64_t x[5];
       x[0] = dq2;
       x[1] = a.radq[c1];
@@ -286,8 +294,8 @@ __global__ void k_pairs(PairArgs a, ModelArgs ma) {
       }
       int64_t y = ma.beta0;
       for (int i = 0; i < ma.n_sv; ++i) {
-        const int32_t* s = ma.sv + 5 * i;
-        int32_t d0 = u[0] - s[0], d1 = u[1] - s[1], d2 = u[2] - s[2], d3 = u[3] - s[3], d4 = u[4] - s[4];
+        const int32_t* sv = ma.sv + 5 * i;
+        int32_t d0 = u[0] - sv[0], d1 = u[1] - sv[1], d2 = u[2] - sv[2], d3 = u[3] - sv[3], d4 = u[4] - sv[4];
         uint32_t dist2 = (uint32_t)(d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3 + d4 * d4);
         uint64_t idx = ((uint64_t)dist2 * ma.g_mul) >> 32;
         int32_t K = s_table[idx > (kTableN - 1) ? (kTableN - 1) : idx];
@@ -312,7 +320,7 @@ struct QueueArgs {
   const int64_t* offsets;
   const int32_t* lorder;  // bucket position -> list (largest list first)
   const int32_t* lpos;    // list -> bucket position
-  int32_t* cnt;       // [2][NB] by (class, list id)
+  int32_t* cnt;       // [2][kQSub][NB] by (sub-counter, class, list id)
   int32_t* rank;      // [2][nq*npmax]
   int64_t* pairoff;   // [2][NB+1] by (class, launch position)
   int64_t* unitoff;   // [2][NB+1] by (class, launch position)
@@ -332,6 +340,12 @@ __device__ __forceinline__ int class_pairs(int cls, int wpr, bool fp32) {
   return fp32 ? wpr : wpr * (4 >> cls);
 }
 
+// sub-counter of a pair: the pairs of a much-probed list spread over kQSub
+// counters (in different cache lines), so their atomics do not queue on one
+__device__ __forceinline__ int pair_sub(size_t i) {
+  return (int)(((uint32_t)i * 0x9E3779B1u) >> 28) & (kQSub - 1);
+}
+
 __global__ void k_qhist(QueueArgs a) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t n = (size_t)a.nq * a.npmax;
@@ -339,9 +353,9 @@ __global__ void k_qhist(QueueArgs a) {
   const int p = a.probes[i];
   if (p < 0) return;
   const int cls = pair_class(a.pbits[i], a.M);
-  const int b = cls * a.nlist + p;
   const int NB = a.ncls * a.nlist;
-  a.rank[n + i] = atomicAdd(&a.cnt[NB + b], 1);
+  const size_t b = (size_t)pair_sub(i) * NB + cls * a.nlist + p;
+  a.rank[n + i] = atomicAdd(&a.cnt[(size_t)kQSub * NB + b], 1);
   if (i % a.npmax == 0) a.rank[i] = atomicAdd(&a.cnt[b], 1);
 }
 
@@ -351,7 +365,7 @@ __global__ __launch_bounds__(1024) void k_qscan(QueueArgs a, int fp32) {
   const int NB = a.ncls * a.nlist;
   const int per = (NB + 1023) / 1024;
   for (int ph = 0; ph < 2; ++ph) {
-    const int32_t* cnt = a.cnt + (size_t)ph * NB;
+    int32_t* cnt = a.cnt + (size_t)ph * kQSub * NB;
     int64_t* po = a.pairoff + (size_t)ph * (NB + 1);
     int64_t* uo = a.unitoff + (size_t)ph * (NB + 1);
     const int b0 = threadIdx.x * per;
@@ -361,7 +375,16 @@ __global__ __launch_bounds__(1024) void k_qscan(QueueArgs a, int fp32) {
       const int64_t n = a.offsets[p + 1] - a.offsets[p];
       const int64_t nch = (n + a.chunk - 1) / a.chunk;
       const int G = class_pairs(cls, a.wpr, fp32);
-      const int c = cnt[cls * a.nlist + p];
+      // bucket total; the sub-counters become their offsets inside the bucket
+      int c = 0;
+#pragma unroll
+      for (int u = 0; u < kQSub; ++u) {
+        int32_t* cu = cnt + (size_t)u * NB + cls * a.nlist + p;
+        const int x = *cu;
+        *cu = c;
+        c += x;
+      }
+      po[b] = c;  // kept for the second sweep
       sp += c;
       su += ((c + G - 1) / G) * nch;
     }
@@ -388,7 +411,7 @@ __global__ __launch_bounds__(1024) void k_qscan(QueueArgs a, int fp32) {
       const int64_t n = a.offsets[p + 1] - a.offsets[p];
       const int64_t nch = (n + a.chunk - 1) / a.chunk;
       const int G = class_pairs(cls, a.wpr, fp32);
-      const int c = cnt[cls * a.nlist + p];
+      const int c = (int)po[b];
       po[b] = sp;
       uo[b] = su;
       sp += c;
@@ -407,8 +430,9 @@ __global__ void k_qscatter(QueueArgs a) {
   const int cls = pair_class(a.pbits[i], a.M);
   const int b = cls * a.nlist + a.lpos[p];
   const int NB = a.ncls * a.nlist;
-  a.sorted[n + a.pairoff[(NB + 1) + b] + a.rank[n + i]] = (int32_t)i;
-  if (i % a.npmax == 0) a.sorted[a.pairoff[b] + a.rank[i]] = (int32_t)i;
+  const size_t bs = (size_t)pair_sub(i) * NB + cls * a.nlist + p;  // sub-counter offset
+  a.sorted[n + a.pairoff[(NB + 1) + b] + a.cnt[(size_t)kQSub * NB + bs] + a.rank[n + i]] = (int32_t)i;
+  if (i % a.npmax == 0) a.sorted[a.pairoff[b] + a.cnt[bs] + a.rank[i]] = (int32_t)i;
 }
 
 // grid-stride over (phase, unit): find the unit's bucket by binary search of
@@ -1166,40 +1190,78 @@ struct MergeArgs {
   size_t capq;
 };
 
-__global__ __launch_bounds__(256) void k_merge(MergeArgs a) {
-  extern __shared__ __attribute__((aligned(16))) char lds[];
-  const int q = blockIdx.x;
+// output row r of query q from its sorted candidate r (n candidates)
+__device__ __forceinline__ void merge_emit(const MergeArgs& a, int q, int r, int n, int kk, uint64_t key,
+                                           int64_t id) {
+  const size_t o = (size_t)q * a.kmax + r;
+  if (r < kk && r < n) {
+    a.out_ids[o] = id;
+    if (a.fp32) {
+      a.out_dist[o] = fkey_val((uint32_t)key);
+      if (a.out_qdist) a.out_qdist[o] = -1;
+    } else {
+      const int64_t D = ikey_val(key);
+      a.out_dist[o] = __ll2float_rn(D) * a.h2;
+      if (a.out_qdist) a.out_qdist[o] = D;
+    }
+  } else {
+    a.out_ids[o] = -1;
+    a.out_dist[o] = __builtin_inff();
+    if (a.out_qdist) a.out_qdist[o] = INT64_MAX;
+  }
+}
+
+// queries with at most 64 candidates: one wave per query, a register bitonic
+// sort of (key, id) across the lanes
+__global__ __launch_bounds__(256) void k_merge_wave(MergeArgs a, int nq) {
+  const int lane = threadIdx.x & 63;
+  const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (q >= nq) return;
   const uint32_t cnt = a.ccount[q];
-  if (cnt > a.capq && threadIdx.x == 0) atomicOr(&a.flags[0], 2);
+  if (cnt > a.capq && lane == 0) atomicOr(&a.flags[0], 2);
   const int n = (int)(cnt < a.capq ? cnt : a.capq);
-  int np2 = 1;
-  while (np2 < n) np2 <<= 1;
+  if (n > 64) return;  // the workgroup kernel takes it
+  uint64_t key = lane < n ? a.ckey[(size_t)q * a.capq + lane] : ~0ull;
+  int64_t id = lane < n ? a.cid[(size_t)q * a.capq + lane] : INT64_MAX;
+  for (int kb = 2; kb <= 64; kb <<= 1)
+    for (int jb = kb >> 1; jb > 0; jb >>= 1) {
+      const uint64_t ok = __shfl_xor(key, jb);
+      const int64_t oid = __shfl_xor(id, jb);
+      const bool other_less = ok < key || (ok == key && oid < id);
+      const bool other_more = ok > key || (ok == key && oid > id);
+      const bool keep_min = ((lane & kb) == 0) == ((lane & jb) == 0);
+      if (keep_min ? other_less : other_more) {
+        key = ok;
+        id = oid;
+      }
+    }
+  const int kk = a.kq ? a.kq[q] : a.kconst;
+  for (int r = lane; r < a.kmax; r += 64) merge_emit(a, q, r, n, kk, key, id);
+}
+
+// queries with more than 64 candidates: a workgroup per query (strided over
+// the queries), bitonic sort in LDS
+__global__ __launch_bounds__(256) void k_merge(MergeArgs a, int nq) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
   uint64_t* keys = reinterpret_cast<uint64_t*>(lds);
   int64_t* vals = reinterpret_cast<int64_t*>(lds + a.capq * 8);
-  for (int i = threadIdx.x; i < np2; i += blockDim.x) {
-    keys[i] = i < n ? a.ckey[(size_t)q * a.capq + i] : ~0ull;
-    vals[i] = i < n ? a.cid[(size_t)q * a.capq + i] : INT64_MAX;
-  }
-  __syncthreads();
-  block_bitonic_u64_i64(keys, vals, np2);
-  const int kk = a.kq ? a.kq[q] : a.kconst;
-  for (int r = threadIdx.x; r < a.kmax; r += blockDim.x) {
-    const size_t o = (size_t)q * a.kmax + r;
-    if (r < kk && r < n) {
-      a.out_ids[o] = vals[r];
-      if (a.fp32) {
-        a.out_dist[o] = fkey_val((uint32_t)keys[r]);
-        if (a.out_qdist) a.out_qdist[o] = -1;
-      } else {
-        const int64_t D = ikey_val(keys[r]);
-        a.out_dist[o] = __ll2float_rn(D) * a.h2;
-        if (a.out_qdist) a.out_qdist[o] = D;
-      }
-    } else {
-      a.out_ids[o] = -1;
-      a.out_dist[o] = __builtin_inff();
-      if (a.out_qdist) a.out_qdist[o] = INT64_MAX;
+  for (int q = blockIdx.x; q < nq; q += gridDim.x) {
+    const uint32_t cnt = a.ccount[q];
+    if (cnt > a.capq && threadIdx.x == 0) atomicOr(&a.flags[0], 2);
+    const int n = (int)(cnt < a.capq ? cnt : a.capq);
+    if (n <= 64) continue;  // uniform over the workgroup
+    int np2 = 1;
+    while (np2 < n) np2 <<= 1;
+    for (int i = threadIdx.x; i < np2; i += blockDim.x) {
+      keys[i] = i < n ? a.ckey[(size_t)q * a.capq + i] : ~0ull;
+      vals[i] = i < n ? a.cid[(size_t)q * a.capq + i] : INT64_MAX;
     }
+    __syncthreads();
+    block_bitonic_u64_i64(keys, vals, np2);
+    const int kk = a.kq ? a.kq[q] : a.kconst;
+    for (int r = threadIdx.x; r < a.kmax; r += blockDim.x)
+      merge_emit(a, q, r, n, kk, r < n ? keys[r] : ~0ull, r < n ? vals[r] : INT64_MAX);
+    __syncthreads();  // the LDS is reused by the next query
   }
 }
 
@@ -1354,8 +1416,8 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
                      ws.npq ? ws.npq : nullptr, sd.npconst, sd.npmax, ws.probes, ws.pdist);
   mark(2);
   // resets
-  hipLaunchKernelGGL(k_fill_u32, dim3(64), dim3(256), 0, st, reinterpret_cast<uint32_t*>(ws.cnt), 0u,
-                     (size_t)2 * NB);
+  hipLaunchKernelGGL(k_fill_u32, dim3(256), dim3(256), 0, st, reinterpret_cast<uint32_t*>(ws.cnt), 0u,
+                     (size_t)2 * kQSub * NB);
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, ws.counters, 0u, (size_t)2 * (kNCls + 1));
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(ws.flags), 0u, (size_t)4);
   hipLaunchKernelGGL(k_fill_u64, dim3(64), dim3(256), 0, st, ws.tau, ~0ull, (size_t)sd.nq);
@@ -1380,8 +1442,10 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   pa.lane_sel_M = sd.M;
   pa.allowed = sd.allowed_mask;
   pa.margin = sd.margin;
-  const int pthreads = ((sd.npmax + 63) / 64) * 64;
-  hipLaunchKernelGGL(k_pairs, dim3(sd.nq), dim3(pthreads), 0, st, pa, ma);
+  pa.lg_npp = 0;
+  while ((1 << pa.lg_npp) < sd.npmax) ++pa.lg_npp;
+  const int qpb = 256 >> pa.lg_npp;
+  hipLaunchKernelGGL(k_pairs, dim3((sd.nq + qpb - 1) / qpb), dim3(256), 0, st, pa, ma);
   mark(3);
   // queue
   QueueArgs qa;
@@ -1476,7 +1540,8 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   const size_t mlds = sd.capq * 16;
   err = hipFuncSetAttribute(kaddr(k_merge), hipFuncAttributeMaxDynamicSharedMemorySize, (int)mlds);
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(k_merge, dim3(sd.nq), dim3(256), mlds, st, ma2);
+  hipLaunchKernelGGL(k_merge_wave, dim3((sd.nq + 3) / 4), dim3(256), 0, st, ma2, sd.nq);
+  hipLaunchKernelGGL(k_merge, dim3(sd.nq < 512 ? sd.nq : 512), dim3(256), mlds, st, ma2, sd.nq);
   mark(7);
   return hipGetLastError();
 }
