@@ -66,7 +66,6 @@ struct Workspace {
   float* qnorm = nullptr;      // [nq]
   float* coarse = nullptr;     // [nq][nlist]
   int32_t* probes = nullptr;   // [nq][npmax]
-  float* pdist = nullptr;      // [nq][npmax]
   uint8_t* pbits = nullptr;    // [nq][npmax]
   uint8_t* xbits = nullptr;    // [nq][npmax] explicit widths (uploaded)
   uint64_t* tau = nullptr;     // [nq] pruning threshold key
@@ -104,11 +103,14 @@ struct GraphKey {
   int64_t margin;
   int32_t lut_dtype;
   uint64_t ws_gen, model_gen;
+  int64_t chunk, chunk1;
+  size_t capq;
   bool operator==(const GraphKey& o) const {
     return q == o.q && ids == o.ids && dist == o.dist && qdist == o.qdist && probes == o.probes &&
            bits == o.bits && coarse == o.coarse && stream == o.stream && nq == o.nq && k == o.k &&
            nprobe == o.nprobe && kind == o.kind && fixed_bits == o.fixed_bits && allowed == o.allowed &&
-           margin == o.margin && lut_dtype == o.lut_dtype && ws_gen == o.ws_gen && model_gen == o.model_gen;
+           margin == o.margin && lut_dtype == o.lut_dtype && ws_gen == o.ws_gen && model_gen == o.model_gen &&
+           chunk == o.chunk && chunk1 == o.chunk1 && capq == o.capq;
   }
 };
 }  // namespace amp
@@ -154,7 +156,8 @@ struct SearchDims {
   int nq, d, M, dsub, nlist, npmax, kmax, metric, grid_kind, grid_e;
   int kconst, npconst;   // used when the per-query arrays are null
   int wpr;               // LUT words per row
-  int64_t chunk;         // list chunk length of one work unit
+  int64_t chunk;         // list chunk length of one work unit (phase 2)
+  int64_t chunk1;        // the same for the phase-1 bound (latency-bound: shorter)
   int64_t max_units;     // capacity of each phase's unit table
   size_t capq;
   int policy;            // AMP_POLICY_*

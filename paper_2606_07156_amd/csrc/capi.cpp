@@ -439,7 +439,7 @@ static amp_status ensure_workspace(amp_index* ix, size_t nq, size_t np, size_t k
   amp_status s;
   if ((s = dalloc(&w.queries, nq * ix->d, t)) || (s = dalloc(&w.kq, nq, t)) || (s = dalloc(&w.npq, nq, t)) ||
       (s = dalloc(&w.qnorm, nq, t)) || (s = dalloc(&w.coarse, nq * ix->nlist, t)) ||
-      (s = dalloc(&w.probes, npairs, t)) || (s = dalloc(&w.pdist, npairs, t)) ||
+      (s = dalloc(&w.probes, npairs, t)) ||
       (s = dalloc(&w.pbits, npairs, t)) || (s = dalloc(&w.xbits, npairs, t)) || (s = dalloc(&w.tau, nq, t)) ||
       (s = dalloc(&w.ccount, nq, t)) || (s = dalloc(&w.ckey, nq * capq, t)) || (s = dalloc(&w.cid, nq * capq, t)) ||
       (s = dalloc(&w.cnt, 2 * kQSub * NB, t)) || (s = dalloc(&w.rank, 2 * npairs, t)) ||
@@ -515,9 +515,15 @@ amp_status amp_search(amp_index* ix, const float* queries, int64_t nq, const int
   // keys in place, 16 bytes each in LDS: at most 8192), at least kmax
   size_t capq = 16;
   while ((capq < env_size("AMP_CAPQ", 4096) || capq < (size_t)kmax) && capq < (1u << 13)) capq <<= 1;
-  const int64_t chunk = (int64_t)env_size("AMP_CHUNK", 1 << 16);
+  // list chunk of a work unit (AMP_CHUNK for phase 2, AMP_CHUNK1 for the
+  // phase-1 bound).  Whole lists by default: each chunk rebuilds its pairs'
+  // LUTs, and a chunked phase 1 gives a looser bound (measured slower on the
+  // mid workload for chunks of 1024-4096)
+  const int64_t chunk = std::max<int64_t>(1, (int64_t)env_size("AMP_CHUNK", 1 << 16));
+  const int64_t chunk1 = std::max<int64_t>(1, (int64_t)env_size("AMP_CHUNK1", 1 << 16));
   const int64_t max_nch = std::max<int64_t>(1, (ix->max_list + chunk - 1) / chunk);
-  const int64_t max_units = (int64_t)nq * npmax * max_nch;
+  const int64_t max_nch1 = std::max<int64_t>(1, (ix->max_list + chunk1 - 1) / chunk1);
+  const int64_t max_units = std::max<int64_t>((int64_t)nq * npmax * max_nch, (int64_t)nq * max_nch1);
   if (opts->mem != AMP_MEM_HOST && (reinterpret_cast<uintptr_t>(queries) & 15))
     return set_error(AMP_EINVAL, "device query buffer must be 16-byte aligned");
   if ((s = ensure_workspace(ix, nq, npmax, kmax, capq, max_units)) != AMP_OK) return s;
@@ -553,6 +559,7 @@ amp_status amp_search(amp_index* ix, const float* queries, int64_t nq, const int
   sd.npconst = per_query ? 0 : nprobe[0];
   sd.wpr = scan_wpr(ix->M, pol->kind == AMP_POLICY_FP32, pol->lut_dtype);
   sd.chunk = chunk;
+  sd.chunk1 = chunk1;
   sd.max_units = w.cap_units;
   sd.capq = capq;
   sd.policy = pol->kind;
@@ -607,7 +614,7 @@ amp_status amp_search(amp_index* ix, const float* queries, int64_t nq, const int
     // one captured graph per index, replayed while the launch key is unchanged
     GraphKey key{qdev, out_ids, out_dist, opts->out_qdist, opts->out_probes, opts->out_bits, opts->out_coarse,
                  st, nq, k[0], nprobe[0], pol->kind, pol->fixed_bits, sd.allowed_mask, pol->margin_q40,
-                 pol->lut_dtype, ix->ws_generation, ix->model_generation};
+                 pol->lut_dtype, ix->ws_generation, ix->model_generation, chunk, chunk1, capq};
     if (!ix->graph_exec || !(ix->graph_key == key)) {
       if (ix->graph_exec) hipGraphExecDestroy(ix->graph_exec);
       ix->graph_exec = nullptr;

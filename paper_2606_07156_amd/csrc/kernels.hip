@@ -180,10 +180,11 @@ __device__ void block_bitonic_u64_i64(uint64_t* keys, int64_t* vals, int n) {
   }
 }
 
-// CL selection: the nprobe smallest (distance, list) of each query
+// CL selection: the nprobe smallest (distance, list) of each query.
+// General case: a workgroup per query, bitonic sort of all nlist keys in LDS.
 __global__ __launch_bounds__(256) void k_topn(const float* __restrict__ D, int nlist, int np2,
                                               const int32_t* __restrict__ npq, int npconst, int npmax,
-                                              int32_t* __restrict__ probes, float* __restrict__ pdist) {
+                                              int32_t* __restrict__ probes) {
   extern __shared__ uint64_t keys[];
   const int q = blockIdx.x;
   const float* row = D + (size_t)q * nlist;
@@ -192,11 +193,74 @@ __global__ __launch_bounds__(256) void k_topn(const float* __restrict__ D, int n
   __syncthreads();
   block_bitonic_u64(keys, np2);
   const int np = npq ? npq[q] : npconst;
-  for (int r = threadIdx.x; r < npmax; r += blockDim.x) {
-    bool on = r < np;
-    probes[(size_t)q * npmax + r] = on ? (int32_t)(keys[r] & 0xFFFFFFFFu) : -1;
-    pdist[(size_t)q * npmax + r] = on ? fkey_val((uint32_t)(keys[r] >> 32)) : __builtin_inff();
+  for (int r = threadIdx.x; r < npmax; r += blockDim.x)
+    probes[(size_t)q * npmax + r] = r < np ? (int32_t)(keys[r] & 0xFFFFFFFFu) : -1;
+}
+
+__device__ __forceinline__ int wave_sum(int c) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+  return c;
+}
+
+// nlist <= 64 * PER and nprobe <= 64: one wave per query, no sort of the
+// whole row.  Lane l holds keys l, l + 64, ...  The nprobe-th smallest
+// order key is found bit by bit (count of keys below a candidate, summed
+// over the wave); the keys below it, and the equal ones with the lowest list
+// ids, are compacted and sorted by (key, list) across the lanes.
+template <int PER>
+__global__ __launch_bounds__(256) void k_topn_wave(const float* __restrict__ D, int nlist, int nq,
+                                                   const int32_t* __restrict__ npq, int npconst, int npmax,
+                                                   int32_t* __restrict__ probes) {
+  __shared__ uint64_t s_sel[4][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int q = blockIdx.x * 4 + wv;
+  const bool on = q < nq;  // no early return: the workgroup synchronises below
+  uint32_t key[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int i = j * 64 + lane;
+    key[j] = on && i < nlist ? fkey(D[(size_t)q * nlist + i]) : 0xFFFFFFFFu;
   }
+  const int k = on ? (npq ? npq[q] : npconst) : 0;
+  uint32_t x = 0;  // largest value with fewer than k keys below it: the k-th smallest
+  for (int bit = 31; bit >= 0; --bit) {
+    const uint32_t t = x | (1u << bit);
+    int c = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) c += key[j] < t ? 1 : 0;
+    if (wave_sum(c) < k) x = t;
+  }
+  int lt = 0;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) lt += key[j] < x ? 1 : 0;
+  int need_eq = k - wave_sum(lt);  // keys equal to x to take, lowest list id first
+  s_sel[wv][lane] = ~0ull;
+  __syncthreads();
+  int base = 0;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {  // list ids ascend with (j, lane)
+    const bool eq = key[j] == x;
+    const uint64_t meq = __ballot(eq);
+    const int eq_rank = __popcll(meq & ((1ull << lane) - 1));
+    const bool sel = on && (key[j] < x || (eq && eq_rank < need_eq));
+    need_eq -= __popcll(meq) < need_eq ? __popcll(meq) : need_eq;
+    const uint64_t msel = __ballot(sel);
+    if (sel) {
+      const int pos = base + __popcll(msel & ((1ull << lane) - 1));
+      s_sel[wv][pos] = ((uint64_t)key[j] << 32) | (uint32_t)(j * 64 + lane);
+    }
+    base += __popcll(msel);
+  }
+  __syncthreads();
+  uint64_t v = s_sel[wv][lane];
+  for (int kb = 2; kb <= 64; kb <<= 1)
+    for (int jb = kb >> 1; jb > 0; jb >>= 1) {
+      const uint64_t o = __shfl_xor(v, jb);
+      const bool keep_min = ((lane & kb) == 0) == ((lane & jb) == 0);
+      v = keep_min ? (o < v ? o : v) : (o > v ? o : v);
+    }
+  if (on && lane < npmax) probes[(size_t)q * npmax + lane] = lane < k ? (int32_t)(v & 0xFFFFFFFFu) : -1;
 }
 
 // ------------------------------------------------------------------ PPM
@@ -328,7 +392,7 @@ struct QueueArgs {
   int4* units;        // [2][max_units]: {list, first pair, pair count, chunk}
   int32_t* flags;
   int nq, npmax, nlist, M, ncls, wpr;
-  int64_t chunk, max_units;
+  int64_t chunk[2], max_units;  // list chunk of a work unit in phase 1, phase 2
 };
 
 __device__ __forceinline__ int pair_class(int bits, int M) {
@@ -373,7 +437,7 @@ __global__ __launch_bounds__(1024) void k_qscan(QueueArgs a, int fp32) {
     for (int b = b0; b < b0 + per && b < NB; ++b) {
       const int cls = b / a.nlist, p = a.lorder[b % a.nlist];
       const int64_t n = a.offsets[p + 1] - a.offsets[p];
-      const int64_t nch = (n + a.chunk - 1) / a.chunk;
+      const int64_t nch = (n + a.chunk[ph] - 1) / a.chunk[ph];
       const int G = class_pairs(cls, a.wpr, fp32);
       // bucket total; the sub-counters become their offsets inside the bucket
       int c = 0;
@@ -409,7 +473,7 @@ __global__ __launch_bounds__(1024) void k_qscan(QueueArgs a, int fp32) {
     for (int b = b0; b < b0 + per && b < NB; ++b) {
       const int cls = b / a.nlist, p = a.lorder[b % a.nlist];
       const int64_t n = a.offsets[p + 1] - a.offsets[p];
-      const int64_t nch = (n + a.chunk - 1) / a.chunk;
+      const int64_t nch = (n + a.chunk[ph] - 1) / a.chunk[ph];
       const int G = class_pairs(cls, a.wpr, fp32);
       const int c = (int)po[b];
       po[b] = sp;
@@ -457,7 +521,7 @@ __global__ void k_qunits(QueueArgs a, int fp32) {
       }
       const int b = lo, cls = b / a.nlist, p = a.lorder[b % a.nlist];
       const int64_t n = a.offsets[p + 1] - a.offsets[p];
-      const int64_t nch = (n + a.chunk - 1) / a.chunk;
+      const int64_t nch = (n + a.chunk[ph] - 1) / a.chunk[ph];
       const int G = class_pairs(cls, a.wpr, fp32);
       const int64_t local = u - uo[b], grp = local / nch, ch = local % nch;
       const int64_t left = (po[b + 1] - po[b]) - grp * G;
@@ -1412,8 +1476,23 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   mark(1);
   int np2 = 1;
   while (np2 < sd.nlist) np2 <<= 1;
-  hipLaunchKernelGGL(k_topn, dim3(sd.nq), dim3(256), np2 * sizeof(uint64_t), st, coarse, sd.nlist, np2,
-                     ws.npq ? ws.npq : nullptr, sd.npconst, sd.npmax, ws.probes, ws.pdist);
+  if (sd.npmax <= 64 && sd.nlist <= 1024) {
+    const dim3 g((sd.nq + 3) / 4), b(256);
+    const int32_t* npq = ws.npq ? ws.npq : nullptr;
+    if (sd.nlist <= 64)
+      hipLaunchKernelGGL(k_topn_wave<1>, g, b, 0, st, coarse, sd.nlist, sd.nq, npq, sd.npconst, sd.npmax, ws.probes);
+    else if (sd.nlist <= 128)
+      hipLaunchKernelGGL(k_topn_wave<2>, g, b, 0, st, coarse, sd.nlist, sd.nq, npq, sd.npconst, sd.npmax, ws.probes);
+    else if (sd.nlist <= 256)
+      hipLaunchKernelGGL(k_topn_wave<4>, g, b, 0, st, coarse, sd.nlist, sd.nq, npq, sd.npconst, sd.npmax, ws.probes);
+    else if (sd.nlist <= 512)
+      hipLaunchKernelGGL(k_topn_wave<8>, g, b, 0, st, coarse, sd.nlist, sd.nq, npq, sd.npconst, sd.npmax, ws.probes);
+    else
+      hipLaunchKernelGGL(k_topn_wave<16>, g, b, 0, st, coarse, sd.nlist, sd.nq, npq, sd.npconst, sd.npmax, ws.probes);
+  } else {
+    hipLaunchKernelGGL(k_topn, dim3(sd.nq), dim3(256), np2 * sizeof(uint64_t), st, coarse, sd.nlist, np2,
+                       ws.npq ? ws.npq : nullptr, sd.npconst, sd.npmax, ws.probes);
+  }
   mark(2);
   // resets
   hipLaunchKernelGGL(k_fill_u32, dim3(256), dim3(256), 0, st, reinterpret_cast<uint32_t*>(ws.cnt), 0u,
@@ -1467,7 +1546,8 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   qa.M = sd.M;
   qa.ncls = ncls;
   qa.wpr = sd.wpr;
-  qa.chunk = sd.chunk;
+  qa.chunk[0] = sd.chunk1;
+  qa.chunk[1] = sd.chunk;
   qa.max_units = sd.max_units;
   const int qb = (int)((npairs + 255) / 256);
   hipLaunchKernelGGL(k_qhist, dim3(qb), dim3(256), 0, st, qa);
@@ -1503,7 +1583,7 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   sa.metric = sd.metric;
   sa.kconst = sd.kconst;
   sa.kmax = sd.kmax;
-  sa.chunk = sd.chunk;
+  sa.chunk = sd.chunk;  // per phase below
   sa.capq = sd.capq;
   hipError_t err = hipSuccess;
   // the lane classes run one after another on the caller's stream, each a
@@ -1515,6 +1595,7 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
     sa.sorted = ws.sorted + (ph == 2 ? npairs : 0);
     sa.unitoff = ws.unitoff + (ph == 2 ? (NB + 1) : 0);
     sa.units = ws.units + (ph == 2 ? sd.max_units : 0);
+    sa.chunk = ph == 2 ? sd.chunk : sd.chunk1;
     for (int c = 0; c < ncls; ++c) {
       sa.cls = c;
       sa.counter = ws.counters + (ph - 1) * (kNCls + 1) + c;

@@ -483,3 +483,29 @@ def test_device_queries_must_be_16_byte_aligned(tiny):
     torch.cuda.synchronize()
     ref = amp.amp_search(tiny["h"], Q[1:], 5, 4)
     assert np.array_equal(o["ids"].cpu().numpy(), ref["ids"])
+
+
+@pytest.mark.parametrize("nlist,nprobe", [(64, 5), (1000, 37), (256, 100), (1500, 8)])
+def test_probe_ties_follow_list_ids(nlist, nprobe):
+    """Duplicated centroids give bit-identical coarse distances: the probe
+    order must then follow the list id, including at the nprobe boundary
+    (wave-level selection for nlist <= 1024 and nprobe <= 64, workgroup sort
+    otherwise)."""
+    r = np.random.default_rng(nlist + nprobe)
+    M, dsub = 8, 4
+    d = M * dsub
+    C = r.integers(-20, 21, size=(nlist, d)).astype(np.float32)
+    dup = r.choice(nlist, size=min(nlist, 3 * nprobe), replace=False)
+    C[dup] = C[dup[0]]  # one point repeated many times
+    n_per = 2
+    idx = dict(d=d, M=M, dsub=dsub, nlist=nlist, ksub=256, metric="l2", grid_kind="u9", grid_e=0,
+               centroids=C, codebook=r.integers(-3, 4, size=(M, 256, dsub)).astype(np.float32),
+               list_offsets=np.arange(0, nlist * n_per + 1, n_per), ids=np.arange(nlist * n_per, dtype=np.int64),
+               codes=r.integers(0, 256, size=(nlist * n_per, M)).astype(np.uint8),
+               list_sizes=np.full(nlist, n_per, np.int32), radq=np.full(nlist, 10, np.int32))
+    Q = np.repeat(C[dup[:1]], 6, axis=0) + r.integers(-1, 2, size=(6, d)).astype(np.float32)
+    ctx = _ctx(idx, Q)
+    g = _gpu(ctx, 3, nprobe, policy="fixed", bits=16)
+    for i, q in enumerate(Q):
+        want = oracle.select_probes(oracle.coarse_distances(q, C), nprobe)
+        assert np.array_equal(g["probes"][i], want), (i, g["probes"][i], want)
