@@ -14,7 +14,13 @@ namespace amp {
 
 // -------------------------------------------------------------- constants
 constexpr int kKsub = AMP_KSUB;
-constexpr int kThreads = 256;          // threads per workgroup of the scan
+// threads per workgroup of the scan: 256, two workgroups per CU (384 and 512
+// were measured slower on the mid workload: registers spill at three or four
+// waves per SIMD, and the per-wave phase-1 bound loosens as waves cover less
+// of a list)
+constexpr int kThreads = 256;
+constexpr int kThreadsP2 = 256;        // the next power of two (phase-1 sort rows)
+static_assert(kThreadsP2 >= kThreads && (kThreadsP2 & (kThreadsP2 - 1)) == 0, "kThreadsP2");
 constexpr int kMaxDsub = 8;            // one MFMA lane group holds a subspace
 constexpr int kTableN = 1024;          // predictor kernel table entries
 constexpr int kNCls = 3;               // LUT lane-width classes: 8, 16, 32 bit

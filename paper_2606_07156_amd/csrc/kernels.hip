@@ -585,7 +585,7 @@ __host__ __device__ inline ScanLds scan_lds_layout(int G, int wpr, int M, int d,
   L.psig = take(G * 4);
   // phase 1 keeps per-thread minima after the scan: reuse the LUT space
   L.lmin = L.lut;
-  if (phase == 1 && G * kThreads * 4 > M * kKsub * wpr * 4) L.lmin = take(G * kThreads * 4);
+  if (phase == 1 && G * kThreadsP2 * 4 > M * kKsub * wpr * 4) L.lmin = take(G * kThreadsP2 * 4);
   L.total = o;
   return L;
 }
@@ -729,13 +729,14 @@ __device__ __forceinline__ void lut_mpair(const ScanArgs& a, char* lds, const Sc
 #pragma unroll
   for (int jt = 0; jt < 16; ++jt) {
     const bf16x8 Bf = __builtin_bit_cast(bf16x8, B[jt]);
+    const u32x4 Bdj = Bd[jt];
     const int j = jt * 16 + (lane & 15);
 #pragma unroll
     for (int gt = 0; gt < NGT; ++gt) {
       f4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[gt], Bf, (f4){0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
       if constexpr (DT == DT_F16) {
         acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, Ad[gt]),
-                                                     __builtin_bit_cast(f16x8, Bd[jt]), acc, 0, 0, 0);
+                                                     __builtin_bit_cast(f16x8, Bdj), acc, 0, 0, 0);
       }
       const int g0 = gt * 8 + 4 * (kg & 1);
       if constexpr (PASS == 1) {
@@ -788,10 +789,13 @@ __device__ __forceinline__ void lut_mpair(const ScanArgs& a, char* lds, const Sc
   }
 }
 
+// FP32 LUT entries are built by thread (m, j) = (kMPar i + tid / 256, tid % 256)
+// (threads past kMPar * 256 do not take part)
+constexpr int kMPar = kThreads / kKsub;  // subspaces built side by side
 template <int WPR, int MT>
 struct Owned {
-  // codewords of the FP32 LUT entries a thread owns: (m, j = tid) for every m
-  static constexpr int NM = MT ? MT : 1;
+  // codewords of the FP32 LUT entries a thread owns
+  static constexpr int NM = MT ? MT / kMPar : 1;
   float c[NM][kMaxDsub];
 };
 
@@ -803,7 +807,7 @@ __global__ __launch_bounds__(kThreads, LWB == 0 ? 1 : 2) void k_scan(ScanArgs a)
   constexpr int W = Lane<LWB>::W;
   constexpr int G = WPR * W;
   constexpr uint32_t MASK = Lane<LWB>::MASK;
-  constexpr bool CRES = FP && MT != 0;               // FP32 codewords stay in registers
+  constexpr bool CRES = FP && MT != 0 && MT <= 16;  // FP32 codewords stay in registers
   const int M = MT ? MT : a.M;
   const ScanLds L = scan_lds_layout(G, WPR, M, a.d, FP, PHASE);
   __shared__ int s_u;
@@ -816,13 +820,16 @@ __global__ __launch_bounds__(kThreads, LWB == 0 ? 1 : 2) void k_scan(ScanArgs a)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t ub = a.unitoff[(size_t)a.cls * a.nlist];
   const int64_t ue = a.unitoff[(size_t)(a.cls + 1) * a.nlist];
+  const int own_j = tid % kKsub, own_m0 = tid / kKsub;
+  const bool owner = tid < kMPar * kKsub;
   Owned<WPR, CRES ? MT : 0> own;
   if constexpr (CRES) {
 #pragma unroll
-    for (int m = 0; m < MT; ++m)
+    for (int i = 0; i < MT / kMPar; ++i)
 #pragma unroll
       for (int t = 0; t < kMaxDsub; ++t)
-        own.c[m][t] = t < a.dsub ? a.codebook[((size_t)m * kKsub + tid) * a.dsub + t] : 0.f;
+        own.c[i][t] = owner && t < a.dsub
+                          ? a.codebook[((size_t)(kMPar * i + own_m0) * kKsub + own_j) * a.dsub + t] : 0.f;
   }
   // the next unit is claimed while the current one is processed: its index
   // at the start, its descriptor before the scan, published at the end
@@ -924,7 +931,7 @@ __global__ __launch_bounds__(kThreads, LWB == 0 ? 1 : 2) void k_scan(ScanArgs a)
       }
       float* lut = reinterpret_cast<float*>(lds + L.lut);
       auto entry = [&](int m, const float (&c)[kMaxDsub]) {
-        const int e = m * kKsub + tid;
+        const int e = m * kKsub + own_j;
         float cc = 0.f;
 #pragma unroll
         for (int t = 0; t < kMaxDsub; ++t) cc = fmaf(c[t], c[t], cc);
@@ -956,14 +963,16 @@ __global__ __launch_bounds__(kThreads, LWB == 0 ? 1 : 2) void k_scan(ScanArgs a)
         for (int g = 0; g < WPR; ++g) dst[g] = out[g];
       };
       if constexpr (CRES) {
+        if (owner) {
 #pragma unroll
-        for (int m = 0; m < MT; ++m) entry(m, own.c[m]);
-      } else {
-        for (int m = 0; m < M; ++m) {
+          for (int i = 0; i < MT / kMPar; ++i) entry(kMPar * i + own_m0, own.c[i]);
+        }
+      } else if (owner) {
+        for (int m = own_m0; m < M; m += kMPar) {
           float c[kMaxDsub];
 #pragma unroll
           for (int t = 0; t < kMaxDsub; ++t)
-            c[t] = t < a.dsub ? a.codebook[((size_t)m * kKsub + tid) * a.dsub + t] : 0.f;
+            c[t] = t < a.dsub ? a.codebook[((size_t)m * kKsub + own_j) * a.dsub + t] : 0.f;
           entry(m, c);
         }
       }
@@ -1152,8 +1161,9 @@ __global__ __launch_bounds__(kThreads, LWB == 0 ? 1 : 2) void k_scan(ScanArgs a)
             if (hit) {
 #pragma unroll
               for (int f = 0; f < 4; ++f) {
+                // rare path: thresholds from LDS, not held in registers
                 const uint32_t S = (acc[w] >> (8 * f)) & 0xFFu;
-                if (live[4 * w + f] && S <= sig[4 * w + f]) emit(4 * w + f, S);
+                if (pb[4 * w + f] >= 0 && S <= psig[4 * w + f]) emit(4 * w + f, S);
               }
             }
           }
@@ -1199,18 +1209,23 @@ __global__ __launch_bounds__(kThreads, LWB == 0 ? 1 : 2) void k_scan(ScanArgs a)
       }
     } else if (PHASE == 1) {
       // k > 64: the k-th smallest of the workgroup's per-thread minima
+      // (bitonic sort over a power-of-two row, padded with the largest key)
+      constexpr int TP = kThreadsP2;
       __syncthreads();  // the LUT space is reused below
       uint32_t* lm = reinterpret_cast<uint32_t*>(lds + L.lmin);
 #pragma unroll
-      for (int g = 0; g < G; ++g) lm[g * kThreads + tid] = lmin[g];
+      for (int g = 0; g < G; ++g) {
+        lm[g * TP + tid] = lmin[g];
+        if (tid + kThreads < TP) lm[g * TP + kThreads + tid] = 0xFFFFFFFFu;
+      }
       __syncthreads();
-      for (int size = 2; size <= kThreads; size <<= 1)
+      for (int size = 2; size <= TP; size <<= 1)
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
-          for (int i = tid; i < G * (kThreads / 2); i += kThreads) {
-            const int g = i / (kThreads / 2), ii = i % (kThreads / 2);
+          for (int i = tid; i < G * (TP / 2); i += kThreads) {
+            const int g = i / (TP / 2), ii = i % (TP / 2);
             const int pos = 2 * ii - (ii & (stride - 1));
             const bool asc = (pos & size) == 0;
-            uint32_t* arr = lm + g * kThreads;
+            uint32_t* arr = lm + g * TP;
             const uint32_t x0 = arr[pos], x1 = arr[pos + stride];
             if ((x0 > x1) == asc) { arr[pos] = x1; arr[pos + stride] = x0; }
           }
@@ -1220,7 +1235,7 @@ __global__ __launch_bounds__(kThreads, LWB == 0 ? 1 : 2) void k_scan(ScanArgs a)
         const int q = pq[tid];
         const int kk = a.kq ? a.kq[q] : a.kconst;
         if (kk <= kThreads) {
-          const uint32_t val = lm[tid * kThreads + kk - 1];
+          const uint32_t val = lm[tid * kThreadsP2 + kk - 1];
           if (val != 0xFFFFFFFFu) {
             uint64_t key;
             if constexpr (FP) key = (uint64_t)val;
