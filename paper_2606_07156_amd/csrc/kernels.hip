@@ -596,6 +596,21 @@ struct Lane {
   static constexpr uint32_t MASK = LWB == 32 || LWB == 0 ? 0xFFFFFFFFu : ((1u << LWB) - 1);
 };
 
+// where pair g of a work unit sits in a LUT row: word and field.  The 8-bit
+// class with four words per row interleaves the pairs (word 2 h + t holds
+// pairs 8 t + 4 h + 0..3) so that a lane of the LUT build writes its two
+// words with one 8-byte store; every other layout is word g / W, field g % W.
+template <int LWB, int WPR>
+struct PairSlot {
+  static constexpr bool IL = LWB == 8 && WPR == 4;
+  static constexpr int W = Lane<LWB>::W;
+  __host__ __device__ static constexpr int word(int g) { return IL ? (((g >> 2) & 1) << 1) | (g >> 3) : g / W; }
+  __host__ __device__ static constexpr int field(int g) { return IL ? (g & 3) : g % W; }
+  __host__ __device__ static constexpr int pair(int w, int f) {
+    return IL ? ((w & 1) << 3) | ((w >> 1) << 2) | f : w * W + f;
+  }
+};
+
 template <int WPR>
 __device__ __forceinline__ void lut_row_load(const uint32_t* lut, int row, uint32_t* w) {
   if constexpr (WPR == 4) {
@@ -645,7 +660,7 @@ __device__ __forceinline__ uint32_t f16_bits(float v) {  // exact inputs only
 // PASS 2: quantise (truncation of the exact non-negative value) and pack.
 // The pass is a template argument so that the 16 x NGT products of an m-pair
 // are independent straight-line code the compiler can overlap.
-template <int LWB, int WPR, int DT, int PASS>
+template <int LWB, int WPR, int DT, int PASS, bool IP>
 __device__ __forceinline__ void lut_mpair(const ScanArgs& a, char* lds, const ScanLds& L, int M, int np_u,
                                           int mp, const u32x4 (&B)[16], const u32x4 (&Bd)[16]) {
   constexpr int pass = PASS;
@@ -662,7 +677,7 @@ __device__ __forceinline__ void lut_mpair(const ScanArgs& a, char* lds, const Sc
   const int row = lane & 15, kg = lane >> 4;
   const int ms_row = row >> 3;
   const int dsub = a.dsub;
-  const bool ip = a.metric == AMP_IP;
+  constexpr bool ip = IP;  // metric as a compile-time flag: no per-value select
   bf16x8 A[NGT];
   u32x4 Ad[NGT];
 #pragma unroll
@@ -722,6 +737,7 @@ __device__ __forceinline__ void lut_mpair(const ScanArgs& a, char* lds, const Sc
       rsc[gt][i] = (DT == DT_BF16 || pass == 1 || g >= np_u) ? 1.f : ldexpf(1.f, -ps[g]);
     }
   int mn[NGT][4], mx[NGT][4];
+  uint32_t wv8[NGT];  // packed words of the interleaved 8-bit layout
 #pragma unroll
   for (int gt = 0; gt < NGT; ++gt)
 #pragma unroll
@@ -756,12 +772,20 @@ __device__ __forceinline__ void lut_mpair(const ScanArgs& a, char* lds, const Sc
           qv[i] = (uint32_t)vv;  // exact and >= 0: truncation = floor
         }
         uint32_t* dst = lut + (size_t)(m_out * kKsub + j) * WPR;
-        if constexpr (LWB == 8) {
+        if constexpr (PairSlot<LWB, WPR>::IL) {
+          wv8[gt] = qv[0] | (qv[1] << 8) | (qv[2] << 16) | (qv[3] << 24);
+          if (gt == NGT - 1)  // words 2 h, 2 h + 1 (h = kg & 1): one 8-byte store
+            *reinterpret_cast<u32x2*>(dst + 2 * (kg & 1)) = (u32x2){wv8[0], wv8[1]};
+        } else if constexpr (LWB == 8) {
           dst[g0 >> 2] = qv[0] | (qv[1] << 8) | (qv[2] << 16) | (qv[3] << 24);
         } else if constexpr (LWB == 16) {
           const int w0 = g0 >> 1;
-          if (w0 < WPR) dst[w0] = qv[0] | (qv[1] << 16);
-          if (w0 + 1 < WPR) dst[w0 + 1] = qv[2] | (qv[3] << 16);
+          if (w0 + 1 < WPR)
+            *reinterpret_cast<u32x2*>(dst + w0) = (u32x2){qv[0] | (qv[1] << 16), qv[2] | (qv[3] << 16)};
+          else if (w0 < WPR)
+            dst[w0] = qv[0] | (qv[1] << 16);
+        } else if constexpr (WPR == 4) {
+          *reinterpret_cast<u32x4*>(dst) = (u32x4){qv[0], qv[1], qv[2], qv[3]};  // g0 == 0 here
         } else {
 #pragma unroll
           for (int i = 0; i < 4; ++i)
@@ -991,8 +1015,9 @@ __global__ __launch_bounds__(kThreads, LWB == 0 ? 1 : 2) void k_scan(ScanArgs a)
       }
       __syncthreads();
       // the 16 B fragments of an m-pair are issued together, then consumed
-      auto build = [&](auto pass_tag) {
+      auto build = [&](auto pass_tag, auto ip_tag) {
         constexpr int PASS = decltype(pass_tag)::value;
+        constexpr bool IPM = decltype(ip_tag)::value;
         for (int mp = wave; mp < M / 2; mp += kThreads / 64) {
           u32x4 Bt[16], Bd[16];
 #pragma unroll
@@ -1002,37 +1027,54 @@ __global__ __launch_bounds__(kThreads, LWB == 0 ? 1 : 2) void k_scan(ScanArgs a)
             if constexpr (DT == DT_F16) Bd[jt] = a.bsw16[fi];
             else Bd[jt] = (u32x4){0u, 0u, 0u, 0u};
           }
-          lut_mpair<LWB, WPR, DT, PASS>(a, lds, L, M, np_u, mp, Bt, Bd);
+          lut_mpair<LWB, WPR, DT, PASS, IPM>(a, lds, L, M, np_u, mp, Bt, Bd);
         }
       };
-      build(std::integral_constant<int, 1>{});
+      using P1 = std::integral_constant<int, 1>;
+      using P2 = std::integral_constant<int, 2>;
+      using IPt = std::integral_constant<bool, true>;
+      using L2t = std::integral_constant<bool, false>;
+      if (ip) build(P1{}, IPt{});
+      else build(P1{}, L2t{});
       __syncthreads();
       {
-        int32_t* lo = reinterpret_cast<int32_t*>(lds + L.lo);
+        // per pair g: shift s, base = sum of the subspace minima (inner
+        // product: minus qi.ci); sixteen threads (a 16-lane row) per pair
+        const int32_t* lo = reinterpret_cast<const int32_t*>(lds + L.lo);
         const int32_t* hi = reinterpret_cast<const int32_t*>(lds + L.hi);
-        if (tid < np_u) {
-          const int g = tid;
-          int64_t R = 0, base = 0;
-          for (int m = 0; m < M; ++m) {
-            const int64_t span = (int64_t)hi[g * M + m] - lo[g * M + m];
-            R = span > R ? span : R;
-            base += lo[g * M + m];
+        const int32_t* rrp = reinterpret_cast<const int32_t*>(lds + L.rr);
+        const int g = tid >> 4, r = tid & 15;
+        int32_t span = 0;
+        int64_t bsum = 0;
+        if (g < np_u)
+          for (int m = r; m < M; m += 16) {
+            const int32_t l = lo[g * M + m], h = hi[g * M + m];
+            span = h - l > span ? h - l : span;
+            bsum += l - (ip ? rrp[g * M + m] : 0);
           }
-          if (ip) {
-            const int32_t* rrp = reinterpret_cast<const int32_t*>(lds + L.rr);
-            for (int m = 0; m < M; ++m) base -= rrp[g * M + m];  // -qi.ci
-          }
-          const int64_t top = (1ll << pb[g]) - 1;
-          int s = 0;
-          while (((R + (s ? (1ll << (s - 1)) : 0)) >> s) > top) ++s;
-          const int32_t hf = s ? (1 << (s - 1)) : 0;
-          for (int m = 0; m < M; ++m) lo[g * M + m] = hf - lo[g * M + m];  // -> off
-          ps[g] = s;
-          pbase[g] = base;
+        span = row16_reduce<true>(span);
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) bsum += __shfl_xor(bsum, off, 16);
+        if (r == 15 && g < np_u) {
+          const int64_t top = (1ll << pb[g]) - 1, R = span;
+          int sh = 0;
+          while (((R + (sh ? (1ll << (sh - 1)) : 0)) >> sh) > top) ++sh;
+          ps[g] = sh;
+          pbase[g] = bsum;
         }
       }
       __syncthreads();
-      build(std::integral_constant<int, 2>{});
+      {
+        // lo -> the offset hf(s) - lo that pass 2 adds before the shift
+        int32_t* lo = reinterpret_cast<int32_t*>(lds + L.lo);
+        for (int e = tid; e < np_u * M; e += kThreads) {
+          const int g = e / M, sh = ps[g];
+          lo[e] = (sh ? (1 << (sh - 1)) : 0) - lo[e];
+        }
+      }
+      __syncthreads();
+      if (ip) build(P2{}, IPt{});
+      else build(P2{}, L2t{});
       __syncthreads();
     }
     // ---- per-pair pruning threshold in the lane domain (phase 2)
@@ -1080,7 +1122,7 @@ __global__ __launch_bounds__(kThreads, LWB == 0 ? 1 : 2) void k_scan(ScanArgs a)
         uint32_t se = 0, so = 0, me = 0, mo = 0;
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
-          const int g = 4 * w + f;
+          const int g = PairSlot<LWB, WPR>::pair(w, f);
           const uint32_t sg = live[g] ? (sig[g] > 255u ? 255u : sig[g]) : 255u;
           const uint32_t gb = live[g] ? 0x100u : 0u;
           if (f & 1) { so |= (sg | 0x100u) << (16 * (f >> 1)); mo |= gb << (16 * (f >> 1)); }
@@ -1163,14 +1205,15 @@ __global__ __launch_bounds__(kThreads, LWB == 0 ? 1 : 2) void k_scan(ScanArgs a)
               for (int f = 0; f < 4; ++f) {
                 // rare path: thresholds from LDS, not held in registers
                 const uint32_t S = (acc[w] >> (8 * f)) & 0xFFu;
-                if (pb[4 * w + f] >= 0 && S <= psig[4 * w + f]) emit(4 * w + f, S);
+                const int g = PairSlot<LWB, WPR>::pair(w, f);
+                if (pb[g] >= 0 && S <= psig[g]) emit(g, S);
               }
             }
           }
         } else {
 #pragma unroll
           for (int g = 0; g < G; ++g) {
-            const int w = g / W, f = g % W;
+            const int w = PairSlot<LWB, WPR>::word(g), f = PairSlot<LWB, WPR>::field(g);
             uint32_t S;
             if constexpr (FP) S = fkey(accf[w]);
             else S = LWB == 32 ? acc[w] : ((acc[w] >> (f * LWB)) & MASK);
