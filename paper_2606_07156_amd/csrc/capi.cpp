@@ -672,6 +672,30 @@ amp_status amp_search(amp_index* ix, const float* queries, int64_t nq, const int
     uint32_t mx = 0;
     for (uint32_t c : cc) sum += c, mx = std::max(mx, c);
     fprintf(stderr, "[amp] candidates per query: mean %.1f max %u (capacity %zu)\n", sum / nq, mx, capq);
+    // pairs, work units and scanned vectors per phase and lane class
+    const int ncls = pol->kind == AMP_POLICY_FP32 ? 1 : kNCls;
+    const size_t NB = (size_t)ncls * ix->nlist;
+    std::vector<int64_t> po(2 * (NB + 1)), uo(2 * (NB + 1));
+    AMP_HIP(hipMemcpy(po.data(), w.pairoff, po.size() * 8, hipMemcpyDeviceToHost));
+    AMP_HIP(hipMemcpy(uo.data(), w.unitoff, uo.size() * 8, hipMemcpyDeviceToHost));
+    std::vector<int32_t> order(ix->nlist);
+    AMP_HIP(hipMemcpy(order.data(), ix->dev.lorder, order.size() * 4, hipMemcpyDeviceToHost));
+    for (int ph = 0; ph < 2; ++ph)
+      for (int c = 0; c < ncls; ++c) {
+        const int64_t* P = po.data() + ph * (NB + 1);
+        const int64_t* U = uo.data() + ph * (NB + 1);
+        int64_t vec = 0, maxl = 0;
+        for (int b = 0; b < ix->nlist; ++b) {
+          const int64_t nu = U[c * ix->nlist + b + 1] - U[c * ix->nlist + b];
+          const int32_t p = order[b];
+          const int64_t len = ix->offsets[p + 1] - ix->offsets[p];
+          vec += nu * len;
+          if (nu) maxl = std::max(maxl, len);
+        }
+        fprintf(stderr, "[amp] phase %d class %d: pairs %lld units %lld unit-vectors %lld longest list %lld\n", ph + 1,
+                c, (long long)(P[(c + 1) * ix->nlist] - P[c * ix->nlist]),
+                (long long)(U[(c + 1) * ix->nlist] - U[c * ix->nlist]), (long long)vec, (long long)maxl);
+      }
   }
   if (flags[0] & 8) return set_error(AMP_EDEVICE, "internal error: a work unit exceeded the scan tile");
   if (flags[0] & 4) return set_error(AMP_EOVERFLOW, "work-unit table overflowed");

@@ -440,14 +440,19 @@ __global__ __launch_bounds__(1024) void k_qscan(QueueArgs a, int fp32) {
       const int64_t nch = (n + a.chunk[ph] - 1) / a.chunk[ph];
       const int G = class_pairs(cls, a.wpr, fp32);
       // bucket total; the sub-counters become their offsets inside the bucket
+      // (all loads issued before the stores, which the compiler cannot move)
+      int x[kQSub];
+#pragma unroll
+      for (int u = 0; u < kQSub; ++u) x[u] = cnt[(size_t)u * NB + cls * a.nlist + p];
       int c = 0;
 #pragma unroll
       for (int u = 0; u < kQSub; ++u) {
-        int32_t* cu = cnt + (size_t)u * NB + cls * a.nlist + p;
-        const int x = *cu;
-        *cu = c;
-        c += x;
+        const int xu = x[u];
+        x[u] = c;
+        c += xu;
       }
+#pragma unroll
+      for (int u = 0; u < kQSub; ++u) cnt[(size_t)u * NB + cls * a.nlist + p] = x[u];
       po[b] = c;  // kept for the second sweep
       sp += c;
       su += ((c + G - 1) / G) * nch;
@@ -823,9 +828,12 @@ struct Owned {
   float c[NM][kMaxDsub];
 };
 
-template <int LWB, int MT, int PHASE, int DT>
-__global__ __launch_bounds__(kThreads, LWB == 0 ? 1 : 2) void k_scan(ScanArgs a) {
-  extern __shared__ __attribute__((aligned(16))) char lds[];
+// One work unit (G pairs of one list, lane class LWB; 0 = FP32 LUT): RC, LC,
+// quantisation, DC scan, and the phase's bound or candidate forwarding.
+// L may be the layout of a larger tile (the mixed-class kernel).
+template <int LWB, int MT, int PHASE, int DT, typename Own, typename Fetch>
+__device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const ScanLds& L, const Own& own,
+                                          const int4 unit, Fetch&& fetch_next) {
   constexpr int WPR = kernel_wpr(MT);
   constexpr bool FP = LWB == 0;
   constexpr int W = Lane<LWB>::W;
@@ -833,54 +841,27 @@ __global__ __launch_bounds__(kThreads, LWB == 0 ? 1 : 2) void k_scan(ScanArgs a)
   constexpr uint32_t MASK = Lane<LWB>::MASK;
   constexpr bool CRES = FP && MT != 0 && MT <= 16;  // FP32 codewords stay in registers
   const int M = MT ? MT : a.M;
-  const ScanLds L = scan_lds_layout(G, WPR, M, a.d, FP, PHASE);
-  __shared__ int s_u;
-  __shared__ int4 s_unit;
   int32_t* pq = reinterpret_cast<int32_t*>(lds + L.pq);
   int32_t* pb = reinterpret_cast<int32_t*>(lds + L.pb);
   int32_t* ps = reinterpret_cast<int32_t*>(lds + L.ps);
   int64_t* pbase = reinterpret_cast<int64_t*>(lds + L.pbase);
   uint32_t* psig = reinterpret_cast<uint32_t*>(lds + L.psig);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t ub = a.unitoff[(size_t)a.cls * a.nlist];
-  const int64_t ue = a.unitoff[(size_t)(a.cls + 1) * a.nlist];
   const int own_j = tid % kKsub, own_m0 = tid / kKsub;
   const bool owner = tid < kMPar * kKsub;
-  Owned<WPR, CRES ? MT : 0> own;
-  if constexpr (CRES) {
-#pragma unroll
-    for (int i = 0; i < MT / kMPar; ++i)
-#pragma unroll
-      for (int t = 0; t < kMaxDsub; ++t)
-        own.c[i][t] = owner && t < a.dsub
-                          ? a.codebook[((size_t)(kMPar * i + own_m0) * kKsub + own_j) * a.dsub + t] : 0.f;
-  }
-  // the next unit is claimed while the current one is processed: its index
-  // at the start, its descriptor before the scan, published at the end
-  if (tid == 0) {
-    const int uu = (int)atomicAdd(a.counter, 1u);
-    s_u = uu;
-    if (ub + uu < ue) s_unit = a.units[ub + uu];
-  }
-  __syncthreads();
-  for (;;) {
-    if (ub + s_u >= ue) break;
-    int next_u = 0;
-    int4 next_unit = make_int4(0, 0, 0, 0);
-    if (tid == 0) next_u = (int)atomicAdd(a.counter, 1u);
-    const int p = s_unit.x;
-    int np_u = s_unit.z;
+    const int p = unit.x;
+    int np_u = unit.z;
     if (np_u > G) {  // a unit never holds more pairs than the tile (guarded, flagged)
       if (tid == 0) atomicOr(&a.flags[0], 8);
       np_u = G;
     }
     const int64_t L0 = a.offsets[p];
     const int64_t n_list = a.offsets[p + 1] - L0;
-    const int64_t v0 = (int64_t)s_unit.w * a.chunk;
+    const int64_t v0 = (int64_t)unit.w * a.chunk;
     const int64_t v1 = v0 + a.chunk < n_list ? v0 + a.chunk : n_list;
     if (tid < G) {
       if (tid < np_u) {
-        const int pid = a.sorted[s_unit.y + tid];
+        const int pid = a.sorted[unit.y + tid];
         pq[tid] = pid / a.npmax;
         pb[tid] = a.pbits[pid];
       } else {
@@ -1144,7 +1125,7 @@ __global__ __launch_bounds__(kThreads, LWB == 0 ? 1 : 2) void k_scan(ScanArgs a)
         }
       }
     }
-    if (tid == 0 && ub + next_u < ue) next_unit = a.units[ub + next_u];
+    fetch_next();  // the next unit's descriptor, read while this one scans
     for (int64_t vb = v0; vb < v1; vb += kThreads) {
       const int64_t v = vb + tid;
       uint32_t cw[MQ];
@@ -1288,10 +1269,112 @@ __global__ __launch_bounds__(kThreads, LWB == 0 ? 1 : 2) void k_scan(ScanArgs a)
         }
       }
     }
+}
+
+// persistent scan of one lane class: workgroups claim units of their class
+// from a device counter; the next unit is claimed while the current one is
+// processed (index at the start, descriptor before the scan, published at
+// the end)
+template <int LWB, int MT, int PHASE, int DT>
+__global__ __launch_bounds__(kThreads, LWB == 0 ? 1 : 2) void k_scan(ScanArgs a) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  constexpr int WPR = kernel_wpr(MT);
+  constexpr bool FP = LWB == 0;
+  constexpr int G = WPR * Lane<LWB>::W;
+  constexpr bool CRES = FP && MT != 0 && MT <= 16;
+  const int M = MT ? MT : a.M;
+  const ScanLds L = scan_lds_layout(G, WPR, M, a.d, FP, PHASE);
+  __shared__ int s_u;
+  __shared__ int4 s_unit;
+  const int tid = threadIdx.x;
+  const int64_t ub = a.unitoff[(size_t)a.cls * a.nlist];
+  const int64_t ue = a.unitoff[(size_t)(a.cls + 1) * a.nlist];
+  const int own_j = tid % kKsub, own_m0 = tid / kKsub;
+  const bool owner = tid < kMPar * kKsub;
+  Owned<WPR, CRES ? MT : 0> own;
+  if constexpr (CRES) {
+#pragma unroll
+    for (int i = 0; i < MT / kMPar; ++i)
+#pragma unroll
+      for (int t = 0; t < kMaxDsub; ++t)
+        own.c[i][t] = owner && t < a.dsub
+                          ? a.codebook[((size_t)(kMPar * i + own_m0) * kKsub + own_j) * a.dsub + t] : 0.f;
+  }
+  if (tid == 0) {
+    const int uu = (int)atomicAdd(a.counter, 1u);
+    s_u = uu;
+    if (ub + uu < ue) s_unit = a.units[ub + uu];
+  }
+  __syncthreads();
+  for (;;) {
+    if (ub + s_u >= ue) break;
+    int next_u = 0;
+    int4 next_unit = make_int4(0, 0, 0, 0);
+    if (tid == 0) next_u = (int)atomicAdd(a.counter, 1u);
+    scan_unit<LWB, MT, PHASE, DT>(a, lds, L, own, s_unit, [&] {
+      if (tid == 0 && ub + next_u < ue) next_unit = a.units[ub + next_u];
+    });
     __syncthreads();
     if (tid == 0) {
       s_u = next_u;
       s_unit = next_unit;
+    }
+    __syncthreads();
+  }
+}
+
+// all three lane classes of an integer policy in one persistent launch, in
+// the order 32-bit, 16-bit, 8-bit units (each largest list first): the few
+// wide units start early and the many 8-bit units fill the tail.  The LDS
+// tile of the 8-bit class (the most pairs per unit) serves every class.
+template <int MT, int PHASE, int DT>
+__global__ __launch_bounds__(kThreads, 2) void k_scan_mix(ScanArgs a) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  constexpr int WPR = kernel_wpr(MT);
+  const int M = MT ? MT : a.M;
+  const ScanLds L = scan_lds_layout(WPR * Lane<8>::W, WPR, M, a.d, false, PHASE);
+  __shared__ int s_u, s_cls;
+  __shared__ int4 s_unit;
+  const int tid = threadIdx.x;
+  const int64_t* uo = a.unitoff;
+  const int64_t n2 = uo[3 * (size_t)a.nlist] - uo[2 * (size_t)a.nlist];
+  const int64_t n1 = uo[2 * (size_t)a.nlist] - uo[a.nlist];
+  const int64_t total = uo[3 * (size_t)a.nlist] - uo[0];
+  // unit number in launch order -> (class, row of the class-major unit table)
+  auto locate = [&](int64_t u, int& cls) -> int64_t {
+    if (u < n2) { cls = 2; return uo[2 * (size_t)a.nlist] + u; }
+    if (u < n2 + n1) { cls = 1; return uo[a.nlist] + (u - n2); }
+    cls = 0;
+    return uo[0] + (u - n2 - n1);
+  };
+  Owned<WPR, 0> own;
+  if (tid == 0) {
+    const int uu = (int)atomicAdd(a.counter, 1u);
+    s_u = uu;
+    if (uu < total) {
+      int c;
+      s_unit = a.units[locate(uu, c)];
+      s_cls = c;
+    }
+  }
+  __syncthreads();
+  for (;;) {
+    if (s_u >= total) break;
+    int next_u = 0, next_cls = 0;
+    int4 next_unit = make_int4(0, 0, 0, 0);
+    if (tid == 0) next_u = (int)atomicAdd(a.counter, 1u);
+    auto fetch = [&] {
+      if (tid == 0 && next_u < total) next_unit = a.units[locate(next_u, next_cls)];
+    };
+    const int cls = s_cls;
+    if (cls == 0) scan_unit<8, MT, PHASE, DT>(a, lds, L, own, s_unit, fetch);
+    else if (cls == 1) scan_unit<16, MT, PHASE, DT>(a, lds, L, own, s_unit, fetch);
+    else scan_unit<32, MT, PHASE, DT>(a, lds, L, own, s_unit, fetch);
+    __syncthreads();
+    if (tid == 0) {
+      s_u = next_u;
+      s_unit = next_unit;
+      s_cls = next_cls;
     }
     __syncthreads();
   }
@@ -1494,13 +1577,28 @@ static ScanFn pick_scan(int lwb, int M, int ph, int dt) {
   return nullptr;
 }
 
+template <int MT, int PH, int DT>
+static ScanFn mix_fn() { return k_scan_mix<MT, PH, DT>; }
+
+// the mixed-class variant of the same specialisation as pick_scan's
+static ScanFn pick_mix(int M, int ph, int dt) {
+  const int mt = scan_mt(8, M, dt);
+  if (dt == DT_F16) return ph == 1 ? mix_fn<0, 1, DT_F16>() : mix_fn<0, 2, DT_F16>();
+  if (mt == 8) return ph == 1 ? mix_fn<8, 1, DT_BF16>() : mix_fn<8, 2, DT_BF16>();
+  if (mt == 16) return ph == 1 ? mix_fn<16, 1, DT_BF16>() : mix_fn<16, 2, DT_BF16>();
+  if (mt == 24) return ph == 1 ? mix_fn<24, 1, DT_BF16>() : mix_fn<24, 2, DT_BF16>();
+  return ph == 1 ? mix_fn<0, 1, DT_BF16>() : mix_fn<0, 2, DT_BF16>();
+}
+
 static int g_num_cu = 0;
 
+// lwb < 0: every integer lane class in one launch (k_scan_mix)
 static hipError_t launch_scan(int lwb, int ph, int dt, int wpr, const ScanArgs& sa, hipStream_t st) {
-  ScanFn fn = pick_scan(lwb, sa.M, ph, dt);
+  const bool mix = lwb < 0;
+  ScanFn fn = mix ? pick_mix(sa.M, ph, dt) : pick_scan(lwb, sa.M, ph, dt);
   // the queue packed units for `wpr` words per row: the variant must agree
-  if (!fn || kernel_wpr(scan_mt(lwb, sa.M, dt)) != wpr) return hipErrorInvalidValue;
-  const size_t lds = scan_lds_bytes(lwb, ph, sa.M, sa.d, wpr);
+  if (!fn || kernel_wpr(scan_mt(mix ? 8 : lwb, sa.M, dt)) != wpr) return hipErrorInvalidValue;
+  const size_t lds = scan_lds_bytes(mix ? 8 : lwb, ph, sa.M, sa.d, wpr);
   hipError_t e = hipFuncSetAttribute(kaddr(fn), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   int per_cu = 0;
@@ -1654,10 +1752,16 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
     sa.unitoff = ws.unitoff + (ph == 2 ? (NB + 1) : 0);
     sa.units = ws.units + (ph == 2 ? sd.max_units : 0);
     sa.chunk = ph == 2 ? sd.chunk : sd.chunk1;
-    for (int c = 0; c < ncls; ++c) {
+    if (fp32 || sd.policy == AMP_POLICY_FIXED) {
+      // one lane class holds every pair: its own kernel
+      const int c = fp32 ? 0 : lane_class(sd.M, sd.fixed_bits);
       sa.cls = c;
       sa.counter = ws.counters + (ph - 1) * (kNCls + 1) + c;
       if ((err = launch_scan(fp32 ? 0 : lane_bits(c), ph, dt, sd.wpr, sa, st)) != hipSuccess) return err;
+    } else {
+      sa.cls = -1;
+      sa.counter = ws.counters + (ph - 1) * (kNCls + 1) + kNCls;
+      if ((err = launch_scan(-1, ph, dt, sd.wpr, sa, st)) != hipSuccess) return err;
     }
     mark(4 + ph);
   }
