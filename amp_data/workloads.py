@@ -43,3 +43,29 @@ def load_or_build(name, cache_dir=DEFAULT_CACHE, log=None):
         np.savez(tmp, base=base, **idx)
         os.replace(tmp, cache)
     return w, base, idx
+
+
+def replicate(idx, copies):
+    """An index whose every list holds `copies` copies of the original list
+    (ids of copy c offset by c * N): the same clusters and codes at `copies`
+    times the size, for measurements on a working set larger than the GPU's
+    last-level cache.  Duplicate vectors tie in distance; results are not
+    meant for recall."""
+    offs = np.asarray(idx["list_offsets"], np.int64)
+    ids = np.asarray(idx["ids"], np.int64)
+    codes = np.asarray(idx["codes"])
+    n = len(ids)
+    sizes = np.diff(offs)
+    new_offs = np.concatenate([[0], np.cumsum(sizes * copies)]).astype(np.int64)
+    new_ids = np.empty(n * copies, np.int64)
+    new_codes = np.empty((n * copies, codes.shape[1]), codes.dtype)
+    for p in range(len(sizes)):
+        a, b = offs[p], offs[p + 1]
+        o = new_offs[p]
+        for c in range(copies):
+            new_ids[o + c * (b - a): o + (c + 1) * (b - a)] = ids[a:b] + c * n
+            new_codes[o + c * (b - a): o + (c + 1) * (b - a)] = codes[a:b]
+    out = dict(idx)
+    out.update(list_offsets=new_offs, ids=new_ids, codes=new_codes,
+               list_sizes=(sizes * copies).astype(np.int32))
+    return out

@@ -23,6 +23,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_MFMA_TFLOPS = 157.3
+BF16_MFMA_TFLOPS = 2500.0
 # 32-bit VALU lane operations: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_scan_mid_traffic.json")
@@ -97,6 +99,9 @@ def main():
     ap.add_argument("--recall-queries", type=int, default=200,
                     help="queries checked against exact kNN (0: skip; profiling runs)")
     ap.add_argument("--cache-dir", default="/tmp/amp_bench_cache")
+    ap.add_argument("--replicate", type=int, default=0,
+                    help="R > 1: every list R times larger (working set beyond the last-level cache; "
+                         "use with a small --nq for the streaming regime)")
     ap.add_argument("--graph", type=int, default=1,
                     help="1: timed searches replay a captured HIP graph (0: plain launches)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
@@ -126,6 +131,16 @@ def main():
     w, base, idx = load_or_build(args.workload, args.cache_dir, log=lambda m: log("[bench] " + m))
     if args.nq:
         w = w.scaled(nq=args.nq)
+    if args.replicate > 1:
+        # streaming regime: every list `replicate` times larger, no recall
+        from amp_data.workloads import replicate
+        import dataclasses
+        idx = replicate(idx, args.replicate)
+        w = dataclasses.replace(w, n=w.n * args.replicate)
+        args.recall_queries = 0
+        args.no_cpu = True
+        log(f"[bench] replicated every list {args.replicate}x: {len(idx['ids'])} vectors, "
+            f"{idx['codes'].nbytes / 1e6:.0f} MB of codes")
     log(f"[bench] list sizes min/mean/max {idx['list_sizes'].min()}/{idx['list_sizes'].mean():.0f}/"
         f"{idx['list_sizes'].max()}")
     Q = make_queries(w)
@@ -217,6 +232,25 @@ def main():
     achieved = r["scan_ops"] / (scan_ms / 1e3) / 1e12
     traffic = measured_traffic()
     fp = results.get("fp32")
+    # the two dense contractions on MFMA: CL (FP32 MFMA) and the LUT build
+    # (BF16 MFMA, fused into the scan kernels: rate over the scan stages, a
+    # lower bound on its own utilisation)
+    st_h = r["stages"]
+    n_pairs = float(nq) * nprobe
+    cl_flops = 2.0 * nq * w.nlist * w.d
+    lc_flops = n_pairs * 2.0 * 256 * w.d
+    cl_tf = cl_flops / (st_h["cl"] / 1e3) / 1e12
+    lc_tf = lc_flops / ((st_h["scan1"] + st_h["scan2"]) / 1e3) / 1e12
+    mfma_use = {"cl": {"flop_per_search": cl_flops, "tflops": round(cl_tf, 2), "peak": FP32_MFMA_TFLOPS,
+                       "frac": round(cl_tf / FP32_MFMA_TFLOPS, 4)},
+                "lc": {"flop_per_search": lc_flops, "tflops_over_scan": round(lc_tf, 2), "peak": BF16_MFMA_TFLOPS,
+                       "frac": round(lc_tf / BF16_MFMA_TFLOPS, 4)}}
+    # end-to-end QPS against reading every probed list's codes once per query
+    # from HBM (no reuse) at peak bandwidth
+    bytes_per_q = r["code_bytes"] / nq
+    hbm_q = HBM_PEAK_GBS * 1e9 / bytes_per_q
+    hbm_bound = {"code_bytes_per_query": round(bytes_per_q), "qps_at_hbm_peak": round(hbm_q),
+                 "frac": round(r["qps"] / hbm_q, 4)}
     line = {
         "metric": "QPS at recall@10 (adaptive vs full-precision, same GPU); p99 latency",
         "value": round(r["qps"], 1),
@@ -231,7 +265,9 @@ def main():
         "dtype": "int32" if head != "fp32" else "f32",
         "data": "synthetic",
         "config": {"workload": f"{w.name}: {w.n}x{w.d} integer-valued Gaussian mixture ({w.n_comp} components), "
-                               f"IVF{w.nlist}/PQ{w.M}x256, {nq} queries per step, nprobe {nprobe}, k {k}",
+                               f"IVF{w.nlist}/PQ{w.M}x256, {nq} queries per step, nprobe {nprobe}, k {k}"
+                               + (f"; every list replicated {args.replicate}x (streaming regime)"
+                                  if args.replicate > 1 else ""),
                    "policy": head,
                    "launch": "HIP graph replay" if args.graph else "kernel launches",
                    "recall_at_10": round(r["recall1"], 4),
@@ -246,6 +282,8 @@ def main():
                                     "10_recall_at_10": round(x["recall10"], 4), "ms": round(x["ms"], 4),
                                     "scan_ms": round(x["stages"]["scan2"], 4)}
                                 for n, x in results.items()}},
+        "mfma": mfma_use,
+        "hbm_bound": hbm_bound,
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
                      "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": traffic,
                      "kernel": "k_scan phase 2 (LUT build + quantise + scan), all width classes",

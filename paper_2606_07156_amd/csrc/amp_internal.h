@@ -111,12 +111,13 @@ struct GraphKey {
   uint64_t ws_gen, model_gen;
   int64_t chunk, chunk1;
   size_t capq;
+  int32_t wpr;
   bool operator==(const GraphKey& o) const {
     return q == o.q && ids == o.ids && dist == o.dist && qdist == o.qdist && probes == o.probes &&
            bits == o.bits && coarse == o.coarse && stream == o.stream && nq == o.nq && k == o.k &&
            nprobe == o.nprobe && kind == o.kind && fixed_bits == o.fixed_bits && allowed == o.allowed &&
            margin == o.margin && lut_dtype == o.lut_dtype && ws_gen == o.ws_gen && model_gen == o.model_gen &&
-           chunk == o.chunk && chunk1 == o.chunk1 && capq == o.capq;
+           chunk == o.chunk && chunk1 == o.chunk1 && capq == o.capq && wpr == o.wpr;
   }
 };
 }  // namespace amp
@@ -192,6 +193,6 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
                          hipStream_t st, hipEvent_t* ev /* [AMP_N_STAGES+1] or null */);
 // LUT words per row of the scan variants a search runs (the queue packs its
 // work units to match)
-int scan_wpr(int M, bool fp32, int lut_dtype);
+int scan_wpr(int M, bool fp32, int lut_dtype, bool narrow);
 
 }  // namespace amp

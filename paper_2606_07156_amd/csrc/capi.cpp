@@ -515,12 +515,21 @@ amp_status amp_search(amp_index* ix, const float* queries, int64_t nq, const int
   // keys in place, 16 bytes each in LDS: at most 8192), at least kmax
   size_t capq = 16;
   while ((capq < env_size("AMP_CAPQ", 4096) || capq < (size_t)kmax) && capq < (1u << 13)) capq <<= 1;
-  // list chunk of a work unit (AMP_CHUNK for phase 2, AMP_CHUNK1 for the
-  // phase-1 bound).  Whole lists by default: each chunk rebuilds its pairs'
-  // LUTs, and a chunked phase 1 gives a looser bound (measured slower on the
-  // mid workload for chunks of 1024-4096)
-  const int64_t chunk = std::max<int64_t>(1, (int64_t)env_size("AMP_CHUNK", 1 << 16));
-  const int64_t chunk1 = std::max<int64_t>(1, (int64_t)env_size("AMP_CHUNK1", 1 << 16));
+  // list chunk of a work unit, phase 2 and the phase-1 bound.  Whole lists
+  // when the batch has enough units to fill the chip (each chunk rebuilds
+  // its pairs' LUTs, and a chunked phase 1 gives a looser bound); otherwise
+  // (few queries, long lists: the streaming case) chunks sized for about four
+  // (phase 2) or two (phase 1) units per workgroup slot of the chip, at least
+  // 4096 vectors.  AMP_CHUNK / AMP_CHUNK1 override.
+  const int64_t mean_list = std::max<int64_t>(1, ix->n / ix->nlist);
+  const int64_t slots = 512;  // persistent workgroups: 256 CUs x 2
+  auto pick_chunk = [&](int64_t pairs, int64_t per_slot, const char* env) -> int64_t {
+    const int64_t c = (int64_t)env_size(env, 0);
+    if (c > 0) return c;
+    return std::min<int64_t>(1 << 16, std::max<int64_t>(4096, pairs * mean_list / (per_slot * slots)));
+  };
+  const int64_t chunk = pick_chunk((int64_t)nq * npmax, 4, "AMP_CHUNK");
+  const int64_t chunk1 = pick_chunk((int64_t)nq, 2, "AMP_CHUNK1");
   const int64_t max_nch = std::max<int64_t>(1, (ix->max_list + chunk - 1) / chunk);
   const int64_t max_nch1 = std::max<int64_t>(1, (ix->max_list + chunk1 - 1) / chunk1);
   const int64_t max_units = std::max<int64_t>((int64_t)nq * npmax * max_nch, (int64_t)nq * max_nch1);
@@ -557,7 +566,14 @@ amp_status amp_search(amp_index* ix, const float* queries, int64_t nq, const int
   sd.grid_e = ix->grid_e;
   sd.kconst = per_query ? 0 : k[0];
   sd.npconst = per_query ? 0 : nprobe[0];
-  sd.wpr = scan_wpr(ix->M, pol->kind == AMP_POLICY_FP32, pol->lut_dtype);
+  // a batch with few pairs per list (a few queries: the streaming case) fills
+  // one-word LUT rows: wider rows would multiply LDS traffic per vector
+  // (AMP_NARROW=0/1 forces the choice)
+  {
+    const char* nv = getenv("AMP_NARROW");
+    const bool narrow = nv && *nv ? nv[0] == '1' : (int64_t)nq * npmax < 4 * (int64_t)ix->nlist;
+    sd.wpr = scan_wpr(ix->M, pol->kind == AMP_POLICY_FP32, pol->lut_dtype, narrow);
+  }
   sd.chunk = chunk;
   sd.chunk1 = chunk1;
   sd.max_units = w.cap_units;
@@ -614,7 +630,7 @@ amp_status amp_search(amp_index* ix, const float* queries, int64_t nq, const int
     // one captured graph per index, replayed while the launch key is unchanged
     GraphKey key{qdev, out_ids, out_dist, opts->out_qdist, opts->out_probes, opts->out_bits, opts->out_coarse,
                  st, nq, k[0], nprobe[0], pol->kind, pol->fixed_bits, sd.allowed_mask, pol->margin_q40,
-                 pol->lut_dtype, ix->ws_generation, ix->model_generation, chunk, chunk1, capq};
+                 pol->lut_dtype, ix->ws_generation, ix->model_generation, chunk, chunk1, capq, sd.wpr};
     if (!ix->graph_exec || !(ix->graph_key == key)) {
       if (ix->graph_exec) hipGraphExecDestroy(ix->graph_exec);
       ix->graph_exec = nullptr;
@@ -697,6 +713,7 @@ amp_status amp_search(amp_index* ix, const float* queries, int64_t nq, const int
                 (long long)(U[(c + 1) * ix->nlist] - U[c * ix->nlist]), (long long)vec, (long long)maxl);
       }
   }
+  if (flags[0] & 16) return set_error(AMP_EDEVICE, "internal error: scan kernel with static LDS");
   if (flags[0] & 8) return set_error(AMP_EDEVICE, "internal error: a work unit exceeded the scan tile");
   if (flags[0] & 4) return set_error(AMP_EOVERFLOW, "work-unit table overflowed");
   if (flags[0]) return set_error(AMP_EOVERFLOW, "candidate buffer of %zu entries overflowed", capq);

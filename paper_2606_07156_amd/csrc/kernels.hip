@@ -423,70 +423,89 @@ __global__ void k_qhist(QueueArgs a) {
   if (i % a.npmax == 0) a.rank[i] = atomicAdd(&a.cnt[b], 1);
 }
 
-// exclusive scans of pair and unit counts, one workgroup of 1024 threads
+// per (phase, class, list) bucket: its pair total from the sub-counters
+// (which become offsets inside the bucket) and its unit count, stored at the
+// bucket's launch position (pairoff / unitoff hold counts until k_qscan)
+__global__ void k_qtot(QueueArgs a, int fp32) {
+  const int NB = a.ncls * a.nlist;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * NB) return;
+  const int ph = i / NB, b = i % NB, cls = b / a.nlist, p = b % a.nlist;
+  int32_t* cnt = a.cnt + (size_t)ph * kQSub * NB;
+  int x[kQSub];
+#pragma unroll
+  for (int u = 0; u < kQSub; ++u) x[u] = cnt[(size_t)u * NB + b];
+  int c = 0;
+#pragma unroll
+  for (int u = 0; u < kQSub; ++u) {
+    const int xu = x[u];
+    x[u] = c;
+    c += xu;
+  }
+#pragma unroll
+  for (int u = 0; u < kQSub; ++u) cnt[(size_t)u * NB + b] = x[u];
+  const int64_t n = a.offsets[p + 1] - a.offsets[p];
+  const int64_t nch = (n + a.chunk[ph] - 1) / a.chunk[ph];
+  const int G = class_pairs(cls, a.wpr, fp32);
+  const int pos = cls * a.nlist + a.lpos[p];
+  a.pairoff[(size_t)ph * (NB + 1) + pos] = c;
+  a.unitoff[(size_t)ph * (NB + 1) + pos] = ((c + G - 1) / G) * nch;
+}
+
+// inclusive scan of one int64 over a 1024-thread workgroup (wave scans, then
+// a scan of the 16 wave totals)
+__device__ __forceinline__ int64_t block_scan_1024(int64_t v, int64_t* s_w) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int64_t o = __shfl_up(v, off);
+    if (lane >= off) v += o;
+  }
+  if (lane == 63) s_w[wv] = v;
+  __syncthreads();
+  if (wv == 0) {
+    int64_t t = lane < 16 ? s_w[lane] : 0;
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) {
+      const int64_t o = __shfl_up(t, off);
+      if (lane >= off) t += o;
+    }
+    if (lane < 16) s_w[lane] = t;
+  }
+  __syncthreads();
+  const int64_t r = v + (wv ? s_w[wv - 1] : 0);
+  __syncthreads();  // s_w is reused by the next scan
+  return r;
+}
+
+// exclusive scans of the pair and unit counts in launch order, one
+// workgroup of 1024 threads, each a contiguous run of positions
 __global__ __launch_bounds__(1024) void k_qscan(QueueArgs a, int fp32) {
-  __shared__ int64_t s_part[2][1024];
+  __shared__ int64_t s_w[16];
   const int NB = a.ncls * a.nlist;
   const int per = (NB + 1023) / 1024;
   for (int ph = 0; ph < 2; ++ph) {
-    int32_t* cnt = a.cnt + (size_t)ph * kQSub * NB;
     int64_t* po = a.pairoff + (size_t)ph * (NB + 1);
     int64_t* uo = a.unitoff + (size_t)ph * (NB + 1);
     const int b0 = threadIdx.x * per;
     int64_t sp = 0, su = 0;
     for (int b = b0; b < b0 + per && b < NB; ++b) {
-      const int cls = b / a.nlist, p = a.lorder[b % a.nlist];
-      const int64_t n = a.offsets[p + 1] - a.offsets[p];
-      const int64_t nch = (n + a.chunk[ph] - 1) / a.chunk[ph];
-      const int G = class_pairs(cls, a.wpr, fp32);
-      // bucket total; the sub-counters become their offsets inside the bucket
-      // (all loads issued before the stores, which the compiler cannot move)
-      int x[kQSub];
-#pragma unroll
-      for (int u = 0; u < kQSub; ++u) x[u] = cnt[(size_t)u * NB + cls * a.nlist + p];
-      int c = 0;
-#pragma unroll
-      for (int u = 0; u < kQSub; ++u) {
-        const int xu = x[u];
-        x[u] = c;
-        c += xu;
-      }
-#pragma unroll
-      for (int u = 0; u < kQSub; ++u) cnt[(size_t)u * NB + cls * a.nlist + p] = x[u];
-      po[b] = c;  // kept for the second sweep
-      sp += c;
-      su += ((c + G - 1) / G) * nch;
+      sp += po[b];
+      su += uo[b];
     }
-    s_part[0][threadIdx.x] = sp;
-    s_part[1][threadIdx.x] = su;
-    __syncthreads();
-    // Hillis-Steele inclusive scan over the 1024 partial sums
-    for (int off = 1; off < 1024; off <<= 1) {
-      const int64_t xp = threadIdx.x >= off ? s_part[0][threadIdx.x - off] : 0;
-      const int64_t xu = threadIdx.x >= off ? s_part[1][threadIdx.x - off] : 0;
-      __syncthreads();
-      s_part[0][threadIdx.x] += xp;
-      s_part[1][threadIdx.x] += xu;
-      __syncthreads();
-    }
-    sp = s_part[0][threadIdx.x] - sp;  // exclusive
-    su = s_part[1][threadIdx.x] - su;
+    const int64_t ip = block_scan_1024(sp, s_w), iu = block_scan_1024(su, s_w);
+    int64_t xp = ip - sp, xu = iu - su;  // exclusive
     if (threadIdx.x == 1023) {
-      po[NB] = s_part[0][1023];
-      uo[NB] = s_part[1][1023];
+      po[NB] = ip;
+      uo[NB] = iu;
     }
     for (int b = b0; b < b0 + per && b < NB; ++b) {
-      const int cls = b / a.nlist, p = a.lorder[b % a.nlist];
-      const int64_t n = a.offsets[p + 1] - a.offsets[p];
-      const int64_t nch = (n + a.chunk[ph] - 1) / a.chunk[ph];
-      const int G = class_pairs(cls, a.wpr, fp32);
-      const int c = (int)po[b];
-      po[b] = sp;
-      uo[b] = su;
-      sp += c;
-      su += ((c + G - 1) / G) * nch;
+      const int64_t cp = po[b], cu = uo[b];
+      po[b] = xp;
+      uo[b] = xu;
+      xp += cp;
+      xu += cu;
     }
-    __syncthreads();
   }
 }
 
@@ -572,7 +591,7 @@ __host__ __device__ constexpr int kernel_wpr(int MT) { return MT ? wpr_for(MT) :
 
 // LDS carve-up of one scan workgroup (all offsets in bytes, 16-aligned)
 struct ScanLds {
-  int lut, ri, rr, lo, hi, pq, pb, ps, pbase, psig, lmin, total;
+  int lut, ri, rr, lo, hi, pq, pb, ps, pbase, psig, lmin, ctl, total;
 };
 __host__ __device__ inline ScanLds scan_lds_layout(int G, int wpr, int M, int d, bool fp32, int phase) {
   ScanLds L;
@@ -591,6 +610,9 @@ __host__ __device__ inline ScanLds scan_lds_layout(int G, int wpr, int M, int d,
   // phase 1 keeps per-thread minima after the scan: reuse the LUT space
   L.lmin = L.lut;
   if (phase == 1 && G * kThreadsP2 * 4 > M * kKsub * wpr * 4) L.lmin = take(G * kThreadsP2 * 4);
+  // unit-claim control words: kept in the dynamic LDS too, so that the LUT
+  // starts at LDS address 0 and row addresses fold into instruction offsets
+  L.ctl = take(32);
   L.total = o;
   return L;
 }
@@ -616,13 +638,20 @@ struct PairSlot {
   }
 };
 
+// LDS-address-space views: the scan kernels declare no static LDS, so their
+// dynamic block (the LUT first) starts at LDS address 0 and a row address is
+// a plain constant offset plus the scaled code byte
+typedef __attribute__((address_space(3))) const uint32_t lds_u32;
+typedef __attribute__((address_space(3))) const u32x2 lds_u32x2;
+typedef __attribute__((address_space(3))) const u32x4 lds_u32x4;
+
 template <int WPR>
-__device__ __forceinline__ void lut_row_load(const uint32_t* lut, int row, uint32_t* w) {
+__device__ __forceinline__ void lut_row_load(lds_u32* lut, int row, uint32_t* w) {
   if constexpr (WPR == 4) {
-    u32x4 x = *reinterpret_cast<const u32x4*>(lut + row);
+    u32x4 x = *reinterpret_cast<lds_u32x4*>(lut + row);
     w[0] = x[0]; w[1] = x[1]; w[2] = x[2]; w[3] = x[3];
   } else if constexpr (WPR == 2) {
-    u32x2 x = *reinterpret_cast<const u32x2*>(lut + row);
+    u32x2 x = *reinterpret_cast<lds_u32x2*>(lut + row);
     w[0] = x[0]; w[1] = x[1];
   } else {
     w[0] = lut[row];
@@ -1112,7 +1141,7 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
         sig_e[w] = se; sig_o[w] = so; msk_e[w] = me; msk_o[w] = mo;
       }
     }
-    const uint32_t* lut = reinterpret_cast<const uint32_t*>(lds + L.lut);
+    lds_u32* lut = reinterpret_cast<lds_u32*>((uintptr_t)L.lut);  // LDS address (see lds_u32)
     constexpr int MQ = MT ? MT / 4 : 1;  // code dwords per vector held in registers
     uint32_t cw_next[MQ];
     {
@@ -1276,7 +1305,7 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
 // processed (index at the start, descriptor before the scan, published at
 // the end)
 template <int LWB, int MT, int PHASE, int DT>
-__global__ __launch_bounds__(kThreads, LWB == 0 ? 1 : 2) void k_scan(ScanArgs a) {
+__global__ __launch_bounds__(kThreads, 2) void k_scan(ScanArgs a) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   constexpr int WPR = kernel_wpr(MT);
   constexpr bool FP = LWB == 0;
@@ -1284,8 +1313,12 @@ __global__ __launch_bounds__(kThreads, LWB == 0 ? 1 : 2) void k_scan(ScanArgs a)
   constexpr bool CRES = FP && MT != 0 && MT <= 16;
   const int M = MT ? MT : a.M;
   const ScanLds L = scan_lds_layout(G, WPR, M, a.d, FP, PHASE);
-  __shared__ int s_u;
-  __shared__ int4 s_unit;
+  if (__builtin_amdgcn_groupstaticsize() != 0) {  // the LUT must start at LDS address 0
+    if (threadIdx.x == 0) atomicOr(&a.flags[0], 16);
+    return;
+  }
+  int& s_u = *reinterpret_cast<int*>(lds + L.ctl);
+  int4& s_unit = *reinterpret_cast<int4*>(lds + L.ctl + 16);
   const int tid = threadIdx.x;
   const int64_t ub = a.unitoff[(size_t)a.cls * a.nlist];
   const int64_t ue = a.unitoff[(size_t)(a.cls + 1) * a.nlist];
@@ -1333,8 +1366,13 @@ __global__ __launch_bounds__(kThreads, 2) void k_scan_mix(ScanArgs a) {
   constexpr int WPR = kernel_wpr(MT);
   const int M = MT ? MT : a.M;
   const ScanLds L = scan_lds_layout(WPR * Lane<8>::W, WPR, M, a.d, false, PHASE);
-  __shared__ int s_u, s_cls;
-  __shared__ int4 s_unit;
+  if (__builtin_amdgcn_groupstaticsize() != 0) {  // the LUT must start at LDS address 0
+    if (threadIdx.x == 0) atomicOr(&a.flags[0], 16);
+    return;
+  }
+  int& s_u = *reinterpret_cast<int*>(lds + L.ctl);
+  int& s_cls = *reinterpret_cast<int*>(lds + L.ctl + 4);
+  int4& s_unit = *reinterpret_cast<int4*>(lds + L.ctl + 16);
   const int tid = threadIdx.x;
   const int64_t* uo = a.unitoff;
   const int64_t n2 = uo[3 * (size_t)a.nlist] - uo[2 * (size_t)a.nlist];
@@ -1536,9 +1574,12 @@ static int dt_of(int lut_dtype) {
 // subspace count of the scan variant that runs a lane class (0: generic):
 // registers-resident variants exist for M = 8, 16, 24 with the BF16 LUT build
 // (the FP32 LUT has no LC dtype)
-static int scan_mt(int lwb, int M, int dt) {
+// (wpr: the words per row the queue packed for; a batch too sparse to fill
+// wide rows runs the generic one-word variant, see scan_wpr)
+static int scan_mt(int lwb, int M, int dt, int wpr = 0) {
   if (lwb != 0 && dt != DT_BF16) return 0;
-  return (M == 8 || M == 16 || M == 24) ? M : 0;
+  const int mt = (M == 8 || M == 16 || M == 24) ? M : 0;
+  return (wpr == 1 && kernel_wpr(mt) != 1) ? 0 : mt;
 }
 
 static size_t scan_lds_bytes(int lw_bits, int phase, int M, int d, int wpr) {
@@ -1547,7 +1588,9 @@ static size_t scan_lds_bytes(int lw_bits, int phase, int M, int d, int wpr) {
   return (size_t)scan_lds_layout(G, wpr, M, d, fp, phase).total;
 }
 
-int scan_wpr(int M, bool fp32, int lut_dtype) { return kernel_wpr(scan_mt(fp32 ? 0 : 8, M, dt_of(lut_dtype))); }
+int scan_wpr(int M, bool fp32, int lut_dtype, bool narrow) {
+  return narrow ? 1 : kernel_wpr(scan_mt(fp32 ? 0 : 8, M, dt_of(lut_dtype)));
+}
 
 typedef void (*ScanFn)(ScanArgs);
 template <int LWB, int MT, int PH, int DT>
@@ -1556,8 +1599,8 @@ static ScanFn scan_fn() { return k_scan<LWB, MT, PH, DT>; }
 // kernels specialised for the subspace counts 8, 16 and 24 (codes and, for
 // the FP32 LUT, codewords kept in registers) with the BF16 LUT build; any
 // other M, and the FP16 / FP8 LUT builds, run the generic variant
-static ScanFn pick_scan(int lwb, int M, int ph, int dt) {
-  const int mt = scan_mt(lwb, M, dt);
+static ScanFn pick_scan(int lwb, int M, int ph, int dt, int wpr) {
+  const int mt = scan_mt(lwb, M, dt, wpr);
 #define AMP_PICK_M(L, MT) \
   if (mt == MT) return ph == 1 ? scan_fn<L, MT, 1, DT_BF16>() : scan_fn<L, MT, 2, DT_BF16>();
 #define AMP_PICK(L)                                                                        \
@@ -1581,8 +1624,8 @@ template <int MT, int PH, int DT>
 static ScanFn mix_fn() { return k_scan_mix<MT, PH, DT>; }
 
 // the mixed-class variant of the same specialisation as pick_scan's
-static ScanFn pick_mix(int M, int ph, int dt) {
-  const int mt = scan_mt(8, M, dt);
+static ScanFn pick_mix(int M, int ph, int dt, int wpr) {
+  const int mt = scan_mt(8, M, dt, wpr);
   if (dt == DT_F16) return ph == 1 ? mix_fn<0, 1, DT_F16>() : mix_fn<0, 2, DT_F16>();
   if (mt == 8) return ph == 1 ? mix_fn<8, 1, DT_BF16>() : mix_fn<8, 2, DT_BF16>();
   if (mt == 16) return ph == 1 ? mix_fn<16, 1, DT_BF16>() : mix_fn<16, 2, DT_BF16>();
@@ -1595,9 +1638,9 @@ static int g_num_cu = 0;
 // lwb < 0: every integer lane class in one launch (k_scan_mix)
 static hipError_t launch_scan(int lwb, int ph, int dt, int wpr, const ScanArgs& sa, hipStream_t st) {
   const bool mix = lwb < 0;
-  ScanFn fn = mix ? pick_mix(sa.M, ph, dt) : pick_scan(lwb, sa.M, ph, dt);
+  ScanFn fn = mix ? pick_mix(sa.M, ph, dt, wpr) : pick_scan(lwb, sa.M, ph, dt, wpr);
   // the queue packed units for `wpr` words per row: the variant must agree
-  if (!fn || kernel_wpr(scan_mt(mix ? 8 : lwb, sa.M, dt)) != wpr) return hipErrorInvalidValue;
+  if (!fn || kernel_wpr(scan_mt(mix ? 8 : lwb, sa.M, dt, wpr)) != wpr) return hipErrorInvalidValue;
   const size_t lds = scan_lds_bytes(mix ? 8 : lwb, ph, sa.M, sa.d, wpr);
   hipError_t e = hipFuncSetAttribute(kaddr(fn), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -1707,6 +1750,7 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   qa.max_units = sd.max_units;
   const int qb = (int)((npairs + 255) / 256);
   hipLaunchKernelGGL(k_qhist, dim3(qb), dim3(256), 0, st, qa);
+  hipLaunchKernelGGL(k_qtot, dim3((2 * NB + 255) / 256), dim3(256), 0, st, qa, fp32 ? 1 : 0);
   hipLaunchKernelGGL(k_qscan, dim3(1), dim3(1024), 0, st, qa, fp32 ? 1 : 0);
   hipLaunchKernelGGL(k_qscatter, dim3(qb), dim3(256), 0, st, qa);
   hipLaunchKernelGGL(k_qunits, dim3(512), dim3(256), 0, st, qa, fp32 ? 1 : 0);
