@@ -28,6 +28,7 @@ BF16_MFMA_TFLOPS = 2500.0
 # 32-bit VALU lane operations: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_scan_mid_traffic.json")
+STREAM_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_scan_stream_traffic.json")
 
 
 def _kernel_hash():
@@ -39,11 +40,11 @@ def _kernel_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(path=TRAFFIC_FILE):
     """HBM bytes per launch of the phase-2 scan from the committed counter
     summary, if it was taken on the current kernel source (else None)."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -149,6 +150,17 @@ def main():
     dev = torch.device("cuda:0")
     qd = torch.from_numpy(Q).to(dev)
     nq, k, nprobe = len(Q), w.k, w.nprobe
+    # streaming regime: every search takes a fresh batch from a pool (no code
+    # reuse between consecutive searches); plain launches (the query pointer
+    # changes)
+    n_batches = args.steps + args.warmup if args.replicate > 1 else 1
+    if n_batches > 1:
+        args.graph = 0
+        QP = make_queries(w.scaled(nq=nq * n_batches), nq * n_batches)
+        qpool = torch.from_numpy(QP).to(dev)
+        batch = lambda i: qpool[(i % n_batches) * nq:(i % n_batches + 1) * nq]
+    else:
+        batch = lambda i: qd
     out = dict(ids=torch.empty((nq, k), dtype=torch.int64, device=dev),
                dist=torch.empty((nq, k), dtype=torch.float32, device=dev),
                qdist=torch.empty((nq, k), dtype=torch.int64, device=dev))
@@ -186,21 +198,21 @@ def main():
     sizes = idx["list_sizes"].astype(np.int64)
     for name, kw in pols:
         out["probes"], out["bits"] = (None, None) if nr else (out_probes, out_bits)
-        for _ in range(args.warmup):
-            amp.amp_search(h, qd, k, nprobe, out=out, stream=stream, graph=args.graph, **kw)
+        for i in range(args.warmup):
+            amp.amp_search(h, batch(args.steps + i), k, nprobe, out=out, stream=stream, graph=args.graph, **kw)
         torch.cuda.synchronize()
         # timed region: K searches enqueued back to back on one stream
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        for _ in range(args.steps):
-            amp.amp_search(h, qd, k, nprobe, out=out, stream=stream, graph=args.graph, **kw)
+        for i in range(args.steps):
+            amp.amp_search(h, batch(i), k, nprobe, out=out, stream=stream, graph=args.graph, **kw)
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / args.steps
         # stage breakdown and per-batch latency: separate, synchronised searches
         stages, lat = [], []
-        for _ in range(args.steps):
-            o = amp.amp_search(h, qd, k, nprobe, out=out, stream=stream, stage_ms=True, **kw)
+        for i in range(args.steps):
+            o = amp.amp_search(h, batch(i), k, nprobe, out=out, stream=stream, stage_ms=True, **kw)
             stages.append(o["stage_ms"])
             lat.append(o["stage_ms"]["total"])
         if nr:
@@ -230,7 +242,23 @@ def main():
     # algorithmic work of the phase-2 scan: per (query, probed list) pair one
     # LUT entry per (subspace, codeword) and one lookup-add per (vector, subspace)
     achieved = r["scan_ops"] / (scan_ms / 1e3) / 1e12
-    traffic = measured_traffic()
+    streaming = args.replicate > 1
+    mix = head in ("adaptive",)
+    kname = ("k_scan_mix<M,2,1>: phase-2 scan, every lane class in one launch" if mix else
+             "k_scan<LW,M,2,1>: phase-2 scan of the policy's lane class")
+    traffic = measured_traffic(STREAM_TRAFFIC_FILE if streaming else TRAFFIC_FILE)
+    if streaming:
+        # no cross-query reuse of codes: the scan is bounded by HBM bandwidth;
+        # algorithmic bytes = each probed list's codes once per pair
+        gbs = r["code_bytes"] / (scan_ms / 1e3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
+                    "kernel_ms": round(scan_ms, 4), "algorithmic_code_bytes_per_launch": round(r["code_bytes"])}
+    else:
+        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
+                    "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": traffic, "kernel": kname,
+                    "kernel_ms": round(scan_ms, 4), "algorithmic_code_bytes_per_launch": round(r["code_bytes"]),
+                    "algorithmic_ops_per_launch": round(r["scan_ops"])}
     fp = results.get("fp32")
     # the two dense contractions on MFMA: CL (FP32 MFMA) and the LUT build
     # (BF16 MFMA, fused into the scan kernels: rate over the scan stages, a
@@ -284,12 +312,7 @@ def main():
                                 for n, x in results.items()}},
         "mfma": mfma_use,
         "hbm_bound": hbm_bound,
-        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
-                     "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": traffic,
-                     "kernel": "k_scan phase 2 (LUT build + quantise + scan), all width classes",
-                     "kernel_ms": round(scan_ms, 4),
-                     "algorithmic_code_bytes_per_launch": round(r["code_bytes"]),
-                     "algorithmic_ops_per_launch": round(r["scan_ops"])},
+        "roofline": roofline,
     }
     if not args.no_cpu:
         kw = dict(pols)[head]
