@@ -174,6 +174,47 @@ typedef struct amp_search_opts {
  * listed with amp_index_arrays, including id order inside lists. */
 amp_status amp_index_from_arrays(const amp_index_arrays* arrays, amp_index** out);
 
+/*
+ * Build an IVF-PQ index (Sec. 2.1) from n host vectors base [n][d] float on
+ * the current HIP device: k-means coarse quantiser of nlist centroids,
+ * residual product quantiser of M subspaces with one 256-word codebook per
+ * subspace shared by all lists, PQ codes by nearest codeword, lists stored
+ * contiguously with ids increasing inside a list, per-list radius (Sec. 3.3
+ * feature) in grid units, and the LC operand grid step h = 2^grid_e.
+ *   ids            host [n] int64, or NULL for 0..n-1
+ *   nlist, M       as in amp_index_arrays (d % M == 0, d/M <= 8, M % 4 == 0,
+ *                  1 <= nlist <= min(n, 8192))
+ *   kmeans_iters   Lloyd iterations of every k-means (0..1000)
+ *   seed           seeds the training samples and initial centroids
+ *   metric         AMP_L2 or AMP_IP
+ *   grid_kind      AMP_GRID_U9 or AMP_GRID_E4M3
+ *   integer_data   non-zero: the vectors hold integers; centroids and
+ *                  codewords are rounded to integers after training, every
+ *                  vector is assigned to the rounded centroids and h = 1
+ * k-means trains on at most 256 points per centroid (a seeded sample), starts
+ * from the first distinct points of a seeded order, breaks ties to the lower
+ * centroid index and reseeds an empty cluster with the training point
+ * farthest from its centroid.  Otherwise h is the smallest power of two with
+ * every codeword and residual magnitude (inner product: also every centroid
+ * and vector magnitude) within the grid's largest value (255 for U9, 448 for
+ * E4M3).  Distances and assignments run on the device in FP32; means, radius
+ * and layout on the host (FP64 sums).  The result is an index as from
+ * amp_index_from_arrays, without a predictor.  AMP_EINVAL for bad arguments,
+ * AMP_EUNSUPPORTED beyond the limits, AMP_EDEVICE on a HIP failure; *out is
+ * NULL on failure.
+ */
+typedef struct amp_build_params {
+  int32_t nlist, M, kmeans_iters, metric, grid_kind, integer_data;
+  uint64_t seed;
+} amp_build_params;
+
+amp_status amp_index_build(const float* base, int64_t n, int32_t d, const int64_t* ids,
+                           const amp_build_params* params, amp_index** out);
+
+/* Borrow the arrays of an index (pointers into the handle, valid until it is
+ * freed or modified); the same layout amp_index_from_arrays takes. */
+amp_status amp_index_get_arrays(const amp_index* index, amp_index_arrays* out);
+
 /* Attach (or replace) the precision predictor of an index (copied). */
 amp_status amp_index_set_predictor(amp_index* index, const amp_predictor_model* model);
 

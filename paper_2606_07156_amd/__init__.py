@@ -61,6 +61,11 @@ class _Opts(C.Structure):
                 ("stage_ms", C.c_void_p), ("flags", C.c_uint32)]
 
 
+class _BuildParams(C.Structure):
+    _fields_ = [("nlist", C.c_int32), ("M", C.c_int32), ("kmeans_iters", C.c_int32), ("metric", C.c_int32),
+                ("grid_kind", C.c_int32), ("integer_data", C.c_int32), ("seed", C.c_uint64)]
+
+
 class _TrainParams(C.Structure):
     _fields_ = [("n_samples", C.c_int32), ("max_iter", C.c_int32), ("gamma", C.c_double),
                 ("C", C.c_double), ("epsilon", C.c_double), ("tol", C.c_double),
@@ -73,7 +78,7 @@ class _TrainReport(C.Structure):
 
 
 _lib = None
-EXPORTS = ("amp_index_from_arrays", "amp_index_set_predictor", "amp_index_get_predictor",
+EXPORTS = ("amp_index_from_arrays", "amp_index_build", "amp_index_get_arrays", "amp_index_set_predictor", "amp_index_get_predictor",
            "amp_index_train_predictor", "amp_svr_fit",
            "amp_index_to_device",
            "amp_index_save", "amp_index_load", "amp_index_info", "amp_search",
@@ -175,6 +180,48 @@ def amp_index_from_arrays(ix):
     h = C.c_void_p()
     _check(lib().amp_index_from_arrays(C.byref(a), C.byref(h)))
     return Index(h.value)
+
+
+def amp_index_build(base, nlist, M, iters=20, seed=0, integer_data=False, grid_kind="u9", metric="l2",
+                    ids=None):
+    """Build an index on the current device from host vectors ``base`` [n, d]."""
+    if metric not in ("l2", "ip") or grid_kind not in ("u9", "e4m3"):
+        raise ValueError(f"unknown metric {metric!r} or grid kind {grid_kind!r}")
+    x = np.ascontiguousarray(base, dtype=np.float32)
+    if x.ndim != 2:
+        raise ValueError("base must be [n, d]")
+    idv = None if ids is None else np.ascontiguousarray(ids, dtype=np.int64)
+    if idv is not None and idv.shape != (x.shape[0],):
+        raise ValueError("ids must have one entry per vector")
+    p = _BuildParams(int(nlist), int(M), int(iters), AMP_L2 if metric == "l2" else AMP_IP,
+                     AMP_GRID_U9 if grid_kind == "u9" else AMP_GRID_E4M3, int(bool(integer_data)), int(seed))
+    h = C.c_void_p()
+    _check(lib().amp_index_build(_ptr(x), int(x.shape[0]), int(x.shape[1]), _ptr(idv), C.byref(p), C.byref(h)))
+    return Index(h.value)
+
+
+def amp_index_get_arrays(index):
+    """Copies of the index arrays, as a dict in the amp_index_from_arrays format."""
+    a = _Arrays()
+    _check(lib().amp_index_get_arrays(index.handle, C.byref(a)))
+    info = amp_index_info(index)
+    d, M, nl, n = a.d, a.M, a.nlist, info["n"]
+
+    def arr(ptr, ctype, shape, dt):
+        if n == 0 and ptr is None:
+            return np.zeros(shape, dt)
+        buf = (ctype * int(np.prod(shape))).from_address(ptr)
+        return np.ctypeslib.as_array(buf).reshape(shape).astype(dt, copy=True)
+
+    offs = arr(a.list_offsets, C.c_int64, (nl + 1,), np.int64)
+    return dict(d=d, M=M, dsub=d // M, nlist=nl, metric="l2" if a.metric == AMP_L2 else "ip",
+                grid_kind="u9" if a.grid_kind == AMP_GRID_U9 else "e4m3", grid_e=a.grid_e,
+                centroids=arr(a.centroids, C.c_float, (nl, d), np.float32),
+                codebook=arr(a.codebook, C.c_float, (M, 256, d // M), np.float32),
+                list_offsets=offs, list_sizes=np.diff(offs).astype(np.int32),
+                ids=arr(a.ids, C.c_int64, (n,), np.int64),
+                codes=arr(a.codes, C.c_uint8, (n, M), np.uint8),
+                radq=arr(a.radq, C.c_int32, (nl,), np.int32))
 
 
 def amp_index_set_predictor(index, model):

@@ -7,13 +7,14 @@ Set AMP_HIP_RUNTIME=system to link /opt/rocm's runtime instead.
 """
 from __future__ import annotations
 
+import concurrent.futures
 import glob
 import os
 import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "capi.cpp", "train.cpp")]
+SRC = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "capi.cpp", "train.cpp", "build.cpp")]
 OUT = os.path.join(HERE, "libamp.so")
 BUILD = os.path.join(HERE, "_build")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
@@ -51,17 +52,17 @@ def _run(cmd, verbose):
 
 def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
-    for s in SRC:
-        o = os.path.join(BUILD, os.path.basename(s) + ".o")
-        _run([HIPCC, *CFLAGS, "-c", "-o", o, s], verbose)
-        objs.append(o)
+    objs = [os.path.join(BUILD, os.path.basename(s) + ".o") for s in SRC]
+    # the translation units compile concurrently (the kernels dominate)
+    with concurrent.futures.ThreadPoolExecutor(len(SRC)) as pool:
+        for f in [pool.submit(_run, [HIPCC, *CFLAGS, "-c", "-o", o, s], verbose) for s, o in zip(SRC, objs)]:
+            f.result()
     tdir = None if os.environ.get("AMP_HIP_RUNTIME") == "system" else _torch_lib_dir()
     if tdir:
         rt = ["-L" + tdir, "-l:libamdhip64.so", "-Wl,-rpath," + tdir]
     else:
         rt = ["-L" + os.path.join(ROCM, "lib"), "-lamdhip64", "-Wl,-rpath," + os.path.join(ROCM, "lib")]
-    _run(["g++", "-shared", "-o", OUT + ".tmp", *objs, *rt, "-Wl,--no-undefined", "-lstdc++"], verbose)
+    _run(["g++", "-shared", "-o", OUT + ".tmp", *objs, *rt, "-Wl,--no-undefined", "-lstdc++", "-pthread"], verbose)
     os.replace(OUT + ".tmp", OUT)
     return OUT
 

@@ -191,6 +191,15 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
                          const SearchDims& sd, const ModelArgs& ma, int64_t* out_ids,
                          float* out_dist, int64_t* out_qdist, float* out_coarse,
                          hipStream_t st, hipEvent_t* ev /* [AMP_N_STAGES+1] or null */);
+// index build: nearest centroid of n rows (dd floats, leading dimension ld)
+// among k centroids [k][dd], with its squared distance (out_d may be null);
+// xn [n] and cn [k] are scratch for the squared norms
+hipError_t launch_assign(const float* X, int64_t n, int dd, int ld, const float* C, int k, float* xn, float* cn,
+                         int32_t* out_a, float* out_d, hipStream_t st);
+// out [n][d] = X [n][d] - C[a[i]]
+hipError_t launch_residual(const float* X, const int32_t* a, const float* C, int64_t n, int d, float* out,
+                           hipStream_t st);
+
 // LUT words per row of the scan variants a search runs (the queue packs its
 // work units to match)
 int scan_wpr(int M, bool fp32, int lut_dtype, bool narrow);

@@ -137,6 +137,96 @@ __global__ __launch_bounds__(256) void k_coarse(const float* __restrict__ Q, con
       }
 }
 
+// ------------------------------------------------------------------ index build
+// squared norms of n rows of dd floats with leading dimension ld (a wave per row)
+__global__ void k_sqnorm_ld(const float* __restrict__ X, int64_t n, int dd, int ld, float* __restrict__ out) {
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (r >= n) return;
+  float s = 0.f;
+  for (int t = lane; t < dd; t += 64) {
+    const float v = X[r * ld + t];
+    s = fmaf(v, v, s);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (lane == 0) out[r] = s;
+}
+
+// nearest of k centroids (squared L2 in FP32, ties to the lower index) for n
+// rows of dd floats (leading dimension ld) and its distance.  64 rows per
+// workgroup; centroids in tiles of 64 on FP32 MFMA 16x16x4 (the coarse
+// distance kernel's tiling); each tile's distances go through LDS and the
+// row's thread keeps the running minimum.
+__global__ __launch_bounds__(256) void k_assign(const float* __restrict__ X, const float* __restrict__ xn,
+                                                int64_t n, int dd, int ld, const float* __restrict__ C,
+                                                const float* __restrict__ cn, int k, int32_t* __restrict__ out_a,
+                                                float* __restrict__ out_d) {
+  __shared__ float Xs[CL_T][CL_K + 1];
+  __shared__ float Cs[CL_T][CL_K + 1];
+  __shared__ float Ds[CL_T][CL_T + 1];
+  const int64_t r0 = (int64_t)blockIdx.x * CL_T;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  float best = 3.4e38f;
+  int besti = 0;
+  for (int c0 = 0; c0 < k; c0 += CL_T) {
+    f4 acc[2][2];
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < dd; k0 += CL_K) {
+      for (int i = tid; i < CL_T * CL_K; i += 256) {
+        const int r = i / CL_K, kk = i % CL_K, gk = k0 + kk;
+        Xs[r][kk] = (r0 + r < n && gk < dd) ? X[(r0 + r) * ld + gk] : 0.f;
+        Cs[r][kk] = (c0 + r < k && gk < dd) ? C[(size_t)(c0 + r) * dd + gk] : 0.f;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < CL_K; kk += 4) {
+        const float a0 = Xs[wr + (lane & 15)][kk + (lane >> 4)];
+        const float a1 = Xs[wr + 16 + (lane & 15)][kk + (lane >> 4)];
+        const float b0 = Cs[wc + (lane & 15)][kk + (lane >> 4)];
+        const float b1 = Cs[wc + 16 + (lane & 15)][kk + (lane >> 4)];
+        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+      }
+      __syncthreads();
+    }
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j)
+        for (int q = 0; q < 4; ++q) {
+          const int rr = wr + 16 * i + 4 * (lane >> 4) + q, cc = wc + 16 * j + (lane & 15);
+          Ds[rr][cc] = c0 + cc < k ? cn[c0 + cc] - 2.f * acc[i][j][q] : 3.4e38f;
+        }
+    __syncthreads();
+    if (tid < CL_T)
+      for (int c = 0; c < CL_T && c0 + c < k; ++c) {
+        const float v = Ds[tid][c];
+        if (v < best) {
+          best = v;
+          besti = c0 + c;
+        }
+      }
+    __syncthreads();
+  }
+  if (tid < CL_T && r0 + tid < n) {
+    out_a[r0 + tid] = besti;
+    if (out_d) out_d[r0 + tid] = best + xn[r0 + tid];
+  }
+}
+
+// residual rows x - c_a of a chunk
+__global__ void k_residual(const float* __restrict__ X, const int32_t* __restrict__ a, const float* __restrict__ C,
+                           int64_t n, int d, float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * d) return;
+  const int64_t r = i / d;
+  const int t = (int)(i - r * d);
+  out[i] = X[i] - C[(size_t)a[r] * d + t];
+}
+
 // ------------------------------------------------------------------ sorting
 // ascending bitonic sort of n (power of two) 64-bit keys in LDS by the block
 __device__ void block_bitonic_u64(uint64_t* keys, int n) {
@@ -1654,6 +1744,24 @@ static hipError_t launch_scan(int lwb, int ph, int dt, int wpr, const ScanArgs& 
     (void)hipDeviceGetAttribute(&g_num_cu, hipDeviceAttributeMultiprocessorCount, dev);
   }
   hipLaunchKernelGGL(fn, dim3(g_num_cu * per_cu), dim3(kThreads), lds, st, sa);
+  return hipGetLastError();
+}
+
+hipError_t launch_assign(const float* X, int64_t n, int dd, int ld, const float* C, int k, float* xn, float* cn,
+                         int32_t* out_a, float* out_d, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sqnorm_ld, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, X, n, dd, ld, xn);
+  hipLaunchKernelGGL(k_sqnorm_ld, dim3((unsigned)((k + 3) / 4)), dim3(256), 0, st, C, (int64_t)k, dd, dd, cn);
+  hipLaunchKernelGGL(k_assign, dim3((unsigned)((n + CL_T - 1) / CL_T)), dim3(256), 0, st, X, xn, n, dd, ld, C, cn, k,
+                     out_a, out_d);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual(const float* X, const int32_t* a, const float* C, int64_t n, int d, float* out,
+                           hipStream_t st) {
+  const int64_t total = n * d;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_residual, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, X, a, C, n, d, out);
   return hipGetLastError();
 }
 

@@ -92,6 +92,36 @@ def test_invalid_index_arrays_are_rejected():
     assert e.value.status == amp.AMP_EUNSUPPORTED
 
 
+def test_get_arrays_returns_what_from_arrays_took():
+    idx = _idx()
+    h = amp.amp_index_from_arrays(idx)
+    got = amp.amp_index_get_arrays(h)
+    for key in ("d", "M", "nlist", "metric", "grid_kind", "grid_e"):
+        assert got[key] == idx[key], key
+    for key in ("centroids", "codebook", "list_offsets", "ids", "codes", "radq"):
+        assert np.array_equal(got[key], np.asarray(idx[key]).reshape(got[key].shape)), key
+
+
+@pytest.mark.parametrize("kw,status,frag", [
+    (dict(nlist=8, M=5), amp.AMP_EINVAL, "multiple of M"),
+    (dict(nlist=8, M=2), amp.AMP_EUNSUPPORTED, "multiple of 4"),
+    (dict(nlist=8, M=1), amp.AMP_EUNSUPPORTED, "d/M"),
+    (dict(nlist=0, M=4), amp.AMP_EINVAL, "positive"),
+    (dict(nlist=100, M=4), amp.AMP_EINVAL, "fewer vectors"),
+    (dict(nlist=8, M=4, iters=-1), amp.AMP_EINVAL, "kmeans_iters"),
+    (dict(nlist=8, M=4, metric="cos"), None, None),
+])
+def test_build_argument_validation_happens_before_device_work(kw, status, frag):
+    base = np.zeros((64, 12), np.float32)
+    if status is None:  # unknown metric names are rejected by the binding
+        with pytest.raises(ValueError):
+            amp.amp_index_build(base, **kw)
+        return
+    with pytest.raises(amp.AmpError) as e:
+        amp.amp_index_build(base, **kw)
+    assert e.value.status == status and frag in str(e.value)
+
+
 @pytest.mark.parametrize("kw,frag", [
     (dict(k=0, nprobe=2), "k = 0"),
     (dict(k=2000, nprobe=2), "k = 2000"),
