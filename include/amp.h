@@ -60,6 +60,7 @@ enum {                                           /* precision policy kind       
   AMP_POLICY_EXPLICIT = 3   /* caller gives the width per (query, probe rank)  */
 };
 enum { AMP_LUT_BF16 = 1, AMP_LUT_F16 = 2, AMP_LUT_F8E4M3 = 3 }; /* LC matrix dtype */
+enum { AMP_F32 = 0, AMP_BF16 = 1 };  /* element type of query and base rows */
 
 #define AMP_KSUB 256        /* codewords per subspace                          */
 #define AMP_MAX_K 1024
@@ -151,6 +152,13 @@ typedef struct amp_precision_policy {
  *   out_coarse [nq][nlist] float coarse (CL) distances
  * stage_ms (host, [AMP_N_STAGES] float, optional): per-stage GPU time of this
  * call from events on the stream; forces a synchronisation at the end.
+ * q_dtype: AMP_F32 (0) or AMP_BF16 query rows (bfloat16 bit patterns,
+ * uint16); BF16 rows are widened to FP32 on the device (exact) as the first
+ * step of the search, so a BF16 query searches exactly as the FP32 query of
+ * the same value.
+ * Per-query k / nprobe arrays are staged through pinned memory: the call does
+ * not wait for earlier searches on the stream, and the caller may reuse the
+ * arrays when it returns.
  */
 #define AMP_N_STAGES 8
 #define AMP_SEARCH_GRAPH 1u  /* flags: capture the search as a HIP graph once
@@ -168,6 +176,7 @@ typedef struct amp_search_opts {
   float* out_coarse;
   float* stage_ms;
   uint32_t flags;
+  int32_t q_dtype;
 } amp_search_opts;
 
 /* Build an index handle from arrays (copied).  Validates every constraint
@@ -175,8 +184,9 @@ typedef struct amp_search_opts {
 amp_status amp_index_from_arrays(const amp_index_arrays* arrays, amp_index** out);
 
 /*
- * Build an IVF-PQ index (Sec. 2.1) from n host vectors base [n][d] float on
- * the current HIP device: k-means coarse quantiser of nlist centroids,
+ * Build an IVF-PQ index (Sec. 2.1) from n host vectors base [n][d] (FP32, or
+ * BF16 bit patterns with base_dtype = AMP_BF16, widened exactly) on the
+ * current HIP device: k-means coarse quantiser of nlist centroids,
  * residual product quantiser of M subspaces with one 256-word codebook per
  * subspace shared by all lists, PQ codes by nearest codeword, lists stored
  * contiguously with ids increasing inside a list, per-list radius (Sec. 3.3
@@ -204,11 +214,11 @@ amp_status amp_index_from_arrays(const amp_index_arrays* arrays, amp_index** out
  * NULL on failure.
  */
 typedef struct amp_build_params {
-  int32_t nlist, M, kmeans_iters, metric, grid_kind, integer_data;
+  int32_t nlist, M, kmeans_iters, metric, grid_kind, integer_data, base_dtype;
   uint64_t seed;
 } amp_build_params;
 
-amp_status amp_index_build(const float* base, int64_t n, int32_t d, const int64_t* ids,
+amp_status amp_index_build(const void* base, int64_t n, int32_t d, const int64_t* ids,
                            const amp_build_params* params, amp_index** out);
 
 /* Borrow the arrays of an index (pointers into the handle, valid until it is
@@ -279,19 +289,99 @@ amp_status amp_index_info(const amp_index* index, int32_t* d, int32_t* M,
                           int32_t* nlist, int64_t* n);
 
 /*
- * Search nq queries ([nq][d] float, row-major).  k and nprobe are host
+ * Search nq queries ([nq][d] float, or BF16 with opts.q_dtype, row-major).  k and nprobe are host
  * arrays of nq entries when per_query != 0, else single values; kmax and
  * npmax are their maxima.  Outputs: out_ids [nq][kmax] int64 and out_dist
  * [nq][kmax] float (h^2 * integer estimate for integer policies, FP32 sum for
  * the FP32 policy).  Requires 1 <= k <= AMP_MAX_K, 1 <= nprobe <=
  * min(nlist, AMP_MAX_NPROBE); AMP_POLICY_ADAPTIVE requires a predictor.
- * In device mode the query buffer must be 16-byte aligned (rows are read as
- * float4; d is a multiple of 4), else AMP_EINVAL.
+ * In device mode an FP32 query buffer must be 16-byte aligned (rows are read
+ * as float4; d is a multiple of 4), a BF16 one 2-byte aligned, else
+ * AMP_EINVAL.
  */
-amp_status amp_search(amp_index* index, const float* queries, int64_t nq,
+amp_status amp_search(amp_index* index, const void* queries, int64_t nq,
                       const int32_t* k, const int32_t* nprobe, int32_t per_query,
                       const amp_precision_policy* policy, const amp_search_opts* opts,
                       int64_t* out_ids, float* out_dist);
+
+/*
+ * Serving loop: single-query requests, continuously batched onto the search
+ * path of the device current at creation (the paper's problem statement,
+ * Sec. 1 / Sec. 2.1, served one query at a time).
+ *
+ * Requests are copied at submission into a pool of max_pending pinned query
+ * slots: that pool is the admission bound (memory-based admission), a full
+ * pool rejects with AMP_EBUSY.  A worker thread gathers queued requests of
+ * one precision policy (the oldest request's) into batches of at most
+ * max_batch queries and runs each as one device-mode search with per-query k
+ * and nprobe on a stream of its own; two batches may be in flight.  An idle
+ * device waits up to batch_window_us after the oldest request's arrival for
+ * a batch to fill (0: launch at once).  Results are the same as amp_search
+ * of that query alone.
+ *   max_batch    1..65536 (0 = 1024)       max_pending 1..2^22 (0 = 4*max_batch)
+ *   max_k        1..1024 (0 = 100)         max_nprobe  1..min(nlist, 256) (0 = that)
+ *   q_dtype      AMP_F32 or AMP_BF16 query rows
+ *   policy       default of requests that name none (not EXPLICIT)
+ * Pinned host memory: (max_pending + 2*max_batch) * d * sizeof(row element)
+ * + 2 * max_batch * max_k * 20 bytes; device memory the same staging plus the
+ * index's search scratch, reserved at creation for the largest batch.
+ * The index must outlive the server; other searches on it are allowed (they
+ * serialise on its scratch space).
+ */
+typedef struct amp_server amp_server;
+
+typedef struct amp_server_config {
+  int32_t max_batch, max_pending, max_k, max_nprobe, batch_window_us, q_dtype;
+  amp_precision_policy policy;
+} amp_server_config;
+
+/*
+ * One request.  query: host row of d elements (q_dtype), copied during the
+ * call.  out_ids [k] int64, out_dist [k] float and out_qdist [k] int64
+ * (optional) are host buffers the caller keeps valid until completion; they
+ * are written before done(user, AMP_OK) runs.  done (optional) runs on the
+ * server's worker thread with no server lock held, once per admitted request
+ * with AMP_OK, AMP_ECANCELED (outputs untouched) or the error of its batch; it
+ * may submit or cancel, but must not flush or destroy the server.  policy:
+ * NULL = the server's default.  arrival_ns: CLOCK_MONOTONIC time the request
+ * arrived (latency is measured from it; 0 = the time of submission).
+ */
+typedef struct amp_request {
+  const void* query;
+  int32_t k, nprobe;
+  int64_t* out_ids;
+  float* out_dist;
+  int64_t* out_qdist;
+  void (*done)(void* user, amp_status status);
+  void* user;
+  const amp_precision_policy* policy;
+  int64_t arrival_ns;
+} amp_request;
+
+/* Counters since creation or the last reset; latency percentiles over the
+ * requests completed with AMP_OK in that window (arrival to results written). */
+typedef struct amp_server_report {
+  int64_t submitted, rejected, completed, cancelled, failed, batches, pending, in_flight;
+  double elapsed_s, qps, mean_batch, p50_ms, p99_ms, max_ms;
+} amp_server_report;
+
+/* Start a server on the current device (moves the index there and reserves
+ * its search scratch).  AMP_EINVAL for a bad configuration or policy. */
+amp_status amp_server_create(amp_index* index, const amp_server_config* config, amp_server** out);
+/* Admit a request (AMP_EBUSY when the pool is full or the server is
+ * stopping; AMP_EINVAL for k, nprobe or policy out of range, nothing queued).
+ * *ticket (optional) identifies it for amp_server_cancel. */
+amp_status amp_server_submit(amp_server* server, const amp_request* request, uint64_t* ticket);
+/* Cancel a queued request (its done runs at once with AMP_ECANCELED) or an
+ * in-flight one (its results are dropped; done runs at completion with
+ * AMP_ECANCELED).  AMP_EINVAL if the ticket is neither queued nor in flight. */
+amp_status amp_server_cancel(amp_server* server, uint64_t ticket);
+/* Block until every admitted request has completed (not from a callback). */
+amp_status amp_server_flush(amp_server* server);
+/* Read the counters; reset != 0 starts a new window. */
+amp_status amp_server_stats(amp_server* server, amp_server_report* out, int32_t reset);
+/* Stop admission, finish every admitted request, join the worker, free. */
+void amp_server_destroy(amp_server* server);
 
 void amp_index_free(amp_index* index);
 const char* amp_status_str(amp_status status);

@@ -22,6 +22,7 @@ AMP_GRID_U9, AMP_GRID_E4M3 = 0, 1
 AMP_MEM_HOST, AMP_MEM_DEVICE = 0, 1
 AMP_POLICY_FP32, AMP_POLICY_FIXED, AMP_POLICY_ADAPTIVE, AMP_POLICY_EXPLICIT = 0, 1, 2, 3
 AMP_LUT_BF16, AMP_LUT_F16, AMP_LUT_F8E4M3 = 1, 2, 3
+AMP_F32, AMP_BF16 = 0, 1
 AMP_N_STAGES = 8
 STAGES = ("cl", "topn", "predict", "queue", "scan1", "scan2", "merge", "total")
 POLICIES = {"fp32": AMP_POLICY_FP32, "fixed": AMP_POLICY_FIXED,
@@ -58,12 +59,13 @@ AMP_SEARCH_GRAPH = 1
 class _Opts(C.Structure):
     _fields_ = [("mem", C.c_int32), ("stream", C.c_void_p), ("out_qdist", C.c_void_p),
                 ("out_probes", C.c_void_p), ("out_bits", C.c_void_p), ("out_coarse", C.c_void_p),
-                ("stage_ms", C.c_void_p), ("flags", C.c_uint32)]
+                ("stage_ms", C.c_void_p), ("flags", C.c_uint32), ("q_dtype", C.c_int32)]
 
 
 class _BuildParams(C.Structure):
     _fields_ = [("nlist", C.c_int32), ("M", C.c_int32), ("kmeans_iters", C.c_int32), ("metric", C.c_int32),
-                ("grid_kind", C.c_int32), ("integer_data", C.c_int32), ("seed", C.c_uint64)]
+                ("grid_kind", C.c_int32), ("integer_data", C.c_int32), ("base_dtype", C.c_int32),
+                ("seed", C.c_uint64)]
 
 
 class _TrainParams(C.Structure):
@@ -82,6 +84,8 @@ EXPORTS = ("amp_index_from_arrays", "amp_index_build", "amp_index_get_arrays", "
            "amp_index_train_predictor", "amp_svr_fit",
            "amp_index_to_device",
            "amp_index_save", "amp_index_load", "amp_index_info", "amp_search",
+           "amp_server_create", "amp_server_submit", "amp_server_cancel", "amp_server_flush",
+           "amp_server_stats", "amp_server_destroy",
            "amp_index_free", "amp_status_str", "amp_last_error")
 
 
@@ -120,7 +124,7 @@ def lib():
         L.amp_status_str.restype = C.c_char_p
         L.amp_last_error.restype = C.c_char_p
         for name in EXPORTS:
-            if name not in ("amp_index_free", "amp_status_str", "amp_last_error"):
+            if name not in ("amp_index_free", "amp_server_destroy", "amp_status_str", "amp_last_error"):
                 getattr(L, name).restype = C.c_int32
         _lib = L
     return _lib
@@ -184,17 +188,20 @@ def amp_index_from_arrays(ix):
 
 def amp_index_build(base, nlist, M, iters=20, seed=0, integer_data=False, grid_kind="u9", metric="l2",
                     ids=None):
-    """Build an index on the current device from host vectors ``base`` [n, d]."""
+    """Build an index on the current device from host vectors ``base`` [n, d]
+    (float32, or bfloat16 bit patterns as a uint16 array)."""
     if metric not in ("l2", "ip") or grid_kind not in ("u9", "e4m3"):
         raise ValueError(f"unknown metric {metric!r} or grid kind {grid_kind!r}")
-    x = np.ascontiguousarray(base, dtype=np.float32)
+    bf16 = getattr(base, "dtype", None) == np.uint16
+    x = np.ascontiguousarray(base, dtype=np.uint16 if bf16 else np.float32)
     if x.ndim != 2:
         raise ValueError("base must be [n, d]")
     idv = None if ids is None else np.ascontiguousarray(ids, dtype=np.int64)
     if idv is not None and idv.shape != (x.shape[0],):
         raise ValueError("ids must have one entry per vector")
     p = _BuildParams(int(nlist), int(M), int(iters), AMP_L2 if metric == "l2" else AMP_IP,
-                     AMP_GRID_U9 if grid_kind == "u9" else AMP_GRID_E4M3, int(bool(integer_data)), int(seed))
+                     AMP_GRID_U9 if grid_kind == "u9" else AMP_GRID_E4M3, int(bool(integer_data)),
+                     AMP_BF16 if bf16 else AMP_F32, int(seed))
     h = C.c_void_p()
     _check(lib().amp_index_build(_ptr(x), int(x.shape[0]), int(x.shape[1]), _ptr(idv), C.byref(p), C.byref(h)))
     return Index(h.value)
@@ -311,7 +318,7 @@ def make_policy(policy="fixed", bits=16, allowed=(4, 8, 12, 16), margin_q40=0,
 def amp_search(index, queries, k, nprobe, policy="fixed", bits=16, allowed=(4, 8, 12, 16),
                margin_q40=0, explicit_bits=None, lut_dtype=0, want_qdist=True,
                want_probes=False, want_bits=False, want_coarse=False, stage_ms=False,
-               out=None, stream=None, graph=False):
+               out=None, stream=None, graph=False, q_dtype=None):
     """Search a batch.
 
     Host mode (``queries`` a numpy array): returns a dict of numpy arrays.
@@ -322,6 +329,9 @@ def amp_search(index, queries, k, nprobe, policy="fixed", bits=16, allowed=(4, 8
     """
     device = hasattr(queries, "data_ptr")
     nq = int(queries.shape[0])
+    if q_dtype is None:
+        q_dtype = "bf16" if str(getattr(queries, "dtype", "")) in ("uint16", "torch.bfloat16") else "f32"
+    qd = AMP_BF16 if q_dtype == "bf16" else AMP_F32
     kk = np.atleast_1d(np.asarray(k, dtype=np.int32))
     npb = np.atleast_1d(np.asarray(nprobe, dtype=np.int32))
     per_query = int(kk.size > 1 or npb.size > 1)
@@ -336,13 +346,13 @@ def amp_search(index, queries, k, nprobe, policy="fixed", bits=16, allowed=(4, 8
         sh = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
         opts = _Opts(AMP_MEM_DEVICE, C.c_void_p(sh) if sh else None, _ptr(o.get("qdist")),
                      _ptr(o.get("probes")), _ptr(o.get("bits")), _ptr(o.get("coarse")), _ptr(ms),
-                     AMP_SEARCH_GRAPH if graph else 0)
+                     AMP_SEARCH_GRAPH if graph else 0, qd)
         _check(lib().amp_search(index.handle, _ptr(queries), nq, _ptr(kk), _ptr(npb), per_query,
                                 C.byref(pol), C.byref(opts), _ptr(o["ids"]), _ptr(o["dist"])))
         if stage_ms:
             o["stage_ms"] = dict(zip(STAGES, ms.tolist()))
         return o
-    q = np.ascontiguousarray(queries, dtype=np.float32)
+    q = np.ascontiguousarray(queries, dtype=np.uint16 if qd == AMP_BF16 else np.float32)
     res = dict(ids=np.empty((nq, kmax), np.int64), dist=np.empty((nq, kmax), np.float32))
     if want_qdist:
         res["qdist"] = np.empty((nq, kmax), np.int64)
@@ -355,9 +365,97 @@ def amp_search(index, queries, k, nprobe, policy="fixed", bits=16, allowed=(4, 8
         res["coarse"] = np.empty((nq, info["nlist"]), np.float32)
     opts = _Opts(AMP_MEM_HOST, None, _ptr(res.get("qdist")), _ptr(res.get("probes")),
                  _ptr(res.get("bits")), _ptr(res.get("coarse")), _ptr(ms),
-                 AMP_SEARCH_GRAPH if graph else 0)
+                 AMP_SEARCH_GRAPH if graph else 0, qd)
     _check(lib().amp_search(index.handle, _ptr(q), nq, _ptr(kk), _ptr(npb), per_query,
                             C.byref(pol), C.byref(opts), _ptr(res["ids"]), _ptr(res["dist"])))
     if stage_ms:
         res["stage_ms"] = dict(zip(STAGES, ms.tolist()))
     return res
+
+
+# ------------------------------------------------------------------ serving loop
+DONE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int32)
+
+
+class _ServerConfig(C.Structure):
+    _fields_ = [("max_batch", C.c_int32), ("max_pending", C.c_int32), ("max_k", C.c_int32),
+                ("max_nprobe", C.c_int32), ("batch_window_us", C.c_int32), ("q_dtype", C.c_int32),
+                ("policy", _Policy)]
+
+
+class _Request(C.Structure):
+    _fields_ = [("query", C.c_void_p), ("k", C.c_int32), ("nprobe", C.c_int32), ("out_ids", C.c_void_p),
+                ("out_dist", C.c_void_p), ("out_qdist", C.c_void_p), ("done", DONE_FN), ("user", C.c_void_p),
+                ("policy", C.c_void_p), ("arrival_ns", C.c_int64)]
+
+
+class _Report(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("submitted", "rejected", "completed", "cancelled", "failed", "batches",
+                                         "pending", "in_flight")] + \
+               [(n, C.c_double) for n in ("elapsed_s", "qps", "mean_batch", "p50_ms", "p99_ms", "max_ms")]
+
+
+class Server:
+    """Owning wrapper of an amp_server handle.  Buffers and callbacks of
+    submitted requests are kept alive here until flush()."""
+
+    def __init__(self, handle, index, q_dtype):
+        self.handle = C.c_void_p(handle)
+        self.index = index  # the index must outlive the server
+        self.q_dtype = q_dtype
+        self._keep = []
+
+    def __del__(self):
+        self.close()
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value and _lib is not None:
+            _lib.amp_server_destroy(self.handle)
+            self.handle = C.c_void_p(None)
+            self._keep = []
+
+
+def amp_server_create(index, max_batch=1024, max_pending=0, max_k=100, max_nprobe=0, batch_window_us=0,
+                      q_dtype="f32", policy="fixed", bits=16, allowed=(4, 8, 12, 16), margin_q40=0, lut_dtype=0):
+    pol, _ = make_policy(policy, bits, allowed, margin_q40, None, lut_dtype)
+    qd = AMP_BF16 if q_dtype == "bf16" else AMP_F32
+    cfg = _ServerConfig(int(max_batch), int(max_pending), int(max_k), int(max_nprobe), int(batch_window_us), qd, pol)
+    h = C.c_void_p()
+    _check(lib().amp_server_create(index.handle, C.byref(cfg), C.byref(h)))
+    return Server(h.value, index, qd)
+
+
+def amp_server_submit(server, query, k, nprobe, out_ids, out_dist, out_qdist=None, done=None, arrival_ns=0,
+                      policy=None):
+    """Queue one request.  ``query``: host row (float32, or uint16 bfloat16
+    patterns for a BF16 server); ``out_*``: host numpy buffers of >= k
+    entries; ``done(status)``: optional callable run on the server thread;
+    ``policy``: None or a make_policy() tuple.  Returns the ticket."""
+    q = np.ascontiguousarray(query, dtype=np.uint16 if server.q_dtype == AMP_BF16 else np.float32)
+    cb = DONE_FN(lambda user, st: done(st)) if done is not None else DONE_FN()
+    pol = policy[0] if policy is not None else None
+    r = _Request(_ptr(q), int(k), int(nprobe), _ptr(out_ids), _ptr(out_dist), _ptr(out_qdist), cb, None,
+                 C.cast(C.pointer(pol), C.c_void_p) if pol is not None else None, int(arrival_ns))
+    t = C.c_uint64()
+    _check(lib().amp_server_submit(server.handle, C.byref(r), C.byref(t)))
+    server._keep.append((out_ids, out_dist, out_qdist, cb, pol))
+    return t.value
+
+
+def amp_server_cancel(server, ticket):
+    _check(lib().amp_server_cancel(server.handle, C.c_uint64(ticket)))
+
+
+def amp_server_flush(server):
+    _check(lib().amp_server_flush(server.handle))
+    server._keep = []
+
+
+def amp_server_stats(server, reset=False):
+    r = _Report()
+    _check(lib().amp_server_stats(server.handle, C.byref(r), int(bool(reset))))
+    return {n: getattr(r, n) for n, _ in _Report._fields_}
+
+
+def amp_server_destroy(server):
+    server.close()

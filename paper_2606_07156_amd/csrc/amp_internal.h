@@ -63,10 +63,13 @@ struct DeviceIndex {
 
 // Scratch of one search, grown on demand and kept with the index.
 struct Workspace {
-  std::vector<void*> blocks;
+  std::vector<void*> blocks;   // device allocations
   size_t cap_nq = 0, cap_np = 0, cap_k = 0;
   // per query
-  float* queries = nullptr;    // [nq][d] (host-mode staging)
+  float* queries = nullptr;    // [nq][d] (host-mode staging, converted BF16 queries)
+  uint16_t* qraw = nullptr;    // [nq][d] BF16 queries staged from the host
+  int32_t* hstage = nullptr;   // pinned host [2][nq]: per-query k and nprobe on their way up
+  hipEvent_t ev_stage = nullptr;  // the last upload from hstage has run
   int32_t* kq = nullptr;       // [nq]
   int32_t* npq = nullptr;      // [nq]
   float* qnorm = nullptr;      // [nq]
@@ -112,12 +115,14 @@ struct GraphKey {
   int64_t chunk, chunk1;
   size_t capq;
   int32_t wpr;
+  int32_t q_dtype;
   bool operator==(const GraphKey& o) const {
     return q == o.q && ids == o.ids && dist == o.dist && qdist == o.qdist && probes == o.probes &&
            bits == o.bits && coarse == o.coarse && stream == o.stream && nq == o.nq && k == o.k &&
            nprobe == o.nprobe && kind == o.kind && fixed_bits == o.fixed_bits && allowed == o.allowed &&
            margin == o.margin && lut_dtype == o.lut_dtype && ws_gen == o.ws_gen && model_gen == o.model_gen &&
-           chunk == o.chunk && chunk1 == o.chunk1 && capq == o.capq && wpr == o.wpr;
+           chunk == o.chunk && chunk1 == o.chunk1 && capq == o.capq && wpr == o.wpr &&
+           q_dtype == o.q_dtype;
   }
 };
 }  // namespace amp
@@ -167,6 +172,8 @@ struct SearchDims {
   int64_t chunk1;        // the same for the phase-1 bound (latency-bound: shorter)
   int64_t max_units;     // capacity of each phase's unit table
   size_t capq;
+  const uint16_t* q_bf16;  // BF16 query rows to widen into q_conv first (null: FP32 queries)
+  float* q_conv;
   int policy;            // AMP_POLICY_*
   int lut_dtype;         // AMP_LUT_* (0 = BF16)
   int fixed_bits;
@@ -199,6 +206,11 @@ hipError_t launch_assign(const float* X, int64_t n, int dd, int ld, const float*
 // out [n][d] = X [n][d] - C[a[i]]
 hipError_t launch_residual(const float* X, const int32_t* a, const float* C, int64_t n, int d, float* out,
                            hipStream_t st);
+
+// grow the index's search workspace to hold any search of at most nq queries,
+// npmax probes and k <= kmax (a caller that must not stall on a reallocation
+// while searches are in flight reserves up front); takes the index lock
+amp_status reserve_workspace(amp_index* ix, int64_t nq, int npmax, int kmax);
 
 // LUT words per row of the scan variants a search runs (the queue packs its
 // work units to match)

@@ -177,9 +177,9 @@ amp_status kmeans(const float* rows, int64_t n, int dd, int k, int iters, uint64
 
 using namespace amp;
 
-extern "C" amp_status amp_index_build(const float* base, int64_t n, int32_t d, const int64_t* ids,
+extern "C" amp_status amp_index_build(const void* base_in, int64_t n, int32_t d, const int64_t* ids,
                                       const amp_build_params* prm, amp_index** out) {
-  if (!base || !prm || !out) return set_error(AMP_EINVAL, "null argument");
+  if (!base_in || !prm || !out) return set_error(AMP_EINVAL, "null argument");
   *out = nullptr;
   const int nlist = prm->nlist, M = prm->M;
   if (d <= 0 || M <= 0 || nlist <= 0 || n < 1) return set_error(AMP_EINVAL, "d, M, nlist, n must be positive");
@@ -193,12 +193,28 @@ extern "C" amp_status amp_index_build(const float* base, int64_t n, int32_t d, c
   if (prm->metric != AMP_L2 && prm->metric != AMP_IP) return set_error(AMP_EINVAL, "bad metric %d", prm->metric);
   if (prm->grid_kind != AMP_GRID_U9 && prm->grid_kind != AMP_GRID_E4M3)
     return set_error(AMP_EINVAL, "bad grid kind %d", prm->grid_kind);
+  if (prm->base_dtype != AMP_F32 && prm->base_dtype != AMP_BF16)
+    return set_error(AMP_EINVAL, "bad base dtype %d", prm->base_dtype);
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
     (void)hipGetLastError();
     return set_error(AMP_EDEVICE, "no HIP device");
   }
   const int dsub = d / M, iters = prm->kmeans_iters;
+  // BF16 rows widened once (exact: the bit pattern is the top half)
+  std::vector<float> widened;
+  const float* base = static_cast<const float*>(base_in);
+  if (prm->base_dtype == AMP_BF16) {
+    widened.resize((size_t)n * d);
+    const uint16_t* b16 = static_cast<const uint16_t*>(base_in);
+    parallel_for((int64_t)n * d, [&](int64_t i0, int64_t i1, int) {
+      for (int64_t i = i0; i < i1; ++i) {
+        const uint32_t u = (uint32_t)b16[i] << 16;
+        std::memcpy(&widened[i], &u, 4);
+      }
+    });
+    base = widened.data();
+  }
   hipStream_t st = nullptr;
   AMP_BHIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
   struct StreamGuard {

@@ -55,6 +55,8 @@ static void free_device_index(DeviceIndex& d) {
 
 static void free_workspace(Workspace& w) {
   for (void* p : w.blocks) hipFree(p);
+  if (w.hstage) hipHostFree(w.hstage);
+  if (w.ev_stage) hipEventDestroy(w.ev_stage);
   w = Workspace();
 }
 
@@ -433,11 +435,13 @@ static amp_status ensure_workspace(amp_index* ix, size_t nq, size_t np, size_t k
   np = std::max(np, w.cap_np);
   kmax = std::max(kmax, w.cap_k);
   units = std::max(units, w.cap_units);
+  // the scratch space may still be in use by an earlier search
+  if (ix->dev.ev_done) AMP_HIP(hipEventSynchronize(ix->dev.ev_done));
   free_workspace(w);
   const size_t NB = (size_t)kNCls * ix->nlist, npairs = nq * np;
   std::vector<void*>* t = &w.blocks;
   amp_status s;
-  if ((s = dalloc(&w.queries, nq * ix->d, t)) || (s = dalloc(&w.kq, nq, t)) || (s = dalloc(&w.npq, nq, t)) ||
+  if ((s = dalloc(&w.queries, nq * ix->d, t)) || (s = dalloc(&w.qraw, nq * ix->d, t)) || (s = dalloc(&w.kq, nq, t)) || (s = dalloc(&w.npq, nq, t)) ||
       (s = dalloc(&w.qnorm, nq, t)) || (s = dalloc(&w.coarse, nq * ix->nlist, t)) ||
       (s = dalloc(&w.probes, npairs, t)) ||
       (s = dalloc(&w.pbits, npairs, t)) || (s = dalloc(&w.xbits, npairs, t)) || (s = dalloc(&w.tau, nq, t)) ||
@@ -451,6 +455,13 @@ static amp_status ensure_workspace(amp_index* ix, size_t nq, size_t np, size_t k
     free_workspace(w);
     return s;
   }
+  if (hipHostMalloc(reinterpret_cast<void**>(&w.hstage), 2 * nq * sizeof(int32_t), hipHostMallocDefault) !=
+          hipSuccess ||
+      hipEventCreateWithFlags(&w.ev_stage, hipEventDisableTiming) != hipSuccess) {
+    hipGetLastError();
+    free_workspace(w);
+    return set_error(AMP_ENOMEM, "pinned staging allocation failed");
+  }
   ix->ws_generation++;
   w.cap_nq = nq;
   w.cap_np = np;
@@ -460,13 +471,51 @@ static amp_status ensure_workspace(amp_index* ix, size_t nq, size_t np, size_t k
   return AMP_OK;
 }
 
-amp_status amp_search(amp_index* ix, const float* queries, int64_t nq, const int32_t* k, const int32_t* nprobe,
+// capacity of the candidate buffer, list chunk lengths and the unit-table
+// size of a search (shared by the search and by workspace reservation)
+struct SearchPlan {
+  size_t capq;
+  int64_t chunk, chunk1, max_units;
+};
+
+static SearchPlan plan_search(const amp_index* ix, int64_t nq, int npmax, int kmax, bool worst_case) {
+  SearchPlan p;
+  // candidate capacity per query: a power of two (the merge sorts up to capq
+  // keys in place, 16 bytes each in LDS: at most 8192), at least kmax
+  p.capq = 16;
+  while ((p.capq < env_size("AMP_CAPQ", 4096) || p.capq < (size_t)kmax) && p.capq < (1u << 13)) p.capq <<= 1;
+  // list chunk of a work unit, phase 2 and the phase-1 bound.  Whole lists
+  // when the batch has enough units to fill the chip (each chunk rebuilds
+  // its pairs' LUTs, and a chunked phase 1 gives a looser bound); otherwise
+  // (few queries, long lists: the streaming case) chunks sized for about four
+  // (phase 2) or two (phase 1) units per workgroup slot of the chip, at least
+  // 4096 vectors.  AMP_CHUNK / AMP_CHUNK1 override.  The worst case (any
+  // smaller batch) is the shortest chunk.
+  const int64_t mean_list = std::max<int64_t>(1, ix->n / ix->nlist);
+  const int64_t slots = 512;  // persistent workgroups: 256 CUs x 2
+  auto pick_chunk = [&](int64_t pairs, int64_t per_slot, const char* env) -> int64_t {
+    const int64_t c = (int64_t)env_size(env, 0);
+    if (c > 0) return c;
+    if (worst_case) return 4096;
+    return std::min<int64_t>(1 << 16, std::max<int64_t>(4096, pairs * mean_list / (per_slot * slots)));
+  };
+  p.chunk = pick_chunk(nq * npmax, 4, "AMP_CHUNK");
+  p.chunk1 = pick_chunk(nq, 2, "AMP_CHUNK1");
+  const int64_t max_nch = std::max<int64_t>(1, (ix->max_list + p.chunk - 1) / p.chunk);
+  const int64_t max_nch1 = std::max<int64_t>(1, (ix->max_list + p.chunk1 - 1) / p.chunk1);
+  p.max_units = std::max<int64_t>(nq * npmax * max_nch, nq * max_nch1);
+  return p;
+}
+
+amp_status amp_search(amp_index* ix, const void* queries, int64_t nq, const int32_t* k, const int32_t* nprobe,
                       int32_t per_query, const amp_precision_policy* pol, const amp_search_opts* opts,
                       int64_t* out_ids, float* out_dist) {
   if (!ix || !queries || !k || !nprobe || !pol || !opts || !out_ids || !out_dist)
     return set_error(AMP_EINVAL, "null argument");
   if (nq <= 0 || nq > (1 << 24)) return set_error(AMP_EINVAL, "nq %lld out of range", (long long)nq);
   if (opts->mem != AMP_MEM_HOST && opts->mem != AMP_MEM_DEVICE) return set_error(AMP_EINVAL, "bad mem kind");
+  if (opts->q_dtype != AMP_F32 && opts->q_dtype != AMP_BF16)
+    return set_error(AMP_EINVAL, "bad query dtype %d", opts->q_dtype);
   const int npmax_lim = std::min(ix->nlist, AMP_MAX_NPROBE);
   int kmax = 0, npmax = 0;
   const int64_t nk = per_query ? nq : 1;
@@ -511,48 +560,45 @@ amp_status amp_search(amp_index* ix, const float* queries, int64_t nq, const int
   amp_status s = to_device_locked(ix, dev);
   if (s != AMP_OK) return s;
   if (pol->kind == AMP_POLICY_ADAPTIVE && ix->dev_model_stale && (s = upload_model(ix)) != AMP_OK) return s;
-  // candidate capacity per query: a power of two (the merge sorts up to capq
-  // keys in place, 16 bytes each in LDS: at most 8192), at least kmax
-  size_t capq = 16;
-  while ((capq < env_size("AMP_CAPQ", 4096) || capq < (size_t)kmax) && capq < (1u << 13)) capq <<= 1;
-  // list chunk of a work unit, phase 2 and the phase-1 bound.  Whole lists
-  // when the batch has enough units to fill the chip (each chunk rebuilds
-  // its pairs' LUTs, and a chunked phase 1 gives a looser bound); otherwise
-  // (few queries, long lists: the streaming case) chunks sized for about four
-  // (phase 2) or two (phase 1) units per workgroup slot of the chip, at least
-  // 4096 vectors.  AMP_CHUNK / AMP_CHUNK1 override.
-  const int64_t mean_list = std::max<int64_t>(1, ix->n / ix->nlist);
-  const int64_t slots = 512;  // persistent workgroups: 256 CUs x 2
-  auto pick_chunk = [&](int64_t pairs, int64_t per_slot, const char* env) -> int64_t {
-    const int64_t c = (int64_t)env_size(env, 0);
-    if (c > 0) return c;
-    return std::min<int64_t>(1 << 16, std::max<int64_t>(4096, pairs * mean_list / (per_slot * slots)));
-  };
-  const int64_t chunk = pick_chunk((int64_t)nq * npmax, 4, "AMP_CHUNK");
-  const int64_t chunk1 = pick_chunk((int64_t)nq, 2, "AMP_CHUNK1");
-  const int64_t max_nch = std::max<int64_t>(1, (ix->max_list + chunk - 1) / chunk);
-  const int64_t max_nch1 = std::max<int64_t>(1, (ix->max_list + chunk1 - 1) / chunk1);
-  const int64_t max_units = std::max<int64_t>((int64_t)nq * npmax * max_nch, (int64_t)nq * max_nch1);
-  if (opts->mem != AMP_MEM_HOST && (reinterpret_cast<uintptr_t>(queries) & 15))
-    return set_error(AMP_EINVAL, "device query buffer must be 16-byte aligned");
+  const SearchPlan plan = plan_search(ix, nq, npmax, kmax, false);
+  const size_t capq = plan.capq;
+  const int64_t chunk = plan.chunk, chunk1 = plan.chunk1, max_units = plan.max_units;
+  const bool bf16 = opts->q_dtype == AMP_BF16;
+  if (opts->mem != AMP_MEM_HOST && (reinterpret_cast<uintptr_t>(queries) & (bf16 ? 1 : 15)))
+    return set_error(AMP_EINVAL, "device query buffer must be %d-byte aligned", bf16 ? 2 : 16);
   if ((s = ensure_workspace(ix, nq, npmax, kmax, capq, max_units)) != AMP_OK) return s;
   Workspace& w = ix->ws;
   hipStream_t st = reinterpret_cast<hipStream_t>(opts->stream);
   const bool host = opts->mem == AMP_MEM_HOST;
   // the scratch space is reused: start after the previous search on this index
   AMP_HIP(hipStreamWaitEvent(st, ix->dev.ev_done, 0));
-  const float* qdev = queries;
+  const float* qdev = static_cast<const float*>(queries);
+  const uint16_t* qbf = bf16 ? static_cast<const uint16_t*>(queries) : nullptr;
   if (host) {
-    AMP_HIP(hipMemcpyAsync(w.queries, queries, (size_t)nq * ix->d * 4, hipMemcpyHostToDevice, st));
-    qdev = w.queries;
+    if (bf16) {
+      AMP_HIP(hipMemcpyAsync(w.qraw, queries, (size_t)nq * ix->d * 2, hipMemcpyHostToDevice, st));
+      qbf = w.qraw;
+    } else {
+      AMP_HIP(hipMemcpyAsync(w.queries, queries, (size_t)nq * ix->d * 4, hipMemcpyHostToDevice, st));
+      qdev = w.queries;
+    }
   }
+  if (bf16) qdev = w.queries;  // widened there by the first kernel
   if (per_query) {
-    AMP_HIP(hipMemcpyAsync(w.kq, k, nq * 4, hipMemcpyHostToDevice, st));
-    AMP_HIP(hipMemcpyAsync(w.npq, nprobe, nq * 4, hipMemcpyHostToDevice, st));
+    // through pinned staging, so that the copy is stream-ordered and the call
+    // need not wait for earlier work on the stream; the staging area is free
+    // once the previous upload from it has run
+    AMP_HIP(hipEventSynchronize(w.ev_stage));
+    std::memcpy(w.hstage, k, nq * 4);
+    std::memcpy(w.hstage + nq, nprobe, nq * 4);
+    AMP_HIP(hipMemcpyAsync(w.kq, w.hstage, nq * 4, hipMemcpyHostToDevice, st));
+    AMP_HIP(hipMemcpyAsync(w.npq, w.hstage + nq, nq * 4, hipMemcpyHostToDevice, st));
+    AMP_HIP(hipEventRecord(w.ev_stage, st));
   }
-  if (pol->kind == AMP_POLICY_EXPLICIT)
+  if (pol->kind == AMP_POLICY_EXPLICIT) {
     AMP_HIP(hipMemcpyAsync(w.xbits, pol->explicit_bits, (size_t)nq * npmax, hipMemcpyHostToDevice, st));
-  if (per_query && !host) AMP_HIP(hipStreamSynchronize(st));  // host arrays may go away after return
+    if (!host) AMP_HIP(hipStreamSynchronize(st));  // the host array may go away after return
+  }
   SearchDims sd;
   sd.nq = (int)nq;
   sd.d = ix->d;
@@ -576,6 +622,8 @@ amp_status amp_search(amp_index* ix, const float* queries, int64_t nq, const int
   }
   sd.chunk = chunk;
   sd.chunk1 = chunk1;
+  sd.q_bf16 = qbf;
+  sd.q_conv = w.queries;
   sd.max_units = w.cap_units;
   sd.capq = capq;
   sd.policy = pol->kind;
@@ -628,9 +676,10 @@ amp_status amp_search(amp_index* ix, const float* queries, int64_t nq, const int
   hipError_t he = hipSuccess;
   if (use_graph) {
     // one captured graph per index, replayed while the launch key is unchanged
-    GraphKey key{qdev, out_ids, out_dist, opts->out_qdist, opts->out_probes, opts->out_bits, opts->out_coarse,
+    GraphKey key{queries, out_ids, out_dist, opts->out_qdist, opts->out_probes, opts->out_bits, opts->out_coarse,
                  st, nq, k[0], nprobe[0], pol->kind, pol->fixed_bits, sd.allowed_mask, pol->margin_q40,
-                 pol->lut_dtype, ix->ws_generation, ix->model_generation, chunk, chunk1, capq, sd.wpr};
+                 pol->lut_dtype, ix->ws_generation, ix->model_generation, chunk, chunk1, capq, sd.wpr,
+                 opts->q_dtype};
     if (!ix->graph_exec || !(ix->graph_key == key)) {
       if (ix->graph_exec) hipGraphExecDestroy(ix->graph_exec);
       ix->graph_exec = nullptr;
@@ -721,3 +770,11 @@ amp_status amp_search(amp_index* ix, const float* queries, int64_t nq, const int
 }
 
 }  // extern "C"
+
+namespace amp {
+amp_status reserve_workspace(amp_index* ix, int64_t nq, int npmax, int kmax) {
+  std::lock_guard<std::mutex> lk(ix->mu);
+  const SearchPlan p = plan_search(ix, nq, npmax, kmax, true);
+  return ensure_workspace(ix, nq, npmax, kmax, p.capq, p.max_units);
+}
+}  // namespace amp

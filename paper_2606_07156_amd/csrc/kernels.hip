@@ -137,6 +137,12 @@ __global__ __launch_bounds__(256) void k_coarse(const float* __restrict__ Q, con
       }
 }
 
+// bfloat16 bit patterns to FP32 (exact: the pattern is the top half)
+__global__ void k_bf16_widen(const uint16_t* __restrict__ in, float* __restrict__ out, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    out[i] = __uint_as_float((uint32_t)in[i] << 16);
+}
+
 // ------------------------------------------------------------------ index build
 // squared norms of n rows of dd floats with leading dimension ld (a wave per row)
 __global__ void k_sqnorm_ld(const float* __restrict__ X, int64_t n, int dd, int ld, float* __restrict__ out) {
@@ -1765,7 +1771,7 @@ hipError_t launch_residual(const float* X, const int32_t* a, const float* C, int
   return hipGetLastError();
 }
 
-hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* queries, const SearchDims& sd,
+hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* queries_in, const SearchDims& sd,
                          const ModelArgs& ma, int64_t* out_ids, float* out_dist, int64_t* out_qdist,
                          float* out_coarse, hipStream_t st, hipEvent_t* ev) {
   const DeviceIndex& dv = ix->dev;
@@ -1775,6 +1781,14 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   const size_t npairs = (size_t)sd.nq * sd.npmax;
   auto mark = [&](int i) { if (ev) (void)hipEventRecord(ev[i], st); };
   mark(0);
+  // BF16 query rows are widened first (exact)
+  const float* queries = queries_in;
+  if (sd.q_bf16) {
+    const size_t nel = (size_t)sd.nq * sd.d;
+    hipLaunchKernelGGL(k_bf16_widen, dim3((unsigned)std::min<size_t>((nel + 255) / 256, 65536)), dim3(256), 0, st,
+                       sd.q_bf16, sd.q_conv, nel);
+    queries = sd.q_conv;
+  }
   // CL
   hipLaunchKernelGGL(k_sqnorm, dim3((sd.nq + 3) / 4), dim3(256), 0, st, queries, sd.nq, sd.d, ws.qnorm);
   float* coarse = out_coarse ? out_coarse : ws.coarse;

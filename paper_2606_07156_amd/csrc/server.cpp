@@ -1,0 +1,482 @@
+// Serving loop: continuous batching of single-query requests onto the search
+// path of one device.
+//
+// Requests are admitted into a fixed pool of pinned query slots (the memory
+// bound of the queue: a full pool rejects with AMP_EBUSY), gathered into
+// batches of requests sharing a precision policy, and each batch runs as one
+// device-mode search with per-query k and nprobe.  Two batches may be in
+// flight: the worker launches batch i+1 (query upload, search, result copies,
+// all stream-ordered) before it waits for batch i, so the host-side gather,
+// scatter and callbacks overlap device work.  Latency runs from a request's
+// arrival stamp to the moment its results are in the caller's buffers.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "amp_internal.h"
+
+namespace amp {
+namespace {
+
+int64_t now_ns() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+bool same_policy(const amp_precision_policy& a, const amp_precision_policy& b) {
+  return a.kind == b.kind && a.fixed_bits == b.fixed_bits && a.allowed_bits_mask == b.allowed_bits_mask &&
+         a.lut_dtype == b.lut_dtype && a.margin_q40 == b.margin_q40;
+}
+
+struct Request {
+  uint64_t ticket;
+  int32_t k, nprobe, slot;
+  int64_t* out_ids;
+  float* out_dist;
+  int64_t* out_qdist;
+  void (*done)(void*, amp_status);
+  void* user;
+  int64_t arrival_ns;
+  amp_precision_policy policy;
+  bool cancelled;
+};
+
+struct Batch {  // one in-flight search and its staging set
+  std::vector<Request*> reqs;
+  int set = 0, kmax = 0;
+  amp_status status = AMP_OK;
+};
+
+struct Staging {  // per in-flight batch
+  void* hq = nullptr;        // pinned [max_batch][d] query rows
+  int64_t* hids = nullptr;   // pinned [max_batch][max_k]
+  float* hdist = nullptr;
+  int64_t* hqd = nullptr;
+  void* dq = nullptr;        // device copies
+  int64_t* dids = nullptr;
+  float* ddist = nullptr;
+  int64_t* dqd = nullptr;
+  hipEvent_t ev = nullptr;   // results copied back
+};
+
+}  // namespace
+}  // namespace amp
+
+using namespace amp;
+
+struct amp_server {
+  amp_index* ix = nullptr;
+  amp_server_config cfg{};
+  int device = 0, d = 0, esize = 4;
+  hipStream_t stream = nullptr;
+  // admission pool
+  void* pool = nullptr;  // pinned [max_pending][d] query rows
+  std::vector<int32_t> free_slots;
+  Staging stg[2];
+  std::mutex mu;
+  std::condition_variable cv_work, cv_idle;
+  std::deque<Request*> pending;
+  std::unordered_map<uint64_t, Request*> live;  // pending or in flight
+  std::deque<Batch> inflight;
+  uint64_t next_ticket = 1;
+  bool stopping = false;
+  // statistics since creation or the last reset
+  int64_t submitted = 0, rejected = 0, completed = 0, cancelled = 0, failed = 0, batches = 0, batched = 0;
+  int64_t t0 = 0;
+  std::vector<float> lat_ms;
+  std::thread worker;
+
+  ~amp_server();
+  amp_status init();
+  void run();
+  void launch(Batch& b);
+  void complete(Batch& b);
+};
+
+static constexpr size_t kMaxLatencySamples = 1u << 24;
+
+amp_server::~amp_server() {
+  (void)hipSetDevice(device);
+  for (Staging& s : stg) {
+    if (s.ev) (void)hipEventDestroy(s.ev);
+    void* host[] = {s.hq, s.hids, s.hdist, s.hqd};
+    for (void* p : host)
+      if (p) (void)hipHostFree(p);
+    void* dev[] = {s.dq, s.dids, s.ddist, s.dqd};
+    for (void* p : dev)
+      if (p) (void)hipFree(p);
+  }
+  if (pool) (void)hipHostFree(pool);
+  if (stream) (void)hipStreamDestroy(stream);
+}
+
+amp_status amp_server::init() {
+  const size_t B = cfg.max_batch, K = cfg.max_k, row = (size_t)d * esize;
+  auto hfail = [](const char* what) {
+    (void)hipGetLastError();
+    return set_error(AMP_ENOMEM, "server: %s allocation failed", what);
+  };
+  if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) return hfail("stream");
+  if (hipHostMalloc(&pool, (size_t)cfg.max_pending * row, hipHostMallocDefault) != hipSuccess) return hfail("pool");
+  for (Staging& s : stg) {
+    if (hipHostMalloc(&s.hq, B * row, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&s.hids), B * K * 8, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&s.hdist), B * K * 4, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&s.hqd), B * K * 8, hipHostMallocDefault) != hipSuccess)
+      return hfail("pinned staging");
+    if (hipMalloc(&s.dq, B * row) != hipSuccess || hipMalloc(reinterpret_cast<void**>(&s.dids), B * K * 8) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&s.ddist), B * K * 4) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&s.dqd), B * K * 8) != hipSuccess)
+      return hfail("device staging");
+    if (hipEventCreateWithFlags(&s.ev, hipEventDisableTiming) != hipSuccess) return hfail("event");
+  }
+  free_slots.resize(cfg.max_pending);
+  for (int32_t i = 0; i < cfg.max_pending; ++i) free_slots[i] = cfg.max_pending - 1 - i;
+  // size the search scratch for the largest batch now: growing it later
+  // would wait for the batch in flight
+  amp_status s = amp_index_to_device(ix, device);
+  if (s == AMP_OK) s = reserve_workspace(ix, cfg.max_batch, cfg.max_nprobe, cfg.max_k);
+  return s;
+}
+
+// gather the batch's queries into its staging set and enqueue upload,
+// search and result copies on the server stream
+void amp_server::launch(Batch& b) {
+  Staging& s = stg[b.set];
+  const size_t row = (size_t)d * esize;
+  const int n = (int)b.reqs.size();
+  std::vector<int32_t> kv(n), npv(n);
+  for (int i = 0; i < n; ++i) {
+    Request* r = b.reqs[i];
+    std::memcpy(static_cast<char*>(s.hq) + i * row, static_cast<char*>(pool) + (size_t)r->slot * row, row);
+    kv[i] = r->k;
+    npv[i] = r->nprobe;
+    b.kmax = std::max(b.kmax, r->k);
+  }
+  {
+    std::lock_guard<std::mutex> lk(mu);  // the rows are copied: the slots take new requests
+    for (Request* r : b.reqs) free_slots.push_back(r->slot);
+  }
+  hipError_t e = hipMemcpyAsync(s.dq, s.hq, n * row, hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    b.status = set_error(AMP_EDEVICE, "server: query upload failed: %s", hipGetErrorString(e));
+    return;
+  }
+  amp_search_opts o{};
+  o.mem = AMP_MEM_DEVICE;
+  o.stream = stream;
+  o.out_qdist = s.dqd;
+  o.q_dtype = cfg.q_dtype;
+  b.status = amp_search(ix, s.dq, n, kv.data(), npv.data(), 1, &b.reqs[0]->policy, &o, s.dids, s.ddist);
+  if (b.status != AMP_OK) return;
+  const size_t nk = (size_t)n * b.kmax;
+  if ((e = hipMemcpyAsync(s.hids, s.dids, nk * 8, hipMemcpyDeviceToHost, stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(s.hdist, s.ddist, nk * 4, hipMemcpyDeviceToHost, stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(s.hqd, s.dqd, nk * 8, hipMemcpyDeviceToHost, stream)) != hipSuccess ||
+      (e = hipEventRecord(s.ev, stream)) != hipSuccess) {
+    (void)hipGetLastError();
+    b.status = set_error(AMP_EDEVICE, "server: result copy failed: %s", hipGetErrorString(e));
+  }
+}
+
+// wait for the batch, hand each request its rows, run the callbacks
+void amp_server::complete(Batch& b) {
+  Staging& s = stg[b.set];
+  if (b.status == AMP_OK) {
+    const hipError_t e = hipEventSynchronize(s.ev);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      b.status = set_error(AMP_EDEVICE, "server: batch failed: %s", hipGetErrorString(e));
+    }
+  }
+  std::vector<std::pair<Request*, amp_status>> fin;
+  fin.reserve(b.reqs.size());
+  const int64_t t = now_ns();
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    for (size_t i = 0; i < b.reqs.size(); ++i) {
+      Request* r = b.reqs[i];
+      live.erase(r->ticket);
+      amp_status st = b.status;
+      if (r->cancelled) {
+        st = AMP_ECANCELED;
+        ++cancelled;
+      } else if (st == AMP_OK) {
+        std::memcpy(r->out_ids, s.hids + i * b.kmax, r->k * 8);
+        std::memcpy(r->out_dist, s.hdist + i * b.kmax, r->k * 4);
+        if (r->out_qdist) std::memcpy(r->out_qdist, s.hqd + i * b.kmax, r->k * 8);
+        ++completed;
+        if (lat_ms.size() < kMaxLatencySamples) lat_ms.push_back((float)((t - r->arrival_ns) * 1e-6));
+      } else {
+        ++failed;
+      }
+      fin.emplace_back(r, st);
+    }
+  }
+  for (auto& [r, st] : fin) {
+    if (r->done) r->done(r->user, st);
+    delete r;
+  }
+}
+
+void amp_server::run() {
+  (void)hipSetDevice(device);
+  int next_set = 0;
+  for (;;) {
+    Batch b;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      if (inflight.empty()) {
+        cv_idle.notify_all();
+        cv_work.wait(lk, [&] { return stopping || !pending.empty(); });
+        if (pending.empty()) break;  // stopping and drained
+        // an idle device may wait a little for the batch to fill
+        if (cfg.batch_window_us > 0 && !stopping && (int)pending.size() < cfg.max_batch) {
+          const auto until = std::chrono::steady_clock::time_point(std::chrono::nanoseconds(
+              pending.front()->arrival_ns + (int64_t)cfg.batch_window_us * 1000));
+          cv_work.wait_until(lk, until, [&] { return stopping || (int)pending.size() >= cfg.max_batch; });
+        }
+      }
+      // requests of the oldest one's policy, in arrival order
+      const amp_precision_policy pol = pending.empty() ? amp_precision_policy{} : pending.front()->policy;
+      for (auto it = pending.begin(); it != pending.end() && (int)b.reqs.size() < cfg.max_batch;) {
+        if (same_policy((*it)->policy, pol)) {
+          b.reqs.push_back(*it);
+          it = pending.erase(it);
+        } else {
+          ++it;
+        }
+      }
+      if (!b.reqs.empty()) {
+        b.set = next_set;
+        next_set ^= 1;
+        ++batches;
+        batched += (int64_t)b.reqs.size();
+      }
+    }
+    if (!b.reqs.empty()) {
+      launch(b);
+      inflight.push_back(std::move(b));
+    }
+    // keep at most two batches in flight; with nothing new to launch, finish
+    // the oldest
+    if (inflight.size() == 2 || (b.reqs.empty() && !inflight.empty()) ||
+        (!inflight.empty() && inflight.front().status != AMP_OK)) {
+      complete(inflight.front());
+      inflight.pop_front();
+    }
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      if (stopping && pending.empty() && inflight.empty()) break;
+    }
+  }
+  while (!inflight.empty()) {
+    complete(inflight.front());
+    inflight.pop_front();
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  cv_idle.notify_all();
+}
+
+static amp_status check_policy(const amp_index* ix, const amp_precision_policy& p) {
+  switch (p.kind) {
+    case AMP_POLICY_FP32: break;
+    case AMP_POLICY_FIXED:
+      if (p.fixed_bits != 4 && p.fixed_bits != 8 && p.fixed_bits != 12 && p.fixed_bits != 16)
+        return set_error(AMP_EINVAL, "fixed_bits must be 4, 8, 12 or 16");
+      break;
+    case AMP_POLICY_ADAPTIVE:
+      if (!ix->has_model) return set_error(AMP_EINVAL, "adaptive policy needs a predictor");
+      if (p.allowed_bits_mask & ~((1u << 4) | (1u << 8) | (1u << 12) | (1u << 16)))
+        return set_error(AMP_EINVAL, "allowed_bits_mask has widths outside {4,8,12,16}");
+      break;
+    case AMP_POLICY_EXPLICIT: return set_error(AMP_EINVAL, "the server does not take the explicit policy");
+    default: return set_error(AMP_EINVAL, "bad policy kind %d", p.kind);
+  }
+  if (p.lut_dtype == AMP_LUT_F8E4M3) return set_error(AMP_EUNSUPPORTED, "FP8 LUT build is not supported");
+  if (p.lut_dtype != 0 && p.lut_dtype != AMP_LUT_BF16 && p.lut_dtype != AMP_LUT_F16)
+    return set_error(AMP_EINVAL, "bad LUT build dtype %d", p.lut_dtype);
+  return AMP_OK;
+}
+
+extern "C" amp_status amp_server_create(amp_index* ix, const amp_server_config* cfg_in, amp_server** out) {
+  if (!ix || !cfg_in || !out) return set_error(AMP_EINVAL, "null argument");
+  *out = nullptr;
+  amp_server_config c = *cfg_in;
+  if (c.max_batch == 0) c.max_batch = 1024;
+  if (c.max_pending == 0) c.max_pending = 4 * c.max_batch;
+  if (c.max_k == 0) c.max_k = 100;
+  if (c.max_nprobe == 0) c.max_nprobe = std::min(ix->nlist, AMP_MAX_NPROBE);
+  if (c.max_batch < 1 || c.max_batch > 65536) return set_error(AMP_EINVAL, "max_batch %d outside [1, 65536]", c.max_batch);
+  if (c.max_pending < 1 || c.max_pending > (1 << 22))
+    return set_error(AMP_EINVAL, "max_pending %d outside [1, 2^22]", c.max_pending);
+  if (c.max_k < 1 || c.max_k > AMP_MAX_K) return set_error(AMP_EINVAL, "max_k %d outside [1, %d]", c.max_k, AMP_MAX_K);
+  if (c.max_nprobe < 1 || c.max_nprobe > std::min(ix->nlist, AMP_MAX_NPROBE))
+    return set_error(AMP_EINVAL, "max_nprobe %d outside [1, %d]", c.max_nprobe, std::min(ix->nlist, AMP_MAX_NPROBE));
+  if (c.batch_window_us < 0 || c.batch_window_us > 1000000)
+    return set_error(AMP_EINVAL, "batch_window_us %d outside [0, 1e6]", c.batch_window_us);
+  if (c.q_dtype != AMP_F32 && c.q_dtype != AMP_BF16) return set_error(AMP_EINVAL, "bad query dtype %d", c.q_dtype);
+  amp_status s = check_policy(ix, c.policy);
+  if (s != AMP_OK) return s;
+  c.policy.explicit_bits = nullptr;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(AMP_EDEVICE, "no HIP device");
+  }
+  amp_server* sv = new (std::nothrow) amp_server;
+  if (!sv) return set_error(AMP_ENOMEM, "server allocation failed");
+  sv->ix = ix;
+  sv->cfg = c;
+  sv->device = dev;
+  sv->d = ix->d;
+  sv->esize = c.q_dtype == AMP_BF16 ? 2 : 4;
+  if ((s = sv->init()) != AMP_OK) {
+    delete sv;
+    return s;
+  }
+  sv->t0 = now_ns();
+  sv->worker = std::thread([sv] { sv->run(); });
+  *out = sv;
+  return AMP_OK;
+}
+
+extern "C" amp_status amp_server_submit(amp_server* sv, const amp_request* rq, uint64_t* ticket) {
+  if (!sv || !rq || !rq->query || !rq->out_ids || !rq->out_dist) return set_error(AMP_EINVAL, "null argument");
+  if (rq->k < 1 || rq->k > sv->cfg.max_k) return set_error(AMP_EINVAL, "k = %d outside [1, %d]", rq->k, sv->cfg.max_k);
+  if (rq->nprobe < 1 || rq->nprobe > sv->cfg.max_nprobe)
+    return set_error(AMP_EINVAL, "nprobe = %d outside [1, %d]", rq->nprobe, sv->cfg.max_nprobe);
+  amp_precision_policy pol = sv->cfg.policy;
+  if (rq->policy) {
+    amp_status s = check_policy(sv->ix, *rq->policy);
+    if (s != AMP_OK) return s;
+    pol = *rq->policy;
+    pol.explicit_bits = nullptr;
+  }
+  const int64_t t = now_ns();
+  std::unique_lock<std::mutex> lk(sv->mu);
+  ++sv->submitted;
+  if (sv->stopping) {
+    ++sv->rejected;
+    return set_error(AMP_EBUSY, "server is shutting down");
+  }
+  if (sv->free_slots.empty()) {
+    ++sv->rejected;
+    return set_error(AMP_EBUSY, "admission: %d requests already queued", sv->cfg.max_pending);
+  }
+  Request* r = new (std::nothrow) Request;
+  if (!r) return set_error(AMP_ENOMEM, "request allocation failed");
+  r->slot = sv->free_slots.back();
+  sv->free_slots.pop_back();
+  const size_t row = (size_t)sv->d * sv->esize;
+  std::memcpy(static_cast<char*>(sv->pool) + (size_t)r->slot * row, rq->query, row);
+  r->ticket = sv->next_ticket++;
+  r->k = rq->k;
+  r->nprobe = rq->nprobe;
+  r->out_ids = rq->out_ids;
+  r->out_dist = rq->out_dist;
+  r->out_qdist = rq->out_qdist;
+  r->done = rq->done;
+  r->user = rq->user;
+  r->arrival_ns = rq->arrival_ns > 0 ? rq->arrival_ns : t;
+  r->policy = pol;
+  r->cancelled = false;
+  sv->pending.push_back(r);
+  sv->live.emplace(r->ticket, r);
+  if (ticket) *ticket = r->ticket;
+  lk.unlock();
+  sv->cv_work.notify_one();
+  return AMP_OK;
+}
+
+extern "C" amp_status amp_server_cancel(amp_server* sv, uint64_t ticket) {
+  if (!sv) return set_error(AMP_EINVAL, "null server");
+  Request* gone = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->live.find(ticket);
+    if (it == sv->live.end()) return set_error(AMP_EINVAL, "ticket %llu is not queued or in flight", (unsigned long long)ticket);
+    Request* r = it->second;
+    auto pit = std::find(sv->pending.begin(), sv->pending.end(), r);
+    if (pit != sv->pending.end()) {  // not launched: remove it now
+      sv->pending.erase(pit);
+      sv->live.erase(it);
+      sv->free_slots.push_back(r->slot);
+      ++sv->cancelled;
+      gone = r;
+      if (sv->pending.empty() && sv->inflight.empty()) sv->cv_idle.notify_all();
+    } else {  // in flight: its results are dropped on completion
+      r->cancelled = true;
+    }
+  }
+  if (gone) {
+    if (gone->done) gone->done(gone->user, AMP_ECANCELED);
+    delete gone;
+  }
+  return AMP_OK;
+}
+
+extern "C" amp_status amp_server_flush(amp_server* sv) {
+  if (!sv) return set_error(AMP_EINVAL, "null server");
+  if (std::this_thread::get_id() == sv->worker.get_id())
+    return set_error(AMP_EINVAL, "flush from a completion callback would never return");
+  std::unique_lock<std::mutex> lk(sv->mu);
+  sv->cv_idle.wait(lk, [&] { return sv->live.empty(); });
+  return AMP_OK;
+}
+
+extern "C" amp_status amp_server_stats(amp_server* sv, amp_server_report* out, int32_t reset) {
+  if (!sv || !out) return set_error(AMP_EINVAL, "null argument");
+  std::vector<float> lat;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    const int64_t t = now_ns();
+    out->submitted = sv->submitted;
+    out->rejected = sv->rejected;
+    out->completed = sv->completed;
+    out->cancelled = sv->cancelled;
+    out->failed = sv->failed;
+    out->batches = sv->batches;
+    out->pending = (int64_t)sv->pending.size();
+    out->in_flight = (int64_t)sv->live.size() - (int64_t)sv->pending.size();
+    out->elapsed_s = (t - sv->t0) * 1e-9;
+    out->qps = out->elapsed_s > 0 ? sv->completed / out->elapsed_s : 0.0;
+    out->mean_batch = sv->batches ? (double)sv->batched / sv->batches : 0.0;
+    lat.swap(sv->lat_ms);
+    if (reset) {
+      sv->submitted = sv->rejected = sv->completed = sv->cancelled = sv->failed = sv->batches = sv->batched = 0;
+      sv->t0 = t;
+    } else {
+      sv->lat_ms = lat;
+    }
+  }
+  out->p50_ms = out->p99_ms = out->max_ms = 0.0;
+  if (!lat.empty()) {
+    auto pct = [&](double q) {
+      const size_t i = std::min(lat.size() - 1, (size_t)(q * (double)(lat.size() - 1) + 0.5));
+      std::nth_element(lat.begin(), lat.begin() + i, lat.end());
+      return (double)lat[i];
+    };
+    out->p50_ms = pct(0.50);
+    out->p99_ms = pct(0.99);
+    out->max_ms = *std::max_element(lat.begin(), lat.end());
+  }
+  return AMP_OK;
+}
+
+extern "C" void amp_server_destroy(amp_server* sv) {
+  if (!sv) return;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->stopping = true;
+  }
+  sv->cv_work.notify_all();
+  if (sv->worker.joinable()) sv->worker.join();
+  delete sv;
+}

@@ -88,3 +88,15 @@ def compare_fp32(gpu, ref, M):
         # a swapped id must sit among distances within the bound
         assert abs(g_d[i, j] - r_d[i, j]) <= tol[i, 0], (i, j)
     return int(mism.any(1).sum())
+
+
+def bf16_bits(x):
+    """bfloat16 bit patterns (uint16) of float32 values, round to nearest even
+    (test input preparation: queries and base rows stored as BF16)."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    return ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+
+
+def bf16_widen(b):
+    """float32 values of bfloat16 bit patterns (exact)."""
+    return (np.asarray(b, dtype=np.uint16).astype(np.uint32) << 16).view(np.float32)

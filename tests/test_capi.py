@@ -142,3 +142,20 @@ def test_search_argument_validation_happens_before_device_work(kw, frag):
 def test_status_strings():
     assert amp.amp_status_str(0) == "ok"
     assert amp.amp_status_str(amp.AMP_EOVERFLOW) == "candidate buffer overflow"
+
+
+@pytest.mark.parametrize("kw,frag", [
+    (dict(max_batch=-1), "max_batch"),
+    (dict(max_batch=70000), "max_batch"),
+    (dict(max_k=2000), "max_k"),
+    (dict(max_nprobe=7), "max_nprobe"),
+    (dict(batch_window_us=-5), "batch_window_us"),
+    (dict(policy="explicit"), "explicit"),
+    (dict(policy="adaptive"), "predictor"),
+    (dict(policy="fixed", bits=6), "fixed_bits"),
+])
+def test_server_configuration_is_validated_before_device_work(kw, frag):
+    h = amp.amp_index_from_arrays(_idx())
+    with pytest.raises(amp.AmpError) as e:
+        amp.amp_server_create(h, **kw)
+    assert e.value.status == amp.AMP_EINVAL and frag in str(e.value)

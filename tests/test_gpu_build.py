@@ -227,3 +227,14 @@ def test_few_distinct_vectors_leave_empty_lists():
     g = amp.amp_search(h, Q, 5, 4, policy="fixed", bits=16, want_probes=True)
     ref = oracle.search(idx, Q, 5, 4, probes=g["probes"], policy="fixed", bits=16)
     compare_integer(g, ref)
+
+
+def test_bf16_base_builds_the_index_of_its_fp32_values():
+    from _parity import bf16_bits, bf16_widen
+    w = WORKLOADS["tiny"]
+    b16 = bf16_bits(make_base(w)[:8000])
+    _, a = _build(b16, 32, 8, iters=4, seed=11)
+    _, b = _build(bf16_widen(b16), 32, 8, iters=4, seed=11)
+    for key in ("centroids", "codebook", "list_offsets", "ids", "codes", "radq"):
+        assert np.array_equal(a[key], b[key]), key
+    assert a["grid_e"] == b["grid_e"]

@@ -509,3 +509,55 @@ def test_probe_ties_follow_list_ids(nlist, nprobe):
     for i, q in enumerate(Q):
         want = oracle.select_probes(oracle.coarse_distances(q, C), nprobe)
         assert np.array_equal(g["probes"][i], want), (i, g["probes"][i], want)
+
+
+def test_bf16_queries_search_as_their_fp32_values(tiny):
+    torch = pytest.importorskip("torch")
+    from _parity import bf16_bits, bf16_widen
+    Qb = bf16_bits(tiny["Q"])
+    Qw = bf16_widen(Qb)
+    g = amp.amp_search(tiny["h"], Qb, 10, 8, policy="fixed", bits=8, want_probes=True)
+    ref = oracle.search(tiny["idx"], Qw, 10, 8, probes=g["probes"], policy="fixed", bits=8)
+    certify_probes(g["probes"], tiny["idx"], Qw, 8)
+    compare_integer(g, ref)
+    w = amp.amp_search(tiny["h"], Qw, 10, 8, policy="fixed", bits=8)
+    assert np.array_equal(w["ids"], g["ids"]) and np.array_equal(w["qdist"], g["qdist"])
+    # device mode from a torch bfloat16 tensor
+    qd = torch.from_numpy(Qw).cuda().to(torch.bfloat16)
+    out = dict(ids=torch.empty((len(Qw), 10), dtype=torch.int64, device="cuda"),
+               dist=torch.empty((len(Qw), 10), dtype=torch.float32, device="cuda"),
+               qdist=torch.empty((len(Qw), 10), dtype=torch.int64, device="cuda"))
+    amp.amp_search(tiny["h"], qd, 10, 8, policy="fixed", bits=8, out=out, stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    assert np.array_equal(out["ids"].cpu().numpy(), g["ids"])
+    assert np.array_equal(out["qdist"].cpu().numpy(), g["qdist"])
+    fp = amp.amp_search(tiny["h"], Qb, 10, 8, policy="fp32")
+    fw = amp.amp_search(tiny["h"], Qw, 10, 8, policy="fp32")
+    assert np.array_equal(fp["ids"], fw["ids"]) and np.array_equal(fp["dist"].view(np.uint32), fw["dist"].view(np.uint32))
+
+
+def test_device_mode_per_query_arrays_may_be_reused_at_return(tiny):
+    torch = pytest.importorskip("torch")
+    Q = tiny["Q"]
+    r = np.random.default_rng(8)
+    qd = torch.from_numpy(Q).cuda()
+    s = torch.cuda.Stream()
+    outs, want = [], []
+    kk = np.empty(len(Q), np.int32)
+    npb = np.empty(len(Q), np.int32)
+    with torch.cuda.stream(s):
+        for rep in range(4):
+            kk[:] = r.integers(1, 11, len(Q))
+            npb[:] = r.integers(1, 9, len(Q))
+            want.append(amp.amp_search(tiny["h"], Q, kk.copy(), npb.copy(), policy="fixed", bits=12))
+            o = dict(ids=torch.empty((len(Q), 10), dtype=torch.int64, device="cuda"),
+                     dist=torch.empty((len(Q), 10), dtype=torch.float32, device="cuda"),
+                     qdist=torch.empty((len(Q), 10), dtype=torch.int64, device="cuda"))
+            amp.amp_search(tiny["h"], qd, kk, npb, policy="fixed", bits=12, out=o, stream=s)
+            outs.append((o, int(kk.max())))
+            kk[:] = 1  # overwritten as soon as the call returns
+            npb[:] = 1
+    s.synchronize()
+    for (o, km), w in zip(outs, want):
+        assert np.array_equal(o["ids"].cpu().numpy()[:, :km], w["ids"])
+        assert np.array_equal(o["qdist"].cpu().numpy()[:, :km], w["qdist"])
