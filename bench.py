@@ -84,6 +84,165 @@ def cpu_baseline(idx, Q, k, nprobe, kw, budget_s=20.0):
                        f"{wall:.1f} s wall")
 
 
+def serving_base_on_device(w, dev, chunk=1 << 19):
+    """The serving corpus at full size, drawn on the device: the workload's
+    mixture (means, weights and sigma of amp_data.synth), component labels
+    from numpy's seeded generator, Gaussian noise from torch's seeded device
+    generator, rows normalised and rounded to bfloat16 (nearest-even).
+    Returns the BF16 bit patterns [n][d] uint16 on the host."""
+    import torch
+    from amp_data.synth import _mixture_params
+    means, weights, sigma = _mixture_params(w)
+    comp = np.random.Generator(np.random.PCG64([w.seed, 9001])).choice(w.n_comp, size=w.n, p=weights)
+    g = torch.Generator(device=dev)
+    g.manual_seed(w.seed * 1000 + 17)
+    mu = torch.from_numpy(means.astype(np.float32)).to(dev)
+    sg = torch.from_numpy(sigma.astype(np.float32)).to(dev)
+    ct = torch.from_numpy(comp.astype(np.int64)).to(dev)
+    out = np.empty((w.n, w.d), np.uint16)
+    for s in range(0, w.n, chunk):
+        e = min(w.n, s + chunk)
+        x = mu[ct[s:e]] + torch.randn((e - s, w.d), generator=g, device=dev) * sg
+        x = x / x.norm(dim=1, keepdim=True)
+        out[s:e] = x.to(torch.bfloat16).view(torch.int16).cpu().numpy().view(np.uint16)
+    return out
+
+
+def serving(args):
+    """Serving regime: single-query requests of mixed k and nprobe arriving
+    as a Poisson process at each rate lambda, continuously batched by the
+    library's server; latency from the scheduled arrival to the results in
+    host memory."""
+    import torch
+
+    import paper_2606_07156_amd as amp
+    from amp_data.synth import WORKLOADS, make_queries
+
+    w = WORKLOADS["serving"]
+    if args.serve_n:
+        w = w.scaled(n=args.serve_n)
+    dev = torch.device("cuda:0")
+    t = time.perf_counter()
+    b16 = serving_base_on_device(w, dev)
+    torch.cuda.synchronize()
+    log(f"[serve] generated {b16.shape} bf16 corpus in {time.perf_counter() - t:.1f}s")
+    t = time.perf_counter()
+    h = amp.amp_index_build(b16, w.nlist, w.M, iters=20, seed=w.seed, metric="ip", grid_kind=w.grid_kind)
+    arr = amp.amp_index_get_arrays(h)
+    sizes = np.diff(arr["list_offsets"])
+    log(f"[serve] built IVF{w.nlist}/PQ{w.M} on the device in {time.perf_counter() - t:.1f}s; list sizes "
+        f"min/mean/max {sizes.min()}/{sizes.mean():.0f}/{sizes.max()}, grid_e {arr['grid_e']}")
+    del arr
+    t = time.perf_counter()
+    TQ = make_queries(w, args.train_queries, train=True)
+    rep = amp.amp_index_train_predictor(h, TQ, 10, 64, gamma=args.gamma, epsilon=args.epsilon, C_=args.svr_c,
+                                        n_samples=1280)
+    log(f"[serve] trained predictor in {time.perf_counter() - t:.1f}s: {rep}")
+    R = args.requests
+    Q = make_queries(w, R)  # bf16-representable rows
+    Qb = np.ascontiguousarray((Q.view(np.uint32) >> 16).astype(np.uint16))
+    r = np.random.Generator(np.random.PCG64([w.seed, 9002]))
+    ks = np.array([10, 50, 100], np.int32)[r.integers(0, 3, R)]
+    nps = np.array([16, 64, 256], np.int32)[r.integers(0, 3, R)]
+    ids = np.zeros((R, 100), np.int64)
+    dist = np.zeros((R, 100), np.float32)
+    qaddr = Qb.ctypes.data + np.arange(R, dtype=np.int64) * Qb.strides[0]
+    iaddr = ids.ctypes.data + np.arange(R, dtype=np.int64) * ids.strides[0]
+    daddr = dist.ctypes.data + np.arange(R, dtype=np.int64) * dist.strides[0]
+
+    # recall@10 of the batched search at each nprobe: adaptive and FP32 vs
+    # exact inner-product search (FP64 on the device over the BF16 corpus)
+    nr = min(args.recall_queries, R)
+    recall = {}
+    if nr:
+        xb = torch.from_numpy(b16.view(np.int16)).to(dev).view(torch.bfloat16)
+        qq = torch.from_numpy(Q[:nr].astype(np.float64)).to(dev)
+        best = torch.full((nr, 10), -float("inf"), dtype=torch.float64, device=dev)
+        bid = torch.zeros((nr, 10), dtype=torch.int64, device=dev)
+        for s in range(0, w.n, 1 << 20):
+            sc = qq @ xb[s:s + (1 << 20)].to(torch.float64).T
+            v, i = torch.topk(torch.cat([best, sc], 1), 10, dim=1)
+            bid = torch.gather(torch.cat([bid, torch.arange(s, s + sc.shape[1], device=dev).expand(nr, -1)], 1), 1, i)
+            best = v
+        truth = bid.cpu().numpy()
+        del xb
+        for npb in (16, 64, 256):
+            for pol in ("adaptive", "fp32"):
+                g = amp.amp_search(h, Qb[:nr], 10, npb, policy=pol, want_bits=True)
+                rec = float(np.mean([len(set(g["ids"][i]) & set(truth[i])) / 10 for i in range(nr)]))
+                recall[f"{pol}_nprobe{npb}"] = round(rec, 4)
+                if pol == "adaptive":
+                    bits = g["bits"][:, :npb].ravel()
+                    recall[f"bits_nprobe{npb}"] = {int(b): round(float((bits == b).mean()), 3) for b in np.unique(bits)}
+        log(f"[serve] 10-recall@10 over {nr} queries: {recall}")
+
+    def make_server(policy):
+        return amp.amp_server_create(h, max_batch=args.serve_batch, max_pending=65536, max_k=100, max_nprobe=256,
+                                     q_dtype="bf16", policy=policy)
+
+    def run(srv, lam, n):
+        """open loop: request i is due at its Poisson arrival time (lam <= 0:
+        all due at once, the closed-loop capacity)"""
+        gaps = r.exponential(1.0 / lam, n) if lam > 0 else np.zeros(n)
+        due = (np.cumsum(gaps) * 1e9).astype(np.int64)
+        rejected = 0
+        lag = 0
+        t0 = time.monotonic_ns() + 2_000_000
+        for i in range(n):
+            a = t0 + int(due[i])
+            now = time.monotonic_ns()
+            while now < a:
+                if a - now > 200_000:
+                    time.sleep((a - now - 100_000) * 1e-9)
+                now = time.monotonic_ns()
+            lag = max(lag, now - a)
+            j = i % R
+            if srv.submit_raw(int(qaddr[j]), int(ks[j]), int(nps[j]), int(iaddr[j]), int(daddr[j]), 0, a) != 0:
+                rejected += 1
+        amp.amp_server_flush(srv)
+        st = amp.amp_server_stats(srv, reset=True)
+        st["max_submit_lag_ms"] = lag / 1e6
+        return st
+
+    rows = []
+    for pol in args.serve_policies.split(","):
+        srv = make_server(pol)
+        run(srv, 0, min(R, 4096))  # warm-up
+        cap = run(srv, 0, R)
+        log(f"[serve] {pol}: closed-loop capacity {cap['qps']:.0f} QPS, mean batch {cap['mean_batch']:.0f}, "
+            f"p50 {cap['p50_ms']:.2f} ms p99 {cap['p99_ms']:.2f} ms")
+        rows.append(dict(policy=pol, lam="capacity", qps=round(cap["qps"], 1), p50_ms=round(cap["p50_ms"], 3),
+                         p99_ms=round(cap["p99_ms"], 3), mean_batch=round(cap["mean_batch"], 1)))
+        for lam in [float(x) for x in args.lambdas.split(",")] if pol == args.serve_policies.split(",")[0] else []:
+            n = min(R, max(1000, int(lam * args.serve_seconds)))
+            st = run(srv, lam, n)
+            log(f"[serve] {pol} lambda {lam:.0f}: {n} requests, achieved {st['qps']:.0f} QPS, p50 "
+                f"{st['p50_ms']:.3f} ms, p99 {st['p99_ms']:.3f} ms, max {st['max_ms']:.2f} ms, mean batch "
+                f"{st['mean_batch']:.1f}, rejected {st['rejected']}, submit lag max {st['max_submit_lag_ms']:.2f} ms")
+            rows.append(dict(policy=pol, lam=lam, requests=n, qps=round(st["qps"], 1), p50_ms=round(st["p50_ms"], 3),
+                             p99_ms=round(st["p99_ms"], 3), max_ms=round(st["max_ms"], 3),
+                             mean_batch=round(st["mean_batch"], 1), rejected=st["rejected"],
+                             submit_lag_max_ms=round(st["max_submit_lag_ms"], 3)))
+        srv.close()
+    head = [x for x in rows if x["lam"] != "capacity"]
+    line = {
+        "metric": "p99 latency at Poisson arrival rate (serving)",
+        "value": head[-1]["p99_ms"] if head else None,
+        "unit": "ms",
+        "n_gpus": 1,
+        "higher_is_better": False,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {w.n}x{w.d} bf16 unit-normalised mixture ({w.n_comp} components), "
+                               f"inner product, IVF{w.nlist}/PQ{w.M}x256, k in {{10,50,100}}, "
+                               f"nprobe in {{16,64,256}}, BF16 queries, one query per request",
+                   "server": {"max_batch": args.serve_batch, "max_pending": 65536},
+                   "recall_10_at_10": recall},
+        "serving": rows,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,7 +266,20 @@ def main():
                     help="1: timed searches replay a captured HIP graph (0: plain launches)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--serving", action="store_true",
+                    help="serving regime: Poisson arrivals of single-query requests on the serving workload")
+    ap.add_argument("--lambdas", default="2000,5000,10000,20000,50000")
+    ap.add_argument("--requests", type=int, default=100_000, help="request pool of the serving regime")
+    ap.add_argument("--serve-seconds", type=float, default=10.0, help="arrival window per rate")
+    ap.add_argument("--serve-batch", type=int, default=1024)
+    ap.add_argument("--serve-policies", default="adaptive,fp32")
+    ap.add_argument("--serve-n", type=int, default=0, help="corpus size override (testing)")
     args = ap.parse_args()
+    if args.serving:
+        if args.gpus != 1:
+            print("bench.py measures one GPU only", file=sys.stderr)
+            sys.exit(2)
+        return serving(args)
     if args.calibrate_copy_mb:
         import torch
         n = args.calibrate_copy_mb * (1 << 20) // 4

@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import threading
 
 import numpy as np
 
@@ -404,6 +405,23 @@ class Server:
         self.index = index  # the index must outlive the server
         self.q_dtype = q_dtype
         self._keep = []
+        self._tl = threading.local()
+
+    def submit_raw(self, query_addr, k, nprobe, ids_addr, dist_addr, qdist_addr=0, arrival_ns=0):
+        """Fast path for load generators: host addresses as integers, no
+        callback, default policy; the caller keeps the buffers alive until
+        the request completes.  Returns the status (no exception)."""
+        tl = self._tl
+        if not hasattr(tl, "req"):
+            tl.req = _Request()
+            tl.ticket = C.c_uint64()
+            tl.args = (self.handle, C.byref(tl.req), C.byref(tl.ticket))
+            tl.fn = lib().amp_server_submit
+        r = tl.req
+        r.query, r.k, r.nprobe = query_addr, k, nprobe
+        r.out_ids, r.out_dist, r.out_qdist = ids_addr, dist_addr, qdist_addr or None
+        r.arrival_ns = arrival_ns
+        return tl.fn(*tl.args)
 
     def __del__(self):
         self.close()

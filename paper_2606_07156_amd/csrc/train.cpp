@@ -11,6 +11,7 @@
 #include <cstring>
 #include <numeric>
 #include <random>
+#include <thread>
 #include <vector>
 
 #include "amp_internal.h"
@@ -137,7 +138,6 @@ extern "C" amp_status amp_index_train_predictor(amp_index* ix, const float* tq, 
   if (nq <= 0 || k < 1 || nprobe < 1 || nprobe > ix->nlist) return set_error(AMP_EINVAL, "bad nq / k / nprobe");
   if (prm->n_samples < 8 || prm->n_samples > 8192) return set_error(AMP_EINVAL, "n_samples outside [8, 8192]");
   if (!(prm->gamma > 0) || !(prm->C > 0) || !(prm->epsilon >= 0)) return set_error(AMP_EINVAL, "bad SVR parameters");
-  if (ix->metric != AMP_L2) return set_error(AMP_EUNSUPPORTED, "predictor training implemented for L2 only");
   uint32_t allowed = prm->allowed_bits_mask ? prm->allowed_bits_mask : ((1u << 4) | (1u << 8) | (1u << 12) | (1u << 16));
   std::vector<int> widths;
   for (int b = 4; b <= 16; b += 4)
@@ -145,48 +145,55 @@ extern "C" amp_status amp_index_train_predictor(amp_index* ix, const float* tq, 
   if (widths.empty() || (allowed & ~((1u << 4) | (1u << 8) | (1u << 12) | (1u << 16))))
     return set_error(AMP_EINVAL, "allowed_bits_mask must select widths among 4, 8, 12, 16");
   const int d = ix->d, M = ix->M, dsub = ix->dsub, nl = ix->nlist;
-  // grid codebook and per-codeword squared norms
+  // grid codebook (and, for inner product, grid centroids)
+  const bool ip = ix->metric == AMP_IP;
   std::vector<int32_t> cbi((size_t)M * kKsub * dsub);
   for (size_t i = 0; i < cbi.size(); ++i) cbi[i] = grid_host(ix->codebook[i], ix->grid_e, ix->grid_kind);
-  std::vector<Sample> all;
-  std::vector<double> D(nl);
-  std::vector<int> order(nl);
-  std::vector<int32_t> ri(d);
-  std::vector<int64_t> T((size_t)M * kKsub);
-  for (int64_t qi = 0; qi < nq; ++qi) {
+  std::vector<int32_t> cgi;
+  if (ip) {
+    cgi.resize((size_t)nl * d);
+    for (size_t i = 0; i < cgi.size(); ++i) cgi[i] = grid_host(ix->centroids[i], ix->grid_e, ix->grid_kind);
+  }
+  // labelled pairs of one training query (queries run on worker threads;
+  // their samples are concatenated in query order)
+  auto label_query = [&](int64_t qi, std::vector<Sample>& out) {
+    std::vector<double> D(nl);
+    std::vector<int> order(nl);
+    std::vector<int32_t> ri(d), qg(d);
+    std::vector<int64_t> T((size_t)M * kKsub);
     const float* q = tq + (size_t)qi * d;
-    // CL in FP64, probes by (distance, list)
+    // CL in FP64 (inner product: the negated dot product), probes by
+    // (distance, list)
     for (int c = 0; c < nl; ++c) {
       double s = 0;
       for (int t = 0; t < d; ++t) {
-        const double df = (double)q[t] - (double)ix->centroids[(size_t)c * d + t];
-        s += df * df;
+        if (ip) {
+          s -= (double)q[t] * (double)ix->centroids[(size_t)c * d + t];
+        } else {
+          const double df = (double)q[t] - (double)ix->centroids[(size_t)c * d + t];
+          s += df * df;
+        }
       }
       D[c] = s;
     }
     std::iota(order.begin(), order.end(), 0);
     std::partial_sort(order.begin(), order.begin() + nprobe, order.end(),
                       [&](int a, int b) { return D[a] < D[b] || (D[a] == D[b] && a < b); });
-    // exact integer ADC distances of every candidate, per probed list
-    std::vector<int64_t> dq2(nprobe), R(nprobe);
-    std::vector<std::vector<int64_t>> dist(nprobe);
-    std::vector<std::pair<int64_t, int64_t>> cand;
-    for (int r = 0; r < nprobe; ++r) {
-      const int p = order[r];
-      int64_t s2 = 0;
-      for (int t = 0; t < d; ++t) {
-        ri[t] = grid_host(q[t] - ix->centroids[(size_t)p * d + t], ix->grid_e, ix->grid_kind);
-        s2 += (int64_t)ri[t] * ri[t];
-      }
-      dq2[r] = s2;
+    // the query-wide inner-product LUT -qi.cbi and its spread
+    auto build_lut = [&](const int32_t* v, bool l2) {
       int64_t Rp = 0;
       for (int m = 0; m < M; ++m) {
         int64_t lo = INT64_MAX, hi = INT64_MIN;
         for (int j = 0; j < kKsub; ++j) {
           int64_t s = 0;
           for (int t = 0; t < dsub; ++t) {
-            const int64_t df = ri[m * dsub + t] - cbi[((size_t)m * kKsub + j) * dsub + t];
-            s += df * df;
+            const int64_t c = cbi[((size_t)m * kKsub + j) * dsub + t];
+            if (l2) {
+              const int64_t df = v[m * dsub + t] - c;
+              s += df * df;
+            } else {
+              s -= v[m * dsub + t] * c;
+            }
           }
           T[(size_t)m * kKsub + j] = s;
           lo = std::min(lo, s);
@@ -194,15 +201,39 @@ extern "C" amp_status amp_index_train_predictor(amp_index* ix, const float* tq, 
         }
         Rp = std::max(Rp, hi - lo);
       }
-      R[r] = Rp;
+      return Rp;
+    };
+    int64_t Rq = 0;
+    if (ip) {
+      for (int t = 0; t < d; ++t) qg[t] = grid_host(q[t], ix->grid_e, ix->grid_kind);
+      Rq = build_lut(qg.data(), false);
+    }
+    // exact integer ADC distances of every candidate, per probed list
+    std::vector<int64_t> dq2(nprobe), R(nprobe);
+    std::vector<std::vector<int64_t>> dist(nprobe);
+    std::vector<std::pair<int64_t, int64_t>> cand;
+    for (int r = 0; r < nprobe; ++r) {
+      const int p = order[r];
+      int64_t s2 = 0, extra = 0;
+      for (int t = 0; t < d; ++t) {
+        if (ip) {
+          ri[t] = qg[t] - cgi[(size_t)p * d + t];  // d' of inner product: ||qi - ci||^2
+          extra -= (int64_t)qg[t] * cgi[(size_t)p * d + t];
+        } else {
+          ri[t] = grid_host(q[t] - ix->centroids[(size_t)p * d + t], ix->grid_e, ix->grid_kind);
+        }
+        s2 += (int64_t)ri[t] * ri[t];
+      }
+      dq2[r] = s2;
+      R[r] = ip ? Rq : build_lut(ri.data(), true);
       for (int64_t v = ix->offsets[p]; v < ix->offsets[p + 1]; ++v) {
-        int64_t s = 0;
+        int64_t s = extra;
         for (int m = 0; m < M; ++m) s += T[(size_t)m * kKsub + ix->codes[(size_t)v * M + m]];
         dist[r].push_back(s);
         cand.emplace_back(s, ix->ids[v]);
       }
     }
-    if ((int64_t)cand.size() <= k) continue;
+    if ((int64_t)cand.size() <= k) return;
     std::nth_element(cand.begin(), cand.begin() + k, cand.end());
     std::sort(cand.begin(), cand.begin() + k + 1);
     const int64_t dk = cand[k - 1].first, dk1 = cand[k].first;
@@ -236,9 +267,22 @@ extern "C" amp_status amp_index_train_predictor(amp_index* ix, const float* tq, 
       smp.x[3] = ix->offsets[order[c1] + 1] - ix->offsets[order[c1]];
       smp.x[4] = ix->offsets[p + 1] - ix->offsets[p];
       smp.bits = bstar;
-      all.push_back(smp);
+      out.push_back(smp);
     }
+  };
+  std::vector<std::vector<Sample>> per_q(nq);
+  {
+    const unsigned hw = std::thread::hardware_concurrency();
+    const int T = (int)std::max<int64_t>(1, std::min<int64_t>(nq, std::min(hw ? hw : 1u, 16u)));
+    std::vector<std::thread> th;
+    for (int t = 0; t < T; ++t)
+      th.emplace_back([&, t] {
+        for (int64_t qi = t; qi < nq; qi += T) label_query(qi, per_q[qi]);
+      });
+    for (auto& x : th) x.join();
   }
+  std::vector<Sample> all;
+  for (auto& v : per_q) all.insert(all.end(), v.begin(), v.end());
   if (all.size() < 8) return set_error(AMP_EINVAL, "too few training pairs");
   // integer feature map: fixed-point log2, then min-max onto 0..1023
   int64_t flo[5], fmul[5];

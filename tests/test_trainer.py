@@ -81,3 +81,64 @@ def test_trainer_argument_validation():
         amp.amp_index_train_predictor(h, TQ, 10, 4, allowed=(4, 6))
     with pytest.raises(amp.AmpError):
         amp.amp_index_get_predictor(h)
+
+
+def _labels_by_definition(idx, TQ, k, nprobe, widths=(4, 8, 12, 16)):
+    """Label histogram of the training pairs, recomputed from the oracle's
+    stage functions: exact integer ADC distances on the operand grid; the
+    list's margin between the query's k neighbours (by (distance, id)) and
+    the other candidates; the smallest width whose worst-case quantisation
+    error M * 2^(s-1) stays below that margin (or that needs no shift)."""
+    M, metric, kind = int(idx["M"]), idx["metric"], idx["grid_kind"]
+    inv = 2.0 ** (-int(idx["grid_e"]))
+    cbi, ci = oracle.index_grid(idx)
+    C = np.asarray(idx["centroids"], np.float32)
+    offs, ids, codes = idx["list_offsets"], idx["ids"], idx["codes"].astype(np.int64)
+    hist = [0, 0, 0, 0]
+    for q in TQ:
+        P = oracle.select_probes(oracle.coarse_distances(q, C, metric), nprobe)
+        dists, Ts = [], []
+        if metric == "ip":
+            qi = oracle.grid(q.astype(np.float64) * inv, kind)
+            Tq = oracle.lut_int(qi, cbi, "ip")
+        for p in P:
+            if metric == "l2":
+                T = oracle.lut_int(oracle.grid(oracle.residual_f32(q, C[p]).astype(np.float64) * inv, kind), cbi)
+                extra = 0
+            else:
+                T, extra = Tq, -int((qi * ci[p]).sum())
+            c = codes[offs[p]:offs[p + 1]]
+            dists.append(extra + T[np.arange(M)[None, :], c].sum(1))
+            Ts.append(T)
+        allv = sorted((int(v), int(i)) for r, p in enumerate(P) for v, i in zip(dists[r], ids[offs[p]:offs[p + 1]]))
+        if len(allv) <= k:
+            continue
+        kth, dk, dk1 = allv[k - 1], allv[k - 1][0], allv[k][0]
+        for r, p in enumerate(P):
+            delta = min((dk1 - v if (int(v), int(i)) <= kth else v - dk)
+                        for v, i in zip(dists[r], ids[offs[p]:offs[p + 1]]))
+            b_star = widths[-1]
+            for b in widths:
+                s = oracle.quantize_lut(Ts[r], b)[1]
+                if s == 0 or M * (1 << (s - 1)) < delta:
+                    b_star = b
+                    break
+            hist[b_star // 4 - 1] += 1
+    return hist
+
+
+@pytest.mark.parametrize("metric", ["l2", "ip"])
+def test_trainer_labels_follow_the_margin_definition(metric):
+    w = WORKLOADS["tiny"].scaled(n=6000)
+    base = make_base(w)
+    if metric == "ip":
+        base = base / np.linalg.norm(base, axis=1, keepdims=True)
+    idx = build_index(base, 16, 8, iters=4, seed=3, metric=metric)
+    h = amp.amp_index_from_arrays(idx)
+    TQ = make_queries(w, 12, train=True)
+    if metric == "ip":
+        TQ = TQ / np.linalg.norm(TQ, axis=1, keepdims=True)
+    TQ = TQ.astype(np.float32)
+    rep = amp.amp_index_train_predictor(h, TQ, 10, 4, n_samples=40)
+    assert rep["label_hist"] == _labels_by_definition(idx, TQ, 10, 4)
+    assert rep["n_pairs"] == 12 * 4
