@@ -78,6 +78,8 @@ struct Workspace {
   uint8_t* pbits = nullptr;    // [nq][npmax]
   uint8_t* xbits = nullptr;    // [nq][npmax] explicit widths (uploaded)
   uint64_t* tau = nullptr;     // [nq] pruning threshold key
+  uint8_t* retry = nullptr;    // [nq] query takes part in the phase-2 re-run
+  int64_t* tau_id = nullptr;   // [nq] id part of the re-run's bound
   uint32_t* ccount = nullptr;  // [nq] candidate count
   uint64_t* ckey = nullptr;    // [nq][capq]
   int64_t* cid = nullptr;      // [nq][capq]
@@ -90,7 +92,7 @@ struct Workspace {
   int64_t* unitoff = nullptr;  // [2][NB+1]
   int32_t* sorted = nullptr;   // [2][nq*npmax]
   uint32_t* counters = nullptr;// [2][kNCls+1] unit counters
-  int32_t* flags = nullptr;    // [4]: overflow, ...
+  int32_t* flags = nullptr;    // [4]: error bits, phase-2 re-run requested (two rounds), -
   // outputs staged for host mode
   int64_t* o_ids = nullptr;
   float* o_dist = nullptr;

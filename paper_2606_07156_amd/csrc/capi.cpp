@@ -444,7 +444,7 @@ static amp_status ensure_workspace(amp_index* ix, size_t nq, size_t np, size_t k
   if ((s = dalloc(&w.queries, nq * ix->d, t)) || (s = dalloc(&w.qraw, nq * ix->d, t)) || (s = dalloc(&w.kq, nq, t)) || (s = dalloc(&w.npq, nq, t)) ||
       (s = dalloc(&w.qnorm, nq, t)) || (s = dalloc(&w.coarse, nq * ix->nlist, t)) ||
       (s = dalloc(&w.probes, npairs, t)) ||
-      (s = dalloc(&w.pbits, npairs, t)) || (s = dalloc(&w.xbits, npairs, t)) || (s = dalloc(&w.tau, nq, t)) ||
+      (s = dalloc(&w.pbits, npairs, t)) || (s = dalloc(&w.xbits, npairs, t)) || (s = dalloc(&w.tau, nq, t)) || (s = dalloc(&w.retry, nq, t)) || (s = dalloc(&w.tau_id, nq, t)) ||
       (s = dalloc(&w.ccount, nq, t)) || (s = dalloc(&w.ckey, nq * capq, t)) || (s = dalloc(&w.cid, nq * capq, t)) ||
       (s = dalloc(&w.cnt, 2 * kQSub * NB, t)) || (s = dalloc(&w.rank, 2 * npairs, t)) ||
       (s = dalloc(&w.units, 2 * (size_t)units, t)) || (s = dalloc(&w.pairoff, 2 * (NB + 1), t)) ||
@@ -737,6 +737,7 @@ amp_status amp_search(amp_index* ix, const void* queries, int64_t nq, const int3
     uint32_t mx = 0;
     for (uint32_t c : cc) sum += c, mx = std::max(mx, c);
     fprintf(stderr, "[amp] candidates per query: mean %.1f max %u (capacity %zu)\n", sum / nq, mx, capq);
+    if (host) fprintf(stderr, "[amp] phase-2 re-runs: %d %d\n", flags[1], flags[2]);
     // pairs, work units and scanned vectors per phase and lane class
     const int ncls = pol->kind == AMP_POLICY_FP32 ? 1 : kNCls;
     const size_t NB = (size_t)ncls * ix->nlist;

@@ -477,6 +477,8 @@ __global__ __launch_bounds__(256) void k_pairs(PairArgs a, ModelArgs ma) {
 struct QueueArgs {
   const int32_t* probes;
   const uint8_t* pbits;
+  const int32_t* kq;      // per-query k, or null (kconst)
+  int kconst;
   const int64_t* offsets;
   const int32_t* lorder;  // bucket position -> list (largest list first)
   const int32_t* lpos;    // list -> bucket position
@@ -506,6 +508,24 @@ __device__ __forceinline__ int pair_sub(size_t i) {
   return (int)(((uint32_t)i * 0x9E3779B1u) >> 28) & (kQSub - 1);
 }
 
+// the phase-1 bound of a query comes from its nearest probes: rank 0, and
+// each further rank while the lists of the ranks before it hold fewer than k
+// vectors (so that the bound covers k distinct vectors whenever the probed
+// lists hold that many)
+__device__ __forceinline__ bool in_phase1(const QueueArgs& a, size_t i) {
+  const size_t q = i / a.npmax;
+  const int r = (int)(i - q * a.npmax);
+  if (r == 0) return true;
+  const int kk = a.kq ? a.kq[q] : a.kconst;
+  int64_t cum = 0;
+  for (int j = 0; j < r; ++j) {
+    const int p = a.probes[q * a.npmax + j];
+    cum += a.offsets[p + 1] - a.offsets[p];
+    if (cum >= kk) return false;
+  }
+  return true;
+}
+
 __global__ void k_qhist(QueueArgs a) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t n = (size_t)a.nq * a.npmax;
@@ -516,7 +536,7 @@ __global__ void k_qhist(QueueArgs a) {
   const int NB = a.ncls * a.nlist;
   const size_t b = (size_t)pair_sub(i) * NB + cls * a.nlist + p;
   a.rank[n + i] = atomicAdd(&a.cnt[(size_t)kQSub * NB + b], 1);
-  if (i % a.npmax == 0) a.rank[i] = atomicAdd(&a.cnt[b], 1);
+  if (in_phase1(a, i)) a.rank[i] = atomicAdd(&a.cnt[b], 1);
 }
 
 // per (phase, class, list) bucket: its pair total from the sub-counters
@@ -616,7 +636,7 @@ __global__ void k_qscatter(QueueArgs a) {
   const int NB = a.ncls * a.nlist;
   const size_t bs = (size_t)pair_sub(i) * NB + cls * a.nlist + p;  // sub-counter offset
   a.sorted[n + a.pairoff[(NB + 1) + b] + a.cnt[(size_t)kQSub * NB + bs] + a.rank[n + i]] = (int32_t)i;
-  if (i % a.npmax == 0) a.sorted[a.pairoff[b] + a.cnt[bs] + a.rank[i]] = (int32_t)i;
+  if (in_phase1(a, i)) a.sorted[a.pairoff[b] + a.cnt[bs] + a.rank[i]] = (int32_t)i;
 }
 
 // grid-stride over (phase, unit): find the unit's bucket by binary search of
@@ -671,6 +691,9 @@ struct ScanArgs {
   uint64_t* ckey;
   int64_t* cid;
   int32_t* flags;
+  const uint8_t* retry;     // re-run of phase 2: queries taking part (null: every query)
+  const int64_t* tau_id;    // re-run of phase 2: id of the bound's (distance, id) key
+  const int32_t* any_retry; // re-run of phase 2: non-zero if any query takes part
   int nq, d, M, dsub, nlist, npmax, grid_e, grid_kind, metric, kconst, kmax, cls;
   int64_t chunk;
   size_t capq;
@@ -708,7 +731,7 @@ __host__ __device__ inline ScanLds scan_lds_layout(int G, int wpr, int M, int d,
   if (phase == 1 && G * kThreadsP2 * 4 > M * kKsub * wpr * 4) L.lmin = take(G * kThreadsP2 * 4);
   // unit-claim control words: kept in the dynamic LDS too, so that the LUT
   // starts at LDS address 0 and row addresses fold into instruction offsets
-  L.ctl = take(32);
+  L.ctl = take(32);  // unit index, class, re-run vote, unit descriptor
   L.total = o;
   return L;
 }
@@ -994,6 +1017,20 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
         pb[tid] = 16;
       }
     }
+    if (PHASE == 2 && a.retry) {
+      // re-run: a unit with no pair of a re-run query is skipped whole (the
+      // vote goes through a control word of the dynamic LDS: the scan
+      // kernels use no static LDS)
+      int& s_part = *reinterpret_cast<int*>(lds + L.ctl + 8);
+      if (tid == 0) s_part = 0;
+      __syncthreads();
+      if (tid < np_u && a.retry[pq[tid]]) s_part = 1;
+      __syncthreads();
+      if (!s_part) {
+        fetch_next();
+        return;
+      }
+    }
     __syncthreads();
     // ---- RC: residuals (FP32, then onto the grid for integer policies)
     // (inner product: the query itself, on the grid for integer policies)
@@ -1187,7 +1224,7 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
     if (PHASE == 2 && tid < G) {
       uint32_t sig = 0;
       bool live = false;
-      if (tid < np_u) {
+      if (tid < np_u && (!a.retry || a.retry[pq[tid]])) {
         const uint64_t tk = a.tau[pq[tid]];
         live = true;
         if (tk == ~0ull) {
@@ -1288,15 +1325,16 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
         }
         auto emit = [&](int g, uint32_t S) {
           const int q = pq[g];
+          uint64_t key;
+          if constexpr (FP) key = (uint64_t)S;
+          else key = ikey(pbase[g] + ((int64_t)S << ps[g]));
+          const int64_t id = a.ids[L0 + v];
+          // re-run: the bound is a (distance, id) key, ties past its id go
+          if (PHASE == 2 && a.retry && key == a.tau[q] && id > a.tau_id[q]) return;
           const uint32_t pos = atomicAdd(&a.ccount[q], 1u);
           if (pos < a.capq) {
-            uint64_t key;
-            if constexpr (FP) key = (uint64_t)S;
-            else key = ikey(pbase[g] + ((int64_t)S << ps[g]));
             a.ckey[(size_t)q * a.capq + pos] = key;
-            a.cid[(size_t)q * a.capq + pos] = a.ids[L0 + v];
-          } else {
-            atomicOr(&a.flags[0], 1);
+            a.cid[(size_t)q * a.capq + pos] = id;
           }
         };
         if constexpr (PHASE == 2 && LWB == 8) {
@@ -1346,14 +1384,21 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
             const bool asc = (lane & kb) == 0, lower = (lane & jb) == 0;
             v = (lower == asc) ? (o < v ? o : v) : (o > v ? o : v);
           }
+        // the wave's k smallest minima go to the query's bound buffer (the
+        // candidate buffer, emptied again before phase 2); entries beyond
+        // its capacity are dropped, which only loosens the bound
         const int q = pq[g];
         const int kk = a.kq ? a.kq[q] : a.kconst;
-        const uint32_t val = (uint32_t)__shfl((int)v, kk - 1);
-        if (lane == 0 && val != 0xFFFFFFFFu) {
+        const bool e = lane < kk && v != 0xFFFFFFFFu;
+        const uint64_t bal = __ballot(e);
+        uint32_t base = 0;
+        if (lane == 0 && bal) base = atomicAdd(&a.ccount[q], (uint32_t)__popcll(bal));
+        base = (uint32_t)__shfl((int)base, 0);
+        if (e && base + lane < a.capq) {
           uint64_t key;
-          if constexpr (FP) key = (uint64_t)val;
-          else key = ikey(pbase[g] + ((int64_t)val << ps[g]));
-          atomicMin((unsigned long long*)&a.tau[q], (unsigned long long)key);
+          if constexpr (FP) key = (uint64_t)v;
+          else key = ikey(pbase[g] + ((int64_t)v << ps[g]));
+          a.ckey[(size_t)q * a.capq + base + lane] = key;
         }
       }
     } else if (PHASE == 1) {
@@ -1380,16 +1425,19 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
           }
           __syncthreads();
         }
-      if (tid < np_u) {
-        const int q = pq[tid];
+      // the k smallest of each pair's minima to its query's bound buffer
+      for (int i = tid; i < np_u * TP; i += kThreads) {
+        const int g = i / TP, r = i % TP;
+        const int q = pq[g];
         const int kk = a.kq ? a.kq[q] : a.kconst;
-        if (kk <= kThreads) {
-          const uint32_t val = lm[tid * kThreadsP2 + kk - 1];
-          if (val != 0xFFFFFFFFu) {
+        const uint32_t val = lm[g * TP + r];
+        if (r < kk && val != 0xFFFFFFFFu) {
+          const uint32_t pos = atomicAdd(&a.ccount[q], 1u);
+          if (pos < a.capq) {
             uint64_t key;
             if constexpr (FP) key = (uint64_t)val;
-            else key = ikey(pbase[tid] + ((int64_t)val << ps[tid]));
-            atomicMin((unsigned long long*)&a.tau[q], (unsigned long long)key);
+            else key = ikey(pbase[g] + ((int64_t)val << ps[g]));
+            a.ckey[(size_t)q * a.capq + pos] = key;
           }
         }
       }
@@ -1413,6 +1461,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_scan(ScanArgs a) {
     if (threadIdx.x == 0) atomicOr(&a.flags[0], 16);
     return;
   }
+  if (PHASE == 2 && a.any_retry && *a.any_retry == 0) return;  // re-run with nothing to do
   int& s_u = *reinterpret_cast<int*>(lds + L.ctl);
   int4& s_unit = *reinterpret_cast<int4*>(lds + L.ctl + 16);
   const int tid = threadIdx.x;
@@ -1466,6 +1515,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_scan_mix(ScanArgs a) {
     if (threadIdx.x == 0) atomicOr(&a.flags[0], 16);
     return;
   }
+  if (PHASE == 2 && a.any_retry && *a.any_retry == 0) return;  // re-run with nothing to do
   int& s_u = *reinterpret_cast<int*>(lds + L.ctl);
   int& s_cls = *reinterpret_cast<int*>(lds + L.ctl + 4);
   int4& s_unit = *reinterpret_cast<int4*>(lds + L.ctl + 16);
@@ -1511,6 +1561,96 @@ __global__ __launch_bounds__(kThreads, 2) void k_scan_mix(ScanArgs a) {
       s_cls = next_cls;
     }
     __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ bound
+// tau[q] = the k-th smallest key of the query's phase-1 bound buffer (every
+// entry is the estimate of a distinct vector, so it bounds the query's k-th
+// smallest estimate from above), or no bound with fewer than k entries; the
+// buffer is emptied for phase 2.  Queries with at most 64 entries: one wave
+// each (register bitonic sort); the rest: k_tau, a workgroup each.
+__global__ __launch_bounds__(256) void k_tau_wave(uint32_t* ccount, const uint64_t* ckey, uint64_t* tau,
+                                                  const int32_t* kq, int kconst, int nq, size_t capq,
+                                                  int32_t* any_retry) {
+  const int lane = threadIdx.x & 63;
+  const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (q == 0 && lane < 2) any_retry[lane] = 0;  // no phase-2 re-run requested yet (two rounds)
+  if (q >= nq) return;
+  const uint32_t cnt = ccount[q];
+  const int n = (int)(cnt < capq ? cnt : capq);
+  if (n > 64) return;
+  uint64_t key = lane < n ? ckey[(size_t)q * capq + lane] : ~0ull;
+  for (int kb = 2; kb <= 64; kb <<= 1)
+    for (int jb = kb >> 1; jb > 0; jb >>= 1) {
+      const uint64_t o = __shfl_xor(key, jb);
+      const bool keep_min = ((lane & kb) == 0) == ((lane & jb) == 0);
+      key = keep_min ? (o < key ? o : key) : (o > key ? o : key);
+    }
+  const int kk = kq ? kq[q] : kconst;
+  const uint64_t kth = __shfl(key, kk <= 64 ? kk - 1 : 63);
+  if (lane == 0) {
+    tau[q] = n >= kk ? kth : ~0ull;
+    ccount[q] = 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_tau(uint32_t* ccount, const uint64_t* ckey, uint64_t* tau,
+                                             const int32_t* kq, int kconst, int nq, size_t capq) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  uint64_t* keys = reinterpret_cast<uint64_t*>(lds);
+  for (int q = blockIdx.x; q < nq; q += gridDim.x) {
+    const uint32_t cnt = ccount[q];
+    const int n = (int)(cnt < capq ? cnt : capq);
+    if (n <= 64) continue;  // uniform over the workgroup
+    int np2 = 1;
+    while (np2 < n) np2 <<= 1;
+    for (int i = threadIdx.x; i < np2; i += blockDim.x) keys[i] = i < n ? ckey[(size_t)q * capq + i] : ~0ull;
+    __syncthreads();
+    block_bitonic_u64(keys, np2);
+    const int kk = kq ? kq[q] : kconst;
+    if (threadIdx.x == 0) {
+      tau[q] = n >= kk ? keys[kk - 1] : ~0ull;
+      ccount[q] = 0;
+    }
+    __syncthreads();  // the LDS is reused by the next query
+  }
+}
+
+// after phase 2: a query whose candidates overflowed the buffer takes the
+// k-th smallest (distance, id) of the candidates kept (distinct vectors, each
+// within its old bound) as a tighter bound and is marked for a re-run of
+// phase 2; the others are unmarked.  Block 0 also rewinds the phase-2 unit counters.
+__global__ __launch_bounds__(256) void k_retry(uint32_t* ccount, const uint64_t* ckey, const int64_t* cid,
+                                               uint64_t* tau, int64_t* tau_id, const int32_t* kq, int kconst, int nq,
+                                               size_t capq, uint8_t* retry, int32_t* any_retry, uint32_t* counters,
+                                               int ncounters) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  uint64_t* keys = reinterpret_cast<uint64_t*>(lds);
+  int64_t* vals = reinterpret_cast<int64_t*>(lds + capq * 8);
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < ncounters; i += blockDim.x) counters[i] = 0;
+  for (int q = blockIdx.x; q < nq; q += gridDim.x) {
+    const uint32_t cnt = ccount[q];
+    if (cnt <= capq) {
+      if (threadIdx.x == 0) retry[q] = 0;
+      continue;  // uniform over the workgroup
+    }
+    for (size_t i = threadIdx.x; i < capq; i += blockDim.x) {
+      keys[i] = ckey[(size_t)q * capq + i];
+      vals[i] = cid[(size_t)q * capq + i];
+    }
+    __syncthreads();
+    block_bitonic_u64_i64(keys, vals, (int)capq);
+    const int kk = kq ? kq[q] : kconst;
+    if (threadIdx.x == 0) {
+      tau[q] = keys[kk - 1];
+      tau_id[q] = vals[kk - 1];
+      ccount[q] = 0;
+      retry[q] = 1;
+      *any_retry = 1;
+    }
+    __syncthreads();  // the LDS is reused by the next query
   }
 }
 
@@ -1851,6 +1991,8 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   QueueArgs qa;
   qa.probes = ws.probes;
   qa.pbits = ws.pbits;
+  qa.kq = ws.kq;
+  qa.kconst = sd.kconst;
   qa.offsets = dv.offsets;
   qa.lorder = dv.lorder;
   qa.lpos = dv.lpos;
@@ -1907,6 +2049,9 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   sa.kmax = sd.kmax;
   sa.chunk = sd.chunk;  // per phase below
   sa.capq = sd.capq;
+  sa.retry = nullptr;
+  sa.tau_id = nullptr;
+  sa.any_retry = nullptr;
   hipError_t err = hipSuccess;
   // the lane classes run one after another on the caller's stream, each a
   // persistent kernel over its own unit range.  (Running them concurrently
@@ -1918,16 +2063,47 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
     sa.unitoff = ws.unitoff + (ph == 2 ? (NB + 1) : 0);
     sa.units = ws.units + (ph == 2 ? sd.max_units : 0);
     sa.chunk = ph == 2 ? sd.chunk : sd.chunk1;
+    int sa_lwb;
     if (fp32 || sd.policy == AMP_POLICY_FIXED) {
       // one lane class holds every pair: its own kernel
       const int c = fp32 ? 0 : lane_class(sd.M, sd.fixed_bits);
       sa.cls = c;
       sa.counter = ws.counters + (ph - 1) * (kNCls + 1) + c;
-      if ((err = launch_scan(fp32 ? 0 : lane_bits(c), ph, dt, sd.wpr, sa, st)) != hipSuccess) return err;
+      sa_lwb = fp32 ? 0 : lane_bits(c);
     } else {
       sa.cls = -1;
       sa.counter = ws.counters + (ph - 1) * (kNCls + 1) + kNCls;
-      if ((err = launch_scan(-1, ph, dt, sd.wpr, sa, st)) != hipSuccess) return err;
+      sa_lwb = -1;
+    }
+    if ((err = launch_scan(sa_lwb, ph, dt, sd.wpr, sa, st)) != hipSuccess) return err;
+    if (ph == 2) {
+      // up to two re-runs of phase 2 for queries whose candidates overflowed,
+      // each with a tighter bound (the scan kernels return at once when no
+      // query takes part); each re-run shrinks a query's candidate count by
+      // about k / capq
+      const size_t rlds = sd.capq * 16;
+      err = hipFuncSetAttribute(kaddr(k_retry), hipFuncAttributeMaxDynamicSharedMemorySize, (int)rlds);
+      if (err != hipSuccess) return err;
+      ScanArgs sr = sa;
+      sr.retry = ws.retry;
+      sr.tau_id = ws.tau_id;
+      for (int rr = 0; rr < 2; ++rr) {
+        sr.any_retry = ws.flags + 1 + rr;  // one flag per round
+        hipLaunchKernelGGL(k_retry, dim3(sd.nq < 512 ? sd.nq : 512), dim3(256), rlds, st, ws.ccount, ws.ckey,
+                           ws.cid, ws.tau, ws.tau_id, ws.kq, sd.kconst, sd.nq, sd.capq, ws.retry,
+                           ws.flags + 1 + rr, ws.counters + (kNCls + 1), kNCls + 1);
+        if ((err = launch_scan(sa_lwb, ph, dt, sd.wpr, sr, st)) != hipSuccess) return err;
+      }
+    }
+    if (ph == 1) {
+      // phase-1 minima -> per-query bound, buffer emptied for the candidates
+      hipLaunchKernelGGL(k_tau_wave, dim3((sd.nq + 3) / 4), dim3(256), 0, st, ws.ccount, ws.ckey, ws.tau, ws.kq,
+                         sd.kconst, sd.nq, sd.capq, ws.flags + 1);
+      const size_t tlds = sd.capq * 8;
+      err = hipFuncSetAttribute(kaddr(k_tau), hipFuncAttributeMaxDynamicSharedMemorySize, (int)tlds);
+      if (err != hipSuccess) return err;
+      hipLaunchKernelGGL(k_tau, dim3(sd.nq < 512 ? sd.nq : 512), dim3(256), tlds, st, ws.ccount, ws.ckey, ws.tau,
+                         ws.kq, sd.kconst, sd.nq, sd.capq);
     }
     mark(4 + ph);
   }

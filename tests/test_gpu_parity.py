@@ -561,3 +561,36 @@ def test_device_mode_per_query_arrays_may_be_reused_at_return(tiny):
     for (o, km), w in zip(outs, want):
         assert np.array_equal(o["ids"].cpu().numpy()[:, :km], w["ids"])
         assert np.array_equal(o["qdist"].cpu().numpy()[:, :km], w["qdist"])
+
+
+@pytest.mark.parametrize("policy,bits", [("fixed", 16), ("fixed", 4), ("fp32", 0)])
+def test_bound_spans_probes_when_the_nearest_list_is_smaller_than_k(monkeypatch, policy, bits):
+    # lists of ~25 vectors, k = 50: the phase-1 bound must combine several
+    # nearest lists; a small candidate buffer shows a missing bound as an
+    # overflow
+    c = _small("vmf", metric="ip", n=6_000, d=64, n_comp=64, nlist=256, M=16, seed=21, nq=24)
+    monkeypatch.setenv("AMP_CAPQ", "512")
+    g = _gpu(c, 50, 64, policy=policy, bits=bits)
+    ref = _oracle(c, 50, 64, g, policy=policy, bits=bits)
+    if policy == "fp32":
+        compare_fp32(g, ref, c["idx"]["M"])
+    else:
+        compare_integer(g, ref)
+
+
+@pytest.mark.parametrize("policy,bits", [("fixed", 4), ("fixed", 16), ("fp32", 0)])
+def test_candidate_overflow_is_resolved_by_rerunning_phase_two(tiny, monkeypatch, capfd, policy, bits):
+    # a 64-entry candidate buffer for k = 10: queries whose candidates under
+    # the phase-1 bound overflow it (4-bit LUTs: about 120 per query, with
+    # many ties) are re-scanned with a tighter (distance, id) bound
+    monkeypatch.setenv("AMP_CAPQ", "64")
+    monkeypatch.setenv("AMP_STATS", "1")
+    g = _gpu(tiny, 10, 8, policy=policy, bits=bits)
+    err = capfd.readouterr().err
+    ref = _oracle(tiny, 10, 8, g, policy=policy, bits=bits)
+    if policy == "fp32":
+        compare_fp32(g, ref, tiny["idx"]["M"])
+    else:
+        compare_integer(g, ref)
+    if policy == "fixed" and bits == 4:
+        assert "phase-2 re-runs: 1" in err, err
