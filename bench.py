@@ -243,6 +243,70 @@ def serving(args):
     print(json.dumps(line), flush=True)
 
 
+def sweep(args):
+    """Batched uneven work: the skewed workload (10M x 96, Zipf(1.1) mixture
+    weights, IVF4096 / PQ24) searched in batches of B queries with per-query
+    nprobe uniform in [8, 128], k 10; adaptive (BF16 LC) and FP32 policies,
+    each with its schedule autotuned per batch size."""
+    import torch
+
+    import paper_2606_07156_amd as amp
+    from amp_data.synth import WORKLOADS, draw_nprobe, make_base, make_queries
+
+    w = WORKLOADS["skewed"]
+    if args.serve_n:
+        w = w.scaled(n=args.serve_n)
+    t = time.perf_counter()
+    base = make_base(w)
+    log(f"[sweep] generated base {base.shape} in {time.perf_counter() - t:.1f}s")
+    t = time.perf_counter()
+    h = amp.amp_index_build(base, w.nlist, w.M, iters=20, seed=w.seed)
+    arr = amp.amp_index_get_arrays(h)
+    sizes = np.diff(arr["list_offsets"])
+    log(f"[sweep] built IVF{w.nlist}/PQ{w.M} on the device in {time.perf_counter() - t:.1f}s; list sizes "
+        f"min/median/mean/max {sizes.min()}/{int(np.median(sizes))}/{sizes.mean():.0f}/{sizes.max()}")
+    TQ = make_queries(w, args.train_queries, train=True)
+    rep = amp.amp_index_train_predictor(h, TQ, 10, 64, gamma=args.gamma, epsilon=args.epsilon, C_=args.svr_c,
+                                        n_samples=1280)
+    log(f"[sweep] trained predictor: {rep}")
+    bmax = max(int(b) for b in args.batches.split(","))
+    Q = make_queries(w, max(bmax, w.nq))
+    NP = draw_nprobe(w, len(Q))
+    dev = torch.device("cuda:0")
+    qd = torch.from_numpy(Q).to(dev)
+    stream = torch.cuda.Stream()
+    rows = []
+    for B in [int(b) for b in args.batches.split(",")]:
+        for pol in ("adaptive", "fp32"):
+            kw = dict(policy=pol)
+            e = amp.amp_index_autotune(h, Q[:B], 10, NP[:B], repeats=3, **kw)
+            out = dict(ids=torch.empty((B, 10), dtype=torch.int64, device=dev),
+                       dist=torch.empty((B, 10), dtype=torch.float32, device=dev))
+            reps = max(3, min(200, int(2000 / max(B, 1)) + 3))
+            for i in range(2):
+                amp.amp_search(h, qd[:B], 10, NP[:B], out=out, stream=stream, **kw)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for i in range(reps):
+                amp.amp_search(h, qd[:B], 10, NP[:B], out=out, stream=stream, **kw)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            rows.append(dict(batch=B, policy=pol, ms=round(ms, 4), qps=round(B / ms * 1e3, 1),
+                             schedule={kk: e[kk] for kk in ("chunk", "chunk1", "narrow", "lut_dtype")},
+                             tuned_ms=round(e["ms"], 4), automatic_ms=round(e["ms_default"], 4)))
+            log(f"[sweep] B={B:5d} {pol:8s} {ms:8.3f} ms/batch {B / ms * 1e3:11.0f} QPS  schedule "
+                f"{rows[-1]['schedule']} (tuned {e['ms']:.3f} ms vs automatic {e['ms_default']:.3f} ms)")
+    line = {"metric": "QPS per batch size (batched uneven work)", "unit": "queries/s", "n_gpus": 1,
+            "higher_is_better": True, "data": "synthetic",
+            "config": {"workload": f"{w.name}: {w.n}x{w.d} Zipf(1.1) mixture, IVF{w.nlist}/PQ{w.M}x256, "
+                                   f"nprobe uniform in [{w.nprobe_lo},{w.nprobe}], k 10",
+                       "list_sizes": [int(sizes.min()), int(np.median(sizes)), int(sizes.max())]},
+            "sweep": rows}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -266,6 +330,11 @@ def main():
                     help="1: timed searches replay a captured HIP graph (0: plain launches)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="1: autotune each policy's search schedule for the batch before timing it")
+    ap.add_argument("--sweep", action="store_true",
+                    help="batch-size sweep on the skewed workload (uneven nprobe, Zipf list sizes)")
+    ap.add_argument("--batches", default="1,16,256,1024,4096")
     ap.add_argument("--serving", action="store_true",
                     help="serving regime: Poisson arrivals of single-query requests on the serving workload")
     ap.add_argument("--lambdas", default="2000,5000,10000,20000,50000")
@@ -275,6 +344,11 @@ def main():
     ap.add_argument("--serve-policies", default="adaptive,fp32")
     ap.add_argument("--serve-n", type=int, default=0, help="corpus size override (testing)")
     args = ap.parse_args()
+    if args.sweep:
+        if args.gpus != 1:
+            print("bench.py measures one GPU only", file=sys.stderr)
+            sys.exit(2)
+        return sweep(args)
     if args.serving:
         if args.gpus != 1:
             print("bench.py measures one GPU only", file=sys.stderr)
@@ -368,7 +442,13 @@ def main():
     results = {}
     # algorithmic bytes of the scan: one read of each probed list's codes per pair
     sizes = idx["list_sizes"].astype(np.int64)
+    tuned = {}
     for name, kw in pols:
+        if args.autotune:
+            # schedule (unit chunking, LUT row width, LC dtype) timed for this
+            # batch shape; results do not depend on it
+            tuned[name] = amp.amp_index_autotune(h, QP[:nq] if n_batches > 1 else Q, k, nprobe, repeats=3, **kw)
+            log(f"[bench] {name}: autotuned schedule {tuned[name]}")
         out["probes"], out["bits"] = (None, None) if nr else (out_probes, out_bits)
         for i in range(args.warmup):
             amp.amp_search(h, batch(args.steps + i), k, nprobe, out=out, stream=stream, graph=args.graph, **kw)
@@ -470,6 +550,8 @@ def main():
                                   if args.replicate > 1 else ""),
                    "policy": head,
                    "launch": "HIP graph replay" if args.graph else "kernel launches",
+                   "schedule": ({kk: tuned[head][kk] for kk in ("chunk", "chunk1", "narrow", "lut_dtype", "ms",
+                                                                "ms_default")} if head in tuned else "automatic"),
                    "recall_at_10": round(r["recall1"], 4),
                    "recall_definition": "1-recall@10 (exact nearest neighbour within the 10 returned); "
                                         f"10-recall@10 {r['recall10']:.4f}; {nr} queries vs FP64 brute force",

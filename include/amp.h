@@ -275,6 +275,43 @@ amp_status amp_svr_fit(const double* K, const double* y, int32_t l, double C, do
 amp_status amp_index_get_predictor(const amp_index* index, amp_predictor_model* out, int32_t* sv,
                                    int32_t* beta, int32_t* table, int32_t capacity);
 
+/*
+ * Autotuner of the search schedule.  A search's schedule (not its result:
+ * results are the same under every choice) has four knobs: the list chunk of
+ * a phase-2 work unit and of a phase-1 (bound) unit, the LUT row width (one
+ * 32-bit word per row, or the widest packing of the lane class), and the LC
+ * matrix dtype (BF16 or FP16) for policies that leave it open.  By default
+ * they follow fixed rules of the batch shape.  amp_index_autotune times
+ * candidate schedules on the current device for a representative batch
+ * (queries: host [nq][d], q_dtype rows; k / nprobe as in amp_search; one
+ * coordinate at a time, `repeats` timed searches per trial, 0 = 5) and
+ * records the fastest in the index's table under (policy kind, batch-size
+ * bucket ceil(log2 nq)); later searches of that policy kind and bucket use
+ * it.  Environment overrides (AMP_CHUNK, AMP_CHUNK1, AMP_NARROW) still take
+ * precedence.  Not to be called while other searches run on the index.
+ *   chunk, chunk1  list chunk of a phase-2 / phase-1 unit (0 = automatic)
+ *   narrow         1 one-word LUT rows, 0 widest rows, -1 automatic
+ *   lut_dtype      AMP_LUT_BF16 / AMP_LUT_F16 (0 = automatic)
+ *   ms, ms_default median time of the tuned and of the automatic schedule
+ *   trials         schedules timed
+ */
+typedef struct amp_tune_entry {
+  int32_t policy_kind, nq_log2;
+  int64_t chunk, chunk1;
+  int32_t narrow, lut_dtype;
+  float ms, ms_default;
+  int32_t trials;
+} amp_tune_entry;
+
+amp_status amp_index_autotune(amp_index* index, const void* queries, int64_t nq, const int32_t* k,
+                              const int32_t* nprobe, int32_t per_query, const amp_precision_policy* policy,
+                              int32_t q_dtype, int32_t repeats, amp_tune_entry* out /* optional */);
+/* Read the tuning table (count always set; entries NULL: size query;
+ * capacity below count: nothing copied, AMP_EINVAL) or replace it (count 0
+ * clears; entries are validated: chunks 0 or >= 256, narrow -1..1). */
+amp_status amp_index_get_tuning(const amp_index* index, amp_tune_entry* entries, int32_t capacity, int32_t* count);
+amp_status amp_index_set_tuning(amp_index* index, const amp_tune_entry* entries, int32_t count);
+
 /* Copy the index to device `device` (hipGetDevice numbering) and derive the
  * device-side tables (centroid norms, grid codebook).  Called implicitly by
  * the first search on the current device. */

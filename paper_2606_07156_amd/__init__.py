@@ -85,6 +85,7 @@ EXPORTS = ("amp_index_from_arrays", "amp_index_build", "amp_index_get_arrays", "
            "amp_index_train_predictor", "amp_svr_fit",
            "amp_index_to_device",
            "amp_index_save", "amp_index_load", "amp_index_info", "amp_search",
+           "amp_index_autotune", "amp_index_get_tuning", "amp_index_set_tuning",
            "amp_server_create", "amp_server_submit", "amp_server_cancel", "amp_server_flush",
            "amp_server_stats", "amp_server_destroy",
            "amp_index_free", "amp_status_str", "amp_last_error")
@@ -284,6 +285,52 @@ def amp_svr_fit(K, y, C_=1.0, epsilon=0.1, tol=1e-3, max_iter=100000):
     _check(lib().amp_svr_fit(_ptr(K), _ptr(y), len(y), float(C_), float(epsilon), float(tol), int(max_iter),
                              _ptr(coef), C.byref(b), C.byref(it)))
     return coef, b.value, it.value
+
+
+class _TuneEntry(C.Structure):
+    _fields_ = [("policy_kind", C.c_int32), ("nq_log2", C.c_int32), ("chunk", C.c_int64), ("chunk1", C.c_int64),
+                ("narrow", C.c_int32), ("lut_dtype", C.c_int32), ("ms", C.c_float), ("ms_default", C.c_float),
+                ("trials", C.c_int32)]
+
+
+def _tune_dict(e):
+    return {n: getattr(e, n) for n, _ in _TuneEntry._fields_}
+
+
+def amp_index_autotune(index, queries, k, nprobe, policy="fixed", bits=16, allowed=(4, 8, 12, 16), margin_q40=0,
+                       lut_dtype=0, repeats=5):
+    """Time candidate search schedules for this batch shape on the current
+    device and record the fastest in the index; returns the entry (dict)."""
+    bf16 = getattr(queries, "dtype", None) == np.uint16
+    q = np.ascontiguousarray(queries, dtype=np.uint16 if bf16 else np.float32)
+    nq = int(q.shape[0])
+    kk = np.atleast_1d(np.asarray(k, dtype=np.int32))
+    npb = np.atleast_1d(np.asarray(nprobe, dtype=np.int32))
+    per_query = int(kk.size > 1 or npb.size > 1)
+    if per_query:
+        kk = np.ascontiguousarray(np.broadcast_to(kk, (nq,)), dtype=np.int32)
+        npb = np.ascontiguousarray(np.broadcast_to(npb, (nq,)), dtype=np.int32)
+    pol, _ = make_policy(policy, bits, allowed, margin_q40, None, lut_dtype)
+    e = _TuneEntry()
+    _check(lib().amp_index_autotune(index.handle, _ptr(q), nq, _ptr(kk), _ptr(npb), per_query, C.byref(pol),
+                                    AMP_BF16 if bf16 else AMP_F32, int(repeats), C.byref(e)))
+    return _tune_dict(e)
+
+
+def amp_index_get_tuning(index):
+    n = C.c_int32()
+    _check(lib().amp_index_get_tuning(index.handle, None, 0, C.byref(n)))
+    arr = (_TuneEntry * max(1, n.value))()
+    _check(lib().amp_index_get_tuning(index.handle, arr, n.value, C.byref(n)))
+    return [_tune_dict(arr[i]) for i in range(n.value)]
+
+
+def amp_index_set_tuning(index, entries):
+    arr = (_TuneEntry * max(1, len(entries)))()
+    for i, e in enumerate(entries):
+        for n, _ in _TuneEntry._fields_:
+            setattr(arr[i], n, e.get(n, -1 if n == "narrow" else 0))
+    _check(lib().amp_index_set_tuning(index.handle, arr, len(entries)))
 
 
 def amp_index_to_device(index, device=0):

@@ -150,6 +150,11 @@ struct amp_index {
   uint64_t ws_generation = 0, model_generation = 0;
   hipGraphExec_t graph_exec = nullptr;
   amp::GraphKey graph_key{};
+  // search schedules chosen by the autotuner, by (policy kind, batch bucket);
+  // while tuning, tune_force replaces the lookup
+  std::vector<amp_tune_entry> tune;
+  bool tune_forcing = false;
+  amp_tune_entry tune_force{};
   std::mutex mu;
 };
 

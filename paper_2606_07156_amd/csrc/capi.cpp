@@ -478,7 +478,8 @@ struct SearchPlan {
   int64_t chunk, chunk1, max_units;
 };
 
-static SearchPlan plan_search(const amp_index* ix, int64_t nq, int npmax, int kmax, bool worst_case) {
+static SearchPlan plan_search(const amp_index* ix, int64_t nq, int npmax, int kmax, bool worst_case,
+                              int64_t tuned_chunk = 0, int64_t tuned_chunk1 = 0) {
   SearchPlan p;
   // candidate capacity per query: a power of two (the merge sorts up to capq
   // keys in place, 16 bytes each in LDS: at most 8192), at least kmax
@@ -493,14 +494,15 @@ static SearchPlan plan_search(const amp_index* ix, int64_t nq, int npmax, int km
   // smaller batch) is the shortest chunk.
   const int64_t mean_list = std::max<int64_t>(1, ix->n / ix->nlist);
   const int64_t slots = 512;  // persistent workgroups: 256 CUs x 2
-  auto pick_chunk = [&](int64_t pairs, int64_t per_slot, const char* env) -> int64_t {
+  auto pick_chunk = [&](int64_t pairs, int64_t per_slot, const char* env, int64_t tuned) -> int64_t {
     const int64_t c = (int64_t)env_size(env, 0);
     if (c > 0) return c;
     if (worst_case) return 4096;
+    if (tuned > 0) return tuned;
     return std::min<int64_t>(1 << 16, std::max<int64_t>(4096, pairs * mean_list / (per_slot * slots)));
   };
-  p.chunk = pick_chunk(nq * npmax, 4, "AMP_CHUNK");
-  p.chunk1 = pick_chunk(nq, 2, "AMP_CHUNK1");
+  p.chunk = pick_chunk(nq * npmax, 4, "AMP_CHUNK", tuned_chunk);
+  p.chunk1 = pick_chunk(nq, 2, "AMP_CHUNK1", tuned_chunk1);
   const int64_t max_nch = std::max<int64_t>(1, (ix->max_list + p.chunk - 1) / p.chunk);
   const int64_t max_nch1 = std::max<int64_t>(1, (ix->max_list + p.chunk1 - 1) / p.chunk1);
   p.max_units = std::max<int64_t>(nq * npmax * max_nch, nq * max_nch1);
@@ -560,7 +562,21 @@ amp_status amp_search(amp_index* ix, const void* queries, int64_t nq, const int3
   amp_status s = to_device_locked(ix, dev);
   if (s != AMP_OK) return s;
   if (pol->kind == AMP_POLICY_ADAPTIVE && ix->dev_model_stale && (s = upload_model(ix)) != AMP_OK) return s;
-  const SearchPlan plan = plan_search(ix, nq, npmax, kmax, false);
+  // the schedule: the autotuner's entry for this policy kind and batch size,
+  // if any (results do not depend on it)
+  amp_tune_entry tc{};
+  tc.narrow = -1;
+  if (ix->tune_forcing) {
+    tc = ix->tune_force;
+  } else {
+    int lg = 0;
+    while ((1ll << lg) < nq) ++lg;
+    for (const amp_tune_entry& e : ix->tune)
+      if (e.policy_kind == pol->kind && e.nq_log2 == lg) tc = e;
+  }
+  const int lut_dtype = pol->lut_dtype ? pol->lut_dtype
+                                       : (pol->kind != AMP_POLICY_FP32 ? tc.lut_dtype : 0);
+  const SearchPlan plan = plan_search(ix, nq, npmax, kmax, false, tc.chunk, tc.chunk1);
   const size_t capq = plan.capq;
   const int64_t chunk = plan.chunk, chunk1 = plan.chunk1, max_units = plan.max_units;
   const bool bf16 = opts->q_dtype == AMP_BF16;
@@ -617,8 +633,9 @@ amp_status amp_search(amp_index* ix, const void* queries, int64_t nq, const int3
   // (AMP_NARROW=0/1 forces the choice)
   {
     const char* nv = getenv("AMP_NARROW");
-    const bool narrow = nv && *nv ? nv[0] == '1' : (int64_t)nq * npmax < 4 * (int64_t)ix->nlist;
-    sd.wpr = scan_wpr(ix->M, pol->kind == AMP_POLICY_FP32, pol->lut_dtype, narrow);
+    const bool narrow = nv && *nv ? nv[0] == '1'
+                                  : (tc.narrow >= 0 ? tc.narrow == 1 : (int64_t)nq * npmax < 4 * (int64_t)ix->nlist);
+    sd.wpr = scan_wpr(ix->M, pol->kind == AMP_POLICY_FP32, lut_dtype, narrow);
   }
   sd.chunk = chunk;
   sd.chunk1 = chunk1;
@@ -627,7 +644,7 @@ amp_status amp_search(amp_index* ix, const void* queries, int64_t nq, const int3
   sd.max_units = w.cap_units;
   sd.capq = capq;
   sd.policy = pol->kind;
-  sd.lut_dtype = pol->lut_dtype;
+  sd.lut_dtype = lut_dtype;
   sd.fixed_bits = pol->fixed_bits;
   sd.allowed_mask = pol->allowed_bits_mask ? pol->allowed_bits_mask
                                            : ((1u << 4) | (1u << 8) | (1u << 12) | (1u << 16));
@@ -678,7 +695,7 @@ amp_status amp_search(amp_index* ix, const void* queries, int64_t nq, const int3
     // one captured graph per index, replayed while the launch key is unchanged
     GraphKey key{queries, out_ids, out_dist, opts->out_qdist, opts->out_probes, opts->out_bits, opts->out_coarse,
                  st, nq, k[0], nprobe[0], pol->kind, pol->fixed_bits, sd.allowed_mask, pol->margin_q40,
-                 pol->lut_dtype, ix->ws_generation, ix->model_generation, chunk, chunk1, capq, sd.wpr,
+                 lut_dtype, ix->ws_generation, ix->model_generation, chunk, chunk1, capq, sd.wpr,
                  opts->q_dtype};
     if (!ix->graph_exec || !(ix->graph_key == key)) {
       if (ix->graph_exec) hipGraphExecDestroy(ix->graph_exec);
