@@ -332,6 +332,8 @@ def main():
                     help="only run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: autotune each policy's search schedule for the batch before timing it")
+    ap.add_argument("--schedule", default="",
+                    help="chunk,chunk1,narrow,lut_dtype: use this search schedule instead of autotuning")
     ap.add_argument("--sweep", action="store_true",
                     help="batch-size sweep on the skewed workload (uneven nprobe, Zipf list sizes)")
     ap.add_argument("--batches", default="1,16,256,1024,4096")
@@ -444,7 +446,14 @@ def main():
     sizes = idx["list_sizes"].astype(np.int64)
     tuned = {}
     for name, kw in pols:
-        if args.autotune:
+        if args.schedule:
+            # a fixed schedule for every policy (profiling runs: no tuning trials in the trace)
+            c, c1, nw, lt = (int(x) for x in args.schedule.split(","))
+            ent = dict(policy_kind=amp.POLICIES[kw["policy"]], chunk=c, chunk1=c1, narrow=nw, lut_dtype=lt)
+            lg = int(np.ceil(np.log2(nq)))
+            amp.amp_index_set_tuning(h, [dict(ent, nq_log2=lg)])
+            tuned[name] = dict(ent, ms=0.0, ms_default=0.0)
+        elif args.autotune:
             # schedule (unit chunking, LUT row width, LC dtype) timed for this
             # batch shape; results do not depend on it
             tuned[name] = amp.amp_index_autotune(h, QP[:nq] if n_batches > 1 else Q, k, nprobe, repeats=3, **kw)

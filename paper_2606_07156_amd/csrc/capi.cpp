@@ -490,19 +490,23 @@ static SearchPlan plan_search(const amp_index* ix, int64_t nq, int npmax, int km
   // its pairs' LUTs, and a chunked phase 1 gives a looser bound); otherwise
   // (few queries, long lists: the streaming case) chunks sized for about four
   // (phase 2) or two (phase 1) units per workgroup slot of the chip, at least
-  // 4096 vectors.  AMP_CHUNK / AMP_CHUNK1 override.  The worst case (any
-  // smaller batch) is the shortest chunk.
+  // 4096 vectors.  AMP_CHUNK / AMP_CHUNK1 and the autotuner's table
+  // override.  The worst case (any smaller batch) is the shortest automatic
+  // chunk.
   const int64_t mean_list = std::max<int64_t>(1, ix->n / ix->nlist);
   const int64_t slots = 512;  // persistent workgroups: 256 CUs x 2
-  auto pick_chunk = [&](int64_t pairs, int64_t per_slot, const char* env, int64_t tuned) -> int64_t {
+  auto pick_chunk = [&](int64_t pairs, int64_t per_slot, int64_t lo, const char* env, int64_t tuned) -> int64_t {
     const int64_t c = (int64_t)env_size(env, 0);
     if (c > 0) return c;
-    if (worst_case) return 4096;
+    if (worst_case) return lo;
     if (tuned > 0) return tuned;
-    return std::min<int64_t>(1 << 16, std::max<int64_t>(4096, pairs * mean_list / (per_slot * slots)));
+    return std::min<int64_t>(1 << 16, std::max<int64_t>(lo, pairs * mean_list / (per_slot * slots)));
   };
-  p.chunk = pick_chunk(nq * npmax, 4, "AMP_CHUNK", tuned_chunk);
-  p.chunk1 = pick_chunk(nq, 2, "AMP_CHUNK1", tuned_chunk1);
+  // (every phase-1 chunk adds its own minima to the query's bound, so
+  // splitting a list does not loosen the bound; each chunk rebuilds its
+  // LUTs, so the autotuner may go down to 1024 where that pays)
+  p.chunk = pick_chunk(nq * npmax, 4, 4096, "AMP_CHUNK", tuned_chunk);
+  p.chunk1 = pick_chunk(nq, 2, 4096, "AMP_CHUNK1", tuned_chunk1);
   const int64_t max_nch = std::max<int64_t>(1, (ix->max_list + p.chunk - 1) / p.chunk);
   const int64_t max_nch1 = std::max<int64_t>(1, (ix->max_list + p.chunk1 - 1) / p.chunk1);
   p.max_units = std::max<int64_t>(nq * npmax * max_nch, nq * max_nch1);

@@ -369,7 +369,8 @@ struct PairArgs {
   const uint8_t* xbits;
   uint8_t* pbits;
   int nq, d, npmax, grid_e, grid_kind, metric, policy, fixed_bits, lane_sel_M;
-  int lg_npp;  // log2 of the threads per query (power of two >= npmax, <= 256)
+  int lg_npp;  // log2 of the pair slots per query (power of two >= npmax)
+  int lg_T;    // log2 of the threads per pair (small batches: several share the work)
   uint32_t allowed;
   int64_t margin;
 };
@@ -390,18 +391,21 @@ __device__ __forceinline__ int pick_bits(int64_t y, const int64_t* theta, uint32
   return last;
 }
 
-// 256 threads per workgroup: 256 / npp queries, npp (power of two >= npmax)
-// threads per query, one per probe rank
+// 256 threads per workgroup: 256 / (npp T) queries, npp (power of two >=
+// npmax) pair slots per query, T threads per pair (T > 1 only for batches too
+// small to fill the chip: the T threads split the residual norm and the
+// support-vector sum, then combine them across their lanes)
 __global__ __launch_bounds__(256) void k_pairs(PairArgs a, ModelArgs ma) {
   __shared__ unsigned long long s_best[256];
   __shared__ int32_t s_table[kTableN];
-  const int lg = a.lg_npp;
-  const int slot = threadIdx.x >> lg, r = threadIdx.x & ((1 << lg) - 1);
-  const int q = blockIdx.x * (256 >> lg) + slot;
+  const int lg = a.lg_npp, lt = a.lg_T, T = 1 << lt;
+  const int t = threadIdx.x & (T - 1);
+  const int slot = threadIdx.x >> (lg + lt), r = (threadIdx.x >> lt) & ((1 << lg) - 1);
+  const int q = blockIdx.x * (256 >> (lg + lt)) + slot;
   const bool adaptive = a.policy == AMP_POLICY_ADAPTIVE;
   if (adaptive)
     for (int i = threadIdx.x; i < kTableN; i += blockDim.x) s_table[i] = ma.table[i];
-  if (r == 0) s_best[slot] = ~0ull;
+  if ((threadIdx.x & ((1 << (lg + lt)) - 1)) == 0) s_best[slot] = ~0ull;
   __syncthreads();
   const bool valid = q < a.nq && r < a.npmax;
   const int p = valid ? a.probes[(size_t)q * a.npmax + r] : -1;
@@ -411,8 +415,8 @@ __global__ __launch_bounds__(256) void k_pairs(PairArgs a, ModelArgs ma) {
     const float4* qv = reinterpret_cast<const float4*>(a.Q + (size_t)q * a.d);
     const float4* cv = reinterpret_cast<const float4*>(a.C + (size_t)p * a.d);
     const bool l2 = a.metric == AMP_L2;
-    for (int t = 0; t < (a.d >> 2); ++t) {
-      const float4 x = qv[t], c = cv[t];
+    for (int i = t; i < (a.d >> 2); i += T) {
+      const float4 x = qv[i], c = cv[i];
       int v0, v1, v2, v3;
       if (l2) {
         v0 = grid_val(x.x - c.x, a.grid_e, a.grid_kind);
@@ -427,8 +431,11 @@ __global__ __launch_bounds__(256) void k_pairs(PairArgs a, ModelArgs ma) {
       }
       dq2 += (int64_t)(v0 * v0 + v1 * v1) + (int64_t)(v2 * v2 + v3 * v3);
     }
-    atomicMin(&s_best[slot], (unsigned long long)((uint64_t)dq2 << 13 | (uint64_t)p));
   }
+  // the T threads of a pair are adjacent lanes of one wave (T <= 64)
+  for (int o = 1; o < T; o <<= 1) dq2 += __shfl_xor(dq2, o);
+  if (adaptive && p >= 0 && t == 0)
+    atomicMin(&s_best[slot], (unsigned long long)((uint64_t)dq2 << 13 | (uint64_t)p));
   __syncthreads();
   if (!valid) return;
   uint8_t bits = 0;
@@ -452,8 +459,9 @@ __global__ __launch_bounds__(256) void k_pairs(PairArgs a, ModelArgs ma) {
         int64_t v = ((mitchell_q8(x[f]) - ma.feat_lo[f]) * ma.feat_mul[f]) >> 16;
         u[f] = (int32_t)(v < 0 ? 0 : (v > 1023 ? 1023 : v));
       }
-      int64_t y = ma.beta0;
-      for (int i = 0; i < ma.n_sv; ++i) {
+      // integer sum: the split over threads does not change the result
+      int64_t y = 0;
+      for (int i = t; i < ma.n_sv; i += T) {
         const int32_t* sv = ma.sv + 5 * i;
         int32_t d0 = u[0] - sv[0], d1 = u[1] - sv[1], d2 = u[2] - sv[2], d3 = u[3] - sv[3], d4 = u[4] - sv[4];
         uint32_t dist2 = (uint32_t)(d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3 + d4 * d4);
@@ -461,10 +469,11 @@ __global__ __launch_bounds__(256) void k_pairs(PairArgs a, ModelArgs ma) {
         int32_t K = s_table[idx > (kTableN - 1) ? (kTableN - 1) : idx];
         y += (int64_t)ma.beta[i] * K;
       }
-      bits = (uint8_t)pick_bits(y, ma.theta, a.allowed, a.margin);
+      for (int o = 1; o < T; o <<= 1) y += __shfl_xor(y, o);
+      bits = (uint8_t)pick_bits(ma.beta0 + y, ma.theta, a.allowed, a.margin);
     }
   }
-  a.pbits[(size_t)q * a.npmax + r] = bits;
+  if (t == 0) a.pbits[(size_t)q * a.npmax + r] = bits;
 }
 
 // ------------------------------------------------------------------ queue
@@ -691,9 +700,9 @@ struct ScanArgs {
   uint64_t* ckey;
   int64_t* cid;
   int32_t* flags;
-  const uint8_t* retry;     // re-run of phase 2: queries taking part (null: every query)
-  const int64_t* tau_id;    // re-run of phase 2: id of the bound's (distance, id) key
-  const int32_t* any_retry; // re-run of phase 2: non-zero if any query takes part
+  const uint8_t* retry;     // phase 3 (re-run of phase 2): queries taking part
+  const int64_t* tau_id;    // phase 3: id of the bound's (distance, id) key
+  const int32_t* any_retry; // phase 3: non-zero if any query takes part
   int nq, d, M, dsub, nlist, npmax, grid_e, grid_kind, metric, kconst, kmax, cls;
   int64_t chunk;
   size_t capq;
@@ -707,6 +716,9 @@ __host__ __device__ constexpr int wpr_for(int M) { return M <= 16 ? 4 : (M <= 32
 // The work-unit queue packs pairs into units with the same figure, so both
 // sides take it from here.
 __host__ __device__ constexpr int kernel_wpr(int MT) { return MT ? wpr_for(MT) : 1; }
+// a variant specialised for MT may also run with one-word rows (NR = 1:
+// sparse batches, a few pairs per list), keeping its codes in registers
+__host__ __device__ constexpr int variant_wpr(int MT, int NR) { return NR ? 1 : kernel_wpr(MT); }
 
 // LDS carve-up of one scan workgroup (all offsets in bytes, 16-aligned)
 struct ScanLds {
@@ -731,7 +743,7 @@ __host__ __device__ inline ScanLds scan_lds_layout(int G, int wpr, int M, int d,
   if (phase == 1 && G * kThreadsP2 * 4 > M * kKsub * wpr * 4) L.lmin = take(G * kThreadsP2 * 4);
   // unit-claim control words: kept in the dynamic LDS too, so that the LUT
   // starts at LDS address 0 and row addresses fold into instruction offsets
-  L.ctl = take(32);  // unit index, class, re-run vote, unit descriptor
+  L.ctl = take(32);  // unit index, class, re-run vote, live vote, unit descriptor
   L.total = o;
   return L;
 }
@@ -979,10 +991,10 @@ struct Owned {
 // One work unit (G pairs of one list, lane class LWB; 0 = FP32 LUT): RC, LC,
 // quantisation, DC scan, and the phase's bound or candidate forwarding.
 // L may be the layout of a larger tile (the mixed-class kernel).
-template <int LWB, int MT, int PHASE, int DT, typename Own, typename Fetch>
+template <int LWB, int MT, int PHASE, int DT, int NR, typename Own, typename Fetch>
 __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const ScanLds& L, const Own& own,
                                           const int4 unit, Fetch&& fetch_next) {
-  constexpr int WPR = kernel_wpr(MT);
+  constexpr int WPR = variant_wpr(MT, NR);
   constexpr bool FP = LWB == 0;
   constexpr int W = Lane<LWB>::W;
   constexpr int G = WPR * W;
@@ -1017,7 +1029,7 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
         pb[tid] = 16;
       }
     }
-    if (PHASE == 2 && a.retry) {
+    if (PHASE == 3) {
       // re-run: a unit with no pair of a re-run query is skipped whole (the
       // vote goes through a control word of the dynamic LDS: the scan
       // kernels use no static LDS)
@@ -1070,6 +1082,33 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
       }
     }
     __syncthreads();
+    // ---- per-pair pruning threshold in the lane domain (phases 2, 3): a
+    // pair whose base already exceeds its query's bound is dead (pb = -1)
+    auto thresholds = [&] {
+      if (PHASE >= 2 && tid < G) {
+        uint32_t sig = 0;
+        bool live = false;
+        if (tid < np_u && (PHASE != 3 || a.retry[pq[tid]])) {
+          const uint64_t tk = a.tau[pq[tid]];
+          live = true;
+          if (tk == ~0ull) {
+            sig = 0xFFFFFFFFu;
+          } else if constexpr (FP) {
+            sig = (uint32_t)tk;
+          } else {
+            const int64_t t = ikey_val(tk);
+            if (t < pbase[tid]) {
+              live = false;
+            } else {
+              const int64_t dd = (t - pbase[tid]) >> ps[tid];
+              sig = dd > (int64_t)MASK ? MASK : (uint32_t)dd;
+            }
+          }
+        }
+        psig[tid] = live ? sig : 0;
+        pb[tid] = live ? pb[tid] : -1;  // -1: no candidate can pass
+      }
+    };
     // ---- LC
     if constexpr (FP) {
       // T[m][j] = (|r_m|^2 + |c_mj|^2) - 2 r_m.c_mj in FP32 (one FMA chain per entry)
@@ -1207,6 +1246,20 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
         }
       }
       __syncthreads();
+      if constexpr (PHASE >= 2) {
+        // the bases are known before pass 2: a unit whose pairs are all dead
+        // skips pass 2 and the scan (the vote goes through a control word)
+        thresholds();
+        int& s_live = *reinterpret_cast<int*>(lds + L.ctl + 12);
+        if (tid == 0) s_live = 0;
+        __syncthreads();
+        if (tid < np_u && pb[tid] >= 0) s_live = 1;
+        __syncthreads();
+        if (!s_live) {
+          fetch_next();
+          return;
+        }
+      }
       {
         // lo -> the offset hf(s) - lo that pass 2 adds before the shift
         int32_t* lo = reinterpret_cast<int32_t*>(lds + L.lo);
@@ -1220,38 +1273,17 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
       else build(P2{}, L2t{});
       __syncthreads();
     }
-    // ---- per-pair pruning threshold in the lane domain (phase 2)
-    if (PHASE == 2 && tid < G) {
-      uint32_t sig = 0;
-      bool live = false;
-      if (tid < np_u && (!a.retry || a.retry[pq[tid]])) {
-        const uint64_t tk = a.tau[pq[tid]];
-        live = true;
-        if (tk == ~0ull) {
-          sig = 0xFFFFFFFFu;
-        } else if constexpr (FP) {
-          sig = (uint32_t)tk;
-        } else {
-          const int64_t t = ikey_val(tk);
-          if (t < pbase[tid]) {
-            live = false;
-          } else {
-            const int64_t dd = (t - pbase[tid]) >> ps[tid];
-            sig = dd > (int64_t)MASK ? MASK : (uint32_t)dd;
-          }
-        }
-      }
-      psig[tid] = live ? sig : 0;
-      pb[tid] = live ? pb[tid] : -1;  // -1: no candidate can pass
+    if constexpr (FP) {  // (integer LUTs: right after the shifts, before pass 2)
+      thresholds();
+      __syncthreads();
     }
-    __syncthreads();
     // ---- DC scan: one vector per thread, codes of the next vector prefetched
     uint32_t sig[G];
     bool live[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       sig[g] = psig[g];
-      live[g] = PHASE == 2 ? pb[g] >= 0 : g < np_u;
+      live[g] = PHASE >= 2 ? pb[g] >= 0 : g < np_u;
     }
     uint32_t lmin[G];
 #pragma unroll
@@ -1259,7 +1291,7 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
     // packed thresholds of the 8-bit lane class: fields 0,2 and 1,3 of each
     // word in 16-bit halves with guard bit 8; dead pairs never hit
     uint32_t sig_e[WPR], sig_o[WPR], msk_e[WPR], msk_o[WPR];
-    if constexpr (PHASE == 2 && LWB == 8) {
+    if constexpr (PHASE >= 2 && LWB == 8) {
 #pragma unroll
       for (int w = 0; w < WPR; ++w) {
         uint32_t se = 0, so = 0, me = 0, mo = 0;
@@ -1276,31 +1308,46 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
     }
     lds_u32* lut = reinterpret_cast<lds_u32*>((uintptr_t)L.lut);  // LDS address (see lds_u32)
     constexpr int MQ = MT ? MT / 4 : 1;  // code dwords per vector held in registers
-    uint32_t cw_next[MQ];
-    {
-      const int64_t v = v0 + tid;
-      if constexpr (MT != 0) {
+    // vectors per thread and step: one-word rows (a few pairs per list, the
+    // streaming case) make a vector cheap to scan, so four are kept in flight
+    // to cover HBM latency; wide rows are compute-bound at one
+    constexpr int PV = (NR && MT != 0) ? 4 : 1;
+    uint32_t cw_next[PV][MQ];
+    if constexpr (MT != 0) {
+#pragma unroll
+      for (int pv = 0; pv < PV; ++pv) {
+        const int64_t v = v0 + tid + pv * kThreads;
         if (v < v1) {
           const uint32_t* cp = reinterpret_cast<const uint32_t*>(a.codes + (size_t)(L0 + v) * MT);
 #pragma unroll
-          for (int i = 0; i < MQ; ++i) cw_next[i] = cp[i];
+          for (int i = 0; i < MQ; ++i) cw_next[pv][i] = cp[i];
         }
       }
     }
     fetch_next();  // the next unit's descriptor, read while this one scans
-    for (int64_t vb = v0; vb < v1; vb += kThreads) {
-      const int64_t v = vb + tid;
-      uint32_t cw[MQ];
+    for (int64_t vb = v0; vb < v1; vb += kThreads * PV) {
+      uint32_t cwg[PV][MQ];
 #pragma unroll
-      for (int i = 0; i < MQ; ++i) cw[i] = cw_next[i];
+      for (int pv = 0; pv < PV; ++pv)
+#pragma unroll
+        for (int i = 0; i < MQ; ++i) cwg[pv][i] = cw_next[pv][i];
       if constexpr (MT != 0) {
-        const int64_t vn = v + kThreads;
-        if (vn < v1) {
-          const uint32_t* cp = reinterpret_cast<const uint32_t*>(a.codes + (size_t)(L0 + vn) * MT);
 #pragma unroll
-          for (int i = 0; i < MQ; ++i) cw_next[i] = cp[i];
+        for (int pv = 0; pv < PV; ++pv) {
+          const int64_t vn = vb + tid + (PV + pv) * kThreads;
+          if (vn < v1) {
+            const uint32_t* cp = reinterpret_cast<const uint32_t*>(a.codes + (size_t)(L0 + vn) * MT);
+#pragma unroll
+            for (int i = 0; i < MQ; ++i) cw_next[pv][i] = cp[i];
+          }
         }
       }
+#pragma unroll
+      for (int pv = 0; pv < PV; ++pv) {
+      const int64_t v = vb + tid + pv * kThreads;
+      uint32_t cw[MQ];
+#pragma unroll
+      for (int i = 0; i < MQ; ++i) cw[i] = cwg[pv][i];
       if (v < v1) {
         uint32_t acc[WPR];
         float accf[WPR];
@@ -1330,14 +1377,14 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
           else key = ikey(pbase[g] + ((int64_t)S << ps[g]));
           const int64_t id = a.ids[L0 + v];
           // re-run: the bound is a (distance, id) key, ties past its id go
-          if (PHASE == 2 && a.retry && key == a.tau[q] && id > a.tau_id[q]) return;
+          if (PHASE == 3 && key == a.tau[q] && id > a.tau_id[q]) return;
           const uint32_t pos = atomicAdd(&a.ccount[q], 1u);
           if (pos < a.capq) {
             a.ckey[(size_t)q * a.capq + pos] = key;
             a.cid[(size_t)q * a.capq + pos] = id;
           }
         };
-        if constexpr (PHASE == 2 && LWB == 8) {
+        if constexpr (PHASE >= 2 && LWB == 8) {
           // four 8-bit sums per word: test all four against their thresholds
           // at once in two 16-bit-lane halves (guard bit 8 survives iff S <= sigma)
 #pragma unroll
@@ -1369,6 +1416,7 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
           }
         }
       }
+      }  // vectors of the step
     }
     if (PHASE == 1 && a.kmax <= 64) {
       // the k-th smallest of a wave's per-lane minima bounds the pair's k-th
@@ -1448,10 +1496,10 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
 // from a device counter; the next unit is claimed while the current one is
 // processed (index at the start, descriptor before the scan, published at
 // the end)
-template <int LWB, int MT, int PHASE, int DT>
+template <int LWB, int MT, int PHASE, int DT, int NR>
 __global__ __launch_bounds__(kThreads, 2) void k_scan(ScanArgs a) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
-  constexpr int WPR = kernel_wpr(MT);
+  constexpr int WPR = variant_wpr(MT, NR);
   constexpr bool FP = LWB == 0;
   constexpr int G = WPR * Lane<LWB>::W;
   constexpr bool CRES = FP && MT != 0 && MT <= 16;
@@ -1461,7 +1509,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_scan(ScanArgs a) {
     if (threadIdx.x == 0) atomicOr(&a.flags[0], 16);
     return;
   }
-  if (PHASE == 2 && a.any_retry && *a.any_retry == 0) return;  // re-run with nothing to do
+  if (PHASE == 3 && *a.any_retry == 0) return;  // re-run of phase 2 with nothing to do
   int& s_u = *reinterpret_cast<int*>(lds + L.ctl);
   int4& s_unit = *reinterpret_cast<int4*>(lds + L.ctl + 16);
   const int tid = threadIdx.x;
@@ -1489,7 +1537,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_scan(ScanArgs a) {
     int next_u = 0;
     int4 next_unit = make_int4(0, 0, 0, 0);
     if (tid == 0) next_u = (int)atomicAdd(a.counter, 1u);
-    scan_unit<LWB, MT, PHASE, DT>(a, lds, L, own, s_unit, [&] {
+    scan_unit<LWB, MT, PHASE, DT, NR>(a, lds, L, own, s_unit, [&] {
       if (tid == 0 && ub + next_u < ue) next_unit = a.units[ub + next_u];
     });
     __syncthreads();
@@ -1505,17 +1553,17 @@ __global__ __launch_bounds__(kThreads, 2) void k_scan(ScanArgs a) {
 // the order 32-bit, 16-bit, 8-bit units (each largest list first): the few
 // wide units start early and the many 8-bit units fill the tail.  The LDS
 // tile of the 8-bit class (the most pairs per unit) serves every class.
-template <int MT, int PHASE, int DT>
+template <int MT, int PHASE, int DT, int NR>
 __global__ __launch_bounds__(kThreads, 2) void k_scan_mix(ScanArgs a) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
-  constexpr int WPR = kernel_wpr(MT);
+  constexpr int WPR = variant_wpr(MT, NR);
   const int M = MT ? MT : a.M;
   const ScanLds L = scan_lds_layout(WPR * Lane<8>::W, WPR, M, a.d, false, PHASE);
   if (__builtin_amdgcn_groupstaticsize() != 0) {  // the LUT must start at LDS address 0
     if (threadIdx.x == 0) atomicOr(&a.flags[0], 16);
     return;
   }
-  if (PHASE == 2 && a.any_retry && *a.any_retry == 0) return;  // re-run with nothing to do
+  if (PHASE == 3 && *a.any_retry == 0) return;  // re-run of phase 2 with nothing to do
   int& s_u = *reinterpret_cast<int*>(lds + L.ctl);
   int& s_cls = *reinterpret_cast<int*>(lds + L.ctl + 4);
   int4& s_unit = *reinterpret_cast<int4*>(lds + L.ctl + 16);
@@ -1551,9 +1599,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_scan_mix(ScanArgs a) {
       if (tid == 0 && next_u < total) next_unit = a.units[locate(next_u, next_cls)];
     };
     const int cls = s_cls;
-    if (cls == 0) scan_unit<8, MT, PHASE, DT>(a, lds, L, own, s_unit, fetch);
-    else if (cls == 1) scan_unit<16, MT, PHASE, DT>(a, lds, L, own, s_unit, fetch);
-    else scan_unit<32, MT, PHASE, DT>(a, lds, L, own, s_unit, fetch);
+    if (cls == 0) scan_unit<8, MT, PHASE, DT, NR>(a, lds, L, own, s_unit, fetch);
+    else if (cls == 1) scan_unit<16, MT, PHASE, DT, NR>(a, lds, L, own, s_unit, fetch);
+    else scan_unit<32, MT, PHASE, DT, NR>(a, lds, L, own, s_unit, fetch);
     __syncthreads();
     if (tid == 0) {
       s_u = next_u;
@@ -1812,11 +1860,12 @@ static int dt_of(int lut_dtype) {
 // (the FP32 LUT has no LC dtype)
 // (wpr: the words per row the queue packed for; a batch too sparse to fill
 // wide rows runs the generic one-word variant, see scan_wpr)
-static int scan_mt(int lwb, int M, int dt, int wpr = 0) {
+static int scan_mt(int lwb, int M, int dt) {
   if (lwb != 0 && dt != DT_BF16) return 0;
-  const int mt = (M == 8 || M == 16 || M == 24) ? M : 0;
-  return (wpr == 1 && kernel_wpr(mt) != 1) ? 0 : mt;
+  return (M == 8 || M == 16 || M == 24) ? M : 0;
 }
+// one-word rows on a specialised variant
+static int scan_nr(int mt, int wpr) { return (wpr == 1 && kernel_wpr(mt) != 1) ? 1 : 0; }
 
 static size_t scan_lds_bytes(int lw_bits, int phase, int M, int d, int wpr) {
   const bool fp = lw_bits == 0;
@@ -1829,23 +1878,30 @@ int scan_wpr(int M, bool fp32, int lut_dtype, bool narrow) {
 }
 
 typedef void (*ScanFn)(ScanArgs);
-template <int LWB, int MT, int PH, int DT>
-static ScanFn scan_fn() { return k_scan<LWB, MT, PH, DT>; }
+template <int LWB, int MT, int PH, int DT, int NR>
+static ScanFn scan_fn() { return k_scan<LWB, MT, PH, DT, NR>; }
 
 // kernels specialised for the subspace counts 8, 16 and 24 (codes and, for
-// the FP32 LUT, codewords kept in registers) with the BF16 LUT build; any
-// other M, and the FP16 / FP8 LUT builds, run the generic variant
+// the FP32 LUT, codewords kept in registers) with the BF16 LUT build, with
+// wide or one-word rows; any other M, and the FP16 LUT build, run the
+// generic variant
 static ScanFn pick_scan(int lwb, int M, int ph, int dt, int wpr) {
-  const int mt = scan_mt(lwb, M, dt, wpr);
+  const int mt = scan_mt(lwb, M, dt), nr = scan_nr(mt, wpr);
+#define AMP_PH(L, MT, DTV, NRV)                                                            \
+  return ph == 1 ? scan_fn<L, MT, 1, DTV, NRV>()                                           \
+                 : (ph == 2 ? scan_fn<L, MT, 2, DTV, NRV>() : scan_fn<L, MT, 3, DTV, NRV>());
 #define AMP_PICK_M(L, MT) \
-  if (mt == MT) return ph == 1 ? scan_fn<L, MT, 1, DT_BF16>() : scan_fn<L, MT, 2, DT_BF16>();
-#define AMP_PICK(L)                                                                        \
-  if (lwb == L) {                                                                          \
-    if (L != 0 && dt == DT_F16) return ph == 1 ? scan_fn<L, 0, 1, DT_F16>() : scan_fn<L, 0, 2, DT_F16>(); \
-    AMP_PICK_M(L, 8)                                                                       \
-    AMP_PICK_M(L, 16)                                                                      \
-    AMP_PICK_M(L, 24)                                                                      \
-    AMP_PICK_M(L, 0)                                                                       \
+  if (mt == MT) {         \
+    if (nr) { AMP_PH(L, MT, DT_BF16, 1) } \
+    AMP_PH(L, MT, DT_BF16, 0)             \
+  }
+#define AMP_PICK(L)                                  \
+  if (lwb == L) {                                    \
+    if (L != 0 && dt == DT_F16) { AMP_PH(L, 0, DT_F16, 0) } \
+    AMP_PICK_M(L, 8)                                 \
+    AMP_PICK_M(L, 16)                                \
+    AMP_PICK_M(L, 24)                                \
+    AMP_PH(L, 0, DT_BF16, 0)                         \
   }
   AMP_PICK(0)
   AMP_PICK(8)
@@ -1853,30 +1909,42 @@ static ScanFn pick_scan(int lwb, int M, int ph, int dt, int wpr) {
   AMP_PICK(32)
 #undef AMP_PICK
 #undef AMP_PICK_M
+#undef AMP_PH
   return nullptr;
 }
 
-template <int MT, int PH, int DT>
-static ScanFn mix_fn() { return k_scan_mix<MT, PH, DT>; }
+template <int MT, int PH, int DT, int NR>
+static ScanFn mix_fn() { return k_scan_mix<MT, PH, DT, NR>; }
 
 // the mixed-class variant of the same specialisation as pick_scan's
 static ScanFn pick_mix(int M, int ph, int dt, int wpr) {
-  const int mt = scan_mt(8, M, dt, wpr);
-  if (dt == DT_F16) return ph == 1 ? mix_fn<0, 1, DT_F16>() : mix_fn<0, 2, DT_F16>();
-  if (mt == 8) return ph == 1 ? mix_fn<8, 1, DT_BF16>() : mix_fn<8, 2, DT_BF16>();
-  if (mt == 16) return ph == 1 ? mix_fn<16, 1, DT_BF16>() : mix_fn<16, 2, DT_BF16>();
-  if (mt == 24) return ph == 1 ? mix_fn<24, 1, DT_BF16>() : mix_fn<24, 2, DT_BF16>();
-  return ph == 1 ? mix_fn<0, 1, DT_BF16>() : mix_fn<0, 2, DT_BF16>();
+  const int mt = scan_mt(8, M, dt), nr = scan_nr(mt, wpr);
+#define AMP_PH(MT, DTV, NRV) \
+  return ph == 1 ? mix_fn<MT, 1, DTV, NRV>() : (ph == 2 ? mix_fn<MT, 2, DTV, NRV>() : mix_fn<MT, 3, DTV, NRV>());
+  if (dt == DT_F16) { AMP_PH(0, DT_F16, 0) }
+#define AMP_MIX_M(MT)          \
+  if (mt == MT) {              \
+    if (nr) { AMP_PH(MT, DT_BF16, 1) } \
+    AMP_PH(MT, DT_BF16, 0)     \
+  }
+  AMP_MIX_M(8)
+  AMP_MIX_M(16)
+  AMP_MIX_M(24)
+#undef AMP_MIX_M
+  AMP_PH(0, DT_BF16, 0)
+#undef AMP_PH
 }
 
 static int g_num_cu = 0;
 
 // lwb < 0: every integer lane class in one launch (k_scan_mix)
 static hipError_t launch_scan(int lwb, int ph, int dt, int wpr, const ScanArgs& sa, hipStream_t st) {
+  // phase 3 (the re-run) usually has nothing to do: one workgroup per CU
   const bool mix = lwb < 0;
   ScanFn fn = mix ? pick_mix(sa.M, ph, dt, wpr) : pick_scan(lwb, sa.M, ph, dt, wpr);
   // the queue packed units for `wpr` words per row: the variant must agree
-  if (!fn || kernel_wpr(scan_mt(mix ? 8 : lwb, sa.M, dt, wpr)) != wpr) return hipErrorInvalidValue;
+  const int mt = scan_mt(mix ? 8 : lwb, sa.M, dt);
+  if (!fn || variant_wpr(mt, scan_nr(mt, wpr)) != wpr) return hipErrorInvalidValue;
   const size_t lds = scan_lds_bytes(mix ? 8 : lwb, ph, sa.M, sa.d, wpr);
   hipError_t e = hipFuncSetAttribute(kaddr(fn), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -1889,7 +1957,7 @@ static hipError_t launch_scan(int lwb, int ph, int dt, int wpr, const ScanArgs& 
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&g_num_cu, hipDeviceAttributeMultiprocessorCount, dev);
   }
-  hipLaunchKernelGGL(fn, dim3(g_num_cu * per_cu), dim3(kThreads), lds, st, sa);
+  hipLaunchKernelGGL(fn, dim3(g_num_cu * (ph == 3 ? 1 : per_cu)), dim3(kThreads), lds, st, sa);
   return hipGetLastError();
 }
 
@@ -1984,7 +2052,12 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   pa.margin = sd.margin;
   pa.lg_npp = 0;
   while ((1 << pa.lg_npp) < sd.npmax) ++pa.lg_npp;
-  const int qpb = 256 >> pa.lg_npp;
+  // threads per pair: more for batches too small to fill the chip (about
+  // 2^17 threads), at most 64 and at most one query per workgroup
+  pa.lg_T = 0;
+  while (pa.lg_T < 6 && pa.lg_npp + pa.lg_T < 8 && ((int64_t)sd.nq << (pa.lg_npp + pa.lg_T + 1)) <= (1 << 17))
+    ++pa.lg_T;
+  const int qpb = 256 >> (pa.lg_npp + pa.lg_T);
   hipLaunchKernelGGL(k_pairs, dim3((sd.nq + qpb - 1) / qpb), dim3(256), 0, st, pa, ma);
   mark(3);
   // queue
@@ -2076,7 +2149,19 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
       sa_lwb = -1;
     }
     if ((err = launch_scan(sa_lwb, ph, dt, sd.wpr, sa, st)) != hipSuccess) return err;
+    if (ph == 1) {
+      // phase-1 minima -> per-query bound, buffer emptied for the candidates
+      hipLaunchKernelGGL(k_tau_wave, dim3((sd.nq + 3) / 4), dim3(256), 0, st, ws.ccount, ws.ckey, ws.tau, ws.kq,
+                         sd.kconst, sd.nq, sd.capq, ws.flags + 1);
+      const size_t tlds = sd.capq * 8;
+      err = hipFuncSetAttribute(kaddr(k_tau), hipFuncAttributeMaxDynamicSharedMemorySize, (int)tlds);
+      if (err != hipSuccess) return err;
+      hipLaunchKernelGGL(k_tau, dim3(sd.nq < 512 ? sd.nq : 512), dim3(256), tlds, st, ws.ccount, ws.ckey, ws.tau,
+                         ws.kq, sd.kconst, sd.nq, sd.capq);
+    }
+    mark(4 + ph);
     if (ph == 2) {
+      // (timed with the merge stage: the phase-2 stage is its scan alone)
       // up to two re-runs of phase 2 for queries whose candidates overflowed,
       // each with a tighter bound (the scan kernels return at once when no
       // query takes part); each re-run shrinks a query's candidate count by
@@ -2089,23 +2174,13 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
       sr.tau_id = ws.tau_id;
       for (int rr = 0; rr < 2; ++rr) {
         sr.any_retry = ws.flags + 1 + rr;  // one flag per round
-        hipLaunchKernelGGL(k_retry, dim3(sd.nq < 512 ? sd.nq : 512), dim3(256), rlds, st, ws.ccount, ws.ckey,
+        hipLaunchKernelGGL(k_retry, dim3(sd.nq < 256 ? sd.nq : 256), dim3(256), rlds, st, ws.ccount, ws.ckey,
                            ws.cid, ws.tau, ws.tau_id, ws.kq, sd.kconst, sd.nq, sd.capq, ws.retry,
                            ws.flags + 1 + rr, ws.counters + (kNCls + 1), kNCls + 1);
-        if ((err = launch_scan(sa_lwb, ph, dt, sd.wpr, sr, st)) != hipSuccess) return err;
+        // phase 3: the phase-2 scan's re-run (its own kernel symbol)
+        if ((err = launch_scan(sa_lwb, 3, dt, sd.wpr, sr, st)) != hipSuccess) return err;
       }
     }
-    if (ph == 1) {
-      // phase-1 minima -> per-query bound, buffer emptied for the candidates
-      hipLaunchKernelGGL(k_tau_wave, dim3((sd.nq + 3) / 4), dim3(256), 0, st, ws.ccount, ws.ckey, ws.tau, ws.kq,
-                         sd.kconst, sd.nq, sd.capq, ws.flags + 1);
-      const size_t tlds = sd.capq * 8;
-      err = hipFuncSetAttribute(kaddr(k_tau), hipFuncAttributeMaxDynamicSharedMemorySize, (int)tlds);
-      if (err != hipSuccess) return err;
-      hipLaunchKernelGGL(k_tau, dim3(sd.nq < 512 ? sd.nq : 512), dim3(256), tlds, st, ws.ccount, ws.ckey, ws.tau,
-                         ws.kq, sd.kconst, sd.nq, sd.capq);
-    }
-    mark(4 + ph);
   }
   // TS
   MergeArgs ma2;

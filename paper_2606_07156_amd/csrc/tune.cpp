@@ -162,7 +162,7 @@ extern "C" amp_status amp_index_autotune(amp_index* ix, const void* queries, int
     }
     {
       amp_tune_entry base = best;
-      const int64_t cands[] = {whole, 16384, 4096};
+      const int64_t cands[] = {whole, 16384, 4096, 1024};
       for (int64_t c0 : cands) {
         if (c0 != whole && c0 >= whole) continue;
         amp_tune_entry c = base;
