@@ -22,6 +22,9 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+KIND_TEXT = {"uint8": "integer-valued Gaussian mixture", "iso": "isotropic Gaussian mixture",
+             "zipf": "Zipf(1.1)-weighted Gaussian mixture", "aniso": "anisotropic Gaussian mixture",
+             "vmf": "unit-normalised mixture"}
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_TFLOPS = 157.3
 BF16_MFMA_TFLOPS = 2500.0
@@ -49,6 +52,28 @@ def measured_traffic(path=TRAFFIC_FILE):
     except (OSError, ValueError):
         return None
     return t.get("bytes_per_launch") if t.get("kernel_hash") == _kernel_hash() else None
+
+
+def exact_knn_device(base, Q, k, metric, chunk=1 << 18):
+    """Exact top-k ids by (distance, id) in FP64 on the device (ground truth
+    for recall on corpora too large for the host brute force)."""
+    import torch
+    dev = torch.device("cuda:0")
+    q = torch.from_numpy(np.asarray(Q, np.float64)).to(dev)
+    qn = (q * q).sum(1, keepdim=True)
+    best = torch.full((len(Q), k), float("inf"), dtype=torch.float64, device=dev)
+    bid = torch.zeros((len(Q), k), dtype=torch.int64, device=dev)
+    for s in range(0, len(base), chunk):
+        x = torch.from_numpy(np.asarray(base[s:s + chunk], np.float64)).to(dev)
+        D = -(q @ x.T) if metric == "ip" else qn + (x * x).sum(1)[None, :] - 2.0 * (q @ x.T)
+        ids = torch.arange(s, s + len(x), device=dev).expand(len(Q), -1)
+        D2, I2 = torch.cat([best, D], 1), torch.cat([bid, ids], 1)
+        # order by (distance, id): ids break ties
+        o = torch.argsort(I2, dim=1, stable=True)
+        D2, I2 = torch.gather(D2, 1, o), torch.gather(I2, 1, o)
+        o = torch.argsort(D2, dim=1, stable=True)[:, :k]
+        best, bid = torch.gather(D2, 1, o), torch.gather(I2, 1, o)
+    return bid.cpu().numpy()
 
 
 def log(*a):
@@ -332,6 +357,9 @@ def main():
                     help="only run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: autotune each policy's search schedule for the batch before timing it")
+    ap.add_argument("--gpu-build", action="store_true",
+                    help="build the index on the device (amp_index_build) instead of the cached numpy build")
+    ap.add_argument("--allowed", default="4,8,12,16", help="widths the adaptive policy may choose")
     ap.add_argument("--schedule", default="",
                     help="chunk,chunk1,narrow,lut_dtype: use this search schedule instead of autotuning")
     ap.add_argument("--sweep", action="store_true",
@@ -377,7 +405,21 @@ def main():
     from amp_data.synth import make_queries
     from amp_data.workloads import load_or_build
 
-    w, base, idx = load_or_build(args.workload, args.cache_dir, log=lambda m: log("[bench] " + m))
+    if args.gpu_build:
+        # large workloads: index built on the device by the library's builder
+        from amp_data.synth import WORKLOADS, make_base
+        w = WORKLOADS[args.workload]
+        t = time.perf_counter()
+        base = make_base(w)
+        log(f"[bench] generated base {base.shape} in {time.perf_counter() - t:.1f}s")
+        t = time.perf_counter()
+        hb = amp.amp_index_build(base, w.nlist, w.M, iters=20, seed=w.seed, integer_data=w.integer_data,
+                                 grid_kind=w.grid_kind, metric=w.metric)
+        idx = amp.amp_index_get_arrays(hb)
+        del hb
+        log(f"[bench] built IVF{w.nlist}/PQ{w.M} on the device in {time.perf_counter() - t:.1f}s")
+    else:
+        w, base, idx = load_or_build(args.workload, args.cache_dir, log=lambda m: log("[bench] " + m))
     if args.nq:
         w = w.scaled(nq=args.nq)
     if args.replicate > 1:
@@ -422,13 +464,17 @@ def main():
     import oracle
     nr = min(args.recall_queries, nq)
     t = time.perf_counter()
-    truth = oracle.exact_knn(base, Q[:nr], k) if nr else None
+    if nr and base.shape[0] * base.shape[1] > 2e8:
+        truth = exact_knn_device(base, Q[:nr], k, w.metric)  # FP64 on the device
+    else:
+        truth = oracle.exact_knn(base, Q[:nr], k, w.metric) if nr else None
     log(f"[bench] exact kNN of {nr} queries in {time.perf_counter() - t:.1f}s")
 
+    allowed = tuple(int(b) for b in args.allowed.split(","))
     # precision predictor fitted on a disjoint training query stream
     t = time.perf_counter()
     TQ = make_queries(w, args.train_queries, train=True)
-    rep = amp.amp_index_train_predictor(h, TQ, k, nprobe, gamma=args.gamma, epsilon=args.epsilon,
+    rep = amp.amp_index_train_predictor(h, TQ, k, nprobe, gamma=args.gamma, epsilon=args.epsilon, allowed=allowed,
                                         C_=args.svr_c, n_samples=1280)
     model = amp.amp_index_get_predictor(h)
     log(f"[bench] trained predictor in {time.perf_counter() - t:.1f}s: {rep}")
@@ -438,7 +484,7 @@ def main():
         if p == "fp32":
             pols.append(("fp32", dict(policy="fp32")))
         elif p == "adaptive":
-            pols.append(("adaptive", dict(policy="adaptive")))
+            pols.append(("adaptive", dict(policy="adaptive", allowed=allowed)))
         elif p.startswith("fixed"):
             pols.append((p, dict(policy="fixed", bits=int(p[5:]))))
     results = {}
@@ -471,11 +517,12 @@ def main():
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / args.steps
         # stage breakdown and per-batch latency: separate, synchronised searches
-        stages, lat = [], []
+        stages, lat, works = [], [], []
         for i in range(args.steps):
-            o = amp.amp_search(h, batch(i), k, nprobe, out=out, stream=stream, stage_ms=True, **kw)
+            o = amp.amp_search(h, batch(i), k, nprobe, out=out, stream=stream, stage_ms=True, work=True, **kw)
             stages.append(o["stage_ms"])
             lat.append(o["stage_ms"]["total"])
+            works.append(o["work"])
         if nr:
             g = amp.amp_search(h, Q[:nr], k, nprobe, want_probes=True, want_bits=True, **kw)
             rec1 = oracle.recall_1_at(g["ids"], truth)
@@ -489,11 +536,21 @@ def main():
         hist = {int(b): round(float((bits == b).mean()), 4) for b in np.unique(bits)}
         scale = nq / len(pr)
         code_bytes = float(sizes[pr[pr >= 0]].sum()) * w.M * scale
+        # the phase-2 scan's own counters: code bytes of the (query, list)
+        # pairs it scanned, live and skipped pairs (a pair whose LUT base
+        # exceeds its query's bound is skipped whole after LUT pass 1)
+        wk = {kk: float(np.mean([x[kk] for x in works])) for kk in works[0]}
+        n_pairs_all = wk["live_pairs"] + wk["dead_pairs"]
+        # algorithmic work per launch = per-pair figure x pairs processed:
+        # every probed pair's LUT (256 M entries) and its list's lookup-adds
+        # (n M), whether the bound test let it skip the scan or not
         scan_ops = (float(sizes[pr[pr >= 0]].sum()) + 256.0 * (pr >= 0).sum()) * w.M * scale
+        exec_ops = wk["scan_bytes"] + 256.0 * w.M * n_pairs_all
         st = {s: float(np.mean([x[s] for x in stages])) for s in stages[0]}
         results[name] = dict(qps=nq / (ms / 1e3), ms=ms, recall1=rec1, recall10=rec10, stages=st,
-                             code_bytes=code_bytes, scan_ops=scan_ops, bits=hist, p50=float(np.percentile(lat, 50)),
-                             p99=float(np.percentile(lat, 99)))
+                             code_bytes=code_bytes, scan_ops=scan_ops, exec_ops=exec_ops, scan_bytes=wk["scan_bytes"],
+                             live_pairs=wk["live_pairs"], dead_pairs=wk["dead_pairs"], bits=hist,
+                             p50=float(np.percentile(lat, 50)), p99=float(np.percentile(lat, 99)))
         log(f"[bench] {name:8s} {ms:8.3f} ms/step  {nq / ms * 1e3:12.0f} QPS  1-recall@10 {rec1:.4f}  "
             f"10-recall@10 {rec10:.4f}  bits {hist}  " + " ".join(f"{s}={v:.3f}" for s, v in st.items()))
 
@@ -501,25 +558,37 @@ def main():
     r = results[head]
     scan_ms = r["stages"]["scan2"]
     # algorithmic work of the phase-2 scan: per (query, probed list) pair one
-    # LUT entry per (subspace, codeword) and one lookup-add per (vector, subspace)
+    # LUT entry per (subspace, codeword) and one lookup-add per (vector,
+    # subspace); "executed" counts only what ran (pairs skipped whole after
+    # the LUT's first pass scan nothing)
     achieved = r["scan_ops"] / (scan_ms / 1e3) / 1e12
+    executed = r["exec_ops"] / (scan_ms / 1e3) / 1e12
     streaming = args.replicate > 1
     mix = head in ("adaptive",)
-    kname = ("k_scan_mix<M,2,1>: phase-2 scan, every lane class in one launch" if mix else
-             "k_scan<LW,M,2,1>: phase-2 scan of the policy's lane class")
+    kname = ("k_scan_mix<M,2,1,NR>: phase-2 scan, every lane class in one launch" if mix else
+             "k_scan<LW,M,2,1,NR>: phase-2 scan of the policy's lane class")
     traffic = measured_traffic(STREAM_TRAFFIC_FILE if streaming else TRAFFIC_FILE)
+    work = {"live_pairs": round(r["live_pairs"]), "skipped_pairs": round(r["dead_pairs"]),
+            "scanned_code_bytes": round(r["scan_bytes"]), "probed_code_bytes": round(r["code_bytes"])}
     if streaming:
-        # no cross-query reuse of codes: the scan is bounded by HBM bandwidth;
-        # algorithmic bytes = each probed list's codes once per pair
+        # no cross-query reuse of codes: a scan of every probed pair's codes
+        # would be bounded by HBM bandwidth; algorithmic bytes = each probed
+        # list's codes once per pair; "executed" = the bytes of the pairs the
+        # scan read (the rest were skipped by the bound test)
         gbs = r["code_bytes"] / (scan_ms / 1e3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
-                    "kernel_ms": round(scan_ms, 4), "algorithmic_code_bytes_per_launch": round(r["code_bytes"])}
+                    "kernel_ms": round(scan_ms, 4), "algorithmic_bytes_per_launch": round(r["code_bytes"]),
+                    "executed": {"bytes_per_launch": round(r["scan_bytes"]),
+                                 "GB/s": round(r["scan_bytes"] / (scan_ms / 1e3) / 1e9, 1)},
+                    "work": work}
     else:
         roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
                     "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": traffic, "kernel": kname,
-                    "kernel_ms": round(scan_ms, 4), "algorithmic_code_bytes_per_launch": round(r["code_bytes"]),
-                    "algorithmic_ops_per_launch": round(r["scan_ops"])}
+                    "kernel_ms": round(scan_ms, 4), "algorithmic_ops_per_launch": round(r["scan_ops"]),
+                    "executed": {"ops_per_launch": round(r["exec_ops"]), "TOP/s": round(executed, 3),
+                                 "frac": round(executed / ALU_PEAK_TOPS, 4)},
+                    "work": work}
     fp = results.get("fp32")
     # the two dense contractions on MFMA: CL (FP32 MFMA) and the LUT build
     # (BF16 MFMA, fused into the scan kernels: rate over the scan stages, a
@@ -553,8 +622,9 @@ def main():
         "vs_baseline": None,
         "dtype": "int32" if head != "fp32" else "f32",
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: {w.n}x{w.d} integer-valued Gaussian mixture ({w.n_comp} components), "
-                               f"IVF{w.nlist}/PQ{w.M}x256, {nq} queries per step, nprobe {nprobe}, k {k}"
+        "config": {"workload": f"{w.name}: {w.n}x{w.d} {KIND_TEXT.get(w.kind, w.kind)} ({w.n_comp} components), "
+                               f"{w.metric}, IVF{w.nlist}/PQ{w.M}x256, {nq} queries per step, nprobe {nprobe}, k {k}"
+                               + (", index built on the device" if args.gpu_build else "")
                                + (f"; every list replicated {args.replicate}x (streaming regime)"
                                   if args.replicate > 1 else ""),
                    "policy": head,

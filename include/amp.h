@@ -159,6 +159,10 @@ typedef struct amp_precision_policy {
  * Per-query k / nprobe arrays are staged through pinned memory: the call does
  * not wait for earlier searches on the stream, and the caller may reuse the
  * arrays when it returns.
+ * work (host, [3] int64, optional): work of the full scan (phase 2): code
+ * bytes scanned summed over the live (query, list) pairs, live pairs, pairs
+ * skipped whole because their LUT base exceeds the query's bound; forces a
+ * synchronisation at the end (not with AMP_SEARCH_GRAPH).
  */
 #define AMP_N_STAGES 8
 #define AMP_SEARCH_GRAPH 1u  /* flags: capture the search as a HIP graph once
@@ -177,6 +181,7 @@ typedef struct amp_search_opts {
   float* stage_ms;
   uint32_t flags;
   int32_t q_dtype;
+  int64_t* work;
 } amp_search_opts;
 
 /* Build an index handle from arrays (copied).  Validates every constraint

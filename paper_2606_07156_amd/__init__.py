@@ -60,7 +60,7 @@ AMP_SEARCH_GRAPH = 1
 class _Opts(C.Structure):
     _fields_ = [("mem", C.c_int32), ("stream", C.c_void_p), ("out_qdist", C.c_void_p),
                 ("out_probes", C.c_void_p), ("out_bits", C.c_void_p), ("out_coarse", C.c_void_p),
-                ("stage_ms", C.c_void_p), ("flags", C.c_uint32), ("q_dtype", C.c_int32)]
+                ("stage_ms", C.c_void_p), ("flags", C.c_uint32), ("q_dtype", C.c_int32), ("work", C.c_void_p)]
 
 
 class _BuildParams(C.Structure):
@@ -366,7 +366,7 @@ def make_policy(policy="fixed", bits=16, allowed=(4, 8, 12, 16), margin_q40=0,
 def amp_search(index, queries, k, nprobe, policy="fixed", bits=16, allowed=(4, 8, 12, 16),
                margin_q40=0, explicit_bits=None, lut_dtype=0, want_qdist=True,
                want_probes=False, want_bits=False, want_coarse=False, stage_ms=False,
-               out=None, stream=None, graph=False, q_dtype=None):
+               out=None, stream=None, graph=False, q_dtype=None, work=False):
     """Search a batch.
 
     Host mode (``queries`` a numpy array): returns a dict of numpy arrays.
@@ -389,16 +389,19 @@ def amp_search(index, queries, k, nprobe, policy="fixed", bits=16, allowed=(4, 8
     kmax, npmax = int(kk.max()), int(npb.max())
     pol, xb = make_policy(policy, bits, allowed, margin_q40, explicit_bits, lut_dtype)
     ms = np.zeros(AMP_N_STAGES, dtype=np.float32) if stage_ms else None
+    wk = np.zeros(3, dtype=np.int64) if work else None
     if device:
         o = out
         sh = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
         opts = _Opts(AMP_MEM_DEVICE, C.c_void_p(sh) if sh else None, _ptr(o.get("qdist")),
                      _ptr(o.get("probes")), _ptr(o.get("bits")), _ptr(o.get("coarse")), _ptr(ms),
-                     AMP_SEARCH_GRAPH if graph else 0, qd)
+                     AMP_SEARCH_GRAPH if graph else 0, qd, _ptr(wk))
         _check(lib().amp_search(index.handle, _ptr(queries), nq, _ptr(kk), _ptr(npb), per_query,
                                 C.byref(pol), C.byref(opts), _ptr(o["ids"]), _ptr(o["dist"])))
         if stage_ms:
             o["stage_ms"] = dict(zip(STAGES, ms.tolist()))
+        if work:
+            o["work"] = dict(zip(("scan_bytes", "live_pairs", "dead_pairs"), wk.tolist()))
         return o
     q = np.ascontiguousarray(queries, dtype=np.uint16 if qd == AMP_BF16 else np.float32)
     res = dict(ids=np.empty((nq, kmax), np.int64), dist=np.empty((nq, kmax), np.float32))
@@ -413,11 +416,13 @@ def amp_search(index, queries, k, nprobe, policy="fixed", bits=16, allowed=(4, 8
         res["coarse"] = np.empty((nq, info["nlist"]), np.float32)
     opts = _Opts(AMP_MEM_HOST, None, _ptr(res.get("qdist")), _ptr(res.get("probes")),
                  _ptr(res.get("bits")), _ptr(res.get("coarse")), _ptr(ms),
-                 AMP_SEARCH_GRAPH if graph else 0, qd)
+                 AMP_SEARCH_GRAPH if graph else 0, qd, _ptr(wk))
     _check(lib().amp_search(index.handle, _ptr(q), nq, _ptr(kk), _ptr(npb), per_query,
                             C.byref(pol), C.byref(opts), _ptr(res["ids"]), _ptr(res["dist"])))
     if stage_ms:
         res["stage_ms"] = dict(zip(STAGES, ms.tolist()))
+    if work:
+        res["work"] = dict(zip(("scan_bytes", "live_pairs", "dead_pairs"), wk.tolist()))
     return res
 
 

@@ -93,6 +93,7 @@ struct Workspace {
   int32_t* sorted = nullptr;   // [2][nq*npmax]
   uint32_t* counters = nullptr;// [2][kNCls+1] unit counters
   int32_t* flags = nullptr;    // [4]: error bits, phase-2 re-run requested (two rounds), -
+  uint64_t* work = nullptr;    // [4]: phase-2 code bytes scanned, live pairs, dead pairs, -
   // outputs staged for host mode
   int64_t* o_ids = nullptr;
   float* o_dist = nullptr;
@@ -181,6 +182,7 @@ struct SearchDims {
   size_t capq;
   const uint16_t* q_bf16;  // BF16 query rows to widen into q_conv first (null: FP32 queries)
   float* q_conv;
+  bool want_work;        // count the phase-2 work (code bytes scanned, live / skipped pairs)
   int policy;            // AMP_POLICY_*
   int lut_dtype;         // AMP_LUT_* (0 = BF16)
   int fixed_bits;

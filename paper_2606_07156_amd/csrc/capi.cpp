@@ -450,6 +450,7 @@ static amp_status ensure_workspace(amp_index* ix, size_t nq, size_t np, size_t k
       (s = dalloc(&w.units, 2 * (size_t)units, t)) || (s = dalloc(&w.pairoff, 2 * (NB + 1), t)) ||
       (s = dalloc(&w.unitoff, 2 * (NB + 1), t)) || (s = dalloc(&w.sorted, 2 * npairs, t)) ||
       (s = dalloc(&w.counters, 2 * (size_t)(kNCls + 1), t)) || (s = dalloc(&w.flags, 4, t)) ||
+      (s = dalloc(&w.work, 4, t)) ||
       (s = dalloc(&w.o_ids, nq * kmax, t)) || (s = dalloc(&w.o_dist, nq * kmax, t)) ||
       (s = dalloc(&w.o_qdist, nq * kmax, t))) {
     free_workspace(w);
@@ -645,6 +646,7 @@ amp_status amp_search(amp_index* ix, const void* queries, int64_t nq, const int3
   sd.chunk1 = chunk1;
   sd.q_bf16 = qbf;
   sd.q_conv = w.queries;
+  sd.want_work = opts->work != nullptr;
   sd.max_units = w.cap_units;
   sd.capq = capq;
   sd.policy = pol->kind;
@@ -665,9 +667,9 @@ amp_status amp_search(amp_index* ix, const void* queries, int64_t nq, const int3
     for (int i = 0; i < 3; ++i) ma.theta[i] = ix->theta[i];
   }
   const bool use_graph = (opts->flags & AMP_SEARCH_GRAPH) != 0;
-  if (use_graph && (host || per_query || opts->stage_ms || pol->kind == AMP_POLICY_EXPLICIT))
+  if (use_graph && (host || per_query || opts->stage_ms || opts->work || pol->kind == AMP_POLICY_EXPLICIT))
     return set_error(AMP_EINVAL, "graph replay needs device memory, constant k and nprobe, no stage timing "
-                                 "and a non-explicit policy");
+                                 "or work counters, and a non-explicit policy");
   if (use_graph && st == nullptr)
     return set_error(AMP_EINVAL, "graph replay needs a created stream (the null stream cannot be captured)");
   hipEvent_t ev[AMP_N_STAGES + 1];
@@ -748,6 +750,12 @@ amp_status amp_search(amp_index* ix, const void* queries, int64_t nq, const int3
     }
     opts->stage_ms[7] = total;
     for (auto& e : ev) hipEventDestroy(e);
+  }
+  if (opts->work) {
+    uint64_t wk[4];
+    AMP_HIP(hipStreamSynchronize(st));
+    AMP_HIP(hipMemcpy(wk, w.work, sizeof wk, hipMemcpyDeviceToHost));
+    for (int i = 0; i < 3; ++i) opts->work[i] = (int64_t)wk[i];
   }
   if (getenv("AMP_STATS")) {
     // debug: candidates forwarded to the merge per query

@@ -703,6 +703,7 @@ struct ScanArgs {
   const uint8_t* retry;     // phase 3 (re-run of phase 2): queries taking part
   const int64_t* tau_id;    // phase 3: id of the bound's (distance, id) key
   const int32_t* any_retry; // phase 3: non-zero if any query takes part
+  uint64_t* work;           // phase 2 work counters (code bytes scanned, live pairs, dead pairs) or null
   int nq, d, M, dsub, nlist, npmax, grid_e, grid_kind, metric, kconst, kmax, cls;
   int64_t chunk;
   size_t capq;
@@ -743,7 +744,7 @@ __host__ __device__ inline ScanLds scan_lds_layout(int G, int wpr, int M, int d,
   if (phase == 1 && G * kThreadsP2 * 4 > M * kKsub * wpr * 4) L.lmin = take(G * kThreadsP2 * 4);
   // unit-claim control words: kept in the dynamic LDS too, so that the LUT
   // starts at LDS address 0 and row addresses fold into instruction offsets
-  L.ctl = take(32);  // unit index, class, re-run vote, live vote, unit descriptor
+  L.ctl = take(64);  // unit index, class, re-run vote, live vote, unit descriptor, 3 work counters
   L.total = o;
   return L;
 }
@@ -1095,6 +1096,8 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
             sig = 0xFFFFFFFFu;
           } else if constexpr (FP) {
             sig = (uint32_t)tk;
+            // the pair's lower bound (sum of its row minima) already above
+            if (PHASE >= 2 && fkey(reinterpret_cast<const float*>(lds + L.pbase)[tid]) > sig) live = false;
           } else {
             const int64_t t = ikey_val(tk);
             if (t < pbase[tid]) {
@@ -1253,9 +1256,18 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
         int& s_live = *reinterpret_cast<int*>(lds + L.ctl + 12);
         if (tid == 0) s_live = 0;
         __syncthreads();
-        if (tid < np_u && pb[tid] >= 0) s_live = 1;
+        if (tid < np_u && pb[tid] >= 0) atomicAdd(&s_live, 1);
         __syncthreads();
-        if (!s_live) {
+        const int nlive = s_live;
+        if (PHASE == 2 && tid == 0 && a.work) {
+          // work counters (code bytes of the pairs scanned, live and skipped
+          // pairs): kept by the workgroup, added to the totals at its end
+          uint64_t* wc = reinterpret_cast<uint64_t*>(lds + L.ctl + 32);
+          wc[0] += (uint64_t)(nlive * (v1 - v0) * M);
+          wc[1] += (uint64_t)nlive;
+          wc[2] += (uint64_t)(np_u - nlive);
+        }
+        if (!nlive) {
           fetch_next();
           return;
         }
@@ -1274,8 +1286,58 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
       __syncthreads();
     }
     if constexpr (FP) {  // (integer LUTs: right after the shifts, before pass 2)
-      thresholds();
-      __syncthreads();
+      if constexpr (PHASE >= 2) {
+        // lower bound of each pair's FP32 sums: its row minima summed in the
+        // scan's subspace order (FP32 addition is monotone, so no vector's
+        // in-order sum is below it); sixteen threads per subspace, WPR pairs
+        // per 16-byte LUT row
+        __syncthreads();  // the LUT entries are written
+        const float* lutf = reinterpret_cast<const float*>(lds + L.lut);
+        float* rmin = reinterpret_cast<float*>(lds + L.lo);  // [G][M]
+        for (int m0 = 0; m0 < M; m0 += kThreads / 16) {
+          const int m = m0 + (tid >> 4), jb = (tid & 15) * 16;
+          float mn[WPR];
+#pragma unroll
+          for (int g = 0; g < WPR; ++g) mn[g] = __builtin_inff();
+          if (m < M)
+            for (int j = jb; j < jb + 16; ++j) {
+#pragma unroll
+              for (int g = 0; g < WPR; ++g) mn[g] = fminf(mn[g], lutf[(m * kKsub + j) * WPR + g]);
+            }
+#pragma unroll
+          for (int g = 0; g < WPR; ++g) {
+#pragma unroll
+            for (int o = 8; o > 0; o >>= 1) mn[g] = fminf(mn[g], __shfl_xor(mn[g], o, 16));
+            if (m < M && (tid & 15) == 0 && g < np_u) rmin[g * M + m] = mn[g];
+          }
+        }
+        __syncthreads();
+        if (tid < np_u) {
+          float sb = 0.f;
+          for (int m = 0; m < M; ++m) sb += rmin[tid * M + m];
+          reinterpret_cast<float*>(lds + L.pbase)[tid] = sb;
+        }
+        __syncthreads();
+        thresholds();
+        int& s_live = *reinterpret_cast<int*>(lds + L.ctl + 12);
+        if (tid == 0) s_live = 0;
+        __syncthreads();
+        if (tid < np_u && pb[tid] >= 0) atomicAdd(&s_live, 1);
+        __syncthreads();
+        const int nlive = s_live;
+        if (PHASE == 2 && tid == 0 && a.work) {
+          uint64_t* wc = reinterpret_cast<uint64_t*>(lds + L.ctl + 32);
+          wc[0] += (uint64_t)(nlive * (v1 - v0) * M);
+          wc[1] += (uint64_t)nlive;
+          wc[2] += (uint64_t)(np_u - nlive);
+        }
+        if (!nlive) {
+          fetch_next();
+          return;
+        }
+      } else {
+        __syncthreads();  // the LUT entries are written
+      }
     }
     // ---- DC scan: one vector per thread, codes of the next vector prefetched
     uint32_t sig[G];
@@ -1531,6 +1593,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_scan(ScanArgs a) {
     s_u = uu;
     if (ub + uu < ue) s_unit = a.units[ub + uu];
   }
+  if (tid == 0)
+    for (int i = 0; i < 3; ++i) reinterpret_cast<uint64_t*>(lds + L.ctl + 32)[i] = 0;
   __syncthreads();
   for (;;) {
     if (ub + s_u >= ue) break;
@@ -1547,6 +1611,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_scan(ScanArgs a) {
     }
     __syncthreads();
   }
+  if (PHASE == 2 && tid == 0 && a.work)
+    for (int i = 0; i < 3; ++i)
+      atomicAdd((unsigned long long*)&a.work[i],
+                (unsigned long long)reinterpret_cast<const uint64_t*>(lds + L.ctl + 32)[i]);
 }
 
 // all three lane classes of an integer policy in one persistent launch, in
@@ -1589,6 +1657,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_scan_mix(ScanArgs a) {
       s_cls = c;
     }
   }
+  if (tid == 0)
+    for (int i = 0; i < 3; ++i) reinterpret_cast<uint64_t*>(lds + L.ctl + 32)[i] = 0;
   __syncthreads();
   for (;;) {
     if (s_u >= total) break;
@@ -1610,6 +1680,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_scan_mix(ScanArgs a) {
     }
     __syncthreads();
   }
+  if (PHASE == 2 && tid == 0 && a.work)
+    for (int i = 0; i < 3; ++i)
+      atomicAdd((unsigned long long*)&a.work[i],
+                (unsigned long long)reinterpret_cast<const uint64_t*>(lds + L.ctl + 32)[i]);
 }
 
 // ------------------------------------------------------------------ bound
@@ -2029,6 +2103,7 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, ws.counters, 0u, (size_t)2 * (kNCls + 1));
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(ws.flags), 0u, (size_t)4);
   hipLaunchKernelGGL(k_fill_u64, dim3(64), dim3(256), 0, st, ws.tau, ~0ull, (size_t)sd.nq);
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, ws.work, 0ull, (size_t)4);
   hipLaunchKernelGGL(k_fill_u32, dim3(64), dim3(256), 0, st, ws.ccount, 0u, (size_t)sd.nq);
   // PPM
   PairArgs pa;
@@ -2125,6 +2200,7 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   sa.retry = nullptr;
   sa.tau_id = nullptr;
   sa.any_retry = nullptr;
+  sa.work = nullptr;
   hipError_t err = hipSuccess;
   // the lane classes run one after another on the caller's stream, each a
   // persistent kernel over its own unit range.  (Running them concurrently
@@ -2148,7 +2224,9 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
       sa.counter = ws.counters + (ph - 1) * (kNCls + 1) + kNCls;
       sa_lwb = -1;
     }
-    if ((err = launch_scan(sa_lwb, ph, dt, sd.wpr, sa, st)) != hipSuccess) return err;
+    ScanArgs sp = sa;
+    sp.work = (ph == 2 && sd.want_work) ? ws.work : nullptr;
+    if ((err = launch_scan(sa_lwb, ph, dt, sd.wpr, sp, st)) != hipSuccess) return err;
     if (ph == 1) {
       // phase-1 minima -> per-query bound, buffer emptied for the candidates
       hipLaunchKernelGGL(k_tau_wave, dim3((sd.nq + 3) / 4), dim3(256), 0, st, ws.ccount, ws.ckey, ws.tau, ws.kq,

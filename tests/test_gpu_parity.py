@@ -594,3 +594,17 @@ def test_candidate_overflow_is_resolved_by_rerunning_phase_two(tiny, monkeypatch
         compare_integer(g, ref)
     if policy == "fixed" and bits == 4:
         assert "phase-2 re-runs: 1" in err, err
+
+
+@pytest.mark.parametrize("policy,bits", [("fixed", 8), ("fp32", 0), ("adaptive", 0)])
+def test_work_counters_account_for_every_pair(tiny, policy, bits):
+    if policy == "adaptive":
+        amp.amp_index_set_predictor(tiny["h"], _spread_model(tiny, 8))
+    g = amp.amp_search(tiny["h"], tiny["Q"], 10, 8, policy=policy, bits=bits, want_probes=True, work=True)
+    wk = g["work"]
+    P = g["probes"]
+    sizes = np.diff(tiny["idx"]["list_offsets"])
+    assert wk["live_pairs"] + wk["dead_pairs"] == (P >= 0).sum()
+    assert 0 < wk["scan_bytes"] <= sizes[P[P >= 0]].sum() * tiny["idx"]["M"]
+    # pairs skipped whole scan nothing: the bytes are those of the live pairs' lists
+    assert wk["live_pairs"] > 0
