@@ -50,7 +50,9 @@ enum {
   AMP_EOVERFLOW = -9     /* a query's candidate buffer overflowed             */
 };
 
-enum { AMP_L2 = 0, AMP_IP = 1 };                 /* metric                      */
+enum { AMP_L2 = 0, AMP_IP = 1, AMP_L1 = 2 };    /* metric: squared L2, inner     *
+                                                  * product, L1 (sum of absolute *
+                                                  * differences)                 */
 enum { AMP_GRID_U9 = 0, AMP_GRID_E4M3 = 1 };     /* LC operand grid             */
 enum { AMP_MEM_HOST = 0, AMP_MEM_DEVICE = 1 };
 enum {                                           /* precision policy kind       */
@@ -201,7 +203,8 @@ amp_status amp_index_from_arrays(const amp_index_arrays* arrays, amp_index** out
  *                  1 <= nlist <= min(n, 8192))
  *   kmeans_iters   Lloyd iterations of every k-means (0..1000)
  *   seed           seeds the training samples and initial centroids
- *   metric         AMP_L2 or AMP_IP
+ *   metric         AMP_L2, AMP_IP or AMP_L1 (the coarse quantiser and the
+ *                  codebooks are trained under L2 for every metric)
  *   grid_kind      AMP_GRID_U9 or AMP_GRID_E4M3
  *   integer_data   non-zero: the vectors hold integers; centroids and
  *                  codewords are rounded to integers after training, every
@@ -334,8 +337,8 @@ amp_status amp_index_info(const amp_index* index, int32_t* d, int32_t* M,
  * Search nq queries ([nq][d] float, or BF16 with opts.q_dtype, row-major).  k and nprobe are host
  * arrays of nq entries when per_query != 0, else single values; kmax and
  * npmax are their maxima.  Outputs: out_ids [nq][kmax] int64 and out_dist
- * [nq][kmax] float (h^2 * integer estimate for integer policies, FP32 sum for
- * the FP32 policy).  Requires 1 <= k <= AMP_MAX_K, 1 <= nprobe <=
+ * [nq][kmax] float (h^2 * integer estimate for integer policies, h * it under
+ * L1, FP32 sum for the FP32 policy).  Requires 1 <= k <= AMP_MAX_K, 1 <= nprobe <=
  * min(nlist, AMP_MAX_NPROBE); AMP_POLICY_ADAPTIVE requires a predictor.
  * In device mode an FP32 query buffer must be 16-byte aligned (rows are read
  * as float4; d is a multiple of 4), a BF16 one 2-byte aligned, else

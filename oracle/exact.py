@@ -7,17 +7,18 @@ import numpy as np
 def exact_knn(base, queries, k, metric="l2"):
     """Exact top-k ids by (distance, id) over the raw vectors, FP64.
 
-    ``metric`` "l2": squared Euclidean distance; "ip": negative inner product.
+    ``metric`` "l2": squared Euclidean distance; "l1": sum of absolute
+    differences; "ip": negative inner product.
     """
     B = np.asarray(base, dtype=np.float64)
     n = len(B)
     out = np.full((len(queries), k), -1, dtype=np.int64)
     for i, q in enumerate(np.asarray(queries, dtype=np.float64)):
-        if metric == "l2":
+        if metric in ("l2", "l1"):
             D = np.empty(n)
             for s in range(0, n, 1 << 16):
                 diff = B[s:s + (1 << 16)] - q
-                D[s:s + (1 << 16)] = (diff * diff).sum(1)
+                D[s:s + (1 << 16)] = (diff * diff).sum(1) if metric == "l2" else np.abs(diff).sum(1)
         else:
             D = -(B @ q)
         kk = min(k, n)

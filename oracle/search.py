@@ -46,13 +46,16 @@ BITS_ALL = (4, 8, 12, 16)
 def coarse_distances(q, centroids, metric="l2"):
     """CL (Sec. 2.1): distance from one query to every centroid, FP64.
 
-    L2: sum_t (q_t - c_t)^2.  IP: -sum_t q_t c_t.
+    L2: sum_t (q_t - c_t)^2.  L1 (the distance module's second mode,
+    Sec. 4.1): sum_t |q_t - c_t|.  IP: -sum_t q_t c_t.
     """
     q = np.asarray(q, dtype=F64)
     C = np.asarray(centroids, dtype=F64)
     if metric == "l2":
         diff = C - q[None, :]
         return (diff * diff).sum(1)
+    if metric == "l1":
+        return np.abs(C - q[None, :]).sum(1)
     return -(C @ q)
 
 
@@ -125,6 +128,7 @@ def lut_int(ri, cbi, metric="l2"):
     """LC (Sec. 2.1) on the integer grid, exact int64.
 
     L2: T[m][j] = sum_{t in m} (ri_t - cbi[m][j][t])^2.
+    L1: T[m][j] = sum_{t in m} |ri_t - cbi[m][j][t]|.
     IP: T[m][j] = -sum_{t in m} qi_t * cbi[m][j][t].
     """
     M, ksub, dsub = cbi.shape
@@ -132,6 +136,8 @@ def lut_int(ri, cbi, metric="l2"):
     if metric == "l2":
         diff = r - cbi
         return (diff * diff).sum(2)
+    if metric == "l1":
+        return np.abs(r - cbi).sum(2)
     return -(r * cbi).sum(2)
 
 
@@ -143,6 +149,8 @@ def lut_f64(r, codebook, metric="l2"):
     if metric == "l2":
         diff = rr - CB
         return (diff * diff).sum(2)
+    if metric == "l1":
+        return np.abs(rr - CB).sum(2)
     return -(rr * CB).sum(2)
 
 
@@ -259,7 +267,9 @@ def search(index, queries, k, nprobe, policy="fixed", bits=16, allowed=BITS_ALL,
     metric = index["metric"]
     e = int(index["grid_e"])
     inv = 2.0 ** (-e)
-    h2 = 2.0 ** (2 * e)
+    # distance unit of an integer estimate: h^2 (L2, IP: products of two grid
+    # values), h (L1: sums of grid values)
+    h2 = 2.0 ** (e if metric == "l1" else 2 * e)
     kq = _per_query(k, nq)
     npq = _per_query(nprobe, nq)
     kmax, npmax = int(kq.max()), int(npq.max())
@@ -290,7 +300,7 @@ def search(index, queries, k, nprobe, policy="fixed", bits=16, allowed=BITS_ALL,
         cand_d, cand_id = [], []
         if policy == "fp32":
             for p in P.tolist():
-                if metric == "l2":
+                if metric in ("l2", "l1"):
                     T = lut_f64(residual_f32(q, C[p]), CB, metric)
                     add = 0.0
                 else:
@@ -307,8 +317,8 @@ def search(index, queries, k, nprobe, policy="fixed", bits=16, allowed=BITS_ALL,
             out_q[i, :] = -1
             out_d[i, :len(order)] = Dall[order].astype(np.float32)
             continue
-        # RC on the grid
-        if metric == "l2":
+        # RC on the grid (L2 and L1: the residual; IP: the query)
+        if metric in ("l2", "l1"):
             RI = [grid(residual_f32(q, C[p]).astype(F64) * inv, index["grid_kind"])
                   for p in P.tolist()]
         else:
@@ -329,8 +339,8 @@ def search(index, queries, k, nprobe, policy="fixed", bits=16, allowed=BITS_ALL,
             T_query = lut_int(qi, cbi, "ip")
         for j, p in enumerate(P.tolist()):
             # LC
-            if metric == "l2":
-                T = lut_int(RI[j], cbi, "l2")
+            if metric in ("l2", "l1"):
+                T = lut_int(RI[j], cbi, metric)
                 extra = 0
             else:
                 T = T_query

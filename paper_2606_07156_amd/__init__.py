@@ -18,7 +18,9 @@ LIB_PATH = os.path.join(_HERE, "libamp.so")
 
 AMP_OK, AMP_EINVAL, AMP_ENOMEM, AMP_EDEVICE, AMP_EIO, AMP_EFORMAT = 0, -1, -2, -3, -4, -5
 AMP_EBUSY, AMP_ECANCELED, AMP_EUNSUPPORTED, AMP_EOVERFLOW = -6, -7, -8, -9
-AMP_L2, AMP_IP = 0, 1
+AMP_L2, AMP_IP, AMP_L1 = 0, 1, 2
+METRICS = {"l2": AMP_L2, "ip": AMP_IP, "l1": AMP_L1}
+METRIC_NAMES = {v: k for k, v in METRICS.items()}
 AMP_GRID_U9, AMP_GRID_E4M3 = 0, 1
 AMP_MEM_HOST, AMP_MEM_DEVICE = 0, 1
 AMP_POLICY_FP32, AMP_POLICY_FIXED, AMP_POLICY_ADAPTIVE, AMP_POLICY_EXPLICIT = 0, 1, 2, 3
@@ -179,7 +181,7 @@ def amp_index_from_arrays(ix):
         radq=np.ascontiguousarray(ix["radq"], dtype=np.int32),
     )
     a = _Arrays(int(ix["d"]), int(ix["M"]), int(ix["nlist"]),
-                AMP_L2 if ix.get("metric", "l2") == "l2" else AMP_IP,
+                METRICS[ix.get("metric", "l2")],
                 AMP_GRID_U9 if ix.get("grid_kind", "u9") == "u9" else AMP_GRID_E4M3,
                 int(ix["grid_e"]), _ptr(keep["centroids"]), _ptr(keep["codebook"]),
                 _ptr(keep["offsets"]), _ptr(keep["ids"]), _ptr(keep["codes"]), _ptr(keep["radq"]))
@@ -192,7 +194,7 @@ def amp_index_build(base, nlist, M, iters=20, seed=0, integer_data=False, grid_k
                     ids=None):
     """Build an index on the current device from host vectors ``base`` [n, d]
     (float32, or bfloat16 bit patterns as a uint16 array)."""
-    if metric not in ("l2", "ip") or grid_kind not in ("u9", "e4m3"):
+    if metric not in METRICS or grid_kind not in ("u9", "e4m3"):
         raise ValueError(f"unknown metric {metric!r} or grid kind {grid_kind!r}")
     bf16 = getattr(base, "dtype", None) == np.uint16
     x = np.ascontiguousarray(base, dtype=np.uint16 if bf16 else np.float32)
@@ -201,7 +203,7 @@ def amp_index_build(base, nlist, M, iters=20, seed=0, integer_data=False, grid_k
     idv = None if ids is None else np.ascontiguousarray(ids, dtype=np.int64)
     if idv is not None and idv.shape != (x.shape[0],):
         raise ValueError("ids must have one entry per vector")
-    p = _BuildParams(int(nlist), int(M), int(iters), AMP_L2 if metric == "l2" else AMP_IP,
+    p = _BuildParams(int(nlist), int(M), int(iters), METRICS[metric],
                      AMP_GRID_U9 if grid_kind == "u9" else AMP_GRID_E4M3, int(bool(integer_data)),
                      AMP_BF16 if bf16 else AMP_F32, int(seed))
     h = C.c_void_p()
@@ -223,7 +225,7 @@ def amp_index_get_arrays(index):
         return np.ctypeslib.as_array(buf).reshape(shape).astype(dt, copy=True)
 
     offs = arr(a.list_offsets, C.c_int64, (nl + 1,), np.int64)
-    return dict(d=d, M=M, dsub=d // M, nlist=nl, metric="l2" if a.metric == AMP_L2 else "ip",
+    return dict(d=d, M=M, dsub=d // M, nlist=nl, metric=METRIC_NAMES[a.metric],
                 grid_kind="u9" if a.grid_kind == AMP_GRID_U9 else "e4m3", grid_e=a.grid_e,
                 centroids=arr(a.centroids, C.c_float, (nl, d), np.float32),
                 codebook=arr(a.codebook, C.c_float, (M, 256, d // M), np.float32),

@@ -51,6 +51,7 @@ struct DeviceIndex {
   float* codebook = nullptr;   // [M][256][dsub]
   uint4* bsw = nullptr;        // [M/2][16][64] MFMA B fragments (8 bf16 each)
   uint4* bsw16 = nullptr;      // [M/2][16][64] FP16 dims fragments
+  int16_t* cbi16 = nullptr;    // [M][256][8] grid codebook (L1 LUT build)
   int32_t* lorder = nullptr;   // [nlist] lists by decreasing size (ties: id)
   int32_t* lpos = nullptr;     // [nlist] position of each list in lorder
   uint8_t* codes = nullptr;    // [N][M]

@@ -190,7 +190,8 @@ extern "C" amp_status amp_index_build(const void* base_in, int64_t n, int32_t d,
   if (M % 4) return set_error(AMP_EUNSUPPORTED, "M (%d) must be a multiple of 4", M);
   if (nlist > AMP_MAX_NLIST) return set_error(AMP_EINVAL, "nlist %d > %d", nlist, AMP_MAX_NLIST);
   if (prm->kmeans_iters < 0 || prm->kmeans_iters > 1000) return set_error(AMP_EINVAL, "kmeans_iters out of range");
-  if (prm->metric != AMP_L2 && prm->metric != AMP_IP) return set_error(AMP_EINVAL, "bad metric %d", prm->metric);
+  if (prm->metric != AMP_L2 && prm->metric != AMP_IP && prm->metric != AMP_L1)
+    return set_error(AMP_EINVAL, "bad metric %d", prm->metric);
   if (prm->grid_kind != AMP_GRID_U9 && prm->grid_kind != AMP_GRID_E4M3)
     return set_error(AMP_EINVAL, "bad grid kind %d", prm->grid_kind);
   if (prm->base_dtype != AMP_F32 && prm->base_dtype != AMP_BF16)

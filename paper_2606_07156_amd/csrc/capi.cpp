@@ -46,7 +46,7 @@ static amp_status dalloc(T** p, size_t n, std::vector<void*>* track = nullptr) {
 
 static void free_device_index(DeviceIndex& d) {
   if (d.ev_done) hipEventDestroy(d.ev_done);
-  void* ptrs[] = {d.centroids, d.cnorm, d.codebook, d.bsw, d.bsw16, d.lorder, d.lpos, d.codes, d.ids,
+  void* ptrs[] = {d.centroids, d.cnorm, d.codebook, d.bsw, d.bsw16, d.cbi16, d.lorder, d.lpos, d.codes, d.ids,
                   d.offsets, d.radq, d.model.sv, d.model.beta, d.model.table};
   for (void* p : ptrs)
     if (p) hipFree(p);
@@ -94,7 +94,8 @@ amp_status amp_index_from_arrays(const amp_index_arrays* a, amp_index** out) {
   if (a->d / a->M > kMaxDsub) return set_error(AMP_EUNSUPPORTED, "d/M = %d > %d", a->d / a->M, kMaxDsub);
   if (a->M % 4) return set_error(AMP_EUNSUPPORTED, "M (%d) must be a multiple of 4", a->M);
   if (a->nlist > AMP_MAX_NLIST) return set_error(AMP_EINVAL, "nlist %d > %d", a->nlist, AMP_MAX_NLIST);
-  if (a->metric != AMP_L2 && a->metric != AMP_IP) return set_error(AMP_EINVAL, "bad metric %d", a->metric);
+  if (a->metric != AMP_L2 && a->metric != AMP_IP && a->metric != AMP_L1)
+    return set_error(AMP_EINVAL, "bad metric %d", a->metric);
   if (a->grid_kind != AMP_GRID_U9 && a->grid_kind != AMP_GRID_E4M3)
     return set_error(AMP_EINVAL, "bad grid kind %d", a->grid_kind);
   if (a->grid_e < -60 || a->grid_e > 60) return set_error(AMP_EINVAL, "grid exponent out of range");
@@ -207,7 +208,7 @@ static amp_status to_device_locked(amp_index* ix, int device) {
   const size_t nl = ix->nlist, dd = ix->d, M = ix->M, n = ix->n;
   if ((s = dalloc(&d.centroids, nl * dd)) || (s = dalloc(&d.cnorm, nl)) ||
       (s = dalloc(&d.codebook, M * kKsub * ix->dsub)) || (s = dalloc(&d.bsw, (M / 2) * 16 * 64)) ||
-      (s = dalloc(&d.bsw16, (M / 2) * 16 * 64)) ||
+      (s = dalloc(&d.bsw16, (M / 2) * 16 * 64)) || (s = dalloc(&d.cbi16, M * kKsub * 8)) ||
       (s = dalloc(&d.lorder, nl)) || (s = dalloc(&d.lpos, nl)) ||
       (s = dalloc(&d.codes, std::max<size_t>(1, n * M))) || (s = dalloc(&d.ids, std::max<size_t>(1, n))) ||
       (s = dalloc(&d.offsets, nl + 1)) || (s = dalloc(&d.radq, nl))) {

@@ -137,6 +137,48 @@ __global__ __launch_bounds__(256) void k_coarse(const float* __restrict__ Q, con
       }
 }
 
+// CL under L1: D = sum_t |q_t - c_t| (no dense product to put on MFMA):
+// 64 x 64 (query, centroid) tile per workgroup staged through LDS, each
+// thread 16 sums
+__global__ __launch_bounds__(256) void k_coarse_l1(const float* __restrict__ Q, const float* __restrict__ C,
+                                                   float* __restrict__ D, int nq, int nlist, int d) {
+  __shared__ float Qs[CL_T][CL_K + 1];
+  __shared__ float Cs[CL_T][CL_K + 1];
+  const int q0 = blockIdx.y * CL_T, c0 = blockIdx.x * CL_T;
+  const int tid = threadIdx.x, tq = tid >> 4, tc = tid & 15;
+  float acc[4][4];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.f;
+  for (int k0 = 0; k0 < d; k0 += CL_K) {
+    for (int i = tid; i < CL_T * CL_K; i += 256) {
+      const int r = i / CL_K, kk = i % CL_K, gk = k0 + kk;
+      Qs[r][kk] = (q0 + r < nq && gk < d) ? Q[(size_t)(q0 + r) * d + gk] : 0.f;
+      Cs[r][kk] = (c0 + r < nlist && gk < d) ? C[(size_t)(c0 + r) * d + gk] : 0.f;
+    }
+    __syncthreads();
+    for (int kk = 0; kk < CL_K; ++kk)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += fabsf(Qs[tq + 16 * i][kk] - Cs[tc + 16 * j][kk]);
+    __syncthreads();
+  }
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      const int qi = q0 + tq + 16 * i, ci = c0 + tc + 16 * j;
+      if (qi < nq && ci < nlist) D[(size_t)qi * nlist + ci] = acc[i][j];
+    }
+}
+
+// grid codebook as int16 [M][256][8] (zero-padded), for the L1 LUT build
+__global__ void k_prep_cbi(const float* __restrict__ cb, int M, int dsub, int grid_e, int grid_kind,
+                           int16_t* __restrict__ cbi) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M * kKsub * 8) return;
+  const int t = i & 7, e = i >> 3;
+  cbi[i] = t < dsub ? (int16_t)grid_val(cb[(size_t)e * dsub + t], grid_e, grid_kind) : (int16_t)0;
+}
+
 // bfloat16 bit patterns to FP32 (exact: the pattern is the top half)
 __global__ void k_bf16_widen(const uint16_t* __restrict__ in, float* __restrict__ out, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
@@ -414,7 +456,7 @@ __global__ __launch_bounds__(256) void k_pairs(PairArgs a, ModelArgs ma) {
     // d' = |grid residual|^2, four coordinates per step (d % 4 == 0)
     const float4* qv = reinterpret_cast<const float4*>(a.Q + (size_t)q * a.d);
     const float4* cv = reinterpret_cast<const float4*>(a.C + (size_t)p * a.d);
-    const bool l2 = a.metric == AMP_L2;
+    const bool l2 = a.metric != AMP_IP;  // L2 and L1: d' of the grid residual
     for (int i = t; i < (a.d >> 2); i += T) {
       const float4 x = qv[i], c = cv[i];
       int v0, v1, v2, v3;
@@ -686,6 +728,7 @@ struct ScanArgs {
   const float* codebook;   // FP32 policy
   const u32x4* bsw;        // integer policy MFMA B fragments (BF16, with aug slots)
   const u32x4* bsw16;      // FP16 dims fragments
+  const int16_t* cbi16;    // [M][256][8] grid codebook (L1 LUT build)
   const uint8_t* codes;
   const int64_t* ids;
   const int64_t* offsets;
@@ -1050,6 +1093,7 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
     // four coordinates per thread and step (d is a multiple of 4, query rows
     // and centroids 16-byte aligned); (pair, quad) advanced without division
     const bool ip = a.metric == AMP_IP;
+    const bool l1 = a.metric == AMP_L1;
     {
       const int d4 = a.d >> 2;
       const int gstep = kThreads / d4, tstep = kThreads - gstep * d4;
@@ -1139,30 +1183,42 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
         pbase[tid] = 0;
       }
       float* lut = reinterpret_cast<float*>(lds + L.lut);
-      auto entry = [&](int m, const float (&c)[kMaxDsub]) {
+      // the metric is a compile-time tag of the entry code (0 L2, 1 IP, 2 L1)
+      auto entry = [&](auto mtag, int m, const float (&c)[kMaxDsub]) {
+        constexpr int MM = decltype(mtag)::value;
         const int e = m * kKsub + own_j;
         float cc = 0.f;
+        if constexpr (MM == 0) {
 #pragma unroll
-        for (int t = 0; t < kMaxDsub; ++t) cc = fmaf(c[t], c[t], cc);
+          for (int t = 0; t < kMaxDsub; ++t) cc = fmaf(c[t], c[t], cc);
+        }
         float out[WPR];
 #pragma unroll
         for (int g = 0; g < WPR; ++g) {
           float sv = 0.f;
           if (g < np_u) {
             const float* r = r32 + g * a.d + m * a.dsub;
-            float dot = 0.f;
+            if constexpr (MM == 2) {
+              float ad = 0.f;
 #pragma unroll
-            for (int t = 0; t < kMaxDsub; ++t)
-              if (t < a.dsub) dot = fmaf(r[t], c[t], dot);
-            if (ip) {
-              // inner product: the pair's base -q.c (sum of the subspace
-              // partials) is folded into subspace 0's entries
-              float bf = 0.f;
-              if (m == 0)
-                for (int mm = 0; mm < M; ++mm) bf += rr32[g * M + mm];
-              sv = bf - dot;
+              for (int t = 0; t < kMaxDsub; ++t)
+                if (t < a.dsub) ad += fabsf(r[t] - c[t]);
+              sv = ad;
             } else {
-              sv = fmaf(-2.f, dot, rr32[g * M + m] + cc);
+              float dot = 0.f;
+#pragma unroll
+              for (int t = 0; t < kMaxDsub; ++t)
+                if (t < a.dsub) dot = fmaf(r[t], c[t], dot);
+              if constexpr (MM == 1) {
+                // inner product: the pair's base -q.c (sum of the subspace
+                // partials) is folded into subspace 0's entries
+                float bf = 0.f;
+                if (m == 0)
+                  for (int mm = 0; mm < M; ++mm) bf += rr32[g * M + mm];
+                sv = bf - dot;
+              } else {
+                sv = fmaf(-2.f, dot, rr32[g * M + m] + cc);
+              }
             }
           }
           out[g] = sv;
@@ -1171,20 +1227,25 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
 #pragma unroll
         for (int g = 0; g < WPR; ++g) dst[g] = out[g];
       };
-      if constexpr (CRES) {
-        if (owner) {
+      auto fill = [&](auto mtag) {
+        if constexpr (CRES) {
+          if (owner) {
 #pragma unroll
-          for (int i = 0; i < MT / kMPar; ++i) entry(kMPar * i + own_m0, own.c[i]);
-        }
-      } else if (owner) {
-        for (int m = own_m0; m < M; m += kMPar) {
-          float c[kMaxDsub];
+            for (int i = 0; i < MT / kMPar; ++i) entry(mtag, kMPar * i + own_m0, own.c[i]);
+          }
+        } else if (owner) {
+          for (int m = own_m0; m < M; m += kMPar) {
+            float c[kMaxDsub];
 #pragma unroll
-          for (int t = 0; t < kMaxDsub; ++t)
-            c[t] = t < a.dsub ? a.codebook[((size_t)m * kKsub + own_j) * a.dsub + t] : 0.f;
-          entry(m, c);
+            for (int t = 0; t < kMaxDsub; ++t)
+              c[t] = t < a.dsub ? a.codebook[((size_t)m * kKsub + own_j) * a.dsub + t] : 0.f;
+            entry(mtag, m, c);
+          }
         }
-      }
+      };
+      if (l1) fill(std::integral_constant<int, 2>{});
+      else if (ip) fill(std::integral_constant<int, 1>{});
+      else fill(std::integral_constant<int, 0>{});
     } else {
       int32_t* rr = reinterpret_cast<int32_t*>(lds + L.rr);
       const int16_t* ri = reinterpret_cast<const int16_t*>(lds + L.ri);
@@ -1219,7 +1280,64 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
       using P2 = std::integral_constant<int, 2>;
       using IPt = std::integral_constant<bool, true>;
       using L2t = std::integral_constant<bool, false>;
-      if (ip) build(P1{}, IPt{});
+      // L1: T[m][j] = sum_t |ri_t - cbi_t| on the VALU (not a product, no
+      // MFMA), exact integers.  Pass 1: a thread per (pair, subspace) row
+      // finds its min / max over the 256 codewords; pass 2: a thread per
+      // (subspace, codeword) entry quantises it for every pair of the unit
+      // and packs the row words as the MFMA build does.
+      auto build_l1 = [&](int pass) {
+        int32_t* lo = reinterpret_cast<int32_t*>(lds + L.lo);
+        int32_t* hi = reinterpret_cast<int32_t*>(lds + L.hi);
+        if (pass == 1) {
+          for (int e = tid; e < np_u * M; e += kThreads) {
+            const int g = e / M, m = e % M;
+            int rv[kMaxDsub];
+#pragma unroll
+            for (int t = 0; t < kMaxDsub; ++t) rv[t] = t < a.dsub ? (int)ri[g * a.d + m * a.dsub + t] : 0;
+            int mn = 0x7FFFFFFF, mx = 0;
+            const int16_t* cb = a.cbi16 + (size_t)m * kKsub * 8;
+            for (int j = 0; j < kKsub; ++j) {
+              int v = 0;
+#pragma unroll
+              for (int t = 0; t < kMaxDsub; ++t) v += abs(rv[t] - (int)cb[j * 8 + t]);
+              mn = v < mn ? v : mn;
+              mx = v > mx ? v : mx;
+            }
+            lo[e] = mn;
+            hi[e] = mx;
+          }
+        } else {
+          uint32_t* lut = reinterpret_cast<uint32_t*>(lds + L.lut);
+          for (int e = tid; e < M * kKsub; e += kThreads) {
+            const int m = e / kKsub, j = e % kKsub;
+            int cv[kMaxDsub];
+#pragma unroll
+            for (int t = 0; t < kMaxDsub; ++t) cv[t] = a.cbi16[((size_t)m * kKsub + j) * 8 + t];
+            uint32_t wds[WPR];
+#pragma unroll
+            for (int w = 0; w < WPR; ++w) wds[w] = 0;
+#pragma unroll
+            for (int w = 0; w < WPR; ++w)
+#pragma unroll
+              for (int f = 0; f < W; ++f) {
+                const int g = PairSlot<LWB, WPR>::pair(w, f);
+                if (g < np_u) {
+                  int v = 0;
+#pragma unroll
+                  for (int t = 0; t < kMaxDsub; ++t)
+                    if (t < a.dsub) v += abs((int)ri[g * a.d + m * a.dsub + t] - cv[t]);
+                  const uint32_t qv = (uint32_t)((v + lo[g * M + m]) >> ps[g]);  // lo: hf(s) - min here
+                  wds[w] |= LWB == 32 ? qv : (qv << (f * LWB));
+                }
+              }
+            uint32_t* dst = lut + (size_t)(m * kKsub + j) * WPR;
+#pragma unroll
+            for (int w = 0; w < WPR; ++w) dst[w] = wds[w];
+          }
+        }
+      };
+      if (l1) build_l1(1);
+      else if (ip) build(P1{}, IPt{});
       else build(P1{}, L2t{});
       __syncthreads();
       {
@@ -1281,7 +1399,8 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
         }
       }
       __syncthreads();
-      if (ip) build(P2{}, IPt{});
+      if (l1) build_l1(2);
+      else if (ip) build(P2{}, IPt{});
       else build(P2{}, L2t{});
       __syncthreads();
     }
@@ -1917,6 +2036,8 @@ hipError_t launch_prep_index(const amp_index* ix, hipStream_t st) {
   hipLaunchKernelGGL(k_sqnorm, dim3((ix->nlist + 3) / 4), dim3(256), 0, st, dv.centroids, ix->nlist,
                      ix->d, dv.cnorm);
   const int total = (ix->M / 2) * 16 * 64;
+  hipLaunchKernelGGL(k_prep_cbi, dim3((ix->M * kKsub * 8 + 255) / 256), dim3(256), 0, st, dv.codebook, ix->M,
+                     ix->dsub, ix->grid_e, ix->grid_kind, dv.cbi16);
   hipLaunchKernelGGL(k_prep_bsw, dim3((total + 255) / 256), dim3(256), 0, st, dv.codebook, ix->M, ix->dsub,
                      ix->grid_e, ix->grid_kind, reinterpret_cast<u32x4*>(dv.bsw),
                      reinterpret_cast<u32x4*>(dv.bsw16));
@@ -2072,10 +2193,15 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
     queries = sd.q_conv;
   }
   // CL
-  hipLaunchKernelGGL(k_sqnorm, dim3((sd.nq + 3) / 4), dim3(256), 0, st, queries, sd.nq, sd.d, ws.qnorm);
   float* coarse = out_coarse ? out_coarse : ws.coarse;
-  hipLaunchKernelGGL(k_coarse, dim3((sd.nlist + CL_T - 1) / CL_T, (sd.nq + CL_T - 1) / CL_T), dim3(256), 0, st,
-                     queries, dv.centroids, ws.qnorm, dv.cnorm, coarse, sd.nq, sd.nlist, sd.d, sd.metric);
+  if (sd.metric == AMP_L1) {
+    hipLaunchKernelGGL(k_coarse_l1, dim3((sd.nlist + CL_T - 1) / CL_T, (sd.nq + CL_T - 1) / CL_T), dim3(256), 0,
+                       st, queries, dv.centroids, coarse, sd.nq, sd.nlist, sd.d);
+  } else {
+    hipLaunchKernelGGL(k_sqnorm, dim3((sd.nq + 3) / 4), dim3(256), 0, st, queries, sd.nq, sd.d, ws.qnorm);
+    hipLaunchKernelGGL(k_coarse, dim3((sd.nlist + CL_T - 1) / CL_T, (sd.nq + CL_T - 1) / CL_T), dim3(256), 0, st,
+                       queries, dv.centroids, ws.qnorm, dv.cnorm, coarse, sd.nq, sd.nlist, sd.d, sd.metric);
+  }
   mark(1);
   int np2 = 1;
   while (np2 < sd.nlist) np2 <<= 1;
@@ -2174,6 +2300,7 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   sa.codebook = dv.codebook;
   sa.bsw = reinterpret_cast<const u32x4*>(dv.bsw);
   sa.bsw16 = reinterpret_cast<const u32x4*>(dv.bsw16);
+  sa.cbi16 = dv.cbi16;
   sa.codes = dv.codes;
   sa.ids = dv.ids;
   sa.offsets = dv.offsets;
@@ -2273,7 +2400,7 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   ma2.kconst = sd.kconst;
   ma2.kmax = sd.kmax;
   ma2.fp32 = fp32 ? 1 : 0;
-  ma2.h2 = ldexpf(1.f, 2 * sd.grid_e);
+  ma2.h2 = ldexpf(1.f, sd.metric == AMP_L1 ? sd.grid_e : 2 * sd.grid_e);  // L1 estimates are in units of h
   ma2.capq = sd.capq;
   const size_t mlds = sd.capq * 16;
   err = hipFuncSetAttribute(kaddr(k_merge), hipFuncAttributeMaxDynamicSharedMemorySize, (int)mlds);

@@ -146,7 +146,7 @@ extern "C" amp_status amp_index_train_predictor(amp_index* ix, const float* tq, 
     return set_error(AMP_EINVAL, "allowed_bits_mask must select widths among 4, 8, 12, 16");
   const int d = ix->d, M = ix->M, dsub = ix->dsub, nl = ix->nlist;
   // grid codebook (and, for inner product, grid centroids)
-  const bool ip = ix->metric == AMP_IP;
+  const bool ip = ix->metric == AMP_IP, l1 = ix->metric == AMP_L1;
   std::vector<int32_t> cbi((size_t)M * kKsub * dsub);
   for (size_t i = 0; i < cbi.size(); ++i) cbi[i] = grid_host(ix->codebook[i], ix->grid_e, ix->grid_kind);
   std::vector<int32_t> cgi;
@@ -169,6 +169,8 @@ extern "C" amp_status amp_index_train_predictor(amp_index* ix, const float* tq, 
       for (int t = 0; t < d; ++t) {
         if (ip) {
           s -= (double)q[t] * (double)ix->centroids[(size_t)c * d + t];
+        } else if (l1) {
+          s += std::fabs((double)q[t] - (double)ix->centroids[(size_t)c * d + t]);
         } else {
           const double df = (double)q[t] - (double)ix->centroids[(size_t)c * d + t];
           s += df * df;
@@ -180,7 +182,8 @@ extern "C" amp_status amp_index_train_predictor(amp_index* ix, const float* tq, 
     std::partial_sort(order.begin(), order.begin() + nprobe, order.end(),
                       [&](int a, int b) { return D[a] < D[b] || (D[a] == D[b] && a < b); });
     // the query-wide inner-product LUT -qi.cbi and its spread
-    auto build_lut = [&](const int32_t* v, bool l2) {
+    // mode 0: inner product, 1: L2, 2: L1
+    auto build_lut = [&](const int32_t* v, int mode) {
       int64_t Rp = 0;
       for (int m = 0; m < M; ++m) {
         int64_t lo = INT64_MAX, hi = INT64_MIN;
@@ -188,9 +191,11 @@ extern "C" amp_status amp_index_train_predictor(amp_index* ix, const float* tq, 
           int64_t s = 0;
           for (int t = 0; t < dsub; ++t) {
             const int64_t c = cbi[((size_t)m * kKsub + j) * dsub + t];
-            if (l2) {
+            if (mode == 1) {
               const int64_t df = v[m * dsub + t] - c;
               s += df * df;
+            } else if (mode == 2) {
+              s += std::llabs(v[m * dsub + t] - c);
             } else {
               s -= v[m * dsub + t] * c;
             }
@@ -206,7 +211,7 @@ extern "C" amp_status amp_index_train_predictor(amp_index* ix, const float* tq, 
     int64_t Rq = 0;
     if (ip) {
       for (int t = 0; t < d; ++t) qg[t] = grid_host(q[t], ix->grid_e, ix->grid_kind);
-      Rq = build_lut(qg.data(), false);
+      Rq = build_lut(qg.data(), 0);
     }
     // exact integer ADC distances of every candidate, per probed list
     std::vector<int64_t> dq2(nprobe), R(nprobe);
@@ -225,7 +230,7 @@ extern "C" amp_status amp_index_train_predictor(amp_index* ix, const float* tq, 
         s2 += (int64_t)ri[t] * ri[t];
       }
       dq2[r] = s2;
-      R[r] = ip ? Rq : build_lut(ri.data(), true);
+      R[r] = ip ? Rq : build_lut(ri.data(), l1 ? 2 : 1);
       for (int64_t v = ix->offsets[p]; v < ix->offsets[p + 1]; ++v) {
         int64_t s = extra;
         for (int m = 0; m < M; ++m) s += T[(size_t)m * kKsub + ix->codes[(size_t)v * M + m]];

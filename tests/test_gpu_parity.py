@@ -608,3 +608,40 @@ def test_work_counters_account_for_every_pair(tiny, policy, bits):
     assert 0 < wk["scan_bytes"] <= sizes[P[P >= 0]].sum() * tiny["idx"]["M"]
     # pairs skipped whole scan nothing: the bytes are those of the live pairs' lists
     assert wk["live_pairs"] > 0
+
+
+@pytest.fixture(scope="module")
+def l1ctx():
+    # the L1 mode of the distance module: same index construction, L1 search
+    return _small("iso", metric="l1", n=12_000, d=64, n_comp=48, nlist=32, M=16, seed=31, nq=40)
+
+
+def _l1_probes_ok(g, ctx, nprobe):
+    C = np.asarray(ctx["idx"]["centroids"], np.float32)
+    for i, q in enumerate(ctx["Q"]):
+        D64 = oracle.coarse_distances(q, C, "l1")
+        assert np.allclose(g["coarse"][i], D64, rtol=1e-5, atol=1e-5 * np.abs(D64).max())
+        want = oracle.select_probes(D64, nprobe)
+        for a, b in zip(g["probes"][i][:nprobe].tolist(), want.tolist()):
+            if a != b:  # only FP32 near-ties may swap
+                assert abs(D64[a] - D64[b]) <= 1e-5 * D64.max(), (i, a, b)
+
+
+@pytest.mark.parametrize("policy,bits", [("fixed", 4), ("fixed", 8), ("fixed", 16), ("fp32", 0)])
+def test_l1_search(l1ctx, policy, bits):
+    g = _gpu(l1ctx, 10, 6, policy=policy, bits=bits)
+    _l1_probes_ok(g, l1ctx, 6)
+    ref = _oracle(l1ctx, 10, 6, g, policy=policy, bits=bits)
+    if policy == "fp32":
+        compare_fp32(g, ref, l1ctx["idx"]["M"])
+    else:
+        compare_integer(g, ref)
+
+
+def test_l1_adaptive_search(l1ctx):
+    m = _spread_model(l1ctx, 6)
+    amp.amp_index_set_predictor(l1ctx["h"], m)
+    g = _gpu(l1ctx, 10, 6, policy="adaptive")
+    ref = _oracle(l1ctx, 10, 6, g, policy="adaptive", model=m)
+    assert np.array_equal(g["bits"], ref["bits"])
+    compare_integer(g, ref)

@@ -39,6 +39,17 @@ def test_coarse_l2_and_ip_match_python_loops():
             assert abs(Dip[c] - t) <= 1e-12 * max(1.0, abs(t))
 
 
+def test_coarse_l1_matches_python_loops():
+    r = np.random.default_rng(21)
+    Q = r.normal(size=(3, 6)).astype(np.float32)
+    C = r.normal(size=(5, 6)).astype(np.float32)
+    for q in Q:
+        D = oracle.coarse_distances(q, C, "l1")
+        for c in range(5):
+            s = sum(abs(float(q[j]) - float(C[c, j])) for j in range(6))
+            assert abs(D[c] - s) <= 1e-12 * max(1.0, s)
+
+
 def test_select_probes_orders_by_distance_then_list_id():
     D = np.array([5.0, 1.0, 3.0, 1.0, 3.0, 0.5, 9.0])
     want = [c for _, c in sorted((float(D[c]), c) for c in range(len(D)))]
@@ -116,6 +127,29 @@ def test_lut_int_identity_sum_equals_direct_distance():
         direct = sum((int(a) - b) ** 2 for a, b in zip(ri, rec))
         assert int(sum(T[m, code[m]] for m in range(M))) == direct
         assert int(sum(Tip[m, code[m]] for m in range(M))) == -sum(int(a) * b for a, b in zip(ri, rec))
+
+
+def test_l1_lut_sum_equals_direct_distance():
+    """L1 is separable over coordinates: sum_m T[m][code_m] = |ri - cbi(code)|_1
+    (exact integers), and the FP64 LUT of the FP32 residual sums to the L1
+    distance from the query to the reconstruction."""
+    r = np.random.default_rng(22)
+    M, dsub = 5, 4
+    cbi = r.integers(-255, 256, size=(M, 256, dsub))
+    ri = r.integers(-255, 256, size=M * dsub)
+    T = oracle.lut_int(ri, cbi, "l1")
+    CB = r.normal(size=(M, 256, dsub)).astype(np.float32)
+    c = r.normal(size=M * dsub).astype(np.float32) * 3
+    q = r.normal(size=M * dsub).astype(np.float32) * 3
+    res = oracle.residual_f32(q, c)
+    T64 = oracle.lut_f64(res, CB, "l1")
+    for _ in range(40):
+        code = r.integers(0, 256, size=M)
+        rec = [int(v) for m in range(M) for v in cbi[m, code[m]]]
+        assert int(sum(T[m, code[m]] for m in range(M))) == sum(abs(int(a) - b) for a, b in zip(ri, rec))
+        xr = np.concatenate([CB[m, code[m]] for m in range(M)]).astype(np.float64)
+        direct = float(np.abs(res.astype(np.float64) - xr).sum())
+        assert abs(float(sum(T64[m, code[m]] for m in range(M))) - direct) <= 1e-12 * direct
 
 
 def test_full_precision_adc_equals_reconstruction_distance():
@@ -324,6 +358,23 @@ def test_lossless_index_recovers_exact_knn():
     d64 = ((base[truth].astype(np.float64) - Q[:, None, :]) ** 2).sum(-1)
     assert np.array_equal(r16["qdist"], d64.astype(np.int64))
     assert oracle.recall_at(r16["ids"], truth) == 1.0
+
+
+def test_lossless_index_recovers_exact_l1_knn():
+    """Special case for the L1 mode: integer queries, base vectors exactly
+    centroid + codewords, every list probed: the exact integer search (s = 0)
+    returns the exact L1 nearest neighbours with their exact distances."""
+    idx, base = lossless_index(seed=5, nlist=6, M=4, dsub=4, per_list=[40, 3, 77, 0, 12, 60])
+    idx = dict(idx, metric="l1")
+    Q = np.random.default_rng(14).integers(-40, 41, size=(8, 16)).astype(np.float32)
+    truth = oracle.exact_knn(base, Q, 10, "l1")
+    r16 = oracle.search(idx, Q, 10, 6, policy="fixed", bits=16)
+    assert (r16["shift"] == 0).all()
+    assert np.array_equal(r16["ids"], truth)
+    d1 = np.abs(base[truth].astype(np.float64) - Q[:, None, :]).sum(-1)
+    assert np.array_equal(r16["qdist"], d1.astype(np.int64))
+    r32 = oracle.search(idx, Q, 10, 6, policy="fp32")
+    assert np.array_equal(r32["ids"], truth)
 
 
 @pytest.mark.slow

@@ -102,8 +102,9 @@ def _labels_by_definition(idx, TQ, k, nprobe, widths=(4, 8, 12, 16)):
             qi = oracle.grid(q.astype(np.float64) * inv, kind)
             Tq = oracle.lut_int(qi, cbi, "ip")
         for p in P:
-            if metric == "l2":
-                T = oracle.lut_int(oracle.grid(oracle.residual_f32(q, C[p]).astype(np.float64) * inv, kind), cbi)
+            if metric in ("l2", "l1"):
+                T = oracle.lut_int(oracle.grid(oracle.residual_f32(q, C[p]).astype(np.float64) * inv, kind), cbi,
+                                   metric)
                 extra = 0
             else:
                 T, extra = Tq, -int((qi * ci[p]).sum())
@@ -127,7 +128,7 @@ def _labels_by_definition(idx, TQ, k, nprobe, widths=(4, 8, 12, 16)):
     return hist
 
 
-@pytest.mark.parametrize("metric", ["l2", "ip"])
+@pytest.mark.parametrize("metric", ["l2", "ip", "l1"])
 def test_trainer_labels_follow_the_margin_definition(metric):
     w = WORKLOADS["tiny"].scaled(n=6000)
     base = make_base(w)
