@@ -502,15 +502,23 @@ __global__ __launch_bounds__(256) void k_pairs(PairArgs a, ModelArgs ma) {
         u[f] = (int32_t)(v < 0 ? 0 : (v > 1023 ? 1023 : v));
       }
       // integer sum: the split over threads does not change the result
-      int64_t y = 0;
-      for (int i = t; i < ma.n_sv; i += T) {
+      auto term = [&](int i) -> int64_t {
         const int32_t* sv = ma.sv + 5 * i;
         int32_t d0 = u[0] - sv[0], d1 = u[1] - sv[1], d2 = u[2] - sv[2], d3 = u[3] - sv[3], d4 = u[4] - sv[4];
         uint32_t dist2 = (uint32_t)(d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3 + d4 * d4);
         uint64_t idx = ((uint64_t)dist2 * ma.g_mul) >> 32;
         int32_t K = s_table[idx > (kTableN - 1) ? (kTableN - 1) : idx];
-        y += (int64_t)ma.beta[i] * K;
+        return (int64_t)ma.beta[i] * K;
+      };
+      // two independent chains (an integer sum: the order does not matter)
+      int64_t y = 0, y1 = 0;
+      int i = t;
+      for (; i + T < ma.n_sv; i += 2 * T) {
+        y += term(i);
+        y1 += term(i + T);
       }
+      if (i < ma.n_sv) y += term(i);
+      y += y1;
       for (int o = 1; o < T; o <<= 1) y += __shfl_xor(y, o);
       bits = (uint8_t)pick_bits(ma.beta0 + y, ma.theta, a.allowed, a.margin);
     }
@@ -1129,32 +1137,34 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
     __syncthreads();
     // ---- per-pair pruning threshold in the lane domain (phases 2, 3): a
     // pair whose base already exceeds its query's bound is dead (pb = -1)
-    auto thresholds = [&] {
-      if (PHASE >= 2 && tid < G) {
-        uint32_t sig = 0;
-        bool live = false;
-        if (tid < np_u && (PHASE != 3 || a.retry[pq[tid]])) {
-          const uint64_t tk = a.tau[pq[tid]];
-          live = true;
-          if (tk == ~0ull) {
-            sig = 0xFFFFFFFFu;
-          } else if constexpr (FP) {
-            sig = (uint32_t)tk;
-            // the pair's lower bound (sum of its row minima) already above
-            if (PHASE >= 2 && fkey(reinterpret_cast<const float*>(lds + L.pbase)[tid]) > sig) live = false;
+    auto pair_threshold = [&](int g) -> bool {
+      uint32_t sig = 0;
+      bool live = false;
+      if (g < np_u && (PHASE != 3 || a.retry[pq[g]])) {
+        const uint64_t tk = a.tau[pq[g]];
+        live = true;
+        if (tk == ~0ull) {
+          sig = 0xFFFFFFFFu;
+        } else if constexpr (FP) {
+          sig = (uint32_t)tk;
+          // the pair's lower bound (sum of its row minima) already above
+          if (PHASE >= 2 && fkey(reinterpret_cast<const float*>(lds + L.pbase)[g]) > sig) live = false;
+        } else {
+          const int64_t t = ikey_val(tk);
+          if (t < pbase[g]) {
+            live = false;
           } else {
-            const int64_t t = ikey_val(tk);
-            if (t < pbase[tid]) {
-              live = false;
-            } else {
-              const int64_t dd = (t - pbase[tid]) >> ps[tid];
-              sig = dd > (int64_t)MASK ? MASK : (uint32_t)dd;
-            }
+            const int64_t dd = (t - pbase[g]) >> ps[g];
+            sig = dd > (int64_t)MASK ? MASK : (uint32_t)dd;
           }
         }
-        psig[tid] = live ? sig : 0;
-        pb[tid] = live ? pb[tid] : -1;  // -1: no candidate can pass
       }
+      psig[g] = live ? sig : 0;
+      pb[g] = live ? pb[g] : -1;  // -1: no candidate can pass
+      return live;
+    };
+    auto thresholds = [&] {
+      if (PHASE >= 2 && tid < G) pair_threshold(tid);
     };
     // ---- LC
     if constexpr (FP) {
@@ -1339,6 +1349,7 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
       if (l1) build_l1(1);
       else if (ip) build(P1{}, IPt{});
       else build(P1{}, L2t{});
+      if (tid == 0) *reinterpret_cast<int*>(lds + L.ctl + 12) = 0;  // live-pair count of the unit
       __syncthreads();
       {
         // per pair g: shift s, base = sum of the subspace minima (inner
@@ -1358,25 +1369,25 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
         span = row16_reduce<true>(span);
 #pragma unroll
         for (int off = 1; off < 16; off <<= 1) bsum += __shfl_xor(bsum, off, 16);
-        if (r == 15 && g < np_u) {
-          const int64_t top = (1ll << pb[g]) - 1, R = span;
-          int sh = 0;
-          while (((R + (sh ? (1ll << (sh - 1)) : 0)) >> sh) > top) ++sh;
-          ps[g] = sh;
-          pbase[g] = bsum;
+        if (r == 15 && g < G) {
+          if (g < np_u) {
+            const int64_t top = (1ll << pb[g]) - 1, R = span;
+            int sh = 0;
+            while (((R + (sh ? (1ll << (sh - 1)) : 0)) >> sh) > top) ++sh;
+            ps[g] = sh;
+            pbase[g] = bsum;
+          }
+          // phases 2, 3: the bases are known before pass 2, the pair's
+          // threshold too (same lane, no barrier); live pairs are counted
+          if (PHASE >= 2 && pair_threshold(g))
+            atomicAdd(reinterpret_cast<int*>(lds + L.ctl + 12), 1);
         }
       }
       __syncthreads();
       if constexpr (PHASE >= 2) {
-        // the bases are known before pass 2: a unit whose pairs are all dead
-        // skips pass 2 and the scan (the vote goes through a control word)
-        thresholds();
-        int& s_live = *reinterpret_cast<int*>(lds + L.ctl + 12);
-        if (tid == 0) s_live = 0;
-        __syncthreads();
-        if (tid < np_u && pb[tid] >= 0) atomicAdd(&s_live, 1);
-        __syncthreads();
-        const int nlive = s_live;
+        // a unit whose pairs are all dead skips pass 2 and the scan (the
+        // count goes through a control word, zeroed before pass 1 ended)
+        const int nlive = *reinterpret_cast<int*>(lds + L.ctl + 12);
         if (PHASE == 2 && tid == 0 && a.work) {
           // work counters (code bytes of the pairs scanned, live and skipped
           // pairs): kept by the workgroup, added to the totals at its end
