@@ -319,7 +319,7 @@ def sweep(args):
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / reps
             rows.append(dict(batch=B, policy=pol, ms=round(ms, 4), qps=round(B / ms * 1e3, 1),
-                             schedule={kk: e[kk] for kk in ("chunk", "chunk1", "narrow", "lut_dtype")},
+                             schedule={kk: e[kk] for kk in ("chunk", "chunk1", "narrow", "lut_dtype", "queue")},
                              tuned_ms=round(e["ms"], 4), automatic_ms=round(e["ms_default"], 4)))
             log(f"[sweep] B={B:5d} {pol:8s} {ms:8.3f} ms/batch {B / ms * 1e3:11.0f} QPS  schedule "
                 f"{rows[-1]['schedule']} (tuned {e['ms']:.3f} ms vs automatic {e['ms_default']:.3f} ms)")
@@ -361,7 +361,7 @@ def main():
                     help="build the index on the device (amp_index_build) instead of the cached numpy build")
     ap.add_argument("--allowed", default="4,8,12,16", help="widths the adaptive policy may choose")
     ap.add_argument("--schedule", default="",
-                    help="chunk,chunk1,narrow,lut_dtype: use this search schedule instead of autotuning")
+                    help="chunk,chunk1,narrow,lut_dtype[,queue]: use this search schedule instead of autotuning")
     ap.add_argument("--sweep", action="store_true",
                     help="batch-size sweep on the skewed workload (uneven nprobe, Zipf list sizes)")
     ap.add_argument("--batches", default="1,16,256,1024,4096")
@@ -494,8 +494,10 @@ def main():
     for name, kw in pols:
         if args.schedule:
             # a fixed schedule for every policy (profiling runs: no tuning trials in the trace)
-            c, c1, nw, lt = (int(x) for x in args.schedule.split(","))
-            ent = dict(policy_kind=amp.POLICIES[kw["policy"]], chunk=c, chunk1=c1, narrow=nw, lut_dtype=lt)
+            f = [int(x) for x in args.schedule.split(",")]
+            c, c1, nw, lt = f[:4]
+            ent = dict(policy_kind=amp.POLICIES[kw["policy"]], chunk=c, chunk1=c1, narrow=nw, lut_dtype=lt,
+                       queue=f[4] if len(f) > 4 else 0)
             lg = int(np.ceil(np.log2(nq)))
             amp.amp_index_set_tuning(h, [dict(ent, nq_log2=lg)])
             tuned[name] = dict(ent, ms=0.0, ms_default=0.0)
@@ -629,7 +631,7 @@ def main():
                                   if args.replicate > 1 else ""),
                    "policy": head,
                    "launch": "HIP graph replay" if args.graph else "kernel launches",
-                   "schedule": ({kk: tuned[head][kk] for kk in ("chunk", "chunk1", "narrow", "lut_dtype", "ms",
+                   "schedule": ({kk: tuned[head][kk] for kk in ("chunk", "chunk1", "narrow", "lut_dtype", "queue", "ms",
                                                                 "ms_default")} if head in tuned else "automatic"),
                    "recall_at_10": round(r["recall1"], 4),
                    "recall_definition": "1-recall@10 (exact nearest neighbour within the 10 returned); "

@@ -285,10 +285,12 @@ amp_status amp_index_get_predictor(const amp_index* index, amp_predictor_model* 
 
 /*
  * Autotuner of the search schedule.  A search's schedule (not its result:
- * results are the same under every choice) has four knobs: the list chunk of
+ * results are the same under every choice) has five knobs: the list chunk of
  * a phase-2 work unit and of a phase-1 (bound) unit, the LUT row width (one
- * 32-bit word per row, or the widest packing of the lane class), and the LC
- * matrix dtype (BF16 or FP16) for policies that leave it open.  By default
+ * 32-bit word per row, or the widest packing of the lane class), the LC
+ * matrix dtype (BF16 or FP16) for policies that leave it open, and the work
+ * queue of the scan kernels (one counter over the cost-sorted units, or one
+ * range per XCD with stealing from the neighbouring ranges).  By default
  * they follow fixed rules of the batch shape.  amp_index_autotune times
  * candidate schedules on the current device for a representative batch
  * (queries: host [nq][d], q_dtype rows; k / nprobe as in amp_search; one
@@ -300,13 +302,18 @@ amp_status amp_index_get_predictor(const amp_index* index, amp_predictor_model* 
  *   chunk, chunk1  list chunk of a phase-2 / phase-1 unit (0 = automatic)
  *   narrow         1 one-word LUT rows, 0 widest rows, -1 automatic
  *   lut_dtype      AMP_LUT_BF16 / AMP_LUT_F16 (0 = automatic)
+ *   queue          0 one counter over the cost-sorted unit order; 1 the
+ *                  order cut into eight contiguous ranges, one per XCD (the
+ *                  units of a list stay on one XCD's L2), a workgroup taking
+ *                  from its own XCD's range, then from the next ranges in
+ *                  ring order once its own is used up (work stealing)
  *   ms, ms_default median time of the tuned and of the automatic schedule
  *   trials         schedules timed
  */
 typedef struct amp_tune_entry {
   int32_t policy_kind, nq_log2;
   int64_t chunk, chunk1;
-  int32_t narrow, lut_dtype;
+  int32_t narrow, lut_dtype, queue;
   float ms, ms_default;
   int32_t trials;
 } amp_tune_entry;
@@ -316,7 +323,8 @@ amp_status amp_index_autotune(amp_index* index, const void* queries, int64_t nq,
                               int32_t q_dtype, int32_t repeats, amp_tune_entry* out /* optional */);
 /* Read the tuning table (count always set; entries NULL: size query;
  * capacity below count: nothing copied, AMP_EINVAL) or replace it (count 0
- * clears; entries are validated: chunks 0 or >= 256, narrow -1..1). */
+ * clears; entries are validated: chunks 0 or >= 256, narrow -1..1,
+ * queue 0..1). */
 amp_status amp_index_get_tuning(const amp_index* index, amp_tune_entry* entries, int32_t capacity, int32_t* count);
 amp_status amp_index_set_tuning(amp_index* index, const amp_tune_entry* entries, int32_t count);
 

@@ -291,7 +291,8 @@ def amp_svr_fit(K, y, C_=1.0, epsilon=0.1, tol=1e-3, max_iter=100000):
 
 class _TuneEntry(C.Structure):
     _fields_ = [("policy_kind", C.c_int32), ("nq_log2", C.c_int32), ("chunk", C.c_int64), ("chunk1", C.c_int64),
-                ("narrow", C.c_int32), ("lut_dtype", C.c_int32), ("ms", C.c_float), ("ms_default", C.c_float),
+                ("narrow", C.c_int32), ("lut_dtype", C.c_int32), ("queue", C.c_int32), ("ms", C.c_float),
+                ("ms_default", C.c_float),
                 ("trials", C.c_int32)]
 
 

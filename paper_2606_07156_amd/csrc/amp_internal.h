@@ -25,6 +25,9 @@ constexpr int kMaxDsub = 8;            // one MFMA lane group holds a subspace
 constexpr int kTableN = 1024;          // predictor kernel table entries
 constexpr int kNCls = 3;               // LUT lane-width classes: 8, 16, 32 bit
 constexpr int kQSub = 16;              // queue sub-counters per (class, list) bucket
+constexpr int kXcd = 8;                // XCDs of the device (ranges of a stealing unit queue)
+constexpr int kCtrStride = 32;         // unit counters one 128-byte line apart
+constexpr int kQueueSlot = kXcd * kCtrStride;  // u32 words per scan unit queue
 
 // lane-width class of a b-bit LUT for M subspaces: the sum of M entries of at
 // most 2^b - 1 must fit in the lane
@@ -92,7 +95,7 @@ struct Workspace {
   int64_t* pairoff = nullptr;  // [2][NB+1]
   int64_t* unitoff = nullptr;  // [2][NB+1]
   int32_t* sorted = nullptr;   // [2][nq*npmax]
-  uint32_t* counters = nullptr;// [2][kNCls+1] unit counters
+  uint32_t* counters = nullptr;// [2][kNCls+1][kQueueSlot] unit counters
   int32_t* flags = nullptr;    // [4]: error bits, phase-2 re-run requested (two rounds), -
   uint64_t* work = nullptr;    // [4]: phase-2 code bytes scanned, live pairs, dead pairs, -
   // outputs staged for host mode
@@ -120,13 +123,14 @@ struct GraphKey {
   size_t capq;
   int32_t wpr;
   int32_t q_dtype;
+  int32_t queue;
   bool operator==(const GraphKey& o) const {
     return q == o.q && ids == o.ids && dist == o.dist && qdist == o.qdist && probes == o.probes &&
            bits == o.bits && coarse == o.coarse && stream == o.stream && nq == o.nq && k == o.k &&
            nprobe == o.nprobe && kind == o.kind && fixed_bits == o.fixed_bits && allowed == o.allowed &&
            margin == o.margin && lut_dtype == o.lut_dtype && ws_gen == o.ws_gen && model_gen == o.model_gen &&
            chunk == o.chunk && chunk1 == o.chunk1 && capq == o.capq && wpr == o.wpr &&
-           q_dtype == o.q_dtype;
+           q_dtype == o.q_dtype && queue == o.queue;
   }
 };
 }  // namespace amp
@@ -186,6 +190,7 @@ struct SearchDims {
   bool want_work;        // count the phase-2 work (code bytes scanned, live / skipped pairs)
   int policy;            // AMP_POLICY_*
   int lut_dtype;         // AMP_LUT_* (0 = BF16)
+  int queue;             // scan unit queue: 0 one counter, 1 per-XCD ranges with stealing
   int fixed_bits;
   uint32_t allowed_mask;
   int64_t margin;

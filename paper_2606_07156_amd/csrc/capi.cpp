@@ -450,7 +450,7 @@ static amp_status ensure_workspace(amp_index* ix, size_t nq, size_t np, size_t k
       (s = dalloc(&w.cnt, 2 * kQSub * NB, t)) || (s = dalloc(&w.rank, 2 * npairs, t)) ||
       (s = dalloc(&w.units, 2 * (size_t)units, t)) || (s = dalloc(&w.pairoff, 2 * (NB + 1), t)) ||
       (s = dalloc(&w.unitoff, 2 * (NB + 1), t)) || (s = dalloc(&w.sorted, 2 * npairs, t)) ||
-      (s = dalloc(&w.counters, 2 * (size_t)(kNCls + 1), t)) || (s = dalloc(&w.flags, 4, t)) ||
+      (s = dalloc(&w.counters, 2 * (size_t)(kNCls + 1) * kQueueSlot, t)) || (s = dalloc(&w.flags, 4, t)) ||
       (s = dalloc(&w.work, 4, t)) ||
       (s = dalloc(&w.o_ids, nq * kmax, t)) || (s = dalloc(&w.o_dist, nq * kmax, t)) ||
       (s = dalloc(&w.o_qdist, nq * kmax, t))) {
@@ -652,6 +652,11 @@ amp_status amp_search(amp_index* ix, const void* queries, int64_t nq, const int3
   sd.capq = capq;
   sd.policy = pol->kind;
   sd.lut_dtype = lut_dtype;
+  {
+    // scan unit queue (AMP_QUEUE=0/1 forces the choice)
+    const char* qv = getenv("AMP_QUEUE");
+    sd.queue = qv && *qv ? (qv[0] == '1') : (tc.queue == 1);
+  }
   sd.fixed_bits = pol->fixed_bits;
   sd.allowed_mask = pol->allowed_bits_mask ? pol->allowed_bits_mask
                                            : ((1u << 4) | (1u << 8) | (1u << 12) | (1u << 16));
@@ -703,7 +708,7 @@ amp_status amp_search(amp_index* ix, const void* queries, int64_t nq, const int3
     GraphKey key{queries, out_ids, out_dist, opts->out_qdist, opts->out_probes, opts->out_bits, opts->out_coarse,
                  st, nq, k[0], nprobe[0], pol->kind, pol->fixed_bits, sd.allowed_mask, pol->margin_q40,
                  lut_dtype, ix->ws_generation, ix->model_generation, chunk, chunk1, capq, sd.wpr,
-                 opts->q_dtype};
+                 opts->q_dtype, sd.queue};
     if (!ix->graph_exec || !(ix->graph_key == key)) {
       if (ix->graph_exec) hipGraphExecDestroy(ix->graph_exec);
       ix->graph_exec = nullptr;

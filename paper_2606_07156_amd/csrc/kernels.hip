@@ -756,8 +756,39 @@ struct ScanArgs {
   const int32_t* any_retry; // phase 3: non-zero if any query takes part
   uint64_t* work;           // phase 2 work counters (code bytes scanned, live pairs, dead pairs) or null
   int nq, d, M, dsub, nlist, npmax, grid_e, grid_kind, metric, kconst, kmax, cls;
+  int steal;                // unit queue: 0 one counter, 1 per-XCD ranges with stealing
   int64_t chunk;
   size_t capq;
+};
+
+// Unit fetch of the persistent scan kernels (called by one thread of the
+// workgroup; returns a unit number of the launch order, `total` once the
+// queue is drained).  steal = 0: one counter over the cost-sorted order.
+// steal = 1: the order is cut into kXcd contiguous ranges, range x served
+// by the workgroups of XCD x (workgroups are dispatched to the XCDs in turn,
+// so blockIdx mod kXcd is the XCD), which keeps the units of one list
+// (adjacent in the order) on one XCD's L2; a workgroup whose range is used
+// up takes units from the next ranges in ring order (work stealing).  Every
+// counter sits in its own 128-byte line; the counters only grow, so a
+// drained range stays drained and every workgroup ends after at most kXcd
+// failed attempts.
+struct UnitQueue {
+  uint32_t* ctr;
+  int64_t total;
+  int steal, home, vic;
+  __device__ UnitQueue(uint32_t* c, int64_t t, int s)
+      : ctr(c), total(t), steal(s), home((int)(blockIdx.x % kXcd)), vic(0) {}
+  __device__ int64_t next() {
+    if (!steal) return (int64_t)atomicAdd(ctr, 1u);
+    for (; vic < kXcd; ++vic) {
+      const int x = (home + vic) % kXcd;
+      const int64_t lo = total * x / kXcd, hi = total * (x + 1) / kXcd;
+      if (lo >= hi) continue;
+      const int64_t u = lo + (int64_t)atomicAdd(ctr + x * kCtrStride, 1u);
+      if (u < hi) return u;
+    }
+    return total;
+  }
 };
 
 // words per LUT row for a subspace count: the LUT of one work unit takes
@@ -1718,9 +1749,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_scan(ScanArgs a) {
         own.c[i][t] = owner && t < a.dsub
                           ? a.codebook[((size_t)(kMPar * i + own_m0) * kKsub + own_j) * a.dsub + t] : 0.f;
   }
+  UnitQueue uq(a.counter, ue - ub, a.steal);
   if (tid == 0) {
-    const int uu = (int)atomicAdd(a.counter, 1u);
-    s_u = uu;
+    const int64_t uu = uq.next();
+    s_u = (int)uu;
     if (ub + uu < ue) s_unit = a.units[ub + uu];
   }
   if (tid == 0)
@@ -1730,7 +1762,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_scan(ScanArgs a) {
     if (ub + s_u >= ue) break;
     int next_u = 0;
     int4 next_unit = make_int4(0, 0, 0, 0);
-    if (tid == 0) next_u = (int)atomicAdd(a.counter, 1u);
+    if (tid == 0) next_u = (int)uq.next();
     scan_unit<LWB, MT, PHASE, DT, NR>(a, lds, L, own, s_unit, [&] {
       if (tid == 0 && ub + next_u < ue) next_unit = a.units[ub + next_u];
     });
@@ -1778,8 +1810,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_scan_mix(ScanArgs a) {
     return uo[0] + (u - n2 - n1);
   };
   Owned<WPR, 0> own;
+  UnitQueue uq(a.counter, total, a.steal);
   if (tid == 0) {
-    const int uu = (int)atomicAdd(a.counter, 1u);
+    const int uu = (int)uq.next();
     s_u = uu;
     if (uu < total) {
       int c;
@@ -1794,7 +1827,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_scan_mix(ScanArgs a) {
     if (s_u >= total) break;
     int next_u = 0, next_cls = 0;
     int4 next_unit = make_int4(0, 0, 0, 0);
-    if (tid == 0) next_u = (int)atomicAdd(a.counter, 1u);
+    if (tid == 0) next_u = (int)uq.next();
     auto fetch = [&] {
       if (tid == 0 && next_u < total) next_unit = a.units[locate(next_u, next_cls)];
     };
@@ -2237,7 +2270,7 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   // resets
   hipLaunchKernelGGL(k_fill_u32, dim3(256), dim3(256), 0, st, reinterpret_cast<uint32_t*>(ws.cnt), 0u,
                      (size_t)2 * kQSub * NB);
-  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, ws.counters, 0u, (size_t)2 * (kNCls + 1));
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, ws.counters, 0u, (size_t)2 * (kNCls + 1) * kQueueSlot);
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(ws.flags), 0u, (size_t)4);
   hipLaunchKernelGGL(k_fill_u64, dim3(64), dim3(256), 0, st, ws.tau, ~0ull, (size_t)sd.nq);
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, ws.work, 0ull, (size_t)4);
@@ -2339,6 +2372,7 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   sa.tau_id = nullptr;
   sa.any_retry = nullptr;
   sa.work = nullptr;
+  sa.steal = sd.queue;
   hipError_t err = hipSuccess;
   // the lane classes run one after another on the caller's stream, each a
   // persistent kernel over its own unit range.  (Running them concurrently
@@ -2355,11 +2389,11 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
       // one lane class holds every pair: its own kernel
       const int c = fp32 ? 0 : lane_class(sd.M, sd.fixed_bits);
       sa.cls = c;
-      sa.counter = ws.counters + (ph - 1) * (kNCls + 1) + c;
+      sa.counter = ws.counters + ((ph - 1) * (kNCls + 1) + c) * kQueueSlot;
       sa_lwb = fp32 ? 0 : lane_bits(c);
     } else {
       sa.cls = -1;
-      sa.counter = ws.counters + (ph - 1) * (kNCls + 1) + kNCls;
+      sa.counter = ws.counters + ((ph - 1) * (kNCls + 1) + kNCls) * kQueueSlot;
       sa_lwb = -1;
     }
     ScanArgs sp = sa;
@@ -2392,7 +2426,8 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
         sr.any_retry = ws.flags + 1 + rr;  // one flag per round
         hipLaunchKernelGGL(k_retry, dim3(sd.nq < 256 ? sd.nq : 256), dim3(256), rlds, st, ws.ccount, ws.ckey,
                            ws.cid, ws.tau, ws.tau_id, ws.kq, sd.kconst, sd.nq, sd.capq, ws.retry,
-                           ws.flags + 1 + rr, ws.counters + (kNCls + 1), kNCls + 1);
+                           ws.flags + 1 + rr, ws.counters + (kNCls + 1) * kQueueSlot,
+                           (kNCls + 1) * kQueueSlot);
         // phase 3: the phase-2 scan's re-run (its own kernel symbol)
         if ((err = launch_scan(sa_lwb, 3, dt, sd.wpr, sr, st)) != hipSuccess) return err;
       }

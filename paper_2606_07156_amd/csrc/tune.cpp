@@ -66,6 +66,7 @@ amp_status check_entry(const amp_tune_entry& e) {
   if (e.narrow < -1 || e.narrow > 1) return set_error(AMP_EINVAL, "tuning entry: narrow %d", e.narrow);
   if (e.lut_dtype != 0 && e.lut_dtype != AMP_LUT_BF16 && e.lut_dtype != AMP_LUT_F16)
     return set_error(AMP_EINVAL, "tuning entry: LUT dtype %d", e.lut_dtype);
+  if (e.queue < 0 || e.queue > 1) return set_error(AMP_EINVAL, "tuning entry: queue %d", e.queue);
   return AMP_OK;
 }
 
@@ -177,6 +178,11 @@ extern "C" amp_status amp_index_autotune(amp_index* ix, const void* queries, int
         c.lut_dtype = dtp;
         try_cfg(c);
       }
+    }
+    {
+      amp_tune_entry c = best;  // work stealing between XCD ranges
+      c.queue = 1;
+      try_cfg(c);
     }
     best.ms = t_best;
     best.trials = trials;

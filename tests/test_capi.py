@@ -165,13 +165,13 @@ def test_tuning_table_roundtrip_and_validation():
     h = amp.amp_index_from_arrays(_idx())
     assert amp.amp_index_get_tuning(h) == []
     ents = [dict(policy_kind=amp.AMP_POLICY_FIXED, nq_log2=7, chunk=4096, chunk1=0, narrow=1,
-                 lut_dtype=amp.AMP_LUT_F16, ms=1.5, ms_default=2.0, trials=3),
+                 lut_dtype=amp.AMP_LUT_F16, queue=1, ms=1.5, ms_default=2.0, trials=3),
             dict(policy_kind=amp.AMP_POLICY_ADAPTIVE, nq_log2=14, chunk=0, chunk1=8192, narrow=-1,
-                 lut_dtype=0, ms=0.0, ms_default=0.0, trials=0)]
+                 lut_dtype=0, queue=0, ms=0.0, ms_default=0.0, trials=0)]
     amp.amp_index_set_tuning(h, ents)
     got = amp.amp_index_get_tuning(h)
     assert got == ents
-    for bad in [dict(ents[0], chunk=100), dict(ents[0], narrow=2), dict(ents[0], lut_dtype=3),
+    for bad in [dict(ents[0], chunk=100), dict(ents[0], narrow=2), dict(ents[0], lut_dtype=3), dict(ents[0], queue=2),
                 dict(ents[0], policy_kind=9), dict(ents[0], nq_log2=30)]:
         with pytest.raises(amp.AmpError) as e:
             amp.amp_index_set_tuning(h, [bad])

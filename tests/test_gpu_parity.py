@@ -83,6 +83,24 @@ def test_explicit_widths_are_bit_exact(tiny):
     compare_integer(g, ref)
 
 
+@pytest.mark.parametrize("policy", ["explicit", "fixed"])
+def test_stealing_unit_queue_is_bit_exact(tiny, policy):
+    # the scan kernels' work-stealing queue (one range of units per XCD)
+    # forced through the tuning table: same results as the oracle
+    r = np.random.default_rng(5)
+    nq = len(tiny["Q"])
+    xb = r.choice(np.array([4, 8, 12, 16], np.uint8), size=(nq, 8)) if policy == "explicit" else None
+    kw = dict(policy="explicit", explicit_bits=xb) if xb is not None else dict(policy="fixed", bits=8)
+    amp.amp_index_set_tuning(tiny["h"], [dict(policy_kind=amp.POLICIES[policy], nq_log2=int(np.ceil(np.log2(nq))),
+                                              chunk=256, chunk1=256, narrow=-1, lut_dtype=0, queue=1)])
+    try:
+        g = _gpu(tiny, 10, 8, **kw)
+    finally:
+        amp.amp_index_set_tuning(tiny["h"], [])
+    ref = _oracle(tiny, 10, 8, g, **kw)
+    compare_integer(g, ref)
+
+
 def _spread_model(ctx, nprobe, seed=0, n_sv=200):
     """A seeded random regressor whose feature map covers the index's feature
     ranges and whose thresholds split the scores of these queries into four
