@@ -106,8 +106,9 @@ typedef struct amp_index_arrays {
  *   y   = beta0 + sum_i beta[i] * table[min(1023, (g_mul * |u - sv_i|^2) >> 32)]
  *   bits = smallest allowed b in {4,8,12} with y + margin <= theta[b/4-1],
  *          else the largest allowed width.
- * sv [n_sv][5] int32, beta [n_sv] int32 (Q20), table [1024] int32 (Q20),
- * beta0 and theta in Q40.  n_sv <= 4096.  Host pointers, copied.
+ * sv [n_sv][5] int32 in [0, 1023] (the feature range), beta [n_sv] int32
+ * (Q20), table [1024] int32 (Q20), beta0 and theta in Q40.  n_sv <= 4096,
+ * g_mul < 2^32 (else AMP_EINVAL).  Host pointers, copied.
  */
 typedef struct amp_predictor_model {
   int32_t n_sv;

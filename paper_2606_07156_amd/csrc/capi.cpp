@@ -140,6 +140,9 @@ amp_status amp_index_set_predictor(amp_index* ix, const amp_predictor_model* m) 
   if (m->n_sv < 0 || m->n_sv > 4096) return set_error(AMP_EINVAL, "n_sv %d outside [0, 4096]", m->n_sv);
   if ((m->n_sv && (!m->sv || !m->beta)) || !m->table) return set_error(AMP_EINVAL, "null model array");
   if (m->g_mul >= (1ull << 32)) return set_error(AMP_EINVAL, "g_mul must be below 2^32");
+  for (int64_t i = 0; i < 5 * (int64_t)m->n_sv; ++i)
+    if (m->sv[i] < 0 || m->sv[i] > 1023)
+      return set_error(AMP_EINVAL, "support vector coordinate %d outside the feature range [0, 1023]", m->sv[i]);
   std::lock_guard<std::mutex> lk(ix->mu);
   ix->n_sv = m->n_sv;
   ix->sv.assign(m->sv, m->sv + 5 * (size_t)m->n_sv);

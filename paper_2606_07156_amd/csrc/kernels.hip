@@ -335,12 +335,6 @@ __global__ __launch_bounds__(256) void k_topn(const float* __restrict__ D, int n
     probes[(size_t)q * npmax + r] = r < np ? (int32_t)(keys[r] & 0xFFFFFFFFu) : -1;
 }
 
-__device__ __forceinline__ int wave_sum(int c) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
-  return c;
-}
-
 // nlist <= 64 * PER and nprobe <= 64: one wave per query, no sort of the
 // whole row.  Lane l holds keys l, l + 64, ...  The nprobe-th smallest
 // order key is found bit by bit (count of keys below a candidate, summed
@@ -361,18 +355,20 @@ __global__ __launch_bounds__(256) void k_topn_wave(const float* __restrict__ D, 
     key[j] = on && i < nlist ? fkey(D[(size_t)q * nlist + i]) : 0xFFFFFFFFu;
   }
   const int k = on ? (npq ? npq[q] : npconst) : 0;
+  // wave-wide count of keys below t: one ballot per key slot and a bit
+  // count of the mask (no cross-lane shuffles)
+  auto count_below = [&](uint32_t t) {
+    int c = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) c += __popcll(__ballot(key[j] < t));
+    return c;
+  };
   uint32_t x = 0;  // largest value with fewer than k keys below it: the k-th smallest
   for (int bit = 31; bit >= 0; --bit) {
     const uint32_t t = x | (1u << bit);
-    int c = 0;
-#pragma unroll
-    for (int j = 0; j < PER; ++j) c += key[j] < t ? 1 : 0;
-    if (wave_sum(c) < k) x = t;
+    if (count_below(t) < k) x = t;
   }
-  int lt = 0;
-#pragma unroll
-  for (int j = 0; j < PER; ++j) lt += key[j] < x ? 1 : 0;
-  int need_eq = k - wave_sum(lt);  // keys equal to x to take, lowest list id first
+  int need_eq = k - count_below(x);  // keys equal to x to take, lowest list id first
   s_sel[wv][lane] = ~0ull;
   __syncthreads();
   int base = 0;
@@ -502,22 +498,39 @@ __global__ __launch_bounds__(256) void k_pairs(PairArgs a, ModelArgs ma) {
         u[f] = (int32_t)(v < 0 ? 0 : (v > 1023 ? 1023 : v));
       }
       // integer sum: the split over threads does not change the result
+      // u and sv lie in [0, 1023] (sv checked when the model is set): the
+      // squared differences are exact 24-bit products (full-rate multiplies)
+      // and |u - sv|^2 < 2^23; g_mul < 2^32, so the table index is the high
+      // word of one 32 x 32-bit product
+      const uint32_t gm = (uint32_t)ma.g_mul;
       auto term = [&](int i) -> int64_t {
         const int32_t* sv = ma.sv + 5 * i;
-        int32_t d0 = u[0] - sv[0], d1 = u[1] - sv[1], d2 = u[2] - sv[2], d3 = u[3] - sv[3], d4 = u[4] - sv[4];
-        uint32_t dist2 = (uint32_t)(d0 * d0 + d1 * d1 + d2 * d2 + d3 * d3 + d4 * d4);
-        uint64_t idx = ((uint64_t)dist2 * ma.g_mul) >> 32;
-        int32_t K = s_table[idx > (kTableN - 1) ? (kTableN - 1) : idx];
+        const int d0 = u[0] - sv[0], d1 = u[1] - sv[1], d2 = u[2] - sv[2], d3 = u[3] - sv[3], d4 = u[4] - sv[4];
+        const uint32_t dist2 = (uint32_t)(__mul24(d0, d0) + __mul24(d1, d1) + __mul24(d2, d2) + __mul24(d3, d3) +
+                                          __mul24(d4, d4));
+        const uint32_t idx = __umulhi(dist2, gm);
+        const int32_t K = s_table[idx < (uint32_t)(kTableN - 1) ? idx : (uint32_t)(kTableN - 1)];
         return (int64_t)ma.beta[i] * K;
       };
       // two independent chains (an integer sum: the order does not matter)
       int64_t y = 0, y1 = 0;
-      int i = t;
-      for (; i + T < ma.n_sv; i += 2 * T) {
-        y += term(i);
-        y1 += term(i + T);
+      if (T == 1) {
+        // a thread per pair: the support-vector index is the same across the
+        // wave, so sv and beta are read through scalar loads
+        int i = 0;
+        for (; i + 1 < ma.n_sv; i += 2) {
+          y += term(i);
+          y1 += term(i + 1);
+        }
+        if (i < ma.n_sv) y += term(i);
+      } else {
+        int i = t;
+        for (; i + T < ma.n_sv; i += 2 * T) {
+          y += term(i);
+          y1 += term(i + T);
+        }
+        if (i < ma.n_sv) y += term(i);
       }
-      if (i < ma.n_sv) y += term(i);
       y += y1;
       for (int o = 1; o < T; o <<= 1) y += __shfl_xor(y, o);
       bits = (uint8_t)pick_bits(ma.beta0 + y, ma.theta, a.allowed, a.margin);

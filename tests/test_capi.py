@@ -179,3 +179,18 @@ def test_tuning_table_roundtrip_and_validation():
     assert amp.amp_index_get_tuning(h) == ents  # unchanged by the rejected calls
     amp.amp_index_set_tuning(h, [])
     assert amp.amp_index_get_tuning(h) == []
+
+
+def test_predictor_model_is_validated():
+    # support vectors outside the 10-bit feature range, and g_mul of 2^32 or
+    # more, are refused (the device sums take both as given)
+    from amp_data.model import random_model
+    h = amp.amp_index_from_arrays(_idx())
+    m = random_model(0, 8, [0] * 5, [1 << 16] * 5)
+    amp.amp_index_set_predictor(h, m)
+    for bad in [dict(m, sv=np.where(np.arange(40).reshape(8, 5) == 7, 1024, m["sv"]).astype(np.int32)),
+                dict(m, sv=np.where(np.arange(40).reshape(8, 5) == 3, -1, m["sv"]).astype(np.int32)),
+                dict(m, g_mul=1 << 32)]:
+        with pytest.raises(amp.AmpError) as e:
+            amp.amp_index_set_predictor(h, bad)
+        assert e.value.status == amp.AMP_EINVAL
