@@ -1656,33 +1656,41 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
     }
     if (PHASE == 1 && a.kmax <= 64) {
       // the k-th smallest of a wave's per-lane minima bounds the pair's k-th
-      // smallest (each minimum is a distinct vector); bitonic sort of the
-      // 64 minima across the lanes, then the tightest bound over the waves
+      // smallest (each minimum is a distinct vector): the wave's k smallest
+      // minima go to the query's bound buffer, and the bound is taken over
+      // all of them.  The k-th smallest minimum x is found bit by bit (the
+      // largest x with fewer than k minima below it; counts are ballot bit
+      // counts, no cross-lane shuffles); the minima below x and the
+      // lowest-lane ones equal to x make up the k.
 #pragma unroll
       for (int g = 0; g < G; ++g) {
         if (g >= np_u) break;
-        uint32_t v = lmin[g];
-        for (int kb = 2; kb <= 64; kb <<= 1)
-          for (int jb = kb >> 1; jb > 0; jb >>= 1) {
-            const uint32_t o = (uint32_t)__shfl_xor((int)v, jb);
-            const bool asc = (lane & kb) == 0, lower = (lane & jb) == 0;
-            v = (lower == asc) ? (o < v ? o : v) : (o > v ? o : v);
-          }
-        // the wave's k smallest minima go to the query's bound buffer (the
-        // candidate buffer, emptied again before phase 2); entries beyond
-        // its capacity are dropped, which only loosens the bound
+        const uint32_t v = lmin[g];
         const int q = pq[g];
         const int kk = a.kq ? a.kq[q] : a.kconst;
-        const bool e = lane < kk && v != 0xFFFFFFFFu;
+        uint32_t x = 0;
+        for (int bit = 31; bit >= 0; --bit) {
+          const uint32_t t = x | (1u << bit);
+          if (__popcll(__ballot(v < t)) < kk) x = t;
+        }
+        const uint64_t below = __ballot(v < x), eqm = __ballot(v == x);
+        const int need = kk - __popcll(below);
+        const uint64_t lower_lanes = (1ull << lane) - 1;
+        // (lanes that scanned no vector hold the largest key: never sent)
+        const bool e = (v < x || (v == x && __popcll(eqm & lower_lanes) < need)) && v != 0xFFFFFFFFu;
+        // the candidate buffer serves as the bound buffer (emptied again
+        // before phase 2); entries beyond its capacity are dropped, which
+        // only loosens the bound
         const uint64_t bal = __ballot(e);
         uint32_t base = 0;
         if (lane == 0 && bal) base = atomicAdd(&a.ccount[q], (uint32_t)__popcll(bal));
         base = (uint32_t)__shfl((int)base, 0);
-        if (e && base + lane < a.capq) {
+        const uint32_t pos = base + (uint32_t)__popcll(bal & lower_lanes);
+        if (e && pos < a.capq) {
           uint64_t key;
           if constexpr (FP) key = (uint64_t)v;
           else key = ikey(pbase[g] + ((int64_t)v << ps[g]));
-          a.ckey[(size_t)q * a.capq + base + lane] = key;
+          a.ckey[(size_t)q * a.capq + pos] = key;
         }
       }
     } else if (PHASE == 1) {
