@@ -2,7 +2,7 @@
 //
 // Stage map (paper Sec. 2.1 and Sec. 4.1):
 //   k_sqnorm / k_coarse  CL distances on FP32 MFMA (16x16x4) with norm epilogue
-//   k_topn               CL selection: nprobe smallest by (distance, list id)
+//   k_topn*              CL selection: nprobe smallest by (distance, list id)
 //   k_pairs              RC on the operand grid, PPM features and the fixed-point
 //                        RBF regressor -> LUT width per (query, probed list)
 //   k_qhist/qscan/qscatter  work queue: pairs grouped by (lane class, list)
@@ -333,6 +333,75 @@ __global__ __launch_bounds__(256) void k_topn(const float* __restrict__ D, int n
   const int np = npq ? npq[q] : npconst;
   for (int r = threadIdx.x; r < npmax; r += blockDim.x)
     probes[(size_t)q * npmax + r] = r < np ? (int32_t)(keys[r] & 0xFFFFFFFFu) : -1;
+}
+
+// nlist <= 256 * PER (larger rows or nprobe > 64): a workgroup per query
+// holds the row in registers (key j * 256 + thread).  The nprobe-th smallest
+// order key x is found bit by bit: the count of keys below a candidate is
+// the sum over the four waves of ballot bit counts, exchanged through LDS
+// (two alternating slots: one barrier per bit).  The keys up to x, with
+// their list ids, are gathered in LDS (any order), padded to a power of two
+// and sorted by (key, list id); the first nprobe are the probes, the same as
+// a sort of the whole row.
+template <int PER>
+__global__ __launch_bounds__(256) void k_topn_wg(const float* __restrict__ D, int nlist,
+                                                 const int32_t* __restrict__ npq, int npconst, int npmax,
+                                                 int32_t* __restrict__ probes) {
+  extern __shared__ uint64_t sel[];  // room for the next power of two >= nlist
+  __shared__ int s_cnt[2][4];
+  __shared__ int s_n;
+  const int q = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const float* row = D + (size_t)q * nlist;
+  uint32_t key[PER];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int i = j * 256 + tid;
+    key[j] = i < nlist ? fkey(row[i]) : 0xFFFFFFFFu;
+  }
+  const int k = npq ? npq[q] : npconst;
+  if (tid == 0) s_n = 0;
+  uint32_t x = 0;  // largest value with fewer than k keys below it: the k-th smallest
+  for (int bit = 31; bit >= 0; --bit) {
+    const uint32_t t = x | (1u << bit);
+    int c = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) c += __popcll(__ballot(key[j] < t));
+    if (lane == 0) s_cnt[bit & 1][wv] = c;
+    __syncthreads();
+    if (s_cnt[bit & 1][0] + s_cnt[bit & 1][1] + s_cnt[bit & 1][2] + s_cnt[bit & 1][3] < k) x = t;
+  }
+  // gather the keys <= x (at least k of them; ties at x all come along)
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int i = j * 256 + tid;
+    const bool take = i < nlist && key[j] <= x;
+    const uint64_t bal = __ballot(take);
+    int base = 0;
+    if (lane == 0 && bal) base = atomicAdd(&s_n, __popcll(bal));
+    base = __shfl(base, 0);
+    if (take) sel[base + __popcll(bal & ((1ull << lane) - 1))] = ((uint64_t)key[j] << 32) | (uint32_t)i;
+  }
+  __syncthreads();
+  const int n = s_n;
+  int n2 = 1;
+  while (n2 < n) n2 <<= 1;
+  for (int i = n + tid; i < n2; i += 256) sel[i] = ~0ull;
+  __syncthreads();
+  for (int size = 2; size <= n2; size <<= 1)
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = tid; i < (n2 >> 1); i += 256) {
+        const int pos = 2 * i - (i & (stride - 1));
+        const bool asc = (pos & size) == 0;
+        const uint64_t u = sel[pos], v = sel[pos + stride];
+        if ((u > v) == asc) {
+          sel[pos] = v;
+          sel[pos + stride] = u;
+        }
+      }
+      __syncthreads();
+    }
+  for (int r = tid; r < npmax; r += 256)
+    probes[(size_t)q * npmax + r] = r < k ? (int32_t)(sel[r] & 0xFFFFFFFFu) : -1;
 }
 
 // nlist <= 64 * PER and nprobe <= 64: one wave per query, no sort of the
@@ -2283,6 +2352,18 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
       hipLaunchKernelGGL(k_topn_wave<8>, g, b, 0, st, coarse, sd.nlist, sd.nq, npq, sd.npconst, sd.npmax, ws.probes);
     else
       hipLaunchKernelGGL(k_topn_wave<16>, g, b, 0, st, coarse, sd.nlist, sd.nq, npq, sd.npconst, sd.npmax, ws.probes);
+  } else if (sd.nlist <= 4096) {
+    const int32_t* npq = ws.npq ? ws.npq : nullptr;
+    const size_t lds = np2 * sizeof(uint64_t);
+    if (sd.nlist <= 1024)
+      hipLaunchKernelGGL(k_topn_wg<4>, dim3(sd.nq), dim3(256), lds, st, coarse, sd.nlist, npq, sd.npconst, sd.npmax,
+                         ws.probes);
+    else if (sd.nlist <= 2048)
+      hipLaunchKernelGGL(k_topn_wg<8>, dim3(sd.nq), dim3(256), lds, st, coarse, sd.nlist, npq, sd.npconst, sd.npmax,
+                         ws.probes);
+    else
+      hipLaunchKernelGGL(k_topn_wg<16>, dim3(sd.nq), dim3(256), lds, st, coarse, sd.nlist, npq, sd.npconst,
+                         sd.npmax, ws.probes);
   } else {
     hipLaunchKernelGGL(k_topn, dim3(sd.nq), dim3(256), np2 * sizeof(uint64_t), st, coarse, sd.nlist, np2,
                        ws.npq ? ws.npq : nullptr, sd.npconst, sd.npmax, ws.probes);

@@ -503,12 +503,13 @@ def test_device_queries_must_be_16_byte_aligned(tiny):
     assert np.array_equal(o["ids"].cpu().numpy(), ref["ids"])
 
 
-@pytest.mark.parametrize("nlist,nprobe", [(64, 5), (1000, 37), (256, 100), (1500, 8)])
+@pytest.mark.parametrize("nlist,nprobe", [(64, 5), (1000, 37), (256, 100), (1500, 8), (2048, 64), (3000, 130),
+                                          (4096, 256), (5000, 20)])
 def test_probe_ties_follow_list_ids(nlist, nprobe):
     """Duplicated centroids give bit-identical coarse distances: the probe
     order must then follow the list id, including at the nprobe boundary
-    (wave-level selection for nlist <= 1024 and nprobe <= 64, workgroup sort
-    otherwise)."""
+    (wave-level selection for nlist <= 1024 and nprobe <= 64, workgroup-level
+    selection for nlist <= 4096, a sort of the whole row beyond)."""
     r = np.random.default_rng(nlist + nprobe)
     M, dsub = 8, 4
     d = M * dsub
