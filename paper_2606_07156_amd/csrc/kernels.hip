@@ -2003,29 +2003,44 @@ __global__ __launch_bounds__(256) void k_retry(uint32_t* ccount, const uint64_t*
   extern __shared__ __attribute__((aligned(16))) char lds[];
   uint64_t* keys = reinterpret_cast<uint64_t*>(lds);
   int64_t* vals = reinterpret_cast<int64_t*>(lds + capq * 8);
+  int* s_n = reinterpret_cast<int*>(lds + capq * 16);
+  int* s_q = s_n + 1;  // [blockDim.x]
   if (blockIdx.x == 0)
     for (int i = threadIdx.x; i < ncounters; i += blockDim.x) counters[i] = 0;
-  for (int q = blockIdx.x; q < nq; q += gridDim.x) {
-    const uint32_t cnt = ccount[q];
-    if (cnt <= capq) {
-      if (threadIdx.x == 0) retry[q] = 0;
-      continue;  // uniform over the workgroup
+  // the workgroup's queries q = blockIdx.x + i * gridDim.x, a thread each:
+  // the candidate counts are read side by side (no chain of dependent
+  // loads), and only the overflowed queries go on to the sort
+  for (int64_t base = blockIdx.x; base < nq; base += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t q = base + (int64_t)threadIdx.x * gridDim.x;
+    bool over = false;
+    if (q < nq) {
+      over = ccount[q] > capq;
+      if (!over) retry[q] = 0;
     }
-    for (size_t i = threadIdx.x; i < capq; i += blockDim.x) {
-      keys[i] = ckey[(size_t)q * capq + i];
-      vals[i] = cid[(size_t)q * capq + i];
-    }
+    if (threadIdx.x == 0) *s_n = 0;
     __syncthreads();
-    block_bitonic_u64_i64(keys, vals, (int)capq);
-    const int kk = kq ? kq[q] : kconst;
-    if (threadIdx.x == 0) {
-      tau[q] = keys[kk - 1];
-      tau_id[q] = vals[kk - 1];
-      ccount[q] = 0;
-      retry[q] = 1;
-      *any_retry = 1;
+    if (over) s_q[atomicAdd(s_n, 1)] = (int)q;
+    __syncthreads();
+    const int n = *s_n;
+    for (int t = 0; t < n; ++t) {
+      const int qq = s_q[t];
+      for (size_t i = threadIdx.x; i < capq; i += blockDim.x) {
+        keys[i] = ckey[(size_t)qq * capq + i];
+        vals[i] = cid[(size_t)qq * capq + i];
+      }
+      __syncthreads();
+      block_bitonic_u64_i64(keys, vals, (int)capq);
+      const int kk = kq ? kq[qq] : kconst;
+      if (threadIdx.x == 0) {
+        tau[qq] = keys[kk - 1];
+        tau_id[qq] = vals[kk - 1];
+        ccount[qq] = 0;
+        retry[qq] = 1;
+        *any_retry = 1;
+      }
+      __syncthreads();  // the LDS is reused by the next query
     }
-    __syncthreads();  // the LDS is reused by the next query
+    __syncthreads();  // every thread has read the list before it is reset
   }
 }
 
@@ -2518,7 +2533,7 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
       // each with a tighter bound (the scan kernels return at once when no
       // query takes part); each re-run shrinks a query's candidate count by
       // about k / capq
-      const size_t rlds = sd.capq * 16;
+      const size_t rlds = sd.capq * 16 + 4 * (1 + 256);  // sort rows + overflowed-query list
       err = hipFuncSetAttribute(kaddr(k_retry), hipFuncAttributeMaxDynamicSharedMemorySize, (int)rlds);
       if (err != hipSuccess) return err;
       ScanArgs sr = sa;
