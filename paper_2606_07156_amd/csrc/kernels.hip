@@ -1974,21 +1974,40 @@ __global__ __launch_bounds__(256) void k_tau(uint32_t* ccount, const uint64_t* c
                                              const int32_t* kq, int kconst, int nq, size_t capq) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   uint64_t* keys = reinterpret_cast<uint64_t*>(lds);
-  for (int q = blockIdx.x; q < nq; q += gridDim.x) {
-    const uint32_t cnt = ccount[q];
-    const int n = (int)(cnt < capq ? cnt : capq);
-    if (n <= 64) continue;  // uniform over the workgroup
-    int np2 = 1;
-    while (np2 < n) np2 <<= 1;
-    for (int i = threadIdx.x; i < np2; i += blockDim.x) keys[i] = i < n ? ckey[(size_t)q * capq + i] : ~0ull;
-    __syncthreads();
-    block_bitonic_u64(keys, np2);
-    const int kk = kq ? kq[q] : kconst;
-    if (threadIdx.x == 0) {
-      tau[q] = n >= kk ? keys[kk - 1] : ~0ull;
-      ccount[q] = 0;
+  int* s_n = reinterpret_cast<int*>(lds + capq * 8);
+  int* s_q = s_n + 1;  // [blockDim.x]
+  // the workgroup's queries q = blockIdx.x + i * gridDim.x, a thread each:
+  // the entry counts are read side by side, and only the queries with more
+  // than 64 entries are sorted
+  for (int64_t base = blockIdx.x; base < nq; base += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t q = base + (int64_t)threadIdx.x * gridDim.x;
+    bool big = false;
+    if (q < nq) {
+      const uint32_t c = ccount[q];
+      big = (c < capq ? c : capq) > 64;  // (the others: k_tau_wave)
     }
-    __syncthreads();  // the LDS is reused by the next query
+    if (threadIdx.x == 0) *s_n = 0;
+    __syncthreads();
+    if (big) s_q[atomicAdd(s_n, 1)] = (int)q;
+    __syncthreads();
+    const int nb = *s_n;
+    for (int t = 0; t < nb; ++t) {
+      const int qq = s_q[t];
+      const uint32_t cnt = ccount[qq];
+      const int n = (int)(cnt < capq ? cnt : capq);
+      int np2 = 1;
+      while (np2 < n) np2 <<= 1;
+      for (int i = threadIdx.x; i < np2; i += blockDim.x) keys[i] = i < n ? ckey[(size_t)qq * capq + i] : ~0ull;
+      __syncthreads();
+      block_bitonic_u64(keys, np2);
+      const int kk = kq ? kq[qq] : kconst;
+      if (threadIdx.x == 0) {
+        tau[qq] = n >= kk ? keys[kk - 1] : ~0ull;
+        ccount[qq] = 0;
+      }
+      __syncthreads();  // the LDS is reused by the next query
+    }
+    __syncthreads();  // every thread has read the list before it is reset
   }
 }
 
@@ -2520,7 +2539,7 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
       // phase-1 minima -> per-query bound, buffer emptied for the candidates
       hipLaunchKernelGGL(k_tau_wave, dim3((sd.nq + 3) / 4), dim3(256), 0, st, ws.ccount, ws.ckey, ws.tau, ws.kq,
                          sd.kconst, sd.nq, sd.capq, ws.flags + 1);
-      const size_t tlds = sd.capq * 8;
+      const size_t tlds = sd.capq * 8 + 4 * (1 + 256);  // sort row + list of the queries to sort
       err = hipFuncSetAttribute(kaddr(k_tau), hipFuncAttributeMaxDynamicSharedMemorySize, (int)tlds);
       if (err != hipSuccess) return err;
       hipLaunchKernelGGL(k_tau, dim3(sd.nq < 512 ? sd.nq : 512), dim3(256), tlds, st, ws.ccount, ws.ckey, ws.tau,
