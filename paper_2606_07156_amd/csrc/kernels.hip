@@ -885,6 +885,12 @@ __host__ __device__ constexpr int kernel_wpr(int MT) { return MT ? wpr_for(MT) :
 // sparse batches, a few pairs per list), keeping its codes in registers
 __host__ __device__ constexpr int variant_wpr(int MT, int NR) { return NR ? 1 : kernel_wpr(MT); }
 
+// row stride (int16 elements) of the integer residuals in LDS: each row is
+// padded by 32 bytes, so the eight rows that the LC A-operand build reads at
+// once (d a multiple of 64 puts them all in one bank otherwise) fall in
+// distinct banks, as do the two subspaces of an m-pair
+__host__ __device__ constexpr int ri_stride(int d) { return d + 16; }
+
 // LDS carve-up of one scan workgroup (all offsets in bytes, 16-aligned)
 struct ScanLds {
   int lut, ri, rr, lo, hi, pq, pb, ps, pbase, psig, lmin, ctl, total;
@@ -894,7 +900,7 @@ __host__ __device__ inline ScanLds scan_lds_layout(int G, int wpr, int M, int d,
   int o = 0;
   auto take = [&](int bytes) { int r = o; o += (bytes + 15) & ~15; return r; };
   L.lut = take(M * kKsub * wpr * 4);
-  L.ri = take(G * d * (fp32 ? 4 : 2));
+  L.ri = take(G * (fp32 ? d * 4 : ri_stride(d) * 2));
   L.rr = take(G * M * 4);
   L.lo = take(G * M * 4);
   L.hi = take(G * M * 4);
@@ -1007,6 +1013,7 @@ __device__ __forceinline__ void lut_mpair(const ScanArgs& a, char* lds, const Sc
   const int row = lane & 15, kg = lane >> 4;
   const int ms_row = row >> 3;
   const int dsub = a.dsub;
+  const int rs = ri_stride(a.d);
   constexpr bool ip = IP;  // metric as a compile-time flag: no per-value select
   bf16x8 A[NGT];
   u32x4 Ad[NGT];
@@ -1023,13 +1030,13 @@ __device__ __forceinline__ void lut_mpair(const ScanArgs& a, char* lds, const Sc
         if constexpr (DT == DT_BF16) {
           float v[8];
 #pragma unroll
-          for (int t = 0; t < 8; ++t) v[t] = t < dsub ? (float)(coef * (int)ri[g * a.d + m * dsub + t]) * sc : 0.f;
+          for (int t = 0; t < 8; ++t) v[t] = t < dsub ? (float)(coef * (int)ri[g * rs + m * dsub + t]) * sc : 0.f;
 #pragma unroll
           for (int t = 0; t < 4; ++t) pk[t] = bf16_bits(v[2 * t]) | (bf16_bits(v[2 * t + 1]) << 16);
         } else {
           float v[8];
 #pragma unroll
-          for (int t = 0; t < 8; ++t) v[t] = t < dsub ? (float)(coef * (int)ri[g * a.d + m * dsub + t]) : 0.f;
+          for (int t = 0; t < 8; ++t) v[t] = t < dsub ? (float)(coef * (int)ri[g * rs + m * dsub + t]) : 0.f;
 #pragma unroll
           for (int t = 0; t < 4; ++t) pd[t] = f16_bits(v[2 * t]) | (f16_bits(v[2 * t + 1]) << 16);
         }
@@ -1237,7 +1244,7 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
           const uint32_t v1 = (uint32_t)grid_val(r.y, a.grid_e, a.grid_kind) & 0xFFFFu;
           const uint32_t v2 = (uint32_t)grid_val(r.z, a.grid_e, a.grid_kind) & 0xFFFFu;
           const uint32_t v3 = (uint32_t)grid_val(r.w, a.grid_e, a.grid_kind) & 0xFFFFu;
-          reinterpret_cast<u32x2*>(lds + L.ri)[g * d4 + t4] = (u32x2){v0 | (v1 << 16), v2 | (v3 << 16)};
+          reinterpret_cast<u32x2*>(lds + L.ri)[g * (ri_stride(a.d) >> 2) + t4] = (u32x2){v0 | (v1 << 16), v2 | (v3 << 16)};
         }
         g += gstep;
         t4 += tstep;
@@ -1376,7 +1383,7 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
         const int g = e / M, m = e % M;
         int32_t sacc = 0;
         for (int t = 0; t < a.dsub; ++t) {
-          const int v = ri[g * a.d + m * a.dsub + t];
+          const int v = ri[g * ri_stride(a.d) + m * a.dsub + t];
           // L2: |ri|^2 of the subspace; IP: qi.ci of the subspace (base term)
           sacc += ip ? v * grid_val(a.C[(size_t)p * a.d + m * a.dsub + t], a.grid_e, a.grid_kind) : v * v;
         }
@@ -1416,7 +1423,7 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
             const int g = e / M, m = e % M;
             int rv[kMaxDsub];
 #pragma unroll
-            for (int t = 0; t < kMaxDsub; ++t) rv[t] = t < a.dsub ? (int)ri[g * a.d + m * a.dsub + t] : 0;
+            for (int t = 0; t < kMaxDsub; ++t) rv[t] = t < a.dsub ? (int)ri[g * ri_stride(a.d) + m * a.dsub + t] : 0;
             int mn = 0x7FFFFFFF, mx = 0;
             const int16_t* cb = a.cbi16 + (size_t)m * kKsub * 8;
             for (int j = 0; j < kKsub; ++j) {
@@ -1448,7 +1455,7 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
                   int v = 0;
 #pragma unroll
                   for (int t = 0; t < kMaxDsub; ++t)
-                    if (t < a.dsub) v += abs((int)ri[g * a.d + m * a.dsub + t] - cv[t]);
+                    if (t < a.dsub) v += abs((int)ri[g * ri_stride(a.d) + m * a.dsub + t] - cv[t]);
                   const uint32_t qv = (uint32_t)((v + lo[g * M + m]) >> ps[g]);  // lo: hf(s) - min here
                   wds[w] |= LWB == 32 ? qv : (qv << (f * LWB));
                 }
