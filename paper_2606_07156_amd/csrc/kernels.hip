@@ -1027,16 +1027,30 @@ __device__ __forceinline__ void lut_mpair(const ScanArgs& a, char* lds, const Sc
       const float sc = DT == DT_BF16 ? ldexpf(1.f, -s) : 1.f;
       if ((kg & 1) == 0) {
         const int coef = ip ? -1 : -2;
+        // the subspace's grid residual: one 16-byte read when d_sub = 8
+        // (rows and subspaces 16-byte aligned), else element by element
+        int rv[8];
+        if (dsub == 8 && (a.d & 7) == 0) {
+          const u32x4 w = *reinterpret_cast<const u32x4*>(ri + g * rs + m * 8);
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            rv[2 * t] = (int)(int16_t)(w[t] & 0xFFFFu);
+            rv[2 * t + 1] = (int)(int16_t)(w[t] >> 16);
+          }
+        } else {
+#pragma unroll
+          for (int t = 0; t < 8; ++t) rv[t] = t < dsub ? (int)ri[g * rs + m * dsub + t] : 0;
+        }
         if constexpr (DT == DT_BF16) {
           float v[8];
 #pragma unroll
-          for (int t = 0; t < 8; ++t) v[t] = t < dsub ? (float)(coef * (int)ri[g * rs + m * dsub + t]) * sc : 0.f;
+          for (int t = 0; t < 8; ++t) v[t] = t < dsub ? (float)(coef * rv[t]) * sc : 0.f;
 #pragma unroll
           for (int t = 0; t < 4; ++t) pk[t] = bf16_bits(v[2 * t]) | (bf16_bits(v[2 * t + 1]) << 16);
         } else {
           float v[8];
 #pragma unroll
-          for (int t = 0; t < 8; ++t) v[t] = t < dsub ? (float)(coef * (int)ri[g * rs + m * dsub + t]) : 0.f;
+          for (int t = 0; t < 8; ++t) v[t] = t < dsub ? (float)(coef * rv[t]) : 0.f;
 #pragma unroll
           for (int t = 0; t < 4; ++t) pd[t] = f16_bits(v[2 * t]) | (f16_bits(v[2 * t + 1]) << 16);
         }
