@@ -1393,13 +1393,24 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
     } else {
       int32_t* rr = reinterpret_cast<int32_t*>(lds + L.rr);
       const int16_t* ri = reinterpret_cast<const int16_t*>(lds + L.ri);
+      const bool vec8 = a.dsub == 8 && (a.d & 7) == 0;  // 16-byte aligned subspace rows
       for (int e = tid; e < np_u * M; e += kThreads) {
         const int g = e / M, m = e % M;
         int32_t sacc = 0;
-        for (int t = 0; t < a.dsub; ++t) {
-          const int v = ri[g * ri_stride(a.d) + m * a.dsub + t];
-          // L2: |ri|^2 of the subspace; IP: qi.ci of the subspace (base term)
-          sacc += ip ? v * grid_val(a.C[(size_t)p * a.d + m * a.dsub + t], a.grid_e, a.grid_kind) : v * v;
+        if (vec8 && !ip) {
+          // |ri|^2 of the subspace from one 16-byte read
+          const u32x4 w = *reinterpret_cast<const u32x4*>(ri + g * ri_stride(a.d) + m * 8);
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int lo16 = (int)(int16_t)(w[t] & 0xFFFFu), hi16 = (int)(int16_t)(w[t] >> 16);
+            sacc += lo16 * lo16 + hi16 * hi16;
+          }
+        } else {
+          for (int t = 0; t < a.dsub; ++t) {
+            const int v = ri[g * ri_stride(a.d) + m * a.dsub + t];
+            // L2: |ri|^2 of the subspace; IP: qi.ci of the subspace (base term)
+            sacc += ip ? v * grid_val(a.C[(size_t)p * a.d + m * a.dsub + t], a.grid_e, a.grid_kind) : v * v;
+          }
         }
         rr[e] = sacc;
       }
