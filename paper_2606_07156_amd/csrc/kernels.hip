@@ -858,9 +858,9 @@ struct UnitQueue {
   uint32_t* ctr;
   int64_t total;
   int steal, home, vic;
-  __device__ UnitQueue(uint32_t* c, int64_t t, int s)
+  __device__ __forceinline__ UnitQueue(uint32_t* c, int64_t t, int s)
       : ctr(c), total(t), steal(s), home((int)(blockIdx.x % kXcd)), vic(0) {}
-  __device__ int64_t next() {
+  __device__ __forceinline__ int64_t next() {
     if (!steal) return (int64_t)atomicAdd(ctr, 1u);
     for (; vic < kXcd; ++vic) {
       const int x = (home + vic) % kXcd;
