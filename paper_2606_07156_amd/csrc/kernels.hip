@@ -67,14 +67,34 @@ __device__ __forceinline__ uint32_t bf16_bits(float v) {  // exact inputs only
   return __float_as_uint(v) >> 16;
 }
 
-// ------------------------------------------------------------------ fills
-__global__ void k_fill_u32(uint32_t* p, uint32_t v, size_t n) {
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
-}
-__global__ void k_fill_u64(uint64_t* p, uint64_t v, size_t n) {
-  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+// ------------------------------------------------------------------ resets
+// the per-search resets of the search workspace in one launch (fills by
+// kernel, not memsets: a captured search graph holds no memset node):
+// bucket counters, unit counters, flags and work counters to 0, bounds to
+// "none", candidate counts to 0
+struct ResetArgs {
+  uint32_t* cnt;
+  size_t ncnt;
+  uint32_t* counters;
+  size_t ncounters;
+  uint32_t* flags;   // [4]
+  uint64_t* work;    // [4]
+  uint64_t* tau;     // [nq]
+  uint32_t* ccount;  // [nq]
+  size_t nq;
+};
+__global__ void k_reset(ResetArgs r) {
+  const size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x, st = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = i0; i < r.ncnt; i += st) r.cnt[i] = 0;
+  for (size_t i = i0; i < r.ncounters; i += st) r.counters[i] = 0;
+  for (size_t i = i0; i < r.nq; i += st) {
+    r.tau[i] = ~0ull;
+    r.ccount[i] = 0;
+  }
+  if (i0 < 4) {
+    r.flags[i0] = 0;
+    r.work[i0] = 0;
+  }
 }
 
 // ------------------------------------------------------------------ CL
@@ -2435,14 +2455,20 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
                        ws.npq ? ws.npq : nullptr, sd.npconst, sd.npmax, ws.probes);
   }
   mark(2);
-  // resets
-  hipLaunchKernelGGL(k_fill_u32, dim3(256), dim3(256), 0, st, reinterpret_cast<uint32_t*>(ws.cnt), 0u,
-                     (size_t)2 * kQSub * NB);
-  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, ws.counters, 0u, (size_t)2 * (kNCls + 1) * kQueueSlot);
-  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(ws.flags), 0u, (size_t)4);
-  hipLaunchKernelGGL(k_fill_u64, dim3(64), dim3(256), 0, st, ws.tau, ~0ull, (size_t)sd.nq);
-  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, ws.work, 0ull, (size_t)4);
-  hipLaunchKernelGGL(k_fill_u32, dim3(64), dim3(256), 0, st, ws.ccount, 0u, (size_t)sd.nq);
+  // resets, one launch
+  {
+    ResetArgs ra;
+    ra.cnt = reinterpret_cast<uint32_t*>(ws.cnt);
+    ra.ncnt = (size_t)2 * kQSub * NB;
+    ra.counters = ws.counters;
+    ra.ncounters = (size_t)2 * (kNCls + 1) * kQueueSlot;
+    ra.flags = reinterpret_cast<uint32_t*>(ws.flags);
+    ra.work = ws.work;
+    ra.tau = ws.tau;
+    ra.ccount = ws.ccount;
+    ra.nq = (size_t)sd.nq;
+    hipLaunchKernelGGL(k_reset, dim3(256), dim3(256), 0, st, ra);
+  }
   // PPM
   PairArgs pa;
   pa.Q = queries;
