@@ -1,0 +1,78 @@
+// Device helpers shared by the kernel translation units of the search
+// library (kernels.hip and the scan translation units).
+#pragma once
+#include "amp_internal.h"
+
+#include <type_traits>
+
+namespace amp {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+// ------------------------------------------------------------------ helpers
+// order-preserving keys: integers (sign flip) and floats (IEEE total order)
+__device__ __forceinline__ uint64_t ikey(int64_t v) { return (uint64_t)v ^ 0x8000000000000000ull; }
+__device__ __forceinline__ int64_t ikey_val(uint64_t k) { return (int64_t)(k ^ 0x8000000000000000ull); }
+__device__ __forceinline__ uint32_t fkey(float f) {
+  uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float fkey_val(uint32_t k) {
+  uint32_t u = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
+  return __uint_as_float(u);
+}
+
+// nearest E4M3 value of an integer: 3 mantissa bits, ties to even, saturating
+// at 448 (OCP 8-bit floating point specification, E4M3 "fn" encoding)
+__device__ __forceinline__ int e4m3_int(int v) {
+  int a = v < 0 ? -v : v;
+  if (a >= 16) {
+    int E = 31 - __clz(a);
+    int sh = E - 3;
+    int q = a >> sh;
+    int rem = a & ((1 << sh) - 1);
+    int half = 1 << (sh - 1);
+    if (rem > half || (rem == half && (q & 1))) q++;
+    a = q << sh;
+  }
+  a = a > 448 ? 448 : a;
+  return v < 0 ? -a : a;
+}
+
+// operand grid: round half to even of r * 2^-e, then saturate (9-bit grid) or
+// round to the e4m3-representable integers
+__device__ __forceinline__ int grid_val(float r, int e, int kind) {
+  const float x = rintf(ldexpf(r, -e));
+  if (kind == AMP_GRID_U9) return (int)__builtin_amdgcn_fmed3f(x, -255.f, 255.f);
+  return e4m3_int((int)__builtin_amdgcn_fmed3f(x, -65536.f, 65536.f));
+}
+
+__device__ __forceinline__ uint32_t bf16_bits(float v) {  // exact inputs only
+  return __float_as_uint(v) >> 16;
+}
+
+// min / max over each 16-lane row of a wave: after row shifts by 1, 2, 4, 8
+// (lanes without a source keep their value) lane 15 of the row holds it
+template <bool MAX, int K>
+__device__ __forceinline__ int row16_step(int v) {
+  const int o = __builtin_amdgcn_update_dpp(v, v, 0x110 + K, 0xF, 0xF, false);  // row_shr:K
+  return MAX ? (o > v ? o : v) : (o < v ? o : v);
+}
+template <bool MAX>
+__device__ __forceinline__ int row16_reduce(int v) {
+  return row16_step<MAX, 8>(row16_step<MAX, 4>(row16_step<MAX, 2>(row16_step<MAX, 1>(v))));
+}
+
+// LC matrix dtypes of the integer LUT build.  (An FP8 e4m3 variant is not
+// offered: the 16x16x32 FP8 MFMA of gfx950 does not return the exact sum of
+// e4m3-grid products of the magnitudes the grid allows.)
+enum { DT_BF16 = 1, DT_F16 = 2 };
+
+__device__ __forceinline__ uint32_t f16_bits(float v) {  // exact inputs only
+  return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)v);
+}
+}  // namespace amp

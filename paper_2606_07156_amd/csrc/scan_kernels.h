@@ -1,0 +1,1176 @@
+// Scan kernels of the search (LC, quantisation, DC scan, unit top-k):
+// templates instantiated per phase in scan_ph1.hip, scan_ph2.hip and
+// scan_ph3.hip (three translation units that compile side by side).
+#pragma once
+#include "device_common.h"
+
+namespace amp {
+
+// ------------------------------------------------------------------ scan
+struct ScanArgs {
+  const float* Q;
+  const float* C;
+  const float* codebook;   // FP32 policy
+  const u32x4* bsw;        // integer policy MFMA B fragments (BF16, with aug slots)
+  const u32x4* bsw16;      // FP16 dims fragments
+  const int16_t* cbi16;    // [M][256][8] grid codebook (L1 LUT build)
+  const uint8_t* codes;
+  const int64_t* ids;
+  const int64_t* offsets;
+  const int32_t* kq;
+  const uint8_t* pbits;
+  const int32_t* sorted;   // this phase's sorted pairs
+  const int64_t* unitoff;  // this phase's unit offsets (NB+1)
+  const int4* units;       // this phase's unit table
+  uint32_t* counter;       // this phase/class unit counter
+  uint64_t* tau;
+  uint32_t* ccount;
+  uint64_t* ckey;
+  int64_t* cid;
+  int32_t* flags;
+  const uint8_t* retry;     // phase 3 (re-run of phase 2): queries taking part
+  const int64_t* tau_id;    // phase 3: id of the bound's (distance, id) key
+  const int32_t* any_retry; // phase 3: non-zero if any query takes part
+  uint64_t* work;           // phase 2 work counters (code bytes scanned, live pairs, dead pairs) or null
+  int nq, d, M, dsub, nlist, npmax, grid_e, grid_kind, metric, kconst, kmax, cls;
+  int steal;                // unit queue: 0 one counter, 1 per-XCD ranges with stealing
+  int64_t chunk;
+  size_t capq;
+};
+
+// Unit fetch of the persistent scan kernels (called by one thread of the
+// workgroup; returns a unit number of the launch order, `total` once the
+// queue is drained).  steal = 0: one counter over the cost-sorted order.
+// steal = 1: the order is cut into kXcd contiguous ranges, range x served
+// by the workgroups of XCD x (workgroups are dispatched to the XCDs in turn,
+// so blockIdx mod kXcd is the XCD), which keeps the units of one list
+// (adjacent in the order) on one XCD's L2; a workgroup whose range is used
+// up takes units from the next ranges in ring order (work stealing).  Every
+// counter sits in its own 128-byte line; the counters only grow, so a
+// drained range stays drained and every workgroup ends after at most kXcd
+// failed attempts.
+struct UnitQueue {
+  uint32_t* ctr;
+  int64_t total;
+  int steal, home, vic;
+  __device__ __forceinline__ UnitQueue(uint32_t* c, int64_t t, int s)
+      : ctr(c), total(t), steal(s), home((int)(blockIdx.x % kXcd)), vic(0) {}
+  __device__ __forceinline__ int64_t next() {
+    if (!steal) return (int64_t)atomicAdd(ctr, 1u);
+    for (; vic < kXcd; ++vic) {
+      const int x = (home + vic) % kXcd;
+      const int64_t lo = total * x / kXcd, hi = total * (x + 1) / kXcd;
+      if (lo >= hi) continue;
+      const int64_t u = lo + (int64_t)atomicAdd(ctr + x * kCtrStride, 1u);
+      if (u < hi) return u;
+    }
+    return total;
+  }
+};
+
+// words per LUT row for a subspace count: the LUT of one work unit takes
+// M * 256 * WPR * 4 bytes of LDS
+__host__ __device__ constexpr int wpr_for(int M) { return M <= 16 ? 4 : (M <= 32 ? 2 : 1); }
+// words per LUT row of a scan kernel variant: the variants specialised for a
+// subspace count MT pack wpr_for(MT) words, the generic one (MT = 0) one word.
+// The work-unit queue packs pairs into units with the same figure, so both
+// sides take it from here.
+__host__ __device__ constexpr int kernel_wpr(int MT) { return MT ? wpr_for(MT) : 1; }
+// a variant specialised for MT may also run with one-word rows (NR = 1:
+// sparse batches, a few pairs per list), keeping its codes in registers
+__host__ __device__ constexpr int variant_wpr(int MT, int NR) { return NR ? 1 : kernel_wpr(MT); }
+
+// row stride (int16 elements) of the integer residuals in LDS: each row is
+// padded by 32 bytes, so the eight rows that the LC A-operand build reads at
+// once (d a multiple of 64 puts them all in one bank otherwise) fall in
+// distinct banks, as do the two subspaces of an m-pair
+__host__ __device__ constexpr int ri_stride(int d) { return d + 16; }
+
+// LDS carve-up of one scan workgroup (all offsets in bytes, 16-aligned)
+struct ScanLds {
+  int lut, ri, rr, lo, hi, pq, pb, ps, pbase, psig, lmin, ctl, total;
+};
+__host__ __device__ inline ScanLds scan_lds_layout(int G, int wpr, int M, int d, bool fp32, int phase) {
+  ScanLds L;
+  int o = 0;
+  auto take = [&](int bytes) { int r = o; o += (bytes + 15) & ~15; return r; };
+  L.lut = take(M * kKsub * wpr * 4);
+  L.ri = take(G * (fp32 ? d * 4 : ri_stride(d) * 2));
+  L.rr = take(G * M * 4);
+  L.lo = take(G * M * 4);
+  L.hi = take(G * M * 4);
+  L.pq = take(G * 4);
+  L.pb = take(G * 4);
+  L.ps = take(G * 4);
+  L.pbase = take(G * 8);
+  L.psig = take(G * 4);
+  // phase 1 keeps per-thread minima after the scan: reuse the LUT space
+  L.lmin = L.lut;
+  if (phase == 1 && G * kThreadsP2 * 4 > M * kKsub * wpr * 4) L.lmin = take(G * kThreadsP2 * 4);
+  // unit-claim control words: kept in the dynamic LDS too, so that the LUT
+  // starts at LDS address 0 and row addresses fold into instruction offsets
+  L.ctl = take(64);  // unit index, class, re-run vote, live vote, unit descriptor, 3 work counters
+  L.total = o;
+  return L;
+}
+
+template <int LWB>  // lane bits 8/16/32, 0 = FP32 LUT
+struct Lane {
+  static constexpr int W = LWB ? 32 / LWB : 1;
+  static constexpr uint32_t MASK = LWB == 32 || LWB == 0 ? 0xFFFFFFFFu : ((1u << LWB) - 1);
+};
+
+// where pair g of a work unit sits in a LUT row: word and field.  The 8-bit
+// class with four words per row interleaves the pairs (word 2 h + t holds
+// pairs 8 t + 4 h + 0..3) so that a lane of the LUT build writes its two
+// words with one 8-byte store; every other layout is word g / W, field g % W.
+template <int LWB, int WPR>
+struct PairSlot {
+  static constexpr bool IL = LWB == 8 && WPR == 4;
+  static constexpr int W = Lane<LWB>::W;
+  __host__ __device__ static constexpr int word(int g) { return IL ? (((g >> 2) & 1) << 1) | (g >> 3) : g / W; }
+  __host__ __device__ static constexpr int field(int g) { return IL ? (g & 3) : g % W; }
+  __host__ __device__ static constexpr int pair(int w, int f) {
+    return IL ? ((w & 1) << 3) | ((w >> 1) << 2) | f : w * W + f;
+  }
+};
+
+// LDS-address-space views: the scan kernels declare no static LDS, so their
+// dynamic block (the LUT first) starts at LDS address 0 and a row address is
+// a plain constant offset plus the scaled code byte
+typedef __attribute__((address_space(3))) const uint32_t lds_u32;
+typedef __attribute__((address_space(3))) const u32x2 lds_u32x2;
+typedef __attribute__((address_space(3))) const u32x4 lds_u32x4;
+
+template <int WPR>
+__device__ __forceinline__ void lut_row_load(lds_u32* lut, int row, uint32_t* w) {
+  if constexpr (WPR == 4) {
+    u32x4 x = *reinterpret_cast<lds_u32x4*>(lut + row);
+    w[0] = x[0]; w[1] = x[1]; w[2] = x[2]; w[3] = x[3];
+  } else if constexpr (WPR == 2) {
+    u32x2 x = *reinterpret_cast<lds_u32x2*>(lut + row);
+    w[0] = x[0]; w[1] = x[1];
+  } else {
+    w[0] = lut[row];
+  }
+}
+
+// One m-pair of the integer LUT of a work unit.  Rows of the A operand are
+// (subspace slot ms, pair g) = ms*8 + g; K holds [dims m0 | aug m0 | dims m1 |
+// aug m1], 8 slots each.  The aug slots carry |cbi|^2 (digits in B, powers
+// of two in A) and |ri|^2 + off (digits in A, powers of two in B).
+//  * DT_BF16: one BF16 MFMA 16x16x32 with everything scaled by 2^-s in A
+//    gives exactly 2^-s (T + off) (every partial sum is an integer multiple of
+//    2^-s below 2^(24-s));
+//  * DT_F16: the aug terms on BF16 MFMA, then the dot products (-2 ri, or
+//    -ri for inner product) on an FP16 MFMA accumulating into the same FP32
+//    registers: T + off exactly, scaled by 2^-s afterwards.
+// Inner product: dims coefficient -1 and no |ri|^2, |cbi|^2 terms.
+// PASS 1: off = 0, s = 0, record min/max over the codewords (integer
+// compares of the exact values);
+// PASS 2: quantise (truncation of the exact non-negative value) and pack.
+// The pass is a template argument so that the 16 x NGT products of an m-pair
+// are independent straight-line code the compiler can overlap.
+template <int LWB, int WPR, int DT, int PASS, bool IP>
+__device__ __forceinline__ void lut_mpair(const ScanArgs& a, char* lds, const ScanLds& L, int M, int np_u,
+                                          int mp, const u32x4 (&B)[16], const u32x4 (&Bd)[16]) {
+  constexpr int pass = PASS;
+  constexpr int W = Lane<LWB>::W;
+  constexpr int G = WPR * W;
+  constexpr int NGT = (G + 7) / 8;
+  const int lane = threadIdx.x & 63;
+  const int16_t* ri = reinterpret_cast<const int16_t*>(lds + L.ri);
+  const int32_t* rr = reinterpret_cast<const int32_t*>(lds + L.rr);
+  int32_t* lo = reinterpret_cast<int32_t*>(lds + L.lo);
+  int32_t* hi = reinterpret_cast<int32_t*>(lds + L.hi);
+  const int32_t* ps = reinterpret_cast<const int32_t*>(lds + L.ps);
+  uint32_t* lut = reinterpret_cast<uint32_t*>(lds + L.lut);
+  const int row = lane & 15, kg = lane >> 4;
+  const int ms_row = row >> 3;
+  const int dsub = a.dsub;
+  const int rs = ri_stride(a.d);
+  constexpr bool ip = IP;  // metric as a compile-time flag: no per-value select
+  bf16x8 A[NGT];
+  u32x4 Ad[NGT];
+#pragma unroll
+  for (int gt = 0; gt < NGT; ++gt) {
+    const int g = gt * 8 + (row & 7);
+    const int m = 2 * mp + ms_row;
+    uint32_t pk[4] = {0, 0, 0, 0}, pd[4] = {0, 0, 0, 0};
+    if (g < np_u && (kg >> 1) == ms_row) {
+      const int s = pass == 1 ? 0 : ps[g];
+      const float sc = DT == DT_BF16 ? ldexpf(1.f, -s) : 1.f;
+      if ((kg & 1) == 0) {
+        const int coef = ip ? -1 : -2;
+        // the subspace's grid residual: one 16-byte read when d_sub = 8
+        // (rows and subspaces 16-byte aligned), else element by element
+        int rv[8];
+        if (dsub == 8 && (a.d & 7) == 0) {
+          const u32x4 w = *reinterpret_cast<const u32x4*>(ri + g * rs + m * 8);
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            rv[2 * t] = (int)(int16_t)(w[t] & 0xFFFFu);
+            rv[2 * t + 1] = (int)(int16_t)(w[t] >> 16);
+          }
+        } else {
+#pragma unroll
+          for (int t = 0; t < 8; ++t) rv[t] = t < dsub ? (int)ri[g * rs + m * dsub + t] : 0;
+        }
+        if constexpr (DT == DT_BF16) {
+          float v[8];
+#pragma unroll
+          for (int t = 0; t < 8; ++t) v[t] = t < dsub ? (float)(coef * rv[t]) * sc : 0.f;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) pk[t] = bf16_bits(v[2 * t]) | (bf16_bits(v[2 * t + 1]) << 16);
+        } else {
+          float v[8];
+#pragma unroll
+          for (int t = 0; t < 8; ++t) v[t] = t < dsub ? (float)(coef * rv[t]) : 0.f;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) pd[t] = f16_bits(v[2 * t]) | (f16_bits(v[2 * t + 1]) << 16);
+        }
+      } else {
+        int32_t X = ip ? 0 : rr[g * M + m];
+        if (pass == 2) X += lo[g * M + m];  // lo holds off = hf(s) - min after pass 1
+        const float sg = X < 0 ? -1.f : 1.f;
+        const uint32_t ax = (uint32_t)(X < 0 ? -X : X);
+        const float cm = ip ? 0.f : sc;
+        float v[8];
+        v[0] = 65536.f * cm;
+        v[1] = 256.f * cm;
+        v[2] = cm;
+        v[3] = sg * (float)(ax >> 16) * sc;
+        v[4] = sg * (float)((ax >> 8) & 255u) * sc;
+        v[5] = sg * (float)(ax & 255u) * sc;
+        v[6] = 0.f;
+        v[7] = 0.f;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) pk[t] = bf16_bits(v[2 * t]) | (bf16_bits(v[2 * t + 1]) << 16);
+      }
+    }
+    u32x4 u = {pk[0], pk[1], pk[2], pk[3]};
+    A[gt] = __builtin_bit_cast(bf16x8, u);
+    Ad[gt] = (u32x4){pd[0], pd[1], pd[2], pd[3]};
+  }
+  // D rows of this lane: (ms = kg>>1, g = gt*8 + 4*(kg&1) + i), column j
+  const int m_out = 2 * mp + (kg >> 1);
+  float rsc[NGT][4];  // 2^-s of each row (used after a non-BF16 build)
+#pragma unroll
+  for (int gt = 0; gt < NGT; ++gt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int g = gt * 8 + 4 * (kg & 1) + i;
+      rsc[gt][i] = (DT == DT_BF16 || pass == 1 || g >= np_u) ? 1.f : ldexpf(1.f, -ps[g]);
+    }
+  int mn[NGT][4], mx[NGT][4];
+  uint32_t wv8[NGT];  // packed words of the interleaved 8-bit layout
+#pragma unroll
+  for (int gt = 0; gt < NGT; ++gt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { mn[gt][i] = 0x7FFFFFFF; mx[gt][i] = -0x7FFFFFFF - 1; }
+#pragma unroll
+  for (int jt = 0; jt < 16; ++jt) {
+    const bf16x8 Bf = __builtin_bit_cast(bf16x8, B[jt]);
+    const u32x4 Bdj = Bd[jt];
+    const int j = jt * 16 + (lane & 15);
+#pragma unroll
+    for (int gt = 0; gt < NGT; ++gt) {
+      f4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[gt], Bf, (f4){0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+      if constexpr (DT == DT_F16) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, Ad[gt]),
+                                                     __builtin_bit_cast(f16x8, Bdj), acc, 0, 0, 0);
+      }
+      const int g0 = gt * 8 + 4 * (kg & 1);
+      if constexpr (PASS == 1) {
+        // exact integers: for L2 (T >= 0) the float bit patterns order as
+        // integers; inner product values may be negative and are converted
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int t = ip ? (int)acc[i] : __float_as_int(acc[i]);
+          mn[gt][i] = t < mn[gt][i] ? t : mn[gt][i];
+          mx[gt][i] = t > mx[gt][i] ? t : mx[gt][i];
+        }
+      } else if (g0 < G) {
+        uint32_t qv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float vv = DT == DT_BF16 ? acc[i] : acc[i] * rsc[gt][i];  // power-of-two scale: exact
+          qv[i] = (uint32_t)vv;  // exact and >= 0: truncation = floor
+        }
+        uint32_t* dst = lut + (size_t)(m_out * kKsub + j) * WPR;
+        if constexpr (PairSlot<LWB, WPR>::IL) {
+          wv8[gt] = qv[0] | (qv[1] << 8) | (qv[2] << 16) | (qv[3] << 24);
+          if (gt == NGT - 1)  // words 2 h, 2 h + 1 (h = kg & 1): one 8-byte store
+            *reinterpret_cast<u32x2*>(dst + 2 * (kg & 1)) = (u32x2){wv8[0], wv8[1]};
+        } else if constexpr (LWB == 8) {
+          dst[g0 >> 2] = qv[0] | (qv[1] << 8) | (qv[2] << 16) | (qv[3] << 24);
+        } else if constexpr (LWB == 16) {
+          const int w0 = g0 >> 1;
+          if (w0 + 1 < WPR)
+            *reinterpret_cast<u32x2*>(dst + w0) = (u32x2){qv[0] | (qv[1] << 16), qv[2] | (qv[3] << 16)};
+          else if (w0 < WPR)
+            dst[w0] = qv[0] | (qv[1] << 16);
+        } else if constexpr (WPR == 4) {
+          *reinterpret_cast<u32x4*>(dst) = (u32x4){qv[0], qv[1], qv[2], qv[3]};  // g0 == 0 here
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            if (g0 + i < WPR) dst[g0 + i] = qv[i];
+        }
+      }
+    }
+  }
+  if constexpr (PASS == 1) {
+#pragma unroll
+    for (int gt = 0; gt < NGT; ++gt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        int a0 = row16_reduce<false>(mn[gt][i]), b0 = row16_reduce<true>(mx[gt][i]);
+        if (!ip) {
+          a0 = (int)__int_as_float(a0);
+          b0 = (int)__int_as_float(b0);
+        }
+        const int g = gt * 8 + 4 * (kg & 1) + i;
+        if ((lane & 15) == 15 && g < np_u) {
+          lo[g * M + m_out] = a0;
+          hi[g * M + m_out] = b0;
+        }
+      }
+  }
+}
+
+// FP32 LUT entries are built by thread (m, j) = (kMPar i + tid / 256, tid % 256)
+// (threads past kMPar * 256 do not take part)
+constexpr int kMPar = kThreads / kKsub;  // subspaces built side by side
+template <int WPR, int MT>
+struct Owned {
+  // codewords of the FP32 LUT entries a thread owns
+  static constexpr int NM = MT ? MT / kMPar : 1;
+  float c[NM][kMaxDsub];
+};
+
+// One work unit (G pairs of one list, lane class LWB; 0 = FP32 LUT): RC, LC,
+// quantisation, DC scan, and the phase's bound or candidate forwarding.
+// L may be the layout of a larger tile (the mixed-class kernel).
+template <int LWB, int MT, int PHASE, int DT, int NR, typename Own, typename Fetch>
+__device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const ScanLds& L, const Own& own,
+                                          const int4 unit, Fetch&& fetch_next) {
+  constexpr int WPR = variant_wpr(MT, NR);
+  constexpr bool FP = LWB == 0;
+  constexpr int W = Lane<LWB>::W;
+  constexpr int G = WPR * W;
+  constexpr uint32_t MASK = Lane<LWB>::MASK;
+  constexpr bool CRES = FP && MT != 0 && MT <= 16;  // FP32 codewords stay in registers
+  const int M = MT ? MT : a.M;
+  int32_t* pq = reinterpret_cast<int32_t*>(lds + L.pq);
+  int32_t* pb = reinterpret_cast<int32_t*>(lds + L.pb);
+  int32_t* ps = reinterpret_cast<int32_t*>(lds + L.ps);
+  int64_t* pbase = reinterpret_cast<int64_t*>(lds + L.pbase);
+  uint32_t* psig = reinterpret_cast<uint32_t*>(lds + L.psig);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int own_j = tid % kKsub, own_m0 = tid / kKsub;
+  const bool owner = tid < kMPar * kKsub;
+    const int p = unit.x;
+    int np_u = unit.z;
+    if (np_u > G) {  // a unit never holds more pairs than the tile (guarded, flagged)
+      if (tid == 0) atomicOr(&a.flags[0], 8);
+      np_u = G;
+    }
+    const int64_t L0 = a.offsets[p];
+    const int64_t n_list = a.offsets[p + 1] - L0;
+    const int64_t v0 = (int64_t)unit.w * a.chunk;
+    const int64_t v1 = v0 + a.chunk < n_list ? v0 + a.chunk : n_list;
+    if (tid < G) {
+      if (tid < np_u) {
+        const int pid = a.sorted[unit.y + tid];
+        pq[tid] = pid / a.npmax;
+        pb[tid] = a.pbits[pid];
+      } else {
+        pq[tid] = -1;
+        pb[tid] = 16;
+      }
+    }
+    if (PHASE == 3) {
+      // re-run: a unit with no pair of a re-run query is skipped whole (the
+      // vote goes through a control word of the dynamic LDS: the scan
+      // kernels use no static LDS)
+      int& s_part = *reinterpret_cast<int*>(lds + L.ctl + 8);
+      if (tid == 0) s_part = 0;
+      __syncthreads();
+      if (tid < np_u && a.retry[pq[tid]]) s_part = 1;
+      __syncthreads();
+      if (!s_part) {
+        fetch_next();
+        return;
+      }
+    }
+    __syncthreads();
+    // ---- RC: residuals (FP32, then onto the grid for integer policies)
+    // (inner product: the query itself, on the grid for integer policies)
+    // four coordinates per thread and step (d is a multiple of 4, query rows
+    // and centroids 16-byte aligned); (pair, quad) advanced without division
+    const bool ip = a.metric == AMP_IP;
+    const bool l1 = a.metric == AMP_L1;
+    {
+      const int d4 = a.d >> 2;
+      const int gstep = kThreads / d4, tstep = kThreads - gstep * d4;
+      int g = tid / d4, t4 = tid - g * d4;
+      const float4* C4 = reinterpret_cast<const float4*>(a.C + (size_t)p * a.d);
+      while (g < np_u) {
+        const float4 qv = reinterpret_cast<const float4*>(a.Q + (size_t)pq[g] * a.d)[t4];
+        float4 r = qv;
+        if (!ip) {
+          const float4 cv = C4[t4];
+          r.x = qv.x - cv.x;
+          r.y = qv.y - cv.y;
+          r.z = qv.z - cv.z;
+          r.w = qv.w - cv.w;
+        }
+        if constexpr (FP) {
+          reinterpret_cast<float4*>(lds + L.ri)[g * d4 + t4] = r;
+        } else {
+          const uint32_t v0 = (uint32_t)grid_val(r.x, a.grid_e, a.grid_kind) & 0xFFFFu;
+          const uint32_t v1 = (uint32_t)grid_val(r.y, a.grid_e, a.grid_kind) & 0xFFFFu;
+          const uint32_t v2 = (uint32_t)grid_val(r.z, a.grid_e, a.grid_kind) & 0xFFFFu;
+          const uint32_t v3 = (uint32_t)grid_val(r.w, a.grid_e, a.grid_kind) & 0xFFFFu;
+          reinterpret_cast<u32x2*>(lds + L.ri)[g * (ri_stride(a.d) >> 2) + t4] = (u32x2){v0 | (v1 << 16), v2 | (v3 << 16)};
+        }
+        g += gstep;
+        t4 += tstep;
+        if (t4 >= d4) {
+          t4 -= d4;
+          ++g;
+        }
+      }
+    }
+    __syncthreads();
+    // ---- per-pair pruning threshold in the lane domain (phases 2, 3): a
+    // pair whose base already exceeds its query's bound is dead (pb = -1)
+    auto pair_threshold = [&](int g) -> bool {
+      uint32_t sig = 0;
+      bool live = false;
+      if (g < np_u && (PHASE != 3 || a.retry[pq[g]])) {
+        const uint64_t tk = a.tau[pq[g]];
+        live = true;
+        if (tk == ~0ull) {
+          sig = 0xFFFFFFFFu;
+        } else if constexpr (FP) {
+          sig = (uint32_t)tk;
+          // the pair's lower bound (sum of its row minima) already above
+          if (PHASE >= 2 && fkey(reinterpret_cast<const float*>(lds + L.pbase)[g]) > sig) live = false;
+        } else {
+          const int64_t t = ikey_val(tk);
+          if (t < pbase[g]) {
+            live = false;
+          } else {
+            const int64_t dd = (t - pbase[g]) >> ps[g];
+            sig = dd > (int64_t)MASK ? MASK : (uint32_t)dd;
+          }
+        }
+      }
+      psig[g] = live ? sig : 0;
+      pb[g] = live ? pb[g] : -1;  // -1: no candidate can pass
+      return live;
+    };
+    auto thresholds = [&] {
+      if (PHASE >= 2 && tid < G) pair_threshold(tid);
+    };
+    // ---- LC
+    if constexpr (FP) {
+      // T[m][j] = (|r_m|^2 + |c_mj|^2) - 2 r_m.c_mj in FP32 (one FMA chain per entry)
+      const float* r32 = reinterpret_cast<const float*>(lds + L.ri);
+      float* rr32 = reinterpret_cast<float*>(lds + L.rr);
+      for (int e = tid; e < np_u * M; e += kThreads) {
+        const int g = e / M, m = e % M;
+        const float* r = r32 + g * a.d + m * a.dsub;
+        float sq = 0.f;
+        if (ip) {  // partial -q.c of this subspace
+          const float* c = a.C + (size_t)p * a.d + m * a.dsub;
+#pragma unroll
+          for (int t = 0; t < kMaxDsub; ++t)
+            if (t < a.dsub) sq = fmaf(-r[t], c[t], sq);
+        } else {
+#pragma unroll
+          for (int t = 0; t < kMaxDsub; ++t)
+            if (t < a.dsub) sq = fmaf(r[t], r[t], sq);
+        }
+        rr32[e] = sq;
+      }
+      __syncthreads();
+      if (tid < G) {
+        ps[tid] = 0;
+        pbase[tid] = 0;
+      }
+      float* lut = reinterpret_cast<float*>(lds + L.lut);
+      // the metric is a compile-time tag of the entry code (0 L2, 1 IP, 2 L1)
+      auto entry = [&](auto mtag, int m, const float (&c)[kMaxDsub]) {
+        constexpr int MM = decltype(mtag)::value;
+        const int e = m * kKsub + own_j;
+        float cc = 0.f;
+        if constexpr (MM == 0) {
+#pragma unroll
+          for (int t = 0; t < kMaxDsub; ++t) cc = fmaf(c[t], c[t], cc);
+        }
+        float out[WPR];
+#pragma unroll
+        for (int g = 0; g < WPR; ++g) {
+          float sv = 0.f;
+          if (g < np_u) {
+            const float* r = r32 + g * a.d + m * a.dsub;
+            if constexpr (MM == 2) {
+              float ad = 0.f;
+#pragma unroll
+              for (int t = 0; t < kMaxDsub; ++t)
+                if (t < a.dsub) ad += fabsf(r[t] - c[t]);
+              sv = ad;
+            } else {
+              float dot = 0.f;
+#pragma unroll
+              for (int t = 0; t < kMaxDsub; ++t)
+                if (t < a.dsub) dot = fmaf(r[t], c[t], dot);
+              if constexpr (MM == 1) {
+                // inner product: the pair's base -q.c (sum of the subspace
+                // partials) is folded into subspace 0's entries
+                float bf = 0.f;
+                if (m == 0)
+                  for (int mm = 0; mm < M; ++mm) bf += rr32[g * M + mm];
+                sv = bf - dot;
+              } else {
+                sv = fmaf(-2.f, dot, rr32[g * M + m] + cc);
+              }
+            }
+          }
+          out[g] = sv;
+        }
+        float* dst = lut + (size_t)e * WPR;
+#pragma unroll
+        for (int g = 0; g < WPR; ++g) dst[g] = out[g];
+      };
+      auto fill = [&](auto mtag) {
+        if constexpr (CRES) {
+          if (owner) {
+#pragma unroll
+            for (int i = 0; i < MT / kMPar; ++i) entry(mtag, kMPar * i + own_m0, own.c[i]);
+          }
+        } else if (owner) {
+          for (int m = own_m0; m < M; m += kMPar) {
+            float c[kMaxDsub];
+#pragma unroll
+            for (int t = 0; t < kMaxDsub; ++t)
+              c[t] = t < a.dsub ? a.codebook[((size_t)m * kKsub + own_j) * a.dsub + t] : 0.f;
+            entry(mtag, m, c);
+          }
+        }
+      };
+      if (l1) fill(std::integral_constant<int, 2>{});
+      else if (ip) fill(std::integral_constant<int, 1>{});
+      else fill(std::integral_constant<int, 0>{});
+    } else {
+      int32_t* rr = reinterpret_cast<int32_t*>(lds + L.rr);
+      const int16_t* ri = reinterpret_cast<const int16_t*>(lds + L.ri);
+      const bool vec8 = a.dsub == 8 && (a.d & 7) == 0;  // 16-byte aligned subspace rows
+      for (int e = tid; e < np_u * M; e += kThreads) {
+        const int g = e / M, m = e % M;
+        int32_t sacc = 0;
+        if (vec8 && !ip) {
+          // |ri|^2 of the subspace from one 16-byte read
+          const u32x4 w = *reinterpret_cast<const u32x4*>(ri + g * ri_stride(a.d) + m * 8);
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int lo16 = (int)(int16_t)(w[t] & 0xFFFFu), hi16 = (int)(int16_t)(w[t] >> 16);
+            sacc += lo16 * lo16 + hi16 * hi16;
+          }
+        } else {
+          for (int t = 0; t < a.dsub; ++t) {
+            const int v = ri[g * ri_stride(a.d) + m * a.dsub + t];
+            // L2: |ri|^2 of the subspace; IP: qi.ci of the subspace (base term)
+            sacc += ip ? v * grid_val(a.C[(size_t)p * a.d + m * a.dsub + t], a.grid_e, a.grid_kind) : v * v;
+          }
+        }
+        rr[e] = sacc;
+      }
+      __syncthreads();
+      // the 16 B fragments of an m-pair are issued together, then consumed
+      auto build = [&](auto pass_tag, auto ip_tag) {
+        constexpr int PASS = decltype(pass_tag)::value;
+        constexpr bool IPM = decltype(ip_tag)::value;
+        for (int mp = wave; mp < M / 2; mp += kThreads / 64) {
+          u32x4 Bt[16], Bd[16];
+#pragma unroll
+          for (int jt = 0; jt < 16; ++jt) {
+            const size_t fi = ((size_t)mp * 16 + jt) * 64 + lane;
+            Bt[jt] = a.bsw[fi];
+            if constexpr (DT == DT_F16) Bd[jt] = a.bsw16[fi];
+            else Bd[jt] = (u32x4){0u, 0u, 0u, 0u};
+          }
+          lut_mpair<LWB, WPR, DT, PASS, IPM>(a, lds, L, M, np_u, mp, Bt, Bd);
+        }
+      };
+      using P1 = std::integral_constant<int, 1>;
+      using P2 = std::integral_constant<int, 2>;
+      using IPt = std::integral_constant<bool, true>;
+      using L2t = std::integral_constant<bool, false>;
+      // L1: T[m][j] = sum_t |ri_t - cbi_t| on the VALU (not a product, no
+      // MFMA), exact integers.  Pass 1: a thread per (pair, subspace) row
+      // finds its min / max over the 256 codewords; pass 2: a thread per
+      // (subspace, codeword) entry quantises it for every pair of the unit
+      // and packs the row words as the MFMA build does.
+      auto build_l1 = [&](int pass) {
+        int32_t* lo = reinterpret_cast<int32_t*>(lds + L.lo);
+        int32_t* hi = reinterpret_cast<int32_t*>(lds + L.hi);
+        if (pass == 1) {
+          for (int e = tid; e < np_u * M; e += kThreads) {
+            const int g = e / M, m = e % M;
+            int rv[kMaxDsub];
+#pragma unroll
+            for (int t = 0; t < kMaxDsub; ++t) rv[t] = t < a.dsub ? (int)ri[g * ri_stride(a.d) + m * a.dsub + t] : 0;
+            int mn = 0x7FFFFFFF, mx = 0;
+            const int16_t* cb = a.cbi16 + (size_t)m * kKsub * 8;
+            for (int j = 0; j < kKsub; ++j) {
+              int v = 0;
+#pragma unroll
+              for (int t = 0; t < kMaxDsub; ++t) v += abs(rv[t] - (int)cb[j * 8 + t]);
+              mn = v < mn ? v : mn;
+              mx = v > mx ? v : mx;
+            }
+            lo[e] = mn;
+            hi[e] = mx;
+          }
+        } else {
+          uint32_t* lut = reinterpret_cast<uint32_t*>(lds + L.lut);
+          for (int e = tid; e < M * kKsub; e += kThreads) {
+            const int m = e / kKsub, j = e % kKsub;
+            int cv[kMaxDsub];
+#pragma unroll
+            for (int t = 0; t < kMaxDsub; ++t) cv[t] = a.cbi16[((size_t)m * kKsub + j) * 8 + t];
+            uint32_t wds[WPR];
+#pragma unroll
+            for (int w = 0; w < WPR; ++w) wds[w] = 0;
+#pragma unroll
+            for (int w = 0; w < WPR; ++w)
+#pragma unroll
+              for (int f = 0; f < W; ++f) {
+                const int g = PairSlot<LWB, WPR>::pair(w, f);
+                if (g < np_u) {
+                  int v = 0;
+#pragma unroll
+                  for (int t = 0; t < kMaxDsub; ++t)
+                    if (t < a.dsub) v += abs((int)ri[g * ri_stride(a.d) + m * a.dsub + t] - cv[t]);
+                  const uint32_t qv = (uint32_t)((v + lo[g * M + m]) >> ps[g]);  // lo: hf(s) - min here
+                  wds[w] |= LWB == 32 ? qv : (qv << (f * LWB));
+                }
+              }
+            uint32_t* dst = lut + (size_t)(m * kKsub + j) * WPR;
+#pragma unroll
+            for (int w = 0; w < WPR; ++w) dst[w] = wds[w];
+          }
+        }
+      };
+      if (l1) build_l1(1);
+      else if (ip) build(P1{}, IPt{});
+      else build(P1{}, L2t{});
+      if (tid == 0) *reinterpret_cast<int*>(lds + L.ctl + 12) = 0;  // live-pair count of the unit
+      __syncthreads();
+      {
+        // per pair g: shift s, base = sum of the subspace minima (inner
+        // product: minus qi.ci); sixteen threads (a 16-lane row) per pair
+        const int32_t* lo = reinterpret_cast<const int32_t*>(lds + L.lo);
+        const int32_t* hi = reinterpret_cast<const int32_t*>(lds + L.hi);
+        const int32_t* rrp = reinterpret_cast<const int32_t*>(lds + L.rr);
+        const int g = tid >> 4, r = tid & 15;
+        int32_t span = 0;
+        int64_t bsum = 0;
+        if (g < np_u)
+          for (int m = r; m < M; m += 16) {
+            const int32_t l = lo[g * M + m], h = hi[g * M + m];
+            span = h - l > span ? h - l : span;
+            bsum += l - (ip ? rrp[g * M + m] : 0);
+          }
+        span = row16_reduce<true>(span);
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) bsum += __shfl_xor(bsum, off, 16);
+        if (r == 15 && g < G) {
+          if (g < np_u) {
+            const int64_t top = (1ll << pb[g]) - 1, R = span;
+            int sh = 0;
+            while (((R + (sh ? (1ll << (sh - 1)) : 0)) >> sh) > top) ++sh;
+            ps[g] = sh;
+            pbase[g] = bsum;
+          }
+          // phases 2, 3: the bases are known before pass 2, the pair's
+          // threshold too (same lane, no barrier); live pairs are counted
+          if (PHASE >= 2 && pair_threshold(g))
+            atomicAdd(reinterpret_cast<int*>(lds + L.ctl + 12), 1);
+        }
+      }
+      __syncthreads();
+      if constexpr (PHASE >= 2) {
+        // a unit whose pairs are all dead skips pass 2 and the scan (the
+        // count goes through a control word, zeroed before pass 1 ended)
+        const int nlive = *reinterpret_cast<int*>(lds + L.ctl + 12);
+        if (PHASE == 2 && tid == 0 && a.work) {
+          // work counters (code bytes of the pairs scanned, live and skipped
+          // pairs): kept by the workgroup, added to the totals at its end
+          uint64_t* wc = reinterpret_cast<uint64_t*>(lds + L.ctl + 32);
+          wc[0] += (uint64_t)(nlive * (v1 - v0) * M);
+          wc[1] += (uint64_t)nlive;
+          wc[2] += (uint64_t)(np_u - nlive);
+        }
+        if (!nlive) {
+          fetch_next();
+          return;
+        }
+      }
+      {
+        // lo -> the offset hf(s) - lo that pass 2 adds before the shift
+        int32_t* lo = reinterpret_cast<int32_t*>(lds + L.lo);
+        for (int e = tid; e < np_u * M; e += kThreads) {
+          const int g = e / M, sh = ps[g];
+          lo[e] = (sh ? (1 << (sh - 1)) : 0) - lo[e];
+        }
+      }
+      __syncthreads();
+      if (l1) build_l1(2);
+      else if (ip) build(P2{}, IPt{});
+      else build(P2{}, L2t{});
+      __syncthreads();
+    }
+    if constexpr (FP) {  // (integer LUTs: right after the shifts, before pass 2)
+      if constexpr (PHASE >= 2) {
+        // lower bound of each pair's FP32 sums: its row minima summed in the
+        // scan's subspace order (FP32 addition is monotone, so no vector's
+        // in-order sum is below it); sixteen threads per subspace, WPR pairs
+        // per 16-byte LUT row
+        __syncthreads();  // the LUT entries are written
+        const float* lutf = reinterpret_cast<const float*>(lds + L.lut);
+        float* rmin = reinterpret_cast<float*>(lds + L.lo);  // [G][M]
+        for (int m0 = 0; m0 < M; m0 += kThreads / 16) {
+          const int m = m0 + (tid >> 4), jb = (tid & 15) * 16;
+          float mn[WPR];
+#pragma unroll
+          for (int g = 0; g < WPR; ++g) mn[g] = __builtin_inff();
+          if (m < M)
+            for (int j = jb; j < jb + 16; ++j) {
+#pragma unroll
+              for (int g = 0; g < WPR; ++g) mn[g] = fminf(mn[g], lutf[(m * kKsub + j) * WPR + g]);
+            }
+#pragma unroll
+          for (int g = 0; g < WPR; ++g) {
+#pragma unroll
+            for (int o = 8; o > 0; o >>= 1) mn[g] = fminf(mn[g], __shfl_xor(mn[g], o, 16));
+            if (m < M && (tid & 15) == 0 && g < np_u) rmin[g * M + m] = mn[g];
+          }
+        }
+        __syncthreads();
+        if (tid < np_u) {
+          float sb = 0.f;
+          for (int m = 0; m < M; ++m) sb += rmin[tid * M + m];
+          reinterpret_cast<float*>(lds + L.pbase)[tid] = sb;
+        }
+        __syncthreads();
+        thresholds();
+        int& s_live = *reinterpret_cast<int*>(lds + L.ctl + 12);
+        if (tid == 0) s_live = 0;
+        __syncthreads();
+        if (tid < np_u && pb[tid] >= 0) atomicAdd(&s_live, 1);
+        __syncthreads();
+        const int nlive = s_live;
+        if (PHASE == 2 && tid == 0 && a.work) {
+          uint64_t* wc = reinterpret_cast<uint64_t*>(lds + L.ctl + 32);
+          wc[0] += (uint64_t)(nlive * (v1 - v0) * M);
+          wc[1] += (uint64_t)nlive;
+          wc[2] += (uint64_t)(np_u - nlive);
+        }
+        if (!nlive) {
+          fetch_next();
+          return;
+        }
+      } else {
+        __syncthreads();  // the LUT entries are written
+      }
+    }
+    // ---- DC scan: one vector per thread, codes of the next vector prefetched
+    uint32_t sig[G];
+    bool live[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      sig[g] = psig[g];
+      live[g] = PHASE >= 2 ? pb[g] >= 0 : g < np_u;
+    }
+    uint32_t lmin[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) lmin[g] = 0xFFFFFFFFu;
+    // packed thresholds of the 8-bit lane class: fields 0,2 and 1,3 of each
+    // word in 16-bit halves with guard bit 8; dead pairs never hit
+    uint32_t sig_e[WPR], sig_o[WPR], msk_e[WPR], msk_o[WPR];
+    if constexpr (PHASE >= 2 && LWB == 8) {
+#pragma unroll
+      for (int w = 0; w < WPR; ++w) {
+        uint32_t se = 0, so = 0, me = 0, mo = 0;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+          const int g = PairSlot<LWB, WPR>::pair(w, f);
+          const uint32_t sg = live[g] ? (sig[g] > 255u ? 255u : sig[g]) : 255u;
+          const uint32_t gb = live[g] ? 0x100u : 0u;
+          if (f & 1) { so |= (sg | 0x100u) << (16 * (f >> 1)); mo |= gb << (16 * (f >> 1)); }
+          else { se |= (sg | 0x100u) << (16 * (f >> 1)); me |= gb << (16 * (f >> 1)); }
+        }
+        sig_e[w] = se; sig_o[w] = so; msk_e[w] = me; msk_o[w] = mo;
+      }
+    }
+    lds_u32* lut = reinterpret_cast<lds_u32*>((uintptr_t)L.lut);  // LDS address (see lds_u32)
+    constexpr int MQ = MT ? MT / 4 : 1;  // code dwords per vector held in registers
+    // vectors per thread and step: one-word rows (a few pairs per list, the
+    // streaming case) make a vector cheap to scan, so four are kept in flight
+    // to cover HBM latency; wide rows are compute-bound at one
+    constexpr int PV = (NR && MT != 0) ? 4 : 1;
+    uint32_t cw_next[PV][MQ];
+    if constexpr (MT != 0) {
+#pragma unroll
+      for (int pv = 0; pv < PV; ++pv) {
+        const int64_t v = v0 + tid + pv * kThreads;
+        if (v < v1) {
+          const uint32_t* cp = reinterpret_cast<const uint32_t*>(a.codes + (size_t)(L0 + v) * MT);
+#pragma unroll
+          for (int i = 0; i < MQ; ++i) cw_next[pv][i] = cp[i];
+        }
+      }
+    }
+    fetch_next();  // the next unit's descriptor, read while this one scans
+    for (int64_t vb = v0; vb < v1; vb += kThreads * PV) {
+      uint32_t cwg[PV][MQ];
+#pragma unroll
+      for (int pv = 0; pv < PV; ++pv)
+#pragma unroll
+        for (int i = 0; i < MQ; ++i) cwg[pv][i] = cw_next[pv][i];
+      if constexpr (MT != 0) {
+#pragma unroll
+        for (int pv = 0; pv < PV; ++pv) {
+          const int64_t vn = vb + tid + (PV + pv) * kThreads;
+          if (vn < v1) {
+            const uint32_t* cp = reinterpret_cast<const uint32_t*>(a.codes + (size_t)(L0 + vn) * MT);
+#pragma unroll
+            for (int i = 0; i < MQ; ++i) cw_next[pv][i] = cp[i];
+          }
+        }
+      }
+#pragma unroll
+      for (int pv = 0; pv < PV; ++pv) {
+      const int64_t v = vb + tid + pv * kThreads;
+      uint32_t cw[MQ];
+#pragma unroll
+      for (int i = 0; i < MQ; ++i) cw[i] = cwg[pv][i];
+      if (v < v1) {
+        uint32_t acc[WPR];
+        float accf[WPR];
+#pragma unroll
+        for (int w = 0; w < WPR; ++w) { acc[w] = 0; accf[w] = 0.f; }
+        const uint32_t* cpg = reinterpret_cast<const uint32_t*>(a.codes + (size_t)(L0 + v) * M);
+        for (int m4 = 0; m4 < M; m4 += 4) {
+          uint32_t c4;
+          if constexpr (MT != 0) c4 = cw[m4 >> 2];
+          else c4 = cpg[m4 >> 2];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int rowi = ((m4 + i) * kKsub + ((c4 >> (8 * i)) & 255u)) * WPR;
+            uint32_t x[WPR];
+            lut_row_load<WPR>(lut, rowi, x);
+#pragma unroll
+            for (int w = 0; w < WPR; ++w) {
+              if constexpr (FP) accf[w] += __uint_as_float(x[w]);
+              else acc[w] += x[w];
+            }
+          }
+        }
+        auto emit = [&](int g, uint32_t S) {
+          const int q = pq[g];
+          uint64_t key;
+          if constexpr (FP) key = (uint64_t)S;
+          else key = ikey(pbase[g] + ((int64_t)S << ps[g]));
+          const int64_t id = a.ids[L0 + v];
+          // re-run: the bound is a (distance, id) key, ties past its id go
+          if (PHASE == 3 && key == a.tau[q] && id > a.tau_id[q]) return;
+          const uint32_t pos = atomicAdd(&a.ccount[q], 1u);
+          if (pos < a.capq) {
+            a.ckey[(size_t)q * a.capq + pos] = key;
+            a.cid[(size_t)q * a.capq + pos] = id;
+          }
+        };
+        if constexpr (PHASE >= 2 && LWB == 8) {
+          // four 8-bit sums per word: test all four against their thresholds
+          // at once in two 16-bit-lane halves (guard bit 8 survives iff S <= sigma)
+#pragma unroll
+          for (int w = 0; w < WPR; ++w) {
+            const uint32_t e = acc[w] & 0x00FF00FFu, o = (acc[w] >> 8) & 0x00FF00FFu;
+            const uint32_t hit = ((sig_e[w] - e) & msk_e[w]) | ((sig_o[w] - o) & msk_o[w]);
+            if (hit) {
+#pragma unroll
+              for (int f = 0; f < 4; ++f) {
+                // rare path: thresholds from LDS, not held in registers
+                const uint32_t S = (acc[w] >> (8 * f)) & 0xFFu;
+                const int g = PairSlot<LWB, WPR>::pair(w, f);
+                if (pb[g] >= 0 && S <= psig[g]) emit(g, S);
+              }
+            }
+          }
+        } else {
+#pragma unroll
+          for (int g = 0; g < G; ++g) {
+            const int w = PairSlot<LWB, WPR>::word(g), f = PairSlot<LWB, WPR>::field(g);
+            uint32_t S;
+            if constexpr (FP) S = fkey(accf[w]);
+            else S = LWB == 32 ? acc[w] : ((acc[w] >> (f * LWB)) & MASK);
+            if (PHASE == 1) {
+              lmin[g] = S < lmin[g] ? S : lmin[g];
+            } else if (live[g] && S <= sig[g]) {
+              emit(g, S);
+            }
+          }
+        }
+      }
+      }  // vectors of the step
+    }
+    if (PHASE == 1 && a.kmax <= 64) {
+      // the k-th smallest of a wave's per-lane minima bounds the pair's k-th
+      // smallest (each minimum is a distinct vector): the wave's k smallest
+      // minima go to the query's bound buffer, and the bound is taken over
+      // all of them.  The k-th smallest minimum x is found bit by bit (the
+      // largest x with fewer than k minima below it; counts are ballot bit
+      // counts, no cross-lane shuffles); the minima below x and the
+      // lowest-lane ones equal to x make up the k.
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        if (g >= np_u) break;
+        const uint32_t v = lmin[g];
+        const int q = pq[g];
+        const int kk = a.kq ? a.kq[q] : a.kconst;
+        uint32_t x = 0;
+        for (int bit = 31; bit >= 0; --bit) {
+          const uint32_t t = x | (1u << bit);
+          if (__popcll(__ballot(v < t)) < kk) x = t;
+        }
+        const uint64_t below = __ballot(v < x), eqm = __ballot(v == x);
+        const int need = kk - __popcll(below);
+        const uint64_t lower_lanes = (1ull << lane) - 1;
+        // (lanes that scanned no vector hold the largest key: never sent)
+        const bool e = (v < x || (v == x && __popcll(eqm & lower_lanes) < need)) && v != 0xFFFFFFFFu;
+        // the candidate buffer serves as the bound buffer (emptied again
+        // before phase 2); entries beyond its capacity are dropped, which
+        // only loosens the bound
+        const uint64_t bal = __ballot(e);
+        uint32_t base = 0;
+        if (lane == 0 && bal) base = atomicAdd(&a.ccount[q], (uint32_t)__popcll(bal));
+        base = (uint32_t)__shfl((int)base, 0);
+        const uint32_t pos = base + (uint32_t)__popcll(bal & lower_lanes);
+        if (e && pos < a.capq) {
+          uint64_t key;
+          if constexpr (FP) key = (uint64_t)v;
+          else key = ikey(pbase[g] + ((int64_t)v << ps[g]));
+          a.ckey[(size_t)q * a.capq + pos] = key;
+        }
+      }
+    } else if (PHASE == 1) {
+      // k > 64: the k-th smallest of the workgroup's per-thread minima
+      // (bitonic sort over a power-of-two row, padded with the largest key)
+      constexpr int TP = kThreadsP2;
+      __syncthreads();  // the LUT space is reused below
+      uint32_t* lm = reinterpret_cast<uint32_t*>(lds + L.lmin);
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        lm[g * TP + tid] = lmin[g];
+        if (tid + kThreads < TP) lm[g * TP + kThreads + tid] = 0xFFFFFFFFu;
+      }
+      __syncthreads();
+      for (int size = 2; size <= TP; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+          for (int i = tid; i < G * (TP / 2); i += kThreads) {
+            const int g = i / (TP / 2), ii = i % (TP / 2);
+            const int pos = 2 * ii - (ii & (stride - 1));
+            const bool asc = (pos & size) == 0;
+            uint32_t* arr = lm + g * TP;
+            const uint32_t x0 = arr[pos], x1 = arr[pos + stride];
+            if ((x0 > x1) == asc) { arr[pos] = x1; arr[pos + stride] = x0; }
+          }
+          __syncthreads();
+        }
+      // the k smallest of each pair's minima to its query's bound buffer
+      for (int i = tid; i < np_u * TP; i += kThreads) {
+        const int g = i / TP, r = i % TP;
+        const int q = pq[g];
+        const int kk = a.kq ? a.kq[q] : a.kconst;
+        const uint32_t val = lm[g * TP + r];
+        if (r < kk && val != 0xFFFFFFFFu) {
+          const uint32_t pos = atomicAdd(&a.ccount[q], 1u);
+          if (pos < a.capq) {
+            uint64_t key;
+            if constexpr (FP) key = (uint64_t)val;
+            else key = ikey(pbase[g] + ((int64_t)val << ps[g]));
+            a.ckey[(size_t)q * a.capq + pos] = key;
+          }
+        }
+      }
+    }
+}
+
+// persistent scan of one lane class: workgroups claim units of their class
+// from a device counter; the next unit is claimed while the current one is
+// processed (index at the start, descriptor before the scan, published at
+// the end)
+template <int LWB, int MT, int PHASE, int DT, int NR>
+__global__ __launch_bounds__(kThreads, 2) void k_scan(ScanArgs a) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  constexpr int WPR = variant_wpr(MT, NR);
+  constexpr bool FP = LWB == 0;
+  constexpr int G = WPR * Lane<LWB>::W;
+  constexpr bool CRES = FP && MT != 0 && MT <= 16;
+  const int M = MT ? MT : a.M;
+  const ScanLds L = scan_lds_layout(G, WPR, M, a.d, FP, PHASE);
+  if (__builtin_amdgcn_groupstaticsize() != 0) {  // the LUT must start at LDS address 0
+    if (threadIdx.x == 0) atomicOr(&a.flags[0], 16);
+    return;
+  }
+  if (PHASE == 3 && *a.any_retry == 0) return;  // re-run of phase 2 with nothing to do
+  int& s_u = *reinterpret_cast<int*>(lds + L.ctl);
+  int4& s_unit = *reinterpret_cast<int4*>(lds + L.ctl + 16);
+  const int tid = threadIdx.x;
+  const int64_t ub = a.unitoff[(size_t)a.cls * a.nlist];
+  const int64_t ue = a.unitoff[(size_t)(a.cls + 1) * a.nlist];
+  const int own_j = tid % kKsub, own_m0 = tid / kKsub;
+  const bool owner = tid < kMPar * kKsub;
+  Owned<WPR, CRES ? MT : 0> own;
+  if constexpr (CRES) {
+#pragma unroll
+    for (int i = 0; i < MT / kMPar; ++i)
+#pragma unroll
+      for (int t = 0; t < kMaxDsub; ++t)
+        own.c[i][t] = owner && t < a.dsub
+                          ? a.codebook[((size_t)(kMPar * i + own_m0) * kKsub + own_j) * a.dsub + t] : 0.f;
+  }
+  UnitQueue uq(a.counter, ue - ub, a.steal);
+  if (tid == 0) {
+    const int64_t uu = uq.next();
+    s_u = (int)uu;
+    if (ub + uu < ue) s_unit = a.units[ub + uu];
+  }
+  if (tid == 0)
+    for (int i = 0; i < 3; ++i) reinterpret_cast<uint64_t*>(lds + L.ctl + 32)[i] = 0;
+  __syncthreads();
+  for (;;) {
+    if (ub + s_u >= ue) break;
+    int next_u = 0;
+    int4 next_unit = make_int4(0, 0, 0, 0);
+    if (tid == 0) next_u = (int)uq.next();
+    scan_unit<LWB, MT, PHASE, DT, NR>(a, lds, L, own, s_unit, [&] {
+      if (tid == 0 && ub + next_u < ue) next_unit = a.units[ub + next_u];
+    });
+    __syncthreads();
+    if (tid == 0) {
+      s_u = next_u;
+      s_unit = next_unit;
+    }
+    __syncthreads();
+  }
+  if (PHASE == 2 && tid == 0 && a.work)
+    for (int i = 0; i < 3; ++i)
+      atomicAdd((unsigned long long*)&a.work[i],
+                (unsigned long long)reinterpret_cast<const uint64_t*>(lds + L.ctl + 32)[i]);
+}
+
+// all three lane classes of an integer policy in one persistent launch, in
+// the order 32-bit, 16-bit, 8-bit units (each largest list first): the few
+// wide units start early and the many 8-bit units fill the tail.  The LDS
+// tile of the 8-bit class (the most pairs per unit) serves every class.
+template <int MT, int PHASE, int DT, int NR>
+__global__ __launch_bounds__(kThreads, 2) void k_scan_mix(ScanArgs a) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  constexpr int WPR = variant_wpr(MT, NR);
+  const int M = MT ? MT : a.M;
+  const ScanLds L = scan_lds_layout(WPR * Lane<8>::W, WPR, M, a.d, false, PHASE);
+  if (__builtin_amdgcn_groupstaticsize() != 0) {  // the LUT must start at LDS address 0
+    if (threadIdx.x == 0) atomicOr(&a.flags[0], 16);
+    return;
+  }
+  if (PHASE == 3 && *a.any_retry == 0) return;  // re-run of phase 2 with nothing to do
+  int& s_u = *reinterpret_cast<int*>(lds + L.ctl);
+  int& s_cls = *reinterpret_cast<int*>(lds + L.ctl + 4);
+  int4& s_unit = *reinterpret_cast<int4*>(lds + L.ctl + 16);
+  const int tid = threadIdx.x;
+  const int64_t* uo = a.unitoff;
+  const int64_t n2 = uo[3 * (size_t)a.nlist] - uo[2 * (size_t)a.nlist];
+  const int64_t n1 = uo[2 * (size_t)a.nlist] - uo[a.nlist];
+  const int64_t total = uo[3 * (size_t)a.nlist] - uo[0];
+  // unit number in launch order -> (class, row of the class-major unit table)
+  auto locate = [&](int64_t u, int& cls) -> int64_t {
+    if (u < n2) { cls = 2; return uo[2 * (size_t)a.nlist] + u; }
+    if (u < n2 + n1) { cls = 1; return uo[a.nlist] + (u - n2); }
+    cls = 0;
+    return uo[0] + (u - n2 - n1);
+  };
+  Owned<WPR, 0> own;
+  UnitQueue uq(a.counter, total, a.steal);
+  if (tid == 0) {
+    const int uu = (int)uq.next();
+    s_u = uu;
+    if (uu < total) {
+      int c;
+      s_unit = a.units[locate(uu, c)];
+      s_cls = c;
+    }
+  }
+  if (tid == 0)
+    for (int i = 0; i < 3; ++i) reinterpret_cast<uint64_t*>(lds + L.ctl + 32)[i] = 0;
+  __syncthreads();
+  for (;;) {
+    if (s_u >= total) break;
+    int next_u = 0, next_cls = 0;
+    int4 next_unit = make_int4(0, 0, 0, 0);
+    if (tid == 0) next_u = (int)uq.next();
+    auto fetch = [&] {
+      if (tid == 0 && next_u < total) next_unit = a.units[locate(next_u, next_cls)];
+    };
+    const int cls = s_cls;
+    if (cls == 0) scan_unit<8, MT, PHASE, DT, NR>(a, lds, L, own, s_unit, fetch);
+    else if (cls == 1) scan_unit<16, MT, PHASE, DT, NR>(a, lds, L, own, s_unit, fetch);
+    else scan_unit<32, MT, PHASE, DT, NR>(a, lds, L, own, s_unit, fetch);
+    __syncthreads();
+    if (tid == 0) {
+      s_u = next_u;
+      s_unit = next_unit;
+      s_cls = next_cls;
+    }
+    __syncthreads();
+  }
+  if (PHASE == 2 && tid == 0 && a.work)
+    for (int i = 0; i < 3; ++i)
+      atomicAdd((unsigned long long*)&a.work[i],
+                (unsigned long long)reinterpret_cast<const uint64_t*>(lds + L.ctl + 32)[i]);
+}
+
+// LC matrix dtype of an AMP_LUT_* value (0 selects BF16; the FP8 value is
+// rejected before a search launches)
+inline int dt_of(int lut_dtype) {
+  return lut_dtype == AMP_LUT_F16 ? DT_F16 : DT_BF16;
+}
+
+
+// subspace count of the scan variant that runs a lane class (0: generic):
+// registers-resident variants exist for M = 8, 16, 24 with the BF16 LUT build
+// (the FP32 LUT has no LC dtype)
+// (wpr: the words per row the queue packed for; a batch too sparse to fill
+// wide rows runs the generic one-word variant, see scan_wpr)
+inline int scan_mt(int lwb, int M, int dt) {
+  if (lwb != 0 && dt != DT_BF16) return 0;
+  return (M == 8 || M == 16 || M == 24) ? M : 0;
+}
+// one-word rows on a specialised variant
+inline int scan_nr(int mt, int wpr) { return (wpr == 1 && kernel_wpr(mt) != 1) ? 1 : 0; }
+
+
+typedef void (*ScanFn)(ScanArgs);
+// the kernel of a lane class (lwb 0 = FP32 LUT, 8/16/32) or, with lwb < 0,
+// the mixed-class kernel, for one phase; nullptr if none fits
+ScanFn pick_scan_ph1(int lwb, int M, int dt, int wpr);
+ScanFn pick_scan_ph2(int lwb, int M, int dt, int wpr);
+ScanFn pick_scan_ph3(int lwb, int M, int dt, int wpr);
+
+}  // namespace amp
