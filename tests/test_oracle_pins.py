@@ -232,6 +232,39 @@ def test_mitchell_log2_hand_worked_and_bounds():
     assert np.all(np.diff(oracle.mitchell_log2_q8(xs)) >= 0)
 
 
+def _worked_model(g):
+    m = dict(g["model"])
+    assert m.pop("table_rule") == "1024 - i"
+    m["table"] = np.array([1024 - i for i in range(1024)], dtype=np.int64)
+    m["sv"] = np.asarray(m["sv"], dtype=np.int64)
+    m["beta"] = np.asarray(m["beta"], dtype=np.int64)
+    m["n_sv"] = len(m["beta"])
+    return m
+
+
+def test_predictor_hand_worked_fixture():
+    """Features, C1 choice, affine map with clamps, table-read RBF score and
+    width choice (thresholds inclusive, margin, allowed sets with and without
+    12 bits) against the hand-worked values of tests/golden/predictor_worked.json."""
+    g = _gold("predictor_worked.json")
+    m = _worked_model(g)
+    for x, L in g["log2_q8"].items():
+        assert int(oracle.mitchell_log2_q8(np.array([int(x)]))[0]) == L
+    P = np.asarray(g["probes"])
+    dq2 = np.asarray(g["dq2"])
+    radq, sizes = np.asarray(g["radq"]), np.asarray(g["sizes"])
+    c1 = g["c1"]
+    for i, p in enumerate(P.tolist()):
+        x = [int(dq2[i]), int(radq[c1]), int(radq[p]), int(sizes[c1]), int(sizes[p])]
+        u = oracle.feature_u(x, m)
+        assert u.tolist() == g["u"][i]
+        assert oracle.svr_eval(u, m) == g["score"][i]
+    for case in g["cases"]:
+        bits, ys = oracle.predict_pair_bits(dq2, P, radq, sizes, m, case["allowed"], case["margin"])
+        assert bits.tolist() == case["bits"], case
+        assert [int(y) for y in ys] == g["score"]
+
+
 def _lin_model(n_sv=64, gamma=1.0, seed=0):
     return random_model(seed, n_sv, feat_lo=[0] * 5, feat_mul=[1 << 12] * 5, gamma=gamma)
 
@@ -375,6 +408,93 @@ def test_lossless_index_recovers_exact_l1_knn():
     assert np.array_equal(r16["qdist"], d1.astype(np.int64))
     r32 = oracle.search(idx, Q, 10, 6, policy="fp32")
     assert np.array_equal(r32["ids"], truth)
+
+
+def test_lossless_index_recovers_exact_inner_product_knn():
+    """Special case for the inner-product metric: integer queries, base
+    vectors exactly centroid + codewords, every list probed at 16 bits: the
+    integer estimate is -<q, x> exactly (s = 0) and the ids are the exact
+    inner-product neighbours; the full-precision policy returns the same ids."""
+    idx, base = lossless_index(seed=9, nlist=6, M=4, dsub=4, per_list=[40, 3, 77, 0, 12, 60])
+    idx = dict(idx, metric="ip")
+    Q = np.random.default_rng(15).integers(-40, 41, size=(8, 16)).astype(np.float32)
+    truth = oracle.exact_knn(base, Q, 10, "ip")
+    r16 = oracle.search(idx, Q, 10, 6, policy="fixed", bits=16)
+    assert (r16["shift"] == 0).all()
+    assert np.array_equal(r16["ids"], truth)
+    ip = (base[truth].astype(np.float64) * Q[:, None, :]).sum(-1)
+    assert np.array_equal(r16["qdist"], -ip.astype(np.int64))
+    r32 = oracle.search(idx, Q, 10, 6, policy="fp32")
+    assert np.array_equal(r32["ids"], truth)
+    assert np.array_equal(r32["dist"], (-ip).astype(np.float32))
+
+
+def test_full_precision_inner_product_adc_equals_reconstruction_score():
+    """Inner product: the full-precision LUT sum plus the list term -<q, c> is
+    -<q, x_hat> with x_hat = c + concat cb(code), to FP64 rounding."""
+    r = np.random.default_rng(16)
+    M, dsub, d = 8, 4, 32
+    CB = r.normal(size=(M, 256, dsub)).astype(np.float32)
+    c = r.normal(size=d).astype(np.float32) * 5
+    for _ in range(20):
+        q = r.normal(size=d).astype(np.float32) * 5
+        code = r.integers(0, 256, size=M)
+        T = oracle.lut_f64(q, CB, "ip")
+        add = -float(q.astype(np.float64) @ c.astype(np.float64))
+        adc = add + float(sum(T[m, code[m]] for m in range(M)))
+        xhat = c.astype(np.float64) + np.concatenate([CB[m, code[m]] for m in range(M)]).astype(np.float64)
+        direct = -float(q.astype(np.float64) @ xhat)
+        scale = float(np.abs(q.astype(np.float64)) @ np.abs(xhat))
+        assert abs(adc - direct) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("e", [1, -1])
+def test_lossless_index_on_a_power_of_two_grid_step(e):
+    """index_grid and the grid exponent: centroids, codewords and queries are
+    multiples of h = 2^e, so every residual and codeword maps to the grid
+    exactly; the 16-bit search then returns the exact neighbours with integer
+    estimates D / h^2 and reported distances D (L2 and inner product)."""
+    h = 2.0 ** e
+    idx0, base0 = lossless_index(seed=6, nlist=5, M=4, dsub=4, per_list=[30, 8, 0, 50, 21],
+                                 cb_range=6, c_range=30)
+    idx = dict(idx0, grid_e=e, centroids=(idx0["centroids"] * h).astype(np.float32),
+               codebook=(idx0["codebook"] * h).astype(np.float32))
+    base = (base0 * h).astype(np.float32)
+    cbi, ci = oracle.index_grid(idx)
+    assert np.array_equal(cbi, idx0["codebook"].astype(np.int64))
+    assert np.array_equal(ci, idx0["centroids"].astype(np.int64))
+    Q = (np.random.default_rng(17).integers(-30, 31, size=(6, 16)) * h).astype(np.float32)
+    for metric in ("l2", "ip"):
+        im = dict(idx, metric=metric)
+        truth = oracle.exact_knn(base, Q, 8, metric)
+        res = oracle.search(im, Q, 8, 5, policy="fixed", bits=16)
+        assert (res["shift"] == 0).all()
+        assert np.array_equal(res["ids"], truth)
+        X = base[truth].astype(np.float64)
+        D = ((X - Q[:, None, :]) ** 2).sum(-1) if metric == "l2" else -(X * Q[:, None, :]).sum(-1)
+        assert np.array_equal(res["qdist"].astype(np.float64) * h * h, D)
+        assert np.array_equal(res["dist"], D.astype(np.float32))
+
+
+@pytest.mark.parametrize("metric", ["l2", "ip", "l1"])
+def test_exact_knn_matches_a_python_sort_with_ties(metric):
+    """Brute force: exact_knn equals Python's sort of (distance, id) over every
+    vector, with duplicated vectors so that ties must go to the lower id."""
+    r = np.random.default_rng(18)
+    B = r.integers(-3, 4, size=(60, 5)).astype(np.float32)
+    B[30:45] = B[0:15]  # exact duplicates: equal distances at different ids
+    Q = r.integers(-3, 4, size=(7, 5)).astype(np.float32)
+    got = oracle.exact_knn(B, Q, 12, metric)
+    for i, q in enumerate(Q):
+        def dist(x):
+            if metric == "l2":
+                return sum((float(a) - float(b)) ** 2 for a, b in zip(x, q))
+            if metric == "l1":
+                return sum(abs(float(a) - float(b)) for a, b in zip(x, q))
+            return -sum(float(a) * float(b) for a, b in zip(x, q))
+        want = [j for _, j in sorted((dist(B[j]), j) for j in range(len(B)))][:12]
+        assert got[i].tolist() == want
+    assert oracle.exact_knn(B[:5], Q[:2], 8, metric)[:, 5:].tolist() == [[-1] * 3] * 2
 
 
 @pytest.mark.slow
