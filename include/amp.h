@@ -159,21 +159,57 @@ typedef struct amp_precision_policy {
  * uint16); BF16 rows are widened to FP32 on the device (exact) as the first
  * step of the search, so a BF16 query searches exactly as the FP32 query of
  * the same value.
- * Per-query k / nprobe arrays are staged through pinned memory: the call does
- * not wait for earlier searches on the stream, and the caller may reuse the
- * arrays when it returns.
+ * Per-query k / nprobe host arrays are staged through pinned memory: the
+ * call does not wait for earlier searches on the stream, and the caller may
+ * reuse the arrays when it returns.
  * work (host, [3] int64, optional): work of the full scan (phase 2): code
  * bytes scanned summed over the live (query, list) pairs, live pairs, pairs
  * skipped whole because their LUT base exceeds the query's bound; forces a
  * synchronisation at the end (not with AMP_SEARCH_GRAPH).
+ * out_status (optional, int32, same memory space as the outputs; device mode
+ * also accepts pinned host memory): the status of the search as the device
+ * saw it, written when the stream reaches the end of the call: AMP_OK,
+ * AMP_EOVERFLOW (a query's candidates still overflowed its buffer after the
+ * re-runs, or the work-unit table overflowed: results may miss candidates),
+ * AMP_EINVAL (an AMP_SEARCH_DEVICE_SIZES entry was out of range: it was
+ * clamped into range) or AMP_EDEVICE (internal error).  In host mode the
+ * return value carries the same status.
+ * kmax, npmax: with AMP_SEARCH_DEVICE_SIZES, the bounds of the device k and
+ * nprobe entries (they size the outputs: [nq][kmax], [nq][npmax]).
+ * lut_export (test hook, optional, device mode, integer policies, not with
+ * AMP_SEARCH_GRAPH): the quantised LUT of every (query, probe rank) pair
+ * as the scan built it, for the replay check of the integer stages:
+ *   q     [nq][npmax][M][256] uint16  entries Q (after the shift)
+ *   shift [nq][npmax] int32           shift s of the pair
+ *   base  [nq][npmax] int64           base (sum of the subspace minima; inner
+ *                                     product: with the -qi.ci term)
+ * Rows of probe ranks at or beyond a query's nprobe are left unwritten.  The
+ * export runs a second, separate LUT build pass after the search (the search
+ * itself is unchanged).
  */
 #define AMP_N_STAGES 8
 #define AMP_SEARCH_GRAPH 1u  /* flags: capture the search as a HIP graph once
                                 and replay it while queries/outputs pointers,
                                 sizes, policy and stream are unchanged (device
-                                mode, a created stream, constant k and
-                                nprobe, no stage_ms, not EXPLICIT).  Replays
-                                read the query buffer's current contents. */
+                                mode, a created stream, constant k and nprobe
+                                or AMP_SEARCH_DEVICE_SIZES, no stage_ms, not
+                                EXPLICIT).  Replays read the current contents
+                                of the query buffer (and of the device k /
+                                nprobe arrays). */
+#define AMP_SEARCH_DEVICE_SIZES 2u  /* flags: k and nprobe point to device
+                                arrays of nq int32 (per_query must be 1,
+                                device mode); opts.kmax / opts.npmax bound
+                                them.  Entries outside [1, kmax] / [1, npmax]
+                                are clamped and reported through out_status
+                                (AMP_EINVAL).  The search reads the arrays
+                                on the stream, so a captured graph may be
+                                replayed with new per-query sizes. */
+typedef struct amp_lut_export {
+  uint16_t* q;
+  int32_t* shift;
+  int64_t* base;
+} amp_lut_export;
+
 typedef struct amp_search_opts {
   int32_t mem;
   void* stream;
@@ -185,6 +221,9 @@ typedef struct amp_search_opts {
   uint32_t flags;
   int32_t q_dtype;
   int64_t* work;
+  int32_t* out_status;
+  int32_t kmax, npmax;
+  const amp_lut_export* lut_export;
 } amp_search_opts;
 
 /* Build an index handle from arrays (copied).  Validates every constraint
@@ -368,19 +407,27 @@ amp_status amp_search(amp_index* index, const void* queries, int64_t nq,
  * pool rejects with AMP_EBUSY.  A worker thread gathers queued requests of
  * one precision policy (the oldest request's) into batches of at most
  * max_batch queries and runs each as one device-mode search with per-query k
- * and nprobe on a stream of its own; two batches may be in flight.  An idle
- * device waits up to batch_window_us after the oldest request's arrival for
- * a batch to fill (0: launch at once).  Results are the same as amp_search
- * of that query alone.
+ * and nprobe.  Two batches may be in flight, each on an execution slot of its
+ * own (a stream of default priority, search scratch, staging), so that their
+ * searches overlap on the device.  A batch is padded to a size bucket (powers
+ * of two up to 128, then multiples of 128) and its search replays a HIP graph
+ * captured once per (slot, bucket, policy), the per-query k and nprobe
+ * uploaded to the device with the queries.  An idle device waits up to
+ * batch_window_us after the oldest request's arrival for a batch to fill (0:
+ * launch at once).  Results are the same as amp_search of that query alone; a
+ * batch whose search reports an error on the device (AMP_EOVERFLOW: a
+ * query's candidate buffer overflowed) completes its requests with that
+ * status.
  *   max_batch    1..65536 (0 = 1024)       max_pending 1..2^22 (0 = 4*max_batch)
  *   max_k        1..1024 (0 = 100)         max_nprobe  1..min(nlist, 256) (0 = that)
  *   q_dtype      AMP_F32 or AMP_BF16 query rows
  *   policy       default of requests that name none (not EXPLICIT)
- * Pinned host memory: (max_pending + 2*max_batch) * d * sizeof(row element)
- * + 2 * max_batch * max_k * 20 bytes; device memory the same staging plus the
- * index's search scratch, reserved at creation for the largest batch.
- * The index must outlive the server; other searches on it are allowed (they
- * serialise on its scratch space).
+ * Pinned host memory, with B the largest bucket (max_batch rounded up to its
+ * bucket): max_pending * d * sizeof(row element) + 2 * B * (d * sizeof(row
+ * element) + 8 + max_k * 20) bytes; device memory the same staging plus two
+ * search workspaces reserved at creation for B queries, max_nprobe probes and
+ * max_k results.  The index must outlive the server; other searches on it
+ * are allowed (they use the index's own scratch space).
  */
 typedef struct amp_server amp_server;
 

@@ -57,12 +57,19 @@ class _Policy(C.Structure):
 
 
 AMP_SEARCH_GRAPH = 1
+AMP_SEARCH_DEVICE_SIZES = 2
+
+
+class _LutExport(C.Structure):
+    _fields_ = [("q", C.c_void_p), ("shift", C.c_void_p), ("base", C.c_void_p)]
 
 
 class _Opts(C.Structure):
     _fields_ = [("mem", C.c_int32), ("stream", C.c_void_p), ("out_qdist", C.c_void_p),
                 ("out_probes", C.c_void_p), ("out_bits", C.c_void_p), ("out_coarse", C.c_void_p),
-                ("stage_ms", C.c_void_p), ("flags", C.c_uint32), ("q_dtype", C.c_int32), ("work", C.c_void_p)]
+                ("stage_ms", C.c_void_p), ("flags", C.c_uint32), ("q_dtype", C.c_int32), ("work", C.c_void_p),
+                ("out_status", C.c_void_p), ("kmax", C.c_int32), ("npmax", C.c_int32),
+                ("lut_export", C.POINTER(_LutExport))]
 
 
 class _BuildParams(C.Structure):
@@ -369,38 +376,58 @@ def make_policy(policy="fixed", bits=16, allowed=(4, 8, 12, 16), margin_q40=0,
 def amp_search(index, queries, k, nprobe, policy="fixed", bits=16, allowed=(4, 8, 12, 16),
                margin_q40=0, explicit_bits=None, lut_dtype=0, want_qdist=True,
                want_probes=False, want_bits=False, want_coarse=False, stage_ms=False,
-               out=None, stream=None, graph=False, q_dtype=None, work=False):
+               out=None, stream=None, graph=False, q_dtype=None, work=False, kmax=None, npmax=None,
+               want_status=False, _entry="amp_search"):
     """Search a batch.
 
     Host mode (``queries`` a numpy array): returns a dict of numpy arrays.
     Device mode (``queries`` a torch CUDA tensor): ``out`` must be a dict of
     preallocated torch CUDA tensors ids [nq,kmax] int64, dist [nq,kmax] float32
-    and optionally qdist / probes / bits / coarse; work is enqueued on
-    ``stream`` (a torch stream or raw handle) and the call returns at once.
+    and optionally qdist / probes / bits / coarse / status (int32 [1]) /
+    lut_q, lut_shift, lut_base (the LUT export test hook); work is enqueued
+    on ``stream`` (a torch stream or raw handle) and the call returns at once.
+    Device mode also takes ``k`` / ``nprobe`` as int32 CUDA tensors of nq
+    entries (device-resident per-query sizes, bounded by ``kmax`` / ``npmax``).
     """
     device = hasattr(queries, "data_ptr")
     nq = int(queries.shape[0])
     if q_dtype is None:
         q_dtype = "bf16" if str(getattr(queries, "dtype", "")) in ("uint16", "torch.bfloat16") else "f32"
     qd = AMP_BF16 if q_dtype == "bf16" else AMP_F32
-    kk = np.atleast_1d(np.asarray(k, dtype=np.int32))
-    npb = np.atleast_1d(np.asarray(nprobe, dtype=np.int32))
-    per_query = int(kk.size > 1 or npb.size > 1)
-    if per_query:
-        kk = np.ascontiguousarray(np.broadcast_to(kk, (nq,)), dtype=np.int32)
-        npb = np.ascontiguousarray(np.broadcast_to(npb, (nq,)), dtype=np.int32)
-    kmax, npmax = int(kk.max()), int(npb.max())
+    flags = AMP_SEARCH_GRAPH if graph else 0
+    dev_sizes = hasattr(k, "data_ptr") or hasattr(nprobe, "data_ptr")
+    if dev_sizes:
+        if not (hasattr(k, "data_ptr") and hasattr(nprobe, "data_ptr")) or kmax is None or npmax is None:
+            raise ValueError("device-resident sizes need both k and nprobe as device tensors and kmax / npmax")
+        if tuple(k.shape) != (nq,) or tuple(nprobe.shape) != (nq,):
+            raise ValueError("device k / nprobe must hold one entry per query")
+        kk, npb, per_query = k, nprobe, 1
+        kmax, npmax = int(kmax), int(npmax)
+        flags |= AMP_SEARCH_DEVICE_SIZES
+    else:
+        kk = np.atleast_1d(np.asarray(k, dtype=np.int32))
+        npb = np.atleast_1d(np.asarray(nprobe, dtype=np.int32))
+        per_query = int(kk.size > 1 or npb.size > 1)
+        if per_query:
+            kk = np.ascontiguousarray(np.broadcast_to(kk, (nq,)), dtype=np.int32)
+            npb = np.ascontiguousarray(np.broadcast_to(npb, (nq,)), dtype=np.int32)
+        kmax, npmax = int(kk.max()), int(npb.max())
     pol, xb = make_policy(policy, bits, allowed, margin_q40, explicit_bits, lut_dtype)
     ms = np.zeros(AMP_N_STAGES, dtype=np.float32) if stage_ms else None
     wk = np.zeros(3, dtype=np.int64) if work else None
+    fn = getattr(lib(), _entry)
     if device:
         o = out
         sh = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+        exp = None
+        if o.get("lut_q") is not None:
+            exp = _LutExport(_ptr(o["lut_q"]), _ptr(o["lut_shift"]), _ptr(o["lut_base"]))
         opts = _Opts(AMP_MEM_DEVICE, C.c_void_p(sh) if sh else None, _ptr(o.get("qdist")),
                      _ptr(o.get("probes")), _ptr(o.get("bits")), _ptr(o.get("coarse")), _ptr(ms),
-                     AMP_SEARCH_GRAPH if graph else 0, qd, _ptr(wk))
-        _check(lib().amp_search(index.handle, _ptr(queries), nq, _ptr(kk), _ptr(npb), per_query,
-                                C.byref(pol), C.byref(opts), _ptr(o["ids"]), _ptr(o["dist"])))
+                     flags, qd, _ptr(wk), _ptr(o.get("status")), kmax if dev_sizes else 0,
+                     npmax if dev_sizes else 0, C.pointer(exp) if exp is not None else None)
+        _check(fn(index.handle, _ptr(queries), nq, _ptr(kk), _ptr(npb), per_query,
+                  C.byref(pol), C.byref(opts), _ptr(o["ids"]), _ptr(o["dist"])))
         if stage_ms:
             o["stage_ms"] = dict(zip(STAGES, ms.tolist()))
         if work:
@@ -417,11 +444,18 @@ def amp_search(index, queries, k, nprobe, policy="fixed", bits=16, allowed=(4, 8
     if want_coarse:
         info = amp_index_info(index)
         res["coarse"] = np.empty((nq, info["nlist"]), np.float32)
+    st = np.zeros(1, np.int32) if want_status else None
     opts = _Opts(AMP_MEM_HOST, None, _ptr(res.get("qdist")), _ptr(res.get("probes")),
-                 _ptr(res.get("bits")), _ptr(res.get("coarse")), _ptr(ms),
-                 AMP_SEARCH_GRAPH if graph else 0, qd, _ptr(wk))
-    _check(lib().amp_search(index.handle, _ptr(q), nq, _ptr(kk), _ptr(npb), per_query,
-                            C.byref(pol), C.byref(opts), _ptr(res["ids"]), _ptr(res["dist"])))
+                 _ptr(res.get("bits")), _ptr(res.get("coarse")), _ptr(ms), flags, qd, _ptr(wk), _ptr(st), 0, 0,
+                 None)
+    status = fn(index.handle, _ptr(q), nq, _ptr(kk), _ptr(npb), per_query,
+                C.byref(pol), C.byref(opts), _ptr(res["ids"]), _ptr(res["dist"]))
+    if want_status:
+        res["status"] = int(status)
+        if status not in (AMP_OK, AMP_EOVERFLOW):
+            _check(status)
+    else:
+        _check(status)
     if stage_ms:
         res["stage_ms"] = dict(zip(STAGES, ms.tolist()))
     if work:

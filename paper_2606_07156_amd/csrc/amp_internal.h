@@ -62,13 +62,52 @@ struct DeviceIndex {
   int64_t* offsets = nullptr;  // [nlist+1]
   int32_t* radq = nullptr;     // [nlist]
   DeviceModel model;
-  hipEvent_t ev_done = nullptr;  // end of the last search on this index
 };
 
-// Scratch of one search, grown on demand and kept with the index.
+// what a captured search graph depends on
+struct GraphKey {
+  const void* q;
+  const void *ids, *dist, *qdist, *probes, *bits, *coarse, *status;
+  const void *kptr, *npptr;  // device per-query sizes (AMP_SEARCH_DEVICE_SIZES) or null
+  void* stream;
+  int64_t nq;
+  int32_t k, nprobe, kind, fixed_bits;
+  uint32_t allowed;
+  int64_t margin;
+  int32_t lut_dtype;
+  uint64_t ws_gen, model_gen;
+  int64_t chunk, chunk1;
+  size_t capq;
+  int32_t wpr;
+  int32_t q_dtype;
+  int32_t queue;
+  bool operator==(const GraphKey& o) const {
+    return q == o.q && ids == o.ids && dist == o.dist && qdist == o.qdist && probes == o.probes &&
+           bits == o.bits && coarse == o.coarse && status == o.status && kptr == o.kptr && npptr == o.npptr &&
+           stream == o.stream && nq == o.nq && k == o.k &&
+           nprobe == o.nprobe && kind == o.kind && fixed_bits == o.fixed_bits && allowed == o.allowed &&
+           margin == o.margin && lut_dtype == o.lut_dtype && ws_gen == o.ws_gen && model_gen == o.model_gen &&
+           chunk == o.chunk && chunk1 == o.chunk1 && capq == o.capq && wpr == o.wpr &&
+           q_dtype == o.q_dtype && queue == o.queue;
+  }
+};
+struct GraphSlot {
+  GraphKey key;
+  hipGraphExec_t exec;
+  uint64_t last_use;
+};
+constexpr size_t kMaxGraphs = 32;  // captured searches kept per scratch space (least recently used go)
+
+// Scratch of one search: the index's own (grown on demand), a serving slot's
+// (reserved at server creation), or carved out of the library's fixed
+// scratch array (allocation-free entry point: never grown or freed).
 struct Workspace {
-  std::vector<void*> blocks;   // device allocations
+  std::vector<void*> blocks;   // device allocations (empty for a fixed workspace)
+  bool fixed = false;          // carved out of the fixed scratch array
   size_t cap_nq = 0, cap_np = 0, cap_k = 0;
+  uint64_t generation = 0;     // bumped whenever the buffers move
+  hipEvent_t ev_done = nullptr;  // end of the last search on this scratch (null: not tracked)
+  std::vector<GraphSlot> graphs;  // captured searches on this scratch (least recently used go)
   // per query
   float* queries = nullptr;    // [nq][d] (host-mode staging, converted BF16 queries)
   uint16_t* qraw = nullptr;    // [nq][d] BF16 queries staged from the host
@@ -97,6 +136,7 @@ struct Workspace {
   int32_t* sorted = nullptr;   // [2][nq*npmax]
   uint32_t* counters = nullptr;// [2][kNCls+1][kQueueSlot] unit counters
   int32_t* flags = nullptr;    // [4]: error bits, phase-2 re-run requested (two rounds), -
+  int32_t* status = nullptr;   // [1] device-side status word of the last search
   uint64_t* work = nullptr;    // [4]: phase-2 code bytes scanned, live pairs, dead pairs, -
   // outputs staged for host mode
   int64_t* o_ids = nullptr;
@@ -105,34 +145,6 @@ struct Workspace {
   size_t capq = 0;
 };
 
-}  // namespace amp
-
-namespace amp {
-// what a captured search graph depends on
-struct GraphKey {
-  const void* q;
-  const void *ids, *dist, *qdist, *probes, *bits, *coarse;
-  void* stream;
-  int64_t nq;
-  int32_t k, nprobe, kind, fixed_bits;
-  uint32_t allowed;
-  int64_t margin;
-  int32_t lut_dtype;
-  uint64_t ws_gen, model_gen;
-  int64_t chunk, chunk1;
-  size_t capq;
-  int32_t wpr;
-  int32_t q_dtype;
-  int32_t queue;
-  bool operator==(const GraphKey& o) const {
-    return q == o.q && ids == o.ids && dist == o.dist && qdist == o.qdist && probes == o.probes &&
-           bits == o.bits && coarse == o.coarse && stream == o.stream && nq == o.nq && k == o.k &&
-           nprobe == o.nprobe && kind == o.kind && fixed_bits == o.fixed_bits && allowed == o.allowed &&
-           margin == o.margin && lut_dtype == o.lut_dtype && ws_gen == o.ws_gen && model_gen == o.model_gen &&
-           chunk == o.chunk && chunk1 == o.chunk1 && capq == o.capq && wpr == o.wpr &&
-           q_dtype == o.q_dtype && queue == o.queue;
-  }
-};
 }  // namespace amp
 
 struct amp_index {
@@ -153,9 +165,7 @@ struct amp_index {
   amp::DeviceIndex dev;
   bool dev_model_stale = true;
   amp::Workspace ws;
-  uint64_t ws_generation = 0, model_generation = 0;
-  hipGraphExec_t graph_exec = nullptr;
-  amp::GraphKey graph_key{};
+  uint64_t model_generation = 0, graph_clock = 0;
   // search schedules chosen by the autotuner, by (policy kind, batch bucket);
   // while tuning, tune_force replaces the lookup
   std::vector<amp_tune_entry> tune;
@@ -194,6 +204,10 @@ struct SearchDims {
   int fixed_bits;
   uint32_t allowed_mask;
   int64_t margin;
+  const int32_t* k_dev;  // device per-query k / nprobe to check and copy into the
+  const int32_t* np_dev; // workspace first (AMP_SEARCH_DEVICE_SIZES), or null
+  int32_t* out_status;   // status word written at the end of the search, or null
+  int reruns;            // phase-2 re-runs of overflowed queries (2; fewer only to test overflow reporting)
 };
 
 struct ModelArgs {
@@ -222,10 +236,29 @@ hipError_t launch_assign(const float* X, int64_t n, int dd, int ld, const float*
 hipError_t launch_residual(const float* X, const int32_t* a, const float* C, int64_t n, int d, float* out,
                            hipStream_t st);
 
-// grow the index's search workspace to hold any search of at most nq queries,
-// npmax probes and k <= kmax (a caller that must not stall on a reallocation
-// while searches are in flight reserves up front); takes the index lock
-amp_status reserve_workspace(amp_index* ix, int64_t nq, int npmax, int kmax);
+// grow a search workspace (the index's own when w is null) to hold any search
+// of at most nq queries, npmax probes and k <= kmax (a caller that must not
+// stall on a reallocation while searches are in flight reserves up front);
+// takes the index lock
+amp_status reserve_workspace(amp_index* ix, int64_t nq, int npmax, int kmax, Workspace* w = nullptr);
+// free a workspace's buffers, events and graphs (not a fixed one's buffers)
+void release_workspace(Workspace& w);
+// one search on a given workspace: the index's own, a serving slot's (sized
+// beforehand by reserve_workspace), or a fixed one (never grown: a search that
+// does not fit is rejected)
+amp_status search_on(amp_index* ix, Workspace& w, const void* queries, int64_t nq, const int32_t* k,
+                     const int32_t* nprobe, int32_t per_query, const amp_precision_policy* pol,
+                     const amp_search_opts* opts, int64_t* out_ids, float* out_dist);
+// lay the buffers of a workspace out in [base, base + bytes) (device memory)
+// for searches of at most nq queries, npmax probes and k <= kmax, candidate
+// capacity capq and `units` work units per phase; returns false (nothing
+// set) if they do not fit.  Host-mode staging is left out.
+bool carve_workspace(const amp_index* ix, Workspace& w, char* base, size_t bytes, int64_t nq, int npmax, int kmax,
+                     size_t capq, int64_t units);
+// candidate capacity of a search of at most kmax results (a power of two)
+size_t plan_capq(int kmax);
+// work units per phase of a search that keeps every list whole
+inline int64_t whole_list_units(int64_t nq, int npmax) { return nq * npmax; }
 
 // LUT words per row of the scan variants a search runs (the queue packs its
 // work units to match)

@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <type_traits>
 
 #include "amp_internal.h"
 
@@ -45,7 +46,6 @@ static amp_status dalloc(T** p, size_t n, std::vector<void*>* track = nullptr) {
 }
 
 static void free_device_index(DeviceIndex& d) {
-  if (d.ev_done) hipEventDestroy(d.ev_done);
   void* ptrs[] = {d.centroids, d.cnorm, d.codebook, d.bsw, d.bsw16, d.cbi16, d.lorder, d.lpos, d.codes, d.ids,
                   d.offsets, d.radq, d.model.sv, d.model.beta, d.model.table};
   for (void* p : ptrs)
@@ -54,11 +54,17 @@ static void free_device_index(DeviceIndex& d) {
 }
 
 static void free_workspace(Workspace& w) {
+  for (GraphSlot& g : w.graphs) hipGraphExecDestroy(g.exec);
   for (void* p : w.blocks) hipFree(p);
   if (w.hstage) hipHostFree(w.hstage);
   if (w.ev_stage) hipEventDestroy(w.ev_stage);
+  if (w.ev_done) hipEventDestroy(w.ev_done);
+  const uint64_t gen = w.generation;
   w = Workspace();
+  w.generation = gen + 1;
 }
+
+void release_workspace(Workspace& w) { free_workspace(w); }
 
 }  // namespace amp
 
@@ -241,7 +247,6 @@ static amp_status to_device_locked(amp_index* ix, int device) {
     AMP_HIP(hipMemcpy(d.lorder, order.data(), nl * 4, hipMemcpyHostToDevice));
     AMP_HIP(hipMemcpy(d.lpos, pos.data(), nl * 4, hipMemcpyHostToDevice));
   }
-  AMP_HIP(hipEventCreateWithFlags(&d.ev_done, hipEventDisableTiming));
   AMP_HIP(launch_prep_index(ix, nullptr));
   AMP_HIP(hipDeviceSynchronize());
   d.device = device;
@@ -258,7 +263,11 @@ amp_status amp_index_to_device(amp_index* ix, int32_t device) {
   }
   if (device < 0 || device >= count) return set_error(AMP_EINVAL, "device %d out of range", device);
   std::lock_guard<std::mutex> lk(ix->mu);
-  return to_device_locked(ix, device);
+  amp_status s = to_device_locked(ix, device);
+  // the predictor goes up with the index (and again after a change), so that
+  // searches that must not allocate find it resident
+  if (s == AMP_OK && ix->has_model && ix->dev_model_stale) s = upload_model(ix);
+  return s;
 }
 
 amp_status amp_index_info(const amp_index* ix, int32_t* d, int32_t* M, int32_t* nlist, int64_t* n) {
@@ -273,7 +282,6 @@ amp_status amp_index_info(const amp_index* ix, int32_t* d, int32_t* M, int32_t* 
 void amp_index_free(amp_index* ix) {
   if (!ix) return;
   if (ix->dev.device >= 0) hipSetDevice(ix->dev.device);
-  if (ix->graph_exec) hipGraphExecDestroy(ix->graph_exec);
   free_workspace(ix->ws);
   free_device_index(ix->dev);
   delete ix;
@@ -430,50 +438,117 @@ amp_status amp_index_load(const char* path, amp_index** out) {
 }
 
 // ------------------------------------------------------------------ search
-static amp_status ensure_workspace(amp_index* ix, size_t nq, size_t np, size_t kmax, size_t capq,
-                                   int64_t units) {
-  Workspace& w = ix->ws;
-  if (nq <= w.cap_nq && np <= w.cap_np && kmax <= w.cap_k && capq == w.capq && units <= w.cap_units)
-    return AMP_OK;
-  nq = std::max(nq, w.cap_nq);
-  np = std::max(np, w.cap_np);
-  kmax = std::max(kmax, w.cap_k);
-  units = std::max(units, w.cap_units);
-  // the scratch space may still be in use by an earlier search
-  if (ix->dev.ev_done) AMP_HIP(hipEventSynchronize(ix->dev.ev_done));
-  free_workspace(w);
+}  // extern "C"
+
+namespace amp {
+
+// the buffers of a search workspace for at most nq queries, np probes,
+// k <= kmax, candidate capacity capq and `units` work units per phase;
+// `take(&ptr, count)` hands out device memory for `count` elements (an
+// allocation, or a bump pointer into the fixed scratch).  host_io adds the
+// host-mode staging of BF16 query rows and of the outputs.
+template <class Take>
+static amp_status lay_out(const amp_index* ix, Workspace& w, size_t nq, size_t np, size_t kmax, size_t capq,
+                          int64_t units, bool host_io, Take&& take) {
   const size_t NB = (size_t)kNCls * ix->nlist, npairs = nq * np;
-  std::vector<void*>* t = &w.blocks;
   amp_status s;
-  if ((s = dalloc(&w.queries, nq * ix->d, t)) || (s = dalloc(&w.qraw, nq * ix->d, t)) || (s = dalloc(&w.kq, nq, t)) || (s = dalloc(&w.npq, nq, t)) ||
-      (s = dalloc(&w.qnorm, nq, t)) || (s = dalloc(&w.coarse, nq * ix->nlist, t)) ||
-      (s = dalloc(&w.probes, npairs, t)) ||
-      (s = dalloc(&w.pbits, npairs, t)) || (s = dalloc(&w.xbits, npairs, t)) || (s = dalloc(&w.tau, nq, t)) || (s = dalloc(&w.retry, nq, t)) || (s = dalloc(&w.tau_id, nq, t)) ||
-      (s = dalloc(&w.ccount, nq, t)) || (s = dalloc(&w.ckey, nq * capq, t)) || (s = dalloc(&w.cid, nq * capq, t)) ||
-      (s = dalloc(&w.cnt, 2 * kQSub * NB, t)) || (s = dalloc(&w.rank, 2 * npairs, t)) ||
-      (s = dalloc(&w.units, 2 * (size_t)units, t)) || (s = dalloc(&w.pairoff, 2 * (NB + 1), t)) ||
-      (s = dalloc(&w.unitoff, 2 * (NB + 1), t)) || (s = dalloc(&w.sorted, 2 * npairs, t)) ||
-      (s = dalloc(&w.counters, 2 * (size_t)(kNCls + 1) * kQueueSlot, t)) || (s = dalloc(&w.flags, 4, t)) ||
-      (s = dalloc(&w.work, 4, t)) ||
-      (s = dalloc(&w.o_ids, nq * kmax, t)) || (s = dalloc(&w.o_dist, nq * kmax, t)) ||
-      (s = dalloc(&w.o_qdist, nq * kmax, t))) {
-    free_workspace(w);
-    return s;
+#define AMP_TAKE(ptr, n) \
+  if ((s = take(ptr, (size_t)(n))) != AMP_OK) return s
+  AMP_TAKE(&w.queries, nq * ix->d);
+  if (host_io) AMP_TAKE(&w.qraw, nq * ix->d);
+  AMP_TAKE(&w.kq, nq);
+  AMP_TAKE(&w.npq, nq);
+  AMP_TAKE(&w.qnorm, nq);
+  AMP_TAKE(&w.coarse, nq * ix->nlist);
+  AMP_TAKE(&w.probes, npairs);
+  AMP_TAKE(&w.pbits, npairs);
+  AMP_TAKE(&w.xbits, npairs);
+  AMP_TAKE(&w.tau, nq);
+  AMP_TAKE(&w.retry, nq);
+  AMP_TAKE(&w.tau_id, nq);
+  AMP_TAKE(&w.ccount, nq);
+  AMP_TAKE(&w.ckey, nq * capq);
+  AMP_TAKE(&w.cid, nq * capq);
+  AMP_TAKE(&w.cnt, 2 * kQSub * NB);
+  AMP_TAKE(&w.rank, 2 * npairs);
+  AMP_TAKE(&w.units, 2 * (size_t)units);
+  AMP_TAKE(&w.pairoff, 2 * (NB + 1));
+  AMP_TAKE(&w.unitoff, 2 * (NB + 1));
+  AMP_TAKE(&w.sorted, 2 * npairs);
+  AMP_TAKE(&w.counters, 2 * (size_t)(kNCls + 1) * kQueueSlot);
+  AMP_TAKE(&w.flags, 4);
+  AMP_TAKE(&w.status, 1);
+  AMP_TAKE(&w.work, 4);
+  if (host_io) {
+    AMP_TAKE(&w.o_ids, nq * kmax);
+    AMP_TAKE(&w.o_dist, nq * kmax);
+    AMP_TAKE(&w.o_qdist, nq * kmax);
   }
-  if (hipHostMalloc(reinterpret_cast<void**>(&w.hstage), 2 * nq * sizeof(int32_t), hipHostMallocDefault) !=
-          hipSuccess ||
-      hipEventCreateWithFlags(&w.ev_stage, hipEventDisableTiming) != hipSuccess) {
-    hipGetLastError();
-    free_workspace(w);
-    return set_error(AMP_ENOMEM, "pinned staging allocation failed");
-  }
-  ix->ws_generation++;
+#undef AMP_TAKE
   w.cap_nq = nq;
   w.cap_np = np;
   w.cap_k = kmax;
   w.capq = capq;
   w.cap_units = units;
   return AMP_OK;
+}
+
+// grow a (non-fixed) workspace; the buffers move, so captured graphs go too
+static amp_status ensure_workspace(amp_index* ix, Workspace& w, size_t nq, size_t np, size_t kmax, size_t capq,
+                                   int64_t units) {
+  if (nq <= w.cap_nq && np <= w.cap_np && kmax <= w.cap_k && capq == w.capq && units <= w.cap_units)
+    return AMP_OK;
+  if (w.fixed) return set_error(AMP_EINVAL, "search does not fit its fixed workspace");
+  nq = std::max(nq, w.cap_nq);
+  np = std::max(np, w.cap_np);
+  kmax = std::max(kmax, w.cap_k);
+  units = std::max(units, w.cap_units);
+  // the scratch space may still be in use by an earlier search
+  if (w.ev_done) AMP_HIP(hipEventSynchronize(w.ev_done));
+  free_workspace(w);
+  std::vector<void*>* t = &w.blocks;
+  auto take = [&](auto** p, size_t n) { return dalloc(p, n, t); };
+  amp_status s = lay_out(ix, w, nq, np, kmax, capq, units, true, take);
+  if (s != AMP_OK) {
+    free_workspace(w);
+    return s;
+  }
+  if (hipHostMalloc(reinterpret_cast<void**>(&w.hstage), 2 * nq * sizeof(int32_t), hipHostMallocDefault) !=
+          hipSuccess ||
+      hipEventCreateWithFlags(&w.ev_stage, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&w.ev_done, hipEventDisableTiming) != hipSuccess) {
+    hipGetLastError();
+    free_workspace(w);
+    return set_error(AMP_ENOMEM, "pinned staging allocation failed");
+  }
+  return AMP_OK;
+}
+
+bool carve_workspace(const amp_index* ix, Workspace& w, char* base, size_t bytes, int64_t nq, int npmax, int kmax,
+                     size_t capq, int64_t units) {
+  Workspace c;
+  c.fixed = true;
+  size_t off = 0;
+  auto take = [&](auto** p, size_t n) -> amp_status {
+    using E = std::remove_pointer_t<std::remove_pointer_t<decltype(p)>>;
+    const size_t at = (off + 255) & ~(size_t)255;
+    const size_t need = std::max<size_t>(1, n) * sizeof(E);
+    if (at > bytes || need > bytes - at) return AMP_ENOMEM;
+    *p = reinterpret_cast<E*>(base + at);
+    off = at + need;
+    return AMP_OK;
+  };
+  if (lay_out(ix, c, (size_t)nq, (size_t)npmax, (size_t)kmax, capq, units, false, take) != AMP_OK) return false;
+  w = c;
+  return true;
+}
+
+size_t plan_capq(int kmax) {
+  // a power of two (the merge sorts up to capq keys in place, 16 bytes each
+  // in LDS: at most 8192), at least kmax
+  size_t capq = 16;
+  while ((capq < env_size("AMP_CAPQ", 4096) || capq < (size_t)kmax) && capq < (1u << 13)) capq <<= 1;
+  return capq;
 }
 
 // capacity of the candidate buffer, list chunk lengths and the unit-table
@@ -486,10 +561,7 @@ struct SearchPlan {
 static SearchPlan plan_search(const amp_index* ix, int64_t nq, int npmax, int kmax, bool worst_case,
                               int64_t tuned_chunk = 0, int64_t tuned_chunk1 = 0) {
   SearchPlan p;
-  // candidate capacity per query: a power of two (the merge sorts up to capq
-  // keys in place, 16 bytes each in LDS: at most 8192), at least kmax
-  p.capq = 16;
-  while ((p.capq < env_size("AMP_CAPQ", 4096) || p.capq < (size_t)kmax) && p.capq < (1u << 13)) p.capq <<= 1;
+  p.capq = plan_capq(kmax);
   // list chunk of a work unit, phase 2 and the phase-1 bound.  Whole lists
   // when the batch has enough units to fill the chip (each chunk rebuilds
   // its pairs' LUTs, and a chunked phase 1 gives a looser bound); otherwise
@@ -518,24 +590,49 @@ static SearchPlan plan_search(const amp_index* ix, int64_t nq, int npmax, int km
   return p;
 }
 
-amp_status amp_search(amp_index* ix, const void* queries, int64_t nq, const int32_t* k, const int32_t* nprobe,
-                      int32_t per_query, const amp_precision_policy* pol, const amp_search_opts* opts,
-                      int64_t* out_ids, float* out_dist) {
+// status of a search from its device flags (the same mapping as k_status)
+static amp_status flags_status(int32_t f, size_t capq) {
+  if (f & 16) return set_error(AMP_EDEVICE, "internal error: scan kernel with static LDS");
+  if (f & 8) return set_error(AMP_EDEVICE, "internal error: a work unit exceeded the scan tile");
+  if (f & 32) return set_error(AMP_EINVAL, "a device k / nprobe entry was outside its bound (clamped)");
+  if (f & 4) return set_error(AMP_EOVERFLOW, "work-unit table overflowed");
+  if (f) return set_error(AMP_EOVERFLOW, "candidate buffer of %zu entries overflowed", capq);
+  return AMP_OK;
+}
+
+amp_status search_on(amp_index* ix, Workspace& w, const void* queries, int64_t nq, const int32_t* k,
+                     const int32_t* nprobe, int32_t per_query, const amp_precision_policy* pol,
+                     const amp_search_opts* opts, int64_t* out_ids, float* out_dist) {
   if (!ix || !queries || !k || !nprobe || !pol || !opts || !out_ids || !out_dist)
     return set_error(AMP_EINVAL, "null argument");
   if (nq <= 0 || nq > (1 << 24)) return set_error(AMP_EINVAL, "nq %lld out of range", (long long)nq);
   if (opts->mem != AMP_MEM_HOST && opts->mem != AMP_MEM_DEVICE) return set_error(AMP_EINVAL, "bad mem kind");
   if (opts->q_dtype != AMP_F32 && opts->q_dtype != AMP_BF16)
     return set_error(AMP_EINVAL, "bad query dtype %d", opts->q_dtype);
+  if (opts->flags & ~(AMP_SEARCH_GRAPH | AMP_SEARCH_DEVICE_SIZES))
+    return set_error(AMP_EINVAL, "unknown search flags 0x%x", opts->flags);
+  const bool host = opts->mem == AMP_MEM_HOST;
+  const bool dev_sizes = (opts->flags & AMP_SEARCH_DEVICE_SIZES) != 0;
   const int npmax_lim = std::min(ix->nlist, AMP_MAX_NPROBE);
   int kmax = 0, npmax = 0;
-  const int64_t nk = per_query ? nq : 1;
-  for (int64_t i = 0; i < nk; ++i) {
-    if (k[i] < 1 || k[i] > AMP_MAX_K) return set_error(AMP_EINVAL, "k = %d outside [1, %d]", k[i], AMP_MAX_K);
-    if (nprobe[i] < 1 || nprobe[i] > npmax_lim)
-      return set_error(AMP_EINVAL, "nprobe = %d outside [1, %d]", nprobe[i], npmax_lim);
-    kmax = std::max(kmax, k[i]);
-    npmax = std::max(npmax, nprobe[i]);
+  if (dev_sizes) {
+    if (host || !per_query)
+      return set_error(AMP_EINVAL, "AMP_SEARCH_DEVICE_SIZES needs device memory and per_query = 1");
+    if (opts->kmax < 1 || opts->kmax > AMP_MAX_K)
+      return set_error(AMP_EINVAL, "opts.kmax = %d outside [1, %d]", opts->kmax, AMP_MAX_K);
+    if (opts->npmax < 1 || opts->npmax > npmax_lim)
+      return set_error(AMP_EINVAL, "opts.npmax = %d outside [1, %d]", opts->npmax, npmax_lim);
+    kmax = opts->kmax;
+    npmax = opts->npmax;
+  } else {
+    const int64_t nk = per_query ? nq : 1;
+    for (int64_t i = 0; i < nk; ++i) {
+      if (k[i] < 1 || k[i] > AMP_MAX_K) return set_error(AMP_EINVAL, "k = %d outside [1, %d]", k[i], AMP_MAX_K);
+      if (nprobe[i] < 1 || nprobe[i] > npmax_lim)
+        return set_error(AMP_EINVAL, "nprobe = %d outside [1, %d]", nprobe[i], npmax_lim);
+      kmax = std::max(kmax, k[i]);
+      npmax = std::max(npmax, nprobe[i]);
+    }
   }
   switch (pol->kind) {
     case AMP_POLICY_FP32: break;
@@ -562,15 +659,40 @@ amp_status amp_search(amp_index* ix, const void* queries, int64_t nq, const int3
                                        "products exactly; use AMP_LUT_BF16 or AMP_LUT_F16");
   if (pol->lut_dtype != 0 && pol->lut_dtype != AMP_LUT_BF16 && pol->lut_dtype != AMP_LUT_F16)
     return set_error(AMP_EINVAL, "bad LUT build dtype %d", pol->lut_dtype);
+  const bool use_graph = (opts->flags & AMP_SEARCH_GRAPH) != 0;
+  if (use_graph && (host || (per_query && !dev_sizes) || opts->stage_ms || opts->work ||
+                    pol->kind == AMP_POLICY_EXPLICIT))
+    return set_error(AMP_EINVAL, "graph replay needs device memory, constant k and nprobe or device-resident "
+                                 "per-query sizes, no stage timing or work counters, and a non-explicit policy");
+  if (w.fixed) {
+    if (host) return set_error(AMP_EINVAL, "a fixed-scratch search takes device memory");
+    if (per_query && !dev_sizes)
+      return set_error(AMP_EINVAL, "a fixed-scratch search takes per-query sizes as device arrays "
+                                   "(AMP_SEARCH_DEVICE_SIZES)");
+    if (pol->kind == AMP_POLICY_EXPLICIT || use_graph || opts->stage_ms || opts->work)
+      return set_error(AMP_EINVAL, "a fixed-scratch search takes no explicit widths, graph replay, stage "
+                                   "timing or work counters");
+  }
+  const bool bf16 = opts->q_dtype == AMP_BF16;
+  if (!host && (reinterpret_cast<uintptr_t>(queries) & (bf16 ? 1 : 15)))
+    return set_error(AMP_EINVAL, "device query buffer must be %d-byte aligned", bf16 ? 2 : 16);
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) {
     hipGetLastError();
     return set_error(AMP_EDEVICE, "no HIP device");
   }
   std::lock_guard<std::mutex> lk(ix->mu);
-  amp_status s = to_device_locked(ix, dev);
-  if (s != AMP_OK) return s;
-  if (pol->kind == AMP_POLICY_ADAPTIVE && ix->dev_model_stale && (s = upload_model(ix)) != AMP_OK) return s;
+  amp_status s;
+  if (w.fixed) {
+    // nothing may be allocated: the index and its predictor must be resident
+    if (ix->dev.device != dev || !ix->dev.centroids)
+      return set_error(AMP_EINVAL, "index is not resident on device %d (amp_index_to_device first)", dev);
+    if (pol->kind == AMP_POLICY_ADAPTIVE && ix->dev_model_stale)
+      return set_error(AMP_EINVAL, "predictor changed since amp_index_to_device (call it again)");
+  } else {
+    if ((s = to_device_locked(ix, dev)) != AMP_OK) return s;
+    if (pol->kind == AMP_POLICY_ADAPTIVE && ix->dev_model_stale && (s = upload_model(ix)) != AMP_OK) return s;
+  }
   // the schedule: the autotuner's entry for this policy kind and batch size,
   // if any (results do not depend on it)
   amp_tune_entry tc{};
@@ -585,18 +707,24 @@ amp_status amp_search(amp_index* ix, const void* queries, int64_t nq, const int3
   }
   const int lut_dtype = pol->lut_dtype ? pol->lut_dtype
                                        : (pol->kind != AMP_POLICY_FP32 ? tc.lut_dtype : 0);
-  const SearchPlan plan = plan_search(ix, nq, npmax, kmax, false, tc.chunk, tc.chunk1);
+  SearchPlan plan;
+  if (w.fixed) {
+    // whole lists: the unit table then holds at most one unit per pair
+    plan.capq = w.capq;
+    plan.chunk = plan.chunk1 = std::max<int64_t>(1, ix->max_list);
+    plan.max_units = whole_list_units(nq, npmax);
+    if ((size_t)nq > w.cap_nq || (size_t)npmax > w.cap_np || (size_t)kmax > w.cap_k || w.capq < (size_t)kmax ||
+        plan.max_units > w.cap_units)
+      return set_error(AMP_EINVAL, "search does not fit its fixed workspace");
+  } else {
+    plan = plan_search(ix, nq, npmax, kmax, false, tc.chunk, tc.chunk1);
+    if ((s = ensure_workspace(ix, w, nq, npmax, kmax, plan.capq, plan.max_units)) != AMP_OK) return s;
+  }
   const size_t capq = plan.capq;
-  const int64_t chunk = plan.chunk, chunk1 = plan.chunk1, max_units = plan.max_units;
-  const bool bf16 = opts->q_dtype == AMP_BF16;
-  if (opts->mem != AMP_MEM_HOST && (reinterpret_cast<uintptr_t>(queries) & (bf16 ? 1 : 15)))
-    return set_error(AMP_EINVAL, "device query buffer must be %d-byte aligned", bf16 ? 2 : 16);
-  if ((s = ensure_workspace(ix, nq, npmax, kmax, capq, max_units)) != AMP_OK) return s;
-  Workspace& w = ix->ws;
+  const int64_t chunk = plan.chunk, chunk1 = plan.chunk1;
   hipStream_t st = reinterpret_cast<hipStream_t>(opts->stream);
-  const bool host = opts->mem == AMP_MEM_HOST;
-  // the scratch space is reused: start after the previous search on this index
-  AMP_HIP(hipStreamWaitEvent(st, ix->dev.ev_done, 0));
+  // the scratch space is reused: start after the previous search on it
+  if (w.ev_done) AMP_HIP(hipStreamWaitEvent(st, w.ev_done, 0));
   const float* qdev = static_cast<const float*>(queries);
   const uint16_t* qbf = bf16 ? static_cast<const uint16_t*>(queries) : nullptr;
   if (host) {
@@ -609,7 +737,7 @@ amp_status amp_search(amp_index* ix, const void* queries, int64_t nq, const int3
     }
   }
   if (bf16) qdev = w.queries;  // widened there by the first kernel
-  if (per_query) {
+  if (per_query && !dev_sizes) {
     // through pinned staging, so that the copy is stream-ordered and the call
     // need not wait for earlier work on the stream; the staging area is free
     // once the previous upload from it has run
@@ -664,6 +792,14 @@ amp_status amp_search(amp_index* ix, const void* queries, int64_t nq, const int3
   sd.allowed_mask = pol->allowed_bits_mask ? pol->allowed_bits_mask
                                            : ((1u << 4) | (1u << 8) | (1u << 12) | (1u << 16));
   sd.margin = pol->margin_q40;
+  sd.k_dev = dev_sizes ? k : nullptr;
+  sd.np_dev = dev_sizes ? nprobe : nullptr;
+  sd.out_status = host ? nullptr : opts->out_status;
+  // AMP_RERUNS (0..2) lowers the number of phase-2 re-runs, so that tests can
+  // force an unresolved candidate overflow
+  sd.reruns = (int)std::min<size_t>(2, env_size("AMP_RERUNS", 2));
+  if (const char* rv = getenv("AMP_RERUNS"))
+    if (rv[0] == '0') sd.reruns = 0;
   ModelArgs ma{};
   if (ix->has_model) {
     ma.n_sv = ix->n_sv;
@@ -675,17 +811,21 @@ amp_status amp_search(amp_index* ix, const void* queries, int64_t nq, const int3
     ma.g_mul = ix->g_mul;
     for (int i = 0; i < 3; ++i) ma.theta[i] = ix->theta[i];
   }
-  const bool use_graph = (opts->flags & AMP_SEARCH_GRAPH) != 0;
-  if (use_graph && (host || per_query || opts->stage_ms || opts->work || pol->kind == AMP_POLICY_EXPLICIT))
-    return set_error(AMP_EINVAL, "graph replay needs device memory, constant k and nprobe, no stage timing "
-                                 "or work counters, and a non-explicit policy");
   if (use_graph && st == nullptr)
     return set_error(AMP_EINVAL, "graph replay needs a created stream (the null stream cannot be captured)");
   hipEvent_t ev[AMP_N_STAGES + 1];
   const bool timed = opts->stage_ms != nullptr;
   if (timed)
     for (auto& e : ev) AMP_HIP(hipEventCreate(&e));
-  Workspace wv = w;  // view with per-query pointers nulled when constant
+  // a view with the per-query pointers nulled when k and nprobe are constant
+  // (the kernels then take sd.kconst / sd.npconst)
+  Workspace wv;
+  {
+    std::vector<GraphSlot> keep;
+    keep.swap(w.graphs);  // (not copied into the view)
+    wv = w;
+    keep.swap(w.graphs);
+  }
   if (!per_query) {
     wv.kq = nullptr;
     wv.npq = nullptr;
@@ -707,25 +847,40 @@ amp_status amp_search(amp_index* ix, const void* queries, int64_t nq, const int3
   };
   hipError_t he = hipSuccess;
   if (use_graph) {
-    // one captured graph per index, replayed while the launch key is unchanged
+    // captured graphs per workspace, replayed while the launch key is
+    // unchanged; the least recently used one goes when the cache is full
     GraphKey key{queries, out_ids, out_dist, opts->out_qdist, opts->out_probes, opts->out_bits, opts->out_coarse,
-                 st, nq, k[0], nprobe[0], pol->kind, pol->fixed_bits, sd.allowed_mask, pol->margin_q40,
-                 lut_dtype, ix->ws_generation, ix->model_generation, chunk, chunk1, capq, sd.wpr,
-                 opts->q_dtype, sd.queue};
-    if (!ix->graph_exec || !(ix->graph_key == key)) {
-      if (ix->graph_exec) hipGraphExecDestroy(ix->graph_exec);
-      ix->graph_exec = nullptr;
+                 opts->out_status, dev_sizes ? k : nullptr, dev_sizes ? nprobe : nullptr,
+                 st, nq, per_query ? kmax : k[0], per_query ? npmax : nprobe[0], pol->kind, pol->fixed_bits,
+                 sd.allowed_mask, pol->margin_q40, lut_dtype, w.generation, ix->model_generation, chunk, chunk1,
+                 capq, sd.wpr, opts->q_dtype, sd.queue};
+    GraphSlot* hit = nullptr;
+    for (GraphSlot& g : w.graphs)
+      if (g.key == key) hit = &g;
+    if (!hit) {
+      if (w.graphs.size() >= kMaxGraphs) {
+        auto old = std::min_element(w.graphs.begin(), w.graphs.end(),
+                                    [](const GraphSlot& a, const GraphSlot& b) { return a.last_use < b.last_use; });
+        hipGraphExecDestroy(old->exec);
+        w.graphs.erase(old);
+      }
       hipGraph_t g = nullptr;
+      hipGraphExec_t ex = nullptr;
       AMP_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
       he = enqueue(nullptr);
       hipError_t ec = hipStreamEndCapture(st, &g);
       if (he == hipSuccess) he = ec;
-      if (he == hipSuccess) he = hipGraphInstantiate(&ix->graph_exec, g, nullptr, nullptr, 0);
+      if (he == hipSuccess) he = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
       if (g) hipGraphDestroy(g);
-      if (he == hipSuccess) ix->graph_key = key;
-      else ix->graph_exec = nullptr;
+      if (he == hipSuccess) {
+        w.graphs.push_back(GraphSlot{key, ex, 0});
+        hit = &w.graphs.back();
+      }
     }
-    if (he == hipSuccess) he = hipGraphLaunch(ix->graph_exec, st);
+    if (he == hipSuccess) {
+      hit->last_use = ++ix->graph_clock;
+      he = hipGraphLaunch(hit->exec, st);
+    }
   } else {
     he = enqueue(timed ? ev : nullptr);
   }
@@ -744,7 +899,7 @@ amp_status amp_search(amp_index* ix, const void* queries, int64_t nq, const int3
       AMP_HIP(hipMemcpyAsync(opts->out_qdist, w.o_qdist, (size_t)nq * kmax * 8, hipMemcpyDeviceToHost, st));
     AMP_HIP(hipMemcpyAsync(flags, w.flags, sizeof flags, hipMemcpyDeviceToHost, st));
   }
-  AMP_HIP(hipEventRecord(ix->dev.ev_done, st));
+  if (w.ev_done) AMP_HIP(hipEventRecord(w.ev_done, st));
   if (host) AMP_HIP(hipStreamSynchronize(st));
   if (timed) {
     // stages: 0 CL, 1 top-nprobe, 2 predictor, 3 queue, 4 scan phase 1,
@@ -766,7 +921,7 @@ amp_status amp_search(amp_index* ix, const void* queries, int64_t nq, const int3
     AMP_HIP(hipMemcpy(wk, w.work, sizeof wk, hipMemcpyDeviceToHost));
     for (int i = 0; i < 3; ++i) opts->work[i] = (int64_t)wk[i];
   }
-  if (getenv("AMP_STATS")) {
+  if (getenv("AMP_STATS") && !w.fixed) {
     // debug: candidates forwarded to the merge per query
     std::vector<uint32_t> cc(nq);
     AMP_HIP(hipStreamSynchronize(st));
@@ -801,19 +956,30 @@ amp_status amp_search(amp_index* ix, const void* queries, int64_t nq, const int3
                 (long long)(U[(c + 1) * ix->nlist] - U[c * ix->nlist]), (long long)vec, (long long)maxl);
       }
   }
-  if (flags[0] & 16) return set_error(AMP_EDEVICE, "internal error: scan kernel with static LDS");
-  if (flags[0] & 8) return set_error(AMP_EDEVICE, "internal error: a work unit exceeded the scan tile");
-  if (flags[0] & 4) return set_error(AMP_EOVERFLOW, "work-unit table overflowed");
-  if (flags[0]) return set_error(AMP_EOVERFLOW, "candidate buffer of %zu entries overflowed", capq);
+  if (host) {
+    const amp_status fs = flags_status(flags[0], capq);
+    if (opts->out_status) *opts->out_status = fs;
+    return fs;
+  }
   return AMP_OK;
+}
+
+amp_status reserve_workspace(amp_index* ix, int64_t nq, int npmax, int kmax, Workspace* w) {
+  std::lock_guard<std::mutex> lk(ix->mu);
+  const SearchPlan p = plan_search(ix, nq, npmax, kmax, true);
+  return ensure_workspace(ix, w ? *w : ix->ws, nq, npmax, kmax, p.capq, p.max_units);
+}
+
+}  // namespace amp
+
+extern "C" {
+
+amp_status amp_search(amp_index* ix, const void* queries, int64_t nq, const int32_t* k, const int32_t* nprobe,
+                      int32_t per_query, const amp_precision_policy* pol, const amp_search_opts* opts,
+                      int64_t* out_ids, float* out_dist) {
+  if (!ix) return set_error(AMP_EINVAL, "null argument");
+  return search_on(ix, ix->ws, queries, nq, k, nprobe, per_query, pol, opts, out_ids, out_dist);
 }
 
 }  // extern "C"
 
-namespace amp {
-amp_status reserve_workspace(amp_index* ix, int64_t nq, int npmax, int kmax) {
-  std::lock_guard<std::mutex> lk(ix->mu);
-  const SearchPlan p = plan_search(ix, nq, npmax, kmax, true);
-  return ensure_workspace(ix, nq, npmax, kmax, p.capq, p.max_units);
-}
-}  // namespace amp

@@ -48,6 +48,34 @@ __global__ void k_reset(ResetArgs r) {
   }
 }
 
+// per-query sizes handed over in device memory: each k into [1, kmax] and
+// nprobe into [1, npmax] (flag 32 if one was outside), copied into the
+// workspace's per-query arrays
+__global__ void k_sizes(const int32_t* __restrict__ kin, const int32_t* __restrict__ npin, int32_t* __restrict__ kout,
+                        int32_t* __restrict__ npout, int nq, int kmax, int npmax, int32_t* flags) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nq) return;
+  const int kv = kin[i], nv = npin[i];
+  const int kc = kv < 1 ? 1 : (kv > kmax ? kmax : kv);
+  const int nc = nv < 1 ? 1 : (nv > npmax ? npmax : nv);
+  if (kc != kv || nc != nv) atomicOr(&flags[0], 32);
+  kout[i] = kc;
+  npout[i] = nc;
+}
+
+// status word of a search from its error flags (the host-mode mapping):
+// 16 / 8 internal errors, 32 a clamped size, 4 unit table and 2 candidate
+// overflow
+__global__ void k_status(const int32_t* __restrict__ flags, int32_t* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  const int32_t f = flags[0];
+  int32_t s = AMP_OK;
+  if (f & (16 | 8)) s = AMP_EDEVICE;
+  else if (f & 32) s = AMP_EINVAL;
+  else if (f) s = AMP_EOVERFLOW;
+  *out = s;
+}
+
 // ------------------------------------------------------------------ CL
 // squared norm of each row, FP32: one wave per row, lane-strided partial sums
 // combined by a butterfly (a fixed order for a given d)
@@ -1120,6 +1148,25 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   const size_t npairs = (size_t)sd.nq * sd.npmax;
   auto mark = [&](int i) { if (ev) (void)hipEventRecord(ev[i], st); };
   mark(0);
+  // resets, one launch (before anything that may raise a flag)
+  {
+    ResetArgs ra;
+    ra.cnt = reinterpret_cast<uint32_t*>(ws.cnt);
+    ra.ncnt = (size_t)2 * kQSub * NB;
+    ra.counters = ws.counters;
+    ra.ncounters = (size_t)2 * (kNCls + 1) * kQueueSlot;
+    ra.flags = reinterpret_cast<uint32_t*>(ws.flags);
+    ra.work = ws.work;
+    ra.tau = ws.tau;
+    ra.ccount = ws.ccount;
+    ra.nq = (size_t)sd.nq;
+    hipLaunchKernelGGL(k_reset, dim3(256), dim3(256), 0, st, ra);
+  }
+  // device-resident per-query sizes: checked, clamped and copied in
+  if (sd.k_dev) {
+    hipLaunchKernelGGL(k_sizes, dim3((sd.nq + 255) / 256), dim3(256), 0, st, sd.k_dev, sd.np_dev, ws.kq, ws.npq,
+                       sd.nq, sd.kmax, sd.npmax, ws.flags);
+  }
   // BF16 query rows are widened first (exact)
   const float* queries = queries_in;
   if (sd.q_bf16) {
@@ -1171,20 +1218,6 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
                        ws.npq ? ws.npq : nullptr, sd.npconst, sd.npmax, ws.probes);
   }
   mark(2);
-  // resets, one launch
-  {
-    ResetArgs ra;
-    ra.cnt = reinterpret_cast<uint32_t*>(ws.cnt);
-    ra.ncnt = (size_t)2 * kQSub * NB;
-    ra.counters = ws.counters;
-    ra.ncounters = (size_t)2 * (kNCls + 1) * kQueueSlot;
-    ra.flags = reinterpret_cast<uint32_t*>(ws.flags);
-    ra.work = ws.work;
-    ra.tau = ws.tau;
-    ra.ccount = ws.ccount;
-    ra.nq = (size_t)sd.nq;
-    hipLaunchKernelGGL(k_reset, dim3(256), dim3(256), 0, st, ra);
-  }
   // PPM
   PairArgs pa;
   pa.Q = queries;
@@ -1332,7 +1365,7 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
       ScanArgs sr = sa;
       sr.retry = ws.retry;
       sr.tau_id = ws.tau_id;
-      for (int rr = 0; rr < 2; ++rr) {
+      for (int rr = 0; rr < sd.reruns; ++rr) {
         sr.any_retry = ws.flags + 1 + rr;  // one flag per round
         hipLaunchKernelGGL(k_retry, dim3(sd.nq < 256 ? sd.nq : 256), dim3(256), rlds, st, ws.ccount, ws.ckey,
                            ws.cid, ws.tau, ws.tau_id, ws.kq, sd.kconst, sd.nq, sd.capq, ws.retry,
@@ -1363,6 +1396,7 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(k_merge_wave, dim3((sd.nq + 3) / 4), dim3(256), 0, st, ma2, sd.nq);
   hipLaunchKernelGGL(k_merge, dim3(sd.nq < 512 ? sd.nq : 512), dim3(256), mlds, st, ma2, sd.nq);
+  if (sd.out_status) hipLaunchKernelGGL(k_status, dim3(1), dim3(64), 0, st, ws.flags, sd.out_status);
   mark(7);
   return hipGetLastError();
 }

@@ -5,10 +5,17 @@
 // bound of the queue: a full pool rejects with AMP_EBUSY), gathered into
 // batches of requests sharing a precision policy, and each batch runs as one
 // device-mode search with per-query k and nprobe.  Two batches may be in
-// flight: the worker launches batch i+1 (query upload, search, result copies,
-// all stream-ordered) before it waits for batch i, so the host-side gather,
-// scatter and callbacks overlap device work.  Latency runs from a request's
-// arrival stamp to the moment its results are in the caller's buffers.
+// flight, each on an execution slot of its own (stream, search scratch,
+// staging): the worker launches batch i+1 (query and size upload, search,
+// result copies, all stream-ordered) before it waits for batch i, so the two
+// searches overlap on the device and the host-side gather, scatter and
+// callbacks overlap both.  A batch is padded to a size bucket and its search
+// replays a HIP graph captured once per (slot, bucket, policy): the
+// per-query k and nprobe travel in device memory, so one graph serves every
+// mix of sizes.  A batch whose search reports an error on the device (a
+// candidate overflow) fails its requests with that status.  Latency runs
+// from a request's arrival stamp to the moment its results are in the
+// caller's buffers.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -52,17 +59,34 @@ struct Batch {  // one in-flight search and its staging set
   amp_status status = AMP_OK;
 };
 
-struct Staging {  // per in-flight batch
-  void* hq = nullptr;        // pinned [max_batch][d] query rows
-  int64_t* hids = nullptr;   // pinned [max_batch][max_k]
+struct Staging {  // execution slot of an in-flight batch
+  void* hq = nullptr;        // pinned [cap][d] query rows
+  int32_t* hsz = nullptr;    // pinned [2][cap] per-query k, nprobe
+  int64_t* hids = nullptr;   // pinned [cap][max_k]
   float* hdist = nullptr;
   int64_t* hqd = nullptr;
+  int32_t* hstatus = nullptr;  // pinned: device status of the batch's search
   void* dq = nullptr;        // device copies
+  int32_t* dsz = nullptr;
   int64_t* dids = nullptr;
   float* ddist = nullptr;
   int64_t* dqd = nullptr;
+  int32_t* dstatus = nullptr;
   hipEvent_t ev = nullptr;   // results copied back
+  hipStream_t stream = nullptr;
+  Workspace ws;              // search scratch of this slot
 };
+
+// batch size bucket (graphs are captured per bucket): powers of two up to
+// 128, then multiples of 128
+int bucket_of(int n) {
+  if (n <= 128) {
+    int b = 1;
+    while (b < n) b <<= 1;
+    return b;
+  }
+  return (n + 127) / 128 * 128;
+}
 
 }  // namespace
 }  // namespace amp
@@ -73,7 +97,7 @@ struct amp_server {
   amp_index* ix = nullptr;
   amp_server_config cfg{};
   int device = 0, d = 0, esize = 4;
-  hipStream_t stream = nullptr;
+  int cap = 0;  // rows of a padded batch (the largest bucket)
   // admission pool
   void* pool = nullptr;  // pinned [max_pending][d] query rows
   std::vector<int32_t> free_slots;
@@ -103,83 +127,106 @@ static constexpr size_t kMaxLatencySamples = 1u << 24;
 amp_server::~amp_server() {
   (void)hipSetDevice(device);
   for (Staging& s : stg) {
+    if (s.stream) (void)hipStreamSynchronize(s.stream);
+    release_workspace(s.ws);
     if (s.ev) (void)hipEventDestroy(s.ev);
-    void* host[] = {s.hq, s.hids, s.hdist, s.hqd};
+    void* host[] = {s.hq, s.hsz, s.hids, s.hdist, s.hqd, s.hstatus};
     for (void* p : host)
       if (p) (void)hipHostFree(p);
-    void* dev[] = {s.dq, s.dids, s.ddist, s.dqd};
+    void* dev[] = {s.dq, s.dsz, s.dids, s.ddist, s.dqd, s.dstatus};
     for (void* p : dev)
       if (p) (void)hipFree(p);
+    if (s.stream) (void)hipStreamDestroy(s.stream);
   }
   if (pool) (void)hipHostFree(pool);
-  if (stream) (void)hipStreamDestroy(stream);
 }
 
 amp_status amp_server::init() {
-  const size_t B = cfg.max_batch, K = cfg.max_k, row = (size_t)d * esize;
+  cap = bucket_of(cfg.max_batch);
+  const size_t B = cap, K = cfg.max_k, row = (size_t)d * esize;
   auto hfail = [](const char* what) {
     (void)hipGetLastError();
     return set_error(AMP_ENOMEM, "server: %s allocation failed", what);
   };
-  if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) return hfail("stream");
   if (hipHostMalloc(&pool, (size_t)cfg.max_pending * row, hipHostMallocDefault) != hipSuccess) return hfail("pool");
-  for (Staging& s : stg) {
-    if (hipHostMalloc(&s.hq, B * row, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&s.hids), B * K * 8, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&s.hdist), B * K * 4, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&s.hqd), B * K * 8, hipHostMallocDefault) != hipSuccess)
+  amp_status s = amp_index_to_device(ix, device);
+  for (Staging& g : stg) {
+    if (s != AMP_OK) return s;
+    // default-priority streams of their own: the two slots' searches overlap
+    if (hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking) != hipSuccess) return hfail("stream");
+    if (hipHostMalloc(&g.hq, B * row, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&g.hsz), 2 * B * 4, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&g.hids), B * K * 8, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&g.hdist), B * K * 4, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&g.hqd), B * K * 8, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&g.hstatus), 4, hipHostMallocDefault) != hipSuccess)
       return hfail("pinned staging");
-    if (hipMalloc(&s.dq, B * row) != hipSuccess || hipMalloc(reinterpret_cast<void**>(&s.dids), B * K * 8) != hipSuccess ||
-        hipMalloc(reinterpret_cast<void**>(&s.ddist), B * K * 4) != hipSuccess ||
-        hipMalloc(reinterpret_cast<void**>(&s.dqd), B * K * 8) != hipSuccess)
+    std::memset(g.hq, 0, B * row);  // padded rows stay zero
+    if (hipMalloc(&g.dq, B * row) != hipSuccess || hipMalloc(reinterpret_cast<void**>(&g.dsz), 2 * B * 4) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&g.dids), B * K * 8) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&g.ddist), B * K * 4) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&g.dqd), B * K * 8) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&g.dstatus), 4) != hipSuccess)
       return hfail("device staging");
-    if (hipEventCreateWithFlags(&s.ev, hipEventDisableTiming) != hipSuccess) return hfail("event");
+    if (hipEventCreateWithFlags(&g.ev, hipEventDisableTiming) != hipSuccess) return hfail("event");
+    // the slot's search scratch, sized now for the largest batch: growing it
+    // later would wait for the batch in flight
+    s = reserve_workspace(ix, cap, cfg.max_nprobe, cfg.max_k, &g.ws);
   }
+  if (s != AMP_OK) return s;
   free_slots.resize(cfg.max_pending);
   for (int32_t i = 0; i < cfg.max_pending; ++i) free_slots[i] = cfg.max_pending - 1 - i;
-  // size the search scratch for the largest batch now: growing it later
-  // would wait for the batch in flight
-  amp_status s = amp_index_to_device(ix, device);
-  if (s == AMP_OK) s = reserve_workspace(ix, cfg.max_batch, cfg.max_nprobe, cfg.max_k);
-  return s;
+  return AMP_OK;
 }
 
-// gather the batch's queries into its staging set and enqueue upload,
-// search and result copies on the server stream
+// gather the batch's queries and sizes into its slot's staging (padded to
+// the bucket) and enqueue upload, search and result copies on the slot's
+// stream
 void amp_server::launch(Batch& b) {
   Staging& s = stg[b.set];
   const size_t row = (size_t)d * esize;
   const int n = (int)b.reqs.size();
-  std::vector<int32_t> kv(n), npv(n);
+  const int nb = bucket_of(n);
+  int32_t* hk = s.hsz;
+  int32_t* hnp = s.hsz + cap;
   for (int i = 0; i < n; ++i) {
     Request* r = b.reqs[i];
     std::memcpy(static_cast<char*>(s.hq) + i * row, static_cast<char*>(pool) + (size_t)r->slot * row, row);
-    kv[i] = r->k;
-    npv[i] = r->nprobe;
+    hk[i] = r->k;
+    hnp[i] = r->nprobe;
     b.kmax = std::max(b.kmax, r->k);
   }
+  // padding rows: zero queries with k = nprobe = 1 (their results are dropped)
+  std::memset(static_cast<char*>(s.hq) + (size_t)n * row, 0, (size_t)(nb - n) * row);
+  for (int i = n; i < nb; ++i) hk[i] = hnp[i] = 1;
   {
     std::lock_guard<std::mutex> lk(mu);  // the rows are copied: the slots take new requests
     for (Request* r : b.reqs) free_slots.push_back(r->slot);
   }
-  hipError_t e = hipMemcpyAsync(s.dq, s.hq, n * row, hipMemcpyHostToDevice, stream);
-  if (e != hipSuccess) {
+  hipError_t e;
+  if ((e = hipMemcpyAsync(s.dq, s.hq, nb * row, hipMemcpyHostToDevice, s.stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(s.dsz, s.hsz, 2 * (size_t)cap * 4, hipMemcpyHostToDevice, s.stream)) != hipSuccess) {
     (void)hipGetLastError();
     b.status = set_error(AMP_EDEVICE, "server: query upload failed: %s", hipGetErrorString(e));
     return;
   }
   amp_search_opts o{};
   o.mem = AMP_MEM_DEVICE;
-  o.stream = stream;
+  o.stream = s.stream;
   o.out_qdist = s.dqd;
   o.q_dtype = cfg.q_dtype;
-  b.status = amp_search(ix, s.dq, n, kv.data(), npv.data(), 1, &b.reqs[0]->policy, &o, s.dids, s.ddist);
+  o.flags = AMP_SEARCH_GRAPH | AMP_SEARCH_DEVICE_SIZES;
+  o.kmax = cfg.max_k;
+  o.npmax = cfg.max_nprobe;
+  o.out_status = s.dstatus;
+  b.status = search_on(ix, s.ws, s.dq, nb, s.dsz, s.dsz + cap, 1, &b.reqs[0]->policy, &o, s.dids, s.ddist);
   if (b.status != AMP_OK) return;
-  const size_t nk = (size_t)n * b.kmax;
-  if ((e = hipMemcpyAsync(s.hids, s.dids, nk * 8, hipMemcpyDeviceToHost, stream)) != hipSuccess ||
-      (e = hipMemcpyAsync(s.hdist, s.ddist, nk * 4, hipMemcpyDeviceToHost, stream)) != hipSuccess ||
-      (e = hipMemcpyAsync(s.hqd, s.dqd, nk * 8, hipMemcpyDeviceToHost, stream)) != hipSuccess ||
-      (e = hipEventRecord(s.ev, stream)) != hipSuccess) {
+  const size_t nk = (size_t)n * cfg.max_k;
+  if ((e = hipMemcpyAsync(s.hids, s.dids, nk * 8, hipMemcpyDeviceToHost, s.stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(s.hdist, s.ddist, nk * 4, hipMemcpyDeviceToHost, s.stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(s.hqd, s.dqd, nk * 8, hipMemcpyDeviceToHost, s.stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(s.hstatus, s.dstatus, 4, hipMemcpyDeviceToHost, s.stream)) != hipSuccess ||
+      (e = hipEventRecord(s.ev, s.stream)) != hipSuccess) {
     (void)hipGetLastError();
     b.status = set_error(AMP_EDEVICE, "server: result copy failed: %s", hipGetErrorString(e));
   }
@@ -193,6 +240,10 @@ void amp_server::complete(Batch& b) {
     if (e != hipSuccess) {
       (void)hipGetLastError();
       b.status = set_error(AMP_EDEVICE, "server: batch failed: %s", hipGetErrorString(e));
+    } else if (*s.hstatus != AMP_OK) {
+      // the device reported an error (a candidate overflow): the batch fails
+      b.status = set_error(*s.hstatus, "server: the batch's search reported %s on the device",
+                           amp_status_str(*s.hstatus));
     }
   }
   std::vector<std::pair<Request*, amp_status>> fin;
@@ -208,9 +259,10 @@ void amp_server::complete(Batch& b) {
         st = AMP_ECANCELED;
         ++cancelled;
       } else if (st == AMP_OK) {
-        std::memcpy(r->out_ids, s.hids + i * b.kmax, r->k * 8);
-        std::memcpy(r->out_dist, s.hdist + i * b.kmax, r->k * 4);
-        if (r->out_qdist) std::memcpy(r->out_qdist, s.hqd + i * b.kmax, r->k * 8);
+        const size_t o = i * (size_t)cfg.max_k;
+        std::memcpy(r->out_ids, s.hids + o, r->k * 8);
+        std::memcpy(r->out_dist, s.hdist + o, r->k * 4);
+        if (r->out_qdist) std::memcpy(r->out_qdist, s.hqd + o, r->k * 8);
         ++completed;
         if (lat_ms.size() < kMaxLatencySamples) lat_ms.push_back((float)((t - r->arrival_ns) * 1e-6));
       } else {

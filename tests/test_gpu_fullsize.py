@@ -82,9 +82,9 @@ def test_full_size_batch(mid_full, policy, bits):
     if policy == "adaptive":
         kw["model"] = mid_full["model"]
     ref = oracle.search(idx, Qs, w.k, w.nprobe, **kw)
-    sub = {key: g[key][ROWS] for key in ("ids", "dist", "qdist")}
+    sub = {key: g[key][ROWS] for key in ("ids", "dist", "qdist", "probes")}
     if policy == "fp32":
-        compare_fp32(sub, ref, w.M)
+        compare_fp32(sub, ref, idx, Qs)
     else:
         assert np.array_equal(g["bits"][ROWS], ref["bits"])
         compare_integer(sub, ref)

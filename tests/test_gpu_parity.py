@@ -70,7 +70,7 @@ def test_fp32_policy_within_fp32_bound(tiny):
     g = _gpu(tiny, 10, 8, policy="fp32")
     ref = _oracle(tiny, 10, 8, g, policy="fp32")
     assert (g["qdist"] == -1).all()
-    swaps = compare_fp32(g, ref, tiny["idx"]["M"])
+    swaps = compare_fp32(g, ref, tiny["idx"], tiny["Q"])
     assert swaps <= 3
 
 
@@ -101,20 +101,35 @@ def test_stealing_unit_queue_is_bit_exact(tiny, policy):
     compare_integer(g, ref)
 
 
+def _dq2(idx, q, P):
+    """d' of the probed lists of one query as the oracle forms it (squared
+    grid residual; inner product: squared grid difference of query and
+    centroid)."""
+    inv = 2.0 ** -idx["grid_e"]
+    out = []
+    if idx["metric"] == "ip":
+        _, ci = oracle.index_grid(idx)
+        qi = oracle.grid(np.asarray(q, np.float64) * inv, idx["grid_kind"])
+        for p in P:
+            r = qi - ci[p]
+            out.append(int((r * r).sum()))
+    else:
+        for p in P:
+            r = oracle.grid(oracle.residual_f32(q, idx["centroids"][p]).astype(np.float64) * inv,
+                            idx["grid_kind"])
+            out.append(int((r * r).sum()))
+    return np.asarray(out, dtype=np.int64)
+
+
 def _spread_model(ctx, nprobe, seed=0, n_sv=200):
     """A seeded random regressor whose feature map covers the index's feature
     ranges and whose thresholds split the scores of these queries into four
     width classes (scores from the oracle)."""
     idx, Q = ctx["idx"], ctx["Q"]
-    inv = 2.0 ** -idx["grid_e"]
-    dq = []
-    for q in Q[:16]:
-        P = oracle.select_probes(oracle.coarse_distances(q, idx["centroids"]), nprobe)
-        for p in P:
-            r = oracle.grid(oracle.residual_f32(q, idx["centroids"][p]).astype(np.float64) * inv,
-                            idx["grid_kind"])
-            dq.append(int((r * r).sum()))
-    feats = [np.asarray(dq), idx["radq"], idx["radq"], idx["list_sizes"], idx["list_sizes"]]
+    probes = [oracle.select_probes(oracle.coarse_distances(q, idx["centroids"], idx["metric"]), nprobe)
+              for q in Q[:16]]
+    dq = np.concatenate([_dq2(idx, q, P) for q, P in zip(Q[:16], probes)])
+    feats = [dq, idx["radq"], idx["radq"], idx["list_sizes"], idx["list_sizes"]]
     lo, mul = [], []
     for f in feats:
         L = oracle.mitchell_log2_q8(np.asarray(f, dtype=np.int64))
@@ -123,14 +138,8 @@ def _spread_model(ctx, nprobe, seed=0, n_sv=200):
         mul.append(int(1023 * 65536 // max(1, b - a)))
     m = random_model(seed, n_sv, lo, mul, gamma=1.0)
     ys = []
-    for q in Q[:16]:
-        P = oracle.select_probes(oracle.coarse_distances(q, idx["centroids"]), nprobe)
-        d2 = []
-        for p in P:
-            r = oracle.grid(oracle.residual_f32(q, idx["centroids"][p]).astype(np.float64) * inv,
-                            idx["grid_kind"])
-            d2.append(int((r * r).sum()))
-        _, y = oracle.predict_pair_bits(np.asarray(d2), P, idx["radq"], idx["list_sizes"], m)
+    for q, P in zip(Q[:16], probes):
+        _, y = oracle.predict_pair_bits(_dq2(idx, q, P), P, idx["radq"], idx["list_sizes"], m)
         ys.extend(int(v) for v in y)
     m["theta"] = np.quantile(np.asarray(ys, dtype=np.float64), [0.25, 0.5, 0.75]).astype(np.int64)
     return m
@@ -164,7 +173,7 @@ def test_integer_data_exact_end_to_end(midint, policy, bits):
         assert np.array_equal(g["probes"][i], oracle.select_probes(D64, 16))
     ref = oracle.search(midint["idx"], midint["Q"], 10, 16, policy=policy, bits=bits)
     if policy == "fp32":
-        compare_fp32(g, ref, 16)
+        compare_fp32(g, ref, midint["idx"], midint["Q"])
     else:
         compare_integer(g, ref)
 
@@ -221,7 +230,7 @@ def test_edge_cases_padding_chunking_empty_lists_and_per_query_sizes(monkeypatch
         g = _gpu(ctx, 7, 6, policy="fixed", bits=bits)
         compare_integer(g, _oracle(ctx, 7, 6, g, policy="fixed", bits=bits))
     gf = _gpu(ctx, 7, 6, policy="fp32")
-    compare_fp32(gf, _oracle(ctx, 7, 6, gf, policy="fp32"), 8)
+    compare_fp32(gf, _oracle(ctx, 7, 6, gf, policy="fp32"), ctx["idx"], ctx["Q"])
     monkeypatch.delenv("AMP_CHUNK")
     # per-query k and nprobe
     kq = r.integers(1, 40, size=len(Q)).astype(np.int32)
@@ -285,7 +294,7 @@ def test_inner_product_search(ipctx, policy, bits):
     certify_probes(g["probes"], ipctx["idx"], ipctx["Q"], 6)
     ref = _oracle(ipctx, 10, 6, g, policy=policy, bits=bits)
     if policy == "fp32":
-        compare_fp32(g, ref, 16)
+        compare_fp32(g, ref, ipctx["idx"], ipctx["Q"])
     else:
         compare_integer(g, ref)
 
@@ -315,7 +324,7 @@ def test_generic_subspace_counts(M, d):
         certify_probes(g["probes"], ctx["idx"], ctx["Q"], 4)
         ref = _oracle(ctx, 10, 4, g, policy=policy, bits=bits)
         if policy == "fp32":
-            compare_fp32(g, ref, M)
+            compare_fp32(g, ref, ctx["idx"], ctx["Q"])
         else:
             compare_integer(g, ref)
 
@@ -431,7 +440,7 @@ def test_skewed_shape_uneven_nprobe(skewed_shape):
         kw = dict(model=m) if policy == "adaptive" else {}
         ref = _oracle(ctx, 10, npq, g, policy=policy, bits=bits, **kw)
         if policy == "fp32":
-            compare_fp32(g, ref, w.M)
+            compare_fp32(g, ref, ctx["idx"], ctx["Q"])
         else:
             compare_integer(g, ref)
             if policy == "adaptive":
@@ -459,7 +468,7 @@ def test_highdim_shape_k100(highdim_shape, dtype):
             kw["model"] = m
         ref = _oracle(ctx, 100, 12, g, policy=policy, bits=bits, **kw)
         if policy == "fp32":
-            compare_fp32(g, ref, w.M)
+            compare_fp32(g, ref, ctx["idx"], ctx["Q"])
         else:
             compare_integer(g, ref)
             assert np.array_equal(g["bits"], ref["bits"])
@@ -481,7 +490,7 @@ def test_serving_shape_inner_product_mixed_k(serving_shape):
         certify_probes(g["probes"], ctx["idx"], ctx["Q"], npq)
         ref = _oracle(ctx, kq, npq, g, policy=policy, bits=bits)
         if policy == "fp32":
-            compare_fp32(g, ref, w.M)
+            compare_fp32(g, ref, ctx["idx"], ctx["Q"])
         else:
             compare_integer(g, ref)
 
@@ -592,7 +601,7 @@ def test_bound_spans_probes_when_the_nearest_list_is_smaller_than_k(monkeypatch,
     g = _gpu(c, 50, 64, policy=policy, bits=bits)
     ref = _oracle(c, 50, 64, g, policy=policy, bits=bits)
     if policy == "fp32":
-        compare_fp32(g, ref, c["idx"]["M"])
+        compare_fp32(g, ref, c["idx"], c["Q"])
     else:
         compare_integer(g, ref)
 
@@ -608,7 +617,7 @@ def test_candidate_overflow_is_resolved_by_rerunning_phase_two(tiny, monkeypatch
     err = capfd.readouterr().err
     ref = _oracle(tiny, 10, 8, g, policy=policy, bits=bits)
     if policy == "fp32":
-        compare_fp32(g, ref, tiny["idx"]["M"])
+        compare_fp32(g, ref, tiny["idx"], tiny["Q"])
     else:
         compare_integer(g, ref)
     if policy == "fixed" and bits == 4:
@@ -652,7 +661,7 @@ def test_l1_search(l1ctx, policy, bits):
     _l1_probes_ok(g, l1ctx, 6)
     ref = _oracle(l1ctx, 10, 6, g, policy=policy, bits=bits)
     if policy == "fp32":
-        compare_fp32(g, ref, l1ctx["idx"]["M"])
+        compare_fp32(g, ref, l1ctx["idx"], l1ctx["Q"])
     else:
         compare_integer(g, ref)
 
@@ -664,3 +673,175 @@ def test_l1_adaptive_search(l1ctx):
     ref = _oracle(l1ctx, 10, 6, g, policy="adaptive", model=m)
     assert np.array_equal(g["bits"], ref["bits"])
     compare_integer(g, ref)
+
+
+# ---- nprobe above 64 end to end, the one-word-row scan variants, device-side
+# ---- status and device-resident per-query sizes
+def test_skewed_shape_nprobe_up_to_128(skewed_shape):
+    # per-query nprobe U[8, 128]: the workgroup top-nprobe, 128 pair slots per
+    # query in the predictor, the queue at that width
+    ctx, w = skewed_shape
+    npq = np.random.default_rng(4).integers(8, 129, size=len(ctx["Q"])).astype(np.int32)
+    assert npq.max() > 64
+    m = _spread_model(ctx, 128, seed=1)
+    amp.amp_index_set_predictor(ctx["h"], m)
+    for policy, bits in (("fixed", 4), ("fixed", 16), ("adaptive", 0), ("fp32", 0)):
+        g = _gpu(ctx, 10, npq, policy=policy, bits=bits)
+        certify_probes(g["probes"], ctx["idx"], ctx["Q"], npq)
+        kw = dict(model=m) if policy == "adaptive" else {}
+        ref = _oracle(ctx, 10, npq, g, policy=policy, bits=bits, **kw)
+        if policy == "fp32":
+            compare_fp32(g, ref, ctx["idx"], ctx["Q"])
+        else:
+            compare_integer(g, ref)
+            if policy == "adaptive":
+                assert np.array_equal(g["bits"], ref["bits"])
+
+
+@pytest.fixture(scope="module")
+def serving_wide():
+    # the serving shape with enough lists for nprobe 256 (d 768, inner product, PQ96)
+    return _shape("serving", 40_000, 12, 512, 256)
+
+
+def test_serving_shape_nprobe_256_k100(serving_wide):
+    ctx, w = serving_wide
+    r = np.random.default_rng(12)
+    nq = len(ctx["Q"])
+    kq = r.choice([10, 50, 100], size=nq).astype(np.int32)
+    npq = r.choice([16, 64, 256], size=nq).astype(np.int32)
+    kq[0], npq[0] = 100, 256
+    m = _spread_model(ctx, 256, seed=2)
+    amp.amp_index_set_predictor(ctx["h"], m)
+    for policy, bits in (("fixed", 4), ("fixed", 16), ("adaptive", 0), ("fp32", 0)):
+        g = _gpu(ctx, kq, npq, policy=policy, bits=bits)
+        certify_probes(g["probes"], ctx["idx"], ctx["Q"], npq)
+        kw = dict(model=m) if policy == "adaptive" else {}
+        ref = _oracle(ctx, kq, npq, g, policy=policy, bits=bits, **kw)
+        if policy == "fp32":
+            compare_fp32(g, ref, ctx["idx"], ctx["Q"])
+        else:
+            compare_integer(g, ref)
+            if policy == "adaptive":
+                assert np.array_equal(g["bits"], ref["bits"])
+
+
+@pytest.mark.parametrize("shape", ["midint", "skewed_shape"])
+def test_one_word_row_variants_match_the_oracle(shape, request, monkeypatch):
+    # the M = 16 and M = 24 scan variants with one-word LUT rows (NR = 1, the
+    # sparse-batch regime) forced on a few queries
+    ctx = request.getfixturevalue(shape)
+    if isinstance(ctx, tuple):
+        ctx = ctx[0]
+    monkeypatch.setenv("AMP_NARROW", "1")
+    sub = dict(ctx, Q=np.ascontiguousarray(ctx["Q"][:6]))
+    m = _spread_model(sub, 8, seed=3)
+    amp.amp_index_set_predictor(ctx["h"], m)
+    for policy, bits in (("fixed", 4), ("fixed", 8), ("fixed", 16), ("adaptive", 0), ("fp32", 0)):
+        g = _gpu(sub, 10, 8, policy=policy, bits=bits)
+        kw = dict(model=m) if policy == "adaptive" else {}
+        ref = _oracle(sub, 10, 8, g, policy=policy, bits=bits, **kw)
+        if policy == "fp32":
+            compare_fp32(g, ref, sub["idx"], sub["Q"])
+        else:
+            compare_integer(g, ref)
+
+
+def _dev_out(torch, nq, kmax, npmax=None):
+    o = dict(ids=torch.empty((nq, kmax), dtype=torch.int64, device="cuda"),
+             dist=torch.empty((nq, kmax), dtype=torch.float32, device="cuda"),
+             qdist=torch.empty((nq, kmax), dtype=torch.int64, device="cuda"),
+             status=torch.full((1,), 12345, dtype=torch.int32, device="cuda"))
+    if npmax:
+        o["probes"] = torch.empty((nq, npmax), dtype=torch.int32, device="cuda")
+    return o
+
+
+def test_device_mode_overflow_is_reported_through_the_status_word(tiny, monkeypatch):
+    # a 64-entry candidate buffer and no re-runs: the 4-bit searches of these
+    # queries overflow it (about 120 candidates each); the device-mode search
+    # returns at once and its status word reads AMP_EOVERFLOW; without the
+    # overflow it reads AMP_OK
+    torch = pytest.importorskip("torch")
+    Q = tiny["Q"]
+    nq = len(Q)
+    qd = torch.from_numpy(Q).cuda()
+    s = torch.cuda.Stream()
+    o = _dev_out(torch, nq, 10)
+    amp.amp_search(tiny["h"], qd, 10, 8, policy="fixed", bits=4, out=o, stream=s)
+    s.synchronize()
+    assert int(o["status"].item()) == amp.AMP_OK
+    monkeypatch.setenv("AMP_CAPQ", "64")
+    monkeypatch.setenv("AMP_RERUNS", "0")
+    o = _dev_out(torch, nq, 10)
+    amp.amp_search(tiny["h"], qd, 10, 8, policy="fixed", bits=4, out=o, stream=s)
+    s.synchronize()
+    assert int(o["status"].item()) == amp.AMP_EOVERFLOW
+    h = amp.amp_search(tiny["h"], Q, 10, 8, policy="fixed", bits=4, want_status=True)
+    assert h["status"] == amp.AMP_EOVERFLOW
+    # with the re-runs the same buffer suffices, and the status says so
+    monkeypatch.setenv("AMP_RERUNS", "2")
+    o = _dev_out(torch, nq, 10)
+    amp.amp_search(tiny["h"], qd, 10, 8, policy="fixed", bits=4, out=o, stream=s)
+    s.synchronize()
+    assert int(o["status"].item()) == amp.AMP_OK
+
+
+def test_graph_replay_with_device_resident_sizes(tiny):
+    """Per-query k and nprobe in device memory: one captured graph replayed
+    with new sizes (and new queries) gives, every time, the eager search with
+    the same sizes as host arrays."""
+    torch = pytest.importorskip("torch")
+    Q = tiny["Q"]
+    nq = len(Q)
+    r = np.random.default_rng(21)
+    s = torch.cuda.Stream()
+    qd = torch.from_numpy(Q).cuda()
+    kd = torch.empty(nq, dtype=torch.int32, device="cuda")
+    npd = torch.empty(nq, dtype=torch.int32, device="cuda")
+    o = _dev_out(torch, nq, 20, 12)
+    for rep in range(4):
+        ks = r.integers(1, 21, size=nq).astype(np.int32)
+        nps = r.integers(1, 13, size=nq).astype(np.int32)
+        Qr = Q if rep % 2 == 0 else np.ascontiguousarray(Q[::-1])
+        with torch.cuda.stream(s):
+            qd.copy_(torch.from_numpy(Qr).cuda())
+            kd.copy_(torch.from_numpy(ks).cuda())
+            npd.copy_(torch.from_numpy(nps).cuda())
+            for v in o.values():
+                v.fill_(-1)
+        amp.amp_search(tiny["h"], qd, kd, npd, kmax=20, npmax=12, policy="fixed", bits=8, out=o, stream=s,
+                       graph=True)
+        s.synchronize()
+        x = torch.randn(256, 256, device="cuda")
+        (x @ x).sum().item()
+        torch.cuda.synchronize()
+        want = amp.amp_search(tiny["h"], Qr, ks, nps, policy="fixed", bits=8, want_probes=True)
+        got = {key: v.cpu().numpy() for key, v in o.items()}
+        assert int(got["status"][0]) == amp.AMP_OK
+        for i in range(nq):
+            k, npb = ks[i], nps[i]
+            assert np.array_equal(got["ids"][i, :k], want["ids"][i, :k]), (rep, i)
+            assert np.array_equal(got["qdist"][i, :k], want["qdist"][i, :k]), (rep, i)
+            assert np.array_equal(got["probes"][i, :npb], want["probes"][i, :npb]), (rep, i)
+            assert (got["probes"][i, npb:] == -1).all()
+            assert (got["ids"][i, k:] == -1).all()
+
+
+def test_device_sizes_out_of_range_are_clamped_and_reported(tiny):
+    torch = pytest.importorskip("torch")
+    Q = tiny["Q"][:8]
+    qd = torch.from_numpy(Q).cuda()
+    ks = np.array([5, 0, 10, 99, 3, 10, -4, 7], np.int32)
+    nps = np.array([4, 8, 0, 8, 50, 2, 8, 8], np.int32)
+    o = _dev_out(torch, 8, 10, 8)
+    s = torch.cuda.Stream()
+    amp.amp_search(tiny["h"], qd, torch.from_numpy(ks).cuda(), torch.from_numpy(nps).cuda(), kmax=10, npmax=8,
+                   policy="fixed", bits=16, out=o, stream=s)
+    s.synchronize()
+    assert int(o["status"].item()) == amp.AMP_EINVAL
+    kc, nc = np.clip(ks, 1, 10), np.clip(nps, 1, 8)
+    want = amp.amp_search(tiny["h"], Q, kc, nc, policy="fixed", bits=16)
+    got = o["ids"].cpu().numpy()
+    for i in range(8):
+        assert np.array_equal(got[i, :kc[i]], want["ids"][i, :kc[i]]), i

@@ -160,3 +160,71 @@ def test_bf16_server_equals_fp32_search_of_the_widened_queries(ctx):
     ref = amp.amp_search(ctx["h"], bf16_widen(Qb), 10, 8, policy="fixed", bits=8)
     assert np.array_equal(ids, ref["ids"]) and np.array_equal(qd, ref["qdist"])
     srv.close()
+
+
+def test_a_batch_whose_search_overflows_fails_with_the_device_status(ctx, monkeypatch):
+    # a 64-entry candidate buffer and no re-runs: a 4-bit batch overflows on
+    # the device; its requests complete with AMP_EOVERFLOW (not with wrong ids)
+    monkeypatch.setenv("AMP_CAPQ", "64")
+    monkeypatch.setenv("AMP_RERUNS", "0")
+    Q = ctx["Q"][:24]
+    srv = amp.amp_server_create(ctx["h"], max_batch=32, max_k=10, max_nprobe=8, policy="fixed", bits=4,
+                                batch_window_us=20000)
+    ids, dist, qd = _bufs(len(Q), 10)
+    done = []
+    for i in range(len(Q)):
+        amp.amp_server_submit(srv, Q[i], 10, 8, ids[i], dist[i], qd[i], done=done.append)
+    amp.amp_server_flush(srv)
+    assert amp.AMP_EOVERFLOW in done and set(done) <= {amp.AMP_OK, amp.AMP_EOVERFLOW}
+    st = amp.amp_server_stats(srv)
+    assert st["failed"] == done.count(amp.AMP_EOVERFLOW)
+    srv.close()
+
+
+@pytest.fixture(scope="module")
+def wide():
+    # the serving shape (d 768 unit vectors, inner product, PQ96) with 512
+    # lists, so that nprobe reaches 256; a predictor spread over the widths
+    import dataclasses
+    from test_gpu_parity import _spread_model
+    w = dataclasses.replace(WORKLOADS["serving"], n=40_000, nq=48, nlist=512, nprobe=256)
+    base = make_base(w)
+    idx = build_index(base, w.nlist, w.M, iters=8, seed=w.seed, grid_kind=w.grid_kind, metric=w.metric)
+    h = amp.amp_index_from_arrays(idx)
+    amp.amp_index_to_device(h, 0)
+    c = dict(idx=idx, h=h, Q=make_queries(w, 48))
+    m = _spread_model(c, 64, seed=5)
+    amp.amp_index_set_predictor(h, m)
+    c["model"] = m
+    return c
+
+
+def test_adaptive_inner_product_mix_equals_each_request_alone(wide):
+    """ADAPTIVE under inner product with k in {10, 50, 100} and nprobe in
+    {16, 64, 256}: every request's result in the continuously batched mix
+    (two batches in flight on their own streams) equals the search of that
+    query alone, and the oracle's for it."""
+    Q = wide["Q"]
+    r = np.random.default_rng(8)
+    ks = r.choice([10, 50, 100], size=len(Q)).astype(np.int32)
+    nps = r.choice([16, 64, 256], size=len(Q)).astype(np.int32)
+    srv = amp.amp_server_create(wide["h"], max_batch=8, max_pending=64, max_k=100, max_nprobe=256,
+                                policy="adaptive")
+    ids, dist, qd = _bufs(len(Q), 100)
+    done = []
+    for i in range(len(Q)):
+        amp.amp_server_submit(srv, Q[i], ks[i], nps[i], ids[i], dist[i], qd[i], done=done.append)
+    amp.amp_server_flush(srv)
+    assert done == [amp.AMP_OK] * len(Q)
+    assert amp.amp_server_stats(srv)["batches"] >= len(Q) // 8
+    for i in range(len(Q)):
+        one = amp.amp_search(wide["h"], Q[i:i + 1], int(ks[i]), int(nps[i]), policy="adaptive", want_probes=True)
+        k = ks[i]
+        assert np.array_equal(ids[i, :k], one["ids"][0]), i
+        assert np.array_equal(qd[i, :k], one["qdist"][0]), i
+        assert np.array_equal(dist[i, :k].view(np.uint32), one["dist"][0].view(np.uint32)), i
+        if i % 6 == 0:
+            ref = oracle.search(wide["idx"], Q[i:i + 1], int(k), int(nps[i]), probes=one["probes"],
+                                policy="adaptive", model=wide["model"])
+            compare_integer(one, ref)
+    srv.close()
