@@ -398,6 +398,35 @@ amp_status amp_search(amp_index* index, const void* queries, int64_t nq,
                       int64_t* out_ids, float* out_dist);
 
 /*
+ * amp_search without allocation, for callers that cannot allocate device or
+ * host memory during a search: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation.  Same arguments, results and
+ * errors as amp_search, with these differences:
+ *  - the search's scratch is a fixed array of device memory, 64 MiB per
+ *    device, that the library holds from its first use on a device until the
+ *    process ends; a search that does not fit it (roughly: nq * nlist * 4 +
+ *    nq * npmax * 40 + nq * capq * 16 bytes, capq the candidate capacity, at
+ *    least k rounded up to a power of two) is rejected with AMP_EINVAL;
+ *  - every call on a device shares that device's array: calls that overlap on
+ *    one device (different streams, threads) race and give wrong results;
+ *    successive calls on one stream are safe;
+ *  - device mode only; per-query sizes only as device arrays
+ *    (AMP_SEARCH_DEVICE_SIZES); no EXPLICIT policy, AMP_SEARCH_GRAPH,
+ *    stage_ms or work;
+ *  - the index must be resident on the current device with its predictor
+ *    (amp_index_to_device after the last amp_index_set_predictor), else
+ *    AMP_EINVAL;
+ *  - long lists are not split into several work units (a batch of few
+ *    queries over very long lists runs slower than with amp_search);
+ *  - overflows are reported through opts.out_status only (the return value
+ *    covers the enqueue).
+ */
+amp_status amp_search_noalloc(amp_index* index, const void* queries, int64_t nq,
+                              const int32_t* k, const int32_t* nprobe, int32_t per_query,
+                              const amp_precision_policy* policy, const amp_search_opts* opts,
+                              int64_t* out_ids, float* out_dist);
+
+/*
  * Serving loop: single-query requests, continuously batched onto the search
  * path of the device current at creation (the paper's problem statement,
  * Sec. 1 / Sec. 2.1, served one query at a time).

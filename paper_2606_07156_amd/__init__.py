@@ -93,7 +93,7 @@ _lib = None
 EXPORTS = ("amp_index_from_arrays", "amp_index_build", "amp_index_get_arrays", "amp_index_set_predictor", "amp_index_get_predictor",
            "amp_index_train_predictor", "amp_svr_fit",
            "amp_index_to_device",
-           "amp_index_save", "amp_index_load", "amp_index_info", "amp_search",
+           "amp_index_save", "amp_index_load", "amp_index_info", "amp_search", "amp_search_noalloc",
            "amp_index_autotune", "amp_index_get_tuning", "amp_index_set_tuning",
            "amp_server_create", "amp_server_submit", "amp_server_cancel", "amp_server_flush",
            "amp_server_stats", "amp_server_destroy",
@@ -129,6 +129,7 @@ def lib():
                                      C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
         L.amp_search.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_int32,
                                  C.POINTER(_Policy), C.POINTER(_Opts), C.c_void_p, C.c_void_p]
+        L.amp_search_noalloc.argtypes = L.amp_search.argtypes
         L.amp_index_free.argtypes = [C.c_void_p]
         L.amp_index_free.restype = None
         L.amp_status_str.argtypes = [C.c_int32]
@@ -461,6 +462,12 @@ def amp_search(index, queries, k, nprobe, policy="fixed", bits=16, allowed=(4, 8
     if work:
         res["work"] = dict(zip(("scan_bytes", "live_pairs", "dead_pairs"), wk.tolist()))
     return res
+
+
+def amp_search_noalloc(index, queries, k, nprobe, **kw):
+    """amp_search on the library's fixed scratch (no allocation): device mode
+    only, per-query sizes as device tensors; see amp_search."""
+    return amp_search(index, queries, k, nprobe, _entry="amp_search_noalloc", **kw)
 
 
 # ------------------------------------------------------------------ serving loop
