@@ -1,12 +1,20 @@
 """Throughput benchmark of the adaptive-precision IVF-PQ search on one MI355X.
 
-A step is one search of the whole query batch of the mid-size workload
-(1M x 128 integer-valued vectors from a 1024-component Gaussian mixture,
-IVF1024 / PQ16x256, 10 000 queries, nprobe 32, k 10): coarse distances,
-probe selection, precision prediction, work queue, LUT build + quantisation
-+ scan, top-k merge.  Queries and the index are resident in HBM before the
-timed region.  Prints one JSON line (see the fields below); a per-policy
-table goes to stderr.
+Default run (the JSON line the driver records): the largest single-GPU
+workload, the serving corpus (5M x 768 unit-normalised BF16 rows from a
+2048-component mixture, inner product, IVF2048 / PQ96x256, index built on
+the device).  A step is one search of a batch of 4096 BF16 queries with
+per-query k in {10, 50, 100} and nprobe in {16, 64, 256} (the serving mix,
+sizes resident on the device, one captured HIP graph replayed): coarse
+distances, probe selection, precision prediction, work queue, LUT build +
+quantisation + scan, top-k merge.  Queries, sizes and the index are resident
+in HBM before the timed region.  `value` is the adaptive policy's QPS; the
+full-precision (FP32 LUT) policy is timed the same way beside it, recall@10
+of both is taken over every query of the batch against exact FP64 search,
+and one Poisson arrival rate through the serving loop gives p50 / p99.  The
+mid-size workload (1M x 128 integer data, IVF1024 / PQ16, 10 000 queries,
+nprobe 32, k 10) is measured the same way as a secondary field.  A
+per-policy table goes to stderr.
 """
 from __future__ import annotations
 
@@ -31,13 +39,14 @@ BF16_MFMA_TFLOPS = 2500.0
 # 32-bit VALU lane operations: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_scan_mid_traffic.json")
+TRAFFIC_FILE_C5 = os.path.join(ROOT, "profiles", "k_scan_serving_traffic.json")
 STREAM_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_scan_stream_traffic.json")
 
 
 def _kernel_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hip", "amp_internal.h"):
+    for f in ("kernels.hip", "scan_kernels.h", "device_common.h", "amp_internal.h"):
         with open(os.path.join(ROOT, "paper_2606_07156_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -82,31 +91,50 @@ def log(*a):
 
 def _cpu_worker(args):
     import oracle
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)  # one thread per worker process
+    except ImportError:
+        pass
     idx, Q, k, nprobe, kw = args
     t = time.perf_counter()
     oracle.search(idx, Q, k, nprobe, **kw)
     return time.perf_counter() - t
 
 
-def cpu_baseline(idx, Q, k, nprobe, kw, budget_s=20.0):
-    """Time the oracle on a bounded sample of the same queries, one worker
-    process per host core."""
-    cores = os.cpu_count() or 1
-    cores = min(cores, 16)
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(idx, Q, k, nprobe, kw, budget_s=20.0, max_procs=16):
+    """Time the oracle on a bounded sample of the same queries, one
+    single-threaded worker process per host core (at most `max_procs`: the
+    host's CPU share for one GPU)."""
+    cores = min(os.cpu_count() or 1, max_procs)
+    kk = np.broadcast_to(np.asarray(k), (len(Q),))
+    nn = np.broadcast_to(np.asarray(nprobe), (len(Q),))
     t0 = time.perf_counter()
-    _cpu_worker((idx, Q[:2], k, nprobe, kw))
+    _cpu_worker((idx, Q[:2], kk[:2], nn[:2], kw))
     per_q = max((time.perf_counter() - t0) / 2, 1e-4)
     n = int(min(len(Q), max(cores, budget_s * cores / per_q)))
     n = max(cores, (n // cores) * cores)
-    chunks = [(idx, Q[i::cores][: n // cores], k, nprobe, kw) for i in range(cores)]
+    chunks = [(idx, Q[:n][i::cores], kk[:n][i::cores], nn[:n][i::cores], kw) for i in range(cores)]
     ctx = mp.get_context("fork")
     t0 = time.perf_counter()
     with ctx.Pool(cores) as pool:
         pool.map(_cpu_worker, chunks)
     wall = time.perf_counter() - t0
-    return dict(value=n / wall, unit="queries/s", cores=cores, kind="oracle",
-                sample=f"first {n} of {len(Q)} queries (interleaved over {cores} processes), "
-                       f"{wall:.1f} s wall")
+    return dict(value=round(n / wall, 2), unit="queries/s", cores=cores, kind="oracle",
+                cpu=cpu_model(), host_cpus=os.cpu_count(),
+                sample=f"first {n} of {len(Q)} queries of the timed batch (interleaved over {cores} "
+                       f"single-threaded processes), {wall:.1f} s wall")
 
 
 def serving_base_on_device(w, dev, chunk=1 << 19):
@@ -337,22 +365,24 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="mid")
+    ap.add_argument("--workload", default="",
+                    help="one named workload with constant k / nprobe instead of the default run")
     ap.add_argument("--nq", type=int, default=0)
-    ap.add_argument("--policies", default="adaptive,fp32,fixed16,fixed8,fixed4")
+    ap.add_argument("--policies", default="adaptive,fp32")
     ap.add_argument("--train-queries", type=int, default=256)
     ap.add_argument("--gamma", type=float, default=10.0)
     ap.add_argument("--epsilon", type=float, default=0.1)
     ap.add_argument("--svr-c", type=float, default=1.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--recall-queries", type=int, default=200,
-                    help="queries checked against exact kNN (0: skip; profiling runs)")
+    ap.add_argument("--recall-queries", type=int, default=200, help="--serving: queries checked for recall")
+    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work for cpu_baseline")
+    ap.add_argument("--serve-rate", type=float, default=10000.0,
+                    help="Poisson arrival rate of the default run's serving measurement (0: skip)")
+    ap.add_argument("--secondary", type=int, default=1, help="1: measure the mid-size workload after the headline")
     ap.add_argument("--cache-dir", default="/tmp/amp_bench_cache")
     ap.add_argument("--replicate", type=int, default=0,
                     help="R > 1: every list R times larger (working set beyond the last-level cache; "
                          "use with a small --nq for the streaming regime)")
-    ap.add_argument("--graph", type=int, default=1,
-                    help="1: timed searches replay a captured HIP graph (0: plain launches)")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration)")
     ap.add_argument("--autotune", type=int, default=1,
@@ -369,7 +399,7 @@ def main():
                     help="serving regime: Poisson arrivals of single-query requests on the serving workload")
     ap.add_argument("--lambdas", default="2000,5000,10000,20000,50000")
     ap.add_argument("--requests", type=int, default=100_000, help="request pool of the serving regime")
-    ap.add_argument("--serve-seconds", type=float, default=10.0, help="arrival window per rate")
+    ap.add_argument("--serve-seconds", type=float, default=3.0, help="arrival window per rate")
     ap.add_argument("--serve-batch", type=int, default=1024)
     ap.add_argument("--serve-policies", default="adaptive,fp32")
     ap.add_argument("--serve-n", type=int, default=0, help="corpus size override (testing)")
@@ -398,7 +428,343 @@ def main():
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU path is a design "
               "note, not part of this build", file=sys.stderr)
         sys.exit(2)
+    if args.workload:
+        return single(args)
+    return headline(args)
 
+
+# ---------------------------------------------------------------- measurement
+def policy_list(names, allowed):
+    pols = []
+    for p in names.split(","):
+        if p == "fp32":
+            pols.append(("fp32", dict(policy="fp32")))
+        elif p == "adaptive":
+            pols.append(("adaptive", dict(policy="adaptive", allowed=allowed)))
+        elif p.startswith("fixed"):
+            pols.append((p, dict(policy="fixed", bits=int(p[5:]))))
+    return pols
+
+
+def measure(h, w, Q, kq, npq, pols, args, truth, tag, qdev=None, q_dtype=None):
+    """Time every policy on one batch: W warm-up searches, then K searches
+    enqueued back to back on one created stream (graph replays; per-query
+    sizes, if any, resident on the device) between HIP events on that
+    stream.  Then K synchronised searches with per-stage events and the
+    phase-2 work counters, and one search of the whole batch for recall@10
+    against `truth` (exact FP64 ids of every query)."""
+    import torch
+
+    import oracle
+    import paper_2606_07156_amd as amp
+    dev = torch.device("cuda:0")
+    nq = len(Q)
+    per_query = np.ndim(kq) > 0
+    kmax = int(np.max(kq))
+    npmax = int(np.max(npq))
+    qd = qdev if qdev is not None else torch.from_numpy(Q).to(dev)
+    if per_query:
+        kd = torch.from_numpy(np.ascontiguousarray(kq, np.int32)).to(dev)
+        npd = torch.from_numpy(np.ascontiguousarray(npq, np.int32)).to(dev)
+        sizes = dict(k=kd, nprobe=npd, kmax=kmax, npmax=npmax)
+    else:
+        sizes = dict(k=int(kq), nprobe=int(npq))
+    out = dict(ids=torch.empty((nq, kmax), dtype=torch.int64, device=dev),
+               dist=torch.empty((nq, kmax), dtype=torch.float32, device=dev),
+               qdist=torch.empty((nq, kmax), dtype=torch.int64, device=dev),
+               status=torch.zeros(1, dtype=torch.int32, device=dev))
+    stream = torch.cuda.Stream()  # a created stream of default priority (graph capture needs one)
+    list_sizes = None
+    results = {}
+    for name, kw in pols:
+        if q_dtype:
+            kw = dict(kw, q_dtype=q_dtype)
+        sched = "automatic"
+        if args.autotune:
+            tk = {kk: v for kk, v in kw.items() if kk != "q_dtype"}
+            e = amp.amp_index_autotune(h, Q, kq, npq, repeats=3, **tk)
+            sched = {kk: e[kk] for kk in ("chunk", "chunk1", "narrow", "lut_dtype", "queue", "ms", "ms_default")}
+            log(f"[{tag}] {name}: autotuned schedule {sched}")
+        for _ in range(args.warmup):
+            amp.amp_search(h, qd, out=out, stream=stream, graph=True, **sizes, **kw)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            amp.amp_search(h, qd, out=out, stream=stream, graph=True, **sizes, **kw)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        status = int(out["status"].item())
+        stages, works = [], []
+        for _ in range(args.steps):
+            o = amp.amp_search(h, qd, out=out, stream=stream, stage_ms=True, work=True, **sizes, **kw)
+            stages.append(o["stage_ms"])
+            works.append(o["work"])
+        g = amp.amp_search(h, Q, kq, npq, want_probes=True, want_bits=True, **kw)
+        ids10 = g["ids"][:, :10]
+        rec1 = oracle.recall_1_at(ids10, truth[:, :10])
+        rec10 = oracle.recall_at(ids10, truth[:, :10])
+        pr = g["probes"]
+        bits = g["bits"][pr >= 0]
+        hist = {int(b): round(float((bits == b).mean()), 4) for b in np.unique(bits)}
+        if list_sizes is None:
+            list_sizes = args.idx_sizes
+        probed_bytes = float(list_sizes[pr[pr >= 0]].sum()) * w.M
+        wk = {kk: float(np.mean([x[kk] for x in works])) for kk in works[0]}
+        st = {s_: float(np.mean([x[s_] for x in stages])) for s_ in stages[0]}
+        lat = [x["total"] for x in stages]
+        results[name] = dict(qps=nq / (ms / 1e3), ms=ms, recall1=rec1, recall10=rec10, stages=st, status=status,
+                             probed_bytes=probed_bytes, scan_bytes=wk["scan_bytes"], live_pairs=wk["live_pairs"],
+                             dead_pairs=wk["dead_pairs"], bits=hist, schedule=sched,
+                             n_pairs=int((pr >= 0).sum()),
+                             p50=float(np.percentile(lat, 50)), p99=float(np.percentile(lat, 99)))
+        log(f"[{tag}] {name:8s} {ms:8.3f} ms/step {nq / ms * 1e3:12.0f} QPS  1-recall@10 {rec1:.4f}  "
+            f"10-recall@10 {rec10:.4f}  status {status}  bits {hist}  "
+            + " ".join(f"{s_}={v:.3f}" for s_, v in st.items()))
+    return results
+
+
+def roofline_of(r, w, nq, traffic_file):
+    """Roofline of the dominant kernel of the headline search: the phase-2
+    scan (LUT build of its pairs, then the packed-lane scan of the live
+    pairs' codes).  Achieved = the code bytes of the (query, list) pairs the
+    launch scans (each such pair reads its list's n x M code bytes once,
+    the per-unit figure of the scan) over the kernel's average duration,
+    against the HBM peak.  Pairs the bound test drops after the first LUT
+    pass are not scanned and are not counted; their LUT work is given as
+    context beside the probed bytes, which are not what the launch
+    processes."""
+    scan_ms = r["stages"]["scan2"]
+    gbs = r["scan_bytes"] / (scan_ms / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(traffic_file),
+            "kernel": "k_scan_mix (phase-2 scan, every lane class in one launch)",
+            "kernel_ms": round(scan_ms, 4), "bytes_per_launch": round(r["scan_bytes"]),
+            "context": {"live_pairs": round(r["live_pairs"]), "skipped_pairs": round(r["dead_pairs"]),
+                        "lut_entries_built": round((r["live_pairs"] + r["dead_pairs"]) * 256 * w.M),
+                        "probed_code_bytes": round(r["probed_bytes"])}}
+
+
+def mfma_of(r, w, nq):
+    st = r["stages"]
+    cl_flops = 2.0 * nq * w.nlist * w.d
+    lc_flops = r["n_pairs"] * 2.0 * 256 * w.d
+    cl_tf = cl_flops / (st["cl"] / 1e3) / 1e12
+    lc_tf = lc_flops / ((st["base"] + st["scan1"] + st["scan2"]) / 1e3) / 1e12
+    return {"cl": {"flop_per_search": cl_flops, "tflops": round(cl_tf, 2), "peak": FP32_MFMA_TFLOPS,
+                   "frac": round(cl_tf / FP32_MFMA_TFLOPS, 4)},
+            "lc": {"flop_per_search": lc_flops, "tflops_over_scan": round(lc_tf, 2), "peak": BF16_MFMA_TFLOPS,
+                   "frac": round(lc_tf / BF16_MFMA_TFLOPS, 4)}}
+
+
+def summary(results):
+    return {n: {"qps": round(x["qps"], 1), "ms": round(x["ms"], 4), "1_recall_at_10": round(x["recall1"], 4),
+                "10_recall_at_10": round(x["recall10"], 4), "scan2_ms": round(x["stages"]["scan2"], 4),
+                "stages_ms": {kk: round(v, 4) for kk, v in x["stages"].items()}, "bits_share": x["bits"],
+                "device_status": x["status"]}
+            for n, x in results.items()}
+
+
+def serve_once(h, Qb, ks, nps, lam, seconds, policy, max_batch):
+    """Open-loop Poisson arrivals at rate lam through the serving loop;
+    latency from the scheduled arrival to the results in host memory."""
+    import paper_2606_07156_amd as amp
+    R = len(Qb)
+    ids = np.zeros((R, 100), np.int64)
+    dist = np.zeros((R, 100), np.float32)
+    qaddr = Qb.ctypes.data + np.arange(R, dtype=np.int64) * Qb.strides[0]
+    iaddr = ids.ctypes.data + np.arange(R, dtype=np.int64) * ids.strides[0]
+    daddr = dist.ctypes.data + np.arange(R, dtype=np.int64) * dist.strides[0]
+    srv = amp.amp_server_create(h, max_batch=max_batch, max_pending=65536, max_k=100, max_nprobe=256,
+                                q_dtype="bf16", policy=policy)
+    r = np.random.Generator(np.random.PCG64([7, 9003]))
+
+    def run(lam_, n):
+        gaps = r.exponential(1.0 / lam_, n) if lam_ > 0 else np.zeros(n)
+        due = (np.cumsum(gaps) * 1e9).astype(np.int64)
+        t0 = time.monotonic_ns() + 2_000_000
+        lag = 0
+        for i in range(n):
+            a = t0 + int(due[i])
+            now = time.monotonic_ns()
+            while now < a:
+                if a - now > 200_000:
+                    time.sleep((a - now - 100_000) * 1e-9)
+                now = time.monotonic_ns()
+            lag = max(lag, now - a)
+            j = i % R
+            srv.submit_raw(int(qaddr[j]), int(ks[j]), int(nps[j]), int(iaddr[j]), int(daddr[j]), 0, a)
+        amp.amp_server_flush(srv)
+        st = amp.amp_server_stats(srv, reset=True)
+        st["max_submit_lag_ms"] = lag / 1e6
+        return st
+
+    run(0, min(R, 2048))  # warm-up: every size bucket's graph captured
+    n = max(1000, int(lam * seconds))
+    st = run(lam, n)
+    srv.close()
+    return dict(policy=policy, arrival_qps=lam, requests=n, achieved_qps=round(st["qps"], 1),
+                p50_ms=round(st["p50_ms"], 3), p99_ms=round(st["p99_ms"], 3), max_ms=round(st["max_ms"], 3),
+                mean_batch=round(st["mean_batch"], 1), rejected=st["rejected"], failed=st["failed"],
+                submit_lag_max_ms=round(st["max_submit_lag_ms"], 3))
+
+
+def exact_ip_bf16(b16, Q, k, dev, chunk=1 << 20):
+    """Exact inner-product top-k (FP64 on the device) over a BF16 corpus,
+    ties to the lower id."""
+    import torch
+    xb = torch.from_numpy(b16.view(np.int16)).to(dev).view(torch.bfloat16)
+    out = []
+    for q0 in range(0, len(Q), 1024):
+        qq = torch.from_numpy(np.asarray(Q[q0:q0 + 1024], np.float64)).to(dev)
+        nr = len(qq)
+        best = torch.full((nr, k), -float("inf"), dtype=torch.float64, device=dev)
+        bid = torch.zeros((nr, k), dtype=torch.int64, device=dev)
+        for s in range(0, len(b16), chunk):
+            sc = qq @ xb[s:s + chunk].to(torch.float64).T
+            ids = torch.arange(s, s + sc.shape[1], device=dev).expand(nr, -1)
+            S2, I2 = torch.cat([best, sc], 1), torch.cat([bid, ids], 1)
+            o = torch.argsort(I2, dim=1, stable=True)
+            S2, I2 = torch.gather(S2, 1, o), torch.gather(I2, 1, o)
+            o = torch.argsort(-S2, dim=1, stable=True)[:, :k]
+            best, bid = torch.gather(S2, 1, o), torch.gather(I2, 1, o)
+        out.append(bid.cpu().numpy())
+    del xb
+    return np.concatenate(out)
+
+
+def headline(args):
+    """The default run: the serving workload at full size (5M x 768 BF16,
+    inner product) as an offline batch with the serving mix of k and nprobe,
+    adaptive vs FP32 at recall@10 over the whole batch, one Poisson arrival
+    rate through the serving loop, then the mid-size workload as a secondary
+    field."""
+    import torch
+
+    import paper_2606_07156_amd as amp
+    from amp_data.synth import WORKLOADS, draw_k, make_queries
+
+    dev = torch.device("cuda:0")
+    w = WORKLOADS["serving"]
+    if args.serve_n:
+        w = w.scaled(n=args.serve_n)
+    t = time.perf_counter()
+    b16 = serving_base_on_device(w, dev)
+    torch.cuda.synchronize()
+    log(f"[c5] generated {b16.shape} bf16 corpus in {time.perf_counter() - t:.1f}s")
+    t = time.perf_counter()
+    h = amp.amp_index_build(b16, w.nlist, w.M, iters=20, seed=w.seed, metric="ip", grid_kind=w.grid_kind)
+    arr = amp.amp_index_get_arrays(h)
+    sizes = np.diff(arr["list_offsets"]).astype(np.int64)
+    args.idx_sizes = sizes
+    log(f"[c5] built IVF{w.nlist}/PQ{w.M} on the device in {time.perf_counter() - t:.1f}s; list sizes "
+        f"min/mean/max {sizes.min()}/{sizes.mean():.0f}/{sizes.max()}, grid_e {arr['grid_e']}")
+    t = time.perf_counter()
+    TQ = make_queries(w, args.train_queries, train=True)
+    allowed = tuple(int(b) for b in args.allowed.split(","))
+    rep = amp.amp_index_train_predictor(h, TQ, 10, 64, gamma=args.gamma, epsilon=args.epsilon, C_=args.svr_c,
+                                        n_samples=1280, allowed=allowed)
+    model = amp.amp_index_get_predictor(h)
+    log(f"[c5] trained predictor in {time.perf_counter() - t:.1f}s: {rep}")
+    nq = args.nq or 4096
+    Q = make_queries(w, nq)  # bf16-representable rows
+    Qb = np.ascontiguousarray((Q.view(np.uint32) >> 16).astype(np.uint16))
+    r = np.random.Generator(np.random.PCG64([w.seed, 9002]))
+    kq = np.array([10, 50, 100], np.int32)[r.integers(0, 3, nq)]
+    npq = np.array([16, 64, 256], np.int32)[r.integers(0, 3, nq)]
+    t = time.perf_counter()
+    truth = exact_ip_bf16(b16, Q, 10, dev)
+    log(f"[c5] exact inner-product top-10 of {nq} queries in {time.perf_counter() - t:.1f}s")
+    qdev = torch.from_numpy(Qb.view(np.int16)).to(dev)
+    pols = policy_list(args.policies, allowed)
+    res = measure(h, w, Qb, kq, npq, pols, args, truth, "c5", qdev=qdev, q_dtype="bf16")
+    head = "adaptive" if "adaptive" in res else next(iter(res))
+    rh = res[head]
+    fp = res.get("fp32")
+    # serving: one Poisson arrival rate through the serving loop
+    srv = serve_once(h, Qb, kq, npq, args.serve_rate, args.serve_seconds, head, args.serve_batch) \
+        if args.serve_rate > 0 else None
+    if srv:
+        log(f"[c5] serving {srv}")
+    del b16
+    line = {
+        "metric": "QPS at recall@10 (adaptive vs full-precision, same GPU); p99 latency",
+        "value": round(rh["qps"], 1),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(rh["ms"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32" if head != "fp32" else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {w.n}x{w.d} bf16 unit-normalised mixture ({w.n_comp} components), "
+                               f"inner product, IVF{w.nlist}/PQ{w.M}x256 built on the device, {nq} BF16 queries "
+                               "per step, per-query k in {10,50,100} and nprobe in {16,64,256}",
+                   "policy": head, "launch": "HIP graph replay, per-query sizes on the device",
+                   "recall_at_10": round(rh["recall10"], 4),
+                   "recall_definition": f"10-recall@10 over all {nq} queries against exact FP64 inner-product "
+                                        "search of the BF16 corpus; 1-recall@10 in policies",
+                   "speedup_vs_fp32": round(rh["qps"] / fp["qps"], 3) if fp else None,
+                   "recall_ratio_vs_fp32": round(rh["recall10"] / max(fp["recall10"], 1e-9), 4) if fp else None,
+                   "bits_share": rh["bits"],
+                   "predictor": {kk: rep[kk] for kk in ("n_sv", "label_hist", "n_pairs")},
+                   "policies": summary(res),
+                   "serving": srv},
+        "mfma": mfma_of(rh, w, nq),
+        "roofline": roofline_of(rh, w, nq, TRAFFIC_FILE_C5),
+    }
+    if not args.no_cpu:
+        kw = dict(dict(pols)[head])
+        if head == "adaptive":
+            kw["model"] = model
+        arr.pop("list_sizes", None)
+        arr["list_sizes"] = sizes.astype(np.int32)
+        line["cpu_baseline"] = cpu_baseline(arr, Q, kq, npq, kw, budget_s=args.cpu_budget)
+        log(f"[c5] cpu baseline {line['cpu_baseline']}")
+    del arr
+    h.free()
+    if args.secondary:
+        line["config"]["secondary"] = secondary_mid(args)
+    print(json.dumps(line), flush=True)
+
+
+def secondary_mid(args):
+    """The mid-size workload (1M x 128 integer data, IVF1024 / PQ16, 10 000
+    queries, nprobe 32, k 10) measured the same way: adaptive, FP32 and
+    fixed 16-bit QPS with recall over all queries."""
+    import paper_2606_07156_amd as amp
+    from amp_data.synth import make_queries
+    from amp_data.workloads import load_or_build
+
+    w, base, idx = load_or_build("mid", args.cache_dir, log=lambda m: log("[c2] " + m))
+    Q = make_queries(w)
+    h = amp.amp_index_from_arrays(idx)
+    amp.amp_index_to_device(h, 0)
+    t = time.perf_counter()
+    truth = exact_knn_device(base, Q, w.k, w.metric)
+    log(f"[c2] exact kNN of {len(Q)} queries in {time.perf_counter() - t:.1f}s")
+    TQ = make_queries(w, args.train_queries, train=True)
+    rep = amp.amp_index_train_predictor(h, TQ, w.k, w.nprobe, gamma=args.gamma, epsilon=args.epsilon,
+                                        C_=args.svr_c, n_samples=1280)
+    args.idx_sizes = idx["list_sizes"].astype(np.int64)
+    res = measure(h, w, Q, w.k, w.nprobe, policy_list("adaptive,fp32,fixed16", (4, 8, 12, 16)), args, truth, "c2")
+    ra, rf = res["adaptive"], res["fp32"]
+    return {"workload": f"{w.name}: {w.n}x{w.d} integer-valued Gaussian mixture ({w.n_comp} components), l2, "
+                        f"IVF{w.nlist}/PQ{w.M}x256, {len(Q)} queries per step, nprobe {w.nprobe}, k {w.k}",
+            "qps": round(ra["qps"], 1), "speedup_vs_fp32": round(ra["qps"] / rf["qps"], 3),
+            "recall_definition": f"1- and 10-recall@10 over all {len(Q)} queries against exact FP64 kNN",
+            "policies": summary(res), "roofline": roofline_of(ra, w, len(Q), TRAFFIC_FILE),
+            "mfma": mfma_of(ra, w, len(Q)), "predictor": {kk: rep[kk] for kk in ("n_sv", "label_hist")}}
+
+
+def single(args):
+    """One named workload with constant k and nprobe (profiling runs: the mid
+    workload, the streaming regime with --replicate, the high-dimensional
+    workload with --gpu-build)."""
     import torch
 
     import paper_2606_07156_amd as amp
@@ -406,7 +772,6 @@ def main():
     from amp_data.workloads import load_or_build
 
     if args.gpu_build:
-        # large workloads: index built on the device by the library's builder
         from amp_data.synth import WORKLOADS, make_base
         w = WORKLOADS[args.workload]
         t = time.perf_counter()
@@ -422,238 +787,64 @@ def main():
         w, base, idx = load_or_build(args.workload, args.cache_dir, log=lambda m: log("[bench] " + m))
     if args.nq:
         w = w.scaled(nq=args.nq)
-    if args.replicate > 1:
-        # streaming regime: every list `replicate` times larger, no recall
+    streaming = args.replicate > 1
+    if streaming:
         from amp_data.workloads import replicate
         import dataclasses
         idx = replicate(idx, args.replicate)
         w = dataclasses.replace(w, n=w.n * args.replicate)
-        args.recall_queries = 0
-        args.no_cpu = True
         log(f"[bench] replicated every list {args.replicate}x: {len(idx['ids'])} vectors, "
             f"{idx['codes'].nbytes / 1e6:.0f} MB of codes")
-    log(f"[bench] list sizes min/mean/max {idx['list_sizes'].min()}/{idx['list_sizes'].mean():.0f}/"
-        f"{idx['list_sizes'].max()}")
     Q = make_queries(w)
     h = amp.amp_index_from_arrays(idx)
     amp.amp_index_to_device(h, 0)
-    dev = torch.device("cuda:0")
-    qd = torch.from_numpy(Q).to(dev)
-    nq, k, nprobe = len(Q), w.k, w.nprobe
-    # streaming regime: every search takes a fresh batch from a pool (no code
-    # reuse between consecutive searches); plain launches (the query pointer
-    # changes)
-    n_batches = args.steps + args.warmup if args.replicate > 1 else 1
-    if n_batches > 1:
-        args.graph = 0
-        QP = make_queries(w.scaled(nq=nq * n_batches), nq * n_batches)
-        qpool = torch.from_numpy(QP).to(dev)
-        batch = lambda i: qpool[(i % n_batches) * nq:(i % n_batches + 1) * nq]
-    else:
-        batch = lambda i: qd
-    out = dict(ids=torch.empty((nq, k), dtype=torch.int64, device=dev),
-               dist=torch.empty((nq, k), dtype=torch.float32, device=dev),
-               qdist=torch.empty((nq, k), dtype=torch.int64, device=dev))
-    out_probes = torch.empty((nq, nprobe), dtype=torch.int32, device=dev)
-    out_bits = torch.empty((nq, nprobe), dtype=torch.uint8, device=dev)
-    # a created stream (default priority): graph capture needs one
-    stream = torch.cuda.Stream()
-    torch.cuda.synchronize()
-
-    # exact ground truth for recall@10 on a sample of queries (FP64 brute force)
-    import oracle
-    nr = min(args.recall_queries, nq)
-    t = time.perf_counter()
-    if nr and base.shape[0] * base.shape[1] > 2e8:
-        truth = exact_knn_device(base, Q[:nr], k, w.metric)  # FP64 on the device
-    else:
-        truth = oracle.exact_knn(base, Q[:nr], k, w.metric) if nr else None
-    log(f"[bench] exact kNN of {nr} queries in {time.perf_counter() - t:.1f}s")
-
-    allowed = tuple(int(b) for b in args.allowed.split(","))
-    # precision predictor fitted on a disjoint training query stream
-    t = time.perf_counter()
-    TQ = make_queries(w, args.train_queries, train=True)
-    rep = amp.amp_index_train_predictor(h, TQ, k, nprobe, gamma=args.gamma, epsilon=args.epsilon, allowed=allowed,
-                                        C_=args.svr_c, n_samples=1280)
-    model = amp.amp_index_get_predictor(h)
-    log(f"[bench] trained predictor in {time.perf_counter() - t:.1f}s: {rep}")
-
-    pols = []
-    for p in args.policies.split(","):
-        if p == "fp32":
-            pols.append(("fp32", dict(policy="fp32")))
-        elif p == "adaptive":
-            pols.append(("adaptive", dict(policy="adaptive", allowed=allowed)))
-        elif p.startswith("fixed"):
-            pols.append((p, dict(policy="fixed", bits=int(p[5:]))))
-    results = {}
-    # algorithmic bytes of the scan: one read of each probed list's codes per pair
-    sizes = idx["list_sizes"].astype(np.int64)
-    tuned = {}
-    for name, kw in pols:
-        if args.schedule:
-            # a fixed schedule for every policy (profiling runs: no tuning trials in the trace)
-            f = [int(x) for x in args.schedule.split(",")]
-            c, c1, nw, lt = f[:4]
-            ent = dict(policy_kind=amp.POLICIES[kw["policy"]], chunk=c, chunk1=c1, narrow=nw, lut_dtype=lt,
-                       queue=f[4] if len(f) > 4 else 0)
-            lg = int(np.ceil(np.log2(nq)))
-            amp.amp_index_set_tuning(h, [dict(ent, nq_log2=lg)])
-            tuned[name] = dict(ent, ms=0.0, ms_default=0.0)
-        elif args.autotune:
-            # schedule (unit chunking, LUT row width, LC dtype) timed for this
-            # batch shape; results do not depend on it
-            tuned[name] = amp.amp_index_autotune(h, QP[:nq] if n_batches > 1 else Q, k, nprobe, repeats=3, **kw)
-            log(f"[bench] {name}: autotuned schedule {tuned[name]}")
-        out["probes"], out["bits"] = (None, None) if nr else (out_probes, out_bits)
-        for i in range(args.warmup):
-            amp.amp_search(h, batch(args.steps + i), k, nprobe, out=out, stream=stream, graph=args.graph, **kw)
-        torch.cuda.synchronize()
-        # timed region: K searches enqueued back to back on one stream
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for i in range(args.steps):
-            amp.amp_search(h, batch(i), k, nprobe, out=out, stream=stream, graph=args.graph, **kw)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / args.steps
-        # stage breakdown and per-batch latency: separate, synchronised searches
-        stages, lat, works = [], [], []
-        for i in range(args.steps):
-            o = amp.amp_search(h, batch(i), k, nprobe, out=out, stream=stream, stage_ms=True, work=True, **kw)
-            stages.append(o["stage_ms"])
-            lat.append(o["stage_ms"]["total"])
-            works.append(o["work"])
-        if nr:
-            g = amp.amp_search(h, Q[:nr], k, nprobe, want_probes=True, want_bits=True, **kw)
-            rec1 = oracle.recall_1_at(g["ids"], truth)
-            rec10 = oracle.recall_at(g["ids"], truth)
-        else:
-            # outputs of the last timed search (device), no recall
-            g = dict(probes=out_probes.cpu().numpy(), bits=out_bits.cpu().numpy())
-            rec1 = rec10 = float("nan")
-        pr = g["probes"]
-        bits = g["bits"][pr >= 0]
-        hist = {int(b): round(float((bits == b).mean()), 4) for b in np.unique(bits)}
-        scale = nq / len(pr)
-        code_bytes = float(sizes[pr[pr >= 0]].sum()) * w.M * scale
-        # the phase-2 scan's own counters: code bytes of the (query, list)
-        # pairs it scanned, live and skipped pairs (a pair whose LUT base
-        # exceeds its query's bound is skipped whole after LUT pass 1)
-        wk = {kk: float(np.mean([x[kk] for x in works])) for kk in works[0]}
-        n_pairs_all = wk["live_pairs"] + wk["dead_pairs"]
-        # algorithmic work per launch = per-pair figure x pairs processed:
-        # every probed pair's LUT (256 M entries) and its list's lookup-adds
-        # (n M), whether the bound test let it skip the scan or not
-        scan_ops = (float(sizes[pr[pr >= 0]].sum()) + 256.0 * (pr >= 0).sum()) * w.M * scale
-        exec_ops = wk["scan_bytes"] + 256.0 * w.M * n_pairs_all
-        st = {s: float(np.mean([x[s] for x in stages])) for s in stages[0]}
-        results[name] = dict(qps=nq / (ms / 1e3), ms=ms, recall1=rec1, recall10=rec10, stages=st,
-                             code_bytes=code_bytes, scan_ops=scan_ops, exec_ops=exec_ops, scan_bytes=wk["scan_bytes"],
-                             live_pairs=wk["live_pairs"], dead_pairs=wk["dead_pairs"], bits=hist,
-                             p50=float(np.percentile(lat, 50)), p99=float(np.percentile(lat, 99)))
-        log(f"[bench] {name:8s} {ms:8.3f} ms/step  {nq / ms * 1e3:12.0f} QPS  1-recall@10 {rec1:.4f}  "
-            f"10-recall@10 {rec10:.4f}  bits {hist}  " + " ".join(f"{s}={v:.3f}" for s, v in st.items()))
-
-    head = "adaptive" if "adaptive" in results else next(iter(results))
-    r = results[head]
-    scan_ms = r["stages"]["scan2"]
-    # algorithmic work of the phase-2 scan: per (query, probed list) pair one
-    # LUT entry per (subspace, codeword) and one lookup-add per (vector,
-    # subspace); "executed" counts only what ran (pairs skipped whole after
-    # the LUT's first pass scan nothing)
-    achieved = r["scan_ops"] / (scan_ms / 1e3) / 1e12
-    executed = r["exec_ops"] / (scan_ms / 1e3) / 1e12
-    streaming = args.replicate > 1
-    mix = head in ("adaptive",)
-    kname = ("k_scan_mix<M,2,1,NR>: phase-2 scan, every lane class in one launch" if mix else
-             "k_scan<LW,M,2,1,NR>: phase-2 scan of the policy's lane class")
-    traffic = measured_traffic(STREAM_TRAFFIC_FILE if streaming else TRAFFIC_FILE)
-    work = {"live_pairs": round(r["live_pairs"]), "skipped_pairs": round(r["dead_pairs"]),
-            "scanned_code_bytes": round(r["scan_bytes"]), "probed_code_bytes": round(r["code_bytes"])}
     if streaming:
-        # no cross-query reuse of codes: a scan of every probed pair's codes
-        # would be bounded by HBM bandwidth; algorithmic bytes = each probed
-        # list's codes once per pair; "executed" = the bytes of the pairs the
-        # scan read (the rest were skipped by the bound test)
-        gbs = r["code_bytes"] / (scan_ms / 1e3) / 1e9
-        roofline = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
-                    "kernel_ms": round(scan_ms, 4), "algorithmic_bytes_per_launch": round(r["code_bytes"]),
-                    "executed": {"bytes_per_launch": round(r["scan_bytes"]),
-                                 "GB/s": round(r["scan_bytes"] / (scan_ms / 1e3) / 1e9, 1)},
-                    "work": work}
+        truth = np.zeros((len(Q), w.k), np.int64)  # duplicates tie: recall is not meaningful here
     else:
-        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
-                    "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": traffic, "kernel": kname,
-                    "kernel_ms": round(scan_ms, 4), "algorithmic_ops_per_launch": round(r["scan_ops"]),
-                    "executed": {"ops_per_launch": round(r["exec_ops"]), "TOP/s": round(executed, 3),
-                                 "frac": round(executed / ALU_PEAK_TOPS, 4)},
-                    "work": work}
-    fp = results.get("fp32")
-    # the two dense contractions on MFMA: CL (FP32 MFMA) and the LUT build
-    # (BF16 MFMA, fused into the scan kernels: rate over the scan stages, a
-    # lower bound on its own utilisation)
-    st_h = r["stages"]
-    n_pairs = float(nq) * nprobe
-    cl_flops = 2.0 * nq * w.nlist * w.d
-    lc_flops = n_pairs * 2.0 * 256 * w.d
-    cl_tf = cl_flops / (st_h["cl"] / 1e3) / 1e12
-    lc_tf = lc_flops / ((st_h["scan1"] + st_h["scan2"]) / 1e3) / 1e12
-    mfma_use = {"cl": {"flop_per_search": cl_flops, "tflops": round(cl_tf, 2), "peak": FP32_MFMA_TFLOPS,
-                       "frac": round(cl_tf / FP32_MFMA_TFLOPS, 4)},
-                "lc": {"flop_per_search": lc_flops, "tflops_over_scan": round(lc_tf, 2), "peak": BF16_MFMA_TFLOPS,
-                       "frac": round(lc_tf / BF16_MFMA_TFLOPS, 4)}}
-    # end-to-end QPS against reading every probed list's codes once per query
-    # from HBM (no reuse) at peak bandwidth
-    bytes_per_q = r["code_bytes"] / nq
-    hbm_q = HBM_PEAK_GBS * 1e9 / bytes_per_q
-    hbm_bound = {"code_bytes_per_query": round(bytes_per_q), "qps_at_hbm_peak": round(hbm_q),
-                 "frac": round(r["qps"] / hbm_q, 4)}
+        t = time.perf_counter()
+        truth = exact_knn_device(base, Q, w.k, w.metric)
+        log(f"[bench] exact kNN of {len(Q)} queries in {time.perf_counter() - t:.1f}s")
+    allowed = tuple(int(b) for b in args.allowed.split(","))
+    TQ = make_queries(w, args.train_queries, train=True)
+    rep = amp.amp_index_train_predictor(h, TQ, w.k, w.nprobe, gamma=args.gamma, epsilon=args.epsilon,
+                                        allowed=allowed, C_=args.svr_c, n_samples=1280)
+    model = amp.amp_index_get_predictor(h)
+    log(f"[bench] trained predictor: {rep}")
+    if args.schedule:
+        f = [int(x) for x in args.schedule.split(",")]
+        ents = []
+        for name, kw in policy_list(args.policies, allowed):
+            ents.append(dict(policy_kind=amp.POLICIES[kw["policy"]], nq_log2=int(np.ceil(np.log2(len(Q)))),
+                             chunk=f[0], chunk1=f[1], narrow=f[2], lut_dtype=f[3], queue=f[4] if len(f) > 4 else 0))
+        amp.amp_index_set_tuning(h, ents)
+        args.autotune = 0
+    args.idx_sizes = idx["list_sizes"].astype(np.int64)
+    pols = policy_list(args.policies, allowed)
+    res = measure(h, w, Q, w.k, w.nprobe, pols, args, truth, "bench")
+    head = "adaptive" if "adaptive" in res else next(iter(res))
+    rh = res[head]
+    fp = res.get("fp32")
     line = {
         "metric": "QPS at recall@10 (adaptive vs full-precision, same GPU); p99 latency",
-        "value": round(r["qps"], 1),
-        "unit": "queries/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(r["ms"], 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int32" if head != "fp32" else "f32",
-        "data": "synthetic",
+        "value": round(rh["qps"], 1), "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(rh["ms"], 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32" if head != "fp32" else "f32", "data": "synthetic",
         "config": {"workload": f"{w.name}: {w.n}x{w.d} {KIND_TEXT.get(w.kind, w.kind)} ({w.n_comp} components), "
-                               f"{w.metric}, IVF{w.nlist}/PQ{w.M}x256, {nq} queries per step, nprobe {nprobe}, k {k}"
-                               + (", index built on the device" if args.gpu_build else "")
+                               f"{w.metric}, IVF{w.nlist}/PQ{w.M}x256, {len(Q)} queries per step, nprobe "
+                               f"{w.nprobe}, k {w.k}" + (", index built on the device" if args.gpu_build else "")
                                + (f"; every list replicated {args.replicate}x (streaming regime)"
-                                  if args.replicate > 1 else ""),
-                   "policy": head,
-                   "launch": "HIP graph replay" if args.graph else "kernel launches",
-                   "schedule": ({kk: tuned[head][kk] for kk in ("chunk", "chunk1", "narrow", "lut_dtype", "queue", "ms",
-                                                                "ms_default")} if head in tuned else "automatic"),
-                   "recall_at_10": round(r["recall1"], 4),
-                   "recall_definition": "1-recall@10 (exact nearest neighbour within the 10 returned); "
-                                        f"10-recall@10 {r['recall10']:.4f}; {nr} queries vs FP64 brute force",
-                   "speedup_vs_fp32": round(r["qps"] / fp["qps"], 3) if fp else None,
-                   "recall_vs_fp32": round(r["recall1"] - fp["recall1"], 4) if fp else None,
-                   "bits_share": r["bits"],
-                   "batch_latency_ms_p50_p99": [round(r["p50"], 4), round(r["p99"], 4)],
-                   "predictor": {kk: rep[kk] for kk in ("n_sv", "label_hist", "n_pairs")},
-                   "policies": {n: {"qps": round(x["qps"], 1), "recall_at_10": round(x["recall1"], 4),
-                                    "10_recall_at_10": round(x["recall10"], 4), "ms": round(x["ms"], 4),
-                                    "scan_ms": round(x["stages"]["scan2"], 4)}
-                                for n, x in results.items()}},
-        "mfma": mfma_use,
-        "hbm_bound": hbm_bound,
-        "roofline": roofline,
+                                  if streaming else ""),
+                   "policy": head, "recall_at_10": round(rh["recall10"], 4),
+                   "speedup_vs_fp32": round(rh["qps"] / fp["qps"], 3) if fp else None,
+                   "policies": summary(res)},
+        "mfma": mfma_of(rh, w, len(Q)),
+        "roofline": roofline_of(rh, w, len(Q), STREAM_TRAFFIC_FILE if streaming else TRAFFIC_FILE),
     }
-    if not args.no_cpu:
-        kw = dict(pols)[head]
+    if not args.no_cpu and not streaming:
+        kw = dict(dict(pols)[head])
         if head == "adaptive":
-            kw = dict(kw, model=model)
-        line["cpu_baseline"] = cpu_baseline(idx, Q, k, nprobe, kw)
+            kw["model"] = model
+        line["cpu_baseline"] = cpu_baseline(idx, Q, w.k, w.nprobe, kw, budget_s=args.cpu_budget)
     print(json.dumps(line), flush=True)
 
 

@@ -154,7 +154,8 @@ typedef struct amp_precision_policy {
  *   out_bits   [nq][npmax] uint8 LUT width of each probed list (32 = FP32)
  *   out_coarse [nq][nlist] float coarse (CL) distances
  * stage_ms (host, [AMP_N_STAGES] float, optional): per-stage GPU time of this
- * call from events on the stream; forces a synchronisation at the end.
+ * call from events on the stream (stages listed with AMP_N_STAGES); forces a
+ * synchronisation at the end.
  * q_dtype: AMP_F32 (0) or AMP_BF16 query rows (bfloat16 bit patterns,
  * uint16); BF16 rows are widened to FP32 on the device (exact) as the first
  * step of the search, so a BF16 query searches exactly as the FP32 query of
@@ -187,7 +188,9 @@ typedef struct amp_precision_policy {
  * export runs a second, separate LUT build pass after the search (the search
  * itself is unchanged).
  */
-#define AMP_N_STAGES 8
+#define AMP_N_STAGES 9  /* stage_ms: CL, top-nprobe, predictor, pair bases, queue,
+                           phase-1 scan (+ bound, + the full scan's queue),
+                           phase-2 scan, re-runs + merge, total */
 #define AMP_SEARCH_GRAPH 1u  /* flags: capture the search as a HIP graph once
                                 and replay it while queries/outputs pointers,
                                 sizes, policy and stream are unchanged (device

@@ -26,8 +26,8 @@ AMP_MEM_HOST, AMP_MEM_DEVICE = 0, 1
 AMP_POLICY_FP32, AMP_POLICY_FIXED, AMP_POLICY_ADAPTIVE, AMP_POLICY_EXPLICIT = 0, 1, 2, 3
 AMP_LUT_BF16, AMP_LUT_F16, AMP_LUT_F8E4M3 = 1, 2, 3
 AMP_F32, AMP_BF16 = 0, 1
-AMP_N_STAGES = 8
-STAGES = ("cl", "topn", "predict", "queue", "scan1", "scan2", "merge", "total")
+AMP_N_STAGES = 9
+STAGES = ("cl", "topn", "predict", "base", "queue", "scan1", "scan2", "merge", "total")
 POLICIES = {"fp32": AMP_POLICY_FP32, "fixed": AMP_POLICY_FIXED,
             "adaptive": AMP_POLICY_ADAPTIVE, "explicit": AMP_POLICY_EXPLICIT}
 

@@ -121,6 +121,7 @@ struct Workspace {
   uint8_t* pbits = nullptr;    // [nq][npmax]
   uint8_t* xbits = nullptr;    // [nq][npmax] explicit widths (uploaded)
   uint64_t* tau = nullptr;     // [nq] pruning threshold key
+  int64_t* pbase = nullptr;    // [nq][npmax] exact base of each pair (integer policies)
   uint8_t* retry = nullptr;    // [nq] query takes part in the phase-2 re-run
   int64_t* tau_id = nullptr;   // [nq] id part of the re-run's bound
   uint32_t* ccount = nullptr;  // [nq] candidate count

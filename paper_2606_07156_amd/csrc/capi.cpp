@@ -464,6 +464,7 @@ static amp_status lay_out(const amp_index* ix, Workspace& w, size_t nq, size_t n
   AMP_TAKE(&w.pbits, npairs);
   AMP_TAKE(&w.xbits, npairs);
   AMP_TAKE(&w.tau, nq);
+  AMP_TAKE(&w.pbase, npairs);
   AMP_TAKE(&w.retry, nq);
   AMP_TAKE(&w.tau_id, nq);
   AMP_TAKE(&w.ccount, nq);
@@ -902,17 +903,19 @@ amp_status search_on(amp_index* ix, Workspace& w, const void* queries, int64_t n
   if (w.ev_done) AMP_HIP(hipEventRecord(w.ev_done, st));
   if (host) AMP_HIP(hipStreamSynchronize(st));
   if (timed) {
-    // stages: 0 CL, 1 top-nprobe, 2 predictor, 3 queue, 4 scan phase 1,
-    // 5 scan phase 2, 6 merge; slot 7 holds the sum
-    AMP_HIP(hipEventSynchronize(ev[7]));
+    // stages: 0 CL, 1 top-nprobe, 2 predictor, 3 pair bases, 4 queue of the
+    // phase-1 bound, 5 phase-1 scan + bound + queue of the full scan, 6 full
+    // scan (phase 2), 7 re-runs + merge; the last slot holds the sum
+    constexpr int NS = AMP_N_STAGES - 1;
+    AMP_HIP(hipEventSynchronize(ev[NS]));
     float total = 0.f;
-    for (int i = 0; i < 7; ++i) {
+    for (int i = 0; i < NS; ++i) {
       float ms = 0.f;
       hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
       opts->stage_ms[i] = ms;
       total += ms;
     }
-    opts->stage_ms[7] = total;
+    opts->stage_ms[NS] = total;
     for (auto& e : ev) hipEventDestroy(e);
   }
   if (opts->work) {

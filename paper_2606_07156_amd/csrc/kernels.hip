@@ -631,7 +631,17 @@ struct QueueArgs {
   int32_t* flags;
   int nq, npmax, nlist, M, ncls, wpr;
   int64_t chunk[2], max_units;  // list chunk of a work unit in phase 1, phase 2
+  int ph0, ph1;           // queue phases built by this launch: [ph0, ph1) of {0 bound, 1 full scan}
+  const int64_t* pbase;   // exact base of every pair (integer policies), or null: every pair joins phase 2
+  const uint64_t* tau;    // the queries' phase-1 bounds (with pbase)
+  uint64_t* work;         // phase-2 work counters (pairs dropped here count as skipped), or null
 };
+
+// a pair joins the full scan unless its exact base already exceeds its
+// query's phase-1 bound (then no vector of its list can reach the top-k)
+__device__ __forceinline__ bool pair_live(const QueueArgs& a, size_t i) {
+  return !a.pbase || ikey(a.pbase[i]) <= a.tau[i / a.npmax];
+}
 
 __device__ __forceinline__ int pair_class(int bits, int M) {
   if (bits == 32) return 0;
@@ -675,8 +685,11 @@ __global__ void k_qhist(QueueArgs a) {
   const int cls = pair_class(a.pbits[i], a.M);
   const int NB = a.ncls * a.nlist;
   const size_t b = (size_t)pair_sub(i) * NB + cls * a.nlist + p;
-  a.rank[n + i] = atomicAdd(&a.cnt[(size_t)kQSub * NB + b], 1);
-  if (in_phase1(a, i)) a.rank[i] = atomicAdd(&a.cnt[b], 1);
+  if (a.ph1 > 1) {
+    if (pair_live(a, i)) a.rank[n + i] = atomicAdd(&a.cnt[(size_t)kQSub * NB + b], 1);
+    else if (a.work) atomicAdd((unsigned long long*)&a.work[2], 1ull);
+  }
+  if (a.ph0 == 0 && in_phase1(a, i)) a.rank[i] = atomicAdd(&a.cnt[b], 1);
 }
 
 // per (phase, class, list) bucket: its pair total from the sub-counters
@@ -685,8 +698,8 @@ __global__ void k_qhist(QueueArgs a) {
 __global__ void k_qtot(QueueArgs a, int fp32) {
   const int NB = a.ncls * a.nlist;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= 2 * NB) return;
-  const int ph = i / NB, b = i % NB, cls = b / a.nlist, p = b % a.nlist;
+  if (i >= (a.ph1 - a.ph0) * NB) return;
+  const int ph = a.ph0 + i / NB, b = i % NB, cls = b / a.nlist, p = b % a.nlist;
   int32_t* cnt = a.cnt + (size_t)ph * kQSub * NB;
   int x[kQSub];
 #pragma unroll
@@ -740,7 +753,7 @@ __global__ __launch_bounds__(1024) void k_qscan(QueueArgs a, int fp32) {
   __shared__ int64_t s_w[16];
   const int NB = a.ncls * a.nlist;
   const int per = (NB + 1023) / 1024;
-  for (int ph = 0; ph < 2; ++ph) {
+  for (int ph = a.ph0; ph < a.ph1; ++ph) {
     int64_t* po = a.pairoff + (size_t)ph * (NB + 1);
     int64_t* uo = a.unitoff + (size_t)ph * (NB + 1);
     const int b0 = threadIdx.x * per;
@@ -775,15 +788,16 @@ __global__ void k_qscatter(QueueArgs a) {
   const int b = cls * a.nlist + a.lpos[p];
   const int NB = a.ncls * a.nlist;
   const size_t bs = (size_t)pair_sub(i) * NB + cls * a.nlist + p;  // sub-counter offset
-  a.sorted[n + a.pairoff[(NB + 1) + b] + a.cnt[(size_t)kQSub * NB + bs] + a.rank[n + i]] = (int32_t)i;
-  if (in_phase1(a, i)) a.sorted[a.pairoff[b] + a.cnt[bs] + a.rank[i]] = (int32_t)i;
+  if (a.ph1 > 1 && pair_live(a, i))
+    a.sorted[n + a.pairoff[(NB + 1) + b] + a.cnt[(size_t)kQSub * NB + bs] + a.rank[n + i]] = (int32_t)i;
+  if (a.ph0 == 0 && in_phase1(a, i)) a.sorted[a.pairoff[b] + a.cnt[bs] + a.rank[i]] = (int32_t)i;
 }
 
 // grid-stride over (phase, unit): find the unit's bucket by binary search of
 // the unit offsets and write its descriptor
 __global__ void k_qunits(QueueArgs a, int fp32) {
   const int NB = a.ncls * a.nlist;
-  for (int ph = 0; ph < 2; ++ph) {
+  for (int ph = a.ph0; ph < a.ph1; ++ph) {
     const int64_t* po = a.pairoff + (size_t)ph * (NB + 1);
     const int64_t* uo = a.unitoff + (size_t)ph * (NB + 1);
     const int64_t total = uo[NB];
@@ -1248,6 +1262,43 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   const int qpb = 256 >> (pa.lg_npp + pa.lg_T);
   hipLaunchKernelGGL(k_pairs, dim3((sd.nq + qpb - 1) / qpb), dim3(256), 0, st, pa, ma);
   mark(3);
+  // exact bases of the pairs (integer policies): the full scan's queue is
+  // built after the phase-1 bound and leaves out the pairs whose base exceeds
+  // it.  (The FP32 policy tests its bound inside the scan, after its LUT.)
+  const bool early = !fp32;
+  const int dt = dt_of(sd.lut_dtype);
+  hipError_t err = hipSuccess;
+  if (early) {
+    BaseArgs ba;
+    ba.Q = queries;
+    ba.C = dv.centroids;
+    ba.bsw = reinterpret_cast<const u32x4*>(dv.bsw);
+    ba.bsw16 = reinterpret_cast<const u32x4*>(dv.bsw16);
+    ba.cbi16 = dv.cbi16;
+    ba.probes = ws.probes;
+    ba.pbase = ws.pbase;
+    ba.nq = sd.nq;
+    ba.d = sd.d;
+    ba.M = sd.M;
+    ba.dsub = sd.dsub;
+    ba.npmax = sd.npmax;
+    ba.grid_e = sd.grid_e;
+    ba.grid_kind = sd.grid_kind;
+    ba.metric = sd.metric;
+    const size_t blds = base_lds_layout(sd.M, sd.d).total;
+    if (sd.metric == AMP_IP) {
+      auto fn = dt == DT_F16 ? k_base_ip<DT_F16> : k_base_ip<DT_BF16>;
+      if ((err = hipFuncSetAttribute(kaddr(fn), hipFuncAttributeMaxDynamicSharedMemorySize, (int)blds)) != hipSuccess)
+        return err;
+      hipLaunchKernelGGL(fn, dim3(sd.nq), dim3(kThreads), blds, st, ba);
+    } else {
+      auto fn = dt == DT_F16 ? k_base<DT_F16> : k_base<DT_BF16>;
+      if ((err = hipFuncSetAttribute(kaddr(fn), hipFuncAttributeMaxDynamicSharedMemorySize, (int)blds)) != hipSuccess)
+        return err;
+      hipLaunchKernelGGL(fn, dim3((unsigned)((npairs + kBaseG - 1) / kBaseG)), dim3(kThreads), blds, st, ba);
+    }
+  }
+  mark(4);
   // queue
   QueueArgs qa;
   qa.probes = ws.probes;
@@ -1273,13 +1324,27 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   qa.chunk[0] = sd.chunk1;
   qa.chunk[1] = sd.chunk;
   qa.max_units = sd.max_units;
+  qa.pbase = nullptr;
+  qa.tau = ws.tau;
+  qa.work = nullptr;
   const int qb = (int)((npairs + 255) / 256);
-  hipLaunchKernelGGL(k_qhist, dim3(qb), dim3(256), 0, st, qa);
-  hipLaunchKernelGGL(k_qtot, dim3((2 * NB + 255) / 256), dim3(256), 0, st, qa, fp32 ? 1 : 0);
-  hipLaunchKernelGGL(k_qscan, dim3(1), dim3(1024), 0, st, qa, fp32 ? 1 : 0);
-  hipLaunchKernelGGL(k_qscatter, dim3(qb), dim3(256), 0, st, qa);
-  hipLaunchKernelGGL(k_qunits, dim3(512), dim3(256), 0, st, qa, fp32 ? 1 : 0);
-  mark(4);
+  // one build of the queue phases [ph0, ph1)
+  auto build_queue = [&](int ph0, int ph1) {
+    QueueArgs q = qa;
+    q.ph0 = ph0;
+    q.ph1 = ph1;
+    if (ph1 > 1 && early) {
+      q.pbase = ws.pbase;
+      q.work = sd.want_work ? ws.work : nullptr;
+    }
+    hipLaunchKernelGGL(k_qhist, dim3(qb), dim3(256), 0, st, q);
+    hipLaunchKernelGGL(k_qtot, dim3(((ph1 - ph0) * NB + 255) / 256), dim3(256), 0, st, q, fp32 ? 1 : 0);
+    hipLaunchKernelGGL(k_qscan, dim3(1), dim3(1024), 0, st, q, fp32 ? 1 : 0);
+    hipLaunchKernelGGL(k_qscatter, dim3(qb), dim3(256), 0, st, q);
+    hipLaunchKernelGGL(k_qunits, dim3(512), dim3(256), 0, st, q, fp32 ? 1 : 0);
+  };
+  build_queue(0, early ? 1 : 2);
+  mark(5);
   // LC + DC, phase 1 then phase 2
   ScanArgs sa;
   sa.Q = queries;
@@ -1316,12 +1381,10 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   sa.any_retry = nullptr;
   sa.work = nullptr;
   sa.steal = sd.queue;
-  hipError_t err = hipSuccess;
   // the lane classes run one after another on the caller's stream, each a
   // persistent kernel over its own unit range.  (Running them concurrently
   // on separate streams was measured slower on the mid-size workload: scan
   // phase 2 took 1.86 ms against 1.50 ms serially.)
-  const int dt = dt_of(sd.lut_dtype);
   for (int ph = 1; ph <= 2; ++ph) {
     sa.sorted = ws.sorted + (ph == 2 ? npairs : 0);
     sa.unitoff = ws.unitoff + (ph == 2 ? (NB + 1) : 0);
@@ -1351,8 +1414,9 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
       if (err != hipSuccess) return err;
       hipLaunchKernelGGL(k_tau, dim3(sd.nq < 512 ? sd.nq : 512), dim3(256), tlds, st, ws.ccount, ws.ckey, ws.tau,
                          ws.kq, sd.kconst, sd.nq, sd.capq);
+      if (early) build_queue(1, 2);  // the full scan's queue: live pairs only
     }
-    mark(4 + ph);
+    mark(5 + ph);
     if (ph == 2) {
       // (timed with the merge stage: the phase-2 stage is its scan alone)
       // up to two re-runs of phase 2 for queries whose candidates overflowed,
@@ -1397,7 +1461,7 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   hipLaunchKernelGGL(k_merge_wave, dim3((sd.nq + 3) / 4), dim3(256), 0, st, ma2, sd.nq);
   hipLaunchKernelGGL(k_merge, dim3(sd.nq < 512 ? sd.nq : 512), dim3(256), mlds, st, ma2, sd.nq);
   if (sd.out_status) hipLaunchKernelGGL(k_status, dim3(1), dim3(64), 0, st, ws.flags, sd.out_status);
-  mark(7);
+  mark(8);
   return hipGetLastError();
 }
 

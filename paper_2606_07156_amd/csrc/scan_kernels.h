@@ -1174,3 +1174,190 @@ ScanFn pick_scan_ph2(int lwb, int M, int dt, int wpr);
 ScanFn pick_scan_ph3(int lwb, int M, int dt, int wpr);
 
 }  // namespace amp
+
+namespace amp {
+
+// ------------------------------------------------------------------ exact pair bases
+// The base of a (query, probed list) pair, sum over the subspaces of the
+// minimum of the exact integer LUT row (inner product: minus qi.ci), bounds
+// every integer distance estimate of its list from below.  A pair whose base
+// exceeds its query's phase-1 bound cannot reach the top-k: it is left out of
+// the full scan's work queue (the same test the scan applies after LUT pass
+// 1, made before any unit is formed).  L2 and L1: the LUT minima of every
+// pair (LUT pass 1 on MFMA, or on the VALU for L1); inner product: the table
+// is the query's, so its minima are taken once per query and each pair adds
+// its own -qi.ci.
+struct BaseArgs {
+  const float* Q;
+  const float* C;
+  const u32x4* bsw;
+  const u32x4* bsw16;
+  const int16_t* cbi16;
+  const int32_t* probes;
+  int64_t* pbase;          // [nq][npmax]
+  int nq, d, M, dsub, npmax, grid_e, grid_kind, metric;
+};
+
+constexpr int kBaseG = 16;  // pairs (rows of two 8-row MFMA tiles) per k_base workgroup
+
+__host__ __device__ inline ScanLds base_lds_layout(int M, int d) {
+  ScanLds L{};
+  int o = 0;
+  auto take = [&](int bytes) { int r = o; o += (bytes + 15) & ~15; return r; };
+  L.lut = 0;  // (no LUT: pass 1 only)
+  L.ri = take(kBaseG * ri_stride(d) * 2);
+  L.rr = take(kBaseG * M * 4);
+  L.lo = take(kBaseG * M * 4);
+  L.hi = take(kBaseG * M * 4);
+  L.ps = take(kBaseG * 4);
+  L.ctl = take(64);
+  L.total = o;
+  return L;
+}
+
+// the B fragments of one m-pair, issued together (as in the scan)
+template <int DT>
+__device__ __forceinline__ void base_frags(const BaseArgs& b, int mp, int lane, u32x4 (&Bt)[16], u32x4 (&Bd)[16]) {
+#pragma unroll
+  for (int jt = 0; jt < 16; ++jt) {
+    const size_t fi = ((size_t)mp * 16 + jt) * 64 + lane;
+    Bt[jt] = b.bsw[fi];
+    if constexpr (DT == DT_F16) Bd[jt] = b.bsw16[fi];
+    else Bd[jt] = (u32x4){0u, 0u, 0u, 0u};
+  }
+}
+
+// L2 / L1: kBaseG consecutive pair slots per workgroup (any queries, any
+// lists; empty slots have zero rows and write nothing)
+template <int DT>
+__global__ __launch_bounds__(kThreads) void k_base(BaseArgs b) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  const ScanLds L = base_lds_layout(b.M, b.d);
+  ScanArgs a{};
+  a.d = b.d;
+  a.dsub = b.dsub;
+  a.M = b.M;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int M = b.M;
+  const size_t n = (size_t)b.nq * b.npmax;
+  const size_t i0 = (size_t)blockIdx.x * kBaseG;
+  int* sp = reinterpret_cast<int*>(lds + L.ps);
+  if (tid < kBaseG) sp[tid] = i0 + tid < n ? b.probes[i0 + tid] : -1;
+  __syncthreads();
+  // RC onto the grid (the scan's arithmetic: FP32 subtraction, then the grid)
+  const int d4 = b.d >> 2, rs4 = ri_stride(b.d) >> 2;
+  for (int e = tid; e < kBaseG * d4; e += kThreads) {
+    const int g = e / d4, t4 = e - g * d4;
+    const int p = sp[g];
+    u32x2 v = {0u, 0u};
+    if (p >= 0) {
+      const size_t q = (i0 + g) / b.npmax;
+      const float4 qv = reinterpret_cast<const float4*>(b.Q + q * b.d)[t4];
+      const float4 cv = reinterpret_cast<const float4*>(b.C + (size_t)p * b.d)[t4];
+      const float rx = qv.x - cv.x, ry = qv.y - cv.y, rz = qv.z - cv.z, rw = qv.w - cv.w;
+      const uint32_t v0 = (uint32_t)grid_val(rx, b.grid_e, b.grid_kind) & 0xFFFFu;
+      const uint32_t v1 = (uint32_t)grid_val(ry, b.grid_e, b.grid_kind) & 0xFFFFu;
+      const uint32_t v2 = (uint32_t)grid_val(rz, b.grid_e, b.grid_kind) & 0xFFFFu;
+      const uint32_t v3 = (uint32_t)grid_val(rw, b.grid_e, b.grid_kind) & 0xFFFFu;
+      v = (u32x2){v0 | (v1 << 16), v2 | (v3 << 16)};
+    }
+    reinterpret_cast<u32x2*>(lds + L.ri)[g * rs4 + t4] = v;
+  }
+  __syncthreads();
+  const int16_t* ri = reinterpret_cast<const int16_t*>(lds + L.ri);
+  int32_t* lo = reinterpret_cast<int32_t*>(lds + L.lo);
+  if (b.metric == AMP_L1) {
+    // a thread per (pair, subspace) row: minimum over the codewords on the VALU
+    for (int e = tid; e < kBaseG * M; e += kThreads) {
+      const int g = e / M, m = e % M;
+      int rv[kMaxDsub];
+#pragma unroll
+      for (int t = 0; t < kMaxDsub; ++t) rv[t] = t < b.dsub ? (int)ri[g * ri_stride(b.d) + m * b.dsub + t] : 0;
+      int mn = 0x7FFFFFFF;
+      const int16_t* cb = b.cbi16 + (size_t)m * kKsub * 8;
+      for (int j = 0; j < kKsub; ++j) {
+        int v = 0;
+#pragma unroll
+        for (int t = 0; t < kMaxDsub; ++t) v += abs(rv[t] - (int)cb[j * 8 + t]);
+        mn = v < mn ? v : mn;
+      }
+      lo[e] = mn;
+    }
+  } else {
+    int32_t* rr = reinterpret_cast<int32_t*>(lds + L.rr);
+    for (int e = tid; e < kBaseG * M; e += kThreads) {
+      const int g = e / M, m = e % M;
+      int32_t sacc = 0;
+      for (int t = 0; t < b.dsub; ++t) {
+        const int v = ri[g * ri_stride(b.d) + m * b.dsub + t];
+        sacc += v * v;
+      }
+      rr[e] = sacc;
+    }
+    __syncthreads();
+    for (int mp = wave; mp < M / 2; mp += kThreads / 64) {
+      u32x4 Bt[16], Bd[16];
+      base_frags<DT>(b, mp, lane, Bt, Bd);
+      lut_mpair<32, kBaseG, DT, 1, false>(a, lds, L, M, kBaseG, mp, Bt, Bd);
+    }
+  }
+  __syncthreads();
+  if (tid < kBaseG && sp[tid] >= 0) {
+    int64_t s = 0;
+    for (int m = 0; m < M; ++m) s += lo[tid * M + m];
+    b.pbase[i0 + tid] = s;
+  }
+}
+
+// inner product: a workgroup per query; the minima of the query's table
+// (LUT pass 1 of one row), then base = sum of minima - qi.ci per probed list
+template <int DT>
+__global__ __launch_bounds__(kThreads) void k_base_ip(BaseArgs b) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  const ScanLds L = base_lds_layout(b.M, b.d);
+  ScanArgs a{};
+  a.d = b.d;
+  a.dsub = b.dsub;
+  a.M = b.M;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int M = b.M, q = blockIdx.x;
+  const int d4 = b.d >> 2, rs4 = ri_stride(b.d) >> 2;
+  for (int e = tid; e < kBaseG * d4; e += kThreads) {
+    const int g = e / d4, t4 = e - g * d4;
+    u32x2 v = {0u, 0u};
+    if (g == 0) {
+      const float4 qv = reinterpret_cast<const float4*>(b.Q + (size_t)q * b.d)[t4];
+      const uint32_t v0 = (uint32_t)grid_val(qv.x, b.grid_e, b.grid_kind) & 0xFFFFu;
+      const uint32_t v1 = (uint32_t)grid_val(qv.y, b.grid_e, b.grid_kind) & 0xFFFFu;
+      const uint32_t v2 = (uint32_t)grid_val(qv.z, b.grid_e, b.grid_kind) & 0xFFFFu;
+      const uint32_t v3 = (uint32_t)grid_val(qv.w, b.grid_e, b.grid_kind) & 0xFFFFu;
+      v = (u32x2){v0 | (v1 << 16), v2 | (v3 << 16)};
+    }
+    reinterpret_cast<u32x2*>(lds + L.ri)[g * rs4 + t4] = v;
+  }
+  __syncthreads();
+  for (int mp = wave; mp < M / 2; mp += kThreads / 64) {
+    u32x4 Bt[16], Bd[16];
+    base_frags<DT>(b, mp, lane, Bt, Bd);
+    lut_mpair<32, kBaseG, DT, 1, true>(a, lds, L, M, 1, mp, Bt, Bd);
+  }
+  __syncthreads();
+  const int32_t* lo = reinterpret_cast<const int32_t*>(lds + L.lo);
+  int64_t lsum = 0;  // every lane sums the row minima (wave-uniform)
+  for (int m = lane; m < M; m += 64) lsum += lo[m];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off);
+  const int16_t* qi = reinterpret_cast<const int16_t*>(lds + L.ri);
+  for (int r = wave; r < b.npmax; r += kThreads / 64) {
+    const int p = b.probes[(size_t)q * b.npmax + r];
+    if (p < 0) continue;  // wave-uniform
+    int acc = 0;
+    for (int t = lane; t < b.d; t += 64)
+      acc += (int)qi[t] * grid_val(b.C[(size_t)p * b.d + t], b.grid_e, b.grid_kind);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) b.pbase[(size_t)q * b.npmax + r] = lsum - acc;
+  }
+}
+
+}  // namespace amp
