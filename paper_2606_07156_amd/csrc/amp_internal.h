@@ -55,6 +55,7 @@ struct DeviceIndex {
   uint4* bsw = nullptr;        // [M/2][16][64] MFMA B fragments (8 bf16 each)
   uint4* bsw16 = nullptr;      // [M/2][16][64] FP16 dims fragments
   int16_t* cbi16 = nullptr;    // [M][256][8] grid codebook (L1 LUT build)
+  int16_t* ci16 = nullptr;     // [nlist][d] grid centroids (inner product: qi.ci, d')
   int32_t* lorder = nullptr;   // [nlist] lists by decreasing size (ties: id)
   int32_t* lpos = nullptr;     // [nlist] position of each list in lorder
   uint8_t* codes = nullptr;    // [N][M]
@@ -122,6 +123,16 @@ struct Workspace {
   uint8_t* xbits = nullptr;    // [nq][npmax] explicit widths (uploaded)
   uint64_t* tau = nullptr;     // [nq] pruning threshold key
   int64_t* pbase = nullptr;    // [nq][npmax] exact base of each pair (integer policies)
+  // inner product: the LUT is the query's (every probed list shares it), so
+  // it is built once per query
+  int16_t* qi16 = nullptr;     // [nq][d] queries on the operand grid
+  int32_t* iptab = nullptr;    // [nq][M][256] exact integer table (FP32 policy: FP32 dot products)
+  int32_t* iplo = nullptr;     // [nq][M] row minima of the integer table
+  int32_t* ipspan = nullptr;   // [nq] largest row span (max - min)
+  int64_t* iplsum = nullptr;   // [nq] sum of the row minima
+  uint16_t* iptq = nullptr;    // [nq][4][M][256] quantised tables, one per width the query uses
+  int32_t* ipsh = nullptr;     // [nq][4] their shifts
+  int32_t* ipmask = nullptr;   // [nq] widths the query's pairs use (bit b/4 - 1)
   uint8_t* retry = nullptr;    // [nq] query takes part in the phase-2 re-run
   int64_t* tau_id = nullptr;   // [nq] id part of the re-run's bound
   uint32_t* ccount = nullptr;  // [nq] candidate count

@@ -46,7 +46,7 @@ static amp_status dalloc(T** p, size_t n, std::vector<void*>* track = nullptr) {
 }
 
 static void free_device_index(DeviceIndex& d) {
-  void* ptrs[] = {d.centroids, d.cnorm, d.codebook, d.bsw, d.bsw16, d.cbi16, d.lorder, d.lpos, d.codes, d.ids,
+  void* ptrs[] = {d.centroids, d.cnorm, d.codebook, d.bsw, d.bsw16, d.cbi16, d.ci16, d.lorder, d.lpos, d.codes, d.ids,
                   d.offsets, d.radq, d.model.sv, d.model.beta, d.model.table};
   for (void* p : ptrs)
     if (p) hipFree(p);
@@ -217,7 +217,7 @@ static amp_status to_device_locked(amp_index* ix, int device) {
   const size_t nl = ix->nlist, dd = ix->d, M = ix->M, n = ix->n;
   if ((s = dalloc(&d.centroids, nl * dd)) || (s = dalloc(&d.cnorm, nl)) ||
       (s = dalloc(&d.codebook, M * kKsub * ix->dsub)) || (s = dalloc(&d.bsw, (M / 2) * 16 * 64)) ||
-      (s = dalloc(&d.bsw16, (M / 2) * 16 * 64)) || (s = dalloc(&d.cbi16, M * kKsub * 8)) ||
+      (s = dalloc(&d.bsw16, (M / 2) * 16 * 64)) || (s = dalloc(&d.cbi16, M * kKsub * 8)) || (s = dalloc(&d.ci16, nl * dd)) ||
       (s = dalloc(&d.lorder, nl)) || (s = dalloc(&d.lpos, nl)) ||
       (s = dalloc(&d.codes, std::max<size_t>(1, n * M))) || (s = dalloc(&d.ids, std::max<size_t>(1, n))) ||
       (s = dalloc(&d.offsets, nl + 1)) || (s = dalloc(&d.radq, nl))) {
@@ -465,6 +465,18 @@ static amp_status lay_out(const amp_index* ix, Workspace& w, size_t nq, size_t n
   AMP_TAKE(&w.xbits, npairs);
   AMP_TAKE(&w.tau, nq);
   AMP_TAKE(&w.pbase, npairs);
+  {
+    // inner-product tables (one LUT per query), else a token allocation
+    const bool ip = ix->metric == AMP_IP;
+    AMP_TAKE(&w.qi16, ip ? nq * ix->d : 1);
+    AMP_TAKE(&w.iptab, ip ? nq * ix->M * kKsub : 1);
+    AMP_TAKE(&w.iplo, ip ? nq * ix->M : 1);
+    AMP_TAKE(&w.ipspan, ip ? nq : 1);
+    AMP_TAKE(&w.iplsum, ip ? nq : 1);
+    AMP_TAKE(&w.iptq, ip ? nq * 4 * ix->M * kKsub : 1);
+    AMP_TAKE(&w.ipsh, ip ? nq * 4 : 1);
+    AMP_TAKE(&w.ipmask, ip ? nq : 1);
+  }
   AMP_TAKE(&w.retry, nq);
   AMP_TAKE(&w.tau_id, nq);
   AMP_TAKE(&w.ccount, nq);

@@ -32,6 +32,7 @@ struct ResetArgs {
   uint64_t* work;    // [4]
   uint64_t* tau;     // [nq]
   uint32_t* ccount;  // [nq]
+  int32_t* ipmask;   // [nq] or null
   size_t nq;
 };
 __global__ void k_reset(ResetArgs r) {
@@ -41,6 +42,7 @@ __global__ void k_reset(ResetArgs r) {
   for (size_t i = i0; i < r.nq; i += st) {
     r.tau[i] = ~0ull;
     r.ccount[i] = 0;
+    if (r.ipmask) r.ipmask[i] = 0;
   }
   if (i0 < 4) {
     r.flags[i0] = 0;
@@ -469,6 +471,8 @@ __global__ __launch_bounds__(256) void k_topn_wave(const float* __restrict__ D, 
 struct PairArgs {
   const float* Q;
   const float* C;
+  const int16_t* qi16;    // inner product: queries and centroids on the grid (d' = |qi - ci|^2)
+  const int16_t* ci16;
   const int32_t* probes;
   const int32_t* radq;
   const int64_t* offsets;
@@ -521,6 +525,19 @@ __global__ __launch_bounds__(256) void k_pairs(PairArgs a, ModelArgs ma) {
     const float4* qv = reinterpret_cast<const float4*>(a.Q + (size_t)q * a.d);
     const float4* cv = reinterpret_cast<const float4*>(a.C + (size_t)p * a.d);
     const bool l2 = a.metric != AMP_IP;  // L2 and L1: d' of the grid residual
+    if (!l2 && a.qi16) {
+      // inner product: both sides already on the grid
+      const u32x2* xq = reinterpret_cast<const u32x2*>(a.qi16 + (size_t)q * a.d);
+      const u32x2* xc = reinterpret_cast<const u32x2*>(a.ci16 + (size_t)p * a.d);
+      for (int i = t; i < (a.d >> 2); i += T) {
+        const u32x2 x = xq[i], c = xc[i];
+        const int v0 = (int)(int16_t)(x[0] & 0xFFFFu) - (int)(int16_t)(c[0] & 0xFFFFu);
+        const int v1 = (int)(int16_t)(x[0] >> 16) - (int)(int16_t)(c[0] >> 16);
+        const int v2 = (int)(int16_t)(x[1] & 0xFFFFu) - (int)(int16_t)(c[1] & 0xFFFFu);
+        const int v3 = (int)(int16_t)(x[1] >> 16) - (int)(int16_t)(c[1] >> 16);
+        dq2 += (int64_t)(v0 * v0 + v1 * v1) + (int64_t)(v2 * v2 + v3 * v3);
+      }
+    } else
     for (int i = t; i < (a.d >> 2); i += T) {
       const float4 x = qv[i], c = cv[i];
       int v0, v1, v2, v3;
@@ -1080,6 +1097,88 @@ __global__ void k_prep_bsw(const float* __restrict__ cb, int M, int dsub, int gr
   bsw16[idx] = (u32x4){h[0], h[1], h[2], h[3]};
 }
 
+// ------------------------------------------------------------------ inner-product tables
+// queries on the operand grid (inner product)
+__global__ void k_qgrid(const float* __restrict__ Q, int16_t* __restrict__ qi, size_t n, int grid_e, int grid_kind) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    qi[i] = (int16_t)grid_val(Q[i], grid_e, grid_kind);
+}
+
+// inner product, FP32 policy: each query's dot products q_m . c_mj in FP32
+// (the FMA chain of the scan's FP32 entries, in the same order)
+__global__ void k_iptab_f32(BaseArgs b) {
+  const size_t n = (size_t)b.nq * b.M * kKsub;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const size_t q = i / ((size_t)b.M * kKsub);
+    const int e = (int)(i - q * b.M * kKsub), m = e >> 8;
+    const float* r = b.Q + q * b.d + m * b.dsub;
+    const float* c = b.codebook + (size_t)e * b.dsub;
+    float dot = 0.f;
+#pragma unroll
+    for (int t = 0; t < kMaxDsub; ++t)
+      if (t < b.dsub) dot = fmaf(r[t], c[t], dot);
+    b.iptab[i] = __float_as_int(dot);
+  }
+}
+
+// inner product: base of each pair = sum of its query's row minima - qi.ci
+// (a wave per pair, exact integers)
+__global__ __launch_bounds__(256) void k_ipbase(BaseArgs b) {
+  const int lane = threadIdx.x & 63;
+  const size_t i = (size_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= (size_t)b.nq * b.npmax) return;
+  const int p = b.probes[i];
+  if (p < 0) return;
+  const size_t q = i / b.npmax;
+  const u32x2* qv = reinterpret_cast<const u32x2*>(b.qi16 + q * b.d);
+  const u32x2* cv = reinterpret_cast<const u32x2*>(b.ci16 + (size_t)p * b.d);
+  int acc = 0;
+  for (int t4 = lane; t4 < (b.d >> 2); t4 += 64) {
+    const u32x2 x = qv[t4], c = cv[t4];
+    acc += (int)(int16_t)(x[0] & 0xFFFFu) * (int)(int16_t)(c[0] & 0xFFFFu) +
+           (int)(int16_t)(x[0] >> 16) * (int)(int16_t)(c[0] >> 16) +
+           (int)(int16_t)(x[1] & 0xFFFFu) * (int)(int16_t)(c[1] & 0xFFFFu) +
+           (int)(int16_t)(x[1] >> 16) * (int)(int16_t)(c[1] >> 16);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (lane == 0) {
+    b.pbase[i] = b.iplsum[q] - acc;
+    atomicOr(&b.ipmask[q], 1 << ((b.pbits[i] >> 2) - 1));  // the widths the query's tables are needed at
+  }
+}
+
+// inner product, integer policies: each query's table quantised at every
+// width its pairs use: shift s from the query's span (smallest with
+// (span + hf(s)) >> s <= 2^b - 1), entries (T - min_m + hf(s)) >> s as
+// uint16; eight entries per thread
+__global__ void k_ipq(BaseArgs b) {
+  const size_t per = (size_t)b.M * kKsub / 8;
+  const size_t n = (size_t)b.nq * 4 * per;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const size_t qw = i / per;
+    const int q = (int)(qw >> 2), wi = (int)(qw & 3);
+    if (!(b.ipmask[q] & (1 << wi))) continue;
+    const int bits = 4 * (wi + 1);
+    const int64_t top = (1ll << bits) - 1, R = b.ipspan[q];
+    int sh = 0;
+    while (((R + (sh ? (1ll << (sh - 1)) : 0)) >> sh) > top) ++sh;
+    const int hf = sh ? 1 << (sh - 1) : 0;
+    const size_t e0 = (i - qw * per) * 8;
+    if (e0 == 0) b.ipsh[qw] = sh;
+    const int m = (int)(e0 >> 8);
+    const int off = hf - b.iplo[(size_t)q * b.M + m];
+    const int32_t* T = b.iptab + (size_t)q * b.M * kKsub + e0;
+    uint32_t w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t lo16 = (uint32_t)((T[2 * k] + off) >> sh), hi16 = (uint32_t)((T[2 * k + 1] + off) >> sh);
+      w[k] = lo16 | (hi16 << 16);
+    }
+    *reinterpret_cast<u32x4*>(b.iptq + qw * ((size_t)b.M * kKsub) + e0) = (u32x4){w[0], w[1], w[2], w[3]};
+  }
+}
+
 // ------------------------------------------------------------------ host launchers
 template <typename K>
 static void* kaddr(K k) { return reinterpret_cast<void*>(k); }
@@ -1091,6 +1190,9 @@ hipError_t launch_prep_index(const amp_index* ix, hipStream_t st) {
   const int total = (ix->M / 2) * 16 * 64;
   hipLaunchKernelGGL(k_prep_cbi, dim3((ix->M * kKsub * 8 + 255) / 256), dim3(256), 0, st, dv.codebook, ix->M,
                      ix->dsub, ix->grid_e, ix->grid_kind, dv.cbi16);
+  const size_t nc = (size_t)ix->nlist * ix->d;
+  hipLaunchKernelGGL(k_qgrid, dim3((unsigned)std::min<size_t>((nc + 255) / 256, 65536)), dim3(256), 0, st,
+                     dv.centroids, dv.ci16, nc, ix->grid_e, ix->grid_kind);
   hipLaunchKernelGGL(k_prep_bsw, dim3((total + 255) / 256), dim3(256), 0, st, dv.codebook, ix->M, ix->dsub,
                      ix->grid_e, ix->grid_kind, reinterpret_cast<u32x4*>(dv.bsw),
                      reinterpret_cast<u32x4*>(dv.bsw16));
@@ -1173,6 +1275,7 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
     ra.work = ws.work;
     ra.tau = ws.tau;
     ra.ccount = ws.ccount;
+    ra.ipmask = sd.metric == AMP_IP ? ws.ipmask : nullptr;
     ra.nq = (size_t)sd.nq;
     hipLaunchKernelGGL(k_reset, dim3(256), dim3(256), 0, st, ra);
   }
@@ -1232,10 +1335,20 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
                        ws.npq ? ws.npq : nullptr, sd.npconst, sd.npmax, ws.probes);
   }
   mark(2);
+  const bool ipm = sd.metric == AMP_IP;
+  // inner product, integer policies: the queries on the grid (predictor,
+  // table build, pair bases)
+  if (ipm && !fp32) {
+    const size_t nel = (size_t)sd.nq * sd.d;
+    hipLaunchKernelGGL(k_qgrid, dim3((unsigned)std::min<size_t>((nel + 255) / 256, 65536)), dim3(256), 0, st, queries,
+                       ws.qi16, nel, sd.grid_e, sd.grid_kind);
+  }
   // PPM
   PairArgs pa;
   pa.Q = queries;
   pa.C = dv.centroids;
+  pa.qi16 = (ipm && !fp32) ? ws.qi16 : nullptr;
+  pa.ci16 = dv.ci16;
   pa.probes = ws.probes;
   pa.radq = dv.radq;
   pa.offsets = dv.offsets;
@@ -1268,15 +1381,26 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   const bool early = !fp32;
   const int dt = dt_of(sd.lut_dtype);
   hipError_t err = hipSuccess;
-  if (early) {
+  {
     BaseArgs ba;
     ba.Q = queries;
     ba.C = dv.centroids;
     ba.bsw = reinterpret_cast<const u32x4*>(dv.bsw);
     ba.bsw16 = reinterpret_cast<const u32x4*>(dv.bsw16);
     ba.cbi16 = dv.cbi16;
+    ba.ci16 = dv.ci16;
     ba.probes = ws.probes;
     ba.pbase = ws.pbase;
+    ba.qi16 = ws.qi16;
+    ba.iptab = ws.iptab;
+    ba.iplo = ws.iplo;
+    ba.ipspan = ws.ipspan;
+    ba.iplsum = ws.iplsum;
+    ba.iptq = ws.iptq;
+    ba.ipsh = ws.ipsh;
+    ba.ipmask = ws.ipmask;
+    ba.pbits = ws.pbits;
+    ba.codebook = dv.codebook;
     ba.nq = sd.nq;
     ba.d = sd.d;
     ba.M = sd.M;
@@ -1285,17 +1409,32 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
     ba.grid_e = sd.grid_e;
     ba.grid_kind = sd.grid_kind;
     ba.metric = sd.metric;
-    const size_t blds = base_lds_layout(sd.M, sd.d).total;
-    if (sd.metric == AMP_IP) {
-      auto fn = dt == DT_F16 ? k_base_ip<DT_F16> : k_base_ip<DT_BF16>;
-      if ((err = hipFuncSetAttribute(kaddr(fn), hipFuncAttributeMaxDynamicSharedMemorySize, (int)blds)) != hipSuccess)
+    if (ipm && fp32) {
+      // the queries' FP32 dot-product tables
+      const size_t n = (size_t)sd.nq * sd.M * kKsub;
+      hipLaunchKernelGGL(k_iptab_f32, dim3((unsigned)std::min<size_t>((n + 255) / 256, 1 << 20)), dim3(256), 0, st,
+                         ba);
+    } else if (ipm) {
+      // the queries' exact tables with their minima, then the pair bases
+      const size_t tlds = base_lds_layout(kTabQ, sd.M, sd.d).total;
+      auto fn = dt == DT_F16 ? k_iptab<DT_F16> : k_iptab<DT_BF16>;
+      if ((err = hipFuncSetAttribute(kaddr(fn), hipFuncAttributeMaxDynamicSharedMemorySize, (int)tlds)) != hipSuccess)
         return err;
-      hipLaunchKernelGGL(fn, dim3(sd.nq), dim3(kThreads), blds, st, ba);
-    } else {
+      hipLaunchKernelGGL(fn, dim3((sd.nq + kTabQ - 1) / kTabQ), dim3(kThreads), tlds, st, ba);
+      hipLaunchKernelGGL(k_ipbase, dim3((unsigned)((npairs + 3) / 4)), dim3(256), 0, st, ba);
+      const size_t nq8 = (size_t)sd.nq * 4 * sd.M * kKsub / 8;
+      hipLaunchKernelGGL(k_ipq, dim3((unsigned)std::min<size_t>((nq8 + 255) / 256, 1 << 20)), dim3(256), 0, st, ba);
+    } else if (early) {
+      // L2 / L1: every pair's LUT minima, as many pairs per workgroup as
+      // fit 64 KB of residual rows (128 at most): they share the B fragments
+      int G = 128;
+      while (G > 8 && (size_t)G * ri_stride(sd.d) * 2 > 65536) G >>= 1;
+      ba.G = G;
+      const size_t blds = base_lds_layout(G, sd.M, sd.d).total;
       auto fn = dt == DT_F16 ? k_base<DT_F16> : k_base<DT_BF16>;
       if ((err = hipFuncSetAttribute(kaddr(fn), hipFuncAttributeMaxDynamicSharedMemorySize, (int)blds)) != hipSuccess)
         return err;
-      hipLaunchKernelGGL(fn, dim3((unsigned)((npairs + kBaseG - 1) / kBaseG)), dim3(kThreads), blds, st, ba);
+      hipLaunchKernelGGL(fn, dim3((unsigned)((npairs + G - 1) / G)), dim3(kThreads), blds, st, ba);
     }
   }
   mark(4);
@@ -1381,6 +1520,11 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   sa.any_retry = nullptr;
   sa.work = nullptr;
   sa.steal = sd.queue;
+  sa.iptab = ws.iptab;
+  sa.iptq = ws.iptq;
+  sa.ipsh = ws.ipsh;
+  sa.pbase_g = ws.pbase;
+  sa.tab_out = nullptr;
   // the lane classes run one after another on the caller's stream, each a
   // persistent kernel over its own unit range.  (Running them concurrently
   // on separate streams was measured slower on the mid-size workload: scan

@@ -32,6 +32,14 @@ struct ScanArgs {
   const int64_t* tau_id;    // phase 3: id of the bound's (distance, id) key
   const int32_t* any_retry; // phase 3: non-zero if any query takes part
   uint64_t* work;           // phase 2 work counters (code bytes scanned, live pairs, dead pairs) or null
+  // inner product: the query's table built once per query (integer: exact T
+  // with its row minima and span; FP32 policy: FP32 dot products), and the
+  // pairs' exact bases
+  const int32_t* iptab;     // [nq][M][256] (FP32 policy: the FP32 dot products)
+  const uint16_t* iptq;     // [nq][4][M][256] quantised tables per width
+  const int32_t* ipsh;      // [nq][4] their shifts
+  const int64_t* pbase_g;   // [nq][npmax]
+  int32_t* tab_out;         // LUT pass 1 that also stores T (the per-query table build)
   int nq, d, M, dsub, nlist, npmax, grid_e, grid_kind, metric, kconst, kmax, cls;
   int steal;                // unit queue: 0 one counter, 1 per-XCD ranges with stealing
   int64_t chunk;
@@ -88,7 +96,7 @@ __host__ __device__ constexpr int ri_stride(int d) { return d + 16; }
 
 // LDS carve-up of one scan workgroup (all offsets in bytes, 16-aligned)
 struct ScanLds {
-  int lut, ri, rr, lo, hi, pq, pb, ps, pbase, psig, lmin, ctl, total;
+  int lut, ri, rr, lo, hi, pq, pb, ps, pbase, psig, pid, lmin, ctl, total;
 };
 __host__ __device__ inline ScanLds scan_lds_layout(int G, int wpr, int M, int d, bool fp32, int phase) {
   ScanLds L;
@@ -104,6 +112,7 @@ __host__ __device__ inline ScanLds scan_lds_layout(int G, int wpr, int M, int d,
   L.ps = take(G * 4);
   L.pbase = take(G * 8);
   L.psig = take(G * 4);
+  L.pid = take(G * 4);
   // phase 1 keeps per-thread minima after the scan: reuse the LUT space
   L.lmin = L.lut;
   if (phase == 1 && G * kThreadsP2 * 4 > M * kKsub * wpr * 4) L.lmin = take(G * kThreadsP2 * 4);
@@ -155,6 +164,121 @@ __device__ __forceinline__ void lut_row_load(lds_u32* lut, int row, uint32_t* w)
   }
 }
 
+// A operand of one 8-pair tile gt of an m-pair: rows (subspace slot ms,
+// pair g) = ms*8 + g; K holds [dims m0 | aug m0 | dims m1 | aug m1], 8 slots
+// each (see lut_mpair).  Pairs at or beyond np_u get zero rows.
+template <int DT, int PASS, bool IP>
+__device__ __forceinline__ void mpair_a_tile(const ScanArgs& a, const char* lds, const ScanLds& L, int M, int np_u,
+                                             int mp, int gt, bf16x8& A, u32x4& Ad) {
+  constexpr int pass = PASS;
+  constexpr bool ip = IP;
+  const int lane = threadIdx.x & 63;
+  const int16_t* ri = reinterpret_cast<const int16_t*>(lds + L.ri);
+  const int32_t* rr = reinterpret_cast<const int32_t*>(lds + L.rr);
+  const int32_t* lo = reinterpret_cast<const int32_t*>(lds + L.lo);
+  const int32_t* ps = reinterpret_cast<const int32_t*>(lds + L.ps);
+  const int row = lane & 15, kg = lane >> 4;
+  const int ms_row = row >> 3;
+  const int dsub = a.dsub;
+  const int rs = ri_stride(a.d);
+  const int g = gt * 8 + (row & 7);
+  const int m = 2 * mp + ms_row;
+  uint32_t pk[4] = {0, 0, 0, 0}, pd[4] = {0, 0, 0, 0};
+  if (g < np_u && (kg >> 1) == ms_row) {
+    const int s = pass != 2 ? 0 : ps[g];
+    const float sc = DT == DT_BF16 ? ldexpf(1.f, -s) : 1.f;
+    if ((kg & 1) == 0) {
+      const int coef = ip ? -1 : -2;
+      // the subspace's grid residual: one 16-byte read when d_sub = 8
+      // (rows and subspaces 16-byte aligned), else element by element
+      int rv[8];
+      if (dsub == 8 && (a.d & 7) == 0) {
+        const u32x4 w = *reinterpret_cast<const u32x4*>(ri + g * rs + m * 8);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          rv[2 * t] = (int)(int16_t)(w[t] & 0xFFFFu);
+          rv[2 * t + 1] = (int)(int16_t)(w[t] >> 16);
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) rv[t] = t < dsub ? (int)ri[g * rs + m * dsub + t] : 0;
+      }
+      if constexpr (DT == DT_BF16) {
+        float v[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) v[t] = t < dsub ? (float)(coef * rv[t]) * sc : 0.f;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) pk[t] = bf16_bits(v[2 * t]) | (bf16_bits(v[2 * t + 1]) << 16);
+      } else {
+        float v[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) v[t] = t < dsub ? (float)(coef * rv[t]) : 0.f;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) pd[t] = f16_bits(v[2 * t]) | (f16_bits(v[2 * t + 1]) << 16);
+      }
+    } else {
+      int32_t X = ip ? 0 : rr[g * M + m];
+      if (pass == 2) X += lo[g * M + m];  // lo holds off = hf(s) - min after pass 1
+      const float sg = X < 0 ? -1.f : 1.f;
+      const uint32_t ax = (uint32_t)(X < 0 ? -X : X);
+      const float cm = ip ? 0.f : sc;
+      float v[8];
+      v[0] = 65536.f * cm;
+      v[1] = 256.f * cm;
+      v[2] = cm;
+      v[3] = sg * (float)(ax >> 16) * sc;
+      v[4] = sg * (float)((ax >> 8) & 255u) * sc;
+      v[5] = sg * (float)(ax & 255u) * sc;
+      v[6] = 0.f;
+      v[7] = 0.f;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) pk[t] = bf16_bits(v[2 * t]) | (bf16_bits(v[2 * t + 1]) << 16);
+    }
+  }
+  u32x4 u = {pk[0], pk[1], pk[2], pk[3]};
+  A = __builtin_bit_cast(bf16x8, u);
+  Ad = (u32x4){pd[0], pd[1], pd[2], pd[3]};
+}
+
+// Row minima of an m-pair's exact integer LUT for np_u pairs (L2: min over
+// the 256 codewords of T, written to L.lo), one 8-pair tile at a time, so
+// that only one tile's accumulators are live: the B fragments (kept in
+// registers) serve any number of tiles.
+template <int DT>
+__device__ __forceinline__ void lut_row_minima(const ScanArgs& a, char* lds, const ScanLds& L, int M, int np_u,
+                                               int mp, const u32x4 (&B)[16], const u32x4 (&Bd)[16]) {
+  const int lane = threadIdx.x & 63, kg = lane >> 4;
+  int32_t* lo = reinterpret_cast<int32_t*>(lds + L.lo);
+  const int m_out = 2 * mp + (kg >> 1);
+  const int ntiles = (np_u + 7) >> 3;
+#pragma unroll 1
+  for (int gt = 0; gt < ntiles; ++gt) {
+    bf16x8 A;
+    u32x4 Ad;
+    mpair_a_tile<DT, 1, false>(a, lds, L, M, np_u, mp, gt, A, Ad);
+    int mn[4] = {0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF};
+#pragma unroll
+    for (int jt = 0; jt < 16; ++jt) {
+      f4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, __builtin_bit_cast(bf16x8, B[jt]),
+                                                       (f4){0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+      if constexpr (DT == DT_F16)
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, Ad),
+                                                     __builtin_bit_cast(f16x8, Bd[jt]), acc, 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int t = __float_as_int(acc[i]);  // exact, non-negative: bit patterns order as integers
+        mn[i] = t < mn[i] ? t : mn[i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int v = (int)__int_as_float(row16_reduce<false>(mn[i]));
+      const int g = gt * 8 + 4 * (kg & 1) + i;
+      if ((lane & 15) == 15 && g < np_u) lo[g * M + m_out] = v;
+    }
+  }
+}
+
 // One m-pair of the integer LUT of a work unit.  Rows of the A operand are
 // (subspace slot ms, pair g) = ms*8 + g; K holds [dims m0 | aug m0 | dims m1 |
 // aug m1], 8 slots each.  The aug slots carry |cbi|^2 (digits in B, powers
@@ -193,65 +317,7 @@ __device__ __forceinline__ void lut_mpair(const ScanArgs& a, char* lds, const Sc
   bf16x8 A[NGT];
   u32x4 Ad[NGT];
 #pragma unroll
-  for (int gt = 0; gt < NGT; ++gt) {
-    const int g = gt * 8 + (row & 7);
-    const int m = 2 * mp + ms_row;
-    uint32_t pk[4] = {0, 0, 0, 0}, pd[4] = {0, 0, 0, 0};
-    if (g < np_u && (kg >> 1) == ms_row) {
-      const int s = pass == 1 ? 0 : ps[g];
-      const float sc = DT == DT_BF16 ? ldexpf(1.f, -s) : 1.f;
-      if ((kg & 1) == 0) {
-        const int coef = ip ? -1 : -2;
-        // the subspace's grid residual: one 16-byte read when d_sub = 8
-        // (rows and subspaces 16-byte aligned), else element by element
-        int rv[8];
-        if (dsub == 8 && (a.d & 7) == 0) {
-          const u32x4 w = *reinterpret_cast<const u32x4*>(ri + g * rs + m * 8);
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            rv[2 * t] = (int)(int16_t)(w[t] & 0xFFFFu);
-            rv[2 * t + 1] = (int)(int16_t)(w[t] >> 16);
-          }
-        } else {
-#pragma unroll
-          for (int t = 0; t < 8; ++t) rv[t] = t < dsub ? (int)ri[g * rs + m * dsub + t] : 0;
-        }
-        if constexpr (DT == DT_BF16) {
-          float v[8];
-#pragma unroll
-          for (int t = 0; t < 8; ++t) v[t] = t < dsub ? (float)(coef * rv[t]) * sc : 0.f;
-#pragma unroll
-          for (int t = 0; t < 4; ++t) pk[t] = bf16_bits(v[2 * t]) | (bf16_bits(v[2 * t + 1]) << 16);
-        } else {
-          float v[8];
-#pragma unroll
-          for (int t = 0; t < 8; ++t) v[t] = t < dsub ? (float)(coef * rv[t]) : 0.f;
-#pragma unroll
-          for (int t = 0; t < 4; ++t) pd[t] = f16_bits(v[2 * t]) | (f16_bits(v[2 * t + 1]) << 16);
-        }
-      } else {
-        int32_t X = ip ? 0 : rr[g * M + m];
-        if (pass == 2) X += lo[g * M + m];  // lo holds off = hf(s) - min after pass 1
-        const float sg = X < 0 ? -1.f : 1.f;
-        const uint32_t ax = (uint32_t)(X < 0 ? -X : X);
-        const float cm = ip ? 0.f : sc;
-        float v[8];
-        v[0] = 65536.f * cm;
-        v[1] = 256.f * cm;
-        v[2] = cm;
-        v[3] = sg * (float)(ax >> 16) * sc;
-        v[4] = sg * (float)((ax >> 8) & 255u) * sc;
-        v[5] = sg * (float)(ax & 255u) * sc;
-        v[6] = 0.f;
-        v[7] = 0.f;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) pk[t] = bf16_bits(v[2 * t]) | (bf16_bits(v[2 * t + 1]) << 16);
-      }
-    }
-    u32x4 u = {pk[0], pk[1], pk[2], pk[3]};
-    A[gt] = __builtin_bit_cast(bf16x8, u);
-    Ad[gt] = (u32x4){pd[0], pd[1], pd[2], pd[3]};
-  }
+  for (int gt = 0; gt < NGT; ++gt) mpair_a_tile<DT, PASS, IP>(a, lds, L, M, np_u, mp, gt, A[gt], Ad[gt]);
   // D rows of this lane: (ms = kg>>1, g = gt*8 + 4*(kg&1) + i), column j
   const int m_out = 2 * mp + (kg >> 1);
   float rsc[NGT][4];  // 2^-s of each row (used after a non-BF16 build)
@@ -260,7 +326,7 @@ __device__ __forceinline__ void lut_mpair(const ScanArgs& a, char* lds, const Sc
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int g = gt * 8 + 4 * (kg & 1) + i;
-      rsc[gt][i] = (DT == DT_BF16 || pass == 1 || g >= np_u) ? 1.f : ldexpf(1.f, -ps[g]);
+      rsc[gt][i] = (DT == DT_BF16 || pass != 2 || g >= np_u) ? 1.f : ldexpf(1.f, -ps[g]);
     }
   int mn[NGT][4], mx[NGT][4];
   uint32_t wv8[NGT];  // packed words of the interleaved 8-bit layout
@@ -281,7 +347,7 @@ __device__ __forceinline__ void lut_mpair(const ScanArgs& a, char* lds, const Sc
                                                      __builtin_bit_cast(f16x8, Bdj), acc, 0, 0, 0);
       }
       const int g0 = gt * 8 + 4 * (kg & 1);
-      if constexpr (PASS == 1) {
+      if constexpr (PASS == 1 || PASS == 4) {
         // exact integers: for L2 (T >= 0) the float bit patterns order as
         // integers; inner product values may be negative and are converted
 #pragma unroll
@@ -289,6 +355,14 @@ __device__ __forceinline__ void lut_mpair(const ScanArgs& a, char* lds, const Sc
           const int t = ip ? (int)acc[i] : __float_as_int(acc[i]);
           mn[gt][i] = t < mn[gt][i] ? t : mn[gt][i];
           mx[gt][i] = t > mx[gt][i] ? t : mx[gt][i];
+          if constexpr (PASS == 4) {
+            // the per-query table build also keeps the exact entries
+            const int g = g0 + i;
+            if (g < np_u) {
+              const int q = reinterpret_cast<const int32_t*>(lds + L.pq)[g];
+              a.tab_out[((size_t)q * M + m_out) * kKsub + j] = ip ? t : (int)acc[i];
+            }
+          }
         }
       } else if (g0 < G) {
         uint32_t qv[4];
@@ -320,7 +394,7 @@ __device__ __forceinline__ void lut_mpair(const ScanArgs& a, char* lds, const Sc
       }
     }
   }
-  if constexpr (PASS == 1) {
+  if constexpr (PASS == 1 || PASS == 4) {
 #pragma unroll
     for (int gt = 0; gt < NGT; ++gt)
 #pragma unroll
@@ -380,12 +454,15 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
     const int64_t n_list = a.offsets[p + 1] - L0;
     const int64_t v0 = (int64_t)unit.w * a.chunk;
     const int64_t v1 = v0 + a.chunk < n_list ? v0 + a.chunk : n_list;
+    int32_t* ppid = reinterpret_cast<int32_t*>(lds + L.pid);
     if (tid < G) {
       if (tid < np_u) {
         const int pid = a.sorted[unit.y + tid];
+        ppid[tid] = pid;
         pq[tid] = pid / a.npmax;
         pb[tid] = a.pbits[pid];
       } else {
+        ppid[tid] = -1;
         pq[tid] = -1;
         pb[tid] = 16;
       }
@@ -411,7 +488,7 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
     // and centroids 16-byte aligned); (pair, quad) advanced without division
     const bool ip = a.metric == AMP_IP;
     const bool l1 = a.metric == AMP_L1;
-    {
+    if (FP || !ip) {
       const int d4 = a.d >> 2;
       const int gstep = kThreads / d4, tstep = kThreads - gstep * d4;
       int g = tid / d4, t4 = tid - g * d4;
@@ -525,9 +602,15 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
               sv = ad;
             } else {
               float dot = 0.f;
+              if constexpr (MM == 1) {
+                // the query's FP32 dot products, built once per query (the
+                // same FMA chain)
+                dot = __int_as_float(a.iptab[((size_t)pq[g] * M + m) * kKsub + own_j]);
+              } else {
 #pragma unroll
-              for (int t = 0; t < kMaxDsub; ++t)
-                if (t < a.dsub) dot = fmaf(r[t], c[t], dot);
+                for (int t = 0; t < kMaxDsub; ++t)
+                  if (t < a.dsub) dot = fmaf(r[t], c[t], dot);
+              }
               if constexpr (MM == 1) {
                 // inner product: the pair's base -q.c (sum of the subspace
                 // partials) is folded into subspace 0's entries
@@ -565,6 +648,67 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
       if (l1) fill(std::integral_constant<int, 2>{});
       else if (ip) fill(std::integral_constant<int, 1>{});
       else fill(std::integral_constant<int, 0>{});
+    } else if (ip) {
+      // inner product: the LUT is the query's, quantised once per (query,
+      // width) with the query's shift; the pair's base is its exact base.
+      // The unit copies its pairs' tables into the packed rows.
+      if (tid == 0) *reinterpret_cast<int*>(lds + L.ctl + 12) = 0;  // live-pair count of the unit
+      __syncthreads();
+      int32_t* pw = reinterpret_cast<int32_t*>(lds + L.lo);  // [G]: table index (query, width) of each pair
+      if (tid < G) {
+        if (tid < np_u) {
+          const int wi = (pb[tid] >> 2) - 1;
+          pw[tid] = pq[tid] * 4 + wi;
+          ps[tid] = a.ipsh[pq[tid] * 4 + wi];
+          pbase[tid] = a.pbase_g[ppid[tid]];
+        }
+        if (PHASE >= 2 && pair_threshold(tid)) atomicAdd(reinterpret_cast<int*>(lds + L.ctl + 12), 1);
+      }
+      __syncthreads();
+      if constexpr (PHASE >= 2) {
+        const int nlive = *reinterpret_cast<int*>(lds + L.ctl + 12);
+        if (PHASE == 2 && tid == 0 && a.work) {
+          uint64_t* wc = reinterpret_cast<uint64_t*>(lds + L.ctl + 32);
+          wc[0] += (uint64_t)(nlive * (v1 - v0) * M);
+          wc[1] += (uint64_t)nlive;
+          wc[2] += (uint64_t)(np_u - nlive);
+        }
+        if (!nlive) {
+          fetch_next();
+          return;
+        }
+      }
+      uint32_t* lut = reinterpret_cast<uint32_t*>(lds + L.lut);
+      const size_t tsz = (size_t)M * kKsub;
+      // eight entries (one 16-byte load per pair) per thread and step
+      for (int e8 = tid; e8 < M * kKsub / 8; e8 += kThreads) {
+        uint32_t wds[8][WPR];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+#pragma unroll
+          for (int w = 0; w < WPR; ++w) wds[k][w] = 0;
+#pragma unroll
+        for (int w = 0; w < WPR; ++w)
+#pragma unroll
+          for (int f = 0; f < W; ++f) {
+            const int g = PairSlot<LWB, WPR>::pair(w, f);
+            if (g < np_u) {
+              const u32x4 x = *reinterpret_cast<const u32x4*>(a.iptq + (size_t)pw[g] * tsz + (size_t)e8 * 8);
+#pragma unroll
+              for (int k = 0; k < 8; ++k) {
+                const uint32_t qv = (x[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
+                wds[k][w] |= LWB == 32 ? qv : (qv << (f * LWB));
+              }
+            }
+          }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          uint32_t* dst = lut + ((size_t)e8 * 8 + k) * WPR;
+#pragma unroll
+          for (int w = 0; w < WPR; ++w) dst[w] = wds[k][w];
+        }
+      }
+      __syncthreads();
     } else {
       int32_t* rr = reinterpret_cast<int32_t*>(lds + L.rr);
       const int16_t* ri = reinterpret_cast<const int16_t*>(lds + L.ri);
@@ -584,7 +728,7 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
           for (int t = 0; t < a.dsub; ++t) {
             const int v = ri[g * ri_stride(a.d) + m * a.dsub + t];
             // L2: |ri|^2 of the subspace; IP: qi.ci of the subspace (base term)
-            sacc += ip ? v * grid_val(a.C[(size_t)p * a.d + m * a.dsub + t], a.grid_e, a.grid_kind) : v * v;
+            sacc += v * v;
           }
         }
         rr[e] = sacc;
@@ -608,7 +752,6 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
       };
       using P1 = std::integral_constant<int, 1>;
       using P2 = std::integral_constant<int, 2>;
-      using IPt = std::integral_constant<bool, true>;
       using L2t = std::integral_constant<bool, false>;
       // L1: T[m][j] = sum_t |ri_t - cbi_t| on the VALU (not a product, no
       // MFMA), exact integers.  Pass 1: a thread per (pair, subspace) row
@@ -667,7 +810,6 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
         }
       };
       if (l1) build_l1(1);
-      else if (ip) build(P1{}, IPt{});
       else build(P1{}, L2t{});
       if (tid == 0) *reinterpret_cast<int*>(lds + L.ctl + 12) = 0;  // live-pair count of the unit
       __syncthreads();
@@ -731,7 +873,6 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
       }
       __syncthreads();
       if (l1) build_l1(2);
-      else if (ip) build(P2{}, IPt{});
       else build(P2{}, L2t{});
       __syncthreads();
     }
@@ -1185,7 +1326,7 @@ namespace amp {
 // the full scan's work queue (the same test the scan applies after LUT pass
 // 1, made before any unit is formed).  L2 and L1: the LUT minima of every
 // pair (LUT pass 1 on MFMA, or on the VALU for L1); inner product: the table
-// is the query's, so its minima are taken once per query and each pair adds
+// is the query's, built once per query with its minima, and each pair adds
 // its own -qi.ci.
 struct BaseArgs {
   const float* Q;
@@ -1193,23 +1334,35 @@ struct BaseArgs {
   const u32x4* bsw;
   const u32x4* bsw16;
   const int16_t* cbi16;
+  const int16_t* ci16;     // [nlist][d] grid centroids
   const int32_t* probes;
   int64_t* pbase;          // [nq][npmax]
+  // inner product
+  int16_t* qi16;           // [nq][d] queries on the grid
+  int32_t* iptab;          // [nq][M][256]
+  int32_t* iplo;           // [nq][M]
+  int32_t* ipspan;         // [nq]
+  int64_t* iplsum;         // [nq]
+  uint16_t* iptq;          // [nq][4][M][256]
+  int32_t* ipsh;           // [nq][4]
+  int32_t* ipmask;         // [nq]
+  const uint8_t* pbits;    // [nq][npmax]
+  const float* codebook;   // FP32 policy table
   int nq, d, M, dsub, npmax, grid_e, grid_kind, metric;
+  int G;                   // pairs per workgroup of k_base
 };
 
-constexpr int kBaseG = 16;  // pairs (rows of two 8-row MFMA tiles) per k_base workgroup
-
-__host__ __device__ inline ScanLds base_lds_layout(int M, int d) {
+__host__ __device__ inline ScanLds base_lds_layout(int G, int M, int d) {
   ScanLds L{};
   int o = 0;
   auto take = [&](int bytes) { int r = o; o += (bytes + 15) & ~15; return r; };
   L.lut = 0;  // (no LUT: pass 1 only)
-  L.ri = take(kBaseG * ri_stride(d) * 2);
-  L.rr = take(kBaseG * M * 4);
-  L.lo = take(kBaseG * M * 4);
-  L.hi = take(kBaseG * M * 4);
-  L.ps = take(kBaseG * 4);
+  L.ri = take(G * ri_stride(d) * 2);
+  L.rr = take(G * M * 4);
+  L.lo = take(G * M * 4);
+  L.hi = take(G * M * 4);
+  L.ps = take(G * 4);
+  L.pq = take(G * 4);
   L.ctl = take(64);
   L.total = o;
   return L;
@@ -1227,12 +1380,14 @@ __device__ __forceinline__ void base_frags(const BaseArgs& b, int mp, int lane, 
   }
 }
 
-// L2 / L1: kBaseG consecutive pair slots per workgroup (any queries, any
-// lists; empty slots have zero rows and write nothing)
+// L2 / L1: b.G consecutive pair slots per workgroup (any queries, any
+// lists; empty slots have zero rows and write nothing).  Every m-pair's B
+// fragments, loaded once per workgroup and wave, serve all G pairs.
 template <int DT>
 __global__ __launch_bounds__(kThreads) void k_base(BaseArgs b) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
-  const ScanLds L = base_lds_layout(b.M, b.d);
+  const int G = b.G;
+  const ScanLds L = base_lds_layout(G, b.M, b.d);
   ScanArgs a{};
   a.d = b.d;
   a.dsub = b.dsub;
@@ -1240,13 +1395,13 @@ __global__ __launch_bounds__(kThreads) void k_base(BaseArgs b) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int M = b.M;
   const size_t n = (size_t)b.nq * b.npmax;
-  const size_t i0 = (size_t)blockIdx.x * kBaseG;
+  const size_t i0 = (size_t)blockIdx.x * G;
   int* sp = reinterpret_cast<int*>(lds + L.ps);
-  if (tid < kBaseG) sp[tid] = i0 + tid < n ? b.probes[i0 + tid] : -1;
+  for (int g = tid; g < G; g += kThreads) sp[g] = i0 + g < n ? b.probes[i0 + g] : -1;
   __syncthreads();
   // RC onto the grid (the scan's arithmetic: FP32 subtraction, then the grid)
   const int d4 = b.d >> 2, rs4 = ri_stride(b.d) >> 2;
-  for (int e = tid; e < kBaseG * d4; e += kThreads) {
+  for (int e = tid; e < G * d4; e += kThreads) {
     const int g = e / d4, t4 = e - g * d4;
     const int p = sp[g];
     u32x2 v = {0u, 0u};
@@ -1268,7 +1423,7 @@ __global__ __launch_bounds__(kThreads) void k_base(BaseArgs b) {
   int32_t* lo = reinterpret_cast<int32_t*>(lds + L.lo);
   if (b.metric == AMP_L1) {
     // a thread per (pair, subspace) row: minimum over the codewords on the VALU
-    for (int e = tid; e < kBaseG * M; e += kThreads) {
+    for (int e = tid; e < G * M; e += kThreads) {
       const int g = e / M, m = e % M;
       int rv[kMaxDsub];
 #pragma unroll
@@ -1285,7 +1440,7 @@ __global__ __launch_bounds__(kThreads) void k_base(BaseArgs b) {
     }
   } else {
     int32_t* rr = reinterpret_cast<int32_t*>(lds + L.rr);
-    for (int e = tid; e < kBaseG * M; e += kThreads) {
+    for (int e = tid; e < G * M; e += kThreads) {
       const int g = e / M, m = e % M;
       int32_t sacc = 0;
       for (int t = 0; t < b.dsub; ++t) {
@@ -1298,65 +1453,73 @@ __global__ __launch_bounds__(kThreads) void k_base(BaseArgs b) {
     for (int mp = wave; mp < M / 2; mp += kThreads / 64) {
       u32x4 Bt[16], Bd[16];
       base_frags<DT>(b, mp, lane, Bt, Bd);
-      lut_mpair<32, kBaseG, DT, 1, false>(a, lds, L, M, kBaseG, mp, Bt, Bd);
+      lut_row_minima<DT>(a, lds, L, M, G, mp, Bt, Bd);
     }
   }
   __syncthreads();
-  if (tid < kBaseG && sp[tid] >= 0) {
-    int64_t s = 0;
-    for (int m = 0; m < M; ++m) s += lo[tid * M + m];
-    b.pbase[i0 + tid] = s;
-  }
+  for (int g = tid; g < G; g += kThreads)
+    if (sp[g] >= 0) {
+      int64_t sum = 0;
+      for (int m = 0; m < M; ++m) sum += lo[g * M + m];
+      b.pbase[i0 + g] = sum;
+    }
 }
 
-// inner product: a workgroup per query; the minima of the query's table
-// (LUT pass 1 of one row), then base = sum of minima - qi.ci per probed list
+constexpr int kTabQ = 16;  // queries per workgroup of the table build (two 8-row MFMA tiles)
+
+// inner product, integer policies: each query's exact table T[m][j] =
+// -qi_m . cbi_mj (LUT pass 1 on MFMA, the entries kept), its row minima, the
+// largest row span and the sum of the minima
 template <int DT>
-__global__ __launch_bounds__(kThreads) void k_base_ip(BaseArgs b) {
+__global__ __launch_bounds__(kThreads) void k_iptab(BaseArgs b) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
-  const ScanLds L = base_lds_layout(b.M, b.d);
+  const ScanLds L = base_lds_layout(kTabQ, b.M, b.d);
   ScanArgs a{};
   a.d = b.d;
   a.dsub = b.dsub;
   a.M = b.M;
+  a.tab_out = b.iptab;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int M = b.M, q = blockIdx.x;
+  const int M = b.M;
+  const int q0 = blockIdx.x * kTabQ;
+  const int nqb = b.nq - q0 < kTabQ ? b.nq - q0 : kTabQ;
+  int32_t* pq = reinterpret_cast<int32_t*>(lds + L.pq);
+  if (tid < kTabQ) pq[tid] = q0 + tid;
   const int d4 = b.d >> 2, rs4 = ri_stride(b.d) >> 2;
-  for (int e = tid; e < kBaseG * d4; e += kThreads) {
+  for (int e = tid; e < kTabQ * d4; e += kThreads) {
     const int g = e / d4, t4 = e - g * d4;
     u32x2 v = {0u, 0u};
-    if (g == 0) {
-      const float4 qv = reinterpret_cast<const float4*>(b.Q + (size_t)q * b.d)[t4];
-      const uint32_t v0 = (uint32_t)grid_val(qv.x, b.grid_e, b.grid_kind) & 0xFFFFu;
-      const uint32_t v1 = (uint32_t)grid_val(qv.y, b.grid_e, b.grid_kind) & 0xFFFFu;
-      const uint32_t v2 = (uint32_t)grid_val(qv.z, b.grid_e, b.grid_kind) & 0xFFFFu;
-      const uint32_t v3 = (uint32_t)grid_val(qv.w, b.grid_e, b.grid_kind) & 0xFFFFu;
-      v = (u32x2){v0 | (v1 << 16), v2 | (v3 << 16)};
-    }
+    if (g < nqb) v = reinterpret_cast<const u32x2*>(b.qi16 + (size_t)(q0 + g) * b.d)[t4];
     reinterpret_cast<u32x2*>(lds + L.ri)[g * rs4 + t4] = v;
   }
   __syncthreads();
   for (int mp = wave; mp < M / 2; mp += kThreads / 64) {
     u32x4 Bt[16], Bd[16];
     base_frags<DT>(b, mp, lane, Bt, Bd);
-    lut_mpair<32, kBaseG, DT, 1, true>(a, lds, L, M, 1, mp, Bt, Bd);
+    lut_mpair<32, kTabQ, DT, 4, true>(a, lds, L, M, nqb, mp, Bt, Bd);
   }
   __syncthreads();
   const int32_t* lo = reinterpret_cast<const int32_t*>(lds + L.lo);
-  int64_t lsum = 0;  // every lane sums the row minima (wave-uniform)
-  for (int m = lane; m < M; m += 64) lsum += lo[m];
+  const int32_t* hi = reinterpret_cast<const int32_t*>(lds + L.hi);
+  for (int e = tid; e < nqb * M; e += kThreads) b.iplo[(size_t)q0 * M + e] = lo[e];
+  // per query (a wave each): span and sum of minima
+  for (int g = wave; g < nqb; g += kThreads / 64) {
+    int32_t span = 0;
+    int64_t sum = 0;
+    for (int m = lane; m < M; m += 64) {
+      span = hi[g * M + m] - lo[g * M + m] > span ? hi[g * M + m] - lo[g * M + m] : span;
+      sum += lo[g * M + m];
+    }
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off);
-  const int16_t* qi = reinterpret_cast<const int16_t*>(lds + L.ri);
-  for (int r = wave; r < b.npmax; r += kThreads / 64) {
-    const int p = b.probes[(size_t)q * b.npmax + r];
-    if (p < 0) continue;  // wave-uniform
-    int acc = 0;
-    for (int t = lane; t < b.d; t += 64)
-      acc += (int)qi[t] * grid_val(b.C[(size_t)p * b.d + t], b.grid_e, b.grid_kind);
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-    if (lane == 0) b.pbase[(size_t)q * b.npmax + r] = lsum - acc;
+    for (int off = 32; off > 0; off >>= 1) {
+      const int32_t o = __shfl_xor(span, off);
+      span = o > span ? o : span;
+      sum += __shfl_xor(sum, off);
+    }
+    if (lane == 0) {
+      b.ipspan[q0 + g] = span;
+      b.iplsum[q0 + g] = sum;
+    }
   }
 }
 
