@@ -649,15 +649,20 @@ struct QueueArgs {
   int nq, npmax, nlist, M, ncls, wpr;
   int64_t chunk[2], max_units;  // list chunk of a work unit in phase 1, phase 2
   int ph0, ph1;           // queue phases built by this launch: [ph0, ph1) of {0 bound, 1 full scan}
-  const int64_t* pbase;   // exact base of every pair (integer policies), or null: every pair joins phase 2
+  const int64_t* pbase;   // lower bound of every pair's estimates (integer: exact base; FP32 policy,
+                          // inner product: the key of its in-order FP32 bound), or null: every pair
+                          // joins phase 2
+  int fkeys;              // pbase holds FP32 keys (FP32 policy)
   const uint64_t* tau;    // the queries' phase-1 bounds (with pbase)
   uint64_t* work;         // phase-2 work counters (pairs dropped here count as skipped), or null
 };
 
-// a pair joins the full scan unless its exact base already exceeds its
+// a pair joins the full scan unless its lower bound already exceeds its
 // query's phase-1 bound (then no vector of its list can reach the top-k)
 __device__ __forceinline__ bool pair_live(const QueueArgs& a, size_t i) {
-  return !a.pbase || ikey(a.pbase[i]) <= a.tau[i / a.npmax];
+  if (!a.pbase) return true;
+  const uint64_t key = a.fkeys ? (uint64_t)a.pbase[i] : ikey(a.pbase[i]);
+  return key <= a.tau[i / a.npmax];
 }
 
 __device__ __forceinline__ int pair_class(int bits, int M) {
@@ -1148,6 +1153,49 @@ __global__ __launch_bounds__(256) void k_ipbase(BaseArgs b) {
   }
 }
 
+// inner product, FP32 policy: the largest dot product of each (query,
+// subspace) row of the query's FP32 table (a wave per row)
+__global__ __launch_bounds__(256) void k_ipmax_f32(BaseArgs b) {
+  const int lane = threadIdx.x & 63;
+  const size_t row = (size_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= (size_t)b.nq * b.M) return;
+  const float* t = reinterpret_cast<const float*>(b.iptab) + row * kKsub;
+  float mx = fmaxf(fmaxf(t[lane], t[lane + 64]), fmaxf(t[lane + 128], t[lane + 192]));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+  if (lane == 0) reinterpret_cast<float*>(b.iplo)[row] = mx;
+}
+
+// inner product, FP32 policy: the key of each pair's lower bound, computed
+// with the scan's own FP32 arithmetic (a wave per pair): the pair's base
+// term bf = sum over the subspaces (in order) of the FMA chain of -q_t c_t,
+// then the in-order sum over the subspaces of the smallest LUT entry,
+// bf - max_j dot_0j for subspace 0 and 0 - max_j dot_mj for the others
+// (rounding is monotone, so these are the rows' smallest entries)
+__global__ __launch_bounds__(256) void k_ipbase_f32(BaseArgs b) {
+  const int lane = threadIdx.x & 63;
+  const size_t i = (size_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= (size_t)b.nq * b.npmax) return;
+  const int p = b.probes[i];
+  if (p < 0) return;
+  const size_t q = i / b.npmax;
+  const float* r = b.Q + q * b.d;
+  const float* c = b.C + (size_t)p * b.d;
+  float bf = 0.f;
+  for (int m0 = 0; m0 < b.M; m0 += 64) {
+    const int m = m0 + lane;
+    float sq = 0.f;
+    if (m < b.M)
+      for (int t = 0; t < b.dsub; ++t) sq = fmaf(-r[m * b.dsub + t], c[m * b.dsub + t], sq);
+    const int nm = b.M - m0 < 64 ? b.M - m0 : 64;
+    for (int k = 0; k < nm; ++k) bf += __shfl(sq, k);  // in subspace order, the same on every lane
+  }
+  const float* mx = reinterpret_cast<const float*>(b.iplo) + q * b.M;
+  float sb = 0.f;
+  for (int m = 0; m < b.M; ++m) sb += (m == 0 ? bf : 0.f) - mx[m];
+  if (lane == 0) b.pbase[i] = (int64_t)fkey(sb);
+}
+
 // inner product, integer policies: each query's table quantised at every
 // width its pairs use: shift s from the query's span (smallest with
 // (span + hf(s)) >> s <= 2^b - 1), entries (T - min_m + hf(s)) >> s as
@@ -1378,7 +1426,7 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   // exact bases of the pairs (integer policies): the full scan's queue is
   // built after the phase-1 bound and leaves out the pairs whose base exceeds
   // it.  (The FP32 policy tests its bound inside the scan, after its LUT.)
-  const bool early = !fp32;
+  const bool early = !fp32 || ipm;
   const int dt = dt_of(sd.lut_dtype);
   hipError_t err = hipSuccess;
   {
@@ -1410,10 +1458,13 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
     ba.grid_kind = sd.grid_kind;
     ba.metric = sd.metric;
     if (ipm && fp32) {
-      // the queries' FP32 dot-product tables
+      // the queries' FP32 dot-product tables, their row maxima, the pairs'
+      // FP32 lower bounds
       const size_t n = (size_t)sd.nq * sd.M * kKsub;
       hipLaunchKernelGGL(k_iptab_f32, dim3((unsigned)std::min<size_t>((n + 255) / 256, 1 << 20)), dim3(256), 0, st,
                          ba);
+      hipLaunchKernelGGL(k_ipmax_f32, dim3((unsigned)(((size_t)sd.nq * sd.M + 3) / 4)), dim3(256), 0, st, ba);
+      hipLaunchKernelGGL(k_ipbase_f32, dim3((unsigned)((npairs + 3) / 4)), dim3(256), 0, st, ba);
     } else if (ipm) {
       // the queries' exact tables with their minima, then the pair bases
       const size_t tlds = base_lds_layout(kTabQ, sd.M, sd.d).total;
@@ -1464,6 +1515,7 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   qa.chunk[1] = sd.chunk;
   qa.max_units = sd.max_units;
   qa.pbase = nullptr;
+  qa.fkeys = 0;
   qa.tau = ws.tau;
   qa.work = nullptr;
   const int qb = (int)((npairs + 255) / 256);
@@ -1474,6 +1526,7 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
     q.ph1 = ph1;
     if (ph1 > 1 && early) {
       q.pbase = ws.pbase;
+      q.fkeys = fp32 ? 1 : 0;
       q.work = sd.want_work ? ws.work : nullptr;
     }
     hipLaunchKernelGGL(k_qhist, dim3(qb), dim3(256), 0, st, q);
