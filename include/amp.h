@@ -128,12 +128,15 @@ typedef struct amp_predictor_model {
  *   fixed_bits        width for AMP_POLICY_FIXED: 4, 8, 12 or 16
  *   allowed_bits_mask bit b set => width b allowed (ADAPTIVE); 0 = all four
  *   lut_dtype         AMP_LUT_* matrix dtype of the integer LUT build
- *                     (0 = BF16); the result does not depend on it.
- *                     AMP_LUT_F8E4M3 is reserved and rejected with
- *                     AMP_EUNSUPPORTED: the FP8 MFMA of gfx950 does not
- *                     return exact sums of e4m3-grid products, so the
- *                     entries would not be the exact integers the
- *                     quantiser is defined on
+ *                     (0 = BF16).  BF16 and FP16 give the exact integer LUT
+ *                     (the result does not depend on the choice).
+ *                     AMP_LUT_F8E4M3 (indexes on the e4m3 operand grid, L2
+ *                     or inner product; else AMP_EINVAL): the dimension
+ *                     products on the FP8 MFMA, whose FP32 sums of e4m3-grid
+ *                     products are not always exact; the entries are those
+ *                     sums rounded to integers (quantised entries clamped
+ *                     to the width), so results may differ from the exact
+ *                     LUT's
  *   margin_q40        added to the regressor score before thresholding
  *   explicit_bits     host [nq][npmax] uint8 widths by probe rank (EXPLICIT)
  */
@@ -177,16 +180,21 @@ typedef struct amp_precision_policy {
  * return value carries the same status.
  * kmax, npmax: with AMP_SEARCH_DEVICE_SIZES, the bounds of the device k and
  * nprobe entries (they size the outputs: [nq][kmax], [nq][npmax]).
- * lut_export (test hook, optional, device mode, integer policies, not with
- * AMP_SEARCH_GRAPH): the quantised LUT of every (query, probe rank) pair
- * as the scan built it, for the replay check of the integer stages:
+ * lut_export (test hook, optional, device mode, integer policies, L2 or
+ * inner product, not with AMP_SEARCH_GRAPH): the quantised LUT of every
+ * (query, probe rank) pair as the search builds it, for the replay check of
+ * the integer stages:
  *   q     [nq][npmax][M][256] uint16  entries Q (after the shift)
  *   shift [nq][npmax] int32           shift s of the pair
  *   base  [nq][npmax] int64           base (sum of the subspace minima; inner
  *                                     product: with the -qi.ci term)
+ *   t     [nq][npmax][M][256] int32   optional (NULL: not wanted): the
+ *                                     entries before quantisation (T; the FP8
+ *                                     build's rounded FP32 results)
  * Rows of probe ranks at or beyond a query's nprobe are left unwritten.  The
- * export runs a second, separate LUT build pass after the search (the search
- * itself is unchanged).
+ * export is an extra LUT build after the search with the same kernels'
+ * arithmetic (inner product: a copy of the query's tables); the search itself
+ * is unchanged.
  */
 #define AMP_N_STAGES 9  /* stage_ms: CL, top-nprobe, predictor, pair bases, queue,
                            phase-1 scan (+ bound, + the full scan's queue),
@@ -211,6 +219,7 @@ typedef struct amp_lut_export {
   uint16_t* q;
   int32_t* shift;
   int64_t* base;
+  int32_t* t;
 } amp_lut_export;
 
 typedef struct amp_search_opts {

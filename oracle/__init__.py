@@ -13,6 +13,6 @@ and invariants, except where a function's docstring says "parity unpinned".
 from .search import (  # noqa: F401
     coarse_distances, select_probes, residual_f32, grid, e4m3_round_int,
     index_grid, lut_int, lut_f64, quantize_lut, mitchell_log2_q8,
-    feature_u, svr_eval, bits_from_score, predict_pair_bits, search,
+    feature_u, svr_eval, bits_from_score, predict_pair_bits, dc_ts, search,
 )
 from .exact import exact_knn, recall_1_at, recall_at  # noqa: F401

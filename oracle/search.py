@@ -242,6 +242,33 @@ def predict_pair_bits(dq2, probes, radq, sizes, model, allowed=BITS_ALL, margin_
     return np.asarray(bits, dtype=I64), np.asarray(ys, dtype=object)
 
 
+# --------------------------------------------------------------------- DC + TS
+def dc_ts(index, P, tables, k):
+    """DC and TS (Sec. 2.1; Sec. 4.1 DRM, TSM) of one query on the integer
+    path, given each probed cluster's quantised LUT: for every vector v of
+    probed list P[j], S_v = sum_m Q_j[m][code_v,m] and D_v = base_j + (S_v << s_j);
+    then the k smallest (D, id).  ``tables``: one (Q [M][256], s, base) per
+    probe.  Returns (ids [k], D [k]) padded with (-1, INT64_MAX)."""
+    M = int(index["M"])
+    offs = np.asarray(index["list_offsets"], dtype=I64)
+    ids_all = np.asarray(index["ids"], dtype=I64)
+    codes_all = np.asarray(index["codes"], dtype=I64)
+    cand_d, cand_id = [], []
+    for p, (Qt, s, base) in zip(np.asarray(P).tolist(), tables):
+        codes = codes_all[offs[p]:offs[p + 1]]
+        S = np.asarray(Qt, dtype=I64)[np.arange(M)[None, :], codes].sum(1)
+        cand_d.append(int(base) + (S << int(s)))
+        cand_id.append(ids_all[offs[p]:offs[p + 1]])
+    Dall = np.concatenate(cand_d) if cand_d else np.zeros(0, I64)
+    Iall = np.concatenate(cand_id) if cand_id else np.zeros(0, I64)
+    order = np.lexsort((Iall, Dall))[:k]
+    out_i = np.full(k, -1, dtype=I64)
+    out_d = np.full(k, np.iinfo(I64).max, dtype=I64)
+    out_i[:len(order)] = Iall[order]
+    out_d[:len(order)] = Dall[order]
+    return out_i, out_d
+
+
 # --------------------------------------------------------------------- search
 def _per_query(v, nq):
     v = np.asarray(v)
@@ -337,6 +364,7 @@ def search(index, queries, k, nprobe, policy="fixed", bits=16, allowed=BITS_ALL,
         out_b[i, :len(P)] = B
         if metric == "ip":
             T_query = lut_int(qi, cbi, "ip")
+        tables = []
         for j, p in enumerate(P.tolist()):
             # LC
             if metric in ("l2", "l1"):
@@ -349,17 +377,13 @@ def search(index, queries, k, nprobe, policy="fixed", bits=16, allowed=BITS_ALL,
             base += extra
             out_s[i, j] = s
             out_base[i, j] = base
-            # DC
-            codes = codes_all[offs[p]:offs[p + 1]]
-            S = Qt[np.arange(M)[None, :], codes].sum(1)
-            cand_d.append(base + (S << s))
-            cand_id.append(ids_all[offs[p]:offs[p + 1]])
-        # TS
-        Dall = np.concatenate(cand_d) if cand_d else np.zeros(0, I64)
-        Iall = np.concatenate(cand_id) if cand_id else np.zeros(0, I64)
-        order = np.lexsort((Iall, Dall))[: kq[i]]
-        out_ids[i, :len(order)] = Iall[order]
-        out_q[i, :len(order)] = Dall[order]
-        out_d[i, :len(order)] = (Dall[order].astype(np.float32) * np.float32(h2))
+            tables.append((Qt, s, base))
+        # DC + TS
+        oi, od = dc_ts(index, P, tables, int(kq[i]))
+        kk = int(kq[i])
+        out_ids[i, :kk] = oi
+        out_q[i, :kk] = od
+        fin = oi >= 0
+        out_d[i, :kk][fin] = od[fin].astype(np.float32) * np.float32(h2)
     return dict(ids=out_ids, qdist=out_q, dist=out_d, probes=out_p, bits=out_b,
                 shift=out_s, base=out_base)

@@ -61,7 +61,7 @@ AMP_SEARCH_DEVICE_SIZES = 2
 
 
 class _LutExport(C.Structure):
-    _fields_ = [("q", C.c_void_p), ("shift", C.c_void_p), ("base", C.c_void_p)]
+    _fields_ = [("q", C.c_void_p), ("shift", C.c_void_p), ("base", C.c_void_p), ("t", C.c_void_p)]
 
 
 class _Opts(C.Structure):
@@ -385,7 +385,7 @@ def amp_search(index, queries, k, nprobe, policy="fixed", bits=16, allowed=(4, 8
     Device mode (``queries`` a torch CUDA tensor): ``out`` must be a dict of
     preallocated torch CUDA tensors ids [nq,kmax] int64, dist [nq,kmax] float32
     and optionally qdist / probes / bits / coarse / status (int32 [1]) /
-    lut_q, lut_shift, lut_base (the LUT export test hook); work is enqueued
+    lut_q, lut_shift, lut_base, lut_t (the LUT export test hook); work is enqueued
     on ``stream`` (a torch stream or raw handle) and the call returns at once.
     Device mode also takes ``k`` / ``nprobe`` as int32 CUDA tensors of nq
     entries (device-resident per-query sizes, bounded by ``kmax`` / ``npmax``).
@@ -422,7 +422,7 @@ def amp_search(index, queries, k, nprobe, policy="fixed", bits=16, allowed=(4, 8
         sh = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
         exp = None
         if o.get("lut_q") is not None:
-            exp = _LutExport(_ptr(o["lut_q"]), _ptr(o["lut_shift"]), _ptr(o["lut_base"]))
+            exp = _LutExport(_ptr(o["lut_q"]), _ptr(o["lut_shift"]), _ptr(o["lut_base"]), _ptr(o.get("lut_t")))
         opts = _Opts(AMP_MEM_DEVICE, C.c_void_p(sh) if sh else None, _ptr(o.get("qdist")),
                      _ptr(o.get("probes")), _ptr(o.get("bits")), _ptr(o.get("coarse")), _ptr(ms),
                      flags, qd, _ptr(wk), _ptr(o.get("status")), kmax if dev_sizes else 0,

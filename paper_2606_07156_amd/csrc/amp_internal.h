@@ -54,6 +54,7 @@ struct DeviceIndex {
   float* codebook = nullptr;   // [M][256][dsub]
   uint4* bsw = nullptr;        // [M/2][16][64] MFMA B fragments (8 bf16 each)
   uint4* bsw16 = nullptr;      // [M/2][16][64] FP16 dims fragments
+  uint2* bsw8 = nullptr;       // [M/2][16][64] FP8 (e4m3) dims fragments
   int16_t* cbi16 = nullptr;    // [M][256][8] grid codebook (L1 LUT build)
   int16_t* ci16 = nullptr;     // [nlist][d] grid centroids (inner product: qi.ci, d')
   int32_t* lorder = nullptr;   // [nlist] lists by decreasing size (ties: id)
@@ -220,6 +221,7 @@ struct SearchDims {
   const int32_t* np_dev; // workspace first (AMP_SEARCH_DEVICE_SIZES), or null
   int32_t* out_status;   // status word written at the end of the search, or null
   int reruns;            // phase-2 re-runs of overflowed queries (2; fewer only to test overflow reporting)
+  const amp_lut_export* lut_export;  // test hook: every pair's LUT after the search, or null
 };
 
 struct ModelArgs {

@@ -46,7 +46,7 @@ static amp_status dalloc(T** p, size_t n, std::vector<void*>* track = nullptr) {
 }
 
 static void free_device_index(DeviceIndex& d) {
-  void* ptrs[] = {d.centroids, d.cnorm, d.codebook, d.bsw, d.bsw16, d.cbi16, d.ci16, d.lorder, d.lpos, d.codes, d.ids,
+  void* ptrs[] = {d.centroids, d.cnorm, d.codebook, d.bsw, d.bsw16, d.bsw8, d.cbi16, d.ci16, d.lorder, d.lpos, d.codes, d.ids,
                   d.offsets, d.radq, d.model.sv, d.model.beta, d.model.table};
   for (void* p : ptrs)
     if (p) hipFree(p);
@@ -217,7 +217,7 @@ static amp_status to_device_locked(amp_index* ix, int device) {
   const size_t nl = ix->nlist, dd = ix->d, M = ix->M, n = ix->n;
   if ((s = dalloc(&d.centroids, nl * dd)) || (s = dalloc(&d.cnorm, nl)) ||
       (s = dalloc(&d.codebook, M * kKsub * ix->dsub)) || (s = dalloc(&d.bsw, (M / 2) * 16 * 64)) ||
-      (s = dalloc(&d.bsw16, (M / 2) * 16 * 64)) || (s = dalloc(&d.cbi16, M * kKsub * 8)) || (s = dalloc(&d.ci16, nl * dd)) ||
+      (s = dalloc(&d.bsw16, (M / 2) * 16 * 64)) || (s = dalloc(&d.bsw8, (M / 2) * 16 * 64)) || (s = dalloc(&d.cbi16, M * kKsub * 8)) || (s = dalloc(&d.ci16, nl * dd)) ||
       (s = dalloc(&d.lorder, nl)) || (s = dalloc(&d.lpos, nl)) ||
       (s = dalloc(&d.codes, std::max<size_t>(1, n * M))) || (s = dalloc(&d.ids, std::max<size_t>(1, n))) ||
       (s = dalloc(&d.offsets, nl + 1)) || (s = dalloc(&d.radq, nl))) {
@@ -667,11 +667,18 @@ amp_status search_on(amp_index* ix, Workspace& w, const void* queries, int64_t n
       break;
     default: return set_error(AMP_EINVAL, "bad policy kind %d", pol->kind);
   }
-  if (pol->lut_dtype == AMP_LUT_F8E4M3)
-    return set_error(AMP_EUNSUPPORTED, "FP8 LUT build: the gfx950 FP8 MFMA does not accumulate e4m3-grid "
-                                       "products exactly; use AMP_LUT_BF16 or AMP_LUT_F16");
-  if (pol->lut_dtype != 0 && pol->lut_dtype != AMP_LUT_BF16 && pol->lut_dtype != AMP_LUT_F16)
+  if (pol->lut_dtype != 0 && pol->lut_dtype != AMP_LUT_BF16 && pol->lut_dtype != AMP_LUT_F16 &&
+      pol->lut_dtype != AMP_LUT_F8E4M3)
     return set_error(AMP_EINVAL, "bad LUT build dtype %d", pol->lut_dtype);
+  if (pol->lut_dtype == AMP_LUT_F8E4M3 && (ix->grid_kind != AMP_GRID_E4M3 || ix->metric == AMP_L1))
+    return set_error(AMP_EINVAL, "the FP8 LUT build needs an index on the e4m3 operand grid, L2 or inner product");
+  if (opts->lut_export) {
+    const amp_lut_export* ex = opts->lut_export;
+    if (opts->mem != AMP_MEM_DEVICE || pol->kind == AMP_POLICY_FP32 || ix->metric == AMP_L1 ||
+        (opts->flags & AMP_SEARCH_GRAPH) || !ex->q || !ex->shift || !ex->base)
+      return set_error(AMP_EINVAL, "the LUT export needs device memory, an integer policy, L2 or inner product, "
+                                   "no graph replay, and q, shift and base buffers");
+  }
   const bool use_graph = (opts->flags & AMP_SEARCH_GRAPH) != 0;
   if (use_graph && (host || (per_query && !dev_sizes) || opts->stage_ms || opts->work ||
                     pol->kind == AMP_POLICY_EXPLICIT))
@@ -810,6 +817,7 @@ amp_status search_on(amp_index* ix, Workspace& w, const void* queries, int64_t n
   sd.out_status = host ? nullptr : opts->out_status;
   // AMP_RERUNS (0..2) lowers the number of phase-2 re-runs, so that tests can
   // force an unresolved candidate overflow
+  sd.lut_export = opts->lut_export;
   sd.reruns = (int)std::min<size_t>(2, env_size("AMP_RERUNS", 2));
   if (const char* rv = getenv("AMP_RERUNS"))
     if (rv[0] == '0') sd.reruns = 0;

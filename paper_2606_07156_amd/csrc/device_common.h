@@ -67,10 +67,19 @@ __device__ __forceinline__ int row16_reduce(int v) {
   return row16_step<MAX, 8>(row16_step<MAX, 4>(row16_step<MAX, 2>(row16_step<MAX, 1>(v))));
 }
 
-// LC matrix dtypes of the integer LUT build.  (An FP8 e4m3 variant is not
-// offered: the 16x16x32 FP8 MFMA of gfx950 does not return the exact sum of
-// e4m3-grid products of the magnitudes the grid allows.)
-enum { DT_BF16 = 1, DT_F16 = 2 };
+// LC matrix dtypes of the integer LUT build.  BF16 and FP16 sums of grid
+// products are exact; the FP8 (e4m3) build puts the dimension products on
+// the FP8 MFMA, whose sums of e4m3-grid products are not always exact: its
+// entries are the rounded FP32 results.
+enum { DT_BF16 = 1, DT_F16 = 2, DT_F8 = 3 };
+
+// four floats as OCP e4m3 bytes (the hardware conversion; exact for the
+// e4m3-representable integers of the e4m3 operand grid)
+__device__ __forceinline__ uint32_t f8_bits4(float v0, float v1, float v2, float v3) {
+  int w = __builtin_amdgcn_cvt_pk_fp8_f32(v0, v1, 0, false);
+  w = __builtin_amdgcn_cvt_pk_fp8_f32(v2, v3, w, true);
+  return (uint32_t)w;
+}
 
 __device__ __forceinline__ uint32_t f16_bits(float v) {  // exact inputs only
   return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)v);

@@ -1067,7 +1067,7 @@ __global__ __launch_bounds__(256) void k_merge(MergeArgs a, int nq) {
 //   cc = |cbi[m][j]|^2 (base 256, most significant first) then 65536, 256, 1
 // bsw: BF16 (all groups); bsw16: FP16 dims (odd groups zero).
 __global__ void k_prep_bsw(const float* __restrict__ cb, int M, int dsub, int grid_e, int grid_kind,
-                           u32x4* __restrict__ bsw, u32x4* __restrict__ bsw16) {
+                           u32x4* __restrict__ bsw, u32x4* __restrict__ bsw16, u32x2* __restrict__ bsw8) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   const int total = (M / 2) * 16 * 64;
   if (idx >= total) return;
@@ -1082,10 +1082,13 @@ __global__ void k_prep_bsw(const float* __restrict__ cb, int M, int dsub, int gr
     ci[t] = t < dsub ? grid_val(c[t], grid_e, grid_kind) : 0;
     cc += ci[t] * ci[t];
   }
-  uint32_t h[4] = {0, 0, 0, 0};
+  uint32_t h[4] = {0, 0, 0, 0}, f8[2] = {0, 0};
   if ((kg & 1) == 0) {
     for (int t = 0; t < 8; ++t) v[t] = (float)ci[t];
     for (int t = 0; t < 4; ++t) h[t] = f16_bits(v[2 * t]) | (f16_bits(v[2 * t + 1]) << 16);
+    // e4m3 bytes (exact on the e4m3 grid; the FP8 build is only offered there)
+    f8[0] = f8_bits4(v[0], v[1], v[2], v[3]);
+    f8[1] = f8_bits4(v[4], v[5], v[6], v[7]);
   } else {
     v[0] = (float)(cc >> 16);
     v[1] = (float)((cc >> 8) & 255);
@@ -1100,6 +1103,7 @@ __global__ void k_prep_bsw(const float* __restrict__ cb, int M, int dsub, int gr
   for (int t = 0; t < 4; ++t) o[t] = bf16_bits(v[2 * t]) | (bf16_bits(v[2 * t + 1]) << 16);
   bsw[idx] = o;
   bsw16[idx] = (u32x4){h[0], h[1], h[2], h[3]};
+  bsw8[idx] = (u32x2){f8[0], f8[1]};
 }
 
 // ------------------------------------------------------------------ inner-product tables
@@ -1196,6 +1200,25 @@ __global__ __launch_bounds__(256) void k_ipbase_f32(BaseArgs b) {
   if (lane == 0) b.pbase[i] = (int64_t)fkey(sb);
 }
 
+// LUT export (test hook), inner product: a pair's LUT is its query's table
+// at its width (a workgroup per pair)
+__global__ void k_export_ip(BaseArgs b, uint16_t* exq, int32_t* exs, int64_t* exb, int32_t* ext) {
+  const size_t i = blockIdx.x;
+  const int p = b.probes[i];
+  if (p < 0) return;
+  const size_t q = i / b.npmax;
+  const int wi = (b.pbits[i] >> 2) - 1;
+  const size_t tsz = (size_t)b.M * kKsub;
+  if (threadIdx.x == 0) {
+    exs[i] = b.ipsh[q * 4 + wi];
+    exb[i] = b.pbase[i];
+  }
+  for (size_t e = threadIdx.x; e < tsz; e += blockDim.x) {
+    exq[i * tsz + e] = b.iptq[(q * 4 + wi) * tsz + e];
+    if (ext) ext[i * tsz + e] = b.iptab[q * tsz + e];
+  }
+}
+
 // inner product, integer policies: each query's table quantised at every
 // width its pairs use: shift s from the query's span (smallest with
 // (span + hf(s)) >> s <= 2^b - 1), entries (T - min_m + hf(s)) >> s as
@@ -1243,7 +1266,7 @@ hipError_t launch_prep_index(const amp_index* ix, hipStream_t st) {
                      dv.centroids, dv.ci16, nc, ix->grid_e, ix->grid_kind);
   hipLaunchKernelGGL(k_prep_bsw, dim3((total + 255) / 256), dim3(256), 0, st, dv.codebook, ix->M, ix->dsub,
                      ix->grid_e, ix->grid_kind, reinterpret_cast<u32x4*>(dv.bsw),
-                     reinterpret_cast<u32x4*>(dv.bsw16));
+                     reinterpret_cast<u32x4*>(dv.bsw16), reinterpret_cast<u32x2*>(dv.bsw8));
   return hipGetLastError();
 }
 
@@ -1435,6 +1458,7 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
     ba.C = dv.centroids;
     ba.bsw = reinterpret_cast<const u32x4*>(dv.bsw);
     ba.bsw16 = reinterpret_cast<const u32x4*>(dv.bsw16);
+    ba.bsw8 = reinterpret_cast<const u32x2*>(dv.bsw8);
     ba.cbi16 = dv.cbi16;
     ba.ci16 = dv.ci16;
     ba.probes = ws.probes;
@@ -1468,7 +1492,7 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
     } else if (ipm) {
       // the queries' exact tables with their minima, then the pair bases
       const size_t tlds = base_lds_layout(kTabQ, sd.M, sd.d).total;
-      auto fn = dt == DT_F16 ? k_iptab<DT_F16> : k_iptab<DT_BF16>;
+      auto fn = dt == DT_F16 ? k_iptab<DT_F16> : (dt == DT_F8 ? k_iptab<DT_F8> : k_iptab<DT_BF16>);
       if ((err = hipFuncSetAttribute(kaddr(fn), hipFuncAttributeMaxDynamicSharedMemorySize, (int)tlds)) != hipSuccess)
         return err;
       hipLaunchKernelGGL(fn, dim3((sd.nq + kTabQ - 1) / kTabQ), dim3(kThreads), tlds, st, ba);
@@ -1482,7 +1506,7 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
       while (G > 8 && (size_t)G * ri_stride(sd.d) * 2 > 65536) G >>= 1;
       ba.G = G;
       const size_t blds = base_lds_layout(G, sd.M, sd.d).total;
-      auto fn = dt == DT_F16 ? k_base<DT_F16> : k_base<DT_BF16>;
+      auto fn = dt == DT_F16 ? k_base<DT_F16> : (dt == DT_F8 ? k_base<DT_F8> : k_base<DT_BF16>);
       if ((err = hipFuncSetAttribute(kaddr(fn), hipFuncAttributeMaxDynamicSharedMemorySize, (int)blds)) != hipSuccess)
         return err;
       hipLaunchKernelGGL(fn, dim3((unsigned)((npairs + G - 1) / G)), dim3(kThreads), blds, st, ba);
@@ -1544,6 +1568,7 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   sa.codebook = dv.codebook;
   sa.bsw = reinterpret_cast<const u32x4*>(dv.bsw);
   sa.bsw16 = reinterpret_cast<const u32x4*>(dv.bsw16);
+  sa.bsw8 = reinterpret_cast<const u32x2*>(dv.bsw8);
   sa.cbi16 = dv.cbi16;
   sa.codes = dv.codes;
   sa.ids = dv.ids;
@@ -1657,6 +1682,40 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(k_merge_wave, dim3((sd.nq + 3) / 4), dim3(256), 0, st, ma2, sd.nq);
   hipLaunchKernelGGL(k_merge, dim3(sd.nq < 512 ? sd.nq : 512), dim3(256), mlds, st, ma2, sd.nq);
+  if (sd.lut_export) {
+    // test hook: every pair's LUT as the search builds it
+    const amp_lut_export* ex = sd.lut_export;
+    BaseArgs eb{};
+    eb.Q = queries;
+    eb.C = dv.centroids;
+    eb.bsw = reinterpret_cast<const u32x4*>(dv.bsw);
+    eb.bsw16 = reinterpret_cast<const u32x4*>(dv.bsw16);
+    eb.bsw8 = reinterpret_cast<const u32x2*>(dv.bsw8);
+    eb.probes = ws.probes;
+    eb.pbase = ws.pbase;
+    eb.iptab = ws.iptab;
+    eb.iptq = ws.iptq;
+    eb.ipsh = ws.ipsh;
+    eb.pbits = ws.pbits;
+    eb.nq = sd.nq;
+    eb.d = sd.d;
+    eb.M = sd.M;
+    eb.dsub = sd.dsub;
+    eb.npmax = sd.npmax;
+    eb.grid_e = sd.grid_e;
+    eb.grid_kind = sd.grid_kind;
+    eb.metric = sd.metric;
+    if (ipm) {
+      hipLaunchKernelGGL(k_export_ip, dim3((unsigned)npairs), dim3(256), 0, st, eb, ex->q, ex->shift, ex->base, ex->t);
+    } else {
+      const size_t elds = base_lds_layout(kBaseExport, sd.M, sd.d).total;
+      auto fn = dt == DT_F16 ? k_export<DT_F16> : (dt == DT_F8 ? k_export<DT_F8> : k_export<DT_BF16>);
+      if ((err = hipFuncSetAttribute(kaddr(fn), hipFuncAttributeMaxDynamicSharedMemorySize, (int)elds)) != hipSuccess)
+        return err;
+      hipLaunchKernelGGL(fn, dim3((unsigned)((npairs + kBaseExport - 1) / kBaseExport)), dim3(kThreads), elds, st, eb,
+                         ex->q, ex->shift, ex->base, ex->t);
+    }
+  }
   if (sd.out_status) hipLaunchKernelGGL(k_status, dim3(1), dim3(64), 0, st, ws.flags, sd.out_status);
   mark(8);
   return hipGetLastError();

@@ -13,6 +13,7 @@ struct ScanArgs {
   const float* codebook;   // FP32 policy
   const u32x4* bsw;        // integer policy MFMA B fragments (BF16, with aug slots)
   const u32x4* bsw16;      // FP16 dims fragments
+  const u32x2* bsw8;       // FP8 (e4m3) dims fragments
   const int16_t* cbi16;    // [M][256][8] grid codebook (L1 LUT build)
   const uint8_t* codes;
   const int64_t* ids;
@@ -39,7 +40,8 @@ struct ScanArgs {
   const uint16_t* iptq;     // [nq][4][M][256] quantised tables per width
   const int32_t* ipsh;      // [nq][4] their shifts
   const int64_t* pbase_g;   // [nq][npmax]
-  int32_t* tab_out;         // LUT pass 1 that also stores T (the per-query table build)
+  int32_t* tab_out;         // LUT pass 1 that also stores T (per-query table build, LUT export)
+  uint16_t* ex_q;           // LUT export: quantised entries [pair][M][256]
   int nq, d, M, dsub, nlist, npmax, grid_e, grid_kind, metric, kconst, kmax, cls;
   int steal;                // unit queue: 0 one counter, 1 per-XCD ranges with stealing
   int64_t chunk;
@@ -184,11 +186,14 @@ __device__ __forceinline__ void mpair_a_tile(const ScanArgs& a, const char* lds,
   const int g = gt * 8 + (row & 7);
   const int m = 2 * mp + ms_row;
   uint32_t pk[4] = {0, 0, 0, 0}, pd[4] = {0, 0, 0, 0};
+  constexpr bool Q2 = PASS == 2 || PASS == 5;  // the quantising passes (5: the LUT export)
   if (g < np_u && (kg >> 1) == ms_row) {
-    const int s = pass != 2 ? 0 : ps[g];
+    const int s = !Q2 ? 0 : ps[g];
     const float sc = DT == DT_BF16 ? ldexpf(1.f, -s) : 1.f;
     if ((kg & 1) == 0) {
-      const int coef = ip ? -1 : -2;
+      // (FP8: -ri, exact in e4m3; the L2 factor 2 is applied to the FP8
+      // MFMA's result on the VALU)
+      const int coef = (ip || DT == DT_F8) ? -1 : -2;
       // the subspace's grid residual: one 16-byte read when d_sub = 8
       // (rows and subspaces 16-byte aligned), else element by element
       int rv[8];
@@ -209,16 +214,24 @@ __device__ __forceinline__ void mpair_a_tile(const ScanArgs& a, const char* lds,
         for (int t = 0; t < 8; ++t) v[t] = t < dsub ? (float)(coef * rv[t]) * sc : 0.f;
 #pragma unroll
         for (int t = 0; t < 4; ++t) pk[t] = bf16_bits(v[2 * t]) | (bf16_bits(v[2 * t + 1]) << 16);
-      } else {
+      } else if constexpr (DT == DT_F16) {
         float v[8];
 #pragma unroll
         for (int t = 0; t < 8; ++t) v[t] = t < dsub ? (float)(coef * rv[t]) : 0.f;
 #pragma unroll
         for (int t = 0; t < 4; ++t) pd[t] = f16_bits(v[2 * t]) | (f16_bits(v[2 * t + 1]) << 16);
+      } else {
+        float v[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) v[t] = t < dsub ? (float)(coef * rv[t]) : 0.f;
+        pd[0] = f8_bits4(v[0], v[1], v[2], v[3]);
+        pd[1] = f8_bits4(v[4], v[5], v[6], v[7]);
       }
     } else {
       int32_t X = ip ? 0 : rr[g * M + m];
-      if (pass == 2) X += lo[g * M + m];  // lo holds off = hf(s) - min after pass 1
+      // lo holds off = hf(s) - min after pass 1 (folded in, except for the
+      // FP8 build: its entries are offset and shifted after rounding)
+      if (Q2 && DT != DT_F8) X += lo[g * M + m];
       const float sg = X < 0 ? -1.f : 1.f;
       const uint32_t ax = (uint32_t)(X < 0 ? -X : X);
       const float cm = ip ? 0.f : sc;
@@ -240,6 +253,28 @@ __device__ __forceinline__ void mpair_a_tile(const ScanArgs& a, const char* lds,
   Ad = (u32x4){pd[0], pd[1], pd[2], pd[3]};
 }
 
+// one 16x16 tile of T (+ the aug terms): BF16 MFMA of everything (BF16
+// build) or of the aug terms, then the dims on the FP16 MFMA or, FP8 build,
+// on the FP8 MFMA (-ri.cbi, doubled for L2)
+template <int DT, bool IP>
+__device__ __forceinline__ f4 mpair_mfma(const bf16x8& A, const u32x4& Ad, const u32x4& B, const u32x4& Bd) {
+  f4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, __builtin_bit_cast(bf16x8, B), (f4){0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+  if constexpr (DT == DT_F16) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, Ad), __builtin_bit_cast(f16x8, Bd), acc,
+                                                 0, 0, 0);
+  } else if constexpr (DT == DT_F8) {
+    const long a8 = (long)(((uint64_t)Ad[1] << 32) | Ad[0]);
+    const long b8 = (long)(((uint64_t)Bd[1] << 32) | Bd[0]);
+    // the dot products into an accumulator of their own, added on the VALU
+    // (integers below 2^24: exact), so that this MFMA never takes the BF16
+    // MFMA's result as its C operand
+    const f4 p = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a8, b8, (f4){0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] += (IP ? 1.f : 2.f) * p[i];
+  }
+  return acc;
+}
+
 // Row minima of an m-pair's exact integer LUT for np_u pairs (L2: min over
 // the 256 codewords of T, written to L.lo), one 8-pair tile at a time, so
 // that only one tile's accumulators are live: the B fragments (kept in
@@ -259,20 +294,19 @@ __device__ __forceinline__ void lut_row_minima(const ScanArgs& a, char* lds, con
     int mn[4] = {0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF, 0x7FFFFFFF};
 #pragma unroll
     for (int jt = 0; jt < 16; ++jt) {
-      f4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, __builtin_bit_cast(bf16x8, B[jt]),
-                                                       (f4){0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-      if constexpr (DT == DT_F16)
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, Ad),
-                                                     __builtin_bit_cast(f16x8, Bd[jt]), acc, 0, 0, 0);
+      const f4 acc = mpair_mfma<DT, false>(A, Ad, B[jt], Bd[jt]);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int t = __float_as_int(acc[i]);  // exact, non-negative: bit patterns order as integers
+        // exact non-negative values: bit patterns order as integers (FP8
+        // build: the rounded value)
+        const int t = DT == DT_F8 ? (int)rintf(acc[i]) : __float_as_int(acc[i]);
         mn[i] = t < mn[i] ? t : mn[i];
       }
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int v = (int)__int_as_float(row16_reduce<false>(mn[i]));
+      const int r = row16_reduce<false>(mn[i]);
+      const int v = DT == DT_F8 ? r : (int)__int_as_float(r);
       const int g = gt * 8 + 4 * (kg & 1) + i;
       if ((lane & 15) == 15 && g < np_u) lo[g * M + m_out] = v;
     }
@@ -299,6 +333,7 @@ template <int LWB, int WPR, int DT, int PASS, bool IP>
 __device__ __forceinline__ void lut_mpair(const ScanArgs& a, char* lds, const ScanLds& L, int M, int np_u,
                                           int mp, const u32x4 (&B)[16], const u32x4 (&Bd)[16]) {
   constexpr int pass = PASS;
+  constexpr bool INTV = IP || DT == DT_F8;  // entries held as integers (else L2 float bit patterns)
   constexpr int W = Lane<LWB>::W;
   constexpr int G = WPR * W;
   constexpr int NGT = (G + 7) / 8;
@@ -326,7 +361,7 @@ __device__ __forceinline__ void lut_mpair(const ScanArgs& a, char* lds, const Sc
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int g = gt * 8 + 4 * (kg & 1) + i;
-      rsc[gt][i] = (DT == DT_BF16 || pass != 2 || g >= np_u) ? 1.f : ldexpf(1.f, -ps[g]);
+      rsc[gt][i] = (DT == DT_BF16 || !(PASS == 2 || PASS == 5) || g >= np_u) ? 1.f : ldexpf(1.f, -ps[g]);
     }
   int mn[NGT][4], mx[NGT][4];
   uint32_t wv8[NGT];  // packed words of the interleaved 8-bit layout
@@ -341,35 +376,54 @@ __device__ __forceinline__ void lut_mpair(const ScanArgs& a, char* lds, const Sc
     const int j = jt * 16 + (lane & 15);
 #pragma unroll
     for (int gt = 0; gt < NGT; ++gt) {
-      f4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[gt], Bf, (f4){0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-      if constexpr (DT == DT_F16) {
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, Ad[gt]),
-                                                     __builtin_bit_cast(f16x8, Bdj), acc, 0, 0, 0);
-      }
+      const f4 acc = mpair_mfma<DT, IP>(A[gt], Ad[gt], B[jt], Bdj);
       const int g0 = gt * 8 + 4 * (kg & 1);
       if constexpr (PASS == 1 || PASS == 4) {
         // exact integers: for L2 (T >= 0) the float bit patterns order as
-        // integers; inner product values may be negative and are converted
+        // integers; inner product values may be negative and are converted;
+        // the FP8 build's entries are its rounded FP32 results
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int t = ip ? (int)acc[i] : __float_as_int(acc[i]);
+          const int t = INTV ? (DT == DT_F8 ? (int)rintf(acc[i]) : (int)acc[i]) : __float_as_int(acc[i]);
           mn[gt][i] = t < mn[gt][i] ? t : mn[gt][i];
           mx[gt][i] = t > mx[gt][i] ? t : mx[gt][i];
           if constexpr (PASS == 4) {
-            // the per-query table build also keeps the exact entries
+            // the per-query table build (and the LUT export) also keep the
+            // entries; row g's destination index is in L.pq
             const int g = g0 + i;
-            if (g < np_u) {
-              const int q = reinterpret_cast<const int32_t*>(lds + L.pq)[g];
-              a.tab_out[((size_t)q * M + m_out) * kKsub + j] = ip ? t : (int)acc[i];
-            }
+            const int q = g < np_u ? reinterpret_cast<const int32_t*>(lds + L.pq)[g] : -1;
+            if (q >= 0) a.tab_out[((size_t)q * M + m_out) * kKsub + j] = INTV ? t : (int)acc[i];
           }
         }
       } else if (g0 < G) {
         uint32_t qv[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const float vv = DT == DT_BF16 ? acc[i] : acc[i] * rsc[gt][i];  // power-of-two scale: exact
-          qv[i] = (uint32_t)vv;  // exact and >= 0: truncation = floor
+          if constexpr (DT == DT_F8) {
+            // offset and shift after rounding, clamped to the width (the
+            // entries are the same rounded values as in pass 1)
+            const int g = g0 + i;
+            const int bw = reinterpret_cast<const int32_t*>(lds + L.pb)[g];
+            const int top = bw > 0 ? (1 << bw) - 1 : 0;
+            const int sh = g < np_u ? ps[g] : 0;
+            int v = g < np_u ? ((int)rintf(acc[i]) + lo[g * M + m_out]) >> sh : 0;
+            v = v < 0 ? 0 : (v > top ? top : v);
+            qv[i] = (uint32_t)v;
+          } else {
+            const float vv = DT == DT_BF16 ? acc[i] : acc[i] * rsc[gt][i];  // power-of-two scale: exact
+            qv[i] = (uint32_t)vv;  // exact and >= 0: truncation = floor
+          }
+        }
+        if constexpr (PASS == 5) {
+          // LUT export: the quantised entries to global memory, row g's
+          // destination index in L.pq
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int g = g0 + i;
+            const int q = g < np_u ? reinterpret_cast<const int32_t*>(lds + L.pq)[g] : -1;
+            if (q >= 0) a.ex_q[((size_t)q * M + m_out) * kKsub + j] = (uint16_t)qv[i];
+          }
+          continue;
         }
         uint32_t* dst = lut + (size_t)(m_out * kKsub + j) * WPR;
         if constexpr (PairSlot<LWB, WPR>::IL) {
@@ -400,7 +454,7 @@ __device__ __forceinline__ void lut_mpair(const ScanArgs& a, char* lds, const Sc
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         int a0 = row16_reduce<false>(mn[gt][i]), b0 = row16_reduce<true>(mx[gt][i]);
-        if (!ip) {
+        if (!INTV) {
           a0 = (int)__int_as_float(a0);
           b0 = (int)__int_as_float(b0);
         }
@@ -744,8 +798,14 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
           for (int jt = 0; jt < 16; ++jt) {
             const size_t fi = ((size_t)mp * 16 + jt) * 64 + lane;
             Bt[jt] = a.bsw[fi];
-            if constexpr (DT == DT_F16) Bd[jt] = a.bsw16[fi];
-            else Bd[jt] = (u32x4){0u, 0u, 0u, 0u};
+            if constexpr (DT == DT_F16) {
+              Bd[jt] = a.bsw16[fi];
+            } else if constexpr (DT == DT_F8) {
+              const u32x2 b8 = a.bsw8[fi];
+              Bd[jt] = (u32x4){b8[0], b8[1], 0u, 0u};
+            } else {
+              Bd[jt] = (u32x4){0u, 0u, 0u, 0u};
+            }
           }
           lut_mpair<LWB, WPR, DT, PASS, IPM>(a, lds, L, M, np_u, mp, Bt, Bd);
         }
@@ -1290,7 +1350,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_scan_mix(ScanArgs a) {
 // LC matrix dtype of an AMP_LUT_* value (0 selects BF16; the FP8 value is
 // rejected before a search launches)
 inline int dt_of(int lut_dtype) {
-  return lut_dtype == AMP_LUT_F16 ? DT_F16 : DT_BF16;
+  return lut_dtype == AMP_LUT_F16 ? DT_F16 : (lut_dtype == AMP_LUT_F8E4M3 ? DT_F8 : DT_BF16);
 }
 
 
@@ -1333,6 +1393,7 @@ struct BaseArgs {
   const float* C;
   const u32x4* bsw;
   const u32x4* bsw16;
+  const u32x2* bsw8;
   const int16_t* cbi16;
   const int16_t* ci16;     // [nlist][d] grid centroids
   const int32_t* probes;
@@ -1363,6 +1424,7 @@ __host__ __device__ inline ScanLds base_lds_layout(int G, int M, int d) {
   L.hi = take(G * M * 4);
   L.ps = take(G * 4);
   L.pq = take(G * 4);
+  L.pb = take(G * 4);
   L.ctl = take(64);
   L.total = o;
   return L;
@@ -1375,8 +1437,14 @@ __device__ __forceinline__ void base_frags(const BaseArgs& b, int mp, int lane, 
   for (int jt = 0; jt < 16; ++jt) {
     const size_t fi = ((size_t)mp * 16 + jt) * 64 + lane;
     Bt[jt] = b.bsw[fi];
-    if constexpr (DT == DT_F16) Bd[jt] = b.bsw16[fi];
-    else Bd[jt] = (u32x4){0u, 0u, 0u, 0u};
+    if constexpr (DT == DT_F16) {
+      Bd[jt] = b.bsw16[fi];
+    } else if constexpr (DT == DT_F8) {
+      const u32x2 b8 = b.bsw8[fi];
+      Bd[jt] = (u32x4){b8[0], b8[1], 0u, 0u};
+    } else {
+      Bd[jt] = (u32x4){0u, 0u, 0u, 0u};
+    }
   }
 }
 
@@ -1463,6 +1531,109 @@ __global__ __launch_bounds__(kThreads) void k_base(BaseArgs b) {
       for (int m = 0; m < M; ++m) sum += lo[g * M + m];
       b.pbase[i0 + g] = sum;
     }
+}
+
+// LUT export (test hook, L2): for kBaseExport consecutive pair slots, the
+// LUT exactly as the scan builds it (pass 1, shift and base, pass 2) with the
+// quantised entries, shift and base (and, optionally, the entries before
+// quantisation) written to global memory
+constexpr int kBaseExport = 16;
+template <int DT>
+__global__ __launch_bounds__(kThreads) void k_export(BaseArgs b, uint16_t* exq, int32_t* exs, int64_t* exb,
+                                                     int32_t* ext) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  constexpr int G = kBaseExport;
+  const ScanLds L = base_lds_layout(G, b.M, b.d);
+  ScanArgs a{};
+  a.d = b.d;
+  a.dsub = b.dsub;
+  a.M = b.M;
+  a.tab_out = ext;
+  a.ex_q = exq;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int M = b.M;
+  const size_t n = (size_t)b.nq * b.npmax;
+  const size_t i0 = (size_t)blockIdx.x * G;
+  int32_t* sp = reinterpret_cast<int32_t*>(lds + L.ps);
+  int32_t* pq = reinterpret_cast<int32_t*>(lds + L.pq);
+  int32_t* pb = reinterpret_cast<int32_t*>(lds + L.pb);
+  int32_t* lo = reinterpret_cast<int32_t*>(lds + L.lo);
+  const int32_t* hi = reinterpret_cast<const int32_t*>(lds + L.hi);
+  __shared__ int s_probe[G];
+  if (tid < G) {
+    const bool ok = i0 + tid < n && b.probes[i0 + tid] >= 0;
+    s_probe[tid] = ok ? b.probes[i0 + tid] : -1;
+    pq[tid] = ok ? (int)(i0 + tid) : -1;  // destination row
+    pb[tid] = ok ? b.pbits[i0 + tid] : 16;
+  }
+  __syncthreads();
+  const int d4 = b.d >> 2, rs4 = ri_stride(b.d) >> 2;
+  for (int e = tid; e < G * d4; e += kThreads) {
+    const int g = e / d4, t4 = e - g * d4;
+    const int p = s_probe[g];
+    u32x2 v = {0u, 0u};
+    if (p >= 0) {
+      const size_t q = (i0 + g) / b.npmax;
+      const float4 qv = reinterpret_cast<const float4*>(b.Q + q * b.d)[t4];
+      const float4 cv = reinterpret_cast<const float4*>(b.C + (size_t)p * b.d)[t4];
+      const uint32_t v0 = (uint32_t)grid_val(qv.x - cv.x, b.grid_e, b.grid_kind) & 0xFFFFu;
+      const uint32_t v1 = (uint32_t)grid_val(qv.y - cv.y, b.grid_e, b.grid_kind) & 0xFFFFu;
+      const uint32_t v2 = (uint32_t)grid_val(qv.z - cv.z, b.grid_e, b.grid_kind) & 0xFFFFu;
+      const uint32_t v3 = (uint32_t)grid_val(qv.w - cv.w, b.grid_e, b.grid_kind) & 0xFFFFu;
+      v = (u32x2){v0 | (v1 << 16), v2 | (v3 << 16)};
+    }
+    reinterpret_cast<u32x2*>(lds + L.ri)[g * rs4 + t4] = v;
+  }
+  __syncthreads();
+  {
+    const int16_t* ri = reinterpret_cast<const int16_t*>(lds + L.ri);
+    int32_t* rr = reinterpret_cast<int32_t*>(lds + L.rr);
+    for (int e = tid; e < G * M; e += kThreads) {
+      const int g = e / M, m = e % M;
+      int32_t sacc = 0;
+      for (int t = 0; t < b.dsub; ++t) {
+        const int v = ri[g * ri_stride(b.d) + m * b.dsub + t];
+        sacc += v * v;
+      }
+      rr[e] = sacc;
+    }
+  }
+  __syncthreads();
+  for (int mp = wave; mp < M / 2; mp += kThreads / 64) {
+    u32x4 Bt[16], Bd[16];
+    base_frags<DT>(b, mp, lane, Bt, Bd);
+    if (ext) lut_mpair<32, G, DT, 4, false>(a, lds, L, M, G, mp, Bt, Bd);
+    else lut_mpair<32, G, DT, 1, false>(a, lds, L, M, G, mp, Bt, Bd);
+  }
+  __syncthreads();
+  int32_t* ps = sp;  // (the probe ids are in s_probe now)
+  if (tid < G) {
+    int32_t span = 0;
+    int64_t bsum = 0;
+    for (int m = 0; m < M; ++m) {
+      span = hi[tid * M + m] - lo[tid * M + m] > span ? hi[tid * M + m] - lo[tid * M + m] : span;
+      bsum += lo[tid * M + m];
+    }
+    const int64_t top = (1ll << pb[tid]) - 1, R = span;
+    int sh = 0;
+    while (((R + (sh ? (1ll << (sh - 1)) : 0)) >> sh) > top) ++sh;
+    ps[tid] = sh;
+    if (pq[tid] >= 0) {
+      exs[pq[tid]] = sh;
+      exb[pq[tid]] = bsum;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < G * M; e += kThreads) {
+    const int g = e / M, sh = ps[g];
+    lo[e] = (sh ? (1 << (sh - 1)) : 0) - lo[e];
+  }
+  __syncthreads();
+  for (int mp = wave; mp < M / 2; mp += kThreads / 64) {
+    u32x4 Bt[16], Bd[16];
+    base_frags<DT>(b, mp, lane, Bt, Bd);
+    lut_mpair<32, G, DT, 5, false>(a, lds, L, M, G, mp, Bt, Bd);
+  }
 }
 
 constexpr int kTabQ = 16;  // queries per workgroup of the table build (two 8-row MFMA tiles)

@@ -351,9 +351,10 @@ static amp_status check_policy(const amp_index* ix, const amp_precision_policy& 
     case AMP_POLICY_EXPLICIT: return set_error(AMP_EINVAL, "the server does not take the explicit policy");
     default: return set_error(AMP_EINVAL, "bad policy kind %d", p.kind);
   }
-  if (p.lut_dtype == AMP_LUT_F8E4M3) return set_error(AMP_EUNSUPPORTED, "FP8 LUT build is not supported");
-  if (p.lut_dtype != 0 && p.lut_dtype != AMP_LUT_BF16 && p.lut_dtype != AMP_LUT_F16)
+  if (p.lut_dtype != 0 && p.lut_dtype != AMP_LUT_BF16 && p.lut_dtype != AMP_LUT_F16 && p.lut_dtype != AMP_LUT_F8E4M3)
     return set_error(AMP_EINVAL, "bad LUT build dtype %d", p.lut_dtype);
+  if (p.lut_dtype == AMP_LUT_F8E4M3 && (ix->grid_kind != AMP_GRID_E4M3 || ix->metric == AMP_L1))
+    return set_error(AMP_EINVAL, "the FP8 LUT build needs an index on the e4m3 operand grid, L2 or inner product");
   return AMP_OK;
 }
 
