@@ -16,3 +16,4 @@ from .search import (  # noqa: F401
     feature_u, svr_eval, bits_from_score, predict_pair_bits, dc_ts, search,
 )
 from .exact import exact_knn, recall_1_at, recall_at  # noqa: F401
+from . import cl  # noqa: F401  (reduced-precision cluster locating)

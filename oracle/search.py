@@ -276,14 +276,17 @@ def _per_query(v, nq):
 
 
 def search(index, queries, k, nprobe, policy="fixed", bits=16, allowed=BITS_ALL,
-           model=None, explicit_bits=None, margin_q40=0, probes=None):
+           model=None, explicit_bits=None, margin_q40=0, probes=None, cl=None):
     """Full search of a query batch.
 
     policy: "fp32" (full-precision LUT), "fixed" (every pair at ``bits``),
     "adaptive" (predictor, ``model``), "explicit" (``explicit_bits`` [nq, npmax]
     by probe rank).  ``probes`` [nq, npmax] (-1 padded) overrides CL's
     selection (used to continue from another implementation's probe set when
-    the two differ only by a certified near-tie).
+    the two differ only by a certified near-tie).  ``cl`` selects the
+    integer CL on 8-bit codes (oracle.cl): a dict with "map" (the index's
+    sub-space map), "policy" ("fixed" at "bits", or "adaptive" with "model"
+    and low width "low").
 
     Returns a dict: ids [nq, kmax] int64, qdist [nq, kmax] int64 (-1 for fp32),
     dist [nq, kmax] float32, probes, bits, shift, base [nq, npmax].
@@ -318,7 +321,11 @@ def search(index, queries, k, nprobe, policy="fixed", bits=16, allowed=BITS_ALL,
     for i in range(nq):
         q = Q[i]
         # CL
-        if probes is None:
+        if probes is None and cl is not None:
+            from .cl import cl_probes
+            P, _, _ = cl_probes(q, index, cl["map"], int(npq[i]), cl["policy"], cl.get("bits", 8),
+                                cl.get("low", 4), cl.get("model"))
+        elif probes is None:
             P = select_probes(coarse_distances(q, C, metric), int(npq[i]))
         else:
             P = np.asarray(probes[i], dtype=I64)
