@@ -222,6 +222,24 @@ typedef struct amp_lut_export {
   int32_t* t;
 } amp_lut_export;
 
+/*
+ * Cluster locating (CL) policy of a search (amp_search_opts.cl_policy):
+ *   AMP_CL_FP32      FP32 coarse distances of the FP32 centroids (default)
+ *   AMP_CL_FIXED     integer coarse distances of 8-bit codes, every partial
+ *                    distance at cl_bits (1..8) operand bits
+ *   AMP_CL_ADAPTIVE  the same with a width per (query, dimension slice,
+ *                    sub-space) from the CL predictor: cl_bits (1..7, 0 = 4)
+ *                    or 8 bits
+ * The integer policies need the index's sub-space map (amp_index_build_cl_map;
+ * ADAPTIVE also a CL predictor), else AMP_EINVAL; not with out_coarse.  See
+ * amp_cl_map for the arithmetic.
+ * Optional outputs (same memory space as the other outputs):
+ *   out_cl_dist [nq][nlist] int32  the integer coarse distances D_i
+ *   out_cl_bits [nq][S][P] uint8   the width of every (slice, sub-space)
+ *                                  (ADAPTIVE)
+ */
+enum { AMP_CL_FP32 = 0, AMP_CL_FIXED = 1, AMP_CL_ADAPTIVE = 2 };
+
 typedef struct amp_search_opts {
   int32_t mem;
   void* stream;
@@ -236,6 +254,9 @@ typedef struct amp_search_opts {
   int32_t* out_status;
   int32_t kmax, npmax;
   const amp_lut_export* lut_export;
+  int32_t cl_policy, cl_bits;
+  int32_t* out_cl_dist;
+  uint8_t* out_cl_bits;
 } amp_search_opts;
 
 /* Build an index handle from arrays (copied).  Validates every constraint
@@ -379,6 +400,82 @@ amp_status amp_index_autotune(amp_index* index, const void* queries, int64_t nq,
  * queue 0..1). */
 amp_status amp_index_get_tuning(const amp_index* index, amp_tune_entry* entries, int32_t capacity, int32_t* count);
 amp_status amp_index_set_tuning(amp_index* index, const amp_tune_entry* entries, int32_t count);
+
+/*
+ * Vector space division for cluster locating with adaptive operand precision
+ * (Sec. 3.1: dimension slices, then clusters of each slice; Sec. 3.3
+ * sub-space features; Sec. 4.1 the distance module's CL pass summing
+ * partial distances over slices; Sec. 4.2 MSB-first operand bits).
+ *
+ * Codes: every centroid and query value x becomes the 8-bit signed code
+ * v = clamp(round_half_even((x - o) * 2^-ec), -128, 127), x - o rounded once
+ * to FP32; o is the FP32 midpoint of the centroids' value range (inner
+ * product: 0) and ec the smallest exponent with every centroid value within
+ * 127 * 2^ec of o.  A b-bit operand keeps the top b bits of the code (floor
+ * to a multiple of 2^(8-b)).
+ * Slices: S equal runs of w = d / S consecutive dimensions.  In each slice
+ * the nlist centroid codes are clustered into P sub-spaces (k-means, FP64,
+ * `iters` Lloyd steps from P distinct seeded starting points, empty clusters
+ * reseeded from the farthest point); the centres are then rounded to
+ * integers (half away from zero) and every centroid slice is assigned to its
+ * nearest rounded centre (ties: lower index).  radius = ceil of the largest
+ * member distance, count = members.
+ * Distances: for query q, slice s of centroid i is computed at the width b of
+ * its sub-space assign[i][s]; D_i = sum_s sum_t (vq_t^(b) - vc_it^(b))^2
+ * (L2) or -sum_s sum_t vq_t^(b) vc_it^(b) (inner product), exact integers;
+ * the probes are the nprobe smallest (D_i, i).
+ * Predictor: for slice s and sub-space u the features {d', r1, r2, n1, n2}:
+ * d' = |vq_s - centre_su|^2, r1 / n1 of C1 (the sub-space with the smallest
+ * d', ties: lower index), r2 / n2 of u; the model is evaluated as
+ * amp_predictor_model describes, and the width is the low width if
+ * y <= theta[0], else 8 bits.
+ *
+ * amp_index_build_cl_map: host computation on the index's centroids.
+ * Requires d % S == 0, d / S <= 64, 1 <= P <= min(nlist, 1024), metric L2 or
+ * inner product (else AMP_EINVAL / AMP_EUNSUPPORTED).  Replaces any earlier
+ * map and drops the CL predictor.
+ * amp_index_get_cl_map: borrow the map (pointers into the handle, valid
+ * until it is freed or the map rebuilt); AMP_EINVAL if there is none.
+ *   assign [nlist][S], centre [S][P][w], radius [S][P], count [S][P] int32.
+ */
+typedef struct amp_cl_map {
+  int32_t S, P, w;
+  float o;
+  int32_t ec;
+  const int32_t* assign;
+  const int32_t* centre;
+  const int32_t* radius;
+  const int32_t* count;
+} amp_cl_map;
+
+amp_status amp_index_build_cl_map(amp_index* index, int32_t S, int32_t P, int32_t iters, uint64_t seed);
+amp_status amp_index_get_cl_map(const amp_index* index, amp_cl_map* out);
+
+/* The CL predictor (same fixed-point form as amp_predictor_model; only
+ * theta[0] is used): set (copied; needs a sub-space map, AMP_EINVAL
+ * otherwise), get (as amp_index_get_predictor). */
+amp_status amp_index_set_cl_predictor(amp_index* index, const amp_predictor_model* model);
+amp_status amp_index_get_cl_predictor(const amp_index* index, amp_predictor_model* out, int32_t* sv,
+                                      int32_t* beta, int32_t* table, int32_t capacity);
+
+/*
+ * Offline fit of the CL predictor (Sec. 3.3-3.4; the paper's CL setting is
+ * gamma = 0.1, C = 10) on training queries (host [nq][d] float).  For each
+ * query the trainer takes the full-width (8-bit) integer distances D_i and
+ * the margin of every centroid against the nprobe boundary (a probed
+ * centroid: D of the (nprobe+1)-th minus D_i; another: D_i minus D of the
+ * nprobe-th); for slice s and sub-space u the label is the low width
+ * low_bits if twice the largest change of a member's D_i caused by computing
+ * its slice s at low_bits stays below the smallest member margin, else 8.
+ * Empty sub-spaces give no sample.  n_samples pairs stratified by label, an
+ * epsilon-SVR (gamma, C, epsilon, tol, max_iter as in amp_train_params;
+ * allowed_bits_mask is ignored) fitted by SMO, exported to fixed point with
+ * theta[0] halfway between the two labels, attached to the index.
+ * report->label_hist[0] counts low labels, [1] full-width ones.
+ */
+amp_status amp_index_train_cl_predictor(amp_index* index, const float* train_queries, int64_t nq,
+                                        int32_t nprobe, int32_t low_bits, const amp_train_params* params,
+                                        amp_train_report* report /* optional */);
 
 /* Copy the index to device `device` (hipGetDevice numbering) and derive the
  * device-side tables (centroid norms, grid codebook).  Called implicitly by

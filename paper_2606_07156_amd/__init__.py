@@ -30,6 +30,8 @@ AMP_N_STAGES = 9
 STAGES = ("cl", "topn", "predict", "base", "queue", "scan1", "scan2", "merge", "total")
 POLICIES = {"fp32": AMP_POLICY_FP32, "fixed": AMP_POLICY_FIXED,
             "adaptive": AMP_POLICY_ADAPTIVE, "explicit": AMP_POLICY_EXPLICIT}
+AMP_CL_FP32, AMP_CL_FIXED, AMP_CL_ADAPTIVE = 0, 1, 2
+CL_POLICIES = {"fp32": AMP_CL_FP32, "fixed": AMP_CL_FIXED, "adaptive": AMP_CL_ADAPTIVE}
 
 
 class AmpError(RuntimeError):
@@ -69,7 +71,13 @@ class _Opts(C.Structure):
                 ("out_probes", C.c_void_p), ("out_bits", C.c_void_p), ("out_coarse", C.c_void_p),
                 ("stage_ms", C.c_void_p), ("flags", C.c_uint32), ("q_dtype", C.c_int32), ("work", C.c_void_p),
                 ("out_status", C.c_void_p), ("kmax", C.c_int32), ("npmax", C.c_int32),
-                ("lut_export", C.POINTER(_LutExport))]
+                ("lut_export", C.POINTER(_LutExport)), ("cl_policy", C.c_int32), ("cl_bits", C.c_int32),
+                ("out_cl_dist", C.c_void_p), ("out_cl_bits", C.c_void_p)]
+
+
+class _ClMap(C.Structure):
+    _fields_ = [("S", C.c_int32), ("P", C.c_int32), ("w", C.c_int32), ("o", C.c_float), ("ec", C.c_int32),
+                ("assign", C.c_void_p), ("centre", C.c_void_p), ("radius", C.c_void_p), ("count", C.c_void_p)]
 
 
 class _BuildParams(C.Structure):
@@ -92,6 +100,8 @@ class _TrainReport(C.Structure):
 _lib = None
 EXPORTS = ("amp_index_from_arrays", "amp_index_build", "amp_index_get_arrays", "amp_index_set_predictor", "amp_index_get_predictor",
            "amp_index_train_predictor", "amp_svr_fit",
+           "amp_index_build_cl_map", "amp_index_get_cl_map", "amp_index_set_cl_predictor",
+           "amp_index_get_cl_predictor", "amp_index_train_cl_predictor",
            "amp_index_to_device",
            "amp_index_save", "amp_index_load", "amp_index_info", "amp_search", "amp_search_noalloc",
            "amp_index_autotune", "amp_index_get_tuning", "amp_index_set_tuning",
@@ -122,6 +132,12 @@ def lib():
                                                 C.POINTER(_TrainParams), C.POINTER(_TrainReport)]
         L.amp_svr_fit.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double,
                                   C.c_int32, C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32)]
+        L.amp_index_build_cl_map.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_uint64]
+        L.amp_index_get_cl_map.argtypes = [C.c_void_p, C.POINTER(_ClMap)]
+        L.amp_index_set_cl_predictor.argtypes = [C.c_void_p, C.POINTER(_Model)]
+        L.amp_index_get_cl_predictor.argtypes = L.amp_index_get_predictor.argtypes
+        L.amp_index_train_cl_predictor.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_int32,
+                                                   C.POINTER(_TrainParams), C.POINTER(_TrainReport)]
         L.amp_index_to_device.argtypes = [C.c_void_p, C.c_int32]
         L.amp_index_save.argtypes = [C.c_void_p, C.c_char_p]
         L.amp_index_load.argtypes = [C.c_char_p, C.POINTER(C.c_void_p)]
@@ -286,6 +302,73 @@ def amp_index_train_predictor(index, train_queries, k, nprobe, n_samples=1280, g
                 smo_iterations=r.smo_iterations, train_rmse=r.train_rmse)
 
 
+def amp_index_build_cl_map(index, S, P, iters=20, seed=0):
+    """Vector space division for integer cluster locating (host)."""
+    _check(lib().amp_index_build_cl_map(index.handle, int(S), int(P), int(iters), int(seed)))
+
+
+def amp_index_get_cl_map(index):
+    """Copies of the sub-space map: dict S, P, w, o (float32), ec, assign
+    [nlist, S], centre [S, P, w], radius [S, P], count [S, P]."""
+    m = _ClMap()
+    _check(lib().amp_index_get_cl_map(index.handle, C.byref(m)))
+    nl = amp_index_info(index)["nlist"]
+
+    def arr(ptr, shape):
+        buf = (C.c_int32 * int(np.prod(shape))).from_address(ptr)
+        return np.ctypeslib.as_array(buf).reshape(shape).astype(np.int64, copy=True)
+
+    return dict(S=m.S, P=m.P, w=m.w, o=np.float32(m.o), ec=m.ec, assign=arr(m.assign, (nl, m.S)),
+                centre=arr(m.centre, (m.S, m.P, m.w)), radius=arr(m.radius, (m.S, m.P)),
+                count=arr(m.count, (m.S, m.P)))
+
+
+def _model_struct(model):
+    sv = np.ascontiguousarray(model["sv"], dtype=np.int32)
+    beta = np.ascontiguousarray(model["beta"], dtype=np.int32)
+    table = np.ascontiguousarray(model["table"], dtype=np.int32)
+    m = _Model(int(model["n_sv"]), _ptr(sv), _ptr(beta), _ptr(table), int(model["beta0"]),
+               (C.c_int64 * 5)(*[int(v) for v in model["feat_lo"]]),
+               (C.c_int64 * 5)(*[int(v) for v in model["feat_mul"]]),
+               int(model["g_mul"]), (C.c_int64 * 3)(*[int(v) for v in model["theta"]]))
+    return m, (sv, beta, table)
+
+
+def amp_index_set_cl_predictor(index, model):
+    m, keep = _model_struct(model)
+    _check(lib().amp_index_set_cl_predictor(index.handle, C.byref(m)))
+
+
+def amp_index_get_cl_predictor(index):
+    """The index's CL predictor as a model dict."""
+    m = _Model()
+    st = lib().amp_index_get_cl_predictor(index.handle, C.byref(m), None, None, None, 0)
+    n = m.n_sv
+    if st != AMP_OK and n == 0 and "no CL predictor" in amp_last_error():
+        _check(st)
+    sv = np.zeros((max(n, 1), 5), np.int32)
+    beta = np.zeros(max(n, 1), np.int32)
+    table = np.zeros(1024, np.int32)
+    _check(lib().amp_index_get_cl_predictor(index.handle, C.byref(m), _ptr(sv), _ptr(beta), _ptr(table), n))
+    return dict(n_sv=n, sv=sv[:n], beta=beta[:n], table=table, beta0=m.beta0,
+                feat_lo=np.array(m.feat_lo[:], np.int64), feat_mul=np.array(m.feat_mul[:], np.int64),
+                g_mul=int(m.g_mul), theta=np.array(m.theta[:], np.int64))
+
+
+def amp_index_train_cl_predictor(index, train_queries, nprobe, low=4, n_samples=1280, gamma=0.1, C_=10.0,
+                                 epsilon=0.1, tol=1e-3, max_iter=0, seed=0):
+    """Fit and attach the CL predictor (paper's CL setting gamma 0.1, C 10);
+    returns the training report (label_hist[0]: low labels, [1]: 8 bits)."""
+    q = np.ascontiguousarray(train_queries, dtype=np.float32)
+    p = _TrainParams(int(n_samples), int(max_iter), float(gamma), float(C_), float(epsilon), float(tol), 0,
+                     int(seed))
+    r = _TrainReport()
+    _check(lib().amp_index_train_cl_predictor(index.handle, _ptr(q), int(q.shape[0]), int(nprobe), int(low),
+                                              C.byref(p), C.byref(r)))
+    return dict(n_pairs=r.n_pairs, label_hist=list(r.label_hist)[:2], n_samples=r.n_samples, n_sv=r.n_sv,
+                smo_iterations=r.smo_iterations, train_rmse=r.train_rmse)
+
+
 def amp_svr_fit(K, y, C_=1.0, epsilon=0.1, tol=1e-3, max_iter=100000):
     """Test hook: the SVR solver of the trainer on a precomputed kernel."""
     K = np.ascontiguousarray(K, dtype=np.float64)
@@ -378,17 +461,21 @@ def amp_search(index, queries, k, nprobe, policy="fixed", bits=16, allowed=(4, 8
                margin_q40=0, explicit_bits=None, lut_dtype=0, want_qdist=True,
                want_probes=False, want_bits=False, want_coarse=False, stage_ms=False,
                out=None, stream=None, graph=False, q_dtype=None, work=False, kmax=None, npmax=None,
-               want_status=False, _entry="amp_search"):
+               want_status=False, cl_policy="fp32", cl_bits=0, want_cl_dist=False, want_cl_bits=False,
+               _entry="amp_search"):
     """Search a batch.
 
     Host mode (``queries`` a numpy array): returns a dict of numpy arrays.
     Device mode (``queries`` a torch CUDA tensor): ``out`` must be a dict of
     preallocated torch CUDA tensors ids [nq,kmax] int64, dist [nq,kmax] float32
     and optionally qdist / probes / bits / coarse / status (int32 [1]) /
-    lut_q, lut_shift, lut_base, lut_t (the LUT export test hook); work is enqueued
+    lut_q, lut_shift, lut_base, lut_t (the LUT export test hook) / cl_dist
+    (int32 [nq, nlist]) / cl_bits (uint8 [nq, S, P]); work is enqueued
     on ``stream`` (a torch stream or raw handle) and the call returns at once.
     Device mode also takes ``k`` / ``nprobe`` as int32 CUDA tensors of nq
     entries (device-resident per-query sizes, bounded by ``kmax`` / ``npmax``).
+    ``cl_policy`` "fixed" / "adaptive" selects integer cluster locating on
+    8-bit codes (``cl_bits``: the fixed width, or the adaptive low width).
     """
     device = hasattr(queries, "data_ptr")
     nq = int(queries.shape[0])
@@ -426,7 +513,8 @@ def amp_search(index, queries, k, nprobe, policy="fixed", bits=16, allowed=(4, 8
         opts = _Opts(AMP_MEM_DEVICE, C.c_void_p(sh) if sh else None, _ptr(o.get("qdist")),
                      _ptr(o.get("probes")), _ptr(o.get("bits")), _ptr(o.get("coarse")), _ptr(ms),
                      flags, qd, _ptr(wk), _ptr(o.get("status")), kmax if dev_sizes else 0,
-                     npmax if dev_sizes else 0, C.pointer(exp) if exp is not None else None)
+                     npmax if dev_sizes else 0, C.pointer(exp) if exp is not None else None,
+                     CL_POLICIES[cl_policy], int(cl_bits), _ptr(o.get("cl_dist")), _ptr(o.get("cl_bits")))
         _check(fn(index.handle, _ptr(queries), nq, _ptr(kk), _ptr(npb), per_query,
                   C.byref(pol), C.byref(opts), _ptr(o["ids"]), _ptr(o["dist"])))
         if stage_ms:
@@ -445,10 +533,16 @@ def amp_search(index, queries, k, nprobe, policy="fixed", bits=16, allowed=(4, 8
     if want_coarse:
         info = amp_index_info(index)
         res["coarse"] = np.empty((nq, info["nlist"]), np.float32)
+    if want_cl_dist:
+        res["cl_dist"] = np.empty((nq, amp_index_info(index)["nlist"]), np.int32)
+    if want_cl_bits:
+        cm = _ClMap()
+        _check(lib().amp_index_get_cl_map(index.handle, C.byref(cm)))
+        res["cl_bits"] = np.empty((nq, cm.S, cm.P), np.uint8)
     st = np.zeros(1, np.int32) if want_status else None
     opts = _Opts(AMP_MEM_HOST, None, _ptr(res.get("qdist")), _ptr(res.get("probes")),
                  _ptr(res.get("bits")), _ptr(res.get("coarse")), _ptr(ms), flags, qd, _ptr(wk), _ptr(st), 0, 0,
-                 None)
+                 None, CL_POLICIES[cl_policy], int(cl_bits), _ptr(res.get("cl_dist")), _ptr(res.get("cl_bits")))
     status = fn(index.handle, _ptr(q), nq, _ptr(kk), _ptr(npb), per_query,
                 C.byref(pol), C.byref(opts), _ptr(res["ids"]), _ptr(res["dist"]))
     if want_status:

@@ -14,7 +14,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "scan_ph1.hip", "scan_ph2.hip", "scan_ph3.hip", "noalloc.hip", "capi.cpp", "train.cpp", "build.cpp", "server.cpp", "tune.cpp")]
+SRC = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "scan_ph1.hip", "scan_ph2.hip", "scan_ph3.hip", "cl.hip", "noalloc.hip", "capi.cpp", "train.cpp", "build.cpp", "clmap.cpp", "server.cpp", "tune.cpp")]
 OUT = os.path.join(HERE, "libamp.so")
 BUILD = os.path.join(HERE, "_build")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")

@@ -64,6 +64,13 @@ struct DeviceIndex {
   int64_t* offsets = nullptr;  // [nlist+1]
   int32_t* radq = nullptr;     // [nlist]
   DeviceModel model;
+  // reduced-precision cluster locating (sub-space map, CL predictor)
+  int8_t* clc = nullptr;       // [nlist][S][Kp] centroid codes, each slice zero-padded to Kp bytes
+  uint16_t* clasg = nullptr;   // [nlist][S] sub-space of every centroid slice
+  int8_t* clz = nullptr;       // [S][P][Kp] sub-space centres (codes), zero-padded
+  int32_t* clr = nullptr;      // [S][P] radius
+  int32_t* cln = nullptr;      // [S][P] count
+  DeviceModel clmodel;
 };
 
 // what a captured search graph depends on
@@ -83,6 +90,8 @@ struct GraphKey {
   int32_t wpr;
   int32_t q_dtype;
   int32_t queue;
+  int32_t cl_policy, cl_bits;
+  const void *cl_dist, *cl_bits_out;
   bool operator==(const GraphKey& o) const {
     return q == o.q && ids == o.ids && dist == o.dist && qdist == o.qdist && probes == o.probes &&
            bits == o.bits && coarse == o.coarse && status == o.status && kptr == o.kptr && npptr == o.npptr &&
@@ -90,7 +99,8 @@ struct GraphKey {
            nprobe == o.nprobe && kind == o.kind && fixed_bits == o.fixed_bits && allowed == o.allowed &&
            margin == o.margin && lut_dtype == o.lut_dtype && ws_gen == o.ws_gen && model_gen == o.model_gen &&
            chunk == o.chunk && chunk1 == o.chunk1 && capq == o.capq && wpr == o.wpr &&
-           q_dtype == o.q_dtype && queue == o.queue;
+           q_dtype == o.q_dtype && queue == o.queue && cl_policy == o.cl_policy && cl_bits == o.cl_bits &&
+           cl_dist == o.cl_dist && cl_bits_out == o.cl_bits_out;
   }
 };
 struct GraphSlot {
@@ -136,6 +146,12 @@ struct Workspace {
   int32_t* ipmask = nullptr;   // [nq] widths the query's pairs use (bit b/4 - 1)
   uint8_t* retry = nullptr;    // [nq] query takes part in the phase-2 re-run
   int64_t* tau_id = nullptr;   // [nq] id part of the re-run's bound
+  // integer cluster locating (laid out when the index has a sub-space map)
+  int8_t* clq = nullptr;       // [nq][S][Kp] query codes
+  int32_t* clqn = nullptr;     // [nq][S][2] |vq_s|^2 at the two widths of the search
+  uint32_t* clmask = nullptr;  // [nq][S][PW] sub-spaces at the low width (one bit each)
+  int32_t* clcn = nullptr;     // [nlist][S][2] |vc_s|^2 at the two widths
+  size_t cap_cl = 0;           // cl_layout_key of the index the buffers were laid out for
   uint32_t* ccount = nullptr;  // [nq] candidate count
   uint64_t* ckey = nullptr;    // [nq][capq]
   int64_t* cid = nullptr;      // [nq][capq]
@@ -174,6 +190,19 @@ struct amp_index {
   std::vector<int32_t> sv, beta, table;
   int64_t beta0 = 0, feat_lo[5] = {}, feat_mul[5] = {}, theta[3] = {};
   uint64_t g_mul = 0;
+  // sub-space map of reduced-precision cluster locating (host copy)
+  bool has_clmap = false;
+  int32_t cl_S = 0, cl_P = 0, cl_w = 0, cl_ec = 0;
+  float cl_o = 0.f;
+  std::vector<int8_t> cl_codes;                   // [nlist][d]
+  std::vector<int32_t> cl_assign, cl_centre, cl_radius, cl_count;
+  // CL predictor (host copy)
+  bool has_cl_model = false;
+  int32_t cl_n_sv = 0;
+  std::vector<int32_t> cl_sv, cl_beta, cl_table;
+  int64_t cl_beta0 = 0, cl_feat_lo[5] = {}, cl_feat_mul[5] = {}, cl_theta[3] = {};
+  uint64_t cl_g_mul = 0;
+  bool dev_cl_stale = true;    // the device copy of the map / CL predictor is out of date
   // device side
   amp::DeviceIndex dev;
   bool dev_model_stale = true;
@@ -222,6 +251,13 @@ struct SearchDims {
   int32_t* out_status;   // status word written at the end of the search, or null
   int reruns;            // phase-2 re-runs of overflowed queries (2; fewer only to test overflow reporting)
   const amp_lut_export* lut_export;  // test hook: every pair's LUT after the search, or null
+  // cluster locating
+  int cl_policy;         // AMP_CL_*
+  int cl_lo, cl_hi;      // operand widths of the two classes (fixed: both the fixed width)
+  int cl_S, cl_P, cl_w, cl_kp, cl_pw, cl_ec;
+  float cl_o;
+  int32_t* out_cl_dist;  // [nq][nlist] or null
+  uint8_t* out_cl_bits;  // [nq][S][P] or null
 };
 
 struct ModelArgs {
@@ -236,11 +272,28 @@ struct ModelArgs {
   int64_t theta[3];
 };
 
+// CL operand codes (host; the definition the search kernels follow)
+void cl_params_host(const std::vector<float>& C, int metric, float* o, int* ec);
+int8_t cl_code_host(float x, float o, int ec);
+
+// padded bytes of one slice of CL codes (one MFMA K: 32 or 64)
+inline int cl_kpad(int w) { return w <= 32 ? 32 : 64; }
+// shape of a workspace's CL buffers (0: none): slices, padded slice bytes,
+// mask words per (query, slice)
+inline size_t cl_layout_key(const amp_index* ix) {
+  if (!ix->has_clmap) return 0;
+  return (size_t)ix->cl_S | ((size_t)cl_kpad(ix->cl_w) << 12) | ((size_t)((ix->cl_P + 31) / 32) << 20);
+}
+
 hipError_t launch_prep_index(const amp_index* ix, hipStream_t st);
 hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* queries,
-                         const SearchDims& sd, const ModelArgs& ma, int64_t* out_ids,
+                         const SearchDims& sd, const ModelArgs& ma, const ModelArgs& clma, int64_t* out_ids,
                          float* out_dist, int64_t* out_qdist, float* out_coarse,
                          hipStream_t st, hipEvent_t* ev /* [AMP_N_STAGES+1] or null */);
+// cluster locating on 8-bit codes (integer policies): order keys of the
+// coarse distances into keys [nq][nlist]
+hipError_t launch_cl(const amp_index* ix, const Workspace& ws, const float* queries, const SearchDims& sd,
+                     const ModelArgs& clma, float* keys, hipStream_t st);
 // index build: nearest centroid of n rows (dd floats, leading dimension ld)
 // among k centroids [k][dd], with its squared distance (out_d may be null);
 // xn [n] and cn [k] are scratch for the squared norms

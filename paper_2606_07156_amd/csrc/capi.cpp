@@ -47,7 +47,8 @@ static amp_status dalloc(T** p, size_t n, std::vector<void*>* track = nullptr) {
 
 static void free_device_index(DeviceIndex& d) {
   void* ptrs[] = {d.centroids, d.cnorm, d.codebook, d.bsw, d.bsw16, d.bsw8, d.cbi16, d.ci16, d.lorder, d.lpos, d.codes, d.ids,
-                  d.offsets, d.radq, d.model.sv, d.model.beta, d.model.table};
+                  d.offsets, d.radq, d.model.sv, d.model.beta, d.model.table, d.clc, d.clasg, d.clz, d.clr,
+                  d.cln, d.clmodel.sv, d.clmodel.beta, d.clmodel.table};
   for (void* p : ptrs)
     if (p) hipFree(p);
   d = DeviceIndex();
@@ -207,6 +208,58 @@ static amp_status upload_model(amp_index* ix) {
   return AMP_OK;
 }
 
+// the sub-space map of integer cluster locating (codes padded per slice to
+// one MFMA K) and the CL predictor, to the index's device
+static amp_status upload_cl(amp_index* ix) {
+  DeviceIndex& d = ix->dev;
+  void* old[] = {d.clc, d.clasg, d.clz, d.clr, d.cln, d.clmodel.sv, d.clmodel.beta, d.clmodel.table};
+  for (void* p : old)
+    if (p) hipFree(p);
+  d.clc = nullptr;
+  d.clasg = nullptr;
+  d.clz = nullptr;
+  d.clr = d.cln = nullptr;
+  d.clmodel = DeviceModel();
+  if (!ix->has_clmap) {
+    ix->dev_cl_stale = false;
+    return AMP_OK;
+  }
+  const size_t nl = ix->nlist, S = ix->cl_S, P = ix->cl_P, w = ix->cl_w, kp = cl_kpad(ix->cl_w), dd = ix->d;
+  std::vector<int8_t> codes(nl * S * kp, 0), cent(S * P * kp, 0);
+  std::vector<uint16_t> asg(nl * S);
+  for (size_t i = 0; i < nl; ++i)
+    for (size_t s = 0; s < S; ++s) {
+      for (size_t t = 0; t < w; ++t) codes[(i * S + s) * kp + t] = ix->cl_codes[i * dd + s * w + t];
+      asg[i * S + s] = (uint16_t)ix->cl_assign[i * S + s];
+    }
+  for (size_t s = 0; s < S; ++s)
+    for (size_t u = 0; u < P; ++u)
+      for (size_t t = 0; t < w; ++t) cent[(s * P + u) * kp + t] = (int8_t)ix->cl_centre[(s * P + u) * w + t];
+  amp_status st;
+  if ((st = dalloc(&d.clc, codes.size())) || (st = dalloc(&d.clasg, asg.size())) ||
+      (st = dalloc(&d.clz, cent.size())) || (st = dalloc(&d.clr, S * P)) || (st = dalloc(&d.cln, S * P)))
+    return st;
+  AMP_HIP(hipMemcpy(d.clc, codes.data(), codes.size(), hipMemcpyHostToDevice));
+  AMP_HIP(hipMemcpy(d.clasg, asg.data(), asg.size() * 2, hipMemcpyHostToDevice));
+  AMP_HIP(hipMemcpy(d.clz, cent.data(), cent.size(), hipMemcpyHostToDevice));
+  AMP_HIP(hipMemcpy(d.clr, ix->cl_radius.data(), S * P * 4, hipMemcpyHostToDevice));
+  AMP_HIP(hipMemcpy(d.cln, ix->cl_count.data(), S * P * 4, hipMemcpyHostToDevice));
+  if (ix->has_cl_model) {
+    DeviceModel& dm = d.clmodel;
+    if ((st = dalloc(&dm.sv, 5 * (size_t)std::max(1, ix->cl_n_sv))) ||
+        (st = dalloc(&dm.beta, (size_t)std::max(1, ix->cl_n_sv))) || (st = dalloc(&dm.table, (size_t)kTableN)))
+      return st;
+    if (ix->cl_n_sv) {
+      AMP_HIP(hipMemcpy(dm.sv, ix->cl_sv.data(), ix->cl_sv.size() * 4, hipMemcpyHostToDevice));
+      AMP_HIP(hipMemcpy(dm.beta, ix->cl_beta.data(), ix->cl_beta.size() * 4, hipMemcpyHostToDevice));
+    }
+    AMP_HIP(hipMemcpy(dm.table, ix->cl_table.data(), kTableN * 4, hipMemcpyHostToDevice));
+    dm.n_sv = ix->cl_n_sv;
+  }
+  ix->dev_cl_stale = false;
+  return AMP_OK;
+}
+
 static amp_status to_device_locked(amp_index* ix, int device) {
   if (ix->dev.device == device && ix->dev.centroids) return AMP_OK;
   free_device_index(ix->dev);
@@ -251,6 +304,7 @@ static amp_status to_device_locked(amp_index* ix, int device) {
   AMP_HIP(hipDeviceSynchronize());
   d.device = device;
   ix->dev_model_stale = true;
+  ix->dev_cl_stale = true;
   return AMP_OK;
 }
 
@@ -267,6 +321,7 @@ amp_status amp_index_to_device(amp_index* ix, int32_t device) {
   // the predictor goes up with the index (and again after a change), so that
   // searches that must not allocate find it resident
   if (s == AMP_OK && ix->has_model && ix->dev_model_stale) s = upload_model(ix);
+  if (s == AMP_OK && ix->dev_cl_stale) s = upload_cl(ix);
   return s;
 }
 
@@ -477,6 +532,16 @@ static amp_status lay_out(const amp_index* ix, Workspace& w, size_t nq, size_t n
     AMP_TAKE(&w.ipsh, ip ? nq * 4 : 1);
     AMP_TAKE(&w.ipmask, ip ? nq : 1);
   }
+  {
+    // integer cluster locating (indexes with a sub-space map), else a token
+    const bool cl = ix->has_clmap;
+    const size_t S = cl ? ix->cl_S : 0, kp = cl ? cl_kpad(ix->cl_w) : 0, pw = cl ? (ix->cl_P + 31) / 32 : 0;
+    AMP_TAKE(&w.clq, cl ? nq * S * kp : 1);
+    AMP_TAKE(&w.clqn, cl ? nq * S * 2 : 1);
+    AMP_TAKE(&w.clmask, cl ? nq * S * pw : 1);
+    AMP_TAKE(&w.clcn, cl ? (size_t)ix->nlist * S * 2 : 1);
+    w.cap_cl = cl_layout_key(ix);
+  }
   AMP_TAKE(&w.retry, nq);
   AMP_TAKE(&w.tau_id, nq);
   AMP_TAKE(&w.ccount, nq);
@@ -509,7 +574,8 @@ static amp_status lay_out(const amp_index* ix, Workspace& w, size_t nq, size_t n
 // grow a (non-fixed) workspace; the buffers move, so captured graphs go too
 static amp_status ensure_workspace(amp_index* ix, Workspace& w, size_t nq, size_t np, size_t kmax, size_t capq,
                                    int64_t units) {
-  if (nq <= w.cap_nq && np <= w.cap_np && kmax <= w.cap_k && capq == w.capq && units <= w.cap_units)
+  if (nq <= w.cap_nq && np <= w.cap_np && kmax <= w.cap_k && capq == w.capq && units <= w.cap_units &&
+      w.cap_cl == cl_layout_key(ix))
     return AMP_OK;
   if (w.fixed) return set_error(AMP_EINVAL, "search does not fit its fixed workspace");
   nq = std::max(nq, w.cap_nq);
@@ -679,6 +745,27 @@ amp_status search_on(amp_index* ix, Workspace& w, const void* queries, int64_t n
       return set_error(AMP_EINVAL, "the LUT export needs device memory, an integer policy, L2 or inner product, "
                                    "no graph replay, and q, shift and base buffers");
   }
+  const int cl_policy = opts->cl_policy;
+  int cl_lo = 8, cl_hi = 8;
+  if (cl_policy != AMP_CL_FP32) {
+    if (cl_policy != AMP_CL_FIXED && cl_policy != AMP_CL_ADAPTIVE)
+      return set_error(AMP_EINVAL, "bad cluster-locating policy %d", cl_policy);
+    if (!ix->has_clmap) return set_error(AMP_EINVAL, "integer cluster locating needs a sub-space map");
+    if (cl_policy == AMP_CL_ADAPTIVE && !ix->has_cl_model)
+      return set_error(AMP_EINVAL, "adaptive cluster locating needs a CL predictor");
+    if (opts->out_coarse) return set_error(AMP_EINVAL, "out_coarse is FP32 cluster locating's output (out_cl_dist)");
+    if (cl_policy == AMP_CL_FIXED) {
+      if (opts->cl_bits < 1 || opts->cl_bits > 8) return set_error(AMP_EINVAL, "cl_bits must be 1..8");
+      cl_lo = cl_hi = opts->cl_bits;
+    } else {
+      cl_lo = opts->cl_bits ? opts->cl_bits : 4;
+      if (cl_lo < 1 || cl_lo > 7) return set_error(AMP_EINVAL, "adaptive cl_bits (low width) must be 1..7");
+    }
+  } else if (opts->out_cl_dist || opts->out_cl_bits) {
+    return set_error(AMP_EINVAL, "out_cl_dist / out_cl_bits need an integer cluster-locating policy");
+  }
+  if (opts->out_cl_bits && cl_policy != AMP_CL_ADAPTIVE)
+    return set_error(AMP_EINVAL, "out_cl_bits needs adaptive cluster locating");
   const bool use_graph = (opts->flags & AMP_SEARCH_GRAPH) != 0;
   if (use_graph && (host || (per_query && !dev_sizes) || opts->stage_ms || opts->work ||
                     pol->kind == AMP_POLICY_EXPLICIT))
@@ -709,10 +796,15 @@ amp_status search_on(amp_index* ix, Workspace& w, const void* queries, int64_t n
       return set_error(AMP_EINVAL, "index is not resident on device %d (amp_index_to_device first)", dev);
     if (pol->kind == AMP_POLICY_ADAPTIVE && ix->dev_model_stale)
       return set_error(AMP_EINVAL, "predictor changed since amp_index_to_device (call it again)");
+    if (cl_policy != AMP_CL_FP32 && ix->dev_cl_stale)
+      return set_error(AMP_EINVAL, "sub-space map or CL predictor changed since amp_index_to_device (call it again)");
   } else {
     if ((s = to_device_locked(ix, dev)) != AMP_OK) return s;
     if (pol->kind == AMP_POLICY_ADAPTIVE && ix->dev_model_stale && (s = upload_model(ix)) != AMP_OK) return s;
+    if (cl_policy != AMP_CL_FP32 && ix->dev_cl_stale && (s = upload_cl(ix)) != AMP_OK) return s;
   }
+  if (w.fixed && cl_policy != AMP_CL_FP32 && w.cap_cl != cl_layout_key(ix))
+    return set_error(AMP_EINVAL, "search does not fit its fixed workspace");
   // the schedule: the autotuner's entry for this policy kind and batch size,
   // if any (results do not depend on it)
   amp_tune_entry tc{};
@@ -821,6 +913,51 @@ amp_status search_on(amp_index* ix, Workspace& w, const void* queries, int64_t n
   sd.reruns = (int)std::min<size_t>(2, env_size("AMP_RERUNS", 2));
   if (const char* rv = getenv("AMP_RERUNS"))
     if (rv[0] == '0') sd.reruns = 0;
+  sd.cl_policy = cl_policy;
+  sd.cl_lo = cl_lo;
+  sd.cl_hi = cl_hi;
+  sd.cl_S = ix->cl_S;
+  sd.cl_P = ix->cl_P;
+  sd.cl_w = ix->cl_w;
+  sd.cl_kp = ix->has_clmap ? cl_kpad(ix->cl_w) : 0;
+  sd.cl_pw = (ix->cl_P + 31) / 32;
+  sd.cl_ec = ix->cl_ec;
+  sd.cl_o = ix->cl_o;
+  sd.out_cl_dist = nullptr;
+  sd.out_cl_bits = nullptr;
+  // host mode: the CL outputs go through temporary device buffers
+  std::vector<void*> cl_tmp;
+  struct TmpFree {
+    std::vector<void*>& v;
+    ~TmpFree() {
+      for (void* p : v) hipFree(p);
+    }
+  } cl_tmp_free{cl_tmp};
+  if (opts->out_cl_dist) {
+    if (host) {
+      if ((s = dalloc(&sd.out_cl_dist, (size_t)nq * ix->nlist, &cl_tmp)) != AMP_OK) return s;
+    } else {
+      sd.out_cl_dist = opts->out_cl_dist;
+    }
+  }
+  if (opts->out_cl_bits) {
+    if (host) {
+      if ((s = dalloc(&sd.out_cl_bits, (size_t)nq * ix->cl_S * ix->cl_P, &cl_tmp)) != AMP_OK) return s;
+    } else {
+      sd.out_cl_bits = opts->out_cl_bits;
+    }
+  }
+  ModelArgs clma{};
+  if (ix->has_cl_model) {
+    clma.n_sv = ix->cl_n_sv;
+    clma.sv = ix->dev.clmodel.sv;
+    clma.beta = ix->dev.clmodel.beta;
+    clma.table = ix->dev.clmodel.table;
+    clma.beta0 = ix->cl_beta0;
+    for (int f = 0; f < 5; ++f) clma.feat_lo[f] = ix->cl_feat_lo[f], clma.feat_mul[f] = ix->cl_feat_mul[f];
+    clma.g_mul = ix->cl_g_mul;
+    for (int i = 0; i < 3; ++i) clma.theta[i] = ix->cl_theta[i];
+  }
   ModelArgs ma{};
   if (ix->has_model) {
     ma.n_sv = ix->n_sv;
@@ -857,7 +994,7 @@ amp_status search_on(amp_index* ix, Workspace& w, const void* queries, int64_t n
   float* oc = (!host && opts->out_coarse) ? opts->out_coarse : nullptr;
   const hipMemcpyKind out_kind = host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
   auto enqueue = [&](hipEvent_t* evs) -> hipError_t {
-    hipError_t e = launch_search(ix, wv, qdev, sd, ma, oi, od, oq, oc, st, evs);
+    hipError_t e = launch_search(ix, wv, qdev, sd, ma, clma, oi, od, oq, oc, st, evs);
     if (e != hipSuccess) return e;
     if (opts->out_probes &&
         (e = hipMemcpyAsync(opts->out_probes, w.probes, (size_t)nq * npmax * 4, out_kind, st)) != hipSuccess)
@@ -874,7 +1011,7 @@ amp_status search_on(amp_index* ix, Workspace& w, const void* queries, int64_t n
                  opts->out_status, dev_sizes ? k : nullptr, dev_sizes ? nprobe : nullptr,
                  st, nq, per_query ? kmax : k[0], per_query ? npmax : nprobe[0], pol->kind, pol->fixed_bits,
                  sd.allowed_mask, pol->margin_q40, lut_dtype, w.generation, ix->model_generation, chunk, chunk1,
-                 capq, sd.wpr, opts->q_dtype, sd.queue};
+                 capq, sd.wpr, opts->q_dtype, sd.queue, cl_policy, cl_lo, opts->out_cl_dist, opts->out_cl_bits};
     GraphSlot* hit = nullptr;
     for (GraphSlot& g : w.graphs)
       if (g.key == key) hit = &g;
@@ -912,6 +1049,11 @@ amp_status search_on(amp_index* ix, Workspace& w, const void* queries, int64_t n
   }
   if (host && opts->out_coarse)
     AMP_HIP(hipMemcpyAsync(opts->out_coarse, w.coarse, (size_t)nq * ix->nlist * 4, hipMemcpyDeviceToHost, st));
+  if (host && opts->out_cl_dist)
+    AMP_HIP(hipMemcpyAsync(opts->out_cl_dist, sd.out_cl_dist, (size_t)nq * ix->nlist * 4, hipMemcpyDeviceToHost, st));
+  if (host && opts->out_cl_bits)
+    AMP_HIP(hipMemcpyAsync(opts->out_cl_bits, sd.out_cl_bits, (size_t)nq * ix->cl_S * ix->cl_P, hipMemcpyDeviceToHost,
+                           st));
   int32_t flags[4] = {0, 0, 0, 0};
   if (host) {
     AMP_HIP(hipMemcpyAsync(out_ids, w.o_ids, (size_t)nq * kmax * 8, hipMemcpyDeviceToHost, st));

@@ -1326,7 +1326,8 @@ hipError_t launch_residual(const float* X, const int32_t* a, const float* C, int
 }
 
 hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* queries_in, const SearchDims& sd,
-                         const ModelArgs& ma, int64_t* out_ids, float* out_dist, int64_t* out_qdist,
+                         const ModelArgs& ma, const ModelArgs& clma, int64_t* out_ids, float* out_dist,
+                         int64_t* out_qdist,
                          float* out_coarse, hipStream_t st, hipEvent_t* ev) {
   const DeviceIndex& dv = ix->dev;
   const bool fp32 = sd.policy == AMP_POLICY_FP32;
@@ -1365,7 +1366,13 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   }
   // CL
   float* coarse = out_coarse ? out_coarse : ws.coarse;
-  if (sd.metric == AMP_L1) {
+  if (sd.cl_policy != AMP_CL_FP32) {
+    // integer cluster locating on 8-bit codes (fixed or adaptive operand
+    // widths): order keys of the exact integer distances
+    const hipError_t e = launch_cl(ix, ws, queries, sd, clma, ws.coarse, st);
+    if (e != hipSuccess) return e;
+    coarse = ws.coarse;
+  } else if (sd.metric == AMP_L1) {
     hipLaunchKernelGGL(k_coarse_l1, dim3((sd.nlist + CL_T - 1) / CL_T, (sd.nq + CL_T - 1) / CL_T), dim3(256), 0,
                        st, queries, dv.centroids, coarse, sd.nq, sd.nlist, sd.d);
   } else {

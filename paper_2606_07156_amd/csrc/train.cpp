@@ -386,3 +386,190 @@ extern "C" amp_status amp_index_train_predictor(amp_index* ix, const float* tq, 
   }
   return AMP_OK;
 }
+
+// ------------------------------------------------------------------ CL predictor
+// Labels per (training query, slice, sub-space) from the full-width integer
+// coarse distances and the nprobe boundary; the same feature map, sampling,
+// SMO fit and fixed-point export as the LUT predictor, with two classes (the
+// low width, 8 bits) and one threshold.
+extern "C" amp_status amp_index_train_cl_predictor(amp_index* ix, const float* tq, int64_t nq, int32_t nprobe,
+                                                   int32_t low, const amp_train_params* prm,
+                                                   amp_train_report* rep) {
+  if (!ix || !tq || !prm) return set_error(AMP_EINVAL, "null argument");
+  if (!ix->has_clmap) return set_error(AMP_EINVAL, "index has no sub-space map");
+  if (nq <= 0 || nprobe < 1 || nprobe >= ix->nlist) return set_error(AMP_EINVAL, "bad nq / nprobe");
+  if (low < 1 || low > 7) return set_error(AMP_EINVAL, "low width %d outside [1, 7]", low);
+  if (prm->n_samples < 8 || prm->n_samples > 8192) return set_error(AMP_EINVAL, "n_samples outside [8, 8192]");
+  if (!(prm->gamma > 0) || !(prm->C > 0) || !(prm->epsilon >= 0)) return set_error(AMP_EINVAL, "bad SVR parameters");
+  const int d = ix->d, nl = ix->nlist, S = ix->cl_S, P = ix->cl_P, w = ix->cl_w;
+  const bool ip = ix->metric == AMP_IP;
+  const int klo = 8 - low;
+  auto tr = [](int v, int k) { return (v >> k) << k; };  // arithmetic shift: floor
+  auto label_query = [&](int64_t qi, std::vector<Sample>& out) {
+    const float* q = tq + (size_t)qi * d;
+    std::vector<int> vq(d);
+    for (int t = 0; t < d; ++t) vq[t] = cl_code_host(q[t], ix->cl_o, ix->cl_ec);
+    // partial distances per (centroid, slice) at full and low width
+    std::vector<int64_t> p8((size_t)nl * S), plo((size_t)nl * S), D(nl, 0);
+    for (int i = 0; i < nl; ++i)
+      for (int s = 0; s < S; ++s) {
+        int64_t a8 = 0, al = 0;
+        for (int t = s * w; t < (s + 1) * w; ++t) {
+          const int c = ix->cl_codes[(size_t)i * d + t];
+          if (ip) {
+            a8 -= (int64_t)vq[t] * c;
+            al -= (int64_t)tr(vq[t], klo) * tr(c, klo);
+          } else {
+            const int64_t d8 = vq[t] - c, dl = tr(vq[t], klo) - tr(c, klo);
+            a8 += d8 * d8;
+            al += dl * dl;
+          }
+        }
+        p8[(size_t)i * S + s] = a8;
+        plo[(size_t)i * S + s] = al;
+        D[i] += a8;
+      }
+    std::vector<int> order(nl);
+    std::iota(order.begin(), order.end(), 0);
+    std::partial_sort(order.begin(), order.begin() + nprobe + 1, order.end(),
+                      [&](int a, int b) { return D[a] < D[b] || (D[a] == D[b] && a < b); });
+    const int64_t dnp = D[order[nprobe - 1]], dnp1 = D[order[nprobe]];
+    std::vector<char> nbr(nl, 0);
+    for (int r = 0; r < nprobe; ++r) nbr[order[r]] = 1;
+    for (int s = 0; s < S; ++s) {
+      std::vector<int64_t> delta(P, INT64_MAX), err(P, 0), d2(P, 0);
+      for (int i = 0; i < nl; ++i) {
+        const int u = ix->cl_assign[(size_t)i * S + s];
+        const int64_t m = nbr[i] ? dnp1 - D[i] : D[i] - dnp;
+        delta[u] = std::min(delta[u], m);
+        err[u] = std::max<int64_t>(err[u], std::llabs(plo[(size_t)i * S + s] - p8[(size_t)i * S + s]));
+      }
+      int c1 = 0;
+      for (int u = 0; u < P; ++u) {
+        int64_t a = 0;
+        for (int t = 0; t < w; ++t) {
+          const int64_t df = vq[s * w + t] - ix->cl_centre[((size_t)s * P + u) * w + t];
+          a += df * df;
+        }
+        d2[u] = a;
+        if (a < d2[c1]) c1 = u;
+      }
+      for (int u = 0; u < P; ++u) {
+        if (ix->cl_count[(size_t)s * P + u] == 0) continue;
+        Sample smp;
+        smp.x[0] = d2[u];
+        smp.x[1] = ix->cl_radius[(size_t)s * P + c1];
+        smp.x[2] = ix->cl_radius[(size_t)s * P + u];
+        smp.x[3] = ix->cl_count[(size_t)s * P + c1];
+        smp.x[4] = ix->cl_count[(size_t)s * P + u];
+        smp.bits = 2 * err[u] < delta[u] ? low : 8;
+        out.push_back(smp);
+      }
+    }
+  };
+  std::vector<std::vector<Sample>> per_q(nq);
+  {
+    const unsigned hw = std::thread::hardware_concurrency();
+    const int T = (int)std::max<int64_t>(1, std::min<int64_t>(nq, std::min(hw ? hw : 1u, 16u)));
+    std::vector<std::thread> th;
+    for (int t = 0; t < T; ++t)
+      th.emplace_back([&, t] {
+        for (int64_t qi = t; qi < nq; qi += T) label_query(qi, per_q[qi]);
+      });
+    for (auto& x : th) x.join();
+  }
+  std::vector<Sample> all;
+  for (auto& v : per_q) all.insert(all.end(), v.begin(), v.end());
+  if (all.size() < 8) return set_error(AMP_EINVAL, "too few training samples");
+  int64_t flo[5], fmul[5];
+  for (int f = 0; f < 5; ++f) {
+    int64_t lo = INT64_MAX, hi = INT64_MIN;
+    for (const Sample& s : all) {
+      const int64_t L = mitchell_q8_host(s.x[f]);
+      lo = std::min(lo, L);
+      hi = std::max(hi, L);
+    }
+    flo[f] = lo;
+    fmul[f] = (1023ll * 65536) / std::max<int64_t>(1, hi - lo);
+  }
+  auto to_u = [&](const Sample& s, int32_t* u) {
+    for (int f = 0; f < 5; ++f) {
+      int64_t v = ((mitchell_q8_host(s.x[f]) - flo[f]) * fmul[f]) >> 16;
+      u[f] = (int32_t)std::min<int64_t>(1023, std::max<int64_t>(0, v));
+    }
+  };
+  // stratified sample: alternate between the two classes
+  std::mt19937_64 rng(prm->seed);
+  std::vector<int> cls[2];
+  for (size_t i = 0; i < all.size(); ++i) cls[all[i].bits == low ? 0 : 1].push_back((int)i);
+  for (auto& v : cls) std::shuffle(v.begin(), v.end(), rng);
+  std::vector<int> pick;
+  const int want = std::min<int>(prm->n_samples, (int)all.size());
+  size_t cur[2] = {0, 0};
+  while ((int)pick.size() < want) {
+    bool any = false;
+    for (int c = 0; c < 2; ++c)
+      if (cur[c] < cls[c].size() && (int)pick.size() < want) pick.push_back(cls[c][cur[c]++]), any = true;
+    if (!any) break;
+  }
+  const int l = (int)pick.size();
+  std::vector<int32_t> U((size_t)l * 5);
+  std::vector<double> y(l);
+  for (int i = 0; i < l; ++i) {
+    to_u(all[pick[i]], &U[(size_t)i * 5]);
+    y[i] = all[pick[i]].bits == low ? 0.0 : 1.0;
+  }
+  std::vector<double> K((size_t)l * l);
+  const double gs = prm->gamma / (1023.0 * 1023.0);
+  for (int i = 0; i < l; ++i)
+    for (int j = 0; j < l; ++j) {
+      double s = 0;
+      for (int f = 0; f < 5; ++f) {
+        const double df = U[(size_t)i * 5 + f] - U[(size_t)j * 5 + f];
+        s += df * df;
+      }
+      K[(size_t)i * l + j] = std::exp(-gs * s);
+    }
+  std::vector<double> coef;
+  double bias = 0;
+  int iters = 0;
+  const int max_iter = prm->max_iter > 0 ? prm->max_iter : 100000;
+  svr_smo(K, y, prm->C, prm->epsilon, prm->tol > 0 ? prm->tol : 1e-3, max_iter, coef, bias, iters);
+  std::vector<int32_t> sv, beta;
+  for (int i = 0; i < l; ++i) {
+    const double c = coef[i];
+    if (std::fabs(c) < 1e-9) continue;
+    for (int f = 0; f < 5; ++f) sv.push_back(U[(size_t)i * 5 + f]);
+    beta.push_back((int32_t)std::llround(c * (1 << 20)));
+  }
+  std::vector<int32_t> table(kTableN);
+  for (int i = 0; i < kTableN; ++i) table[i] = (int32_t)std::llround(std::exp(-(i + 0.5) / 64.0) * (1 << 20));
+  amp_predictor_model m{};
+  m.n_sv = (int32_t)beta.size();
+  m.sv = sv.data();
+  m.beta = beta.data();
+  m.table = table.data();
+  m.beta0 = (int64_t)std::llround(bias * 1099511627776.0);
+  for (int f = 0; f < 5; ++f) m.feat_lo[f] = flo[f], m.feat_mul[f] = fmul[f];
+  m.g_mul = (uint64_t)std::llround(prm->gamma * 64.0 / (1023.0 * 1023.0) * 4294967296.0);
+  m.theta[0] = (int64_t)std::llround(0.5 * 1099511627776.0);
+  if (m.n_sv > 4096) return set_error(AMP_EUNSUPPORTED, "%d support vectors exceed 4096", m.n_sv);
+  amp_status st = amp_index_set_cl_predictor(ix, &m);
+  if (st != AMP_OK) return st;
+  if (rep) {
+    memset(rep, 0, sizeof *rep);
+    rep->n_pairs = (int64_t)all.size();
+    rep->n_samples = l;
+    rep->n_sv = m.n_sv;
+    rep->smo_iterations = iters;
+    for (const Sample& s : all) rep->label_hist[s.bits == low ? 0 : 1]++;
+    double se = 0;
+    for (int i = 0; i < l; ++i) {
+      double f = bias;
+      for (int j = 0; j < l; ++j) f += coef[j] * K[(size_t)j * l + i];
+      se += (f - y[i]) * (f - y[i]);
+    }
+    rep->train_rmse = std::sqrt(se / l);
+  }
+  return AMP_OK;
+}
