@@ -374,6 +374,9 @@ def main():
     ap.add_argument("--epsilon", type=float, default=0.1)
     ap.add_argument("--svr-c", type=float, default=1.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cl-slices", type=int, default=16, help="mid workload: CL dimension slices (0: no CL run)")
+    ap.add_argument("--cl-subspaces", type=int, default=64, help="mid workload: CL sub-spaces per slice")
+    ap.add_argument("--cl-epsilon", type=float, default=0.1, help="epsilon of the CL predictor's SVR")
     ap.add_argument("--recall", type=int, default=1,
                     help="0: skip the exact ground truth of the headline (profiling runs); recall is then null")
     ap.add_argument("--recall-queries", type=int, default=200, help="--serving: queries checked for recall")
@@ -483,7 +486,7 @@ def measure(h, w, Q, kq, npq, pols, args, truth, tag, qdev=None, q_dtype=None):
             kw = dict(kw, q_dtype=q_dtype)
         sched = "automatic"
         if args.autotune:
-            tk = {kk: v for kk, v in kw.items() if kk != "q_dtype"}
+            tk = {kk: v for kk, v in kw.items() if kk not in ("q_dtype", "cl_policy", "cl_bits")}
             e = amp.amp_index_autotune(h, Q, kq, npq, repeats=3, **tk)
             sched = {kk: e[kk] for kk in ("chunk", "chunk1", "narrow", "lut_dtype", "queue", "ms", "ms_default")}
             log(f"[{tag}] {name}: autotuned schedule {sched}")
@@ -503,7 +506,14 @@ def measure(h, w, Q, kq, npq, pols, args, truth, tag, qdev=None, q_dtype=None):
             o = amp.amp_search(h, qd, out=out, stream=stream, stage_ms=True, work=True, **sizes, **kw)
             stages.append(o["stage_ms"])
             works.append(o["work"])
-        g = amp.amp_search(h, Q, kq, npq, want_probes=True, want_bits=True, **kw)
+        cl_adaptive = kw.get("cl_policy") == "adaptive"
+        g = amp.amp_search(h, Q, kq, npq, want_probes=True, want_bits=True, want_cl_bits=cl_adaptive, **kw)
+        cl_share = None
+        if cl_adaptive:
+            # share of the (query, centroid, slice) partial distances at the low width
+            cm = amp.amp_index_get_cl_map(h)
+            low = kw.get("cl_bits") or 4
+            cl_share = float(((g["cl_bits"] == low) * cm["count"][None]).sum()) / (nq * cm["count"].sum())
         ids10 = g["ids"][:, :10]
         rec1 = oracle.recall_1_at(ids10, truth[:, :10]) if truth is not None else None
         rec10 = oracle.recall_at(ids10, truth[:, :10]) if truth is not None else None
@@ -517,6 +527,7 @@ def measure(h, w, Q, kq, npq, pols, args, truth, tag, qdev=None, q_dtype=None):
         st = {s_: float(np.mean([x[s_] for x in stages])) for s_ in stages[0]}
         lat = [x["total"] for x in stages]
         results[name] = dict(qps=nq / (ms / 1e3), ms=ms, recall1=rec1, recall10=rec10, stages=st, status=status,
+                             cl_low_share=cl_share,
                              probed_bytes=probed_bytes, scan_bytes=wk["scan_bytes"], live_pairs=wk["live_pairs"],
                              dead_pairs=wk["dead_pairs"], bits=hist, schedule=sched,
                              n_pairs=int((pr >= 0).sum()),
@@ -563,6 +574,7 @@ def mfma_of(r, w, nq):
 def summary(results):
     rnd = lambda v: round(v, 4) if v is not None else None
     return {n: {"qps": round(x["qps"], 1), "ms": round(x["ms"], 4), "1_recall_at_10": rnd(x["recall1"]),
+                **({"cl_low_share": rnd(x["cl_low_share"])} if x.get("cl_low_share") is not None else {}),
                 "10_recall_at_10": rnd(x["recall10"]), "scan2_ms": round(x["stages"]["scan2"], 4),
                 "stages_ms": {kk: round(v, 4) for kk, v in x["stages"].items()}, "bits_share": x["bits"],
                 "device_status": x["status"]}
@@ -757,12 +769,44 @@ def secondary_mid(args):
     args.idx_sizes = idx["list_sizes"].astype(np.int64)
     res = measure(h, w, Q, w.k, w.nprobe, policy_list("adaptive,fp32,fixed16", (4, 8, 12, 16)), args, truth, "c2")
     ra, rf = res["adaptive"], res["fp32"]
-    return {"workload": f"{w.name}: {w.n}x{w.d} integer-valued Gaussian mixture ({w.n_comp} components), l2, "
-                        f"IVF{w.nlist}/PQ{w.M}x256, {len(Q)} queries per step, nprobe {w.nprobe}, k {w.k}",
-            "qps": round(ra["qps"], 1), "speedup_vs_fp32": round(ra["qps"] / rf["qps"], 3),
-            "recall_definition": f"1- and 10-recall@10 over all {len(Q)} queries against exact FP64 kNN",
-            "policies": summary(res), "roofline": roofline_of(ra, w, len(Q), TRAFFIC_FILE),
-            "mfma": mfma_of(ra, w, len(Q)), "predictor": {kk: rep[kk] for kk in ("n_sv", "label_hist")}}
+    out = {"workload": f"{w.name}: {w.n}x{w.d} integer-valued Gaussian mixture ({w.n_comp} components), l2, "
+                       f"IVF{w.nlist}/PQ{w.M}x256, {len(Q)} queries per step, nprobe {w.nprobe}, k {w.k}",
+           "qps": round(ra["qps"], 1), "speedup_vs_fp32": round(ra["qps"] / rf["qps"], 3),
+           "recall_definition": f"1- and 10-recall@10 over all {len(Q)} queries against exact FP64 kNN",
+           "policies": summary(res), "roofline": roofline_of(ra, w, len(Q), TRAFFIC_FILE),
+           "mfma": mfma_of(ra, w, len(Q)), "predictor": {kk: rep[kk] for kk in ("n_sv", "label_hist")}}
+    if args.cl_slices > 0:
+        out["cl"] = measure_cl(h, w, Q, truth, args, ra)
+    return out
+
+
+def measure_cl(h, w, Q, truth, args, r_fp32cl):
+    """Cluster locating on 8-bit codes: the sub-space map (S slices, P
+    sub-spaces per slice) and the CL predictor (gamma 0.1, C 10) on training
+    queries, then the adaptive LUT policy with integer CL at 8 bits and with
+    adaptive CL widths (low width 4): CL stage time (codes, predictor,
+    distances), share of partial distances at the low width, recall."""
+    import paper_2606_07156_amd as amp
+    from amp_data.synth import make_queries
+    t = time.perf_counter()
+    amp.amp_index_build_cl_map(h, args.cl_slices, args.cl_subspaces, iters=20, seed=w.seed)
+    t_map = time.perf_counter() - t
+    TQ = make_queries(w, args.train_queries, train=True)
+    t = time.perf_counter()
+    rep = amp.amp_index_train_cl_predictor(h, TQ, w.nprobe, low=4, n_samples=1280, gamma=0.1, C_=10.0,
+                                           epsilon=args.cl_epsilon)
+    log(f"[cl] map S={args.cl_slices} P={args.cl_subspaces} in {t_map:.1f}s; CL predictor in "
+        f"{time.perf_counter() - t:.1f}s: {rep}")
+    allowed = (4, 8, 12, 16)
+    pols = [("adaptive_cl8", dict(policy="adaptive", allowed=allowed, cl_policy="fixed", cl_bits=8)),
+            ("adaptive_clA", dict(policy="adaptive", allowed=allowed, cl_policy="adaptive", cl_bits=4))]
+    a = argparse.Namespace(**vars(args))
+    a.autotune = 0
+    res = measure(h, w, Q, w.k, w.nprobe, pols, a, truth, "cl")
+    return {"slices": args.cl_slices, "subspaces_per_slice": args.cl_subspaces,
+            "predictor": {kk: rep[kk] for kk in ("n_sv", "label_hist", "n_pairs")},
+            "fp32_cl_ms": round(r_fp32cl["stages"]["cl"], 4),
+            "policies": summary(res)}
 
 
 def single(args):

@@ -71,6 +71,7 @@ struct DeviceIndex {
   int32_t* clr = nullptr;      // [S][P] radius
   int32_t* cln = nullptr;      // [S][P] count
   DeviceModel clmodel;
+  uint32_t* cltab = nullptr;   // [S][P][P][32] exact CL predictor decisions by the 10-bit d' feature, or null
 };
 
 // what a captured search graph depends on
@@ -256,6 +257,7 @@ struct SearchDims {
   int cl_lo, cl_hi;      // operand widths of the two classes (fixed: both the fixed width)
   int cl_S, cl_P, cl_w, cl_kp, cl_pw, cl_ec;
   float cl_o;
+  const uint32_t* cl_tab;  // exact decision table of the CL predictor, or null (direct evaluation)
   int32_t* out_cl_dist;  // [nq][nlist] or null
   uint8_t* out_cl_bits;  // [nq][S][P] or null
 };
@@ -294,6 +296,10 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
 // coarse distances into keys [nq][nlist]
 hipError_t launch_cl(const amp_index* ix, const Workspace& ws, const float* queries, const SearchDims& sd,
                      const ModelArgs& clma, float* keys, hipStream_t st);
+// the CL predictor's exact decision table [S][P][P][32] (bit d' feature value)
+hipError_t launch_cltab(const amp_index* ix, const ModelArgs& clma, uint32_t* tab, hipStream_t st);
+// the table is built when it takes at most this many bytes
+constexpr size_t kClTabMaxBytes = 512ull << 20;
 // index build: nearest centroid of n rows (dd floats, leading dimension ld)
 // among k centroids [k][dd], with its squared distance (out_d may be null);
 // xn [n] and cn [k] are scratch for the squared norms

@@ -48,7 +48,7 @@ static amp_status dalloc(T** p, size_t n, std::vector<void*>* track = nullptr) {
 static void free_device_index(DeviceIndex& d) {
   void* ptrs[] = {d.centroids, d.cnorm, d.codebook, d.bsw, d.bsw16, d.bsw8, d.cbi16, d.ci16, d.lorder, d.lpos, d.codes, d.ids,
                   d.offsets, d.radq, d.model.sv, d.model.beta, d.model.table, d.clc, d.clasg, d.clz, d.clr,
-                  d.cln, d.clmodel.sv, d.clmodel.beta, d.clmodel.table};
+                  d.cln, d.clmodel.sv, d.clmodel.beta, d.clmodel.table, d.cltab};
   for (void* p : ptrs)
     if (p) hipFree(p);
   d = DeviceIndex();
@@ -208,13 +208,29 @@ static amp_status upload_model(amp_index* ix) {
   return AMP_OK;
 }
 
+static ModelArgs cl_model_args(const amp_index* ix) {
+  ModelArgs clma{};
+  if (ix->has_cl_model) {
+    clma.n_sv = ix->cl_n_sv;
+    clma.sv = ix->dev.clmodel.sv;
+    clma.beta = ix->dev.clmodel.beta;
+    clma.table = ix->dev.clmodel.table;
+    clma.beta0 = ix->cl_beta0;
+    for (int f = 0; f < 5; ++f) clma.feat_lo[f] = ix->cl_feat_lo[f], clma.feat_mul[f] = ix->cl_feat_mul[f];
+    clma.g_mul = ix->cl_g_mul;
+    for (int i = 0; i < 3; ++i) clma.theta[i] = ix->cl_theta[i];
+  }
+  return clma;
+}
+
 // the sub-space map of integer cluster locating (codes padded per slice to
 // one MFMA K) and the CL predictor, to the index's device
 static amp_status upload_cl(amp_index* ix) {
   DeviceIndex& d = ix->dev;
-  void* old[] = {d.clc, d.clasg, d.clz, d.clr, d.cln, d.clmodel.sv, d.clmodel.beta, d.clmodel.table};
+  void* old[] = {d.clc, d.clasg, d.clz, d.clr, d.cln, d.clmodel.sv, d.clmodel.beta, d.clmodel.table, d.cltab};
   for (void* p : old)
     if (p) hipFree(p);
+  d.cltab = nullptr;
   d.clc = nullptr;
   d.clasg = nullptr;
   d.clz = nullptr;
@@ -255,6 +271,15 @@ static amp_status upload_cl(amp_index* ix) {
     }
     AMP_HIP(hipMemcpy(dm.table, ix->cl_table.data(), kTableN * 4, hipMemcpyHostToDevice));
     dm.n_sv = ix->cl_n_sv;
+    // the exact decision table (searches then read one bit per sub-space
+    // instead of evaluating the regressor), when it is not too large
+    const size_t words = S * P * P * 32;
+    if (words * 4 <= kClTabMaxBytes) {
+      if ((st = dalloc(&d.cltab, words)) != AMP_OK) return st;
+      const ModelArgs clma = cl_model_args(ix);
+      AMP_HIP(launch_cltab(ix, clma, d.cltab, nullptr));
+      AMP_HIP(hipDeviceSynchronize());
+    }
   }
   ix->dev_cl_stale = false;
   return AMP_OK;
@@ -947,16 +972,11 @@ amp_status search_on(amp_index* ix, Workspace& w, const void* queries, int64_t n
       sd.out_cl_bits = opts->out_cl_bits;
     }
   }
-  ModelArgs clma{};
-  if (ix->has_cl_model) {
-    clma.n_sv = ix->cl_n_sv;
-    clma.sv = ix->dev.clmodel.sv;
-    clma.beta = ix->dev.clmodel.beta;
-    clma.table = ix->dev.clmodel.table;
-    clma.beta0 = ix->cl_beta0;
-    for (int f = 0; f < 5; ++f) clma.feat_lo[f] = ix->cl_feat_lo[f], clma.feat_mul[f] = ix->cl_feat_mul[f];
-    clma.g_mul = ix->cl_g_mul;
-    for (int i = 0; i < 3; ++i) clma.theta[i] = ix->cl_theta[i];
+  const ModelArgs clma = cl_model_args(ix);
+  // AMP_CL_TABLE=0 evaluates the CL regressor directly (same widths)
+  {
+    const char* tv = getenv("AMP_CL_TABLE");
+    sd.cl_tab = (tv && tv[0] == '0') ? nullptr : ix->dev.cltab;
   }
   ModelArgs ma{};
   if (ix->has_model) {

@@ -21,6 +21,7 @@ namespace {
 typedef int v4i __attribute__((ext_vector_type(4)));
 
 struct ClArgs {
+  const uint32_t* tab;  // exact decision table of the CL predictor, or null (direct evaluation)
   const float* Q;
   int nq, d, nlist, S, P, PW, w, ec;
   float o;
@@ -102,6 +103,66 @@ __device__ __forceinline__ int64_t cl_mitchell_q8(int64_t x) {
   return 256 * (int64_t)k + (int64_t)((y << 8) >> k) - 256;
 }
 
+// the 10-bit feature of one raw feature value
+__device__ __forceinline__ int32_t cl_feature(int64_t x, const ModelArgs& ma, int f) {
+  const int64_t v = ((cl_mitchell_q8(x) - ma.feat_lo[f]) * ma.feat_mul[f]) >> 16;
+  return (int32_t)(v < 0 ? 0 : (v > 1023 ? 1023 : v));
+}
+
+// regressor score of one feature vector (the support vectors are the same
+// across the wave: scalar loads); u and sv lie in [0, 1023]: exact 24-bit
+// products, |u - sv|^2 < 2^23
+__device__ __forceinline__ int64_t cl_score(const int32_t (&uf)[5], const ModelArgs& ma, const int32_t* s_table) {
+  const uint32_t gm = (uint32_t)ma.g_mul;
+  auto term = [&](int i) -> int64_t {
+    const int32_t* sv = ma.sv + 5 * i;
+    const int e0 = uf[0] - sv[0], e1 = uf[1] - sv[1], e2 = uf[2] - sv[2], e3 = uf[3] - sv[3], e4 = uf[4] - sv[4];
+    const uint32_t dist2 = (uint32_t)(__mul24(e0, e0) + __mul24(e1, e1) + __mul24(e2, e2) + __mul24(e3, e3) +
+                                      __mul24(e4, e4));
+    const uint32_t idx = __umulhi(dist2, gm);
+    const int32_t K = s_table[idx < (uint32_t)(kTableN - 1) ? idx : (uint32_t)(kTableN - 1)];
+    return (int64_t)ma.beta[i] * K;
+  };
+  int64_t y0 = 0, y1 = 0;
+  int i = 0;
+  for (; i + 1 < ma.n_sv; i += 2) {
+    y0 += term(i);
+    y1 += term(i + 1);
+  }
+  if (i < ma.n_sv) y0 += term(i);
+  return ma.beta0 + y0 + y1;
+}
+
+// Exact decision table of the CL predictor: for slice s, nearest sub-space
+// C1 and sub-space u the features r1, n1 (of C1) and r2, n2 (of u) are
+// fixed, so the width is a function of the 10-bit d' feature alone.  One
+// wave per (s, C1, u) evaluates the regressor at all 1024 values: bit ud of
+// the 32-word row is 1 where the low width is chosen.
+__global__ __launch_bounds__(256) void k_cltab(ClArgs a, ModelArgs ma, uint32_t* tab) {
+  __shared__ int32_t s_table[kTableN];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  for (int i = tid; i < kTableN; i += 256) s_table[i] = ma.table[i];
+  __syncthreads();
+  const int64_t row = (int64_t)blockIdx.x * 4 + wave;  // (s * P + c1) * P + u
+  if (row >= (int64_t)a.S * a.P * a.P) return;
+  const int u = (int)(row % a.P), c1 = (int)((row / a.P) % a.P), s = (int)(row / ((int64_t)a.P * a.P));
+  int32_t uf[5];
+  uf[1] = cl_feature(a.clr[(int64_t)s * a.P + c1], ma, 1);
+  uf[2] = cl_feature(a.clr[(int64_t)s * a.P + u], ma, 2);
+  uf[3] = cl_feature(a.cln[(int64_t)s * a.P + c1], ma, 3);
+  uf[4] = cl_feature(a.cln[(int64_t)s * a.P + u], ma, 4);
+#pragma unroll 1
+  for (int j = 0; j < 16; ++j) {
+    uf[0] = j * 64 + lane;
+    const bool low = cl_score(uf, ma, s_table) <= ma.theta[0];
+    const uint64_t m = __ballot(low);
+    if (lane == 0) {
+      tab[row * 32 + 2 * j] = (uint32_t)m;
+      tab[row * 32 + 2 * j + 1] = (uint32_t)(m >> 32);
+    }
+  }
+}
+
 // One wave per (query, slice); lanes over the sub-spaces (P <= 1024).
 template <int KP>
 __global__ __launch_bounds__(256) void k_clbits(ClArgs a, ModelArgs ma) {
@@ -140,42 +201,27 @@ __global__ __launch_bounds__(256) void k_clbits(ClArgs a, ModelArgs ma) {
     best = o < best ? o : best;
   }
   const int c1 = (int)(best & 1023u);
-  const int64_t r1 = a.clr[(int64_t)s * a.P + c1], n1 = a.cln[(int64_t)s * a.P + c1];
-  const uint32_t gm = (uint32_t)ma.g_mul;
+  const int64_t rowbase = ((int64_t)s * a.P + c1) * a.P;
+  int32_t uf[5];
+  if (!a.tab) {
+    uf[1] = cl_feature(a.clr[(int64_t)s * a.P + c1], ma, 1);
+    uf[3] = cl_feature(a.cln[(int64_t)s * a.P + c1], ma, 3);
+  }
 #pragma unroll 1
   for (int j = 0; j < nj; ++j) {
     const int u = j * 64 + lane;
     bool low = false;
     if (u < a.P) {
-      int64_t x[5];
-      x[0] = d2v[j];
-      x[1] = r1;
-      x[2] = a.clr[(int64_t)s * a.P + u];
-      x[3] = n1;
-      x[4] = a.cln[(int64_t)s * a.P + u];
-      int32_t uf[5];
-      for (int f = 0; f < 5; ++f) {
-        const int64_t v = ((cl_mitchell_q8(x[f]) - ma.feat_lo[f]) * ma.feat_mul[f]) >> 16;
-        uf[f] = (int32_t)(v < 0 ? 0 : (v > 1023 ? 1023 : v));
+      const int32_t ud = cl_feature(d2v[j], ma, 0);
+      if (a.tab) {
+        // the exact decision table: one bit read
+        low = (a.tab[(rowbase + u) * 32 + (ud >> 5)] >> (ud & 31)) & 1u;
+      } else {
+        uf[0] = ud;
+        uf[2] = cl_feature(a.clr[(int64_t)s * a.P + u], ma, 2);
+        uf[4] = cl_feature(a.cln[(int64_t)s * a.P + u], ma, 4);
+        low = cl_score(uf, ma, s_table) <= ma.theta[0];
       }
-      // u and sv lie in [0, 1023]: exact 24-bit products, |u - sv|^2 < 2^23
-      int64_t y0 = 0, y1 = 0;
-      auto term = [&](int i) -> int64_t {
-        const int32_t* sv = ma.sv + 5 * i;
-        const int e0 = uf[0] - sv[0], e1 = uf[1] - sv[1], e2 = uf[2] - sv[2], e3 = uf[3] - sv[3], e4 = uf[4] - sv[4];
-        const uint32_t dist2 = (uint32_t)(__mul24(e0, e0) + __mul24(e1, e1) + __mul24(e2, e2) + __mul24(e3, e3) +
-                                          __mul24(e4, e4));
-        const uint32_t idx = __umulhi(dist2, gm);
-        const int32_t K = s_table[idx < (uint32_t)(kTableN - 1) ? idx : (uint32_t)(kTableN - 1)];
-        return (int64_t)ma.beta[i] * K;
-      };
-      int i = 0;
-      for (; i + 1 < ma.n_sv; i += 2) {
-        y0 += term(i);
-        y1 += term(i + 1);
-      }
-      if (i < ma.n_sv) y0 += term(i);
-      low = ma.beta0 + y0 + y1 <= ma.theta[0];
       if (a.out_bits) a.out_bits[item * a.P + u] = (uint8_t)(low ? a.lo : a.hi);
     }
     const uint64_t m = __ballot(low);
@@ -328,10 +374,23 @@ hipError_t launch_cl_kp(const ClArgs& a, bool adaptive, bool ip, const ModelArgs
 
 }  // namespace
 
+hipError_t launch_cltab(const amp_index* ix, const ModelArgs& clma, uint32_t* tab, hipStream_t st) {
+  const DeviceIndex& dv = ix->dev;
+  ClArgs a{};
+  a.S = ix->cl_S;
+  a.P = ix->cl_P;
+  a.clr = dv.clr;
+  a.cln = dv.cln;
+  const int64_t rows = (int64_t)a.S * a.P * a.P;
+  hipLaunchKernelGGL(k_cltab, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, a, clma, tab);
+  return hipGetLastError();
+}
+
 hipError_t launch_cl(const amp_index* ix, const Workspace& ws, const float* queries, const SearchDims& sd,
                      const ModelArgs& clma, float* keys, hipStream_t st) {
   const DeviceIndex& dv = ix->dev;
   ClArgs a{};
+  a.tab = sd.cl_tab;
   a.Q = queries;
   a.nq = sd.nq;
   a.d = sd.d;

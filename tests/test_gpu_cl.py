@@ -71,8 +71,11 @@ def test_fixed_width_distances_and_probes(clmid, bits):
     _check_cl(clmid, g, "fixed", bits=bits)
 
 
-@pytest.mark.parametrize("low", [4, 2])
-def test_adaptive_widths_distances_and_probes(clmid, low):
+@pytest.mark.parametrize("low,table", [(4, "1"), (4, "0"), (2, "1")])
+def test_adaptive_widths_distances_and_probes(clmid, low, table, monkeypatch):
+    # table "1": the widths read from the predictor's exact decision table;
+    # "0": the regressor evaluated directly (AMP_CL_TABLE=0)
+    monkeypatch.setenv("AMP_CL_TABLE", table)
     g = amp.amp_search(clmid["h"], clmid["Q"], 10, 8, cl_policy="adaptive", cl_bits=low, want_cl_dist=True,
                        want_cl_bits=True, want_probes=True)
     _check_cl(clmid, g, "adaptive", low=low)
@@ -81,9 +84,10 @@ def test_adaptive_widths_distances_and_probes(clmid, low):
 
 
 @pytest.mark.parametrize("ctxname", ["clip768", "clskew"])
-def test_other_shapes(request, ctxname):
+def test_other_shapes(request, ctxname, monkeypatch):
     ctx = request.getfixturevalue(ctxname)
-    for policy, bits in (("fixed", 8), ("fixed", 4), ("adaptive", 8)):
+    for policy, bits, table in (("fixed", 8, "1"), ("fixed", 4, "1"), ("adaptive", 8, "1"), ("adaptive", 8, "0")):
+        monkeypatch.setenv("AMP_CL_TABLE", table)
         kw = dict(want_cl_bits=True) if policy == "adaptive" else {}
         g = amp.amp_search(ctx["h"], ctx["Q"], 10, 8, cl_policy=policy, cl_bits=bits if policy == "fixed" else 0,
                            want_cl_dist=True, want_probes=True, **kw)
@@ -151,3 +155,14 @@ def test_cl_argument_checks(clmid):
         amp.amp_search(h, Q, 10, 8, cl_policy="fixed", cl_bits=8, want_coarse=True)
     with pytest.raises(amp.AmpError):
         amp.amp_search(h, Q, 10, 8, want_cl_dist=True)
+
+
+def test_max_subspaces_direct_evaluation():
+    """P = 1024 sub-spaces per slice (the maximum; the decision table would
+    exceed its size cap, so the regressor is evaluated directly): widths,
+    distances and probes bit-exact."""
+    w = WORKLOADS["mid"].scaled(n=40_000, nlist=1024)
+    ctx = _ctx(w, 1024, 16, 16, 1024, 6, integer_data=True)
+    g = amp.amp_search(ctx["h"], ctx["Q"], 10, 16, cl_policy="adaptive", want_cl_dist=True, want_cl_bits=True,
+                       want_probes=True)
+    _check_cl(ctx, g, "adaptive", nprobe=16)
