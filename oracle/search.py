@@ -154,21 +154,32 @@ def lut_f64(r, codebook, metric="l2"):
     return -(rr * CB).sum(2)
 
 
-def quantize_lut(T, b):
+def quantize_lut(T, b, granularity="pair"):
     """b-bit LUT of one (query, probed cluster) pair (Sec. 4.1 DRM: b-bit
     entries widened to a common width before accumulation).
 
-    lo_m = min_j T[m][j];  R = max_{m,j} (T - lo_m);
-    s = smallest s >= 0 with (R + hf(s)) >> s <= 2^b - 1, hf(s) = 2^(s-1) (0 if s = 0);
+    lo_m = min_j T[m][j];  R_m = max_j (T[m][j] - lo_m);  hf(s) = 2^(s-1) (0 if s = 0);
+    granularity "pair" (one width for every subspace, Sec. 1 cluster level):
+      s = smallest s >= 0 with (max_m R_m + hf(s)) >> s <= 2^b - 1;
+    granularity "subspace" (a width per (pair, subspace), Sec. 5.3: the
+    pair's lane budget M (2^b - 1) shared by its subspaces in proportion to
+    their ranges, subspace m carrying about log2(R_m >> s) bits):
+      s = smallest s >= 0 with (sum_m R_m + M hf(s)) >> s <= M (2^b - 1);
     Q = (T - lo_m + hf(s)) >> s;  base = sum_m lo_m.
     Returns (Q, s, base).
     """
     T = np.asarray(T, dtype=I64)
     lo = T.min(1)
-    R = int((T - lo[:, None]).max())
-    top = (1 << b) - 1
+    Rm = (T - lo[:, None]).max(1)
+    if granularity == "pair":
+        R, n = int(Rm.max()), 1
+    elif granularity == "subspace":
+        R, n = int(Rm.sum()), len(Rm)
+    else:
+        raise ValueError(granularity)
+    top = n * ((1 << b) - 1)
     s = 0
-    while ((R + (1 << (s - 1) if s else 0)) >> s) > top:
+    while ((R + n * (1 << (s - 1) if s else 0)) >> s) > top:
         s += 1
     hf = (1 << (s - 1)) if s else 0
     Q = (T - lo[:, None] + hf) >> s
@@ -276,7 +287,7 @@ def _per_query(v, nq):
 
 
 def search(index, queries, k, nprobe, policy="fixed", bits=16, allowed=BITS_ALL,
-           model=None, explicit_bits=None, margin_q40=0, probes=None, cl=None):
+           model=None, explicit_bits=None, margin_q40=0, probes=None, cl=None, granularity="pair"):
     """Full search of a query batch.
 
     policy: "fp32" (full-precision LUT), "fixed" (every pair at ``bits``),
@@ -286,7 +297,8 @@ def search(index, queries, k, nprobe, policy="fixed", bits=16, allowed=BITS_ALL,
     the two differ only by a certified near-tie).  ``cl`` selects the
     integer CL on 8-bit codes (oracle.cl): a dict with "map" (the index's
     sub-space map), "policy" ("fixed" at "bits", or "adaptive" with "model"
-    and low width "low").
+    and low width "low").  ``granularity``: the quantiser's ("pair" or
+    "subspace", see quantize_lut).
 
     Returns a dict: ids [nq, kmax] int64, qdist [nq, kmax] int64 (-1 for fp32),
     dist [nq, kmax] float32, probes, bits, shift, base [nq, npmax].
@@ -380,7 +392,7 @@ def search(index, queries, k, nprobe, policy="fixed", bits=16, allowed=BITS_ALL,
             else:
                 T = T_query
                 extra = -int((qi * ci[p]).sum())
-            Qt, s, base = quantize_lut(T, int(B[j]))
+            Qt, s, base = quantize_lut(T, int(B[j]), granularity)
             base += extra
             out_s[i, j] = s
             out_base[i, j] = base

@@ -511,3 +511,71 @@ def test_tiny_workload_recall_against_exact_knn():
     r32 = oracle.recall_at(oracle.search(idx, Q, 10, 8, policy="fp32")["ids"], truth)
     assert rec[1] <= rec[8] <= rec[64] + 1e-9
     assert rec[8] >= 0.3 and abs(rec[8] - r32) <= 0.05
+
+
+# ------------------------------------------------- quantiser: per-subspace widths
+def test_subspace_granularity_hand_worked():
+    """Two subspaces with ranges 10 and 100, b = 4.  One width per pair: the
+    largest range sets s = 3 ((100 + 4) >> 3 = 13 <= 15, (100 + 2) >> 2 = 25
+    > 15).  Per-subspace widths: the budget 2 * 15 = 30 for the sum 110 gives
+    s = 2 ((110 + 2 * 2) >> 2 = 28 <= 30, (110 + 2 * 1) >> 1 = 56 > 30); the
+    first subspace then uses entries up to (10 + 2) >> 2 = 3 (2 bits), the
+    second up to (100 + 2) >> 2 = 25 (5 bits)."""
+    T = np.zeros((2, 256), np.int64)
+    T[0, :11] = np.arange(11) + 7        # range 10, minimum 7
+    T[0, 11:] = 12
+    T[1, :101] = np.arange(101) - 40     # range 100, minimum -40
+    T[1, 101:] = 0
+    Q, s, base = oracle.quantize_lut(T, 4)
+    assert s == 3 and base == 7 - 40 and Q.max() == 13
+    Q, s, base = oracle.quantize_lut(T, 4, "subspace")
+    assert s == 2 and base == -33
+    assert Q[0].max() == 3 and Q[1].max() == 25
+    # entry (m = 1, j = 57): T = 17, (17 + 40 + 2) >> 2 = 14
+    assert Q[1, 57] == 14
+
+
+@pytest.mark.parametrize("b", [4, 8, 12, 16])
+def test_subspace_granularity_budget_and_error(b):
+    """Any vector's sum of entries fits the pair's lane budget M (2^b - 1);
+    the estimate is within M 2^(s-1) of the exact sum (round half up: each
+    entry within (-2^(s-1), 2^(s-1)] of its exact value); the shift is the
+    smallest with the budget, checked by brute force over all codes' maxima."""
+    r = np.random.default_rng(40 + b)
+    for trial in range(30):
+        M = int(r.integers(1, 17))
+        scales = 10 ** r.integers(1, 7, size=M)
+        T = np.stack([r.integers(0, int(sc), size=256) for sc in scales]) + r.integers(-999, 999, size=(M, 1))
+        Q, s, base = oracle.quantize_lut(T, b, "subspace")
+        top = M * ((1 << b) - 1)
+        assert int(Q.max(1).sum()) <= top                      # the lane never overflows
+        lo = T.min(1)
+        if s > 0:
+            # one shift less would exceed the budget for the range sum
+            R = int((T - lo[:, None]).max(1).sum())
+            hf = (1 << (s - 2)) if s > 1 else 0
+            assert (R + M * hf) >> (s - 1) > top
+        codes = r.integers(0, 256, size=(200, M))
+        est = base + (Q[np.arange(M)[None, :], codes].sum(1) << s)
+        ex = T[np.arange(M)[None, :], codes].sum(1)
+        half = (1 << (s - 1)) if s else 0
+        assert np.all(np.abs(est - ex) <= M * max(half, 0))
+        if s == 0:
+            assert np.array_equal(est, ex)
+        # per subspace the estimate error of an entry is within (-half, half]
+        err = (Q << s) - (T - lo[:, None])
+        assert err.max() <= half and (s == 0 or err.min() > -half)
+
+
+def test_subspace_granularity_is_as_fine_for_equal_ranges():
+    """With equal ranges the per-subspace rule is the per-pair rule up to the
+    rounding of the shared half-unit: never coarser by more than one step."""
+    r = np.random.default_rng(7)
+    for _ in range(50):
+        M, b = int(r.integers(2, 17)), int(r.choice([4, 8, 12, 16]))
+        R = int(r.integers(1, 10 ** 6))
+        T = np.zeros((M, 256), np.int64)
+        T[:, 1] = R
+        s_pair = oracle.quantize_lut(T, b)[1]
+        s_sub = oracle.quantize_lut(T, b, "subspace")[1]
+        assert s_sub <= s_pair + 1
