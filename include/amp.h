@@ -139,7 +139,25 @@ typedef struct amp_predictor_model {
  *                     LUT's
  *   margin_q40        added to the regressor score before thresholding
  *   explicit_bits     host [nq][npmax] uint8 widths by probe rank (EXPLICIT)
+ *   granularity       of the LUT quantiser (Sec. 5.3 finer LC precision;
+ *                     integer policies): with lo_m the minimum and R_m the
+ *                     range of subspace m's entries, hf(s) = 2^(s-1) (0 for
+ *                     s = 0), entries Q = (T - lo_m + hf(s)) >> s and the
+ *                     estimate sum_m lo_m + (sum_m Q) << s:
+ *                     AMP_GRAN_PAIR (0): one width for every subspace of the
+ *                       pair, s the smallest with
+ *                       (max_m R_m + hf(s)) >> s <= 2^b - 1;
+ *                     AMP_GRAN_SUBSPACE (1): a width per (pair, subspace):
+ *                       the pair's lane budget M (2^b - 1) is shared by its
+ *                       subspaces in proportion to their ranges, s the
+ *                       smallest with (sum_m R_m + M hf(s)) >> s <= M (2^b - 1)
+ *                       (subspace m's entries then take about
+ *                       log2((R_m + hf(s)) >> s) bits; one shift for all
+ *                       subspaces, since the packed sums add entries in
+ *                       common units).  The predictor should be trained
+ *                       with the same granularity (amp_train_params).
  */
+enum { AMP_GRAN_PAIR = 0, AMP_GRAN_SUBSPACE = 1 };
 typedef struct amp_precision_policy {
   int32_t kind;
   int32_t fixed_bits;
@@ -147,6 +165,7 @@ typedef struct amp_precision_policy {
   int32_t lut_dtype;
   int64_t margin_q40;
   const uint8_t* explicit_bits;
+  int32_t granularity;
 } amp_precision_policy;
 
 /*
@@ -314,7 +333,8 @@ amp_status amp_index_set_predictor(amp_index* index, const amp_predictor_model* 
  * (host [nq][d] float).  For every (query, probed list) pair of a search at
  * (k, nprobe) the trainer computes the features {d', r1, r2, n1, n2} and a
  * label: the smallest allowed width whose worst-case LUT quantisation error
- * M * 2^(s-1) stays below the list's margin between the query's k neighbours
+ * M * 2^(s-1) (s from the quantiser of params->granularity) stays below the
+ * list's margin between the query's k neighbours
  * and its non-neighbours (exact integer ADC distances on the operand grid,
  * Sec. 3.3 label definition).  It keeps n_samples pairs stratified by label,
  * fits an epsilon-SVR with the Gaussian kernel exp(-gamma |du|^2) on the
@@ -328,6 +348,7 @@ typedef struct amp_train_params {
   double gamma, C, epsilon, tol;
   uint32_t allowed_bits_mask; /* 0 = {4, 8, 12, 16} */
   uint64_t seed;
+  int32_t granularity;        /* AMP_GRAN_*: the quantiser whose error the labels bound */
 } amp_train_params;
 
 typedef struct amp_train_report {

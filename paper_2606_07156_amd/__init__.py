@@ -55,7 +55,12 @@ class _Model(C.Structure):
 
 class _Policy(C.Structure):
     _fields_ = [("kind", C.c_int32), ("fixed_bits", C.c_int32), ("allowed_bits_mask", C.c_uint32),
-                ("lut_dtype", C.c_int32), ("margin_q40", C.c_int64), ("explicit_bits", C.c_void_p)]
+                ("lut_dtype", C.c_int32), ("margin_q40", C.c_int64), ("explicit_bits", C.c_void_p),
+                ("granularity", C.c_int32)]
+
+
+AMP_GRAN_PAIR, AMP_GRAN_SUBSPACE = 0, 1
+GRANULARITIES = {"pair": AMP_GRAN_PAIR, "subspace": AMP_GRAN_SUBSPACE}
 
 
 AMP_SEARCH_GRAPH = 1
@@ -89,7 +94,7 @@ class _BuildParams(C.Structure):
 class _TrainParams(C.Structure):
     _fields_ = [("n_samples", C.c_int32), ("max_iter", C.c_int32), ("gamma", C.c_double),
                 ("C", C.c_double), ("epsilon", C.c_double), ("tol", C.c_double),
-                ("allowed_bits_mask", C.c_uint32), ("seed", C.c_uint64)]
+                ("allowed_bits_mask", C.c_uint32), ("seed", C.c_uint64), ("granularity", C.c_int32)]
 
 
 class _TrainReport(C.Structure):
@@ -287,14 +292,15 @@ def amp_index_get_predictor(index):
 
 
 def amp_index_train_predictor(index, train_queries, k, nprobe, n_samples=1280, gamma=1.0, C_=1.0,
-                              epsilon=0.05, tol=1e-3, max_iter=0, allowed=(4, 8, 12, 16), seed=0):
+                              epsilon=0.05, tol=1e-3, max_iter=0, allowed=(4, 8, 12, 16), seed=0,
+                              granularity="pair"):
     """Fit and attach the precision predictor; returns the training report."""
     q = np.ascontiguousarray(train_queries, dtype=np.float32)
     mask = 0
     for b in allowed:
         mask |= 1 << int(b)
     p = _TrainParams(int(n_samples), int(max_iter), float(gamma), float(C_), float(epsilon), float(tol),
-                     mask, int(seed))
+                     mask, int(seed), GRANULARITIES[granularity])
     r = _TrainReport()
     _check(lib().amp_index_train_predictor(index.handle, _ptr(q), int(q.shape[0]), int(k), int(nprobe),
                                            C.byref(p), C.byref(r)))
@@ -392,7 +398,7 @@ def _tune_dict(e):
 
 
 def amp_index_autotune(index, queries, k, nprobe, policy="fixed", bits=16, allowed=(4, 8, 12, 16), margin_q40=0,
-                       lut_dtype=0, repeats=5):
+                       lut_dtype=0, repeats=5, granularity="pair"):
     """Time candidate search schedules for this batch shape on the current
     device and record the fastest in the index; returns the entry (dict)."""
     bf16 = getattr(queries, "dtype", None) == np.uint16
@@ -404,7 +410,7 @@ def amp_index_autotune(index, queries, k, nprobe, policy="fixed", bits=16, allow
     if per_query:
         kk = np.ascontiguousarray(np.broadcast_to(kk, (nq,)), dtype=np.int32)
         npb = np.ascontiguousarray(np.broadcast_to(npb, (nq,)), dtype=np.int32)
-    pol, _ = make_policy(policy, bits, allowed, margin_q40, None, lut_dtype)
+    pol, _ = make_policy(policy, bits, allowed, margin_q40, None, lut_dtype, granularity)
     e = _TuneEntry()
     _check(lib().amp_index_autotune(index.handle, _ptr(q), nq, _ptr(kk), _ptr(npb), per_query, C.byref(pol),
                                     AMP_BF16 if bf16 else AMP_F32, int(repeats), C.byref(e)))
@@ -448,12 +454,13 @@ def amp_index_info(index):
 
 
 def make_policy(policy="fixed", bits=16, allowed=(4, 8, 12, 16), margin_q40=0,
-                explicit_bits=None, lut_dtype=0):
+                explicit_bits=None, lut_dtype=0, granularity="pair"):
     mask = 0
     for b in allowed:
         mask |= 1 << int(b)
     xb = None if explicit_bits is None else np.ascontiguousarray(explicit_bits, dtype=np.uint8)
-    pol = _Policy(POLICIES[policy], int(bits), mask, int(lut_dtype), int(margin_q40), _ptr(xb))
+    pol = _Policy(POLICIES[policy], int(bits), mask, int(lut_dtype), int(margin_q40), _ptr(xb),
+                  GRANULARITIES[granularity])
     return pol, xb
 
 
@@ -462,7 +469,7 @@ def amp_search(index, queries, k, nprobe, policy="fixed", bits=16, allowed=(4, 8
                want_probes=False, want_bits=False, want_coarse=False, stage_ms=False,
                out=None, stream=None, graph=False, q_dtype=None, work=False, kmax=None, npmax=None,
                want_status=False, cl_policy="fp32", cl_bits=0, want_cl_dist=False, want_cl_bits=False,
-               _entry="amp_search"):
+               granularity="pair", _entry="amp_search"):
     """Search a batch.
 
     Host mode (``queries`` a numpy array): returns a dict of numpy arrays.
@@ -500,7 +507,7 @@ def amp_search(index, queries, k, nprobe, policy="fixed", bits=16, allowed=(4, 8
             kk = np.ascontiguousarray(np.broadcast_to(kk, (nq,)), dtype=np.int32)
             npb = np.ascontiguousarray(np.broadcast_to(npb, (nq,)), dtype=np.int32)
         kmax, npmax = int(kk.max()), int(npb.max())
-    pol, xb = make_policy(policy, bits, allowed, margin_q40, explicit_bits, lut_dtype)
+    pol, xb = make_policy(policy, bits, allowed, margin_q40, explicit_bits, lut_dtype, granularity)
     ms = np.zeros(AMP_N_STAGES, dtype=np.float32) if stage_ms else None
     wk = np.zeros(3, dtype=np.int64) if work else None
     fn = getattr(lib(), _entry)
@@ -624,8 +631,9 @@ class Server:
 
 
 def amp_server_create(index, max_batch=1024, max_pending=0, max_k=100, max_nprobe=0, batch_window_us=0,
-                      q_dtype="f32", policy="fixed", bits=16, allowed=(4, 8, 12, 16), margin_q40=0, lut_dtype=0):
-    pol, _ = make_policy(policy, bits, allowed, margin_q40, None, lut_dtype)
+                      q_dtype="f32", policy="fixed", bits=16, allowed=(4, 8, 12, 16), margin_q40=0, lut_dtype=0,
+                      granularity="pair"):
+    pol, _ = make_policy(policy, bits, allowed, margin_q40, None, lut_dtype, granularity)
     qd = AMP_BF16 if q_dtype == "bf16" else AMP_F32
     cfg = _ServerConfig(int(max_batch), int(max_pending), int(max_k), int(max_nprobe), int(batch_window_us), qd, pol)
     h = C.c_void_p()

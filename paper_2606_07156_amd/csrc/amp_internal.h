@@ -93,6 +93,7 @@ struct GraphKey {
   int32_t queue;
   int32_t cl_policy, cl_bits;
   const void *cl_dist, *cl_bits_out;
+  int32_t gran;
   bool operator==(const GraphKey& o) const {
     return q == o.q && ids == o.ids && dist == o.dist && qdist == o.qdist && probes == o.probes &&
            bits == o.bits && coarse == o.coarse && status == o.status && kptr == o.kptr && npptr == o.npptr &&
@@ -101,7 +102,7 @@ struct GraphKey {
            margin == o.margin && lut_dtype == o.lut_dtype && ws_gen == o.ws_gen && model_gen == o.model_gen &&
            chunk == o.chunk && chunk1 == o.chunk1 && capq == o.capq && wpr == o.wpr &&
            q_dtype == o.q_dtype && queue == o.queue && cl_policy == o.cl_policy && cl_bits == o.cl_bits &&
-           cl_dist == o.cl_dist && cl_bits_out == o.cl_bits_out;
+           cl_dist == o.cl_dist && cl_bits_out == o.cl_bits_out && gran == o.gran;
   }
 };
 struct GraphSlot {
@@ -140,7 +141,7 @@ struct Workspace {
   int16_t* qi16 = nullptr;     // [nq][d] queries on the operand grid
   int32_t* iptab = nullptr;    // [nq][M][256] exact integer table (FP32 policy: FP32 dot products)
   int32_t* iplo = nullptr;     // [nq][M] row minima of the integer table
-  int32_t* ipspan = nullptr;   // [nq] largest row span (max - min)
+  int32_t* ipspan = nullptr;   // [nq] largest row span (max - min); per-subspace widths: sum of the spans
   int64_t* iplsum = nullptr;   // [nq] sum of the row minima
   uint16_t* iptq = nullptr;    // [nq][4][M][256] quantised tables, one per width the query uses
   int32_t* ipsh = nullptr;     // [nq][4] their shifts
@@ -243,6 +244,7 @@ struct SearchDims {
   bool want_work;        // count the phase-2 work (code bytes scanned, live / skipped pairs)
   int policy;            // AMP_POLICY_*
   int lut_dtype;         // AMP_LUT_* (0 = BF16)
+  int gran;              // quantiser granularity: 0 one width per pair, 1 per-(pair, subspace) widths
   int queue;             // scan unit queue: 0 one counter, 1 per-XCD ranges with stealing
   int fixed_bits;
   uint32_t allowed_mask;

@@ -758,6 +758,8 @@ amp_status search_on(amp_index* ix, Workspace& w, const void* queries, int64_t n
       break;
     default: return set_error(AMP_EINVAL, "bad policy kind %d", pol->kind);
   }
+  if (pol->granularity != AMP_GRAN_PAIR && pol->granularity != AMP_GRAN_SUBSPACE)
+    return set_error(AMP_EINVAL, "bad quantiser granularity %d", pol->granularity);
   if (pol->lut_dtype != 0 && pol->lut_dtype != AMP_LUT_BF16 && pol->lut_dtype != AMP_LUT_F16 &&
       pol->lut_dtype != AMP_LUT_F8E4M3)
     return set_error(AMP_EINVAL, "bad LUT build dtype %d", pol->lut_dtype);
@@ -920,6 +922,7 @@ amp_status search_on(amp_index* ix, Workspace& w, const void* queries, int64_t n
   sd.capq = capq;
   sd.policy = pol->kind;
   sd.lut_dtype = lut_dtype;
+  sd.gran = pol->granularity;
   {
     // scan unit queue (AMP_QUEUE=0/1 forces the choice)
     const char* qv = getenv("AMP_QUEUE");
@@ -1031,7 +1034,8 @@ amp_status search_on(amp_index* ix, Workspace& w, const void* queries, int64_t n
                  opts->out_status, dev_sizes ? k : nullptr, dev_sizes ? nprobe : nullptr,
                  st, nq, per_query ? kmax : k[0], per_query ? npmax : nprobe[0], pol->kind, pol->fixed_bits,
                  sd.allowed_mask, pol->margin_q40, lut_dtype, w.generation, ix->model_generation, chunk, chunk1,
-                 capq, sd.wpr, opts->q_dtype, sd.queue, cl_policy, cl_lo, opts->out_cl_dist, opts->out_cl_bits};
+                 capq, sd.wpr, opts->q_dtype, sd.queue, cl_policy, cl_lo, opts->out_cl_dist, opts->out_cl_bits,
+                 pol->granularity};
     GraphSlot* hit = nullptr;
     for (GraphSlot& g : w.graphs)
       if (g.key == key) hit = &g;

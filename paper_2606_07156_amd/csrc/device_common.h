@@ -51,6 +51,17 @@ __device__ __forceinline__ int grid_val(float r, int e, int kind) {
   return e4m3_int((int)__builtin_amdgcn_fmed3f(x, -65536.f, 65536.f));
 }
 
+// quantiser shift of a pair of width b: the smallest s with
+// (R + n hf(s)) >> s <= n (2^b - 1), hf(s) = 2^(s-1) (0 for s = 0).  One
+// width per pair: R the largest subspace range, n = 1; per-(pair, subspace)
+// widths: R the sum of the ranges, n = M (the pair's lane budget)
+__device__ __forceinline__ int quant_shift(int64_t R, int n, int b) {
+  const int64_t top = (int64_t)n * ((1ll << b) - 1);
+  int sh = 0;
+  while (((R + (sh ? (int64_t)n << (sh - 1) : 0)) >> sh) > top) ++sh;
+  return sh;
+}
+
 __device__ __forceinline__ uint32_t bf16_bits(float v) {  // exact inputs only
   return __float_as_uint(v) >> 16;
 }

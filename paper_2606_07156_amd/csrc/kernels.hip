@@ -1231,9 +1231,7 @@ __global__ void k_ipq(BaseArgs b) {
     const int q = (int)(qw >> 2), wi = (int)(qw & 3);
     if (!(b.ipmask[q] & (1 << wi))) continue;
     const int bits = 4 * (wi + 1);
-    const int64_t top = (1ll << bits) - 1, R = b.ipspan[q];
-    int sh = 0;
-    while (((R + (sh ? (1ll << (sh - 1)) : 0)) >> sh) > top) ++sh;
+    const int sh = quant_shift(b.ipspan[q], b.gran ? b.M : 1, bits);
     const int hf = sh ? 1 << (sh - 1) : 0;
     const size_t e0 = (i - qw * per) * 8;
     if (e0 == 0) b.ipsh[qw] = sh;
@@ -1488,6 +1486,7 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
     ba.grid_e = sd.grid_e;
     ba.grid_kind = sd.grid_kind;
     ba.metric = sd.metric;
+    ba.gran = sd.gran;
     if (ipm && fp32) {
       // the queries' FP32 dot-product tables, their row maxima, the pairs'
       // FP32 lower bounds
@@ -1596,6 +1595,7 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   sa.grid_e = sd.grid_e;
   sa.grid_kind = sd.grid_kind;
   sa.metric = sd.metric;
+  sa.gran = sd.gran;
   sa.kconst = sd.kconst;
   sa.kmax = sd.kmax;
   sa.chunk = sd.chunk;  // per phase below
@@ -1712,6 +1712,7 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
     eb.grid_e = sd.grid_e;
     eb.grid_kind = sd.grid_kind;
     eb.metric = sd.metric;
+    eb.gran = sd.gran;
     if (ipm) {
       hipLaunchKernelGGL(k_export_ip, dim3((unsigned)npairs), dim3(256), 0, st, eb, ex->q, ex->shift, ex->base, ex->t);
     } else {

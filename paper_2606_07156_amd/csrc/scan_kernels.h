@@ -44,6 +44,7 @@ struct ScanArgs {
   uint16_t* ex_q;           // LUT export: quantised entries [pair][M][256]
   int nq, d, M, dsub, nlist, npmax, grid_e, grid_kind, metric, kconst, kmax, cls;
   int steal;                // unit queue: 0 one counter, 1 per-XCD ranges with stealing
+  int gran;                 // quantiser granularity: 0 one width per pair, 1 per-(pair, subspace) widths
   int64_t chunk;
   size_t capq;
 };
@@ -881,21 +882,23 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
         const int32_t* rrp = reinterpret_cast<const int32_t*>(lds + L.rr);
         const int g = tid >> 4, r = tid & 15;
         int32_t span = 0;
-        int64_t bsum = 0;
+        int64_t bsum = 0, rsum = 0;
         if (g < np_u)
           for (int m = r; m < M; m += 16) {
             const int32_t l = lo[g * M + m], h = hi[g * M + m];
             span = h - l > span ? h - l : span;
+            rsum += h - l;
             bsum += l - (ip ? rrp[g * M + m] : 0);
           }
         span = row16_reduce<true>(span);
 #pragma unroll
-        for (int off = 1; off < 16; off <<= 1) bsum += __shfl_xor(bsum, off, 16);
+        for (int off = 1; off < 16; off <<= 1) {
+          bsum += __shfl_xor(bsum, off, 16);
+          rsum += __shfl_xor(rsum, off, 16);
+        }
         if (r == 15 && g < G) {
           if (g < np_u) {
-            const int64_t top = (1ll << pb[g]) - 1, R = span;
-            int sh = 0;
-            while (((R + (sh ? (1ll << (sh - 1)) : 0)) >> sh) > top) ++sh;
+            const int sh = a.gran ? quant_shift(rsum, M, pb[g]) : quant_shift(span, 1, pb[g]);
             ps[g] = sh;
             pbase[g] = bsum;
           }
@@ -1411,6 +1414,7 @@ struct BaseArgs {
   const float* codebook;   // FP32 policy table
   int nq, d, M, dsub, npmax, grid_e, grid_kind, metric;
   int G;                   // pairs per workgroup of k_base
+  int gran;                // quantiser granularity (as ScanArgs)
 };
 
 __host__ __device__ inline ScanLds base_lds_layout(int G, int M, int d) {
@@ -1609,14 +1613,13 @@ __global__ __launch_bounds__(kThreads) void k_export(BaseArgs b, uint16_t* exq, 
   int32_t* ps = sp;  // (the probe ids are in s_probe now)
   if (tid < G) {
     int32_t span = 0;
-    int64_t bsum = 0;
+    int64_t bsum = 0, rsum = 0;
     for (int m = 0; m < M; ++m) {
       span = hi[tid * M + m] - lo[tid * M + m] > span ? hi[tid * M + m] - lo[tid * M + m] : span;
+      rsum += hi[tid * M + m] - lo[tid * M + m];
       bsum += lo[tid * M + m];
     }
-    const int64_t top = (1ll << pb[tid]) - 1, R = span;
-    int sh = 0;
-    while (((R + (sh ? (1ll << (sh - 1)) : 0)) >> sh) > top) ++sh;
+    const int sh = b.gran ? quant_shift(rsum, M, pb[tid]) : quant_shift(span, 1, pb[tid]);
     ps[tid] = sh;
     if (pq[tid] >= 0) {
       exs[pq[tid]] = sh;
@@ -1674,11 +1677,14 @@ __global__ __launch_bounds__(kThreads) void k_iptab(BaseArgs b) {
   const int32_t* hi = reinterpret_cast<const int32_t*>(lds + L.hi);
   for (int e = tid; e < nqb * M; e += kThreads) b.iplo[(size_t)q0 * M + e] = lo[e];
   // per query (a wave each): span and sum of minima
+  // (per-subspace granularity: the sum of the row spans instead of the
+  // largest)
   for (int g = wave; g < nqb; g += kThreads / 64) {
     int32_t span = 0;
-    int64_t sum = 0;
+    int64_t sum = 0, rsum = 0;
     for (int m = lane; m < M; m += 64) {
       span = hi[g * M + m] - lo[g * M + m] > span ? hi[g * M + m] - lo[g * M + m] : span;
+      rsum += hi[g * M + m] - lo[g * M + m];
       sum += lo[g * M + m];
     }
 #pragma unroll
@@ -1686,9 +1692,10 @@ __global__ __launch_bounds__(kThreads) void k_iptab(BaseArgs b) {
       const int32_t o = __shfl_xor(span, off);
       span = o > span ? o : span;
       sum += __shfl_xor(sum, off);
+      rsum += __shfl_xor(rsum, off);
     }
     if (lane == 0) {
-      b.ipspan[q0 + g] = span;
+      b.ipspan[q0 + g] = b.gran ? rsum : span;
       b.iplsum[q0 + g] = sum;
     }
   }

@@ -44,10 +44,14 @@ int64_t mitchell_q8_host(int64_t x) {
   int k = 63 - __builtin_clzll(y);
   return 256 * (int64_t)k + (int64_t)((y << 8) >> k) - 256;
 }
-int shift_for(int64_t R, int b) {
-  const int64_t top = (1ll << b) - 1;
+// quantiser shift (the search kernels' rule): smallest s with
+// (R + n hf(s)) >> s <= n (2^b - 1); n = 1 with R the largest subspace
+// range (one width per pair), n = M with R the sum of the ranges
+// (per-subspace widths)
+int shift_for(int64_t R, int n, int b) {
+  const int64_t top = (int64_t)n * ((1ll << b) - 1);
   int s = 0;
-  while (((R + (s ? (1ll << (s - 1)) : 0)) >> s) > top) ++s;
+  while (((R + (s ? ((int64_t)n << (s - 1)) : 0)) >> s) > top) ++s;
   return s;
 }
 
@@ -138,6 +142,8 @@ extern "C" amp_status amp_index_train_predictor(amp_index* ix, const float* tq, 
   if (nq <= 0 || k < 1 || nprobe < 1 || nprobe > ix->nlist) return set_error(AMP_EINVAL, "bad nq / k / nprobe");
   if (prm->n_samples < 8 || prm->n_samples > 8192) return set_error(AMP_EINVAL, "n_samples outside [8, 8192]");
   if (!(prm->gamma > 0) || !(prm->C > 0) || !(prm->epsilon >= 0)) return set_error(AMP_EINVAL, "bad SVR parameters");
+  if (prm->granularity != AMP_GRAN_PAIR && prm->granularity != AMP_GRAN_SUBSPACE)
+    return set_error(AMP_EINVAL, "bad quantiser granularity %d", prm->granularity);
   uint32_t allowed = prm->allowed_bits_mask ? prm->allowed_bits_mask : ((1u << 4) | (1u << 8) | (1u << 12) | (1u << 16));
   std::vector<int> widths;
   for (int b = 4; b <= 16; b += 4)
@@ -183,6 +189,7 @@ extern "C" amp_status amp_index_train_predictor(amp_index* ix, const float* tq, 
                       [&](int a, int b) { return D[a] < D[b] || (D[a] == D[b] && a < b); });
     // the query-wide inner-product LUT -qi.cbi and its spread
     // mode 0: inner product, 1: L2, 2: L1
+    const bool gsub = prm->granularity == AMP_GRAN_SUBSPACE;
     auto build_lut = [&](const int32_t* v, int mode) {
       int64_t Rp = 0;
       for (int m = 0; m < M; ++m) {
@@ -204,7 +211,7 @@ extern "C" amp_status amp_index_train_predictor(amp_index* ix, const float* tq, 
           lo = std::min(lo, s);
           hi = std::max(hi, s);
         }
-        Rp = std::max(Rp, hi - lo);
+        Rp = gsub ? Rp + (hi - lo) : std::max(Rp, hi - lo);  // sum of the ranges or the largest
       }
       return Rp;
     };
@@ -258,7 +265,7 @@ extern "C" amp_status amp_index_train_predictor(amp_index* ix, const float* tq, 
       }
       int bstar = widths.back();
       for (int b : widths) {
-        const int s = shift_for(R[r], b);
+        const int s = shift_for(R[r], gsub ? M : 1, b);
         const int64_t err = (int64_t)M * (s ? (1ll << (s - 1)) : 0);
         if (err < delta || s == 0) {
           bstar = b;

@@ -941,3 +941,54 @@ def test_device_sizes_out_of_range_are_clamped_and_reported(tiny):
     got = o["ids"].cpu().numpy()
     for i in range(8):
         assert np.array_equal(got[i, :kc[i]], want["ids"][i, :kc[i]]), i
+
+
+# ------------------------------------------- per-(pair, subspace) entry widths
+@pytest.mark.parametrize("policy,bits", [("fixed", 4), ("fixed", 8), ("fixed", 16), ("adaptive", 0)])
+def test_subspace_granularity_is_bit_exact(tiny, midint, policy, bits):
+    """The quantiser with a width per (pair, subspace) (the pair's lane budget
+    shared by its subspaces): ids, integer and float distances bit-exact on
+    the tiny and the integer-data shapes."""
+    for ctx, nprobe in ((tiny, 8), (midint, 16)):
+        kw = {}
+        if policy == "adaptive":
+            m = _spread_model(ctx, nprobe)
+            amp.amp_index_set_predictor(ctx["h"], m)
+            kw = dict(model=m)
+        g = _gpu(ctx, 10, nprobe, policy=policy, bits=bits, granularity="subspace")
+        ref = _oracle(ctx, 10, nprobe, g, policy=policy, bits=bits, granularity="subspace", **kw)
+        compare_integer(g, ref)
+
+
+@pytest.mark.parametrize("name,policy,bits", [("ipctx", "fixed", 4), ("ipctx", "fixed", 8), ("e4ctx", "fixed", 4),
+                                              ("l1ctx", "fixed", 4), ("l1ctx", "fixed", 8)])
+def test_subspace_granularity_other_metrics(request, name, policy, bits):
+    ctx = request.getfixturevalue(name)
+    nprobe = 6
+    g = _gpu(ctx, 10, nprobe, policy=policy, bits=bits, granularity="subspace")
+    ref = _oracle(ctx, 10, nprobe, g, policy=policy, bits=bits, granularity="subspace")
+    compare_integer(g, ref)
+
+
+@pytest.mark.parametrize("dtype", [amp.AMP_LUT_BF16, amp.AMP_LUT_F8E4M3])
+def test_subspace_granularity_export_replays(highdim_shape, dtype):
+    """High-dim shape (PQ120, e4m3 grid, k 100): the exported per-pair tables
+    replay the search exactly, and the BF16 export equals the oracle's
+    per-subspace quantisation of the exact LUT."""
+    torch = pytest.importorskip("torch")
+    ctx, w = highdim_shape
+    idx = ctx["idx"]
+    cbi, _ = oracle.index_grid(idx)
+    inv = 2.0 ** -idx["grid_e"]
+    g = _export_search(torch, ctx, 100, 12, policy="fixed", bits=4, lut_dtype=dtype, granularity="subspace")
+    assert int(g["status"][0]) == amp.AMP_OK
+    _replay(ctx, g, 100)
+    if dtype == amp.AMP_LUT_BF16:
+        for i in range(0, len(ctx["Q"]), 4):
+            for r in range(12):
+                p = int(g["probes"][i, r])
+                ri = oracle.grid(oracle.residual_f32(ctx["Q"][i], idx["centroids"][p]).astype(np.float64) * inv,
+                                 idx["grid_kind"])
+                Qt, sh, base = oracle.quantize_lut(oracle.lut_int(ri, cbi, "l2"), 4, "subspace")
+                assert int(g["lut_shift"][i, r]) == sh and int(g["lut_base"][i, r]) == base
+                assert np.array_equal(g["lut_q"][i, r].astype(np.int64), Qt)

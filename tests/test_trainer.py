@@ -143,3 +143,19 @@ def test_trainer_labels_follow_the_margin_definition(metric):
     rep = amp.amp_index_train_predictor(h, TQ, 10, 4, n_samples=40)
     assert rep["label_hist"] == _labels_by_definition(idx, TQ, 10, 4)
     assert rep["n_pairs"] == 12 * 4
+
+
+def test_trainer_granularity_bounds_with_the_matching_quantiser():
+    """Labels bound the error of the quantiser the search will use: with a
+    width per (pair, subspace) the shift is never larger than with one width
+    per pair by more than one step, so the labels are no wider on the whole."""
+    w = WORKLOADS["mid"].scaled(n=40_000, nlist=64)
+    base = make_base(w)
+    idx = build_index(base, w.nlist, w.M, iters=5, seed=w.seed, integer_data=True)
+    h = amp.amp_index_from_arrays(idx)
+    TQ = make_queries(w, 48, train=True)
+    rp = amp.amp_index_train_predictor(h, TQ, 10, 8, n_samples=200)
+    rs = amp.amp_index_train_predictor(h, TQ, 10, 8, n_samples=200, granularity="subspace")
+    assert rp["n_pairs"] == rs["n_pairs"]
+    mean = lambda hist: sum(c * b for c, b in zip(hist, (4, 8, 12, 16))) / sum(hist)  # noqa: E731
+    assert mean(rs["label_hist"]) <= mean(rp["label_hist"])
