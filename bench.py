@@ -374,6 +374,8 @@ def main():
     ap.add_argument("--epsilon", type=float, default=0.1)
     ap.add_argument("--svr-c", type=float, default=1.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--granularity", type=int, default=1,
+                    help="1: also measure per-(pair, subspace) LUT widths (retrained predictor)")
     ap.add_argument("--cl-slices", type=int, default=16, help="mid workload: CL dimension slices (0: no CL run)")
     ap.add_argument("--cl-subspaces", type=int, default=64, help="mid workload: CL sub-spaces per slice")
     ap.add_argument("--cl-epsilon", type=float, default=0.1, help="epsilon of the CL predictor's SVR")
@@ -702,6 +704,8 @@ def headline(args):
         if args.serve_rate > 0 else None
     if srv:
         log(f"[c5] serving {srv}")
+    gran = measure_granularity(h, w, Qb, kq, npq, truth, args, TQ, 10, 64, allowed, "c5", qdev=qdev,
+                               q_dtype="bf16") if args.granularity else None
     del b16
     line = {
         "metric": "QPS at recall@10 (adaptive vs full-precision, same GPU); p99 latency",
@@ -729,6 +733,7 @@ def headline(args):
                    "bits_share": rh["bits"],
                    "predictor": {kk: rep[kk] for kk in ("n_sv", "label_hist", "n_pairs")},
                    "policies": summary(res),
+                   "granularity_subspace": gran,
                    "serving": srv},
         "mfma": mfma_of(rh, w, nq),
         "roofline": roofline_of(rh, w, nq, TRAFFIC_FILE_C5),
@@ -775,9 +780,29 @@ def secondary_mid(args):
            "recall_definition": f"1- and 10-recall@10 over all {len(Q)} queries against exact FP64 kNN",
            "policies": summary(res), "roofline": roofline_of(ra, w, len(Q), TRAFFIC_FILE),
            "mfma": mfma_of(ra, w, len(Q)), "predictor": {kk: rep[kk] for kk in ("n_sv", "label_hist")}}
+    if args.granularity:
+        out["granularity_subspace"] = measure_granularity(h, w, Q, w.k, w.nprobe, truth, args, TQ, w.k, w.nprobe,
+                                                          (4, 8, 12, 16), "c2")
     if args.cl_slices > 0:
         out["cl"] = measure_cl(h, w, Q, truth, args, ra)
     return out
+
+
+def measure_granularity(h, w, Q, kq, npq, truth, args, TQ, k_train, np_train, allowed, tag, qdev=None,
+                        q_dtype=None):
+    """The adaptive policy with a width per (pair, subspace) in the quantiser
+    (the pair's lane budget shared by its subspaces), its predictor retrained
+    for that quantiser; the per-pair predictor is restored afterwards."""
+    import paper_2606_07156_amd as amp
+    saved = amp.amp_index_get_predictor(h)
+    rep = amp.amp_index_train_predictor(h, TQ, k_train, np_train, gamma=args.gamma, epsilon=args.epsilon,
+                                        C_=args.svr_c, n_samples=1280, allowed=allowed, granularity="subspace")
+    log(f"[{tag}] predictor for per-subspace widths: {rep}")
+    res = measure(h, w, Q, kq, npq, [("adaptive_sub", dict(policy="adaptive", allowed=allowed,
+                                                           granularity="subspace"))],
+                  args, truth, tag, qdev=qdev, q_dtype=q_dtype)
+    amp.amp_index_set_predictor(h, saved)
+    return {"predictor": {kk: rep[kk] for kk in ("n_sv", "label_hist")}, "policies": summary(res)}
 
 
 def measure_cl(h, w, Q, truth, args, r_fp32cl):
