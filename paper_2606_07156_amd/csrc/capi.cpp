@@ -391,7 +391,8 @@ amp_status amp_index_save(const amp_index* ix, const char* path) {
   FILE* f = fopen(path, "wb");
   if (!f) return set_error(AMP_EIO, "cannot open %s for writing", path);
   int32_t hdr[6] = {ix->d, ix->M, ix->nlist, ix->metric, ix->grid_kind, ix->grid_e};
-  uint32_t hm = ix->has_model ? 1 : 0;
+  // flags: 1 LUT predictor, 2 sub-space map of integer CL, 4 CL predictor
+  uint32_t hm = (ix->has_model ? 1u : 0u) | (ix->has_clmap ? 2u : 0u) | (ix->has_cl_model ? 4u : 0u);
   bool ok = wr(f, kMagic, 8) && wr(f, &kVersion, 4) && wr(f, hdr, sizeof hdr) && wr(f, &ix->n, 8) && wr(f, &hm, 4);
   ok = ok && wsec(f, 1, ix->centroids.data(), ix->centroids.size() * 4);
   ok = ok && wsec(f, 2, ix->codebook.data(), ix->codebook.size() * 4);
@@ -399,7 +400,7 @@ amp_status amp_index_save(const amp_index* ix, const char* path) {
   ok = ok && wsec(f, 4, ix->ids.data(), ix->ids.size() * 8);
   ok = ok && wsec(f, 5, ix->codes.data(), ix->codes.size());
   ok = ok && wsec(f, 6, ix->radq.data(), ix->radq.size() * 4);
-  if (hm) {
+  if (hm & 1) {
     int64_t scal[15];
     scal[0] = ix->n_sv;
     scal[1] = ix->beta0;
@@ -410,6 +411,26 @@ amp_status amp_index_save(const amp_index* ix, const char* path) {
     ok = ok && wsec(f, 7, scal, sizeof scal) && wsec(f, 8, &ix->g_mul, 8);
     ok = ok && wsec(f, 9, ix->sv.data(), ix->sv.size() * 4) && wsec(f, 10, ix->beta.data(), ix->beta.size() * 4);
     ok = ok && wsec(f, 11, ix->table.data(), ix->table.size() * 4);
+  }
+  if (hm & 2) {
+    int32_t cs[5] = {ix->cl_S, ix->cl_P, ix->cl_w, ix->cl_ec, 0};
+    std::memcpy(&cs[4], &ix->cl_o, 4);
+    ok = ok && wsec(f, 12, cs, sizeof cs) && wsec(f, 13, ix->cl_codes.data(), ix->cl_codes.size());
+    ok = ok && wsec(f, 14, ix->cl_assign.data(), ix->cl_assign.size() * 4) &&
+         wsec(f, 15, ix->cl_centre.data(), ix->cl_centre.size() * 4) &&
+         wsec(f, 16, ix->cl_radius.data(), ix->cl_radius.size() * 4) &&
+         wsec(f, 17, ix->cl_count.data(), ix->cl_count.size() * 4);
+  }
+  if (hm & 4) {
+    int64_t scal[15];
+    scal[0] = ix->cl_n_sv;
+    scal[1] = ix->cl_beta0;
+    for (int i = 0; i < 5; ++i) scal[2 + i] = ix->cl_feat_lo[i], scal[7 + i] = ix->cl_feat_mul[i];
+    for (int i = 0; i < 3; ++i) scal[12 + i] = ix->cl_theta[i];
+    ok = ok && wsec(f, 18, scal, sizeof scal) && wsec(f, 19, &ix->cl_g_mul, 8);
+    ok = ok && wsec(f, 20, ix->cl_sv.data(), ix->cl_sv.size() * 4) &&
+         wsec(f, 21, ix->cl_beta.data(), ix->cl_beta.size() * 4) &&
+         wsec(f, 22, ix->cl_table.data(), ix->cl_table.size() * 4);
   }
   ok = (fclose(f) == 0) && ok;
   return ok ? AMP_OK : set_error(AMP_EIO, "write to %s failed", path);
@@ -474,7 +495,38 @@ amp_status amp_index_load(const char* path, amp_index** out) {
     fclose(f);
     return s == AMP_EINVAL ? set_error(AMP_EFORMAT, "index content invalid: %s", g_err) : s;
   }
-  if (hm) {
+  if (hm & ~7u) {
+    fclose(f);
+    amp_index_free(ix);
+    return set_error(AMP_EFORMAT, "unknown section flags 0x%x", hm);
+  }
+  // a predictor's sections: scalars, g_mul, support vectors, weights, table
+  auto read_model = [&](uint32_t tag0, amp_predictor_model& m, std::vector<int32_t>& sv, std::vector<int32_t>& beta,
+                        std::vector<int32_t>& table) -> amp_status {
+    int64_t scal[15];
+    uint64_t gm = 0;
+    amp_status st;
+    if ((st = rsec(f, tag0, scal, sizeof scal)) || (st = rsec(f, tag0 + 1, &gm, 8))) return st;
+    const int nsv = (int)scal[0];
+    if (nsv < 0 || nsv > 4096) return set_error(AMP_EFORMAT, "bad model size");
+    sv.resize(5 * (size_t)nsv);
+    beta.resize(nsv);
+    table.resize(kTableN);
+    if ((st = rsec(f, tag0 + 2, sv.data(), sv.size() * 4)) || (st = rsec(f, tag0 + 3, beta.data(), beta.size() * 4)) ||
+        (st = rsec(f, tag0 + 4, table.data(), table.size() * 4)))
+      return st;
+    m = amp_predictor_model{};
+    m.n_sv = nsv;
+    m.sv = sv.data();
+    m.beta = beta.data();
+    m.table = table.data();
+    m.beta0 = scal[1];
+    for (int i = 0; i < 5; ++i) m.feat_lo[i] = scal[2 + i], m.feat_mul[i] = scal[7 + i];
+    for (int i = 0; i < 3; ++i) m.theta[i] = scal[12 + i];
+    m.g_mul = gm;
+    return AMP_OK;
+  };
+  if (hm & 1) {
     int64_t scal[15];
     uint64_t gm = 0;
     if ((s = rsec(f, 7, scal, sizeof scal)) || (s = rsec(f, 8, &gm, 8))) {
@@ -507,6 +559,56 @@ amp_status amp_index_load(const char* path, amp_index** out) {
     m.theta[2] = scal[14];
     m.g_mul = gm;
     if ((s = amp_index_set_predictor(ix, &m)) != AMP_OK) {
+      fclose(f);
+      amp_index_free(ix);
+      return s;
+    }
+  }
+  if (hm & 2) {
+    int32_t cs[5];
+    if ((s = rsec(f, 12, cs, sizeof cs)) != AMP_OK) {
+      fclose(f);
+      amp_index_free(ix);
+      return s;
+    }
+    const int S = cs[0], P = cs[1], w = cs[2];
+    if (S < 1 || w < 1 || S * w != d || w > 64 || P < 1 || P > std::min(nlist, 1024)) {
+      fclose(f);
+      amp_index_free(ix);
+      return set_error(AMP_EFORMAT, "implausible sub-space map");
+    }
+    std::vector<int8_t> codes((size_t)nlist * d);
+    std::vector<int32_t> asg((size_t)nlist * S), cen((size_t)S * P * w), rad((size_t)S * P), cnt((size_t)S * P);
+    if ((s = rsec(f, 13, codes.data(), codes.size())) || (s = rsec(f, 14, asg.data(), asg.size() * 4)) ||
+        (s = rsec(f, 15, cen.data(), cen.size() * 4)) || (s = rsec(f, 16, rad.data(), rad.size() * 4)) ||
+        (s = rsec(f, 17, cnt.data(), cnt.size() * 4))) {
+      fclose(f);
+      amp_index_free(ix);
+      return s;
+    }
+    for (int32_t a : asg)
+      if (a < 0 || a >= P) {
+        fclose(f);
+        amp_index_free(ix);
+        return set_error(AMP_EFORMAT, "sub-space index out of range");
+      }
+    ix->has_clmap = true;
+    ix->cl_S = S;
+    ix->cl_P = P;
+    ix->cl_w = w;
+    ix->cl_ec = cs[3];
+    std::memcpy(&ix->cl_o, &cs[4], 4);
+    ix->cl_codes.swap(codes);
+    ix->cl_assign.swap(asg);
+    ix->cl_centre.swap(cen);
+    ix->cl_radius.swap(rad);
+    ix->cl_count.swap(cnt);
+    ix->dev_cl_stale = true;
+  }
+  if (hm & 4) {
+    amp_predictor_model m;
+    std::vector<int32_t> sv, beta, table;
+    if ((s = read_model(18, m, sv, beta, table)) != AMP_OK || (s = amp_index_set_cl_predictor(ix, &m)) != AMP_OK) {
       fclose(f);
       amp_index_free(ix);
       return s;

@@ -99,3 +99,21 @@ def test_cl_trainer_end_to_end(small):
     amp.amp_index_build_cl_map(h, 16, 24, iters=10, seed=0)
     with pytest.raises(amp.AmpError):
         amp.amp_index_get_cl_predictor(h)
+
+
+def test_map_and_cl_predictor_survive_save_and_load(small, tmp_path):
+    h = small["h"]
+    amp.amp_index_build_cl_map(h, 8, 20, iters=5, seed=4)
+    amp.amp_index_train_cl_predictor(h, make_queries(small["w"], 24, train=True), 8, low=3, n_samples=200)
+    path = str(tmp_path / "cl.ampidx")
+    amp.amp_index_save(h, path)
+    h2 = amp.amp_index_load(path)
+    m1, m2 = amp.amp_index_get_cl_map(h), amp.amp_index_get_cl_map(h2)
+    for key in ("S", "P", "w", "o", "ec"):
+        assert m1[key] == m2[key], key
+    for key in ("assign", "centre", "radius", "count"):
+        assert np.array_equal(m1[key], m2[key]), key
+    p1, p2 = amp.amp_index_get_cl_predictor(h), amp.amp_index_get_cl_predictor(h2)
+    for key in ("sv", "beta", "table", "feat_lo", "feat_mul", "theta"):
+        assert np.array_equal(p1[key], p2[key]), key
+    assert p1["beta0"] == p2["beta0"] and p1["g_mul"] == p2["g_mul"]
