@@ -42,6 +42,9 @@ WORKLOADS = {
     # 1M x 128, values clipped to [0,255] and rounded (SIFT-like uint8 range).
     "mid": Workload("mid", 1_000_000, 128, 1024, 10_000, 1024, 16, 32, 10,
                     "uint8", 1002, integer_data=True),
+    # the same shape with isotropic sigma-32 components (sensitivity run)
+    "mid_iso": Workload("mid_iso", 1_000_000, 128, 1024, 10_000, 1024, 16, 32, 10,
+                        "uint8iso", 1002, integer_data=True),
     # 10M x 96, 4096 components with Zipf(1.1) weights -> skewed lists.
     "skewed": Workload("skewed", 10_000_000, 96, 4096, 4096, 4096, 24, 128, 10,
                        "zipf", 1003, nprobe_lo=8),
@@ -64,7 +67,7 @@ def _rng(seed, purpose):
 
 def _mixture_params(w: Workload):
     r = _rng(w.seed, _MEANS)
-    if w.kind == "uint8":
+    if w.kind in ("uint8", "uint8iso"):
         means = r.uniform(48.0, 208.0, size=(w.n_comp, w.d))
     elif w.kind == "vmf":
         means = r.standard_normal(size=(w.n_comp, w.d))
@@ -82,6 +85,8 @@ def _mixture_params(w: Workload):
         sigma = _rng(w.seed, _SIGMA).uniform(0.1, 2.0, size=w.d)
     elif w.kind == "vmf":
         sigma = np.full(w.d, 0.75 / np.sqrt(w.d))
+    elif w.kind == "uint8iso":
+        sigma = np.full(w.d, ISO_SIGMA)
     else:
         sigma = np.full(w.d, 1.0)
     return means, weights, sigma
@@ -93,6 +98,9 @@ def _mixture_params(w: Workload):
 # SIFT has an intrinsic dimension of this order; isotropic 128-d clusters
 # would make every member of a cluster nearly equidistant from a query.
 LATENT_DIM, LATENT_SIGMA, NOISE_SIGMA = 16, 20.0, 2.0
+# the harder-overlap variant of the mid workload: isotropic components of
+# per-dimension sigma 32 (clipped to [0, 255] and rounded)
+ISO_SIGMA = 32.0
 
 
 def _latent_maps(w: Workload):
@@ -121,6 +129,8 @@ def _draw(w: Workload, n: int, purpose: int, chunk: int = 1 << 18):
             x = means[comp[s:e]] + r.standard_normal(size=(e - s, w.d)) * sigma
             if w.kind == "vmf":
                 x /= np.linalg.norm(x, axis=1, keepdims=True)
+            elif w.kind == "uint8iso":
+                x = np.rint(np.clip(x, 0.0, 255.0))
         out[s:e] = x
     if w.kind == "vmf":
         # the serving corpus is stored in bf16: round to bf16 (nearest-even)

@@ -63,6 +63,19 @@ def measured_traffic(path=TRAFFIC_FILE):
     return t.get("bytes_per_launch") if t.get("kernel_hash") == _kernel_hash() else None
 
 
+def recall_1(ids, truth):
+    """1-recall@10: share of queries whose exact nearest neighbour is among
+    the 10 returned ids."""
+    ids, truth = np.asarray(ids)[:, :10], np.asarray(truth)
+    return float(np.mean([truth[i, 0] in set(ids[i].tolist()) for i in range(len(ids))]))
+
+
+def recall_10(ids, truth):
+    """10-recall@10: mean share of the exact top 10 among the 10 returned."""
+    ids, truth = np.asarray(ids)[:, :10], np.asarray(truth)[:, :10]
+    return float(np.mean([len(set(ids[i].tolist()) & set(truth[i].tolist())) / 10.0 for i in range(len(ids))]))
+
+
 def exact_knn_device(base, Q, k, metric, chunk=1 << 18):
     """Exact top-k ids by (distance, id) in FP64 on the device (ground truth
     for recall on corpora too large for the host brute force)."""
@@ -325,8 +338,14 @@ def sweep(args):
     bmax = max(int(b) for b in args.batches.split(","))
     Q = make_queries(w, max(bmax, w.nq))
     NP = draw_nprobe(w, len(Q))
+    t = time.perf_counter()
+    truth = exact_knn_device(base, Q[:bmax], 10, w.metric)
+    log(f"[sweep] exact kNN of {bmax} queries in {time.perf_counter() - t:.1f}s")
+    del base
     dev = torch.device("cuda:0")
     qd = torch.from_numpy(Q).to(dev)
+    npd = torch.from_numpy(NP.astype(np.int32)).to(dev)
+    kd = torch.full((len(Q),), 10, dtype=torch.int32, device=dev)
     stream = torch.cuda.Stream()
     rows = []
     for B in [int(b) for b in args.batches.split(",")]:
@@ -335,22 +354,27 @@ def sweep(args):
             e = amp.amp_index_autotune(h, Q[:B], 10, NP[:B], repeats=3, **kw)
             out = dict(ids=torch.empty((B, 10), dtype=torch.int64, device=dev),
                        dist=torch.empty((B, 10), dtype=torch.float32, device=dev))
+            szs = dict(k=kd[:B], nprobe=npd[:B], kmax=10, npmax=int(NP.max()))
             reps = max(3, min(200, int(2000 / max(B, 1)) + 3))
             for i in range(2):
-                amp.amp_search(h, qd[:B], 10, NP[:B], out=out, stream=stream, **kw)
+                amp.amp_search(h, qd[:B], out=out, stream=stream, graph=True, **szs, **kw)
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
             for i in range(reps):
-                amp.amp_search(h, qd[:B], 10, NP[:B], out=out, stream=stream, **kw)
+                amp.amp_search(h, qd[:B], out=out, stream=stream, graph=True, **szs, **kw)
             e1.record(stream)
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / reps
+            ids = out["ids"].cpu().numpy()
+            r1, r10 = recall_1(ids, truth[:B]), recall_10(ids, truth[:B])
             rows.append(dict(batch=B, policy=pol, ms=round(ms, 4), qps=round(B / ms * 1e3, 1),
+                             recall_1_at_10=round(r1, 4), recall_10_at_10=round(r10, 4),
                              schedule={kk: e[kk] for kk in ("chunk", "chunk1", "narrow", "lut_dtype", "queue")},
                              tuned_ms=round(e["ms"], 4), automatic_ms=round(e["ms_default"], 4)))
-            log(f"[sweep] B={B:5d} {pol:8s} {ms:8.3f} ms/batch {B / ms * 1e3:11.0f} QPS  schedule "
-                f"{rows[-1]['schedule']} (tuned {e['ms']:.3f} ms vs automatic {e['ms_default']:.3f} ms)")
+            log(f"[sweep] B={B:5d} {pol:8s} {ms:8.3f} ms/batch {B / ms * 1e3:11.0f} QPS  1-recall@10 {r1:.4f} "
+                f"10-recall@10 {r10:.4f}  schedule {rows[-1]['schedule']} (tuned {e['ms']:.3f} ms vs automatic "
+                f"{e['ms_default']:.3f} ms)")
     line = {"metric": "QPS per batch size (batched uneven work)", "unit": "queries/s", "n_gpus": 1,
             "higher_is_better": True, "data": "synthetic",
             "config": {"workload": f"{w.name}: {w.n}x{w.d} Zipf(1.1) mixture, IVF{w.nlist}/PQ{w.M}x256, "
@@ -462,7 +486,6 @@ def measure(h, w, Q, kq, npq, pols, args, truth, tag, qdev=None, q_dtype=None):
     against `truth` (exact FP64 ids of every query)."""
     import torch
 
-    import oracle
     import paper_2606_07156_amd as amp
     dev = torch.device("cuda:0")
     nq = len(Q)
@@ -517,8 +540,8 @@ def measure(h, w, Q, kq, npq, pols, args, truth, tag, qdev=None, q_dtype=None):
             low = kw.get("cl_bits") or 4
             cl_share = float(((g["cl_bits"] == low) * cm["count"][None]).sum()) / (nq * cm["count"].sum())
         ids10 = g["ids"][:, :10]
-        rec1 = oracle.recall_1_at(ids10, truth[:, :10]) if truth is not None else None
-        rec10 = oracle.recall_at(ids10, truth[:, :10]) if truth is not None else None
+        rec1 = recall_1(ids10, truth[:, :10]) if truth is not None else None
+        rec10 = recall_10(ids10, truth[:, :10]) if truth is not None else None
         pr = g["probes"]
         bits = g["bits"][pr >= 0]
         hist = {int(b): round(float((bits == b).mean()), 4) for b in np.unique(bits)}

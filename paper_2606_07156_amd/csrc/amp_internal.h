@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <mutex>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -222,6 +223,17 @@ namespace amp {
 
 // -------------------------------------------------------------- errors
 amp_status set_error(amp_status s, const char* fmt, ...);
+// a host entry point's body with a failed host allocation (std::bad_alloc,
+// also from worker threads that rethrow it) turned into AMP_ENOMEM: no C++
+// exception crosses the C ABI
+template <class F>
+amp_status host_guard(F&& body) {
+  try {
+    return body();
+  } catch (const std::bad_alloc&) {
+    return set_error(AMP_ENOMEM, "host allocation failed");
+  }
+}
 #define AMP_HIP(call)                                                        \
   do {                                                                       \
     hipError_t e_ = (call);                                                  \
@@ -245,6 +257,7 @@ struct SearchDims {
   int policy;            // AMP_POLICY_*
   int lut_dtype;         // AMP_LUT_* (0 = BF16)
   int gran;              // quantiser granularity: 0 one width per pair, 1 per-(pair, subspace) widths
+  int noskip;            // 1: no pair skipped by its base (AMP_PAIR_SKIP=0; measurement of the full scan)
   int queue;             // scan unit queue: 0 one counter, 1 per-XCD ranges with stealing
   int fixed_bits;
   uint32_t allowed_mask;

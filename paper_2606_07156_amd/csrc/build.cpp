@@ -18,6 +18,7 @@
 // Distances and assignments run on the GPU (FP32 MFMA); sums and the final
 // layout on the host in FP64 / integers.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -47,11 +48,27 @@ int n_threads() {
 
 template <typename F>
 void parallel_for(int64_t n, F&& f) {  // f(begin, end, thread)
+  // a failed host allocation (in a worker, or starting one) is rethrown once
+  // every started thread has been joined
   const int T = (int)std::min<int64_t>(n_threads(), std::max<int64_t>(1, n));
   std::vector<std::thread> th;
-  for (int t = 0; t < T; ++t)
-    th.emplace_back([&, t] { f(n * t / T, n * (t + 1) / T, t); });
+  std::atomic<bool> oom{false};
+  try {
+    th.reserve(T);
+    for (int t = 0; t < T; ++t)
+      th.emplace_back([&, t] {
+        try {
+          f(n * t / T, n * (t + 1) / T, t);
+        } catch (const std::bad_alloc&) {
+          oom = true;
+        }
+      });
+  } catch (...) {
+    for (auto& x : th) x.join();
+    throw std::bad_alloc();
+  }
   for (auto& x : th) x.join();
+  if (oom) throw std::bad_alloc();
 }
 
 struct Dev {  // device scratch of the build, freed on scope exit
@@ -177,7 +194,14 @@ amp_status kmeans(const float* rows, int64_t n, int dd, int k, int iters, uint64
 
 using namespace amp;
 
+static amp_status amp_index_build_body(const void* base_in, int64_t n, int32_t d, const int64_t* ids,
+                                      const amp_build_params* prm, amp_index** out);
 extern "C" amp_status amp_index_build(const void* base_in, int64_t n, int32_t d, const int64_t* ids,
+                                      const amp_build_params* prm, amp_index** out) {
+  return host_guard([&] { return amp_index_build_body(base_in, n, d, ids, prm, out); });
+}
+
+static amp_status amp_index_build_body(const void* base_in, int64_t n, int32_t d, const int64_t* ids,
                                       const amp_build_params* prm, amp_index** out) {
   if (!base_in || !prm || !out) return set_error(AMP_EINVAL, "null argument");
   *out = nullptr;

@@ -142,7 +142,12 @@ amp_status amp_index_from_arrays(const amp_index_arrays* a, amp_index** out) {
   return AMP_OK;
 }
 
+static amp_status set_predictor_impl(amp_index* ix, const amp_predictor_model* m);
 amp_status amp_index_set_predictor(amp_index* ix, const amp_predictor_model* m) {
+  return host_guard([&] { return set_predictor_impl(ix, m); });
+}
+
+static amp_status set_predictor_impl(amp_index* ix, const amp_predictor_model* m) {
   if (!ix || !m) return set_error(AMP_EINVAL, "null argument");
   if (m->n_sv < 0 || m->n_sv > 4096) return set_error(AMP_EINVAL, "n_sv %d outside [0, 4096]", m->n_sv);
   if ((m->n_sv && (!m->sv || !m->beta)) || !m->table) return set_error(AMP_EINVAL, "null model array");
@@ -150,11 +155,14 @@ amp_status amp_index_set_predictor(amp_index* ix, const amp_predictor_model* m) 
   for (int64_t i = 0; i < 5 * (int64_t)m->n_sv; ++i)
     if (m->sv[i] < 0 || m->sv[i] > 1023)
       return set_error(AMP_EINVAL, "support vector coordinate %d outside the feature range [0, 1023]", m->sv[i]);
+  // the copies first (they may fail), then the index changes at once
+  std::vector<int32_t> sv(m->sv, m->sv + 5 * (size_t)m->n_sv), beta(m->beta, m->beta + m->n_sv),
+      table(m->table, m->table + kTableN);
   std::lock_guard<std::mutex> lk(ix->mu);
   ix->n_sv = m->n_sv;
-  ix->sv.assign(m->sv, m->sv + 5 * (size_t)m->n_sv);
-  ix->beta.assign(m->beta, m->beta + m->n_sv);
-  ix->table.assign(m->table, m->table + kTableN);
+  ix->sv.swap(sv);
+  ix->beta.swap(beta);
+  ix->table.swap(table);
   ix->beta0 = m->beta0;
   for (int f = 0; f < 5; ++f) {
     ix->feat_lo[f] = m->feat_lo[f];
@@ -333,7 +341,12 @@ static amp_status to_device_locked(amp_index* ix, int device) {
   return AMP_OK;
 }
 
+static amp_status amp_index_to_device_body(amp_index* ix, int32_t device);
 amp_status amp_index_to_device(amp_index* ix, int32_t device) {
+  return host_guard([&] { return amp_index_to_device_body(ix, device); });
+}
+
+static amp_status amp_index_to_device_body(amp_index* ix, int32_t device) {
   if (!ix) return set_error(AMP_EINVAL, "null index");
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || count == 0) {
@@ -447,32 +460,50 @@ static amp_status rsec(FILE* f, uint32_t tag, void* p, size_t n) {
   return AMP_OK;
 }
 
+// reads an index file; the handle goes to *pix as soon as it exists (the
+// caller frees it on failure and closes the file)
+static amp_status index_read(FILE* f, const char* path, int64_t fsize, amp_index** pix);
+
 amp_status amp_index_load(const char* path, amp_index** out) {
   if (!path || !out) return set_error(AMP_EINVAL, "null argument");
   *out = nullptr;
   FILE* f = fopen(path, "rb");
   if (!f) return set_error(AMP_EIO, "cannot open %s", path);
+  int64_t fsize = -1;
+  if (fseek(f, 0, SEEK_END) == 0) fsize = (int64_t)ftell(f);
+  rewind(f);
+  amp_index* ix = nullptr;
+  const amp_status s = host_guard([&] { return index_read(f, path, fsize, &ix); });
+  fclose(f);
+  if (s != AMP_OK) {
+    if (ix) amp_index_free(ix);
+    return s;
+  }
+  *out = ix;
+  return AMP_OK;
+}
+
+static amp_status index_read(FILE* f, const char* path, int64_t fsize, amp_index** pix) {
   char mg[8];
   uint32_t ver = 0, hm = 0;
   int32_t hdr[6];
   int64_t n = 0;
   if (fread(mg, 1, 8, f) != 8 || memcmp(mg, kMagic, 8) != 0) {
-    fclose(f);
     return set_error(AMP_EFORMAT, "%s is not an index file", path);
   }
   if (fread(&ver, 4, 1, f) != 1 || ver != kVersion) {
-    fclose(f);
     return set_error(AMP_EFORMAT, "index file version %u, expected %u", ver, kVersion);
   }
   if (fread(hdr, sizeof hdr, 1, f) != 1 || fread(&n, 8, 1, f) != 1 || fread(&hm, 4, 1, f) != 1) {
-    fclose(f);
     return set_error(AMP_EFORMAT, "truncated header");
   }
   const int d = hdr[0], M = hdr[1], nlist = hdr[2];
   if (d <= 0 || M <= 0 || nlist <= 0 || d % M || nlist > AMP_MAX_NLIST || n < 0 || n >= (1ll << 31)) {
-    fclose(f);
     return set_error(AMP_EFORMAT, "implausible header");
   }
+  // the sections must fit the file before anything is allocated for them
+  const double need = 4.0 * nlist * d + 4.0 * M * kKsub * (d / M) + 8.0 * (nlist + 1) + 8.0 * n + (double)n * M;
+  if (fsize >= 0 && need > (double)fsize) return set_error(AMP_EFORMAT, "header sizes exceed the file");
   std::vector<float> C((size_t)nlist * d), CB((size_t)M * kKsub * (d / M));
   std::vector<int64_t> off(nlist + 1), ids(n);
   std::vector<uint8_t> codes((size_t)n * M);
@@ -481,23 +512,18 @@ amp_status amp_index_load(const char* path, amp_index** out) {
   if ((s = rsec(f, 1, C.data(), C.size() * 4)) || (s = rsec(f, 2, CB.data(), CB.size() * 4)) ||
       (s = rsec(f, 3, off.data(), off.size() * 8)) || (s = rsec(f, 4, ids.data(), ids.size() * 8)) ||
       (s = rsec(f, 5, codes.data(), codes.size())) || (s = rsec(f, 6, radq.data(), radq.size() * 4))) {
-    fclose(f);
     return s;
   }
   if (off[nlist] != n) {
-    fclose(f);
     return set_error(AMP_EFORMAT, "list offsets do not match n");
   }
   amp_index_arrays a{d, M, nlist, hdr[3], hdr[4], hdr[5], C.data(), CB.data(), off.data(), ids.data(), codes.data(),
                      radq.data()};
-  amp_index* ix = nullptr;
+  amp_index*& ix = *pix;
   if ((s = amp_index_from_arrays(&a, &ix)) != AMP_OK) {
-    fclose(f);
     return s == AMP_EINVAL ? set_error(AMP_EFORMAT, "index content invalid: %s", g_err) : s;
   }
   if (hm & ~7u) {
-    fclose(f);
-    amp_index_free(ix);
     return set_error(AMP_EFORMAT, "unknown section flags 0x%x", hm);
   }
   // a predictor's sections: scalars, g_mul, support vectors, weights, table
@@ -530,21 +556,15 @@ amp_status amp_index_load(const char* path, amp_index** out) {
     int64_t scal[15];
     uint64_t gm = 0;
     if ((s = rsec(f, 7, scal, sizeof scal)) || (s = rsec(f, 8, &gm, 8))) {
-      fclose(f);
-      amp_index_free(ix);
       return s;
     }
     const int nsv = (int)scal[0];
     if (nsv < 0 || nsv > 4096) {
-      fclose(f);
-      amp_index_free(ix);
       return set_error(AMP_EFORMAT, "bad model size");
     }
     std::vector<int32_t> sv(5 * (size_t)nsv), beta(nsv), table(kTableN);
     if ((s = rsec(f, 9, sv.data(), sv.size() * 4)) || (s = rsec(f, 10, beta.data(), beta.size() * 4)) ||
         (s = rsec(f, 11, table.data(), table.size() * 4))) {
-      fclose(f);
-      amp_index_free(ix);
       return s;
     }
     amp_predictor_model m{};
@@ -559,22 +579,16 @@ amp_status amp_index_load(const char* path, amp_index** out) {
     m.theta[2] = scal[14];
     m.g_mul = gm;
     if ((s = amp_index_set_predictor(ix, &m)) != AMP_OK) {
-      fclose(f);
-      amp_index_free(ix);
       return s;
     }
   }
   if (hm & 2) {
     int32_t cs[5];
     if ((s = rsec(f, 12, cs, sizeof cs)) != AMP_OK) {
-      fclose(f);
-      amp_index_free(ix);
       return s;
     }
     const int S = cs[0], P = cs[1], w = cs[2];
     if (S < 1 || w < 1 || S * w != d || w > 64 || P < 1 || P > std::min(nlist, 1024)) {
-      fclose(f);
-      amp_index_free(ix);
       return set_error(AMP_EFORMAT, "implausible sub-space map");
     }
     std::vector<int8_t> codes((size_t)nlist * d);
@@ -582,14 +596,10 @@ amp_status amp_index_load(const char* path, amp_index** out) {
     if ((s = rsec(f, 13, codes.data(), codes.size())) || (s = rsec(f, 14, asg.data(), asg.size() * 4)) ||
         (s = rsec(f, 15, cen.data(), cen.size() * 4)) || (s = rsec(f, 16, rad.data(), rad.size() * 4)) ||
         (s = rsec(f, 17, cnt.data(), cnt.size() * 4))) {
-      fclose(f);
-      amp_index_free(ix);
       return s;
     }
     for (int32_t a : asg)
       if (a < 0 || a >= P) {
-        fclose(f);
-        amp_index_free(ix);
         return set_error(AMP_EFORMAT, "sub-space index out of range");
       }
     ix->has_clmap = true;
@@ -609,13 +619,9 @@ amp_status amp_index_load(const char* path, amp_index** out) {
     amp_predictor_model m;
     std::vector<int32_t> sv, beta, table;
     if ((s = read_model(18, m, sv, beta, table)) != AMP_OK || (s = amp_index_set_cl_predictor(ix, &m)) != AMP_OK) {
-      fclose(f);
-      amp_index_free(ix);
       return s;
     }
   }
-  fclose(f);
-  *out = ix;
   return AMP_OK;
 }
 
@@ -1026,6 +1032,13 @@ amp_status search_on(amp_index* ix, Workspace& w, const void* queries, int64_t n
   sd.lut_dtype = lut_dtype;
   sd.gran = pol->granularity;
   {
+    // AMP_PAIR_SKIP=0 scans every pair in full (results unchanged: a pair
+    // whose base exceeds its query's bound holds no top-k vector), to measure
+    // the scan's traffic without the skip
+    const char* pv = getenv("AMP_PAIR_SKIP");
+    sd.noskip = pv && pv[0] == '0';
+  }
+  {
     // scan unit queue (AMP_QUEUE=0/1 forces the choice)
     const char* qv = getenv("AMP_QUEUE");
     sd.queue = qv && *qv ? (qv[0] == '1') : (tc.queue == 1);
@@ -1265,7 +1278,16 @@ amp_status reserve_workspace(amp_index* ix, int64_t nq, int npmax, int kmax, Wor
 
 extern "C" {
 
+static amp_status amp_search_body(amp_index* ix, const void* queries, int64_t nq, const int32_t* k, const int32_t* nprobe,
+                      int32_t per_query, const amp_precision_policy* pol, const amp_search_opts* opts,
+                      int64_t* out_ids, float* out_dist);
 amp_status amp_search(amp_index* ix, const void* queries, int64_t nq, const int32_t* k, const int32_t* nprobe,
+                      int32_t per_query, const amp_precision_policy* pol, const amp_search_opts* opts,
+                      int64_t* out_ids, float* out_dist) {
+  return host_guard([&] { return amp_search_body(ix, queries, nq, k, nprobe, per_query, pol, opts, out_ids, out_dist); });
+}
+
+static amp_status amp_search_body(amp_index* ix, const void* queries, int64_t nq, const int32_t* k, const int32_t* nprobe,
                       int32_t per_query, const amp_precision_policy* pol, const amp_search_opts* opts,
                       int64_t* out_ids, float* out_dist) {
   if (!ix) return set_error(AMP_EINVAL, "null argument");

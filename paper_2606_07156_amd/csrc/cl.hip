@@ -47,7 +47,7 @@ __device__ __forceinline__ int cl_code(float x, float o, int ec) {
   return (int)__builtin_amdgcn_fmed3f(v, -128.f, 127.f);
 }
 // b-bit MSB-first operand: the low 8 - b bits cleared (floor)
-__device__ __forceinline__ int cl_trunc(int v, int b) { return (v >> (8 - b)) << (8 - b); }
+__device__ __forceinline__ int cl_trunc(int v, int b) { return v - (v & ((1 << (8 - b)) - 1)); }
 // the same on four packed codes
 __device__ __forceinline__ uint32_t cl_bytemask(int b) {
   const uint32_t m = (0xFFu << (8 - b)) & 0xFFu;

@@ -45,9 +45,7 @@ int8_t cl_code_host(float x, float o, int ec) {
 
 using namespace amp;
 
-extern "C" {
-
-amp_status amp_index_build_cl_map(amp_index* ix, int32_t S, int32_t P, int32_t iters, uint64_t seed) {
+static amp_status build_cl_map_impl(amp_index* ix, int32_t S, int32_t P, int32_t iters, uint64_t seed) {
   if (!ix) return set_error(AMP_EINVAL, "null index");
   if (ix->metric != AMP_L2 && ix->metric != AMP_IP)
     return set_error(AMP_EUNSUPPORTED, "reduced-precision cluster locating supports L2 and inner product");
@@ -160,6 +158,18 @@ amp_status amp_index_build_cl_map(amp_index* ix, int32_t S, int32_t P, int32_t i
   return AMP_OK;
 }
 
+static amp_status set_cl_predictor_impl(amp_index* ix, const amp_predictor_model* m);
+
+extern "C" {
+
+amp_status amp_index_build_cl_map(amp_index* ix, int32_t S, int32_t P, int32_t iters, uint64_t seed) {
+  return host_guard([&] { return build_cl_map_impl(ix, S, P, iters, seed); });
+}
+
+amp_status amp_index_set_cl_predictor(amp_index* ix, const amp_predictor_model* m) {
+  return host_guard([&] { return set_cl_predictor_impl(ix, m); });
+}
+
 amp_status amp_index_get_cl_map(const amp_index* ix, amp_cl_map* out) {
   if (!ix || !out) return set_error(AMP_EINVAL, "null argument");
   if (!ix->has_clmap) return set_error(AMP_EINVAL, "index has no sub-space map");
@@ -175,7 +185,9 @@ amp_status amp_index_get_cl_map(const amp_index* ix, amp_cl_map* out) {
   return AMP_OK;
 }
 
-amp_status amp_index_set_cl_predictor(amp_index* ix, const amp_predictor_model* m) {
+}  // extern "C"
+
+static amp_status set_cl_predictor_impl(amp_index* ix, const amp_predictor_model* m) {
   if (!ix || !m) return set_error(AMP_EINVAL, "null argument");
   if (!ix->has_clmap) return set_error(AMP_EINVAL, "index has no sub-space map");
   if (m->n_sv < 0 || m->n_sv > 4096) return set_error(AMP_EINVAL, "n_sv %d outside [0, 4096]", m->n_sv);
@@ -184,11 +196,14 @@ amp_status amp_index_set_cl_predictor(amp_index* ix, const amp_predictor_model* 
   for (int64_t i = 0; i < 5 * (int64_t)m->n_sv; ++i)
     if (m->sv[i] < 0 || m->sv[i] > 1023)
       return set_error(AMP_EINVAL, "support vector coordinate %d outside the feature range [0, 1023]", m->sv[i]);
+  // the copies first (they may fail), then the index changes at once
+  std::vector<int32_t> sv(m->sv, m->sv + 5 * (size_t)m->n_sv), beta(m->beta, m->beta + m->n_sv),
+      table(m->table, m->table + kTableN);
   std::lock_guard<std::mutex> lk(ix->mu);
   ix->cl_n_sv = m->n_sv;
-  ix->cl_sv.assign(m->sv, m->sv + 5 * (size_t)m->n_sv);
-  ix->cl_beta.assign(m->beta, m->beta + m->n_sv);
-  ix->cl_table.assign(m->table, m->table + kTableN);
+  ix->cl_sv.swap(sv);
+  ix->cl_beta.swap(beta);
+  ix->cl_table.swap(table);
   ix->cl_beta0 = m->beta0;
   for (int f = 0; f < 5; ++f) ix->cl_feat_lo[f] = m->feat_lo[f], ix->cl_feat_mul[f] = m->feat_mul[f];
   for (int i = 0; i < 3; ++i) ix->cl_theta[i] = m->theta[i];
@@ -199,7 +214,7 @@ amp_status amp_index_set_cl_predictor(amp_index* ix, const amp_predictor_model* 
   return AMP_OK;
 }
 
-amp_status amp_index_get_cl_predictor(const amp_index* ix, amp_predictor_model* m, int32_t* sv, int32_t* beta,
+extern "C" amp_status amp_index_get_cl_predictor(const amp_index* ix, amp_predictor_model* m, int32_t* sv, int32_t* beta,
                                       int32_t* table, int32_t capacity) {
   if (!ix || !m) return set_error(AMP_EINVAL, "null argument");
   if (!ix->has_cl_model) return set_error(AMP_EINVAL, "index has no CL predictor");
@@ -218,5 +233,3 @@ amp_status amp_index_get_cl_predictor(const amp_index* ix, amp_predictor_model* 
   m->g_mul = ix->cl_g_mul;
   return AMP_OK;
 }
-
-}  // extern "C"

@@ -1454,7 +1454,7 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   // exact bases of the pairs (integer policies): the full scan's queue is
   // built after the phase-1 bound and leaves out the pairs whose base exceeds
   // it.  (The FP32 policy tests its bound inside the scan, after its LUT.)
-  const bool early = !fp32 || ipm;
+  const bool early = (!fp32 || ipm) && !sd.noskip;
   const int dt = dt_of(sd.lut_dtype);
   hipError_t err = hipSuccess;
   {
@@ -1596,6 +1596,7 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   sa.grid_kind = sd.grid_kind;
   sa.metric = sd.metric;
   sa.gran = sd.gran;
+  sa.noskip = sd.noskip;
   sa.kconst = sd.kconst;
   sa.kmax = sd.kmax;
   sa.chunk = sd.chunk;  // per phase below

@@ -45,6 +45,7 @@ struct ScanArgs {
   int nq, d, M, dsub, nlist, npmax, grid_e, grid_kind, metric, kconst, kmax, cls;
   int steal;                // unit queue: 0 one counter, 1 per-XCD ranges with stealing
   int gran;                 // quantiser granularity: 0 one width per pair, 1 per-(pair, subspace) widths
+  int noskip;               // 1: no pair is skipped whole by its base (measurement of the full scan's traffic)
   int64_t chunk;
   size_t capq;
 };
@@ -589,11 +590,14 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
         } else if constexpr (FP) {
           sig = (uint32_t)tk;
           // the pair's lower bound (sum of its row minima) already above
-          if (PHASE >= 2 && fkey(reinterpret_cast<const float*>(lds + L.pbase)[g]) > sig) live = false;
+          if (PHASE >= 2 && !a.noskip && fkey(reinterpret_cast<const float*>(lds + L.pbase)[g]) > sig) live = false;
         } else {
           const int64_t t = ikey_val(tk);
           if (t < pbase[g]) {
-            live = false;
+            // (noskip: the pair is scanned all the same; only a vector at
+            // its base could pass, a candidate beyond the bound that the
+            // merge ranks below the top k)
+            live = a.noskip != 0;
           } else {
             const int64_t dd = (t - pbase[g]) >> ps[g];
             sig = dd > (int64_t)MASK ? MASK : (uint32_t)dd;

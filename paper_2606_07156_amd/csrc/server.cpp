@@ -358,7 +358,12 @@ static amp_status check_policy(const amp_index* ix, const amp_precision_policy& 
   return AMP_OK;
 }
 
+static amp_status amp_server_create_body(amp_index* ix, const amp_server_config* cfg_in, amp_server** out);
 extern "C" amp_status amp_server_create(amp_index* ix, const amp_server_config* cfg_in, amp_server** out) {
+  return host_guard([&] { return amp_server_create_body(ix, cfg_in, out); });
+}
+
+static amp_status amp_server_create_body(amp_index* ix, const amp_server_config* cfg_in, amp_server** out) {
   if (!ix || !cfg_in || !out) return set_error(AMP_EINVAL, "null argument");
   *out = nullptr;
   amp_server_config c = *cfg_in;
@@ -400,7 +405,12 @@ extern "C" amp_status amp_server_create(amp_index* ix, const amp_server_config* 
   return AMP_OK;
 }
 
+static amp_status amp_server_submit_body(amp_server* sv, const amp_request* rq, uint64_t* ticket);
 extern "C" amp_status amp_server_submit(amp_server* sv, const amp_request* rq, uint64_t* ticket) {
+  return host_guard([&] { return amp_server_submit_body(sv, rq, ticket); });
+}
+
+static amp_status amp_server_submit_body(amp_server* sv, const amp_request* rq, uint64_t* ticket) {
   if (!sv || !rq || !rq->query || !rq->out_ids || !rq->out_dist) return set_error(AMP_EINVAL, "null argument");
   if (rq->k < 1 || rq->k > sv->cfg.max_k) return set_error(AMP_EINVAL, "k = %d outside [1, %d]", rq->k, sv->cfg.max_k);
   if (rq->nprobe < 1 || rq->nprobe > sv->cfg.max_nprobe)

@@ -6,6 +6,7 @@
 //
 // This is host code that runs once per index; it is not part of a search.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -53,6 +54,32 @@ int shift_for(int64_t R, int n, int b) {
   int s = 0;
   while (((R + (s ? ((int64_t)n << (s - 1)) : 0)) >> s) > top) ++s;
   return s;
+}
+
+// T worker threads running f(t, stop); a failed host allocation in any of
+// them (or in starting them) stops the others and is rethrown after every
+// started thread has been joined
+template <class F>
+void run_workers(int T, F&& f) {
+  std::vector<std::thread> th;
+  std::atomic<bool> oom{false};
+  try {
+    th.reserve(T);
+    for (int t = 0; t < T; ++t)
+      th.emplace_back([&, t] {
+        try {
+          f(t, oom);
+        } catch (const std::bad_alloc&) {
+          oom = true;
+        }
+      });
+  } catch (...) {
+    oom = true;
+    for (auto& x : th) x.join();
+    throw std::bad_alloc();
+  }
+  for (auto& x : th) x.join();
+  if (oom) throw std::bad_alloc();
 }
 
 struct Sample {
@@ -124,7 +151,7 @@ void svr_smo(const std::vector<double>& K, const std::vector<double>& y, double 
 
 using namespace amp;
 
-extern "C" amp_status amp_svr_fit(const double* K, const double* y, int32_t l, double C, double eps, double tol,
+static amp_status svr_fit_impl(const double* K, const double* y, int32_t l, double C, double eps, double tol,
                                   int32_t max_iter, double* coef, double* bias, int32_t* iterations) {
   if (!K || !y || !coef || !bias || l < 1 || !(C > 0) || !(eps >= 0) || !(tol > 0) || max_iter < 1)
     return set_error(AMP_EINVAL, "bad SVR fit arguments");
@@ -136,7 +163,7 @@ extern "C" amp_status amp_svr_fit(const double* K, const double* y, int32_t l, d
   return AMP_OK;
 }
 
-extern "C" amp_status amp_index_train_predictor(amp_index* ix, const float* tq, int64_t nq, int32_t k, int32_t nprobe,
+static amp_status train_predictor_impl(amp_index* ix, const float* tq, int64_t nq, int32_t k, int32_t nprobe,
                                                 const amp_train_params* prm, amp_train_report* rep) {
   if (!ix || !tq || !prm) return set_error(AMP_EINVAL, "null argument");
   if (nq <= 0 || k < 1 || nprobe < 1 || nprobe > ix->nlist) return set_error(AMP_EINVAL, "bad nq / k / nprobe");
@@ -286,12 +313,9 @@ extern "C" amp_status amp_index_train_predictor(amp_index* ix, const float* tq, 
   {
     const unsigned hw = std::thread::hardware_concurrency();
     const int T = (int)std::max<int64_t>(1, std::min<int64_t>(nq, std::min(hw ? hw : 1u, 16u)));
-    std::vector<std::thread> th;
-    for (int t = 0; t < T; ++t)
-      th.emplace_back([&, t] {
-        for (int64_t qi = t; qi < nq; qi += T) label_query(qi, per_q[qi]);
-      });
-    for (auto& x : th) x.join();
+    run_workers(T, [&](int t, const std::atomic<bool>& stop) {
+      for (int64_t qi = t; qi < nq && !stop; qi += T) label_query(qi, per_q[qi]);
+    });
   }
   std::vector<Sample> all;
   for (auto& v : per_q) all.insert(all.end(), v.begin(), v.end());
@@ -399,7 +423,7 @@ extern "C" amp_status amp_index_train_predictor(amp_index* ix, const float* tq, 
 // coarse distances and the nprobe boundary; the same feature map, sampling,
 // SMO fit and fixed-point export as the LUT predictor, with two classes (the
 // low width, 8 bits) and one threshold.
-extern "C" amp_status amp_index_train_cl_predictor(amp_index* ix, const float* tq, int64_t nq, int32_t nprobe,
+static amp_status train_cl_predictor_impl(amp_index* ix, const float* tq, int64_t nq, int32_t nprobe,
                                                    int32_t low, const amp_train_params* prm,
                                                    amp_train_report* rep) {
   if (!ix || !tq || !prm) return set_error(AMP_EINVAL, "null argument");
@@ -411,7 +435,7 @@ extern "C" amp_status amp_index_train_cl_predictor(amp_index* ix, const float* t
   const int d = ix->d, nl = ix->nlist, S = ix->cl_S, P = ix->cl_P, w = ix->cl_w;
   const bool ip = ix->metric == AMP_IP;
   const int klo = 8 - low;
-  auto tr = [](int v, int k) { return (v >> k) << k; };  // arithmetic shift: floor
+  auto tr = [](int v, int k) { return v - (v & ((1 << k) - 1)); };  // floor to a multiple of 2^k
   auto label_query = [&](int64_t qi, std::vector<Sample>& out) {
     const float* q = tq + (size_t)qi * d;
     std::vector<int> vq(d);
@@ -478,12 +502,9 @@ extern "C" amp_status amp_index_train_cl_predictor(amp_index* ix, const float* t
   {
     const unsigned hw = std::thread::hardware_concurrency();
     const int T = (int)std::max<int64_t>(1, std::min<int64_t>(nq, std::min(hw ? hw : 1u, 16u)));
-    std::vector<std::thread> th;
-    for (int t = 0; t < T; ++t)
-      th.emplace_back([&, t] {
-        for (int64_t qi = t; qi < nq; qi += T) label_query(qi, per_q[qi]);
-      });
-    for (auto& x : th) x.join();
+    run_workers(T, [&](int t, const std::atomic<bool>& stop) {
+      for (int64_t qi = t; qi < nq && !stop; qi += T) label_query(qi, per_q[qi]);
+    });
   }
   std::vector<Sample> all;
   for (auto& v : per_q) all.insert(all.end(), v.begin(), v.end());
@@ -579,4 +600,21 @@ extern "C" amp_status amp_index_train_cl_predictor(amp_index* ix, const float* t
     rep->train_rmse = std::sqrt(se / l);
   }
   return AMP_OK;
+}
+
+// ------------------------------------------------------------------ C entry points
+extern "C" amp_status amp_svr_fit(const double* K, const double* y, int32_t l, double C, double eps, double tol,
+                                  int32_t max_iter, double* coef, double* bias, int32_t* iterations) {
+  return host_guard([&] { return svr_fit_impl(K, y, l, C, eps, tol, max_iter, coef, bias, iterations); });
+}
+
+extern "C" amp_status amp_index_train_predictor(amp_index* ix, const float* tq, int64_t nq, int32_t k, int32_t nprobe,
+                                                const amp_train_params* prm, amp_train_report* rep) {
+  return host_guard([&] { return train_predictor_impl(ix, tq, nq, k, nprobe, prm, rep); });
+}
+
+extern "C" amp_status amp_index_train_cl_predictor(amp_index* ix, const float* tq, int64_t nq, int32_t nprobe,
+                                                   int32_t low, const amp_train_params* prm,
+                                                   amp_train_report* rep) {
+  return host_guard([&] { return train_cl_predictor_impl(ix, tq, nq, nprobe, low, prm, rep); });
 }

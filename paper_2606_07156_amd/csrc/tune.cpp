@@ -81,7 +81,16 @@ void put_entry(amp_index* ix, const amp_tune_entry& e) {
 
 }  // namespace
 
+static amp_status amp_index_autotune_body(amp_index* ix, const void* queries, int64_t nq, const int32_t* k,
+                                         const int32_t* nprobe, int32_t per_query, const amp_precision_policy* pol,
+                                         int32_t q_dtype, int32_t repeats, amp_tune_entry* out);
 extern "C" amp_status amp_index_autotune(amp_index* ix, const void* queries, int64_t nq, const int32_t* k,
+                                         const int32_t* nprobe, int32_t per_query, const amp_precision_policy* pol,
+                                         int32_t q_dtype, int32_t repeats, amp_tune_entry* out) {
+  return host_guard([&] { return amp_index_autotune_body(ix, queries, nq, k, nprobe, per_query, pol, q_dtype, repeats, out); });
+}
+
+static amp_status amp_index_autotune_body(amp_index* ix, const void* queries, int64_t nq, const int32_t* k,
                                          const int32_t* nprobe, int32_t per_query, const amp_precision_policy* pol,
                                          int32_t q_dtype, int32_t repeats, amp_tune_entry* out) {
   if (!ix || !queries || !k || !nprobe || !pol) return set_error(AMP_EINVAL, "null argument");
@@ -214,7 +223,12 @@ extern "C" amp_status amp_index_get_tuning(const amp_index* ix, amp_tune_entry* 
   return AMP_OK;
 }
 
+static amp_status amp_index_set_tuning_body(amp_index* ix, const amp_tune_entry* entries, int32_t count);
 extern "C" amp_status amp_index_set_tuning(amp_index* ix, const amp_tune_entry* entries, int32_t count) {
+  return host_guard([&] { return amp_index_set_tuning_body(ix, entries, count); });
+}
+
+static amp_status amp_index_set_tuning_body(amp_index* ix, const amp_tune_entry* entries, int32_t count) {
   if (!ix || count < 0 || (count && !entries)) return set_error(AMP_EINVAL, "bad arguments");
   for (int32_t i = 0; i < count; ++i) {
     amp_status s = check_entry(entries[i]);

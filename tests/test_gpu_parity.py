@@ -992,3 +992,20 @@ def test_subspace_granularity_export_replays(highdim_shape, dtype):
                 Qt, sh, base = oracle.quantize_lut(oracle.lut_int(ri, cbi, "l2"), 4, "subspace")
                 assert int(g["lut_shift"][i, r]) == sh and int(g["lut_base"][i, r]) == base
                 assert np.array_equal(g["lut_q"][i, r].astype(np.int64), Qt)
+
+
+@pytest.mark.parametrize("name,policy,bits", [("midint", "fixed", 4), ("midint", "adaptive", 0),
+                                              ("ipctx", "fixed", 8), ("tiny", "fp32", 0)])
+def test_scanning_every_pair_gives_the_same_results(request, monkeypatch, name, policy, bits):
+    """AMP_PAIR_SKIP=0 (a measurement switch) scans the pairs whose base
+    exceeds their query's bound too: identical results, more live pairs."""
+    ctx = request.getfixturevalue(name)
+    if policy == "adaptive":
+        amp.amp_index_set_predictor(ctx["h"], _spread_model(ctx, 16))
+    g = amp.amp_search(ctx["h"], ctx["Q"], 10, 16 if name == "midint" else 6, policy=policy, bits=bits, work=True)
+    monkeypatch.setenv("AMP_PAIR_SKIP", "0")
+    g0 = amp.amp_search(ctx["h"], ctx["Q"], 10, 16 if name == "midint" else 6, policy=policy, bits=bits, work=True)
+    assert np.array_equal(g["ids"], g0["ids"])
+    assert np.array_equal(g["dist"].view(np.uint32), g0["dist"].view(np.uint32))
+    assert g0["work"]["dead_pairs"] == 0
+    assert g0["work"]["live_pairs"] >= g["work"]["live_pairs"]
