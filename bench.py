@@ -896,6 +896,8 @@ def single(args):
     amp.amp_index_to_device(h, 0)
     if streaming:
         truth = np.zeros((len(Q), w.k), np.int64)  # duplicates tie: recall is not meaningful here
+    elif not args.recall:
+        truth = None
     else:
         t = time.perf_counter()
         truth = exact_knn_device(base, Q, w.k, w.metric)
@@ -930,7 +932,7 @@ def single(args):
                                f"{w.nprobe}, k {w.k}" + (", index built on the device" if args.gpu_build else "")
                                + (f"; every list replicated {args.replicate}x (streaming regime)"
                                   if streaming else ""),
-                   "policy": head, "recall_at_10": round(rh["recall10"], 4),
+                   "policy": head, "recall_at_10": round(rh["recall10"], 4) if rh["recall10"] is not None else None,
                    "speedup_vs_fp32": round(rh["qps"] / fp["qps"], 3) if fp else None,
                    "policies": summary(res)},
         "mfma": mfma_of(rh, w, len(Q)),

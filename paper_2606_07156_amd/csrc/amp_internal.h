@@ -30,9 +30,15 @@ constexpr int kXcd = 8;                // XCDs of the device (ranges of a steali
 constexpr int kCtrStride = 32;         // unit counters one 128-byte line apart
 constexpr int kQueueSlot = kXcd * kCtrStride;  // u32 words per scan unit queue
 
+// subspaces whose 4-bit entries (at most 15) an 8-bit lane adds before its
+// sums are widened into 16-bit lanes
+constexpr int kWideChunk = 16;
 // lane-width class of a b-bit LUT for M subspaces: the sum of M entries of at
-// most 2^b - 1 must fit in the lane
-inline int lane_class(int M, int b) {
+// most 2^b - 1 must fit in the lane; 4-bit widths with one width per pair
+// (entries at most 15) keep 8-bit entries for any M, their sums widened every
+// kWideChunk subspaces (up to M = 2184: sums below 2^15)
+inline int lane_class(int M, int b, int gran = 0) {
+  if (b == 4 && gran == 0 && M <= 2184) return 0;
   uint64_t top = (uint64_t)M * ((1ull << b) - 1);
   if (top <= 0xFFull) return 0;
   if (top <= 0xFFFFull) return 1;

@@ -647,6 +647,7 @@ struct QueueArgs {
   int4* units;        // [2][max_units]: {list, first pair, pair count, chunk}
   int32_t* flags;
   int nq, npmax, nlist, M, ncls, wpr;
+  int gran;               // quantiser granularity (lane classes of 4-bit pairs)
   int64_t chunk[2], max_units;  // list chunk of a work unit in phase 1, phase 2
   int ph0, ph1;           // queue phases built by this launch: [ph0, ph1) of {0 bound, 1 full scan}
   const int64_t* pbase;   // lower bound of every pair's estimates (integer: exact base; FP32 policy,
@@ -665,8 +666,9 @@ __device__ __forceinline__ bool pair_live(const QueueArgs& a, size_t i) {
   return key <= a.tau[i / a.npmax];
 }
 
-__device__ __forceinline__ int pair_class(int bits, int M) {
+__device__ __forceinline__ int pair_class(int bits, int M, int gran) {
   if (bits == 32) return 0;
+  if (bits == 4 && gran == 0 && M <= 2184) return 0;  // 8-bit entries, sums widened (lane_class)
   uint64_t top = (uint64_t)M * ((1ull << bits) - 1);
   return top <= 0xFFull ? 0 : (top <= 0xFFFFull ? 1 : 2);
 }
@@ -704,7 +706,7 @@ __global__ void k_qhist(QueueArgs a) {
   if (i >= n) return;
   const int p = a.probes[i];
   if (p < 0) return;
-  const int cls = pair_class(a.pbits[i], a.M);
+  const int cls = pair_class(a.pbits[i], a.M, a.gran);
   const int NB = a.ncls * a.nlist;
   const size_t b = (size_t)pair_sub(i) * NB + cls * a.nlist + p;
   if (a.ph1 > 1) {
@@ -806,7 +808,7 @@ __global__ void k_qscatter(QueueArgs a) {
   if (i >= n) return;
   const int p = a.probes[i];
   if (p < 0) return;
-  const int cls = pair_class(a.pbits[i], a.M);
+  const int cls = pair_class(a.pbits[i], a.M, a.gran);
   const int b = cls * a.nlist + a.lpos[p];
   const int NB = a.ncls * a.nlist;
   const size_t bs = (size_t)pair_sub(i) * NB + cls * a.nlist + p;  // sub-counter offset
@@ -1540,6 +1542,7 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   qa.nlist = sd.nlist;
   qa.M = sd.M;
   qa.ncls = ncls;
+  qa.gran = sd.gran;
   qa.wpr = sd.wpr;
   qa.chunk[0] = sd.chunk1;
   qa.chunk[1] = sd.chunk;
@@ -1623,7 +1626,7 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
     int sa_lwb;
     if (fp32 || sd.policy == AMP_POLICY_FIXED) {
       // one lane class holds every pair: its own kernel
-      const int c = fp32 ? 0 : lane_class(sd.M, sd.fixed_bits);
+      const int c = fp32 ? 0 : lane_class(sd.M, sd.fixed_bits, sd.gran);
       sa.cls = c;
       sa.counter = ws.counters + ((ph - 1) * (kNCls + 1) + c) * kQueueSlot;
       sa_lwb = fp32 ? 0 : lane_bits(c);

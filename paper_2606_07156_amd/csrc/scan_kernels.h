@@ -492,6 +492,11 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
   constexpr uint32_t MASK = Lane<LWB>::MASK;
   constexpr bool CRES = FP && MT != 0 && MT <= 16;  // FP32 codewords stay in registers
   const int M = MT ? MT : a.M;
+  // 8-bit entries of more than kWideChunk subspaces (4-bit widths, one width
+  // per pair): sums of kWideChunk entries stay in 8-bit lanes and are widened
+  // into 16-bit lanes (at most 2^15 - 1, guard bit 15) between chunks
+  const bool wide = LWB == 8 && M > kWideChunk;
+  const uint32_t SMASK = wide ? 0x7FFFu : MASK;
   int32_t* pq = reinterpret_cast<int32_t*>(lds + L.pq);
   int32_t* pb = reinterpret_cast<int32_t*>(lds + L.pb);
   int32_t* ps = reinterpret_cast<int32_t*>(lds + L.ps);
@@ -600,7 +605,7 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
             live = a.noskip != 0;
           } else {
             const int64_t dd = (t - pbase[g]) >> ps[g];
-            sig = dd > (int64_t)MASK ? MASK : (uint32_t)dd;
+            sig = dd > (int64_t)SMASK ? SMASK : (uint32_t)dd;
           }
         }
       }
@@ -1010,18 +1015,20 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
     for (int g = 0; g < G; ++g) lmin[g] = 0xFFFFFFFFu;
     // packed thresholds of the 8-bit lane class: fields 0,2 and 1,3 of each
     // word in 16-bit halves with guard bit 8; dead pairs never hit
+    // (wide: 15-bit sums in 16-bit halves, guard bit 15)
     uint32_t sig_e[WPR], sig_o[WPR], msk_e[WPR], msk_o[WPR];
     if constexpr (PHASE >= 2 && LWB == 8) {
+      const uint32_t top = wide ? 0x7FFFu : 255u, guard = wide ? 0x8000u : 0x100u;
 #pragma unroll
       for (int w = 0; w < WPR; ++w) {
         uint32_t se = 0, so = 0, me = 0, mo = 0;
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
           const int g = PairSlot<LWB, WPR>::pair(w, f);
-          const uint32_t sg = live[g] ? (sig[g] > 255u ? 255u : sig[g]) : 255u;
-          const uint32_t gb = live[g] ? 0x100u : 0u;
-          if (f & 1) { so |= (sg | 0x100u) << (16 * (f >> 1)); mo |= gb << (16 * (f >> 1)); }
-          else { se |= (sg | 0x100u) << (16 * (f >> 1)); me |= gb << (16 * (f >> 1)); }
+          const uint32_t sg = live[g] ? (sig[g] > top ? top : sig[g]) : top;
+          const uint32_t gb = live[g] ? guard : 0u;
+          if (f & 1) { so |= (sg | guard) << (16 * (f >> 1)); mo |= gb << (16 * (f >> 1)); }
+          else { se |= (sg | guard) << (16 * (f >> 1)); me |= gb << (16 * (f >> 1)); }
         }
         sig_e[w] = se; sig_o[w] = so; msk_e[w] = me; msk_o[w] = mo;
       }
@@ -1069,10 +1076,10 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
 #pragma unroll
       for (int i = 0; i < MQ; ++i) cw[i] = cwg[pv][i];
       if (v < v1) {
-        uint32_t acc[WPR];
+        uint32_t acc[WPR], acc_e[WPR], acc_o[WPR];
         float accf[WPR];
 #pragma unroll
-        for (int w = 0; w < WPR; ++w) { acc[w] = 0; accf[w] = 0.f; }
+        for (int w = 0; w < WPR; ++w) { acc[w] = 0; acc_e[w] = 0; acc_o[w] = 0; accf[w] = 0.f; }
         const uint32_t* cpg = reinterpret_cast<const uint32_t*>(a.codes + (size_t)(L0 + v) * M);
         for (int m4 = 0; m4 < M; m4 += 4) {
           uint32_t c4;
@@ -1087,6 +1094,18 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
             for (int w = 0; w < WPR; ++w) {
               if constexpr (FP) accf[w] += __uint_as_float(x[w]);
               else acc[w] += x[w];
+            }
+          }
+          if constexpr (LWB == 8) {
+            if (wide && (((m4 + 4) % kWideChunk) == 0 || m4 + 4 >= M)) {
+              // widen the chunk's 8-bit sums: fields 0, 2 and 1, 3 into
+              // the 16-bit halves of two words
+#pragma unroll
+              for (int w = 0; w < WPR; ++w) {
+                acc_e[w] += acc[w] & 0x00FF00FFu;
+                acc_o[w] += (acc[w] >> 8) & 0x00FF00FFu;
+                acc[w] = 0;
+              }
             }
           }
         }
@@ -1106,16 +1125,18 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
         };
         if constexpr (PHASE >= 2 && LWB == 8) {
           // four 8-bit sums per word: test all four against their thresholds
-          // at once in two 16-bit-lane halves (guard bit 8 survives iff S <= sigma)
+          // at once in two 16-bit-lane halves (guard bit 8 survives iff S <= sigma;
+          // wide: the widened sums, guard bit 15)
 #pragma unroll
           for (int w = 0; w < WPR; ++w) {
-            const uint32_t e = acc[w] & 0x00FF00FFu, o = (acc[w] >> 8) & 0x00FF00FFu;
+            const uint32_t e = wide ? acc_e[w] : acc[w] & 0x00FF00FFu;
+            const uint32_t o = wide ? acc_o[w] : (acc[w] >> 8) & 0x00FF00FFu;
             const uint32_t hit = ((sig_e[w] - e) & msk_e[w]) | ((sig_o[w] - o) & msk_o[w]);
             if (hit) {
 #pragma unroll
               for (int f = 0; f < 4; ++f) {
                 // rare path: thresholds from LDS, not held in registers
-                const uint32_t S = (acc[w] >> (8 * f)) & 0xFFu;
+                const uint32_t S = ((f & 1) ? o : e) >> (16 * (f >> 1)) & 0xFFFFu;
                 const int g = PairSlot<LWB, WPR>::pair(w, f);
                 if (pb[g] >= 0 && S <= psig[g]) emit(g, S);
               }
@@ -1127,6 +1148,7 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
             const int w = PairSlot<LWB, WPR>::word(g), f = PairSlot<LWB, WPR>::field(g);
             uint32_t S;
             if constexpr (FP) S = fkey(accf[w]);
+            else if (LWB == 8 && wide) S = ((f & 1) ? acc_o[w] : acc_e[w]) >> (16 * (f >> 1)) & 0xFFFFu;
             else S = LWB == 32 ? acc[w] : ((acc[w] >> (f * LWB)) & MASK);
             if (PHASE == 1) {
               lmin[g] = S < lmin[g] ? S : lmin[g];
