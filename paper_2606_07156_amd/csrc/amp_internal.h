@@ -33,6 +33,9 @@ constexpr int kQueueSlot = kXcd * kCtrStride;  // u32 words per scan unit queue
 // subspaces whose 4-bit entries (at most 15) an 8-bit lane adds before its
 // sums are widened into 16-bit lanes
 constexpr int kWideChunk = 16;
+// code dwords per vector that the generic scan variant keeps in registers
+// (M up to 4 kRegMQ subspaces); longer code rows are read as they are scanned
+constexpr int kRegMQ = 32;
 // lane-width class of a b-bit LUT for M subspaces: the sum of M entries of at
 // most 2^b - 1 must fit in the lane; 4-bit widths with one width per pair
 // (entries at most 15) keep 8-bit entries for any M, their sums widened every

@@ -62,6 +62,12 @@ __device__ __forceinline__ int quant_shift(int64_t R, int n, int b) {
   return sh;
 }
 
+// an inner-product query table of width index wi (width 4 (wi + 1)) is kept
+// as bytes for width 4 with one width per pair (entries at most 15; the
+// pairs of the 8-bit lane class are exactly these); per-subspace widths bound
+// only the sum of a row, so their tables stay uint16
+__host__ __device__ __forceinline__ bool ip_bytes(int gran, int wi, int M) { return gran == 0 && wi == 0 && M <= 2184; }
+
 __device__ __forceinline__ uint32_t bf16_bits(float v) {  // exact inputs only
   return __float_as_uint(v) >> 16;
 }

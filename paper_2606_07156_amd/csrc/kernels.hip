@@ -1215,8 +1215,10 @@ __global__ void k_export_ip(BaseArgs b, uint16_t* exq, int32_t* exs, int64_t* ex
     exs[i] = b.ipsh[q * 4 + wi];
     exb[i] = b.pbase[i];
   }
+  const uint16_t* slot = b.iptq + (q * 4 + wi) * tsz;
+  const bool by = ip_bytes(b.gran, wi, b.M);
   for (size_t e = threadIdx.x; e < tsz; e += blockDim.x) {
-    exq[i * tsz + e] = b.iptq[(q * 4 + wi) * tsz + e];
+    exq[i * tsz + e] = by ? reinterpret_cast<const uint8_t*>(slot)[e] : slot[e];
     if (ext) ext[i * tsz + e] = b.iptab[q * tsz + e];
   }
 }
@@ -1224,7 +1226,8 @@ __global__ void k_export_ip(BaseArgs b, uint16_t* exq, int32_t* exs, int64_t* ex
 // inner product, integer policies: each query's table quantised at every
 // width its pairs use: shift s from the query's span (smallest with
 // (span + hf(s)) >> s <= 2^b - 1), entries (T - min_m + hf(s)) >> s as
-// uint16; eight entries per thread
+// uint16, or as bytes in the first half of the table's slot (width 4 with
+// one width per pair: ip_bytes); eight entries per thread
 __global__ void k_ipq(BaseArgs b) {
   const size_t per = (size_t)b.M * kKsub / 8;
   const size_t n = (size_t)b.nq * 4 * per;
@@ -1240,13 +1243,17 @@ __global__ void k_ipq(BaseArgs b) {
     const int m = (int)(e0 >> 8);
     const int off = hf - b.iplo[(size_t)q * b.M + m];
     const int32_t* T = b.iptab + (size_t)q * b.M * kKsub + e0;
-    uint32_t w[4];
+    uint32_t v[8];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const uint32_t lo16 = (uint32_t)((T[2 * k] + off) >> sh), hi16 = (uint32_t)((T[2 * k + 1] + off) >> sh);
-      w[k] = lo16 | (hi16 << 16);
+    for (int k = 0; k < 8; ++k) v[k] = (uint32_t)((T[k] + off) >> sh);
+    uint16_t* slot = b.iptq + qw * ((size_t)b.M * kKsub);
+    if (ip_bytes(b.gran, wi, b.M)) {
+      *reinterpret_cast<u32x2*>(reinterpret_cast<uint8_t*>(slot) + e0) =
+          (u32x2){v[0] | (v[1] << 8) | (v[2] << 16) | (v[3] << 24), v[4] | (v[5] << 8) | (v[6] << 16) | (v[7] << 24)};
+    } else {
+      *reinterpret_cast<u32x4*>(slot + e0) =
+          (u32x4){v[0] | (v[1] << 16), v[2] | (v[3] << 16), v[4] | (v[5] << 16), v[6] | (v[7] << 16)};
     }
-    *reinterpret_cast<u32x4*>(b.iptq + qw * ((size_t)b.M * kKsub) + e0) = (u32x4){w[0], w[1], w[2], w[3]};
   }
 }
 

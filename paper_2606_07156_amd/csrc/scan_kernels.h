@@ -37,7 +37,7 @@ struct ScanArgs {
   // with its row minima and span; FP32 policy: FP32 dot products), and the
   // pairs' exact bases
   const int32_t* iptab;     // [nq][M][256] (FP32 policy: the FP32 dot products)
-  const uint16_t* iptq;     // [nq][4][M][256] quantised tables per width
+  const uint16_t* iptq;     // [nq][4][M][256] quantised tables per width (bytes where ip_bytes)
   const int32_t* ipsh;      // [nq][4] their shifts
   const int64_t* pbase_g;   // [nq][npmax]
   int32_t* tab_out;         // LUT pass 1 that also stores T (per-query table build, LUT export)
@@ -744,33 +744,59 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
       }
       uint32_t* lut = reinterpret_cast<uint32_t*>(lds + L.lut);
       const size_t tsz = (size_t)M * kKsub;
-      // eight entries (one 16-byte load per pair) per thread and step
-      for (int e8 = tid; e8 < M * kKsub / 8; e8 += kThreads) {
-        uint32_t wds[8][WPR];
+      // one 16-byte load per pair and step (16 byte entries or 8 uint16
+      // ones); the loads of U steps are issued before any is consumed
+      constexpr int U = G >= 16 ? 1 : (G >= 8 ? 2 : 4);
+      auto copy = [&](auto by_tag) {
+        constexpr bool BY = decltype(by_tag)::value;
+        constexpr int EPS = BY ? 16 : 8;  // entries per step
+        const int ns = M * kKsub / EPS;
+        for (int eb = tid; eb < ns; eb += U * kThreads) {
+          u32x4 xs[U][G];
 #pragma unroll
-        for (int k = 0; k < 8; ++k)
+          for (int u = 0; u < U; ++u)
 #pragma unroll
-          for (int w = 0; w < WPR; ++w) wds[k][w] = 0;
+            for (int g = 0; g < G; ++g) {
+              const int es = eb + u * kThreads;
+              xs[u][g] = (u32x4){0u, 0u, 0u, 0u};  // absent pairs: zero fields
+              if (g < np_u && es < ns)
+                xs[u][g] = *reinterpret_cast<const u32x4*>(
+                    reinterpret_cast<const uint8_t*>(a.iptq + (size_t)pw[g] * tsz) + (size_t)es * 16);
+            }
 #pragma unroll
-        for (int w = 0; w < WPR; ++w)
+          for (int u = 0; u < U; ++u) {
+            const int es = eb + u * kThreads;
+            if (es >= ns) continue;
+            uint32_t wds[EPS][WPR];
 #pragma unroll
-          for (int f = 0; f < W; ++f) {
-            const int g = PairSlot<LWB, WPR>::pair(w, f);
-            if (g < np_u) {
-              const u32x4 x = *reinterpret_cast<const u32x4*>(a.iptq + (size_t)pw[g] * tsz + (size_t)e8 * 8);
+            for (int k = 0; k < EPS; ++k)
 #pragma unroll
-              for (int k = 0; k < 8; ++k) {
-                const uint32_t qv = (x[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
-                wds[k][w] |= LWB == 32 ? qv : (qv << (f * LWB));
+              for (int w = 0; w < WPR; ++w) {
+                uint32_t wd = 0;
+#pragma unroll
+                for (int f = 0; f < W; ++f) {
+                  const u32x4 x = xs[u][PairSlot<LWB, WPR>::pair(w, f)];
+                  const uint32_t qv = BY ? (x[k >> 2] >> (8 * (k & 3))) & 0xFFu : (x[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
+                  wd |= LWB == 32 ? qv : (qv << (f * LWB));
+                }
+                wds[k][w] = wd;
               }
+#pragma unroll
+            for (int k = 0; k < EPS; ++k) {
+              uint32_t* dst = lut + ((size_t)es * EPS + k) * WPR;
+#pragma unroll
+              for (int w = 0; w < WPR; ++w) dst[w] = wds[k][w];
             }
           }
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          uint32_t* dst = lut + ((size_t)e8 * 8 + k) * WPR;
-#pragma unroll
-          for (int w = 0; w < WPR; ++w) dst[w] = wds[k][w];
         }
+      };
+      // the 8-bit lane class of one width per pair holds width-4 pairs only,
+      // whose tables are bytes (ip_bytes); every other table is uint16
+      if constexpr (LWB == 8) {
+        if (ip_bytes(a.gran, 0, M)) copy(std::true_type{});
+        else copy(std::false_type{});
+      } else {
+        copy(std::false_type{});
       }
       __syncthreads();
     } else {
@@ -1034,21 +1060,32 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
       }
     }
     lds_u32* lut = reinterpret_cast<lds_u32*>((uintptr_t)L.lut);  // LDS address (see lds_u32)
-    constexpr int MQ = MT ? MT / 4 : 1;  // code dwords per vector held in registers
+    // code dwords per vector held in registers: MT / 4 for a specialised
+    // variant; the generic integer BF16 one holds up to kRegMQ (M <= 4
+    // kRegMQ) with its loops unrolled to that bound and branches on M.
+    // Longer rows, the FP16 / FP8 builds (whose B fragments leave no
+    // registers for it) and the FP32 LUT (one dependent chain of FP32 adds
+    // per vector: measured slower with the codes in registers) read the
+    // codes from memory as they are scanned.
+    constexpr bool RG = MT == 0 && DT == DT_BF16 && !FP;
+    constexpr int MQ = MT ? MT / 4 : (RG ? kRegMQ : 1);
+    const bool regc = MT != 0 || (RG && M <= 4 * kRegMQ);
     // vectors per thread and step: one-word rows (a few pairs per list, the
     // streaming case) make a vector cheap to scan, so four are kept in flight
     // to cover HBM latency; wide rows are compute-bound at one
     constexpr int PV = (NR && MT != 0) ? 4 : 1;
     uint32_t cw_next[PV][MQ];
-    if constexpr (MT != 0) {
+    auto load_codes = [&](int64_t v, uint32_t* cw) {
+      const uint32_t* cp = reinterpret_cast<const uint32_t*>(a.codes + (size_t)(L0 + v) * M);
+#pragma unroll
+      for (int i = 0; i < MQ; ++i)
+        if (MT != 0 || 4 * i < M) cw[i] = cp[i];
+    };
+    if (regc) {
 #pragma unroll
       for (int pv = 0; pv < PV; ++pv) {
         const int64_t v = v0 + tid + pv * kThreads;
-        if (v < v1) {
-          const uint32_t* cp = reinterpret_cast<const uint32_t*>(a.codes + (size_t)(L0 + v) * MT);
-#pragma unroll
-          for (int i = 0; i < MQ; ++i) cw_next[pv][i] = cp[i];
-        }
+        if (v < v1) load_codes(v, cw_next[pv]);
       }
     }
     fetch_next();  // the next unit's descriptor, read while this one scans
@@ -1058,33 +1095,23 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
       for (int pv = 0; pv < PV; ++pv)
 #pragma unroll
         for (int i = 0; i < MQ; ++i) cwg[pv][i] = cw_next[pv][i];
-      if constexpr (MT != 0) {
+      if (regc) {
 #pragma unroll
         for (int pv = 0; pv < PV; ++pv) {
           const int64_t vn = vb + tid + (PV + pv) * kThreads;
-          if (vn < v1) {
-            const uint32_t* cp = reinterpret_cast<const uint32_t*>(a.codes + (size_t)(L0 + vn) * MT);
-#pragma unroll
-            for (int i = 0; i < MQ; ++i) cw_next[pv][i] = cp[i];
-          }
+          if (vn < v1) load_codes(vn, cw_next[pv]);
         }
       }
 #pragma unroll
       for (int pv = 0; pv < PV; ++pv) {
       const int64_t v = vb + tid + pv * kThreads;
-      uint32_t cw[MQ];
-#pragma unroll
-      for (int i = 0; i < MQ; ++i) cw[i] = cwg[pv][i];
       if (v < v1) {
         uint32_t acc[WPR], acc_e[WPR], acc_o[WPR];
         float accf[WPR];
 #pragma unroll
         for (int w = 0; w < WPR; ++w) { acc[w] = 0; acc_e[w] = 0; acc_o[w] = 0; accf[w] = 0.f; }
-        const uint32_t* cpg = reinterpret_cast<const uint32_t*>(a.codes + (size_t)(L0 + v) * M);
-        for (int m4 = 0; m4 < M; m4 += 4) {
-          uint32_t c4;
-          if constexpr (MT != 0) c4 = cw[m4 >> 2];
-          else c4 = cpg[m4 >> 2];
+        // four subspaces from one code dword
+        auto step4 = [&](uint32_t c4, int m4) {
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int rowi = ((m4 + i) * kKsub + ((c4 >> (8 * i)) & 255u)) * WPR;
@@ -1108,6 +1135,14 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
               }
             }
           }
+        };
+        if (regc) {
+#pragma unroll
+          for (int i = 0; i < MQ; ++i)
+            if (MT != 0 || 4 * i < M) step4(cwg[pv][i], 4 * i);
+        } else {
+          const uint32_t* cpg = reinterpret_cast<const uint32_t*>(a.codes + (size_t)(L0 + v) * M);
+          for (int m4 = 0; m4 < M; m4 += 4) step4(cpg[m4 >> 2], m4);
         }
         auto emit = [&](int g, uint32_t S) {
           const int q = pq[g];
@@ -1433,7 +1468,7 @@ struct BaseArgs {
   int32_t* iplo;           // [nq][M]
   int32_t* ipspan;         // [nq]
   int64_t* iplsum;         // [nq]
-  uint16_t* iptq;          // [nq][4][M][256]
+  uint16_t* iptq;          // [nq][4][M][256] (bytes where ip_bytes)
   int32_t* ipsh;           // [nq][4]
   int32_t* ipmask;         // [nq]
   const uint8_t* pbits;    // [nq][npmax]
