@@ -1277,10 +1277,10 @@ hipError_t launch_prep_index(const amp_index* ix, hipStream_t st) {
   return hipGetLastError();
 }
 
-static size_t scan_lds_bytes(int lw_bits, int phase, int M, int d, int wpr) {
+static size_t scan_lds_bytes(int lw_bits, int phase, int M, int d, int wpr, int nt) {
   const bool fp = lw_bits == 0;
   const int G = fp ? wpr : wpr * (32 / lw_bits);
-  return (size_t)scan_lds_layout(G, wpr, M, d, fp, phase).total;
+  return (size_t)scan_lds_layout(G, wpr, M, d, fp, phase, nt).total;
 }
 
 int scan_wpr(int M, bool fp32, int lut_dtype, bool narrow) {
@@ -1289,28 +1289,57 @@ int scan_wpr(int M, bool fp32, int lut_dtype, bool narrow) {
 
 static int g_num_cu = 0;
 
-// lwb < 0: every integer lane class in one launch (k_scan_mix)
+// lwb < 0: every integer lane class in one launch (k_scan_mix).  A LUT tile
+// so large that one 256-thread workgroup fills a CU's LDS leaves one wave
+// per SIMD to hide the LDS and code-load latencies: the generic variant then
+// runs 512-thread workgroups (two waves per SIMD on the same LUT;
+// AMP_SCAN_WG512=0 keeps 256).
 static hipError_t launch_scan(int lwb, int ph, int dt, int wpr, const ScanArgs& sa, hipStream_t st) {
-  // phase 3 (the re-run) usually has nothing to do: one workgroup per CU
   const bool mix = lwb < 0;
-  ScanFn fn = ph == 1 ? pick_scan_ph1(lwb, sa.M, dt, wpr)
-                      : (ph == 2 ? pick_scan_ph2(lwb, sa.M, dt, wpr) : pick_scan_ph3(lwb, sa.M, dt, wpr));
+  auto pick = [&](int nt) {
+    return ph == 1 ? pick_scan_ph1(lwb, sa.M, dt, wpr, nt)
+                   : (ph == 2 ? pick_scan_ph2(lwb, sa.M, dt, wpr, nt) : pick_scan_ph3(lwb, sa.M, dt, wpr, nt));
+  };
+  ScanFn fn = pick(kThreads);
+  int nt = kThreads;
   // the queue packed units for `wpr` words per row: the variant must agree
   const int mt = scan_mt(mix ? 8 : lwb, sa.M, dt);
   if (!fn || variant_wpr(mt, scan_nr(mt, wpr)) != wpr) return hipErrorInvalidValue;
-  const size_t lds = scan_lds_bytes(mix ? 8 : lwb, ph, sa.M, sa.d, wpr);
+  size_t lds = scan_lds_bytes(mix ? 8 : lwb, ph, sa.M, sa.d, wpr, nt);
   hipError_t e = hipFuncSetAttribute(kaddr(fn), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   int per_cu = 0;
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kaddr(fn), kThreads, lds);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kaddr(fn), nt, lds);
   if (e != hipSuccess) return e;
   if (per_cu < 1) return hipErrorInvalidConfiguration;
+  static const bool wg512 = [] {
+    const char* v = getenv("AMP_SCAN_WG512");
+    return !(v && v[0] == '0');
+  }();
+  if (per_cu == 1 && wg512) {
+    ScanFn f2 = pick(2 * kThreads);
+    if (f2) {
+      const size_t l2 = scan_lds_bytes(mix ? 8 : lwb, ph, sa.M, sa.d, wpr, 2 * kThreads);
+      int pc2 = 0;
+      if ((e = hipFuncSetAttribute(kaddr(f2), hipFuncAttributeMaxDynamicSharedMemorySize, (int)l2)) != hipSuccess)
+        return e;
+      if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&pc2, kaddr(f2), 2 * kThreads, l2)) != hipSuccess)
+        return e;
+      if (pc2 >= 1) {
+        fn = f2;
+        nt = 2 * kThreads;
+        lds = l2;
+        per_cu = pc2;
+      }
+    }
+  }
   if (!g_num_cu) {
     int dev = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&g_num_cu, hipDeviceAttributeMultiprocessorCount, dev);
   }
-  hipLaunchKernelGGL(fn, dim3(g_num_cu * (ph == 3 ? 1 : per_cu)), dim3(kThreads), lds, st, sa);
+  // phase 3 (the re-run) usually has nothing to do: one workgroup per CU
+  hipLaunchKernelGGL(fn, dim3(g_num_cu * (ph == 3 ? 1 : per_cu)), dim3(nt), lds, st, sa);
   return hipGetLastError();
 }
 

@@ -102,7 +102,7 @@ __host__ __device__ constexpr int ri_stride(int d) { return d + 16; }
 struct ScanLds {
   int lut, ri, rr, lo, hi, pq, pb, ps, pbase, psig, pid, lmin, ctl, total;
 };
-__host__ __device__ inline ScanLds scan_lds_layout(int G, int wpr, int M, int d, bool fp32, int phase) {
+__host__ __device__ inline ScanLds scan_lds_layout(int G, int wpr, int M, int d, bool fp32, int phase, int nt) {
   ScanLds L;
   int o = 0;
   auto take = [&](int bytes) { int r = o; o += (bytes + 15) & ~15; return r; };
@@ -119,7 +119,7 @@ __host__ __device__ inline ScanLds scan_lds_layout(int G, int wpr, int M, int d,
   L.pid = take(G * 4);
   // phase 1 keeps per-thread minima after the scan: reuse the LUT space
   L.lmin = L.lut;
-  if (phase == 1 && G * kThreadsP2 * 4 > M * kKsub * wpr * 4) L.lmin = take(G * kThreadsP2 * 4);
+  if (phase == 1 && G * nt * 4 > M * kKsub * wpr * 4) L.lmin = take(G * nt * 4);
   // unit-claim control words: kept in the dynamic LDS too, so that the LUT
   // starts at LDS address 0 and row addresses fold into instruction offsets
   L.ctl = take(64);  // unit index, class, re-run vote, live vote, unit descriptor, 3 work counters
@@ -469,9 +469,11 @@ __device__ __forceinline__ void lut_mpair(const ScanArgs& a, char* lds, const Sc
   }
 }
 
-// FP32 LUT entries are built by thread (m, j) = (kMPar i + tid / 256, tid % 256)
-// (threads past kMPar * 256 do not take part)
-constexpr int kMPar = kThreads / kKsub;  // subspaces built side by side
+// FP32 LUT entries are built by thread (m, j) = (MPAR i + tid / 256, tid % 256),
+// MPAR = threads / 256 subspaces side by side; the variants specialised for
+// a subspace count (256 threads) keep the codewords of their entries in
+// registers
+constexpr int kMPar = kThreads / kKsub;
 template <int WPR, int MT>
 struct Owned {
   // codewords of the FP32 LUT entries a thread owns
@@ -482,7 +484,7 @@ struct Owned {
 // One work unit (G pairs of one list, lane class LWB; 0 = FP32 LUT): RC, LC,
 // quantisation, DC scan, and the phase's bound or candidate forwarding.
 // L may be the layout of a larger tile (the mixed-class kernel).
-template <int LWB, int MT, int PHASE, int DT, int NR, typename Own, typename Fetch>
+template <int LWB, int MT, int PHASE, int DT, int NR, int NT, typename Own, typename Fetch>
 __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const ScanLds& L, const Own& own,
                                           const int4 unit, Fetch&& fetch_next) {
   constexpr int WPR = variant_wpr(MT, NR);
@@ -491,6 +493,9 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
   constexpr int G = WPR * W;
   constexpr uint32_t MASK = Lane<LWB>::MASK;
   constexpr bool CRES = FP && MT != 0 && MT <= 16;  // FP32 codewords stay in registers
+  constexpr int MPAR = NT / kKsub;  // FP32 LUT: subspaces built side by side
+  static_assert(MT == 0 || NT == kThreads, "the specialised variants run 256-thread workgroups");
+  static_assert(NT % 64 == 0 && (NT & (NT - 1)) == 0, "NT: a power of two number of waves");
   const int M = MT ? MT : a.M;
   // 8-bit entries of more than kWideChunk subspaces (4-bit widths, one width
   // per pair): sums of kWideChunk entries stay in 8-bit lanes and are widened
@@ -504,7 +509,7 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
   uint32_t* psig = reinterpret_cast<uint32_t*>(lds + L.psig);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int own_j = tid % kKsub, own_m0 = tid / kKsub;
-  const bool owner = tid < kMPar * kKsub;
+  const bool owner = tid < MPAR * kKsub;
     const int p = unit.x;
     int np_u = unit.z;
     if (np_u > G) {  // a unit never holds more pairs than the tile (guarded, flagged)
@@ -551,7 +556,7 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
     const bool l1 = a.metric == AMP_L1;
     if (FP || !ip) {
       const int d4 = a.d >> 2;
-      const int gstep = kThreads / d4, tstep = kThreads - gstep * d4;
+      const int gstep = NT / d4, tstep = NT - gstep * d4;
       int g = tid / d4, t4 = tid - g * d4;
       const float4* C4 = reinterpret_cast<const float4*>(a.C + (size_t)p * a.d);
       while (g < np_u) {
@@ -621,7 +626,7 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
       // T[m][j] = (|r_m|^2 + |c_mj|^2) - 2 r_m.c_mj in FP32 (one FMA chain per entry)
       const float* r32 = reinterpret_cast<const float*>(lds + L.ri);
       float* rr32 = reinterpret_cast<float*>(lds + L.rr);
-      for (int e = tid; e < np_u * M; e += kThreads) {
+      for (int e = tid; e < np_u * M; e += NT) {
         const int g = e / M, m = e % M;
         const float* r = r32 + g * a.d + m * a.dsub;
         float sq = 0.f;
@@ -697,10 +702,10 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
         if constexpr (CRES) {
           if (owner) {
 #pragma unroll
-            for (int i = 0; i < MT / kMPar; ++i) entry(mtag, kMPar * i + own_m0, own.c[i]);
+            for (int i = 0; i < MT / MPAR; ++i) entry(mtag, MPAR * i + own_m0, own.c[i]);
           }
         } else if (owner) {
-          for (int m = own_m0; m < M; m += kMPar) {
+          for (int m = own_m0; m < M; m += MPAR) {
             float c[kMaxDsub];
 #pragma unroll
             for (int t = 0; t < kMaxDsub; ++t)
@@ -751,13 +756,13 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
         constexpr bool BY = decltype(by_tag)::value;
         constexpr int EPS = BY ? 16 : 8;  // entries per step
         const int ns = M * kKsub / EPS;
-        for (int eb = tid; eb < ns; eb += U * kThreads) {
+        for (int eb = tid; eb < ns; eb += U * NT) {
           u32x4 xs[U][G];
 #pragma unroll
           for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-              const int es = eb + u * kThreads;
+              const int es = eb + u * NT;
               xs[u][g] = (u32x4){0u, 0u, 0u, 0u};  // absent pairs: zero fields
               if (g < np_u && es < ns)
                 xs[u][g] = *reinterpret_cast<const u32x4*>(
@@ -765,7 +770,7 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
             }
 #pragma unroll
           for (int u = 0; u < U; ++u) {
-            const int es = eb + u * kThreads;
+            const int es = eb + u * NT;
             if (es >= ns) continue;
             uint32_t wds[EPS][WPR];
 #pragma unroll
@@ -803,7 +808,7 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
       int32_t* rr = reinterpret_cast<int32_t*>(lds + L.rr);
       const int16_t* ri = reinterpret_cast<const int16_t*>(lds + L.ri);
       const bool vec8 = a.dsub == 8 && (a.d & 7) == 0;  // 16-byte aligned subspace rows
-      for (int e = tid; e < np_u * M; e += kThreads) {
+      for (int e = tid; e < np_u * M; e += NT) {
         const int g = e / M, m = e % M;
         int32_t sacc = 0;
         if (vec8 && !ip) {
@@ -828,7 +833,7 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
       auto build = [&](auto pass_tag, auto ip_tag) {
         constexpr int PASS = decltype(pass_tag)::value;
         constexpr bool IPM = decltype(ip_tag)::value;
-        for (int mp = wave; mp < M / 2; mp += kThreads / 64) {
+        for (int mp = wave; mp < M / 2; mp += NT / 64) {
           u32x4 Bt[16], Bd[16];
 #pragma unroll
           for (int jt = 0; jt < 16; ++jt) {
@@ -858,7 +863,7 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
         int32_t* lo = reinterpret_cast<int32_t*>(lds + L.lo);
         int32_t* hi = reinterpret_cast<int32_t*>(lds + L.hi);
         if (pass == 1) {
-          for (int e = tid; e < np_u * M; e += kThreads) {
+          for (int e = tid; e < np_u * M; e += NT) {
             const int g = e / M, m = e % M;
             int rv[kMaxDsub];
 #pragma unroll
@@ -877,7 +882,7 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
           }
         } else {
           uint32_t* lut = reinterpret_cast<uint32_t*>(lds + L.lut);
-          for (int e = tid; e < M * kKsub; e += kThreads) {
+          for (int e = tid; e < M * kKsub; e += NT) {
             const int m = e / kKsub, j = e % kKsub;
             int cv[kMaxDsub];
 #pragma unroll
@@ -964,7 +969,7 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
       {
         // lo -> the offset hf(s) - lo that pass 2 adds before the shift
         int32_t* lo = reinterpret_cast<int32_t*>(lds + L.lo);
-        for (int e = tid; e < np_u * M; e += kThreads) {
+        for (int e = tid; e < np_u * M; e += NT) {
           const int g = e / M, sh = ps[g];
           lo[e] = (sh ? (1 << (sh - 1)) : 0) - lo[e];
         }
@@ -983,7 +988,7 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
         __syncthreads();  // the LUT entries are written
         const float* lutf = reinterpret_cast<const float*>(lds + L.lut);
         float* rmin = reinterpret_cast<float*>(lds + L.lo);  // [G][M]
-        for (int m0 = 0; m0 < M; m0 += kThreads / 16) {
+        for (int m0 = 0; m0 < M; m0 += NT / 16) {
           const int m = m0 + (tid >> 4), jb = (tid & 15) * 16;
           float mn[WPR];
 #pragma unroll
@@ -1084,12 +1089,12 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
     if (regc) {
 #pragma unroll
       for (int pv = 0; pv < PV; ++pv) {
-        const int64_t v = v0 + tid + pv * kThreads;
+        const int64_t v = v0 + tid + pv * NT;
         if (v < v1) load_codes(v, cw_next[pv]);
       }
     }
     fetch_next();  // the next unit's descriptor, read while this one scans
-    for (int64_t vb = v0; vb < v1; vb += kThreads * PV) {
+    for (int64_t vb = v0; vb < v1; vb += NT * PV) {
       uint32_t cwg[PV][MQ];
 #pragma unroll
       for (int pv = 0; pv < PV; ++pv)
@@ -1098,13 +1103,13 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
       if (regc) {
 #pragma unroll
         for (int pv = 0; pv < PV; ++pv) {
-          const int64_t vn = vb + tid + (PV + pv) * kThreads;
+          const int64_t vn = vb + tid + (PV + pv) * NT;
           if (vn < v1) load_codes(vn, cw_next[pv]);
         }
       }
 #pragma unroll
       for (int pv = 0; pv < PV; ++pv) {
-      const int64_t v = vb + tid + pv * kThreads;
+      const int64_t v = vb + tid + pv * NT;
       if (v < v1) {
         uint32_t acc[WPR], acc_e[WPR], acc_o[WPR];
         float accf[WPR];
@@ -1237,18 +1242,18 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
     } else if (PHASE == 1) {
       // k > 64: the k-th smallest of the workgroup's per-thread minima
       // (bitonic sort over a power-of-two row, padded with the largest key)
-      constexpr int TP = kThreadsP2;
+      constexpr int TP = NT;
       __syncthreads();  // the LUT space is reused below
       uint32_t* lm = reinterpret_cast<uint32_t*>(lds + L.lmin);
 #pragma unroll
       for (int g = 0; g < G; ++g) {
         lm[g * TP + tid] = lmin[g];
-        if (tid + kThreads < TP) lm[g * TP + kThreads + tid] = 0xFFFFFFFFu;
+        if (tid + NT < TP) lm[g * TP + NT + tid] = 0xFFFFFFFFu;
       }
       __syncthreads();
       for (int size = 2; size <= TP; size <<= 1)
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
-          for (int i = tid; i < G * (TP / 2); i += kThreads) {
+          for (int i = tid; i < G * (TP / 2); i += NT) {
             const int g = i / (TP / 2), ii = i % (TP / 2);
             const int pos = 2 * ii - (ii & (stride - 1));
             const bool asc = (pos & size) == 0;
@@ -1259,7 +1264,7 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
           __syncthreads();
         }
       // the k smallest of each pair's minima to its query's bound buffer
-      for (int i = tid; i < np_u * TP; i += kThreads) {
+      for (int i = tid; i < np_u * TP; i += NT) {
         const int g = i / TP, r = i % TP;
         const int q = pq[g];
         const int kk = a.kq ? a.kq[q] : a.kconst;
@@ -1281,15 +1286,16 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
 // from a device counter; the next unit is claimed while the current one is
 // processed (index at the start, descriptor before the scan, published at
 // the end)
-template <int LWB, int MT, int PHASE, int DT, int NR>
-__global__ __launch_bounds__(kThreads, 2) void k_scan(ScanArgs a) {
+template <int LWB, int MT, int PHASE, int DT, int NR, int NT>
+__global__ __launch_bounds__(NT, 512 / NT) void k_scan(ScanArgs a) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   constexpr int WPR = variant_wpr(MT, NR);
   constexpr bool FP = LWB == 0;
   constexpr int G = WPR * Lane<LWB>::W;
   constexpr bool CRES = FP && MT != 0 && MT <= 16;
+  constexpr int MPAR = NT / kKsub;
   const int M = MT ? MT : a.M;
-  const ScanLds L = scan_lds_layout(G, WPR, M, a.d, FP, PHASE);
+  const ScanLds L = scan_lds_layout(G, WPR, M, a.d, FP, PHASE, NT);
   if (__builtin_amdgcn_groupstaticsize() != 0) {  // the LUT must start at LDS address 0
     if (threadIdx.x == 0) atomicOr(&a.flags[0], 16);
     return;
@@ -1301,15 +1307,15 @@ __global__ __launch_bounds__(kThreads, 2) void k_scan(ScanArgs a) {
   const int64_t ub = a.unitoff[(size_t)a.cls * a.nlist];
   const int64_t ue = a.unitoff[(size_t)(a.cls + 1) * a.nlist];
   const int own_j = tid % kKsub, own_m0 = tid / kKsub;
-  const bool owner = tid < kMPar * kKsub;
+  const bool owner = tid < MPAR * kKsub;
   Owned<WPR, CRES ? MT : 0> own;
   if constexpr (CRES) {
 #pragma unroll
-    for (int i = 0; i < MT / kMPar; ++i)
+    for (int i = 0; i < MT / MPAR; ++i)
 #pragma unroll
       for (int t = 0; t < kMaxDsub; ++t)
         own.c[i][t] = owner && t < a.dsub
-                          ? a.codebook[((size_t)(kMPar * i + own_m0) * kKsub + own_j) * a.dsub + t] : 0.f;
+                          ? a.codebook[((size_t)(MPAR * i + own_m0) * kKsub + own_j) * a.dsub + t] : 0.f;
   }
   UnitQueue uq(a.counter, ue - ub, a.steal);
   if (tid == 0) {
@@ -1325,7 +1331,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_scan(ScanArgs a) {
     int next_u = 0;
     int4 next_unit = make_int4(0, 0, 0, 0);
     if (tid == 0) next_u = (int)uq.next();
-    scan_unit<LWB, MT, PHASE, DT, NR>(a, lds, L, own, s_unit, [&] {
+    scan_unit<LWB, MT, PHASE, DT, NR, NT>(a, lds, L, own, s_unit, [&] {
       if (tid == 0 && ub + next_u < ue) next_unit = a.units[ub + next_u];
     });
     __syncthreads();
@@ -1345,12 +1351,12 @@ __global__ __launch_bounds__(kThreads, 2) void k_scan(ScanArgs a) {
 // the order 32-bit, 16-bit, 8-bit units (each largest list first): the few
 // wide units start early and the many 8-bit units fill the tail.  The LDS
 // tile of the 8-bit class (the most pairs per unit) serves every class.
-template <int MT, int PHASE, int DT, int NR>
-__global__ __launch_bounds__(kThreads, 2) void k_scan_mix(ScanArgs a) {
+template <int MT, int PHASE, int DT, int NR, int NT>
+__global__ __launch_bounds__(NT, 512 / NT) void k_scan_mix(ScanArgs a) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   constexpr int WPR = variant_wpr(MT, NR);
   const int M = MT ? MT : a.M;
-  const ScanLds L = scan_lds_layout(WPR * Lane<8>::W, WPR, M, a.d, false, PHASE);
+  const ScanLds L = scan_lds_layout(WPR * Lane<8>::W, WPR, M, a.d, false, PHASE, NT);
   if (__builtin_amdgcn_groupstaticsize() != 0) {  // the LUT must start at LDS address 0
     if (threadIdx.x == 0) atomicOr(&a.flags[0], 16);
     return;
@@ -1394,9 +1400,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_scan_mix(ScanArgs a) {
       if (tid == 0 && next_u < total) next_unit = a.units[locate(next_u, next_cls)];
     };
     const int cls = s_cls;
-    if (cls == 0) scan_unit<8, MT, PHASE, DT, NR>(a, lds, L, own, s_unit, fetch);
-    else if (cls == 1) scan_unit<16, MT, PHASE, DT, NR>(a, lds, L, own, s_unit, fetch);
-    else scan_unit<32, MT, PHASE, DT, NR>(a, lds, L, own, s_unit, fetch);
+    if (cls == 0) scan_unit<8, MT, PHASE, DT, NR, NT>(a, lds, L, own, s_unit, fetch);
+    else if (cls == 1) scan_unit<16, MT, PHASE, DT, NR, NT>(a, lds, L, own, s_unit, fetch);
+    else scan_unit<32, MT, PHASE, DT, NR, NT>(a, lds, L, own, s_unit, fetch);
     __syncthreads();
     if (tid == 0) {
       s_u = next_u;
@@ -1434,9 +1440,9 @@ inline int scan_nr(int mt, int wpr) { return (wpr == 1 && kernel_wpr(mt) != 1) ?
 typedef void (*ScanFn)(ScanArgs);
 // the kernel of a lane class (lwb 0 = FP32 LUT, 8/16/32) or, with lwb < 0,
 // the mixed-class kernel, for one phase; nullptr if none fits
-ScanFn pick_scan_ph1(int lwb, int M, int dt, int wpr);
-ScanFn pick_scan_ph2(int lwb, int M, int dt, int wpr);
-ScanFn pick_scan_ph3(int lwb, int M, int dt, int wpr);
+ScanFn pick_scan_ph1(int lwb, int M, int dt, int wpr, int nt);
+ScanFn pick_scan_ph2(int lwb, int M, int dt, int wpr, int nt);
+ScanFn pick_scan_ph3(int lwb, int M, int dt, int wpr, int nt);
 
 }  // namespace amp
 
