@@ -494,7 +494,7 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
   constexpr uint32_t MASK = Lane<LWB>::MASK;
   constexpr bool CRES = FP && MT != 0 && MT <= 16;  // FP32 codewords stay in registers
   constexpr int MPAR = NT / kKsub;  // FP32 LUT: subspaces built side by side
-  static_assert(MT == 0 || NT == kThreads, "the specialised variants run 256-thread workgroups");
+  static_assert(!CRES || NT == kThreads, "FP32 codewords in registers: 256-thread workgroups");
   static_assert(NT % 64 == 0 && (NT & (NT - 1)) == 0, "NT: a power of two number of waves");
   const int M = MT ? MT : a.M;
   // 8-bit entries of more than kWideChunk subspaces (4-bit widths, one width
@@ -1115,21 +1115,28 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
         float accf[WPR];
 #pragma unroll
         for (int w = 0; w < WPR; ++w) { acc[w] = 0; acc_e[w] = 0; acc_o[w] = 0; accf[w] = 0.f; }
-        // four subspaces from one code dword
-        auto step4 = [&](uint32_t c4, int m4) {
+        // 4 ND subspaces from ND code dwords: the ND * 4 row reads are issued
+        // before any is added (a scheduling barrier keeps the adds behind
+        // them), then added in subspace order; the 8-bit sums are widened at
+        // every kWideChunk-th subspace (chunks never straddle one)
+        auto stepn = [&](auto nd_tag, const uint32_t* c, int m0) {
+          constexpr int ND = decltype(nd_tag)::value;
+          uint32_t x[4 * ND][WPR];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int rowi = ((m4 + i) * kKsub + ((c4 >> (8 * i)) & 255u)) * WPR;
-            uint32_t x[WPR];
-            lut_row_load<WPR>(lut, rowi, x);
+          for (int k = 0; k < 4 * ND; ++k) {
+            const int rowi = ((m0 + k) * kKsub + ((c[k >> 2] >> (8 * (k & 3))) & 255u)) * WPR;
+            lut_row_load<WPR>(lut, rowi, x[k]);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int k = 0; k < 4 * ND; ++k)
 #pragma unroll
             for (int w = 0; w < WPR; ++w) {
-              if constexpr (FP) accf[w] += __uint_as_float(x[w]);
-              else acc[w] += x[w];
+              if constexpr (FP) accf[w] += __uint_as_float(x[k][w]);
+              else acc[w] += x[k][w];
             }
-          }
           if constexpr (LWB == 8) {
-            if (wide && (((m4 + 4) % kWideChunk) == 0 || m4 + 4 >= M)) {
+            if (wide && (((m0 + 4 * ND) % kWideChunk) == 0 || m0 + 4 * ND >= M)) {
               // widen the chunk's 8-bit sums: fields 0, 2 and 1, 3 into
               // the 16-bit halves of two words
 #pragma unroll
@@ -1141,13 +1148,21 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
             }
           }
         };
+        using One = std::integral_constant<int, 1>;
+        using Two = std::integral_constant<int, 2>;
+        static_assert(kWideChunk % 8 == 0, "two-dword chunks must not straddle a widening point");
         if (regc) {
 #pragma unroll
-          for (int i = 0; i < MQ; ++i)
-            if (MT != 0 || 4 * i < M) step4(cwg[pv][i], 4 * i);
+          for (int i = 0; i < MQ; i += 2) {
+            if (i + 1 < MQ && (MT != 0 || 4 * i + 8 <= M)) stepn(Two{}, &cwg[pv][i], 4 * i);
+            else if (MT != 0 || 4 * i < M) stepn(One{}, &cwg[pv][i], 4 * i);
+          }
         } else {
           const uint32_t* cpg = reinterpret_cast<const uint32_t*>(a.codes + (size_t)(L0 + v) * M);
-          for (int m4 = 0; m4 < M; m4 += 4) step4(cpg[m4 >> 2], m4);
+          for (int m4 = 0; m4 < M; m4 += 4) {
+            const uint32_t c4 = cpg[m4 >> 2];
+            stepn(One{}, &c4, m4);
+          }
         }
         auto emit = [&](int g, uint32_t S) {
           const int q = pq[g];
@@ -1287,13 +1302,14 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
 // processed (index at the start, descriptor before the scan, published at
 // the end)
 template <int LWB, int MT, int PHASE, int DT, int NR, int NT>
-__global__ __launch_bounds__(NT, 512 / NT) void k_scan(ScanArgs a) {
+__global__ __launch_bounds__(NT, 512 / NT) __attribute__((amdgpu_waves_per_eu(NT / 256, NT == 512 ? 2 : 8))) void k_scan(ScanArgs a) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   constexpr int WPR = variant_wpr(MT, NR);
   constexpr bool FP = LWB == 0;
   constexpr int G = WPR * Lane<LWB>::W;
   constexpr bool CRES = FP && MT != 0 && MT <= 16;
   constexpr int MPAR = NT / kKsub;
+  static_assert(!CRES || NT == kThreads, "FP32 codewords in registers: 256-thread workgroups");
   const int M = MT ? MT : a.M;
   const ScanLds L = scan_lds_layout(G, WPR, M, a.d, FP, PHASE, NT);
   if (__builtin_amdgcn_groupstaticsize() != 0) {  // the LUT must start at LDS address 0
@@ -1352,7 +1368,7 @@ __global__ __launch_bounds__(NT, 512 / NT) void k_scan(ScanArgs a) {
 // wide units start early and the many 8-bit units fill the tail.  The LDS
 // tile of the 8-bit class (the most pairs per unit) serves every class.
 template <int MT, int PHASE, int DT, int NR, int NT>
-__global__ __launch_bounds__(NT, 512 / NT) void k_scan_mix(ScanArgs a) {
+__global__ __launch_bounds__(NT, 512 / NT) __attribute__((amdgpu_waves_per_eu(NT / 256, NT == 512 ? 2 : 8))) void k_scan_mix(ScanArgs a) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   constexpr int WPR = variant_wpr(MT, NR);
   const int M = MT ? MT : a.M;
@@ -1425,13 +1441,19 @@ inline int dt_of(int lut_dtype) {
 
 
 // subspace count of the scan variant that runs a lane class (0: generic):
-// registers-resident variants exist for M = 8, 16, 24 with the BF16 LUT build
-// (the FP32 LUT has no LC dtype)
+// variants with straight-line code for their subspace count (codes in
+// registers) exist for M = 8, 16, 24 (every lane class; the FP32 LUT has no
+// LC dtype) and, for the integer lane classes with the BF16 LUT build, for
+// M = 32, 64 (256-thread workgroups) and M = 96, 120, 128 (512-thread
+// workgroups: one workgroup fills a CU's LDS)
 // (wpr: the words per row the queue packed for; a batch too sparse to fill
 // wide rows runs the generic one-word variant, see scan_wpr)
+inline bool scan_mt_wide(int M) { return M == 96 || M == 120 || M == 128; }
 inline int scan_mt(int lwb, int M, int dt) {
   if (lwb != 0 && dt != DT_BF16) return 0;
-  return (M == 8 || M == 16 || M == 24) ? M : 0;
+  if (M == 8 || M == 16 || M == 24) return M;
+  if (lwb != 0 && (M == 32 || M == 64 || scan_mt_wide(M))) return M;
+  return 0;
 }
 // one-word rows on a specialised variant
 inline int scan_nr(int mt, int wpr) { return (wpr == 1 && kernel_wpr(mt) != 1) ? 1 : 0; }

@@ -314,10 +314,11 @@ def test_lut_build_dtypes_are_bit_exact_on_the_e4m3_grid(e4ctx, dtype, bits):
     compare_integer(g, ref)
 
 
-@pytest.mark.parametrize("M,d", [(4, 16), (32, 128), (40, 80)])
-def test_generic_subspace_counts(M, d):
-    """Subspace counts without a specialised scan variant (the generic kernel,
-    one LUT word per row), including d/M = 2 and 4."""
+@pytest.mark.parametrize("M,d", [(4, 16), (32, 128), (40, 80), (64, 128), (128, 256)])
+def test_subspace_counts(M, d):
+    """Subspace counts without a specialised scan variant (4, 40: the generic
+    kernel, one LUT word per row) and with one (32: two-word rows; 64; 128:
+    512-thread workgroups), including d/M = 2 and 4."""
     ctx = _small("aniso", d=d, M=M, nlist=16, n=6000, n_comp=24, nq=24, seed=31 + M)
     for policy, bits in (("fixed", 4), ("fixed", 16), ("fp32", 0)):
         g = _gpu(ctx, 10, 4, policy=policy, bits=bits)
