@@ -1442,17 +1442,17 @@ inline int dt_of(int lut_dtype) {
 
 // subspace count of the scan variant that runs a lane class (0: generic):
 // variants with straight-line code for their subspace count (codes in
-// registers) exist for M = 8, 16, 24 (every lane class; the FP32 LUT has no
-// LC dtype) and, for the integer lane classes with the BF16 LUT build, for
-// M = 32, 64 (256-thread workgroups) and M = 96, 120, 128 (512-thread
-// workgroups: one workgroup fills a CU's LDS)
+// registers) exist for M = 8, 16, 24, 32, 64 (256-thread workgroups) and
+// M = 96, 120, 128 (512-thread workgroups: one workgroup fills a CU's LDS),
+// for the integer lane classes with the BF16 LUT build and for the FP32 LUT
+// (which has no LC dtype)
 // (wpr: the words per row the queue packed for; a batch too sparse to fill
 // wide rows runs the generic one-word variant, see scan_wpr)
 inline bool scan_mt_wide(int M) { return M == 96 || M == 120 || M == 128; }
 inline int scan_mt(int lwb, int M, int dt) {
   if (lwb != 0 && dt != DT_BF16) return 0;
   if (M == 8 || M == 16 || M == 24) return M;
-  if (lwb != 0 && (M == 32 || M == 64 || scan_mt_wide(M))) return M;
+  if (M == 32 || M == 64 || scan_mt_wide(M)) return M;
   return 0;
 }
 // one-word rows on a specialised variant
