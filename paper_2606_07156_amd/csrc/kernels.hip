@@ -507,6 +507,7 @@ __device__ __forceinline__ int pick_bits(int64_t y, const int64_t* theta, uint32
 // support-vector sum, then combine them across their lanes)
 __global__ __launch_bounds__(256) void k_pairs(PairArgs a, ModelArgs ma) {
   __shared__ unsigned long long s_best[256];
+  __shared__ int64_t s_dq2[256];
   __shared__ int32_t s_table[kTableN];
   const int lg = a.lg_npp, lt = a.lg_T, T = 1 << lt;
   const int t = threadIdx.x & (T - 1);
@@ -519,26 +520,28 @@ __global__ __launch_bounds__(256) void k_pairs(PairArgs a, ModelArgs ma) {
   __syncthreads();
   const bool valid = q < a.nq && r < a.npmax;
   const int p = valid ? a.probes[(size_t)q * a.npmax + r] : -1;
-  int64_t dq2 = 0;
-  if (adaptive && p >= 0) {
-    // d' = |grid residual|^2, four coordinates per step (d % 4 == 0)
-    const float4* qv = reinterpret_cast<const float4*>(a.Q + (size_t)q * a.d);
-    const float4* cv = reinterpret_cast<const float4*>(a.C + (size_t)p * a.d);
+  // d' = |grid residual|^2 of pair (qq, pp): the part of lane t of tn
+  // (four coordinates per step, d % 4 == 0)
+  auto dq2_part = [&](int qq, int pp, int t0, int tn) -> int64_t {
+    int64_t s2 = 0;
     const bool l2 = a.metric != AMP_IP;  // L2 and L1: d' of the grid residual
     if (!l2 && a.qi16) {
       // inner product: both sides already on the grid
-      const u32x2* xq = reinterpret_cast<const u32x2*>(a.qi16 + (size_t)q * a.d);
-      const u32x2* xc = reinterpret_cast<const u32x2*>(a.ci16 + (size_t)p * a.d);
-      for (int i = t; i < (a.d >> 2); i += T) {
+      const u32x2* xq = reinterpret_cast<const u32x2*>(a.qi16 + (size_t)qq * a.d);
+      const u32x2* xc = reinterpret_cast<const u32x2*>(a.ci16 + (size_t)pp * a.d);
+      for (int i = t0; i < (a.d >> 2); i += tn) {
         const u32x2 x = xq[i], c = xc[i];
         const int v0 = (int)(int16_t)(x[0] & 0xFFFFu) - (int)(int16_t)(c[0] & 0xFFFFu);
         const int v1 = (int)(int16_t)(x[0] >> 16) - (int)(int16_t)(c[0] >> 16);
         const int v2 = (int)(int16_t)(x[1] & 0xFFFFu) - (int)(int16_t)(c[1] & 0xFFFFu);
         const int v3 = (int)(int16_t)(x[1] >> 16) - (int)(int16_t)(c[1] >> 16);
-        dq2 += (int64_t)(v0 * v0 + v1 * v1) + (int64_t)(v2 * v2 + v3 * v3);
+        s2 += (int64_t)(v0 * v0 + v1 * v1) + (int64_t)(v2 * v2 + v3 * v3);
       }
-    } else
-    for (int i = t; i < (a.d >> 2); i += T) {
+      return s2;
+    }
+    const float4* qv = reinterpret_cast<const float4*>(a.Q + (size_t)qq * a.d);
+    const float4* cv = reinterpret_cast<const float4*>(a.C + (size_t)pp * a.d);
+    for (int i = t0; i < (a.d >> 2); i += tn) {
       const float4 x = qv[i], c = cv[i];
       int v0, v1, v2, v3;
       if (l2) {
@@ -552,8 +555,29 @@ __global__ __launch_bounds__(256) void k_pairs(PairArgs a, ModelArgs ma) {
         v2 = grid_val(x.z, a.grid_e, a.grid_kind) - grid_val(c.z, a.grid_e, a.grid_kind);
         v3 = grid_val(x.w, a.grid_e, a.grid_kind) - grid_val(c.w, a.grid_e, a.grid_kind);
       }
-      dq2 += (int64_t)(v0 * v0 + v1 * v1) + (int64_t)(v2 * v2 + v3 * v3);
+      s2 += (int64_t)(v0 * v0 + v1 * v1) + (int64_t)(v2 * v2 + v3 * v3);
     }
+    return s2;
+  };
+  int64_t dq2 = 0;
+  if (adaptive && T == 1) {
+    // a thread per pair: the rows are read by sixteen lanes per pair, sixteen
+    // pairs of the workgroup at a time (coalesced 128-byte segments), and the
+    // norms handed over through LDS; the thread of a pair slot is its index
+    const int l16 = threadIdx.x & 15, grp = threadIdx.x >> 4;
+    for (int e0 = 0; e0 < 256; e0 += 16) {
+      const int e = e0 + grp;
+      const int qs = blockIdx.x * (256 >> lg) + (e >> lg), rs = e & ((1 << lg) - 1);
+      const int pp = qs < a.nq && rs < a.npmax ? a.probes[(size_t)qs * a.npmax + rs] : -1;
+      int64_t s2 = pp >= 0 ? dq2_part(qs, pp, l16, 16) : 0;
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) s2 += __shfl_xor(s2, o, 16);
+      if (l16 == 0) s_dq2[e] = s2;
+    }
+    __syncthreads();
+    dq2 = s_dq2[threadIdx.x];
+  } else if (adaptive && p >= 0) {
+    dq2 = dq2_part(q, p, t, T);
   }
   // the T threads of a pair are adjacent lanes of one wave (T <= 64)
   for (int o = 1; o < T; o <<= 1) dq2 += __shfl_xor(dq2, o);
@@ -1133,30 +1157,43 @@ __global__ void k_iptab_f32(BaseArgs b) {
 }
 
 // inner product: base of each pair = sum of its query's row minima - qi.ci
-// (a wave per pair, exact integers)
+// (exact integers).  A workgroup per query, sixteen lanes per probed list
+// (sixteen lists per step); the widths the query's pairs use (the tables
+// k_ipq builds) are gathered in the workgroup and set with one atomic.
 __global__ __launch_bounds__(256) void k_ipbase(BaseArgs b) {
-  const int lane = threadIdx.x & 63;
-  const size_t i = (size_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= (size_t)b.nq * b.npmax) return;
-  const int p = b.probes[i];
-  if (p < 0) return;
-  const size_t q = i / b.npmax;
+  __shared__ int s_mask;
+  const size_t q = blockIdx.x;
+  const int tid = threadIdx.x, r = tid & 15, grp = tid >> 4;
+  if (tid == 0) s_mask = 0;
+  __syncthreads();
   const u32x2* qv = reinterpret_cast<const u32x2*>(b.qi16 + q * b.d);
-  const u32x2* cv = reinterpret_cast<const u32x2*>(b.ci16 + (size_t)p * b.d);
-  int acc = 0;
-  for (int t4 = lane; t4 < (b.d >> 2); t4 += 64) {
-    const u32x2 x = qv[t4], c = cv[t4];
-    acc += (int)(int16_t)(x[0] & 0xFFFFu) * (int)(int16_t)(c[0] & 0xFFFFu) +
-           (int)(int16_t)(x[0] >> 16) * (int)(int16_t)(c[0] >> 16) +
-           (int)(int16_t)(x[1] & 0xFFFFu) * (int)(int16_t)(c[1] & 0xFFFFu) +
-           (int)(int16_t)(x[1] >> 16) * (int)(int16_t)(c[1] >> 16);
-  }
+  const int d4 = b.d >> 2;
+  int mask = 0;
+  for (int j0 = 0; j0 < b.npmax; j0 += 16) {
+    const int j = j0 + grp;
+    const size_t i = q * b.npmax + j;
+    const int p = j < b.npmax ? b.probes[i] : -1;
+    int acc = 0;
+    if (p >= 0) {
+      const u32x2* cv = reinterpret_cast<const u32x2*>(b.ci16 + (size_t)p * b.d);
+      for (int t4 = r; t4 < d4; t4 += 16) {
+        const u32x2 x = qv[t4], c = cv[t4];
+        acc += (int)(int16_t)(x[0] & 0xFFFFu) * (int)(int16_t)(c[0] & 0xFFFFu) +
+               (int)(int16_t)(x[0] >> 16) * (int)(int16_t)(c[0] >> 16) +
+               (int)(int16_t)(x[1] & 0xFFFFu) * (int)(int16_t)(c[1] & 0xFFFFu) +
+               (int)(int16_t)(x[1] >> 16) * (int)(int16_t)(c[1] >> 16);
+      }
+    }
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-  if (lane == 0) {
-    b.pbase[i] = b.iplsum[q] - acc;
-    atomicOr(&b.ipmask[q], 1 << ((b.pbits[i] >> 2) - 1));  // the widths the query's tables are needed at
+    for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
+    if (p >= 0 && r == 0) {
+      b.pbase[i] = b.iplsum[q] - acc;
+      mask |= 1 << ((b.pbits[i] >> 2) - 1);
+    }
   }
+  if (mask) atomicOr(&s_mask, mask);
+  __syncthreads();
+  if (tid == 0 && s_mask) atomicOr(&b.ipmask[q], s_mask);
 }
 
 // inner product, FP32 policy: the largest dot product of each (query,
@@ -1227,32 +1264,38 @@ __global__ void k_export_ip(BaseArgs b, uint16_t* exq, int32_t* exs, int64_t* ex
 // width its pairs use: shift s from the query's span (smallest with
 // (span + hf(s)) >> s <= 2^b - 1), entries (T - min_m + hf(s)) >> s as
 // uint16, or as bytes in the first half of the table's slot (width 4 with
-// one width per pair: ip_bytes); eight entries per thread
+// one width per pair: ip_bytes); eight entries per thread, read once and
+// written at every width the query needs
 __global__ void k_ipq(BaseArgs b) {
   const size_t per = (size_t)b.M * kKsub / 8;
-  const size_t n = (size_t)b.nq * 4 * per;
+  const size_t n = (size_t)b.nq * per;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-    const size_t qw = i / per;
-    const int q = (int)(qw >> 2), wi = (int)(qw & 3);
-    if (!(b.ipmask[q] & (1 << wi))) continue;
-    const int bits = 4 * (wi + 1);
-    const int sh = quant_shift(b.ipspan[q], b.gran ? b.M : 1, bits);
-    const int hf = sh ? 1 << (sh - 1) : 0;
-    const size_t e0 = (i - qw * per) * 8;
-    if (e0 == 0) b.ipsh[qw] = sh;
+    const size_t q = i / per;
+    const int mask = b.ipmask[q];
+    if (!mask) continue;
+    const size_t e0 = (i - q * per) * 8;
     const int m = (int)(e0 >> 8);
-    const int off = hf - b.iplo[(size_t)q * b.M + m];
-    const int32_t* T = b.iptab + (size_t)q * b.M * kKsub + e0;
-    uint32_t v[8];
+    const int lo = b.iplo[q * b.M + m];
+    const int32_t* T = b.iptab + q * b.M * kKsub + e0;
+    const u32x4 t0 = *reinterpret_cast<const u32x4*>(T), t1 = *reinterpret_cast<const u32x4*>(T + 4);
+    const int tv[8] = {(int)t0[0], (int)t0[1], (int)t0[2], (int)t0[3], (int)t1[0], (int)t1[1], (int)t1[2], (int)t1[3]};
+    for (int wi = 0; wi < 4; ++wi) {
+      if (!(mask & (1 << wi))) continue;
+      const size_t qw = q * 4 + wi;
+      const int sh = quant_shift(b.ipspan[q], b.gran ? b.M : 1, 4 * (wi + 1));
+      const int off = (sh ? 1 << (sh - 1) : 0) - lo;
+      if (e0 == 0) b.ipsh[qw] = sh;
+      uint32_t v[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) v[k] = (uint32_t)((T[k] + off) >> sh);
-    uint16_t* slot = b.iptq + qw * ((size_t)b.M * kKsub);
-    if (ip_bytes(b.gran, wi, b.M)) {
-      *reinterpret_cast<u32x2*>(reinterpret_cast<uint8_t*>(slot) + e0) =
-          (u32x2){v[0] | (v[1] << 8) | (v[2] << 16) | (v[3] << 24), v[4] | (v[5] << 8) | (v[6] << 16) | (v[7] << 24)};
-    } else {
-      *reinterpret_cast<u32x4*>(slot + e0) =
-          (u32x4){v[0] | (v[1] << 16), v[2] | (v[3] << 16), v[4] | (v[5] << 16), v[6] | (v[7] << 16)};
+      for (int k = 0; k < 8; ++k) v[k] = (uint32_t)((tv[k] + off) >> sh);
+      uint16_t* slot = b.iptq + qw * ((size_t)b.M * kKsub);
+      if (ip_bytes(b.gran, wi, b.M)) {
+        *reinterpret_cast<u32x2*>(reinterpret_cast<uint8_t*>(slot) + e0) =
+            (u32x2){v[0] | (v[1] << 8) | (v[2] << 16) | (v[3] << 24), v[4] | (v[5] << 8) | (v[6] << 16) | (v[7] << 24)};
+      } else {
+        *reinterpret_cast<u32x4*>(slot + e0) =
+            (u32x4){v[0] | (v[1] << 16), v[2] | (v[3] << 16), v[4] | (v[5] << 16), v[6] | (v[7] << 16)};
+      }
     }
   }
 }
@@ -1540,8 +1583,8 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
       if ((err = hipFuncSetAttribute(kaddr(fn), hipFuncAttributeMaxDynamicSharedMemorySize, (int)tlds)) != hipSuccess)
         return err;
       hipLaunchKernelGGL(fn, dim3((sd.nq + kTabQ - 1) / kTabQ), dim3(kThreads), tlds, st, ba);
-      hipLaunchKernelGGL(k_ipbase, dim3((unsigned)((npairs + 3) / 4)), dim3(256), 0, st, ba);
-      const size_t nq8 = (size_t)sd.nq * 4 * sd.M * kKsub / 8;
+      hipLaunchKernelGGL(k_ipbase, dim3((unsigned)sd.nq), dim3(256), 0, st, ba);
+      const size_t nq8 = (size_t)sd.nq * sd.M * kKsub / 8;
       hipLaunchKernelGGL(k_ipq, dim3((unsigned)std::min<size_t>((nq8 + 255) / 256, 1 << 20)), dim3(256), 0, st, ba);
     } else if (early) {
       // L2 / L1: every pair's LUT minima, as many pairs per workgroup as
