@@ -38,8 +38,9 @@ constexpr int kWideChunk = 16;
 constexpr int kRegMQ = 32;
 // lane-width class of a b-bit LUT for M subspaces: the sum of M entries of at
 // most 2^b - 1 must fit in the lane; 4-bit widths with one width per pair
-// (entries at most 15) keep 8-bit entries for any M, their sums widened every
-// kWideChunk subspaces (up to M = 2184: sums below 2^15)
+// (entries at most 15) are class 0 for any M, their 4-bit entries summed in
+// 8-bit lanes that are widened every kWideChunk subspaces (up to M = 2184:
+// sums below 2^15)
 inline int lane_class(int M, int b, int gran = 0) {
   if (b == 4 && gran == 0 && M <= 2184) return 0;
   uint64_t top = (uint64_t)M * ((1ull << b) - 1);
@@ -47,7 +48,9 @@ inline int lane_class(int M, int b, int gran = 0) {
   if (top <= 0xFFFFull) return 1;
   return 2;
 }
-inline int lane_bits(int cls) { return 8 << cls; }
+// lane bits of a class: class 0 holds 4-bit entries with one width per pair
+// (width-4 pairs only), 8-bit ones with per-subspace widths
+inline int lane_bits(int cls, int gran) { return cls == 0 && gran == 0 ? 4 : 8 << cls; }
 
 // -------------------------------------------------------------- device data
 struct DeviceModel {

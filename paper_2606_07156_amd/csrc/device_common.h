@@ -62,9 +62,15 @@ __device__ __forceinline__ int quant_shift(int64_t R, int n, int b) {
   return sh;
 }
 
+// byte permute: byte i of the result is byte sel_i of the 8-byte value
+// (hi : lo), sel_i in 0..7 (0..3: bytes of lo, 4..7: bytes of hi)
+__device__ __forceinline__ uint32_t byte_perm(uint32_t hi, uint32_t lo, uint32_t sel) {
+  return __builtin_amdgcn_perm(hi, lo, sel);
+}
+
 // an inner-product query table of width index wi (width 4 (wi + 1)) is kept
 // as bytes for width 4 with one width per pair (entries at most 15; the
-// pairs of the 8-bit lane class are exactly these); per-subspace widths bound
+// pairs of the 4-bit lane class are exactly these); per-subspace widths bound
 // only the sum of a row, so their tables stay uint16
 __host__ __device__ __forceinline__ bool ip_bytes(int gran, int wi, int M) { return gran == 0 && wi == 0 && M <= 2184; }
 

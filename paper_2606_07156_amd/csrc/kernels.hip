@@ -692,12 +692,13 @@ __device__ __forceinline__ bool pair_live(const QueueArgs& a, size_t i) {
 
 __device__ __forceinline__ int pair_class(int bits, int M, int gran) {
   if (bits == 32) return 0;
-  if (bits == 4 && gran == 0 && M <= 2184) return 0;  // 8-bit entries, sums widened (lane_class)
+  if (bits == 4 && gran == 0 && M <= 2184) return 0;  // 4-bit entries, sums widened (lane_class)
   uint64_t top = (uint64_t)M * ((1ull << bits) - 1);
   return top <= 0xFFull ? 0 : (top <= 0xFFFFull ? 1 : 2);
 }
-__device__ __forceinline__ int class_pairs(int cls, int wpr, bool fp32) {
-  return fp32 ? wpr : wpr * (4 >> cls);
+// pairs of a work unit: WPR LUT words of 32 / lane_bits(class) fields
+__device__ __forceinline__ int class_pairs(int cls, int wpr, bool fp32, int gran) {
+  return fp32 ? wpr : (cls == 0 && !gran ? unit_pairs(4, wpr) : wpr * (4 >> cls));
 }
 
 // sub-counter of a pair: the pairs of a much-probed list spread over kQSub
@@ -763,7 +764,7 @@ __global__ void k_qtot(QueueArgs a, int fp32) {
   for (int u = 0; u < kQSub; ++u) cnt[(size_t)u * NB + b] = x[u];
   const int64_t n = a.offsets[p + 1] - a.offsets[p];
   const int64_t nch = (n + a.chunk[ph] - 1) / a.chunk[ph];
-  const int G = class_pairs(cls, a.wpr, fp32);
+  const int G = class_pairs(cls, a.wpr, fp32, a.gran);
   const int pos = cls * a.nlist + a.lpos[p];
   a.pairoff[(size_t)ph * (NB + 1) + pos] = c;
   a.unitoff[(size_t)ph * (NB + 1) + pos] = ((c + G - 1) / G) * nch;
@@ -864,7 +865,7 @@ __global__ void k_qunits(QueueArgs a, int fp32) {
       const int b = lo, cls = b / a.nlist, p = a.lorder[b % a.nlist];
       const int64_t n = a.offsets[p + 1] - a.offsets[p];
       const int64_t nch = (n + a.chunk[ph] - 1) / a.chunk[ph];
-      const int G = class_pairs(cls, a.wpr, fp32);
+      const int G = class_pairs(cls, a.wpr, fp32, a.gran);
       const int64_t local = u - uo[b], grp = local / nch, ch = local % nch;
       const int64_t left = (po[b + 1] - po[b]) - grp * G;
       units[u] = make_int4(p, (int)(po[b] + grp * G), (int)(left < G ? left : G), (int)ch);
@@ -1320,10 +1321,12 @@ hipError_t launch_prep_index(const amp_index* ix, hipStream_t st) {
   return hipGetLastError();
 }
 
+// dynamic LDS of a scan launch (lw_bits -1: the mixed-class kernel), the
+// layout the kernel computes for itself
 static size_t scan_lds_bytes(int lw_bits, int phase, int M, int d, int wpr, int nt) {
   const bool fp = lw_bits == 0;
-  const int G = fp ? wpr : wpr * (32 / lw_bits);
-  return (size_t)scan_lds_layout(G, wpr, M, d, fp, phase, nt).total;
+  const int cw = lw_bits < 0 ? wpr : class_wpr(lw_bits, wpr);
+  return (size_t)scan_lds_layout(unit_pairs(lw_bits, wpr), cw, M, d, fp, phase, nt).total;
 }
 
 int scan_wpr(int M, bool fp32, int lut_dtype, bool narrow) {
@@ -1348,7 +1351,7 @@ static hipError_t launch_scan(int lwb, int ph, int dt, int wpr, const ScanArgs& 
   // the queue packed units for `wpr` words per row: the variant must agree
   const int mt = scan_mt(mix ? 8 : lwb, sa.M, dt);
   if (!fn || variant_wpr(mt, scan_nr(mt, wpr)) != wpr) return hipErrorInvalidValue;
-  size_t lds = scan_lds_bytes(mix ? 8 : lwb, ph, sa.M, sa.d, wpr, nt);
+  size_t lds = scan_lds_bytes(lwb, ph, sa.M, sa.d, wpr, nt);
   hipError_t e = hipFuncSetAttribute(kaddr(fn), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   int per_cu = 0;
@@ -1362,7 +1365,7 @@ static hipError_t launch_scan(int lwb, int ph, int dt, int wpr, const ScanArgs& 
   if (per_cu == 1 && wg512) {
     ScanFn f2 = pick(2 * kThreads);
     if (f2) {
-      const size_t l2 = scan_lds_bytes(mix ? 8 : lwb, ph, sa.M, sa.d, wpr, 2 * kThreads);
+      const size_t l2 = scan_lds_bytes(lwb, ph, sa.M, sa.d, wpr, 2 * kThreads);
       int pc2 = 0;
       if ((e = hipFuncSetAttribute(kaddr(f2), hipFuncAttributeMaxDynamicSharedMemorySize, (int)l2)) != hipSuccess)
         return e;
@@ -1708,7 +1711,7 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
       const int c = fp32 ? 0 : lane_class(sd.M, sd.fixed_bits, sd.gran);
       sa.cls = c;
       sa.counter = ws.counters + ((ph - 1) * (kNCls + 1) + c) * kQueueSlot;
-      sa_lwb = fp32 ? 0 : lane_bits(c);
+      sa_lwb = fp32 ? 0 : lane_bits(c, sd.gran);
     } else {
       sa.cls = -1;
       sa.counter = ws.counters + ((ph - 1) * (kNCls + 1) + kNCls) * kQueueSlot;

@@ -91,6 +91,16 @@ __host__ __device__ constexpr int kernel_wpr(int MT) { return MT ? wpr_for(MT) :
 // a variant specialised for MT may also run with one-word rows (NR = 1:
 // sparse batches, a few pairs per list), keeping its codes in registers
 __host__ __device__ constexpr int variant_wpr(int MT, int NR) { return NR ? 1 : kernel_wpr(MT); }
+// the 4-bit class (eight pairs per word) packs at most two words per row:
+// sixteen pairs per unit, as the 8-bit class at four words
+__host__ __device__ constexpr int nib_wpr(int wpr) { return wpr > 2 ? 2 : wpr; }
+// words per row and pairs per unit of a lane class (lwb 0: FP32 LUT; -1: the
+// mixed-class kernel, whose tile takes the most pairs of any class)
+__host__ __device__ constexpr int class_wpr(int lwb, int wpr) { return lwb == 4 ? nib_wpr(wpr) : wpr; }
+__host__ __device__ constexpr int unit_pairs(int lwb, int wpr) {
+  return lwb < 0 ? (nib_wpr(wpr) * 8 > wpr * 4 ? nib_wpr(wpr) * 8 : wpr * 4)
+                 : (lwb == 0 ? wpr : class_wpr(lwb, wpr) * (32 / lwb));
+}
 
 // row stride (int16 elements) of the integer residuals in LDS: each row is
 // padded by 32 bytes, so the eight rows that the LC A-operand build reads at
@@ -127,7 +137,7 @@ __host__ __device__ inline ScanLds scan_lds_layout(int G, int wpr, int M, int d,
   return L;
 }
 
-template <int LWB>  // lane bits 8/16/32, 0 = FP32 LUT
+template <int LWB>  // lane bits 4/8/16/32, 0 = FP32 LUT
 struct Lane {
   static constexpr int W = LWB ? 32 / LWB : 1;
   static constexpr uint32_t MASK = LWB == 32 || LWB == 0 ? 0xFFFFFFFFu : ((1u << LWB) - 1);
@@ -136,17 +146,37 @@ struct Lane {
 // where pair g of a work unit sits in a LUT row: word and field.  The 8-bit
 // class with four words per row interleaves the pairs (word 2 h + t holds
 // pairs 8 t + 4 h + 0..3) so that a lane of the LUT build writes its two
-// words with one 8-byte store; every other layout is word g / W, field g % W.
+// words with one 8-byte store.  The 4-bit class keeps pairs 8 w + 0..3 in
+// the low nibbles of word w's bytes and pairs 8 w + 4..7 in the high ones
+// (field 2 i: pair 8 w + i, field 2 i + 1: pair 8 w + 4 + i), so that one
+// mask and one shift split a word into two words of 8-bit lanes, each in
+// pair order.  Every other layout is word g / W, field g % W.
 template <int LWB, int WPR>
 struct PairSlot {
   static constexpr bool IL = LWB == 8 && WPR == 4;
+  static constexpr bool NB = LWB == 4;
   static constexpr int W = Lane<LWB>::W;
   __host__ __device__ static constexpr int word(int g) { return IL ? (((g >> 2) & 1) << 1) | (g >> 3) : g / W; }
-  __host__ __device__ static constexpr int field(int g) { return IL ? (g & 3) : g % W; }
+  __host__ __device__ static constexpr int field(int g) {
+    return IL ? (g & 3) : (NB ? (((g & 3) << 1) | ((g >> 2) & 1)) : g % W);
+  }
   __host__ __device__ static constexpr int pair(int w, int f) {
-    return IL ? ((w & 1) << 3) | ((w >> 1) << 2) | f : w * W + f;
+    return IL ? ((w & 1) << 3) | ((w >> 1) << 2) | f : (NB ? w * 8 + ((f & 1) << 2) + (f >> 1) : w * W + f);
   }
 };
+
+// where the scan holds pair g's sum (phases 2, 3 test four or eight sums at
+// once): the test word (8-bit class: fields 0, 2 / 1, 3 of a LUT word's
+// lanes; 4-bit class: the four words of widened sums, pairs 0, 2 / 1, 3 of
+// the low nibbles, then 4, 6 / 5, 7 of the high ones) and its 16-bit half
+template <int LWB, int WPR>
+__host__ __device__ constexpr int test_word(int g) {
+  return LWB == 4 ? ((((g & 7) >> 2) << 1) | (g & 1)) : (PairSlot<LWB, WPR>::field(g) & 1);
+}
+template <int LWB, int WPR>
+__host__ __device__ constexpr int test_half(int g) {
+  return LWB == 4 ? ((g & 3) >> 1) : (PairSlot<LWB, WPR>::field(g) >> 1);
+}
 
 // LDS-address-space views: the scan kernels declare no static LDS, so their
 // dynamic block (the LUT first) starts at LDS address 0 and a row address is
@@ -428,7 +458,18 @@ __device__ __forceinline__ void lut_mpair(const ScanArgs& a, char* lds, const Sc
           continue;
         }
         uint32_t* dst = lut + (size_t)(m_out * kKsub + j) * WPR;
-        if constexpr (PairSlot<LWB, WPR>::IL) {
+        if constexpr (LWB == 4) {
+          // pairs g0 .. g0 + 3 of word gt: low nibbles of its bytes (kg
+          // even, g0 = 8 gt) or high nibbles (kg odd); the two halves meet
+          // across lanes 16 apart and the even lane stores the row's words
+          const uint32_t h = (qv[0] | (qv[1] << 8) | (qv[2] << 16) | (qv[3] << 24)) << (4 * (kg & 1));
+          wv8[gt] = h | (uint32_t)__shfl_xor((int)h, 16);
+          if (gt == NGT - 1 && (kg & 1) == 0) {
+            if constexpr (WPR == 4) *reinterpret_cast<u32x4*>(dst) = (u32x4){wv8[0], wv8[1], wv8[2], wv8[3]};
+            else if constexpr (WPR == 2) *reinterpret_cast<u32x2*>(dst) = (u32x2){wv8[0], wv8[1]};
+            else dst[0] = wv8[0];
+          }
+        } else if constexpr (PairSlot<LWB, WPR>::IL) {
           wv8[gt] = qv[0] | (qv[1] << 8) | (qv[2] << 16) | (qv[3] << 24);
           if (gt == NGT - 1)  // words 2 h, 2 h + 1 (h = kg & 1): one 8-byte store
             *reinterpret_cast<u32x2*>(dst + 2 * (kg & 1)) = (u32x2){wv8[0], wv8[1]};
@@ -487,7 +528,7 @@ struct Owned {
 template <int LWB, int MT, int PHASE, int DT, int NR, int NT, typename Own, typename Fetch>
 __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const ScanLds& L, const Own& own,
                                           const int4 unit, Fetch&& fetch_next) {
-  constexpr int WPR = variant_wpr(MT, NR);
+  constexpr int WPR = class_wpr(LWB, variant_wpr(MT, NR));
   constexpr bool FP = LWB == 0;
   constexpr int W = Lane<LWB>::W;
   constexpr int G = WPR * W;
@@ -497,11 +538,12 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
   static_assert(!CRES || NT == kThreads, "FP32 codewords in registers: 256-thread workgroups");
   static_assert(NT % 64 == 0 && (NT & (NT - 1)) == 0, "NT: a power of two number of waves");
   const int M = MT ? MT : a.M;
-  // 8-bit entries of more than kWideChunk subspaces (4-bit widths, one width
-  // per pair): sums of kWideChunk entries stay in 8-bit lanes and are widened
-  // into 16-bit lanes (at most 2^15 - 1, guard bit 15) between chunks
-  const bool wide = LWB == 8 && M > kWideChunk;
-  const uint32_t SMASK = wide ? 0x7FFFu : MASK;
+  // 4-bit entries (width 4, one width per pair): a word's low and high
+  // nibbles are added into the 8-bit lanes of two words, whose sums of
+  // kWideChunk subspaces are widened into 16-bit lanes (at most 2^15 - 1,
+  // guard bit 15) between chunks
+  constexpr bool NIB = LWB == 4;
+  const uint32_t SMASK = NIB ? 0x7FFFu : MASK;
   int32_t* pq = reinterpret_cast<int32_t*>(lds + L.pq);
   int32_t* pb = reinterpret_cast<int32_t*>(lds + L.pb);
   int32_t* ps = reinterpret_cast<int32_t*>(lds + L.ps);
@@ -773,19 +815,55 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
             const int es = eb + u * NT;
             if (es >= ns) continue;
             uint32_t wds[EPS][WPR];
+            if constexpr (BY && LWB == 4) {
+              // byte entries (at most 15) of the word's eight pairs: for each
+              // four entries, pairs 8 w + 0..3 and 8 w + 4..7 are two 4 x 4
+              // byte transposes (eight byte permutes each), the second moved
+              // into the high nibbles
 #pragma unroll
-            for (int k = 0; k < EPS; ++k)
+              for (int w = 0; w < WPR; ++w)
 #pragma unroll
-              for (int w = 0; w < WPR; ++w) {
-                uint32_t wd = 0;
+                for (int j = 0; j < 4; ++j) {
+                  uint32_t t4[2][4];
 #pragma unroll
-                for (int f = 0; f < W; ++f) {
-                  const u32x4 x = xs[u][PairSlot<LWB, WPR>::pair(w, f)];
-                  const uint32_t qv = BY ? (x[k >> 2] >> (8 * (k & 3))) & 0xFFu : (x[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
-                  wd |= LWB == 32 ? qv : (qv << (f * LWB));
+                  for (int h = 0; h < 2; ++h) {
+                    const uint32_t pa = xs[u][8 * w + 4 * h + 0][j], pb2 = xs[u][8 * w + 4 * h + 1][j];
+                    const uint32_t pc = xs[u][8 * w + 4 * h + 2][j], pd = xs[u][8 * w + 4 * h + 3][j];
+                    const uint32_t ab0 = byte_perm(pb2, pa, 0x05010400u), ab1 = byte_perm(pb2, pa, 0x07030602u);
+                    const uint32_t cd0 = byte_perm(pd, pc, 0x05010400u), cd1 = byte_perm(pd, pc, 0x07030602u);
+                    t4[h][0] = byte_perm(cd0, ab0, 0x05040100u);
+                    t4[h][1] = byte_perm(cd0, ab0, 0x07060302u);
+                    t4[h][2] = byte_perm(cd1, ab1, 0x05040100u);
+                    t4[h][3] = byte_perm(cd1, ab1, 0x07060302u);
+                  }
+#pragma unroll
+                  for (int i = 0; i < 4; ++i) wds[4 * j + i][w] = t4[0][i] | (t4[1][i] << 4);
                 }
-                wds[k][w] = wd;
-              }
+            } else if constexpr (!BY && LWB == 16) {
+              // uint16 entries of two pairs: one byte permute per word
+#pragma unroll
+              for (int w = 0; w < WPR; ++w)
+#pragma unroll
+                for (int k = 0; k < EPS; ++k)
+                  wds[k][w] = byte_perm(xs[u][PairSlot<LWB, WPR>::pair(w, 1)][k >> 1],
+                                        xs[u][PairSlot<LWB, WPR>::pair(w, 0)][k >> 1],
+                                        (k & 1) ? 0x07060302u : 0x05040100u);
+            } else {
+#pragma unroll
+              for (int k = 0; k < EPS; ++k)
+#pragma unroll
+                for (int w = 0; w < WPR; ++w) {
+                  uint32_t wd = 0;
+#pragma unroll
+                  for (int f = 0; f < W; ++f) {
+                    const u32x4 x = xs[u][PairSlot<LWB, WPR>::pair(w, f)];
+                    const uint32_t qv =
+                        BY ? (x[k >> 2] >> (8 * (k & 3))) & 0xFFu : (x[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
+                    wd |= LWB == 32 ? qv : (qv << (f * LWB));
+                  }
+                  wds[k][w] = wd;
+                }
+            }
 #pragma unroll
             for (int k = 0; k < EPS; ++k) {
               uint32_t* dst = lut + ((size_t)es * EPS + k) * WPR;
@@ -795,14 +873,10 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
           }
         }
       };
-      // the 8-bit lane class of one width per pair holds width-4 pairs only,
+      // the 4-bit lane class holds width-4 pairs of one width per pair only,
       // whose tables are bytes (ip_bytes); every other table is uint16
-      if constexpr (LWB == 8) {
-        if (ip_bytes(a.gran, 0, M)) copy(std::true_type{});
-        else copy(std::false_type{});
-      } else {
-        copy(std::false_type{});
-      }
+      if constexpr (LWB == 4) copy(std::true_type{});
+      else copy(std::false_type{});
       __syncthreads();
     } else {
       int32_t* rr = reinterpret_cast<int32_t*>(lds + L.rr);
@@ -1044,24 +1118,25 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
     uint32_t lmin[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) lmin[g] = 0xFFFFFFFFu;
-    // packed thresholds of the 8-bit lane class: fields 0,2 and 1,3 of each
-    // word in 16-bit halves with guard bit 8; dead pairs never hit
-    // (wide: 15-bit sums in 16-bit halves, guard bit 15)
-    uint32_t sig_e[WPR], sig_o[WPR], msk_e[WPR], msk_o[WPR];
-    if constexpr (PHASE >= 2 && LWB == 8) {
-      const uint32_t top = wide ? 0x7FFFu : 255u, guard = wide ? 0x8000u : 0x100u;
+    // packed thresholds (phases 2, 3) of the 4- and 8-bit lane classes: the
+    // sums of a LUT word's pairs sit in the 16-bit halves of NTW test words
+    // (8-bit: fields 0, 2 and 1, 3 with guard bit 8; 4-bit: the widened
+    // sums, guard bit 15); a sum passes iff (sigma | guard) - sum keeps the
+    // guard bit, and dead pairs have no guard bit in the mask (never hit)
+    constexpr int NTW = NIB ? 4 : 2;
+    uint32_t sigw[WPR][NTW], mskw[WPR][NTW];
+    if constexpr (PHASE >= 2 && (LWB == 8 || NIB)) {
+      const uint32_t top = NIB ? 0x7FFFu : 255u, guard = NIB ? 0x8000u : 0x100u;
 #pragma unroll
-      for (int w = 0; w < WPR; ++w) {
-        uint32_t se = 0, so = 0, me = 0, mo = 0;
+      for (int w = 0; w < WPR; ++w)
 #pragma unroll
-        for (int f = 0; f < 4; ++f) {
-          const int g = PairSlot<LWB, WPR>::pair(w, f);
-          const uint32_t sg = live[g] ? (sig[g] > top ? top : sig[g]) : top;
-          const uint32_t gb = live[g] ? guard : 0u;
-          if (f & 1) { so |= (sg | guard) << (16 * (f >> 1)); mo |= gb << (16 * (f >> 1)); }
-          else { se |= (sg | guard) << (16 * (f >> 1)); me |= gb << (16 * (f >> 1)); }
-        }
-        sig_e[w] = se; sig_o[w] = so; msk_e[w] = me; msk_o[w] = mo;
+        for (int t = 0; t < NTW; ++t) sigw[w][t] = mskw[w][t] = 0;
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int w = PairSlot<LWB, WPR>::word(g), t = test_word<LWB, WPR>(g), h = test_half<LWB, WPR>(g);
+        const uint32_t sg = live[g] ? (sig[g] > top ? top : sig[g]) : top;
+        sigw[w][t] |= (sg | guard) << (16 * h);
+        mskw[w][t] |= (live[g] ? guard : 0u) << (16 * h);
       }
     }
     lds_u32* lut = reinterpret_cast<lds_u32*>((uintptr_t)L.lut);  // LDS address (see lds_u32)
@@ -1111,10 +1186,18 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
       for (int pv = 0; pv < PV; ++pv) {
       const int64_t v = vb + tid + pv * NT;
       if (v < v1) {
-        uint32_t acc[WPR], acc_e[WPR], acc_o[WPR];
+        // acc: the lanes of each LUT word (4-bit class: the low nibbles, with
+        // the high ones in accb), wz: the 4-bit class's widened sums
+        uint32_t acc[WPR], accb[WPR], wz[WPR][4];
         float accf[WPR];
 #pragma unroll
-        for (int w = 0; w < WPR; ++w) { acc[w] = 0; acc_e[w] = 0; acc_o[w] = 0; accf[w] = 0.f; }
+        for (int w = 0; w < WPR; ++w) {
+          acc[w] = 0;
+          accb[w] = 0;
+          accf[w] = 0.f;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) wz[w][t] = 0;
+        }
         // 4 ND subspaces from ND code dwords: the ND * 4 row reads are issued
         // before any is added (a scheduling barrier keeps the adds behind
         // them), then added in subspace order; the 8-bit sums are widened at
@@ -1132,18 +1215,27 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
           for (int k = 0; k < 4 * ND; ++k)
 #pragma unroll
             for (int w = 0; w < WPR; ++w) {
-              if constexpr (FP) accf[w] += __uint_as_float(x[k][w]);
-              else acc[w] += x[k][w];
+              if constexpr (FP) {
+                accf[w] += __uint_as_float(x[k][w]);
+              } else if constexpr (NIB) {
+                acc[w] += x[k][w] & 0x0F0F0F0Fu;
+                accb[w] += (x[k][w] >> 4) & 0x0F0F0F0Fu;
+              } else {
+                acc[w] += x[k][w];
+              }
             }
-          if constexpr (LWB == 8) {
-            if (wide && (((m0 + 4 * ND) % kWideChunk) == 0 || m0 + 4 * ND >= M)) {
-              // widen the chunk's 8-bit sums: fields 0, 2 and 1, 3 into
-              // the 16-bit halves of two words
+          if constexpr (NIB) {
+            if (((m0 + 4 * ND) % kWideChunk) == 0 || m0 + 4 * ND >= M) {
+              // widen the chunk's 8-bit sums: bytes 0, 2 and 1, 3 of the
+              // low- and high-nibble words into the 16-bit halves of four
 #pragma unroll
               for (int w = 0; w < WPR; ++w) {
-                acc_e[w] += acc[w] & 0x00FF00FFu;
-                acc_o[w] += (acc[w] >> 8) & 0x00FF00FFu;
+                wz[w][0] += acc[w] & 0x00FF00FFu;
+                wz[w][1] += (acc[w] >> 8) & 0x00FF00FFu;
+                wz[w][2] += accb[w] & 0x00FF00FFu;
+                wz[w][3] += (accb[w] >> 8) & 0x00FF00FFu;
                 acc[w] = 0;
+                accb[w] = 0;
               }
             }
           }
@@ -1178,21 +1270,26 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
             a.cid[(size_t)q * a.capq + pos] = id;
           }
         };
-        if constexpr (PHASE >= 2 && LWB == 8) {
-          // four 8-bit sums per word: test all four against their thresholds
-          // at once in two 16-bit-lane halves (guard bit 8 survives iff S <= sigma;
-          // wide: the widened sums, guard bit 15)
+        // the test word t of LUT word w (8-bit: fields 0, 2 / 1, 3; 4-bit:
+        // the widened sums)
+        auto tword = [&](int w, int t) -> uint32_t {
+          if constexpr (NIB) return wz[w][t];
+          else return t ? (acc[w] >> 8) & 0x00FF00FFu : acc[w] & 0x00FF00FFu;
+        };
+        if constexpr (PHASE >= 2 && (LWB == 8 || NIB)) {
+          // every sum of a LUT word tested against its threshold at once, in
+          // the 16-bit halves of its test words
 #pragma unroll
           for (int w = 0; w < WPR; ++w) {
-            const uint32_t e = wide ? acc_e[w] : acc[w] & 0x00FF00FFu;
-            const uint32_t o = wide ? acc_o[w] : (acc[w] >> 8) & 0x00FF00FFu;
-            const uint32_t hit = ((sig_e[w] - e) & msk_e[w]) | ((sig_o[w] - o) & msk_o[w]);
+            uint32_t hit = 0;
+#pragma unroll
+            for (int t = 0; t < NTW; ++t) hit |= (sigw[w][t] - tword(w, t)) & mskw[w][t];
             if (hit) {
 #pragma unroll
-              for (int f = 0; f < 4; ++f) {
+              for (int f = 0; f < W; ++f) {
                 // rare path: thresholds from LDS, not held in registers
-                const uint32_t S = ((f & 1) ? o : e) >> (16 * (f >> 1)) & 0xFFFFu;
                 const int g = PairSlot<LWB, WPR>::pair(w, f);
+                const uint32_t S = (tword(w, test_word<LWB, WPR>(g)) >> (16 * test_half<LWB, WPR>(g))) & 0xFFFFu;
                 if (pb[g] >= 0 && S <= psig[g]) emit(g, S);
               }
             }
@@ -1203,7 +1300,7 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
             const int w = PairSlot<LWB, WPR>::word(g), f = PairSlot<LWB, WPR>::field(g);
             uint32_t S;
             if constexpr (FP) S = fkey(accf[w]);
-            else if (LWB == 8 && wide) S = ((f & 1) ? acc_o[w] : acc_e[w]) >> (16 * (f >> 1)) & 0xFFFFu;
+            else if constexpr (NIB) S = (wz[w][test_word<LWB, WPR>(g)] >> (16 * test_half<LWB, WPR>(g))) & 0xFFFFu;
             else S = LWB == 32 ? acc[w] : ((acc[w] >> (f * LWB)) & MASK);
             if (PHASE == 1) {
               lmin[g] = S < lmin[g] ? S : lmin[g];
@@ -1304,7 +1401,7 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
 template <int LWB, int MT, int PHASE, int DT, int NR, int NT>
 __global__ __launch_bounds__(NT, 512 / NT) __attribute__((amdgpu_waves_per_eu(NT / 256, NT == 512 ? 2 : 8))) void k_scan(ScanArgs a) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
-  constexpr int WPR = variant_wpr(MT, NR);
+  constexpr int WPR = class_wpr(LWB, variant_wpr(MT, NR));
   constexpr bool FP = LWB == 0;
   constexpr int G = WPR * Lane<LWB>::W;
   constexpr bool CRES = FP && MT != 0 && MT <= 16;
@@ -1364,15 +1461,16 @@ __global__ __launch_bounds__(NT, 512 / NT) __attribute__((amdgpu_waves_per_eu(NT
 }
 
 // all three lane classes of an integer policy in one persistent launch, in
-// the order 32-bit, 16-bit, 8-bit units (each largest list first): the few
-// wide units start early and the many 8-bit units fill the tail.  The LDS
-// tile of the 8-bit class (the most pairs per unit) serves every class.
+// the order 32-bit, 16-bit, then 4-bit (one width per pair) or 8-bit units
+// (each largest list first): the few wide units start early and the many
+// narrow units fill the tail.  The LDS tile of the 4-bit class (the most
+// pairs per unit) serves every class.
 template <int MT, int PHASE, int DT, int NR, int NT>
 __global__ __launch_bounds__(NT, 512 / NT) __attribute__((amdgpu_waves_per_eu(NT / 256, NT == 512 ? 2 : 8))) void k_scan_mix(ScanArgs a) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   constexpr int WPR = variant_wpr(MT, NR);
   const int M = MT ? MT : a.M;
-  const ScanLds L = scan_lds_layout(WPR * Lane<8>::W, WPR, M, a.d, false, PHASE, NT);
+  const ScanLds L = scan_lds_layout(unit_pairs(-1, WPR), WPR, M, a.d, false, PHASE, NT);
   if (__builtin_amdgcn_groupstaticsize() != 0) {  // the LUT must start at LDS address 0
     if (threadIdx.x == 0) atomicOr(&a.flags[0], 16);
     return;
@@ -1416,7 +1514,8 @@ __global__ __launch_bounds__(NT, 512 / NT) __attribute__((amdgpu_waves_per_eu(NT
       if (tid == 0 && next_u < total) next_unit = a.units[locate(next_u, next_cls)];
     };
     const int cls = s_cls;
-    if (cls == 0) scan_unit<8, MT, PHASE, DT, NR, NT>(a, lds, L, own, s_unit, fetch);
+    if (cls == 0 && !a.gran) scan_unit<4, MT, PHASE, DT, NR, NT>(a, lds, L, own, s_unit, fetch);
+    else if (cls == 0) scan_unit<8, MT, PHASE, DT, NR, NT>(a, lds, L, own, s_unit, fetch);
     else if (cls == 1) scan_unit<16, MT, PHASE, DT, NR, NT>(a, lds, L, own, s_unit, fetch);
     else scan_unit<32, MT, PHASE, DT, NR, NT>(a, lds, L, own, s_unit, fetch);
     __syncthreads();
