@@ -553,7 +553,8 @@ def measure(h, w, Q, kq, npq, pols, args, truth, tag, qdev=None, q_dtype=None):
         lat = [x["total"] for x in stages]
         results[name] = dict(qps=nq / (ms / 1e3), ms=ms, recall1=rec1, recall10=rec10, stages=st, status=status,
                              cl_low_share=cl_share,
-                             probed_bytes=probed_bytes, scan_bytes=wk["scan_bytes"], live_pairs=wk["live_pairs"],
+                             probed_bytes=probed_bytes, scan_bytes=wk["scan_bytes"], unit_bytes=wk["unit_bytes"],
+                             live_pairs=wk["live_pairs"],
                              dead_pairs=wk["dead_pairs"], bits=hist, schedule=sched,
                              n_pairs=int((pr >= 0).sum()),
                              p50=float(np.percentile(lat, 50)), p99=float(np.percentile(lat, 99)))
@@ -565,22 +566,25 @@ def measure(h, w, Q, kq, npq, pols, args, truth, tag, qdev=None, q_dtype=None):
 
 def roofline_of(r, w, nq, traffic_file):
     """Roofline of the dominant kernel of the headline search: the phase-2
-    scan (LUT build of its pairs, then the packed-lane scan of the live
-    pairs' codes).  Achieved = the code bytes of the (query, list) pairs the
-    launch scans (each such pair reads its list's n x M code bytes once,
-    the per-unit figure of the scan) over the kernel's average duration,
-    against the HBM peak.  Pairs the bound test drops after the first LUT
-    pass are not scanned and are not counted; their LUT work is given as
-    context beside the probed bytes, which are not what the launch
-    processes."""
+    scan (LUT of its pairs, then the packed-lane scan of the live pairs'
+    codes).  The per-unit figure is what one work unit of the kernel reads:
+    its list chunk's codes once, however many (query, list) pairs it serves
+    (up to eight per LUT word), plus its LUT sources (inner product: the
+    live pairs' quantised tables); achieved = those bytes summed over the
+    units the launch scans (the search's own work counter) over the
+    kernel's average duration, against the HBM peak.  The per-pair code
+    bytes (each live pair reading its list once) exceed what the kernel
+    moves by the pairs a unit shares and are context only, as are the
+    probed bytes and the pairs the bound drops before any scan."""
     scan_ms = r["stages"]["scan2"]
-    gbs = r["scan_bytes"] / (scan_ms / 1e3) / 1e9
+    gbs = r["unit_bytes"] / (scan_ms / 1e3) / 1e9
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(traffic_file),
             "kernel": "k_scan_mix (phase-2 scan, every lane class in one launch)",
-            "kernel_ms": round(scan_ms, 4), "bytes_per_launch": round(r["scan_bytes"]),
+            "kernel_ms": round(scan_ms, 4), "bytes_per_launch": round(r["unit_bytes"]),
             "context": {"live_pairs": round(r["live_pairs"]), "skipped_pairs": round(r["dead_pairs"]),
-                        "lut_entries_built": round((r["live_pairs"] + r["dead_pairs"]) * 256 * w.M),
+                        "pair_code_bytes": round(r["scan_bytes"]),
+                        "pair_code_gbs": round(r["scan_bytes"] / (scan_ms / 1e3) / 1e9, 1),
                         "probed_code_bytes": round(r["probed_bytes"])}}
 
 

@@ -185,9 +185,12 @@ typedef struct amp_precision_policy {
  * Per-query k / nprobe host arrays are staged through pinned memory: the
  * call does not wait for earlier searches on the stream, and the caller may
  * reuse the arrays when it returns.
- * work (host, [3] int64, optional): work of the full scan (phase 2): code
+ * work (host, [4] int64, optional): work of the full scan (phase 2): code
  * bytes scanned summed over the live (query, list) pairs, live pairs, pairs
- * skipped whole because their LUT base exceeds the query's bound; forces a
+ * skipped whole because their LUT base exceeds the query's bound, and the
+ * bytes its work units read (each unit's list chunk once, however many
+ * pairs it serves, plus its LUT sources: inner product the live pairs'
+ * quantised tables, L2 / L1 the query rows and the centroid); forces a
  * synchronisation at the end (not with AMP_SEARCH_GRAPH).
  * out_status (optional, int32, same memory space as the outputs; device mode
  * also accepts pinned host memory): the status of the search as the device

@@ -509,7 +509,7 @@ def amp_search(index, queries, k, nprobe, policy="fixed", bits=16, allowed=(4, 8
         kmax, npmax = int(kk.max()), int(npb.max())
     pol, xb = make_policy(policy, bits, allowed, margin_q40, explicit_bits, lut_dtype, granularity)
     ms = np.zeros(AMP_N_STAGES, dtype=np.float32) if stage_ms else None
-    wk = np.zeros(3, dtype=np.int64) if work else None
+    wk = np.zeros(4, dtype=np.int64) if work else None
     fn = getattr(lib(), _entry)
     if device:
         o = out
@@ -527,7 +527,7 @@ def amp_search(index, queries, k, nprobe, policy="fixed", bits=16, allowed=(4, 8
         if stage_ms:
             o["stage_ms"] = dict(zip(STAGES, ms.tolist()))
         if work:
-            o["work"] = dict(zip(("scan_bytes", "live_pairs", "dead_pairs"), wk.tolist()))
+            o["work"] = dict(zip(("scan_bytes", "live_pairs", "dead_pairs", "unit_bytes"), wk.tolist()))
         return o
     q = np.ascontiguousarray(queries, dtype=np.uint16 if qd == AMP_BF16 else np.float32)
     res = dict(ids=np.empty((nq, kmax), np.int64), dist=np.empty((nq, kmax), np.float32))
@@ -561,7 +561,7 @@ def amp_search(index, queries, k, nprobe, policy="fixed", bits=16, allowed=(4, 8
     if stage_ms:
         res["stage_ms"] = dict(zip(STAGES, ms.tolist()))
     if work:
-        res["work"] = dict(zip(("scan_bytes", "live_pairs", "dead_pairs"), wk.tolist()))
+        res["work"] = dict(zip(("scan_bytes", "live_pairs", "dead_pairs", "unit_bytes"), wk.tolist()))
     return res
 
 

@@ -1223,7 +1223,7 @@ amp_status search_on(amp_index* ix, Workspace& w, const void* queries, int64_t n
     uint64_t wk[4];
     AMP_HIP(hipStreamSynchronize(st));
     AMP_HIP(hipMemcpy(wk, w.work, sizeof wk, hipMemcpyDeviceToHost));
-    for (int i = 0; i < 3; ++i) opts->work[i] = (int64_t)wk[i];
+    for (int i = 0; i < 4; ++i) opts->work[i] = (int64_t)wk[i];
   }
   if (getenv("AMP_STATS") && !w.fixed) {
     // debug: candidates forwarded to the merge per query

@@ -91,9 +91,11 @@ __host__ __device__ constexpr int kernel_wpr(int MT) { return MT ? wpr_for(MT) :
 // a variant specialised for MT may also run with one-word rows (NR = 1:
 // sparse batches, a few pairs per list), keeping its codes in registers
 __host__ __device__ constexpr int variant_wpr(int MT, int NR) { return NR ? 1 : kernel_wpr(MT); }
-// the 4-bit class (eight pairs per word) packs at most two words per row:
-// sixteen pairs per unit, as the 8-bit class at four words
-__host__ __device__ constexpr int nib_wpr(int wpr) { return wpr > 2 ? 2 : wpr; }
+// the 4-bit class (eight pairs per word) packs half the words per row of
+// the variant (at least one): as many pairs per unit as the 8-bit class
+// from two words per row on, so that its tile (and the registers that hold
+// per-pair thresholds) does not grow where the LUT is small
+__host__ __device__ constexpr int nib_wpr(int wpr) { return wpr > 1 ? wpr / 2 : 1; }
 // words per row and pairs per unit of a lane class (lwb 0: FP32 LUT; -1: the
 // mixed-class kernel, whose tile takes the most pairs of any class)
 __host__ __device__ constexpr int class_wpr(int lwb, int wpr) { return lwb == 4 ? nib_wpr(wpr) : wpr; }
@@ -132,7 +134,7 @@ __host__ __device__ inline ScanLds scan_lds_layout(int G, int wpr, int M, int d,
   if (phase == 1 && G * nt * 4 > M * kKsub * wpr * 4) L.lmin = take(G * nt * 4);
   // unit-claim control words: kept in the dynamic LDS too, so that the LUT
   // starts at LDS address 0 and row addresses fold into instruction offsets
-  L.ctl = take(64);  // unit index, class, re-run vote, live vote, unit descriptor, 3 work counters
+  L.ctl = take(64);  // unit index, class, re-run vote, live vote, unit descriptor, 4 work counters
   L.total = o;
   return L;
 }
@@ -783,6 +785,9 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
           wc[0] += (uint64_t)(nlive * (v1 - v0) * M);
           wc[1] += (uint64_t)nlive;
           wc[2] += (uint64_t)(np_u - nlive);
+          // what the unit reads: its chunk's codes once and the live pairs'
+          // quantised tables (bytes for the 4-bit class, else uint16)
+          if (nlive) wc[3] += (uint64_t)((v1 - v0) * M) + (uint64_t)nlive * M * kKsub * (LWB == 4 ? 1 : 2);
         }
         if (!nlive) {
           fetch_next();
@@ -805,8 +810,8 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
 #pragma unroll
             for (int g = 0; g < G; ++g) {
               const int es = eb + u * NT;
-              xs[u][g] = (u32x4){0u, 0u, 0u, 0u};  // absent pairs: zero fields
-              if (g < np_u && es < ns)
+              xs[u][g] = (u32x4){0u, 0u, 0u, 0u};  // absent and dead pairs: zero fields
+              if (g < np_u && pb[g] >= 0 && es < ns)
                 xs[u][g] = *reinterpret_cast<const u32x4*>(
                     reinterpret_cast<const uint8_t*>(a.iptq + (size_t)pw[g] * tsz) + (size_t)es * 16);
             }
@@ -1034,6 +1039,9 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
           wc[0] += (uint64_t)(nlive * (v1 - v0) * M);
           wc[1] += (uint64_t)nlive;
           wc[2] += (uint64_t)(np_u - nlive);
+          // what the unit reads: the pairs' query rows and the centroid (its
+          // residuals), and, if a pair is live, its chunk's codes once
+          wc[3] += (uint64_t)(np_u + 1) * a.d * 4 + (nlive ? (uint64_t)((v1 - v0) * M) : 0ull);
         }
         if (!nlive) {
           fetch_next();
@@ -1098,6 +1106,12 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
           wc[0] += (uint64_t)(nlive * (v1 - v0) * M);
           wc[1] += (uint64_t)nlive;
           wc[2] += (uint64_t)(np_u - nlive);
+          // what the unit reads: its LUT sources (inner product: the pairs'
+          // FP32 dot-product tables; L2 / L1: the query rows, the centroid
+          // and the codebook) and, if a pair is live, its chunk's codes once
+          wc[3] += (ip ? (uint64_t)np_u * M * kKsub * 4
+                       : (uint64_t)(np_u + 1) * a.d * 4 + (uint64_t)M * kKsub * a.dsub * 4) +
+                   (nlive ? (uint64_t)((v1 - v0) * M) : 0ull);
         }
         if (!nlive) {
           fetch_next();
@@ -1200,8 +1214,10 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
         }
         // 4 ND subspaces from ND code dwords: the ND * 4 row reads are issued
         // before any is added (a scheduling barrier keeps the adds behind
-        // them), then added in subspace order; the 8-bit sums are widened at
-        // every kWideChunk-th subspace (chunks never straddle one)
+        // them: left alone, the compiler waited after every second read of
+        // the long variants), then added in subspace order; the 8-bit sums
+        // are widened at every kWideChunk-th subspace (chunks never straddle
+        // one)
         auto stepn = [&](auto nd_tag, const uint32_t* c, int m0) {
           constexpr int ND = decltype(nd_tag)::value;
           uint32_t x[4 * ND][WPR];
@@ -1210,7 +1226,9 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
             const int rowi = ((m0 + k) * kKsub + ((c[k >> 2] >> (8 * (k & 3))) & 255u)) * WPR;
             lut_row_load<WPR>(lut, rowi, x[k]);
           }
-          __builtin_amdgcn_sched_barrier(0);
+          // (the short straight-line variants, M <= 24, are left to the
+          // scheduler: the barrier made the M = 24 scan 30 % slower)
+          if constexpr (MT == 0 || MT > 24) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
           for (int k = 0; k < 4 * ND; ++k)
 #pragma unroll
@@ -1375,14 +1393,30 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
           }
           __syncthreads();
         }
-      // the k smallest of each pair's minima to its query's bound buffer
+      // the k smallest of each pair's minima to its query's bound buffer:
+      // a pair's thread counts them (its row is sorted, lanes that scanned
+      // no vector hold the largest key at its end) and reserves their slots
+      // with one atomic; every thread then writes its entry
+      int32_t* rbase = reinterpret_cast<int32_t*>(lds + L.rr);  // [G] (free after the LUT build)
+      if (tid < np_u) {
+        const int q = pq[tid];
+        const int kk = a.kq ? a.kq[q] : a.kconst;
+        int lo = 0, hi = TP;  // first entry holding the largest key
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (lm[tid * TP + mid] != 0xFFFFFFFFu) lo = mid + 1; else hi = mid;
+        }
+        const int n = kk < lo ? kk : lo;
+        rbase[tid] = n > 0 ? (int32_t)atomicAdd(&a.ccount[q], (uint32_t)n) : 0;
+      }
+      __syncthreads();
       for (int i = tid; i < np_u * TP; i += NT) {
         const int g = i / TP, r = i % TP;
         const int q = pq[g];
         const int kk = a.kq ? a.kq[q] : a.kconst;
         const uint32_t val = lm[g * TP + r];
         if (r < kk && val != 0xFFFFFFFFu) {
-          const uint32_t pos = atomicAdd(&a.ccount[q], 1u);
+          const uint32_t pos = (uint32_t)rbase[g] + (uint32_t)r;
           if (pos < a.capq) {
             uint64_t key;
             if constexpr (FP) key = (uint64_t)val;
@@ -1394,12 +1428,18 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
     }
 }
 
+// workgroups per CU the register allocation of a scan variant must allow:
+// one of 512 threads; three of 256 for M = 24 (its 48 KB LUT leaves LDS for
+// three), else two
+__host__ __device__ constexpr int scan_min_blocks(int MT, int NT) { return NT == 512 ? 1 : (MT == 24 ? 3 : 2); }
+
 // persistent scan of one lane class: workgroups claim units of their class
 // from a device counter; the next unit is claimed while the current one is
 // processed (index at the start, descriptor before the scan, published at
 // the end)
 template <int LWB, int MT, int PHASE, int DT, int NR, int NT>
-__global__ __launch_bounds__(NT, 512 / NT) __attribute__((amdgpu_waves_per_eu(NT / 256, NT == 512 ? 2 : 8))) void k_scan(ScanArgs a) {
+__global__ __launch_bounds__(NT, scan_min_blocks(MT, NT))
+    __attribute__((amdgpu_waves_per_eu(NT / 64 * scan_min_blocks(MT, NT) / 4, NT == 512 ? 2 : 8))) void k_scan(ScanArgs a) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   constexpr int WPR = class_wpr(LWB, variant_wpr(MT, NR));
   constexpr bool FP = LWB == 0;
@@ -1437,7 +1477,7 @@ __global__ __launch_bounds__(NT, 512 / NT) __attribute__((amdgpu_waves_per_eu(NT
     if (ub + uu < ue) s_unit = a.units[ub + uu];
   }
   if (tid == 0)
-    for (int i = 0; i < 3; ++i) reinterpret_cast<uint64_t*>(lds + L.ctl + 32)[i] = 0;
+    for (int i = 0; i < 4; ++i) reinterpret_cast<uint64_t*>(lds + L.ctl + 32)[i] = 0;
   __syncthreads();
   for (;;) {
     if (ub + s_u >= ue) break;
@@ -1455,7 +1495,7 @@ __global__ __launch_bounds__(NT, 512 / NT) __attribute__((amdgpu_waves_per_eu(NT
     __syncthreads();
   }
   if (PHASE == 2 && tid == 0 && a.work)
-    for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < 4; ++i)
       atomicAdd((unsigned long long*)&a.work[i],
                 (unsigned long long)reinterpret_cast<const uint64_t*>(lds + L.ctl + 32)[i]);
 }
@@ -1466,7 +1506,8 @@ __global__ __launch_bounds__(NT, 512 / NT) __attribute__((amdgpu_waves_per_eu(NT
 // narrow units fill the tail.  The LDS tile of the 4-bit class (the most
 // pairs per unit) serves every class.
 template <int MT, int PHASE, int DT, int NR, int NT>
-__global__ __launch_bounds__(NT, 512 / NT) __attribute__((amdgpu_waves_per_eu(NT / 256, NT == 512 ? 2 : 8))) void k_scan_mix(ScanArgs a) {
+__global__ __launch_bounds__(NT, scan_min_blocks(MT, NT))
+    __attribute__((amdgpu_waves_per_eu(NT / 64 * scan_min_blocks(MT, NT) / 4, NT == 512 ? 2 : 8))) void k_scan_mix(ScanArgs a) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   constexpr int WPR = variant_wpr(MT, NR);
   const int M = MT ? MT : a.M;
@@ -1503,7 +1544,7 @@ __global__ __launch_bounds__(NT, 512 / NT) __attribute__((amdgpu_waves_per_eu(NT
     }
   }
   if (tid == 0)
-    for (int i = 0; i < 3; ++i) reinterpret_cast<uint64_t*>(lds + L.ctl + 32)[i] = 0;
+    for (int i = 0; i < 4; ++i) reinterpret_cast<uint64_t*>(lds + L.ctl + 32)[i] = 0;
   __syncthreads();
   for (;;) {
     if (s_u >= total) break;
@@ -1527,7 +1568,7 @@ __global__ __launch_bounds__(NT, 512 / NT) __attribute__((amdgpu_waves_per_eu(NT
     __syncthreads();
   }
   if (PHASE == 2 && tid == 0 && a.work)
-    for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < 4; ++i)
       atomicAdd((unsigned long long*)&a.work[i],
                 (unsigned long long)reinterpret_cast<const uint64_t*>(lds + L.ctl + 32)[i]);
 }

@@ -733,6 +733,14 @@ def test_work_counters_account_for_every_pair(tiny, policy, bits):
     assert 0 < wk["scan_bytes"] <= sizes[P[P >= 0]].sum() * tiny["idx"]["M"]
     # pairs skipped whole scan nothing: the bytes are those of the live pairs' lists
     assert wk["live_pairs"] > 0
+    # the units read each chunk's codes once (at most the pairs' code bytes)
+    # plus their LUT sources (at most a table or the residual rows per pair
+    # and the codebook per unit)
+    ix = tiny["idx"]
+    d, M = ix["d"], ix["M"]
+    n = int((P >= 0).sum())
+    lut_src = n * max(M * 256 * 4, d * 4) + n * (d * 4 + M * 256 * ix["dsub"] * 4)
+    assert 0 < wk["unit_bytes"] <= wk["scan_bytes"] + lut_src
 
 
 @pytest.fixture(scope="module")
