@@ -678,6 +678,20 @@ def exact_ip_bf16(b16, Q, k, dev, chunk=1 << 20):
     return np.concatenate(out)
 
 
+def apply_schedule(amp, h, args, allowed, nq):
+    """--schedule chunk,chunk1,narrow,lut_dtype[,queue]: that search schedule
+    for every measured policy at this batch size, instead of autotuning."""
+    if not args.schedule:
+        return
+    f = [int(x) for x in args.schedule.split(",")]
+    ents = []
+    for name, kw in policy_list(args.policies, allowed):
+        ents.append(dict(policy_kind=amp.POLICIES[kw["policy"]], nq_log2=int(np.ceil(np.log2(nq))),
+                         chunk=f[0], chunk1=f[1], narrow=f[2], lut_dtype=f[3], queue=f[4] if len(f) > 4 else 0))
+    amp.amp_index_set_tuning(h, ents)
+    args.autotune = 0
+
+
 def headline(args):
     """The default run: the serving workload at full size (5M x 768 BF16,
     inner product) as an offline batch with the serving mix of k and nprobe,
@@ -722,6 +736,7 @@ def headline(args):
     log(f"[c5] exact inner-product top-10 of {nq} queries in {time.perf_counter() - t:.1f}s")
     qdev = torch.from_numpy(Qb.view(np.int16)).to(dev)
     pols = policy_list(args.policies, allowed)
+    apply_schedule(amp, h, args, allowed, nq)
     res = measure(h, w, Qb, kq, npq, pols, args, truth, "c5", qdev=qdev, q_dtype="bf16")
     head = "adaptive" if "adaptive" in res else next(iter(res))
     rh = res[head]
@@ -912,14 +927,7 @@ def single(args):
                                         allowed=allowed, C_=args.svr_c, n_samples=1280)
     model = amp.amp_index_get_predictor(h)
     log(f"[bench] trained predictor: {rep}")
-    if args.schedule:
-        f = [int(x) for x in args.schedule.split(",")]
-        ents = []
-        for name, kw in policy_list(args.policies, allowed):
-            ents.append(dict(policy_kind=amp.POLICIES[kw["policy"]], nq_log2=int(np.ceil(np.log2(len(Q)))),
-                             chunk=f[0], chunk1=f[1], narrow=f[2], lut_dtype=f[3], queue=f[4] if len(f) > 4 else 0))
-        amp.amp_index_set_tuning(h, ents)
-        args.autotune = 0
+    apply_schedule(amp, h, args, allowed, len(Q))
     args.idx_sizes = idx["list_sizes"].astype(np.int64)
     pols = policy_list(args.policies, allowed)
     res = measure(h, w, Q, w.k, w.nprobe, pols, args, truth, "bench")

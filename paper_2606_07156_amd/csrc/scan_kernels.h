@@ -112,7 +112,7 @@ __host__ __device__ constexpr int ri_stride(int d) { return d + 16; }
 
 // LDS carve-up of one scan workgroup (all offsets in bytes, 16-aligned)
 struct ScanLds {
-  int lut, ri, rr, lo, hi, pq, pb, ps, pbase, psig, pid, lmin, ctl, total;
+  int lut, ri, rr, lo, hi, pq, pb, ps, pbase, psig, pid, ctl, total;
 };
 __host__ __device__ inline ScanLds scan_lds_layout(int G, int wpr, int M, int d, bool fp32, int phase, int nt) {
   ScanLds L;
@@ -129,9 +129,6 @@ __host__ __device__ inline ScanLds scan_lds_layout(int G, int wpr, int M, int d,
   L.pbase = take(G * 8);
   L.psig = take(G * 4);
   L.pid = take(G * 4);
-  // phase 1 keeps per-thread minima after the scan: reuse the LUT space
-  L.lmin = L.lut;
-  if (phase == 1 && G * nt * 4 > M * kKsub * wpr * 4) L.lmin = take(G * nt * 4);
   // unit-claim control words: kept in the dynamic LDS too, so that the LUT
   // starts at LDS address 0 and row addresses fold into instruction offsets
   L.ctl = take(64);  // unit index, class, re-run vote, live vote, unit descriptor, 4 work counters
@@ -1330,20 +1327,24 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
       }
       }  // vectors of the step
     }
-    if (PHASE == 1 && a.kmax <= 64) {
+    if (PHASE == 1) {
       // the k-th smallest of a wave's per-lane minima bounds the pair's k-th
-      // smallest (each minimum is a distinct vector): the wave's k smallest
-      // minima go to the query's bound buffer, and the bound is taken over
-      // all of them.  The k-th smallest minimum x is found bit by bit (the
-      // largest x with fewer than k minima below it; counts are ballot bit
-      // counts, no cross-lane shuffles); the minima below x and the
-      // lowest-lane ones equal to x make up the k.
+      // smallest (each minimum is a distinct vector): the wave's min(k, 64)
+      // smallest minima go to the query's bound buffer, and the bound is
+      // taken over all of them (for k > 64 every lane's minimum goes: the k
+      // smallest entries of the buffer are then the pair's k smallest
+      // minima, as a workgroup-wide selection would give).  The kw-th
+      // smallest minimum x is found bit by bit (the largest x with fewer
+      // than kw minima below it; counts are ballot bit counts, no
+      // cross-lane shuffles); the minima below x and the lowest-lane ones
+      // equal to x make up the kw.
 #pragma unroll
       for (int g = 0; g < G; ++g) {
         if (g >= np_u) break;
         const uint32_t v = lmin[g];
         const int q = pq[g];
-        const int kk = a.kq ? a.kq[q] : a.kconst;
+        const int kq = a.kq ? a.kq[q] : a.kconst;
+        const int kk = kq < 64 ? kq : 64;
         uint32_t x = 0;
         for (int bit = 31; bit >= 0; --bit) {
           const uint32_t t = x | (1u << bit);
@@ -1367,62 +1368,6 @@ __device__ __forceinline__ void scan_unit(const ScanArgs& a, char* lds, const Sc
           if constexpr (FP) key = (uint64_t)v;
           else key = ikey(pbase[g] + ((int64_t)v << ps[g]));
           a.ckey[(size_t)q * a.capq + pos] = key;
-        }
-      }
-    } else if (PHASE == 1) {
-      // k > 64: the k-th smallest of the workgroup's per-thread minima
-      // (bitonic sort over a power-of-two row, padded with the largest key)
-      constexpr int TP = NT;
-      __syncthreads();  // the LUT space is reused below
-      uint32_t* lm = reinterpret_cast<uint32_t*>(lds + L.lmin);
-#pragma unroll
-      for (int g = 0; g < G; ++g) {
-        lm[g * TP + tid] = lmin[g];
-        if (tid + NT < TP) lm[g * TP + NT + tid] = 0xFFFFFFFFu;
-      }
-      __syncthreads();
-      for (int size = 2; size <= TP; size <<= 1)
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-          for (int i = tid; i < G * (TP / 2); i += NT) {
-            const int g = i / (TP / 2), ii = i % (TP / 2);
-            const int pos = 2 * ii - (ii & (stride - 1));
-            const bool asc = (pos & size) == 0;
-            uint32_t* arr = lm + g * TP;
-            const uint32_t x0 = arr[pos], x1 = arr[pos + stride];
-            if ((x0 > x1) == asc) { arr[pos] = x1; arr[pos + stride] = x0; }
-          }
-          __syncthreads();
-        }
-      // the k smallest of each pair's minima to its query's bound buffer:
-      // a pair's thread counts them (its row is sorted, lanes that scanned
-      // no vector hold the largest key at its end) and reserves their slots
-      // with one atomic; every thread then writes its entry
-      int32_t* rbase = reinterpret_cast<int32_t*>(lds + L.rr);  // [G] (free after the LUT build)
-      if (tid < np_u) {
-        const int q = pq[tid];
-        const int kk = a.kq ? a.kq[q] : a.kconst;
-        int lo = 0, hi = TP;  // first entry holding the largest key
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (lm[tid * TP + mid] != 0xFFFFFFFFu) lo = mid + 1; else hi = mid;
-        }
-        const int n = kk < lo ? kk : lo;
-        rbase[tid] = n > 0 ? (int32_t)atomicAdd(&a.ccount[q], (uint32_t)n) : 0;
-      }
-      __syncthreads();
-      for (int i = tid; i < np_u * TP; i += NT) {
-        const int g = i / TP, r = i % TP;
-        const int q = pq[g];
-        const int kk = a.kq ? a.kq[q] : a.kconst;
-        const uint32_t val = lm[g * TP + r];
-        if (r < kk && val != 0xFFFFFFFFu) {
-          const uint32_t pos = (uint32_t)rbase[g] + (uint32_t)r;
-          if (pos < a.capq) {
-            uint64_t key;
-            if constexpr (FP) key = (uint64_t)val;
-            else key = ikey(pbase[g] + ((int64_t)val << ps[g]));
-            a.ckey[(size_t)q * a.capq + pos] = key;
-          }
         }
       }
     }

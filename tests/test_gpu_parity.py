@@ -546,7 +546,8 @@ def test_skewed_shape_uneven_nprobe(skewed_shape):
 
 @pytest.fixture(scope="module")
 def highdim_shape():
-    # d 960, PQ120 (d/M = 8) on the e4m3 grid, k 100 (the workgroup-level bound)
+    # d 960, PQ120 (d/M = 8) on the e4m3 grid, k 100 (more than a wave holds: every
+    # lane minimum of a pair goes to the phase-1 bound buffer)
     return _shape("highdim", 16_000, 12, 32, 12)
 
 
