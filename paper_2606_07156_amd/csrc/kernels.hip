@@ -473,6 +473,8 @@ struct PairArgs {
   const float* C;
   const int16_t* qi16;    // inner product: queries and centroids on the grid (d' = |qi - ci|^2)
   const int16_t* ci16;
+  int64_t* dot_out;       // adaptive inner product: qi.ci of every pair (read in the same pass), or null
+  int32_t* ipmask;        // with dot_out: the widths each query's pairs use
   const int32_t* probes;
   const int32_t* radq;
   const int64_t* offsets;
@@ -508,6 +510,8 @@ __device__ __forceinline__ int pick_bits(int64_t y, const int64_t* theta, uint32
 __global__ __launch_bounds__(256) void k_pairs(PairArgs a, ModelArgs ma) {
   __shared__ unsigned long long s_best[256];
   __shared__ int64_t s_dq2[256];
+  __shared__ int32_t s_dot[256];
+  __shared__ int32_t s_wmask[256];  // widths of each query slot's pairs (with dot_out)
   __shared__ int32_t s_table[kTableN];
   const int lg = a.lg_npp, lt = a.lg_T, T = 1 << lt;
   const int t = threadIdx.x & (T - 1);
@@ -516,13 +520,17 @@ __global__ __launch_bounds__(256) void k_pairs(PairArgs a, ModelArgs ma) {
   const bool adaptive = a.policy == AMP_POLICY_ADAPTIVE;
   if (adaptive)
     for (int i = threadIdx.x; i < kTableN; i += blockDim.x) s_table[i] = ma.table[i];
-  if ((threadIdx.x & ((1 << (lg + lt)) - 1)) == 0) s_best[slot] = ~0ull;
+  if ((threadIdx.x & ((1 << (lg + lt)) - 1)) == 0) {
+    s_best[slot] = ~0ull;
+    s_wmask[slot] = 0;
+  }
   __syncthreads();
   const bool valid = q < a.nq && r < a.npmax;
   const int p = valid ? a.probes[(size_t)q * a.npmax + r] : -1;
   // d' = |grid residual|^2 of pair (qq, pp): the part of lane t of tn
   // (four coordinates per step, d % 4 == 0)
-  auto dq2_part = [&](int qq, int pp, int t0, int tn) -> int64_t {
+  // (inner product: also the part of qi.ci, into dot)
+  auto dq2_part = [&](int qq, int pp, int t0, int tn, int& dot) -> int64_t {
     int64_t s2 = 0;
     const bool l2 = a.metric != AMP_IP;  // L2 and L1: d' of the grid residual
     if (!l2 && a.qi16) {
@@ -531,11 +539,13 @@ __global__ __launch_bounds__(256) void k_pairs(PairArgs a, ModelArgs ma) {
       const u32x2* xc = reinterpret_cast<const u32x2*>(a.ci16 + (size_t)pp * a.d);
       for (int i = t0; i < (a.d >> 2); i += tn) {
         const u32x2 x = xq[i], c = xc[i];
-        const int v0 = (int)(int16_t)(x[0] & 0xFFFFu) - (int)(int16_t)(c[0] & 0xFFFFu);
-        const int v1 = (int)(int16_t)(x[0] >> 16) - (int)(int16_t)(c[0] >> 16);
-        const int v2 = (int)(int16_t)(x[1] & 0xFFFFu) - (int)(int16_t)(c[1] & 0xFFFFu);
-        const int v3 = (int)(int16_t)(x[1] >> 16) - (int)(int16_t)(c[1] >> 16);
+        const int x0 = (int)(int16_t)(x[0] & 0xFFFFu), x1 = (int)(int16_t)(x[0] >> 16);
+        const int x2 = (int)(int16_t)(x[1] & 0xFFFFu), x3 = (int)(int16_t)(x[1] >> 16);
+        const int c0 = (int)(int16_t)(c[0] & 0xFFFFu), c1 = (int)(int16_t)(c[0] >> 16);
+        const int c2 = (int)(int16_t)(c[1] & 0xFFFFu), c3 = (int)(int16_t)(c[1] >> 16);
+        const int v0 = x0 - c0, v1 = x1 - c1, v2 = x2 - c2, v3 = x3 - c3;
         s2 += (int64_t)(v0 * v0 + v1 * v1) + (int64_t)(v2 * v2 + v3 * v3);
+        dot += x0 * c0 + x1 * c1 + x2 * c2 + x3 * c3;
       }
       return s2;
     }
@@ -560,6 +570,7 @@ __global__ __launch_bounds__(256) void k_pairs(PairArgs a, ModelArgs ma) {
     return s2;
   };
   int64_t dq2 = 0;
+  int dot = 0;  // (inner product with dot_out)
   if (adaptive && T == 1) {
     // a thread per pair: the rows are read by sixteen lanes per pair, sixteen
     // pairs of the workgroup at a time (coalesced 128-byte segments), and the
@@ -569,83 +580,108 @@ __global__ __launch_bounds__(256) void k_pairs(PairArgs a, ModelArgs ma) {
       const int e = e0 + grp;
       const int qs = blockIdx.x * (256 >> lg) + (e >> lg), rs = e & ((1 << lg) - 1);
       const int pp = qs < a.nq && rs < a.npmax ? a.probes[(size_t)qs * a.npmax + rs] : -1;
-      int64_t s2 = pp >= 0 ? dq2_part(qs, pp, l16, 16) : 0;
+      int dp = 0;
+      int64_t s2 = pp >= 0 ? dq2_part(qs, pp, l16, 16, dp) : 0;
 #pragma unroll
-      for (int o = 8; o > 0; o >>= 1) s2 += __shfl_xor(s2, o, 16);
-      if (l16 == 0) s_dq2[e] = s2;
+      for (int o = 8; o > 0; o >>= 1) {
+        s2 += __shfl_xor(s2, o, 16);
+        dp += __shfl_xor(dp, o, 16);
+      }
+      if (l16 == 0) {
+        s_dq2[e] = s2;
+        s_dot[e] = dp;
+      }
     }
     __syncthreads();
     dq2 = s_dq2[threadIdx.x];
+    dot = s_dot[threadIdx.x];
   } else if (adaptive && p >= 0) {
-    dq2 = dq2_part(q, p, t, T);
+    dq2 = dq2_part(q, p, t, T, dot);
   }
   // the T threads of a pair are adjacent lanes of one wave (T <= 64)
-  for (int o = 1; o < T; o <<= 1) dq2 += __shfl_xor(dq2, o);
+  if (T > 1)
+    for (int o = 1; o < T; o <<= 1) {
+      dq2 += __shfl_xor(dq2, o);
+      dot += __shfl_xor(dot, o);
+    }
   if (adaptive && p >= 0 && t == 0)
     atomicMin(&s_best[slot], (unsigned long long)((uint64_t)dq2 << 13 | (uint64_t)p));
   __syncthreads();
-  if (!valid) return;
-  uint8_t bits = 0;
-  if (p >= 0) {
-    if (a.policy == AMP_POLICY_FP32) {
-      bits = 32;
-    } else if (a.policy == AMP_POLICY_FIXED) {
-      bits = (uint8_t)a.fixed_bits;
-    } else if (a.policy == AMP_POLICY_EXPLICIT) {
-      bits = a.xbits[(size_t)q * a.npmax + r];
-    } else {
-      const int c1 = (int)(s_best[slot] & 8191ull);
-      int64_t x[5];
-      x[0] = dq2;
-      x[1] = a.radq[c1];
-      x[2] = a.radq[p];
-      x[3] = a.offsets[c1 + 1] - a.offsets[c1];
-      x[4] = a.offsets[p + 1] - a.offsets[p];
-      int32_t u[5];
-      for (int f = 0; f < 5; ++f) {
-        int64_t v = ((mitchell_q8(x[f]) - ma.feat_lo[f]) * ma.feat_mul[f]) >> 16;
-        u[f] = (int32_t)(v < 0 ? 0 : (v > 1023 ? 1023 : v));
-      }
-      // integer sum: the split over threads does not change the result
-      // u and sv lie in [0, 1023] (sv checked when the model is set): the
-      // squared differences are exact 24-bit products (full-rate multiplies)
-      // and |u - sv|^2 < 2^23; g_mul < 2^32, so the table index is the high
-      // word of one 32 x 32-bit product
-      const uint32_t gm = (uint32_t)ma.g_mul;
-      auto term = [&](int i) -> int64_t {
-        const int32_t* sv = ma.sv + 5 * i;
-        const int d0 = u[0] - sv[0], d1 = u[1] - sv[1], d2 = u[2] - sv[2], d3 = u[3] - sv[3], d4 = u[4] - sv[4];
-        const uint32_t dist2 = (uint32_t)(__mul24(d0, d0) + __mul24(d1, d1) + __mul24(d2, d2) + __mul24(d3, d3) +
-                                          __mul24(d4, d4));
-        const uint32_t idx = __umulhi(dist2, gm);
-        const int32_t K = s_table[idx < (uint32_t)(kTableN - 1) ? idx : (uint32_t)(kTableN - 1)];
-        return (int64_t)ma.beta[i] * K;
-      };
-      // two independent chains (an integer sum: the order does not matter)
-      int64_t y = 0, y1 = 0;
-      if (T == 1) {
-        // a thread per pair: the support-vector index is the same across the
-        // wave, so sv and beta are read through scalar loads
-        int i = 0;
-        for (; i + 1 < ma.n_sv; i += 2) {
-          y += term(i);
-          y1 += term(i + 1);
-        }
-        if (i < ma.n_sv) y += term(i);
+  if (valid) {
+    uint8_t bits = 0;
+    if (p >= 0) {
+      if (a.policy == AMP_POLICY_FP32) {
+        bits = 32;
+      } else if (a.policy == AMP_POLICY_FIXED) {
+        bits = (uint8_t)a.fixed_bits;
+      } else if (a.policy == AMP_POLICY_EXPLICIT) {
+        bits = a.xbits[(size_t)q * a.npmax + r];
       } else {
-        int i = t;
-        for (; i + T < ma.n_sv; i += 2 * T) {
-          y += term(i);
-          y1 += term(i + T);
+        const int c1 = (int)(s_best[slot] & 8191ull);
+        int64_t x[5];
+        x[0] = dq2;
+        x[1] = a.radq[c1];
+        x[2] = a.radq[p];
+        x[3] = a.offsets[c1 + 1] - a.offsets[c1];
+        x[4] = a.offsets[p + 1] - a.offsets[p];
+        int32_t u[5];
+        for (int f = 0; f < 5; ++f) {
+          int64_t v = ((mitchell_q8(x[f]) - ma.feat_lo[f]) * ma.feat_mul[f]) >> 16;
+          u[f] = (int32_t)(v < 0 ? 0 : (v > 1023 ? 1023 : v));
         }
-        if (i < ma.n_sv) y += term(i);
+        // integer sum: the split over threads does not change the result
+        // u and sv lie in [0, 1023] (sv checked when the model is set): the
+        // squared differences are exact 24-bit products (full-rate multiplies)
+        // and |u - sv|^2 < 2^23; g_mul < 2^32, so the table index is the high
+        // word of one 32 x 32-bit product
+        const uint32_t gm = (uint32_t)ma.g_mul;
+        auto term = [&](int i) -> int64_t {
+          const int32_t* sv = ma.sv + 5 * i;
+          const int d0 = u[0] - sv[0], d1 = u[1] - sv[1], d2 = u[2] - sv[2], d3 = u[3] - sv[3], d4 = u[4] - sv[4];
+          const uint32_t dist2 = (uint32_t)(__mul24(d0, d0) + __mul24(d1, d1) + __mul24(d2, d2) + __mul24(d3, d3) +
+                                            __mul24(d4, d4));
+          const uint32_t idx = __umulhi(dist2, gm);
+          const int32_t K = s_table[idx < (uint32_t)(kTableN - 1) ? idx : (uint32_t)(kTableN - 1)];
+          return (int64_t)ma.beta[i] * K;
+        };
+        // two independent chains (an integer sum: the order does not matter)
+        int64_t y = 0, y1 = 0;
+        if (T == 1) {
+          // a thread per pair: the support-vector index is the same across the
+          // wave, so sv and beta are read through scalar loads
+          int i = 0;
+          for (; i + 1 < ma.n_sv; i += 2) {
+            y += term(i);
+            y1 += term(i + 1);
+          }
+          if (i < ma.n_sv) y += term(i);
+        } else {
+          int i = t;
+          for (; i + T < ma.n_sv; i += 2 * T) {
+            y += term(i);
+            y1 += term(i + T);
+          }
+          if (i < ma.n_sv) y += term(i);
+        }
+        y += y1;
+        for (int o = 1; o < T; o <<= 1) y += __shfl_xor(y, o);
+        bits = (uint8_t)pick_bits(ma.beta0 + y, ma.theta, a.allowed, a.margin);
       }
-      y += y1;
-      for (int o = 1; o < T; o <<= 1) y += __shfl_xor(y, o);
-      bits = (uint8_t)pick_bits(ma.beta0 + y, ma.theta, a.allowed, a.margin);
+    }
+    if (t == 0) a.pbits[(size_t)q * a.npmax + r] = bits;
+    if (a.dot_out && p >= 0 && t == 0) {
+      // the pair's list term for its base (k_iptab subtracts it from the sum
+      // of the query's row minima) and its width in the query slot's mask
+      a.dot_out[(size_t)q * a.npmax + r] = dot;
+      atomicOr(&s_wmask[slot], 1 << ((bits >> 2) - 1));
     }
   }
-  if (t == 0) a.pbits[(size_t)q * a.npmax + r] = bits;
+  if (a.dot_out) {
+    // one atomic per query for the widths its tables are needed at
+    __syncthreads();
+    if ((threadIdx.x & ((1 << (lg + lt)) - 1)) == 0 && q < a.nq && s_wmask[slot])
+      atomicOr(&a.ipmask[q], s_wmask[slot]);
+  }
 }
 
 // ------------------------------------------------------------------ queue
@@ -1157,10 +1193,12 @@ __global__ void k_iptab_f32(BaseArgs b) {
   }
 }
 
-// inner product: base of each pair = sum of its query's row minima - qi.ci
-// (exact integers).  A workgroup per query, sixteen lanes per probed list
-// (sixteen lists per step); the widths the query's pairs use (the tables
-// k_ipq builds) are gathered in the workgroup and set with one atomic.
+// inner product: qi.ci of each pair (exact integers; k_iptab subtracts it
+// from the sum of the query's row minima: the pair's base), for the
+// policies whose predictor pass does not compute it.  A workgroup per query,
+// sixteen lanes per probed list (sixteen lists per step); the widths the
+// query's pairs use (the tables k_ipq builds) are gathered in the workgroup
+// and set with one atomic.
 __global__ __launch_bounds__(256) void k_ipbase(BaseArgs b) {
   __shared__ int s_mask;
   const size_t q = blockIdx.x;
@@ -1188,7 +1226,7 @@ __global__ __launch_bounds__(256) void k_ipbase(BaseArgs b) {
 #pragma unroll
     for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
     if (p >= 0 && r == 0) {
-      b.pbase[i] = b.iplsum[q] - acc;
+      b.pbase[i] = acc;  // qi.ci: k_iptab turns it into the base once the query's minima are known
       mask |= 1 << ((b.pbits[i] >> 2) - 1);
     }
   }
@@ -1509,6 +1547,9 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   pa.C = dv.centroids;
   pa.qi16 = (ipm && !fp32) ? ws.qi16 : nullptr;
   pa.ci16 = dv.ci16;
+  const bool pdot = ipm && !fp32 && sd.policy == AMP_POLICY_ADAPTIVE;
+  pa.dot_out = pdot ? ws.pbase : nullptr;
+  pa.ipmask = pdot ? ws.ipmask : nullptr;
   pa.probes = ws.probes;
   pa.radq = dv.radq;
   pa.offsets = dv.offsets;
@@ -1580,13 +1621,16 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
       hipLaunchKernelGGL(k_ipmax_f32, dim3((unsigned)(((size_t)sd.nq * sd.M + 3) / 4)), dim3(256), 0, st, ba);
       hipLaunchKernelGGL(k_ipbase_f32, dim3((unsigned)((npairs + 3) / 4)), dim3(256), 0, st, ba);
     } else if (ipm) {
-      // the queries' exact tables with their minima, then the pair bases
+      // the pairs' qi.ci and the widths each query needs, then the queries'
+      // tables with their minima (and the pair bases), then the quantised tables
       const size_t tlds = base_lds_layout(kTabQ, sd.M, sd.d).total;
       auto fn = dt == DT_F16 ? k_iptab<DT_F16> : (dt == DT_F8 ? k_iptab<DT_F8> : k_iptab<DT_BF16>);
       if ((err = hipFuncSetAttribute(kaddr(fn), hipFuncAttributeMaxDynamicSharedMemorySize, (int)tlds)) != hipSuccess)
         return err;
+      // (adaptive: the predictor pass wrote qi.ci and the width masks)
+      if (sd.policy != AMP_POLICY_ADAPTIVE)
+        hipLaunchKernelGGL(k_ipbase, dim3((unsigned)sd.nq), dim3(256), 0, st, ba);
       hipLaunchKernelGGL(fn, dim3((sd.nq + kTabQ - 1) / kTabQ), dim3(kThreads), tlds, st, ba);
-      hipLaunchKernelGGL(k_ipbase, dim3((unsigned)sd.nq), dim3(256), 0, st, ba);
       const size_t nq8 = (size_t)sd.nq * sd.M * kKsub / 8;
       hipLaunchKernelGGL(k_ipq, dim3((unsigned)std::min<size_t>((nq8 + 255) / 256, 1 << 20)), dim3(256), 0, st, ba);
     } else if (early) {

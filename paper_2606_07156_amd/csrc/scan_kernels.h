@@ -1817,7 +1817,8 @@ constexpr int kTabQ = 16;  // queries per workgroup of the table build (two 8-ro
 
 // inner product, integer policies: each query's exact table T[m][j] =
 // -qi_m . cbi_mj (LUT pass 1 on MFMA, the entries kept), its row minima, the
-// largest row span and the sum of the minima
+// largest row span and the sum of the minima; the pair bases, which held
+// qi.ci, become the sum of the minima - qi.ci
 template <int DT>
 __global__ __launch_bounds__(kThreads) void k_iptab(BaseArgs b) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
@@ -1871,7 +1872,15 @@ __global__ __launch_bounds__(kThreads) void k_iptab(BaseArgs b) {
     if (lane == 0) {
       b.ipspan[q0 + g] = b.gran ? rsum : span;
       b.iplsum[q0 + g] = sum;
+      reinterpret_cast<int64_t*>(lds + L.rr)[g] = sum;  // (rr is not used by the inner-product build)
     }
+  }
+  __syncthreads();
+  // the pair bases: sum of the query's row minima - qi.ci (pbase held qi.ci)
+  const int64_t* psum = reinterpret_cast<const int64_t*>(lds + L.rr);
+  for (int e = tid; e < nqb * b.npmax; e += kThreads) {
+    const size_t i = (size_t)q0 * b.npmax + e;
+    if (b.probes[i] >= 0) b.pbase[i] = psum[e / b.npmax] - b.pbase[i];
   }
 }
 
