@@ -93,28 +93,58 @@ __global__ void k_sqnorm(const float* __restrict__ X, int rows, int d, float* __
 }
 
 // D[q][c] = (|q|^2 + |c|^2) - 2 q.c (L2) or -q.c (IP).  64x64 tile per
-// workgroup, each wave a 32x32 quarter of 2x2 MFMA 16x16x4 FP32 tiles.
+// workgroup, each wave a 32x32 quarter of 2x2 MFMA 16x16x4 FP32 tiles; K in
+// chunks of KC staged through LDS, the next chunk's loads issued before the
+// current chunk's products (16-byte loads when d is a multiple of 4 and the
+// rows 16-byte aligned).  The products run in k order whatever the chunk, so
+// the sums do not depend on it.
 constexpr int CL_T = 64, CL_K = 32;
+template <int KC, bool VEC>
 __global__ __launch_bounds__(256) void k_coarse(const float* __restrict__ Q, const float* __restrict__ C,
                                                 const float* __restrict__ qn, const float* __restrict__ cn,
                                                 float* __restrict__ D, int nq, int nlist, int d, int metric) {
-  __shared__ float Qs[CL_T][CL_K + 1];
-  __shared__ float Cs[CL_T][CL_K + 1];
+  __shared__ float Qs[CL_T][KC + 1];
+  __shared__ float Cs[CL_T][KC + 1];
   const int q0 = blockIdx.y * CL_T, c0 = blockIdx.x * CL_T;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  constexpr int NV = CL_T * KC / 4 / 256;  // 16-byte loads per thread and tile
+  float4 qa[NV], ca[NV];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      const int f = tid + 256 * u, r = f / (KC / 4), gk = k0 + 4 * (f % (KC / 4));
+      if (VEC) {
+        qa[u] = (q0 + r < nq && gk < d) ? *reinterpret_cast<const float4*>(Q + (size_t)(q0 + r) * d + gk)
+                                        : make_float4(0.f, 0.f, 0.f, 0.f);
+        ca[u] = (c0 + r < nlist && gk < d) ? *reinterpret_cast<const float4*>(C + (size_t)(c0 + r) * d + gk)
+                                           : make_float4(0.f, 0.f, 0.f, 0.f);
+      } else {
+        float* qv = &qa[u].x;
+        float* cv = &ca[u].x;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          qv[e] = (q0 + r < nq && gk + e < d) ? Q[(size_t)(q0 + r) * d + gk + e] : 0.f;
+          cv[e] = (c0 + r < nlist && gk + e < d) ? C[(size_t)(c0 + r) * d + gk + e] : 0.f;
+        }
+      }
+    }
+  };
   f4 acc[2][2];
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < d; k0 += CL_K) {
-    for (int i = tid; i < CL_T * CL_K; i += 256) {
-      int r = i / CL_K, kk = i % CL_K, gk = k0 + kk;
-      Qs[r][kk] = (q0 + r < nq && gk < d) ? Q[(size_t)(q0 + r) * d + gk] : 0.f;
-      Cs[r][kk] = (c0 + r < nlist && gk < d) ? C[(size_t)(c0 + r) * d + gk] : 0.f;
+  load(0);
+  for (int k0 = 0; k0 < d; k0 += KC) {
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      const int f = tid + 256 * u, r = f / (KC / 4), kk = 4 * (f % (KC / 4));
+      Qs[r][kk] = qa[u].x; Qs[r][kk + 1] = qa[u].y; Qs[r][kk + 2] = qa[u].z; Qs[r][kk + 3] = qa[u].w;
+      Cs[r][kk] = ca[u].x; Cs[r][kk + 1] = ca[u].y; Cs[r][kk + 2] = ca[u].z; Cs[r][kk + 3] = ca[u].w;
     }
     __syncthreads();
+    if (k0 + KC < d) load(k0 + KC);
 #pragma unroll
-    for (int kk = 0; kk < CL_K; kk += 4) {
+    for (int kk = 0; kk < KC; kk += 4) {
       float a0 = Qs[wr + (lane & 15)][kk + (lane >> 4)];
       float a1 = Qs[wr + 16 + (lane & 15)][kk + (lane >> 4)];
       float b0 = Cs[wc + (lane & 15)][kk + (lane >> 4)];
@@ -1497,8 +1527,15 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
                        st, queries, dv.centroids, coarse, sd.nq, sd.nlist, sd.d);
   } else {
     hipLaunchKernelGGL(k_sqnorm, dim3((sd.nq + 3) / 4), dim3(256), 0, st, queries, sd.nq, sd.d, ws.qnorm);
-    hipLaunchKernelGGL(k_coarse, dim3((sd.nlist + CL_T - 1) / CL_T, (sd.nq + CL_T - 1) / CL_T), dim3(256), 0, st,
-                       queries, dv.centroids, ws.qnorm, dv.cnorm, coarse, sd.nq, sd.nlist, sd.d, sd.metric);
+    const dim3 g((sd.nlist + CL_T - 1) / CL_T, (sd.nq + CL_T - 1) / CL_T);
+    const bool vec = sd.d % 4 == 0 && ((reinterpret_cast<uintptr_t>(queries) | reinterpret_cast<uintptr_t>(dv.centroids)) & 15) == 0;
+    // (64-wide K chunks measured the same as 32 at 4096 x 2048 x 768)
+    if (vec)
+      hipLaunchKernelGGL((k_coarse<CL_K, true>), g, dim3(256), 0, st, queries, dv.centroids, ws.qnorm, dv.cnorm, coarse,
+                         sd.nq, sd.nlist, sd.d, sd.metric);
+    else
+      hipLaunchKernelGGL((k_coarse<CL_K, false>), g, dim3(256), 0, st, queries, dv.centroids, ws.qnorm, dv.cnorm,
+                         coarse, sd.nq, sd.nlist, sd.d, sd.metric);
   }
   mark(1);
   int np2 = 1;
