@@ -326,6 +326,92 @@ __device__ void block_bitonic_u64(uint64_t* keys, int n) {
   }
 }
 
+// the kk-th smallest (1-based, kk <= n) of n 64-bit keys in LDS, by radix
+// select: passes over 8-bit digits, most significant first, each
+// counting the digits of the keys that share the digits chosen so far and
+// choosing the digit whose count range holds the remaining rank.  hist: 256
+// counters in LDS; sel: two words in LDS.  Every thread of the block returns
+// the key.
+__device__ uint64_t block_select_u64(const uint64_t* keys, int n, int kk, uint32_t* hist, uint32_t* sel) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  // the digits above the highest bit where the smallest and largest keys
+  // differ are common to every key: the passes start below them
+  uint64_t lo = ~0ull, hi = 0;
+  for (int i = tid; i < n; i += blockDim.x) {
+    const uint64_t k = keys[i];
+    lo = k < lo ? k : lo;
+    hi = k > hi ? k : hi;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint64_t a = __shfl_xor(lo, o), b = __shfl_xor(hi, o);
+    lo = a < lo ? a : lo;
+    hi = b > hi ? b : hi;
+  }
+  uint64_t* mm = reinterpret_cast<uint64_t*>(hist);  // two words a wave (at most 16 waves)
+  if (lane == 0) {
+    mm[2 * (tid >> 6)] = lo;
+    mm[2 * (tid >> 6) + 1] = hi;
+  }
+  __syncthreads();
+  lo = mm[0];
+  hi = mm[1];
+  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+    lo = mm[2 * w] < lo ? mm[2 * w] : lo;
+    hi = mm[2 * w + 1] > hi ? mm[2 * w + 1] : hi;
+  }
+  __syncthreads();  // hist is cleared by the first pass
+  if (lo == hi) return lo;
+  const int top = (63 - __builtin_clzll(lo ^ hi)) & ~7;
+  uint64_t mask = top >= 56 ? 0ull : ~((1ull << (top + 8)) - 1);
+  uint64_t prefix = lo & mask;
+  uint32_t rank = (uint32_t)kk;
+  for (int shift = top; shift >= 0; shift -= 8) {
+    for (int i = tid; i < 256; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
+    for (int i = tid; i < n; i += blockDim.x) {
+      const uint64_t k = keys[i];
+      if ((k & mask) == prefix) atomicAdd(&hist[(k >> shift) & 255], 1u);
+    }
+    __syncthreads();
+    if (tid < 64) {
+      // four bins a lane, inclusive scan over the wave
+      const uint32_t h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2], h3 = hist[4 * lane + 3];
+      const uint32_t own = h0 + h1 + h2 + h3;
+      uint32_t inc = own;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t v = __shfl_up(inc, o);
+        if (lane >= o) inc += v;
+      }
+      const uint32_t below = inc - own;
+      if (below < rank && rank <= inc) {
+        uint32_t c = below, dg = 4 * lane;
+        if (c + h0 < rank) {
+          c += h0;
+          ++dg;
+          if (c + h1 < rank) {
+            c += h1;
+            ++dg;
+            if (c + h2 < rank) {
+              c += h2;
+              ++dg;
+            }
+          }
+        }
+        sel[0] = dg;
+        sel[1] = c;
+      }
+    }
+    __syncthreads();
+    prefix |= (uint64_t)sel[0] << shift;
+    mask |= 255ull << shift;
+    rank -= sel[1];
+    __syncthreads();  // sel and hist are rewritten by the next pass
+  }
+  return prefix;
+}
+
 // same with a secondary signed 64-bit tie-breaker
 __device__ void block_bitonic_u64_i64(uint64_t* keys, int64_t* vals, int n) {
   for (int size = 2; size <= n; size <<= 1) {
@@ -944,7 +1030,8 @@ __global__ void k_qunits(QueueArgs a, int fp32) {
 // entry is the estimate of a distinct vector, so it bounds the query's k-th
 // smallest estimate from above), or no bound with fewer than k entries; the
 // buffer is emptied for phase 2.  Queries with at most 64 entries: one wave
-// each (register bitonic sort); the rest: k_tau, a workgroup each.
+// each (register bitonic sort); the rest: k_tau, a workgroup each (radix
+// select).
 __global__ __launch_bounds__(256) void k_tau_wave(uint32_t* ccount, const uint64_t* ckey, uint64_t* tau,
                                                   const int32_t* kq, int kconst, int nq, size_t capq,
                                                   int32_t* any_retry) {
@@ -974,7 +1061,9 @@ __global__ __launch_bounds__(256) void k_tau(uint32_t* ccount, const uint64_t* c
                                              const int32_t* kq, int kconst, int nq, size_t capq) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   uint64_t* keys = reinterpret_cast<uint64_t*>(lds);
-  int* s_n = reinterpret_cast<int*>(lds + capq * 8);
+  uint32_t* hist = reinterpret_cast<uint32_t*>(lds + capq * 8);  // [256]
+  uint32_t* sel = hist + 256;                                     // [2]
+  int* s_n = reinterpret_cast<int*>(sel + 2);
   int* s_q = s_n + 1;  // [blockDim.x]
   // the workgroup's queries q = blockIdx.x + i * gridDim.x, a thread each:
   // the entry counts are read side by side, and only the queries with more
@@ -995,17 +1084,22 @@ __global__ __launch_bounds__(256) void k_tau(uint32_t* ccount, const uint64_t* c
       const int qq = s_q[t];
       const uint32_t cnt = ccount[qq];
       const int n = (int)(cnt < capq ? cnt : capq);
-      int np2 = 1;
-      while (np2 < n) np2 <<= 1;
-      for (int i = threadIdx.x; i < np2; i += blockDim.x) keys[i] = i < n ? ckey[(size_t)qq * capq + i] : ~0ull;
-      __syncthreads();
-      block_bitonic_u64(keys, np2);
       const int kk = kq ? kq[qq] : kconst;
+      if (n < kk) {  // uniform over the workgroup
+        if (threadIdx.x == 0) {
+          tau[qq] = ~0ull;
+          ccount[qq] = 0;
+        }
+        continue;
+      }
+      for (int i = threadIdx.x; i < n; i += blockDim.x) keys[i] = ckey[(size_t)qq * capq + i];
+      __syncthreads();
+      const uint64_t kth = block_select_u64(keys, n, kk, hist, sel);
       if (threadIdx.x == 0) {
-        tau[qq] = n >= kk ? keys[kk - 1] : ~0ull;
+        tau[qq] = kth;
         ccount[qq] = 0;
       }
-      __syncthreads();  // the LDS is reused by the next query
+      // (the select ends on a barrier: the LDS is free for the next query)
     }
     __syncthreads();  // every thread has read the list before it is reset
   }
@@ -1127,17 +1221,81 @@ __global__ __launch_bounds__(256) void k_merge_wave(MergeArgs a, int nq) {
   for (int r = lane; r < a.kmax; r += 64) merge_emit(a, q, r, n, kk, key, id);
 }
 
-// queries with more than 64 candidates: a workgroup per query (strided over
-// the queries), bitonic sort in LDS
+// queries with more than 64 candidates and more than k: a workgroup per
+// query (strided over the queries).  A radix select finds the k-th smallest
+// key; the candidates up to it, when at most kMergeSel, take their output
+// rows from their rank (key, id, position) among themselves.  The other
+// queries (at most k candidates, or more than kMergeSel up to the k-th key)
+// are left to k_merge_full, marked by id -2 in their first output row.
+constexpr int kMergeSel = 256;
+
 __global__ __launch_bounds__(256) void k_merge(MergeArgs a, int nq) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   uint64_t* keys = reinterpret_cast<uint64_t*>(lds);
-  int64_t* vals = reinterpret_cast<int64_t*>(lds + a.capq * 8);
+  uint64_t* skey = reinterpret_cast<uint64_t*>(lds + a.capq * 8);  // [kMergeSel]
+  int64_t* sval = reinterpret_cast<int64_t*>(skey + kMergeSel);    // [kMergeSel]
+  int32_t* sidx = reinterpret_cast<int32_t*>(sval + kMergeSel);    // [kMergeSel]
+  uint32_t* hist = reinterpret_cast<uint32_t*>(sidx + kMergeSel);  // [256]
+  uint32_t* sel = hist + 256;                                       // [2]
+  uint32_t* s_cnt = sel + 2;
   for (int q = blockIdx.x; q < nq; q += gridDim.x) {
     const uint32_t cnt = a.ccount[q];
     if (cnt > a.capq && threadIdx.x == 0) atomicOr(&a.flags[0], 2);
     const int n = (int)(cnt < a.capq ? cnt : a.capq);
     if (n <= 64) continue;  // uniform over the workgroup
+    const int kk = a.kq ? a.kq[q] : a.kconst;
+    if (kk >= n) {
+      if (threadIdx.x == 0) a.out_ids[(size_t)q * a.kmax] = -2;
+      continue;
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) keys[i] = a.ckey[(size_t)q * a.capq + i];
+    if (threadIdx.x == 0) *s_cnt = 0;
+    __syncthreads();
+    const uint64_t v = block_select_u64(keys, n, kk, hist, sel);
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+      if (keys[i] <= v) {
+        const uint32_t j = atomicAdd(s_cnt, 1u);
+        if (j < (uint32_t)kMergeSel) {
+          skey[j] = keys[i];
+          sval[j] = a.cid[(size_t)q * a.capq + i];
+          sidx[j] = i;
+        }
+      }
+    __syncthreads();
+    const int ns = (int)*s_cnt;
+    if (ns > kMergeSel) {  // uniform over the workgroup
+      if (threadIdx.x == 0) a.out_ids[(size_t)q * a.kmax] = -2;
+    } else {
+      for (int t = threadIdx.x; t < ns; t += blockDim.x) {
+        const uint64_t kt = skey[t];
+        const int64_t it = sval[t];
+        const int xt = sidx[t];
+        int rank = 0;
+        for (int j = 0; j < ns; ++j) {
+          const uint64_t kj = skey[j];
+          const int64_t ij = sval[j];
+          rank += kj < kt || (kj == kt && (ij < it || (ij == it && sidx[j] < xt)));
+        }
+        if (rank < kk) merge_emit(a, q, rank, n, kk, kt, it);
+      }
+      for (int r = kk + threadIdx.x; r < a.kmax; r += blockDim.x) merge_emit(a, q, r, n, kk, ~0ull, INT64_MAX);
+    }
+    __syncthreads();  // the LDS is reused by the next query
+  }
+}
+
+// the queries k_merge left (id -2 in the first output row): a workgroup per
+// query (strided over the queries), every candidate sorted by (key, id) in
+// LDS (bitonic over the next power of two)
+__global__ __launch_bounds__(256) void k_merge_full(MergeArgs a, int nq) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  uint64_t* keys = reinterpret_cast<uint64_t*>(lds);
+  int64_t* vals = reinterpret_cast<int64_t*>(lds + a.capq * 8);
+  for (int q = blockIdx.x; q < nq; q += gridDim.x) {
+    const uint32_t cnt = a.ccount[q];
+    const int n = (int)(cnt < a.capq ? cnt : a.capq);
+    if (n <= 64 || a.out_ids[(size_t)q * a.kmax] != -2) continue;  // uniform over the workgroup
+    __syncthreads();  // every thread has read the mark before it is overwritten
     int np2 = 1;
     while (np2 < n) np2 <<= 1;
     for (int i = threadIdx.x; i < np2; i += blockDim.x) {
@@ -1805,10 +1963,11 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
       // phase-1 minima -> per-query bound, buffer emptied for the candidates
       hipLaunchKernelGGL(k_tau_wave, dim3((sd.nq + 3) / 4), dim3(256), 0, st, ws.ccount, ws.ckey, ws.tau, ws.kq,
                          sd.kconst, sd.nq, sd.capq, ws.flags + 1);
-      const size_t tlds = sd.capq * 8 + 4 * (1 + 256);  // sort row + list of the queries to sort
+      // keys + digit counts + selection + list of the queries to select in
+      const size_t tlds = sd.capq * 8 + 4 * (256 + 2 + 1 + 256);
       err = hipFuncSetAttribute(kaddr(k_tau), hipFuncAttributeMaxDynamicSharedMemorySize, (int)tlds);
       if (err != hipSuccess) return err;
-      hipLaunchKernelGGL(k_tau, dim3(sd.nq < 512 ? sd.nq : 512), dim3(256), tlds, st, ws.ccount, ws.ckey, ws.tau,
+      hipLaunchKernelGGL(k_tau, dim3(sd.nq < 1024 ? sd.nq : 1024), dim3(256), tlds, st, ws.ccount, ws.ckey, ws.tau,
                          ws.kq, sd.kconst, sd.nq, sd.capq);
       if (early) build_queue(1, 2);  // the full scan's queue: live pairs only
     }
@@ -1851,11 +2010,15 @@ hipError_t launch_search(const amp_index* ix, const Workspace& ws, const float* 
   ma2.fp32 = fp32 ? 1 : 0;
   ma2.h2 = ldexpf(1.f, sd.metric == AMP_L1 ? sd.grid_e : 2 * sd.grid_e);  // L1 estimates are in units of h
   ma2.capq = sd.capq;
-  const size_t mlds = sd.capq * 16;
+  const size_t mlds = sd.capq * 8 + kMergeSel * 20 + 4 * (256 + 3);
   err = hipFuncSetAttribute(kaddr(k_merge), hipFuncAttributeMaxDynamicSharedMemorySize, (int)mlds);
   if (err != hipSuccess) return err;
+  const size_t flds = sd.capq * 16;
+  err = hipFuncSetAttribute(kaddr(k_merge_full), hipFuncAttributeMaxDynamicSharedMemorySize, (int)flds);
+  if (err != hipSuccess) return err;
   hipLaunchKernelGGL(k_merge_wave, dim3((sd.nq + 3) / 4), dim3(256), 0, st, ma2, sd.nq);
-  hipLaunchKernelGGL(k_merge, dim3(sd.nq < 512 ? sd.nq : 512), dim3(256), mlds, st, ma2, sd.nq);
+  hipLaunchKernelGGL(k_merge, dim3(sd.nq < 1024 ? sd.nq : 1024), dim3(256), mlds, st, ma2, sd.nq);
+  hipLaunchKernelGGL(k_merge_full, dim3(sd.nq < 512 ? sd.nq : 512), dim3(256), flds, st, ma2, sd.nq);
   if (sd.lut_export) {
     // test hook: every pair's LUT as the search builds it
     const amp_lut_export* ex = sd.lut_export;
