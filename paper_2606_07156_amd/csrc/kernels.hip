@@ -651,6 +651,26 @@ __global__ __launch_bounds__(256) void k_pairs(PairArgs a, ModelArgs ma) {
     const bool l2 = a.metric != AMP_IP;  // L2 and L1: d' of the grid residual
     if (!l2 && a.qi16) {
       // inner product: both sides already on the grid
+      auto acc2 = [&](uint32_t x, uint32_t c) {
+        const int x0 = (int)(int16_t)(x & 0xFFFFu), x1 = (int)(int16_t)(x >> 16);
+        const int c0 = (int)(int16_t)(c & 0xFFFFu), c1 = (int)(int16_t)(c >> 16);
+        const int v0 = x0 - c0, v1 = x1 - c1;
+        s2 += (int64_t)(v0 * v0 + v1 * v1);
+        dot += x0 * c0 + x1 * c1;
+      };
+      if ((a.d & 7) == 0) {
+        // eight coordinates per 16-byte read (rows 16-byte aligned)
+        const u32x4* xq = reinterpret_cast<const u32x4*>(a.qi16 + (size_t)qq * a.d);
+        const u32x4* xc = reinterpret_cast<const u32x4*>(a.ci16 + (size_t)pp * a.d);
+        for (int i = t0; i < (a.d >> 3); i += tn) {
+          const u32x4 x = xq[i], c = xc[i];
+          acc2(x[0], c[0]);
+          acc2(x[1], c[1]);
+          acc2(x[2], c[2]);
+          acc2(x[3], c[3]);
+        }
+        return s2;
+      }
       const u32x2* xq = reinterpret_cast<const u32x2*>(a.qi16 + (size_t)qq * a.d);
       const u32x2* xc = reinterpret_cast<const u32x2*>(a.ci16 + (size_t)pp * a.d);
       for (int i = t0; i < (a.d >> 2); i += tn) {
