@@ -1813,7 +1813,7 @@ __global__ __launch_bounds__(kThreads) void k_export(BaseArgs b, uint16_t* exq, 
   }
 }
 
-constexpr int kTabQ = 16;  // queries per workgroup of the table build (two 8-row MFMA tiles)
+constexpr int kTabQ = 8;  // queries per workgroup of the table build (one 8-row MFMA tile)
 
 // inner product, integer policies: each query's exact table T[m][j] =
 // -qi_m . cbi_mj (LUT pass 1 on MFMA, the entries kept), its row minima, the
