@@ -704,6 +704,22 @@ def test_bound_spans_probes_when_the_nearest_list_is_smaller_than_k(monkeypatch,
         compare_integer(g, ref)
 
 
+@pytest.mark.parametrize("k,nprobe", [(65, 8), (200, 8), (300, 8), (700, 1)])
+def test_top_k_select_and_sort_paths(tiny, k, nprobe):
+    # the phase-1 bound and the merge take the k-th smallest key by radix
+    # select (4-bit LUTs: many equal keys); the merge ranks the candidates up
+    # to it when there are at most 256 (k = 65, 200) and sorts them all when
+    # there are more (k = 300) or when a query has at most k candidates (one
+    # probed list of about 300 vectors, k = 700: rows padded with -1)
+    g = _gpu(tiny, k, nprobe, policy="fixed", bits=4)
+    ref = _oracle(tiny, k, nprobe, g, policy="fixed", bits=4)
+    compare_integer(g, ref)
+    if k == 700:
+        sizes = np.diff(tiny["idx"]["list_offsets"])[g["probes"][:, 0]]
+        assert (sizes < k).any()
+        assert (g["ids"][sizes < k, -1] == -1).all()
+
+
 @pytest.mark.parametrize("policy,bits", [("fixed", 4), ("fixed", 16), ("fp32", 0)])
 def test_candidate_overflow_is_resolved_by_rerunning_phase_two(tiny, monkeypatch, capfd, policy, bits):
     # a 64-entry candidate buffer for k = 10: queries whose candidates under
