@@ -457,9 +457,10 @@ __global__ __launch_bounds__(256) void k_topn(const float* __restrict__ D, int n
 // order key x is found bit by bit: the count of keys below a candidate is
 // the sum over the four waves of ballot bit counts, exchanged through LDS
 // (two alternating slots: one barrier per bit).  The keys up to x, with
-// their list ids, are gathered in LDS (any order), padded to a power of two
-// and sorted by (key, list id); the first nprobe are the probes, the same as
-// a sort of the whole row.
+// their list ids, are gathered in LDS (any order); up to 512 of them each
+// take the output row of their rank by (key, list id) among them, more are
+// padded to a power of two and sorted.  The first nprobe are the probes,
+// the same as a sort of the whole row.
 template <int PER>
 __global__ __launch_bounds__(256) void k_topn_wg(const float* __restrict__ D, int nlist,
                                                  const int32_t* __restrict__ npq, int npconst, int npmax,
@@ -500,6 +501,18 @@ __global__ __launch_bounds__(256) void k_topn_wg(const float* __restrict__ D, in
   }
   __syncthreads();
   const int n = s_n;
+  if (n <= 512) {  // uniform over the workgroup
+    // (key, list id) are distinct: each selected key's output row is the
+    // count of selected keys below it (no sort, no barrier)
+    for (int t = tid; t < n; t += 256) {
+      const uint64_t v = sel[t];
+      int rank = 0;
+      for (int j = 0; j < n; ++j) rank += sel[j] < v;
+      if (rank < npmax) probes[(size_t)q * npmax + rank] = rank < k ? (int32_t)(v & 0xFFFFFFFFu) : -1;
+    }
+    for (int r = n + tid; r < npmax; r += 256) probes[(size_t)q * npmax + r] = -1;
+    return;
+  }
   int n2 = 1;
   while (n2 < n) n2 <<= 1;
   for (int i = n + tid; i < n2; i += 256) sel[i] = ~0ull;
