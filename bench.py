@@ -457,7 +457,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU path is a design "
-              "note, not part of this build", file=sys.stderr)
+              "note and is not implemented", file=sys.stderr)
         sys.exit(2)
     if args.workload:
         return single(args)

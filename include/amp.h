@@ -46,7 +46,7 @@ enum {
   AMP_EFORMAT = -5,      /* index file corrupt, truncated or wrong version     */
   AMP_EBUSY = -6,
   AMP_ECANCELED = -7,
-  AMP_EUNSUPPORTED = -8, /* valid request this build does not implement       */
+  AMP_EUNSUPPORTED = -8, /* valid request the library does not implement      */
   AMP_EOVERFLOW = -9     /* a query's candidate buffer overflowed             */
 };
 
